@@ -1,0 +1,11 @@
+"""Seeded synthetic inputs shared by the tests, the oracle and the benchmark.
+
+This package only builds input matrices (planted spectra, noise, offsets and
+ragged batches).  It contains none of the randomized-SVD arithmetic, so the
+oracle and the HIP path can both consume its output without sharing any part
+of the method.
+"""
+from .matrices import (  # noqa: F401
+    haar, planted, planted_torch, spectrum, CONFIGS, c1_matrix, c2_matrix,
+    c2_offsets, c3_matrix_torch, c4_batch, paper_lowrank_product,
+)

@@ -1,0 +1,170 @@
+"""Planted-spectrum test matrices A = U diag(sigma) V^T (+ noise).
+
+U and V are Haar-distributed: the Q factor of a seeded Gaussian matrix with
+its columns multiplied by sign(R_ii) (Mezzadri, "How to generate random
+matrices from the classical compact groups", 2007).
+
+Workload recipes (sizes, spectra and seeds):
+
+* C1  2000 x 1000 float64, sigma_i = 1/i (all 1000 values); k=20, p=10, q=2.
+* C2  100000 x 5000 float32, sigma_i = exp(-i/50) for i <= 1000 plus a
+      Gaussian noise floor of 1e-6 sigma_1 (entries N(0,1) * 1e-6 sigma_1 /
+      sqrt(m)); k=100, p=20, q=2.  For PCA a column offset mu_j ~ N(0,1) *
+      sigma_1 / sqrt(m) is added.
+* C3  200000 x 20000 bfloat16, sigma_i = i^-1.5 for i <= 4096, computed in
+      float64 and rounded to bfloat16 (the rounded matrix is the instance).
+* C4  4096 ragged float32 matrices: m ~ U{256..4096}, n ~ U{64..1024},
+      k ~ U{8..min(64, min(m,n)-10)}, sigma_i = i^-alpha, alpha ~ U[0.5, 3].
+* paper-shaped: the rank-200 product of two Gaussian matrices used for the
+  paper's timing study (Sec. 3.8).
+"""
+import math
+
+import numpy as np
+
+CONFIGS = {
+    "c1": dict(m=2000, n=1000, k=20, p=10, q=2, dtype="f64", gen_seed=1608, omega_seed=2148),
+    "c2": dict(m=100000, n=5000, k=100, p=20, q=2, dtype="f32", gen_seed=5000, omega_seed=2148),
+    "c3": dict(m=200000, n=20000, k=200, p=20, q=2, dtype="bf16", gen_seed=20000, omega_seed=2148),
+    "c4": dict(batch=4096, p=10, q=2, dtype="f32", gen_seed=4096, omega_seed=2148),
+}
+
+
+def spectrum(kind, count, **kw):
+    """Planted singular values sigma_1 >= sigma_2 >= ... (float64)."""
+    i = np.arange(1, count + 1, dtype=np.float64)
+    if kind == "inverse":          # sigma_i = 1 / i
+        return 1.0 / i
+    if kind == "poly":             # sigma_i = i^-alpha
+        return i ** (-float(kw["alpha"]))
+    if kind == "exp":              # sigma_i = exp(-i / tau)
+        return np.exp(-i / float(kw["tau"]))
+    raise ValueError(kind)
+
+
+def haar(rng, m, r):
+    """m x r matrix with orthonormal columns, Haar distributed (r <= m)."""
+    g = rng.standard_normal((m, r))
+    q, rr = np.linalg.qr(g, mode="reduced")
+    s = np.sign(np.diag(rr))
+    s[s == 0] = 1.0
+    return q * s[None, :]
+
+
+def planted(m, n, sigma, seed, noise=0.0):
+    """A = U diag(sigma) V^T + noise * G (float64, numpy)."""
+    rng = np.random.default_rng(seed)
+    r = len(sigma)
+    U = haar(rng, m, r)
+    V = haar(rng, n, r)
+    A = (U * np.asarray(sigma)[None, :]) @ V.T
+    if noise:
+        A += noise * rng.standard_normal((m, n))
+    return A
+
+
+def planted_torch(m, n, sigma, seed, noise=0.0, device="cuda", out_dtype=None,
+                  chunk_rows=16384):
+    """Same recipe as ``planted`` on a torch device, returned in ``out_dtype``.
+
+    Generated in float64 and rounded once to ``out_dtype`` (round to nearest
+    even), in row chunks so that only the rounded matrix is held in full.
+    """
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    r = len(sigma)
+    f64 = torch.float64
+
+    def _haar(rows):
+        x = torch.randn(rows, r, generator=g, device=device, dtype=f64)
+        q, rr = torch.linalg.qr(x, mode="reduced")
+        s = torch.sign(torch.diagonal(rr))
+        s[s == 0] = 1.0
+        return q * s[None, :]
+
+    U = _haar(m)
+    V = _haar(n)
+    sig = torch.as_tensor(np.asarray(sigma, dtype=np.float64), device=device)
+    US = U * sig[None, :]
+    del U
+    out_dtype = out_dtype or f64
+    A = torch.empty(m, n, dtype=out_dtype, device=device)
+    Vt = V.t().contiguous()
+    for r0 in range(0, m, chunk_rows):
+        r1 = min(m, r0 + chunk_rows)
+        blk = US[r0:r1] @ Vt
+        if noise:
+            blk += noise * torch.randn(r1 - r0, n, generator=g, device=device, dtype=f64)
+        A[r0:r1] = blk.to(out_dtype)
+    return A
+
+
+def c1_matrix():
+    """C1 instance: 2000 x 1000 float64 with sigma_i = 1/i."""
+    c = CONFIGS["c1"]
+    sig = spectrum("inverse", min(c["m"], c["n"]))
+    return planted(c["m"], c["n"], sig, c["gen_seed"])
+
+
+def c2_sigma():
+    return spectrum("exp", 1000, tau=50.0)
+
+
+def c2_matrix(device="cuda", m=None, n=None):
+    """C2 instance (float32 torch tensor on ``device``), optionally resized."""
+    import torch
+    c = CONFIGS["c2"]
+    m = m or c["m"]
+    n = n or c["n"]
+    sig = c2_sigma()[: min(m, n, 1000)]
+    noise = 1e-6 * sig[0] / math.sqrt(m)
+    return planted_torch(m, n, sig, c["gen_seed"], noise=noise, device=device,
+                         out_dtype=torch.float32)
+
+
+def c2_offsets(n, m, seed=5001):
+    """Column offsets mu_j ~ N(0,1) * sigma_1 / sqrt(m) for the PCA variant."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(n) * (c2_sigma()[0] / math.sqrt(m))
+
+
+def c3_matrix_torch(device="cuda", m=None, n=None, rank=4096):
+    """C3 instance rounded to bfloat16 (torch tensor on ``device``)."""
+    import torch
+    c = CONFIGS["c3"]
+    m = m or c["m"]
+    n = n or c["n"]
+    sig = spectrum("poly", min(m, n, rank), alpha=1.5)
+    return planted_torch(m, n, sig, c["gen_seed"], device=device,
+                         out_dtype=torch.bfloat16, chunk_rows=8192)
+
+
+def c4_shapes(batch=4096, seed=4096, m_range=(256, 4096), n_range=(64, 1024),
+              k_max=64):
+    """Ragged shapes and decay exponents of the C4 batch (numpy arrays)."""
+    rng = np.random.default_rng(seed)
+    m = rng.integers(m_range[0], m_range[1] + 1, size=batch)
+    n = rng.integers(n_range[0], n_range[1] + 1, size=batch)
+    kmax = np.minimum(k_max, np.minimum(m, n) - 10)
+    k = np.array([rng.integers(8, km + 1) for km in kmax])
+    alpha = rng.uniform(0.5, 3.0, size=batch)
+    return m, n, k, alpha
+
+
+def c4_batch(batch=4096, seed=4096, **shape_kw):
+    """Ragged batch: list of (A float64 numpy, k, alpha).  CPU; small batches."""
+    m, n, k, alpha = c4_shapes(batch, seed, **shape_kw)
+    out = []
+    for b in range(batch):
+        r = int(min(m[b], n[b]))
+        sig = spectrum("poly", r, alpha=alpha[b])
+        A = planted(int(m[b]), int(n[b]), sig, seed * 100003 + b)
+        out.append((A, int(k[b]), float(alpha[b])))
+    return out
+
+
+def paper_lowrank_product(m, n, rank=200, seed=1135):
+    """Rank-``rank`` product of two Gaussian matrices (float64)."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((m, rank)) @ rng.standard_normal((rank, n))
