@@ -1,0 +1,217 @@
+/*
+ * rsvd_mi355x.h -- C ABI of the MI355X (gfx950) randomized SVD / PCA library.
+ *
+ * Method: Erichson, Voronin, Brunton & Kutz, "Randomized Matrix Decompositions
+ * Using R" (arXiv:1608.02148).
+ *   - rsvd_run  : Alg. RSVDalgorithm (Sec. 3.3) on top of Alg. rqb (Sec. 3.3)
+ *                 with Alg. subspace_iter (Sec. 2.2) as the power scheme.
+ *   - rpca_run  : Alg. RPCAalgorithm (Sec. 4.2), interface of Sec. 4.4, with
+ *                 the column centring applied implicitly (A is never modified).
+ *
+ * Conventions shared by every entry point
+ *   - All matrices are ROW-MAJOR with a leading dimension (elements between
+ *     consecutive rows).  A is m x n; U is m x k; V is n x k and is NOT
+ *     transposed (Sec. 3.6: the returned v holds right singular vectors as
+ *     columns).
+ *   - Every matrix / vector argument is a DEVICE pointer owned by the caller.
+ *     The library never allocates device memory on the run path: scratch
+ *     space is the caller's `work` buffer of at least rsvd_workspace_size()
+ *     bytes (256-byte aligned).  A is read-only.
+ *   - Calls are asynchronous and stream-ordered on the handle's HIP stream;
+ *     outputs are valid once that stream has completed.  No call
+ *     synchronises the stream except rsvd_sync_info().
+ *   - Element types: A is f64, f32 or bf16 (rsvd_dtype).  U, V, rotation, x
+ *     and center are f64 when A is f64 and f32 otherwise; singular values,
+ *     eigvals and sdev are always f64.
+ *   - Return value: RSVD_OK or a negative status.  Argument checks run before
+ *     any launch.  Conditions only the device can see (non-finite data, a
+ *     Cholesky breakdown) are reported in rsvd_info.flags.
+ *   - Determinism: identical inputs, parameters and device give bitwise
+ *     identical outputs (no floating-point atomics anywhere).
+ */
+#ifndef RSVD_MI355X_H
+#define RSVD_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rsvd_handle_s* rsvd_handle_t;
+
+/* Storage type of A. */
+typedef enum { RSVD_F64 = 0, RSVD_F32 = 1, RSVD_BF16 = 2 } rsvd_dtype;
+
+/* Distribution of the random test matrix Omega (Sec. 2.3). */
+typedef enum { RSVD_NORMAL = 0, RSVD_UNIF = 1, RSVD_RADEMACHER = 2 } rsvd_sdist;
+
+/* Arithmetic of the passes over A.
+ * RSVD_PREC_PLAIN: products in the storage precision of A (f64 MFMA for f64,
+ *   f32 MFMA for f32 and bf16).
+ * RSVD_PREC_BF16_MIXED: the products with A run on bf16 MFMA with f32
+ *   accumulation; the final projection B = Q^T A is recovered to f32 accuracy
+ *   by splitting Q into two bf16 terms.  Gram matrices, Cholesky factors and
+ *   the small SVD stay f64 in every mode. */
+typedef enum { RSVD_PREC_PLAIN = 0, RSVD_PREC_BF16_MIXED = 1 } rsvd_precision;
+
+/* Parameters of Alg. rqb / Alg. RSVDalgorithm. */
+typedef struct {
+    int32_t  p;          /* oversampling, l = k + p (default 10, Sec. 3.3 remark) */
+    int32_t  q;          /* subspace iterations (default 2, Sec. 3.3 remark)    */
+    uint64_t seed;       /* Philox key of Omega                                  */
+    uint32_t stream_id;  /* Philox counter word 2 of Omega (batch index)        */
+    int32_t  sdist;      /* rsvd_sdist                                           */
+    int32_t  precision;  /* rsvd_precision                                       */
+    int32_t  reserved[3];
+} rsvd_params;
+
+/* Device-side outcome record (optional; written by the last kernel). */
+typedef struct {
+    int32_t  l;          /* sketch width actually used: min(k + p, m, n)          */
+    int32_t  q;          /* subspace iterations performed                         */
+    int32_t  p;          /* oversampling actually used (l - k)                    */
+    uint32_t flags;      /* RSVD_FLAG_* bits                                      */
+    double   est_err;    /* reserved for the a-posteriori error estimate          */
+} rsvd_info;
+
+#define RSVD_FLAG_CHOL_SHIFT   1u  /* a Gram matrix needed the shifted Cholesky    */
+#define RSVD_FLAG_DEGENERATE   2u  /* a column was numerically zero after shifting */
+#define RSVD_FLAG_NONFINITE    4u  /* NaN or Inf reached a Gram matrix             */
+#define RSVD_FLAG_JACOBI_SLOW  8u  /* small SVD stopped at its sweep limit         */
+
+/* Status codes. */
+#define RSVD_OK               0
+#define RSVD_ERR_INVALID     -1   /* bad argument (sizes, NULL, workspace, ...)   */
+#define RSVD_ERR_UNSUPPORTED -2   /* dtype / mode / size not supported            */
+#define RSVD_ERR_HIP         -3   /* HIP runtime error, see rsvd_last_hip_error() */
+#define RSVD_ERR_NONFINITE   -4   /* reported by rsvd_sync_info only              */
+#define RSVD_ERR_BREAKDOWN   -5   /* reported by rsvd_sync_info only              */
+
+/* Largest sketch width l = k + p supported by the single-solve path. */
+#define RSVD_MAX_L 128
+
+/* Fill *p with the paper's defaults: p = 10, q = 2, Gaussian Omega, seed 0. */
+void rsvd_default_params(rsvd_params* p);
+
+/* Create / destroy a handle bound to a HIP stream (hipStream_t passed as
+ * void*; NULL = default stream).  The handle owns no device memory. */
+int rsvd_create(rsvd_handle_t* handle, void* hip_stream);
+int rsvd_destroy(rsvd_handle_t handle);
+int rsvd_set_stream(rsvd_handle_t handle, void* hip_stream);
+int rsvd_last_hip_error(rsvd_handle_t handle);
+const char* rsvd_status_string(int status);
+
+/* Workspace bytes needed by rsvd_run / rpca_run for this problem.
+ * Same argument rules as rsvd_run; returns RSVD_ERR_INVALID for bad sizes. */
+int rsvd_workspace_size(rsvd_handle_t handle, int32_t dtype, int64_t m, int64_t n,
+                        int32_t k, const rsvd_params* params, size_t* bytes);
+
+/* Randomized SVD, Alg. RSVDalgorithm (Sec. 3.3):
+ *   [Q, B] = rqb(A, k, p, q); [U~, S, V] = svd(B); U = Q U~; truncate to k.
+ * A      : m x n, leading dimension lda >= n, dtype `dtype`.
+ * k      : target rank, 1 <= k < min(m, n).  l = min(k + p, m, n) <= RSVD_MAX_L.
+ * U      : m x k (ldu >= k) or NULL (left vectors not wanted).
+ * S      : k singular values, descending (f64, required).
+ * V      : n x k (ldv >= k) or NULL (right vectors not wanted).
+ * info   : device pointer to one rsvd_info, or NULL.
+ * Sign convention: each pair (u_i, v_i) is oriented so that the entry of v_i
+ * with the largest magnitude is positive (lowest index on ties). */
+int rsvd_run(rsvd_handle_t handle, int32_t dtype, int64_t m, int64_t n,
+             const void* A, int64_t lda, int32_t k, const rsvd_params* params,
+             void* U, int64_t ldu, double* S, void* V, int64_t ldv,
+             void* work, size_t work_bytes, rsvd_info* info);
+
+/* Randomized PCA, Alg. RPCAalgorithm (Sec. 4.2) with the outputs of Sec. 4.4.
+ * center != 0: the column means mu are removed implicitly (the products use
+ *   A - 1 mu^T without forming it).  center == 0: A is used as is.
+ * rotation : n x k principal directions W = V (ldr >= k), required.
+ * eigvals  : k values S^2 / (m - 1) (f64), required.
+ * sdev     : k values sqrt(eigvals) (f64) or NULL.
+ * x        : m x k principal components U S (ldx >= k) or NULL (retx = FALSE).
+ * center_out : n column means (zeros when center == 0) or NULL. */
+int rpca_run(rsvd_handle_t handle, int32_t dtype, int64_t m, int64_t n,
+             const void* A, int64_t lda, int32_t k, int32_t center,
+             const rsvd_params* params, void* rotation, int64_t ldr,
+             double* eigvals, double* sdev, void* x, int64_t ldx, void* center_out,
+             void* work, size_t work_bytes, rsvd_info* info);
+
+/* Synchronise the handle's stream, copy the device record `dinfo` to the host
+ * record `hinfo`, and map its flags to a status: RSVD_ERR_NONFINITE when
+ * non-finite data reached a Gram matrix, RSVD_ERR_BREAKDOWN when a column
+ * stayed numerically zero after the shifted Cholesky, else RSVD_OK. */
+int rsvd_sync_info(rsvd_handle_t handle, const rsvd_info* dinfo, rsvd_info* hinfo);
+
+/* ---- Optional per-kernel timing ------------------------------------------
+ * When enabled, every product with A (the passes of Alg. rqb and
+ * Alg. subspace_iter) is bracketed by HIP events on the handle's stream, so a
+ * caller can time those kernels inside its own timed region.  Kinds:
+ * 0 = A X (sketch / power-iteration half), 1 = A^T Q (power-iteration half and
+ * the projection B^T).  flops / bytes are the algorithmic counts of the
+ * recorded launches (2 m n l flops; one read of A plus the skinny operands). */
+typedef struct {
+    int32_t count;       /* launches recorded                       */
+    int32_t reserved;
+    double  total_ms;    /* summed event-to-event durations         */
+    double  flops;       /* summed algorithmic flops                */
+    double  bytes;       /* summed algorithmic HBM bytes            */
+} rsvd_kernel_stat;
+
+#define RSVD_PROFILE_KINDS 2
+
+int rsvd_profile_enable(rsvd_handle_t handle, int32_t enable);
+/* Synchronise the stream, sum the recorded intervals per kind into
+ * out[0 .. RSVD_PROFILE_KINDS), and clear the record. */
+int rsvd_profile_collect(rsvd_handle_t handle, rsvd_kernel_stat* out);
+
+/* ---- Building blocks exposed for kernel-level parity tests ------------- */
+
+/* The 32-bit Philox words behind Omega: out[j * 4*groups + 4*c + t] = word t of
+ * Philox4x32-10(counter (j, c, stream_id, 0), key (seed lo, seed hi)) for
+ * j < n, c < groups.  out is a device array of n * 4 * groups uint32. */
+int rsvd_philox_words(rsvd_handle_t handle, int64_t n, int32_t groups,
+                      uint64_t seed, uint32_t stream_id, uint32_t* out);
+
+/* The random test matrix Omega (n x l, row-major, ld = ldo) of Alg. rqb step 2
+ * in f64 (dtype RSVD_F64) or f32 (otherwise), entries per rsvd_sdist. */
+int rsvd_test_matrix(rsvd_handle_t handle, int32_t dtype, int64_t n, int32_t l,
+                     uint64_t seed, uint32_t stream_id, int32_t sdist,
+                     void* out, int64_t ldo);
+
+/* Y = A X (Alg. rqb step 3, Alg. subspace_iter step 4): A m x K (dtype,
+ * lda), X K x c (f64 for RSVD_F64 else f32, ldx), Y m x c (same type as X,
+ * ldy).  c <= RSVD_MAX_L. */
+int rsvd_gemm_nn(rsvd_handle_t handle, int32_t dtype, int64_t m, int64_t K, int32_t c,
+                 const void* A, int64_t lda, const void* X, int64_t ldx,
+                 void* Y, int64_t ldy, void* work, size_t work_bytes);
+
+/* Z = A^T Q (Alg. subspace_iter step 3; Alg. rqb step 10 gives B^T): A m x n
+ * (dtype, lda), Q m x c (f64/f32, ldq), Z n x c (ldz).  c <= RSVD_MAX_L. */
+int rsvd_gemm_tn(rsvd_handle_t handle, int32_t dtype, int64_t m, int64_t n, int32_t c,
+                 const void* A, int64_t lda, const void* Q, int64_t ldq,
+                 void* Z, int64_t ldz, void* work, size_t work_bytes);
+
+/* Economic QR of Y (m x c, f64 or f32 per dtype, ldy) in place: Y <- Q with
+ * orthonormal columns, R (c x c, f64, row-major, ld c) upper triangular with
+ * positive diagonal, Y = Q R.  CholeskyQR2, shifted CholeskyQR3 on breakdown.
+ * flags (device uint32, may be NULL) receives RSVD_FLAG_* bits. */
+int rsvd_orthonormalize(rsvd_handle_t handle, int32_t dtype, int64_t m, int32_t c,
+                        void* Y, int64_t ldy, double* R, uint32_t* flags,
+                        void* work, size_t work_bytes);
+
+/* Workspace bytes for the three building blocks above at these sizes. */
+int rsvd_block_workspace_size(rsvd_handle_t handle, int32_t dtype, int64_t m,
+                              int64_t n, int32_t c, size_t* bytes);
+
+/* SVD of a small square upper-triangular R (c x c, f64, row-major, ld c):
+ * R = W diag(s) J^T with s descending.  W and J are c x c (f64, row-major,
+ * ld c).  One-sided Jacobi, one workgroup. */
+int rsvd_small_svd(rsvd_handle_t handle, int32_t c, const double* R, double* s,
+                   double* W, double* J, uint32_t* flags, void* work, size_t work_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RSVD_MI355X_H */

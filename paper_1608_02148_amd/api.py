@@ -1,0 +1,227 @@
+"""Torch-facing wrappers of the C ABI (device memory and streams only).
+
+Every step of the computation runs in the HIP library; these functions only
+check shapes, allocate outputs / workspace as torch tensors and pass raw device
+pointers together with torch's current HIP stream.
+"""
+import ctypes
+
+import torch
+
+from . import lib as L
+
+_DTYPES = {torch.float64: L.RSVD_F64, torch.float32: L.RSVD_F32, torch.bfloat16: L.RSVD_BF16}
+
+_handles = {}
+
+
+def handle(device=None):
+    """Per-device library handle bound to torch's current stream."""
+    lib = L.load()
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    idx = dev.index if dev.index is not None else torch.cuda.current_device()
+    h = _handles.get(idx)
+    if h is None:
+        h = ctypes.c_void_p()
+        with torch.cuda.device(idx):
+            L.check(lib.rsvd_create(ctypes.byref(h), None), "rsvd_create")
+        _handles[idx] = h
+    with torch.cuda.device(idx):
+        stream = torch.cuda.current_stream(idx).cuda_stream
+    L.check(lib.rsvd_set_stream(h, ctypes.c_void_p(stream)), "rsvd_set_stream")
+    return h
+
+
+def make_params(p=10, q=2, seed=0, stream_id=0, sdist="normal", precision="plain"):
+    prm = L.Params()
+    L.load().rsvd_default_params(ctypes.byref(prm))
+    prm.p, prm.q, prm.seed, prm.stream_id = int(p), int(q), int(seed), int(stream_id)
+    prm.sdist = L.SDIST[sdist]
+    prm.precision = L.PRECISION[precision]
+    return prm
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _check_matrix(A):
+    if not isinstance(A, torch.Tensor) or A.dim() != 2 or not A.is_cuda:
+        raise ValueError("A must be a 2-D tensor on a GPU")
+    if A.dtype not in _DTYPES:
+        raise ValueError(f"unsupported dtype {A.dtype}")
+    if A.stride(1) != 1:
+        raise ValueError("A must be row-major (unit stride along columns)")
+    return _DTYPES[A.dtype]
+
+
+def out_dtype(A):
+    return torch.float64 if A.dtype == torch.float64 else torch.float32
+
+
+def workspace_size(A, k, prm):
+    dt = _check_matrix(A)
+    m, n = A.shape
+    nbytes = ctypes.c_size_t()
+    L.check(L.load().rsvd_workspace_size(handle(A.device), dt, m, n, int(k), ctypes.byref(prm),
+                                         ctypes.byref(nbytes)), "rsvd_workspace_size")
+    return nbytes.value
+
+
+def workspace(nbytes, device):
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def rsvd(A, k, p=10, q=2, seed=0, stream_id=0, sdist="normal", precision="plain",
+         compute_u=True, compute_v=True, work=None, out=None, info=None):
+    """Randomized SVD (Alg. RSVDalgorithm).  Returns (U m x k, S k, V n x k).
+
+    U / V are None when not requested.  ``work`` (uint8 tensor) and ``out``
+    (tuple U, S, V) may be passed to reuse buffers; ``info`` may be a 24-byte
+    uint8 device tensor receiving the device-side record.
+    """
+    dt = _check_matrix(A)
+    m, n = A.shape
+    prm = make_params(p, q, seed, stream_id, sdist, precision)
+    h = handle(A.device)
+    nbytes = workspace_size(A, k, prm)
+    if work is None or work.numel() < nbytes:
+        work = workspace(nbytes, A.device)
+    od = out_dtype(A)
+    if out is None:
+        U = torch.empty(m, k, dtype=od, device=A.device) if compute_u else None
+        S = torch.empty(k, dtype=torch.float64, device=A.device)
+        V = torch.empty(n, k, dtype=od, device=A.device) if compute_v else None
+    else:
+        U, S, V = out
+    st = L.load().rsvd_run(h, dt, m, n, _ptr(A), A.stride(0), int(k), ctypes.byref(prm),
+                           _ptr(U), U.stride(0) if U is not None else 0, _ptr(S),
+                           _ptr(V), V.stride(0) if V is not None else 0,
+                           _ptr(work), work.numel(), _ptr(info))
+    L.check(st, "rsvd_run")
+    return U, S, V
+
+
+def rpca(A, k, center=True, retx=True, p=10, q=2, seed=0, stream_id=0, sdist="normal",
+         precision="plain", work=None, info=None):
+    """Randomized PCA (Alg. RPCAalgorithm) with implicit centring.
+
+    Returns a dict: rotation (n x k), eigvals, sdev, x (m x k or None), center.
+    """
+    dt = _check_matrix(A)
+    m, n = A.shape
+    prm = make_params(p, q, seed, stream_id, sdist, precision)
+    h = handle(A.device)
+    nbytes = workspace_size(A, k, prm)
+    if work is None or work.numel() < nbytes:
+        work = workspace(nbytes, A.device)
+    od = out_dtype(A)
+    rot = torch.empty(n, k, dtype=od, device=A.device)
+    ev = torch.empty(k, dtype=torch.float64, device=A.device)
+    sd = torch.empty(k, dtype=torch.float64, device=A.device)
+    x = torch.empty(m, k, dtype=od, device=A.device) if retx else None
+    ctr = torch.empty(n, dtype=od, device=A.device)
+    st = L.load().rpca_run(h, dt, m, n, _ptr(A), A.stride(0), int(k), int(bool(center)),
+                           ctypes.byref(prm), _ptr(rot), rot.stride(0), _ptr(ev), _ptr(sd),
+                           _ptr(x), x.stride(0) if x is not None else 0, _ptr(ctr),
+                           _ptr(work), work.numel(), _ptr(info))
+    L.check(st, "rpca_run")
+    return dict(rotation=rot, eigvals=ev, sdev=sd, x=x, center=ctr)
+
+
+def new_info(device):
+    return torch.zeros(ctypes.sizeof(L.Info), dtype=torch.uint8, device=device)
+
+
+def sync_info(info):
+    """Synchronise and decode a device info record; returns (status, Info)."""
+    host = L.Info()
+    st = L.load().rsvd_sync_info(handle(info.device), _ptr(info), ctypes.byref(host))
+    return st, host
+
+
+def profile_enable(enable=True, device=None):
+    """Bracket every product with A by HIP events on the library's stream."""
+    L.check(L.load().rsvd_profile_enable(handle(device), int(bool(enable))), "rsvd_profile_enable")
+
+
+def profile_collect(device=None):
+    """Synchronise and return {kind: dict(count, total_ms, flops, bytes)}."""
+    stats = (L.KernelStat * L.PROFILE_KINDS)()
+    L.check(L.load().rsvd_profile_collect(handle(device), stats), "rsvd_profile_collect")
+    return {name: dict(count=s.count, total_ms=s.total_ms, flops=s.flops, bytes=s.bytes)
+            for name, s in zip(L.PROFILE_NAMES, stats)}
+
+
+# ---------------------------------------------------------------- building blocks
+
+def philox_words(n, groups, seed, stream_id=0, device="cuda"):
+    out = torch.empty(n, 4 * groups, dtype=torch.int32, device=device)
+    L.check(L.load().rsvd_philox_words(handle(device), n, groups, seed, stream_id, _ptr(out)),
+            "rsvd_philox_words")
+    return out
+
+
+def test_matrix(n, l, seed, stream_id=0, sdist="normal", dtype=torch.float64, device="cuda"):
+    out = torch.empty(n, l, dtype=dtype, device=device)
+    dt = L.RSVD_F64 if dtype == torch.float64 else L.RSVD_F32
+    L.check(L.load().rsvd_test_matrix(handle(device), dt, n, l, seed, stream_id, L.SDIST[sdist],
+                                      _ptr(out), out.stride(0)), "rsvd_test_matrix")
+    return out
+
+
+def _block_ws(dt, m, n, c, device):
+    nbytes = ctypes.c_size_t()
+    L.check(L.load().rsvd_block_workspace_size(handle(device), dt, m, n, c, ctypes.byref(nbytes)),
+            "rsvd_block_workspace_size")
+    return workspace(nbytes.value, device)
+
+
+def gemm_nn(A, X):
+    """Y = A X with the library's product kernel."""
+    dt = _check_matrix(A)
+    m, K = A.shape
+    c = X.shape[1]
+    Y = torch.empty(m, c, dtype=out_dtype(A), device=A.device)
+    L.check(L.load().rsvd_gemm_nn(handle(A.device), dt, m, K, c, _ptr(A), A.stride(0), _ptr(X),
+                                  X.stride(0), _ptr(Y), Y.stride(0), None, 0), "rsvd_gemm_nn")
+    return Y
+
+
+def gemm_tn(A, Q):
+    """Z = A^T Q with the library's split-K product kernel."""
+    dt = _check_matrix(A)
+    m, n = A.shape
+    c = Q.shape[1]
+    Z = torch.empty(n, c, dtype=out_dtype(A), device=A.device)
+    work = _block_ws(dt, m, n, c, A.device)
+    L.check(L.load().rsvd_gemm_tn(handle(A.device), dt, m, n, c, _ptr(A), A.stride(0), _ptr(Q),
+                                  Q.stride(0), _ptr(Z), Z.stride(0), _ptr(work), work.numel()),
+            "rsvd_gemm_tn")
+    return Z
+
+
+def orthonormalize(Y):
+    """In-place CholeskyQR2 of Y (m x c); returns (Y, R, flags tensor)."""
+    dt = _check_matrix(Y)
+    m, c = Y.shape
+    R = torch.empty(c, c, dtype=torch.float64, device=Y.device)
+    flags = torch.zeros(1, dtype=torch.int32, device=Y.device)
+    work = _block_ws(dt, m, m, c, Y.device)
+    L.check(L.load().rsvd_orthonormalize(handle(Y.device), dt, m, c, _ptr(Y), Y.stride(0), _ptr(R),
+                                         _ptr(flags), _ptr(work), work.numel()), "rsvd_orthonormalize")
+    return Y, R, flags
+
+
+def small_svd(R):
+    """R (c x c, f64) = W diag(s) J^T via the one-workgroup Jacobi kernel."""
+    c = R.shape[0]
+    R = R.contiguous()
+    s = torch.empty(c, dtype=torch.float64, device=R.device)
+    W = torch.empty(c, c, dtype=torch.float64, device=R.device)
+    J = torch.empty(c, c, dtype=torch.float64, device=R.device)
+    flags = torch.zeros(1, dtype=torch.int32, device=R.device)
+    work = _block_ws(L.RSVD_F64, c, c, c, R.device)
+    L.check(L.load().rsvd_small_svd(handle(R.device), c, _ptr(R), _ptr(s), _ptr(W), _ptr(J), _ptr(flags),
+                                    _ptr(work), work.numel()), "rsvd_small_svd")
+    return s, W, J, flags

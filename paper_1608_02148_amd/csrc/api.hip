@@ -1,0 +1,635 @@
+// C ABI and host orchestration of the randomized SVD / PCA hot path.
+//
+// One solve (Alg. RSVDalgorithm over Alg. rqb with Alg. subspace_iter):
+//   Omega -> Y = A Omega -> [orth(Y); Z = A^T Y; orth(Z); Y = A Z] x q
+//   -> orth(Y) -> B^T = A^T Y -> B^T = Q_b R_b -> R_b = W S J^T (Jacobi)
+//   -> V = Q_b W_k -> sign rule -> U = Q J_k.
+// orth() is CholeskyQR2 (shifted CholeskyQR3 when needed) in place.  Every
+// step is a kernel on the handle's stream; nothing synchronises the host.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "launch.hpp"
+
+namespace rsvd {
+
+constexpr size_t kAlign = 256;
+
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+    size_t off = 0;
+    size_t take(size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; }
+};
+
+inline size_t elem_size(int dtype) { return dtype == RSVD_F64 ? 8 : (dtype == RSVD_F32 ? 4 : 2); }
+inline size_t comp_size(int dtype) { return dtype == RSVD_F64 ? 8 : 4; }
+
+// Work split heuristics (deterministic for a given device and shape).
+struct Splits {
+    int tn;      // split of the m-reduction in A^T Q
+    int gram_m;  // split of the m-reduction of an m x l Gram matrix
+    int gram_n;  // split of the n-reduction of an n x l Gram matrix
+    int colsum;  // row split of the column-mean pass
+};
+
+inline int gram_split(int64_t rows, int num_cu) {
+    return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(cdiv(rows, 256), 2 * num_cu)));
+}
+
+inline Splits make_splits(int64_t m, int64_t n, int num_cu) {
+    Splits s;
+    const int64_t tn_tiles = cdiv(n, 128);
+    s.tn = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(cdiv(2 * num_cu, tn_tiles), cdiv(m, 256))));
+    s.gram_m = gram_split(m, num_cu);
+    s.gram_n = gram_split(n, num_cu);
+    const int64_t cs_cols = cdiv(n, 256);
+    s.colsum = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(cdiv(2 * num_cu, cs_cols), cdiv(m, 64))));
+    return s;
+}
+
+struct Plan {
+    int dtype = 0;
+    int64_t m = 0, n = 0;
+    int k = 0, p = 0, q = 0, l = 0, Lp = 0, kp = 0;
+    Splits sp{};
+    size_t Y = 0, Z = 0, Om = 0, part = 0, gram = 0, rinv = 0, racc = 0, jw = 0, jj = 0, sigma = 0,
+           xv = 0, xu = 0, jk = 0, vtmp = 0, mu = 0, mupart = 0, status = 0, bytes = 0;
+};
+
+inline int validate(int32_t dtype, int64_t m, int64_t n, int32_t k, const rsvd_params* prm) {
+    if (dtype != RSVD_F64 && dtype != RSVD_F32 && dtype != RSVD_BF16) return RSVD_ERR_UNSUPPORTED;
+    if (m < 1 || n < 1 || k < 1 || k >= std::min(m, n)) return RSVD_ERR_INVALID;
+    if (!prm || prm->p < 0 || prm->q < 0) return RSVD_ERR_INVALID;
+    if (prm->sdist < RSVD_NORMAL || prm->sdist > RSVD_RADEMACHER) return RSVD_ERR_INVALID;
+    if (prm->precision != RSVD_PREC_PLAIN) return RSVD_ERR_UNSUPPORTED;
+    if (m > (int64_t(1) << 32) || n > (int64_t(1) << 32)) return RSVD_ERR_UNSUPPORTED;
+    const int64_t l = std::min<int64_t>(static_cast<int64_t>(k) + prm->p, std::min(m, n));
+    if (l > RSVD_MAX_L) return RSVD_ERR_UNSUPPORTED;
+    return RSVD_OK;
+}
+
+inline Plan make_plan(int dtype, int64_t m, int64_t n, int k, const rsvd_params* prm, int num_cu) {
+    Plan P;
+    P.dtype = dtype; P.m = m; P.n = n; P.k = k; P.q = prm->q;
+    P.l = static_cast<int>(std::min<int64_t>(static_cast<int64_t>(k) + prm->p, std::min(m, n)));
+    P.p = P.l - k;
+    P.Lp = tile_cols(P.l);
+    P.kp = tile_cols(k);
+    P.sp = make_splits(m, n, num_cu);
+    const size_t cs = comp_size(dtype);
+    Layout L;
+    P.status = L.take(kAlign);
+    P.Y = L.take(static_cast<size_t>(m) * P.Lp * cs);
+    P.Z = L.take(static_cast<size_t>(n) * P.Lp * cs);
+    P.Om = L.take(static_cast<size_t>(n) * P.Lp * cs);
+    const size_t part_tn = static_cast<size_t>(P.sp.tn) * n * P.Lp * cs;
+    const size_t part_g = static_cast<size_t>(std::max(P.sp.gram_m, P.sp.gram_n)) * P.Lp * P.Lp * 8;
+    P.part = L.take(std::max(part_tn, part_g));
+    P.gram = L.take(static_cast<size_t>(P.Lp) * P.Lp * 8);
+    P.rinv = L.take(static_cast<size_t>(P.Lp) * P.Lp * cs);
+    P.racc = L.take(static_cast<size_t>(P.Lp) * P.Lp * 8);
+    P.jw = L.take(static_cast<size_t>(P.Lp) * P.Lp * 8);
+    P.jj = L.take(static_cast<size_t>(P.Lp) * P.Lp * 8);
+    P.sigma = L.take(static_cast<size_t>(P.Lp) * 8);
+    P.xv = L.take(static_cast<size_t>(P.Lp) * P.kp * cs);
+    P.xu = L.take(static_cast<size_t>(P.Lp) * P.kp * cs);
+    P.jk = L.take(static_cast<size_t>(P.Lp) * P.kp * 8);
+    P.vtmp = L.take(static_cast<size_t>(n) * P.kp * cs);
+    P.mu = L.take(static_cast<size_t>(n) * 8);
+    P.mupart = L.take(static_cast<size_t>(P.sp.colsum) * n * 8);
+    P.bytes = L.off;
+    return P;
+}
+
+template <typename T> inline T* at(void* work, size_t off) {
+    return reinterpret_cast<T*>(static_cast<unsigned char*>(work) + off);
+}
+
+#define RSVD_TRY(expr)                                   \
+    do {                                                 \
+        hipError_t _e = (expr);                          \
+        if (_e != hipSuccess) return _e;                 \
+    } while (0)
+
+// In-place orthonormalisation of M (rows x l, ld ldm, precision TC):
+// CholeskyQR2, with a shifted first pass and a third pass when needed.
+// racc (optional, f64 l x l) receives the product of the R factors.
+template <typename TC>
+hipError_t orthonormalize(hipStream_t st, TC* M, int64_t ldm, int64_t rows, int l, int Lp, int S,
+                          double* part, double* gram, TC* rinv, double* racc, uint32_t* status,
+                          int num_cu) {
+    (void)num_cu;
+    static bool ready = false;
+    const size_t lds = (static_cast<size_t>(l) * (l + 1) + 2 * l) * sizeof(double);
+    if (!ready) {
+        RSVD_TRY(allow_lds(chol_kernel<TC>, (static_cast<size_t>(CHOL_MAX_L) * (CHOL_MAX_L + 1) + 2 * CHOL_MAX_L) * 8));
+        ready = true;
+    }
+    for (int pass = 1; pass <= 3; ++pass) {
+        const uint32_t* skip = (pass == 3) ? status : nullptr;
+        RSVD_TRY((launch_gemm<TC, TC, double, MODE_TN>(st, M, ldm, l, rows, M, ldm, l, part, Lp, S,
+                                                      static_cast<int64_t>(Lp) * Lp, nullptr, skip,
+                                                      ST_SHIFT_PENDING)));
+        if (S > 1) RSVD_TRY(launch_reduce<double>(st, part, S, static_cast<int64_t>(Lp) * Lp, Lp, l, l,
+                                                  gram, Lp, skip, ST_SHIFT_PENDING));
+        CholArgs ca;
+        ca.part = (S > 1) ? gram : part; ca.S = 1; ca.part_stride = 0; ca.ldp = Lp;
+        ca.l = l; ca.mrows = rows; ca.rinv = rinv; ca.ldr = Lp; ca.rout = nullptr;
+        ca.racc = racc; ca.status = status; ca.pass = pass; ca.skip_unless_pending = (pass == 3);
+        hipLaunchKernelGGL(chol_kernel<TC>, dim3(1), dim3(CHOL_THREADS), lds, st, ca);
+        RSVD_TRY(hipGetLastError());
+        RSVD_TRY((launch_gemm<TC, TC, TC, MODE_NN>(st, M, ldm, rows, l, rinv, Lp, l, M, ldm, 1, 0,
+                                                  nullptr, skip, ST_SHIFT_PENDING)));
+    }
+    return hipSuccess;
+}
+
+// Optional event bracketing of the products with A (rsvd_profile_enable).
+inline hipEvent_t pool_event(rsvd_handle_t h) {
+    if (h->pool_used == h->event_pool.size()) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        h->event_pool.push_back(e);
+    }
+    return h->event_pool[h->pool_used++];
+}
+
+template <typename F>
+hipError_t timed(rsvd_handle_t h, int kind, double flops, double bytes, F&& launch) {
+    if (!h->profiling) return launch();
+    ProfRecord r;
+    r.kind = kind; r.flops = flops; r.bytes = bytes;
+    r.start = pool_event(h);
+    r.stop = pool_event(h);
+    if (!r.start || !r.stop) return hipErrorOutOfMemory;
+    RSVD_TRY(hipEventRecord(r.start, h->stream));
+    RSVD_TRY(launch());
+    RSVD_TRY(hipEventRecord(r.stop, h->stream));
+    h->prof.push_back(r);
+    return hipSuccess;
+}
+
+struct SolveOut {
+    void* U; int64_t ldu;      // m x k or null
+    void* V; int64_t ldv;      // n x k or null (then workspace)
+    double* S;                 // k
+    double* eigvals; double* sdev;   // PCA extras or null
+    void* center_out;
+    int scale_u;               // 1: U columns scaled by sigma (PCA x = U S)
+    int center;
+    rsvd_info* info;
+};
+
+template <typename TA, typename TC>
+hipError_t solve(rsvd_handle_t h, const Plan& P, const TA* A, int64_t lda, const rsvd_params* prm,
+                 const SolveOut& o, void* work) {
+    hipStream_t st = h->stream;
+    const int64_t m = P.m, n = P.n;
+    const int l = P.l, Lp = P.Lp, k = P.k;
+    uint32_t* status = at<uint32_t>(work, P.status);
+    TC* Y = at<TC>(work, P.Y);
+    TC* Z = at<TC>(work, P.Z);
+    TC* Om = at<TC>(work, P.Om);
+    TC* partc = at<TC>(work, P.part);
+    double* partd = at<double>(work, P.part);
+    double* gram = at<double>(work, P.gram);
+    TC* rinv = at<TC>(work, P.rinv);
+    double* racc = at<double>(work, P.racc);
+    double* sigma = at<double>(work, P.sigma);
+    TC* xv = at<TC>(work, P.xv);
+    TC* xu = at<TC>(work, P.xu);
+    double* jk = at<double>(work, P.jk);
+    double* mu = o.center ? at<double>(work, P.mu) : nullptr;
+    const int num_cu = h->dev.num_cu;
+
+    hipLaunchKernelGGL(clear_u32_kernel, dim3(1), dim3(64), 0, st, status, 1);
+    RSVD_TRY(hipGetLastError());
+
+    if (mu) {   // column means (implicit centring, Sec. 4.2)
+        const int S = P.sp.colsum;
+        const int64_t rps = cdiv(m, S);
+        double* mp = at<double>(work, P.mupart);
+        hipLaunchKernelGGL(colsum_partial_kernel<TA>, dim3(static_cast<unsigned>(cdiv(n, 256)), S), dim3(256), 0,
+                           st, A, lda, m, n, rps, mp);
+        hipLaunchKernelGGL(colmean_finish_kernel, dim3(static_cast<unsigned>(cdiv(n, 256))), dim3(256), 0, st,
+                           mp, S, m, n, mu);
+        RSVD_TRY(hipGetLastError());
+    }
+
+    // Alg. rqb steps 2-3: Omega and the sketch Y = A Omega.
+    {
+        const int groups = Lp / 4;
+        const int64_t total = n * groups;
+        hipLaunchKernelGGL(omega_kernel<TC>, dim3(static_cast<unsigned>(cdiv(total, 256))), dim3(256), 0, st,
+                           n, l, Lp, prm->seed, prm->stream_id, prm->sdist, Om, static_cast<int64_t>(Lp));
+        RSVD_TRY(hipGetLastError());
+    }
+    const double pass_flops = 2.0 * static_cast<double>(m) * n * l;
+    const double a_bytes = static_cast<double>(m) * n * sizeof(TA);
+    const double nn_bytes = a_bytes + (static_cast<double>(n) + m) * l * sizeof(TC);
+    const double tn_bytes = a_bytes + (static_cast<double>(m) + n) * l * sizeof(TC);
+    auto ax = [&](const TC* X) -> hipError_t {     // Y (m x Lp) = A X
+        return timed(h, 0, pass_flops, nn_bytes, [&] {
+            return launch_gemm<TA, TC, TC, MODE_NN>(st, A, lda, m, n, X, Lp, l, Y, Lp, 1, 0, mu, nullptr, 0);
+        });
+    };
+    RSVD_TRY(ax(Om));
+
+    auto aty = [&](TC* dst) -> hipError_t {     // dst (n x Lp) = A^T Y
+        const int S = P.sp.tn;
+        if (S == 1)
+            return timed(h, 1, pass_flops, tn_bytes, [&] {
+                return launch_gemm<TA, TC, TC, MODE_TN>(st, A, lda, n, m, Y, Lp, l, dst, Lp, 1, 0, mu, nullptr, 0);
+            });
+        RSVD_TRY(timed(h, 1, pass_flops, tn_bytes, [&] {
+            return launch_gemm<TA, TC, TC, MODE_TN>(st, A, lda, n, m, Y, Lp, l, partc, Lp, S,
+                                                    static_cast<int64_t>(n) * Lp, mu, nullptr, 0);
+        }));
+        return launch_reduce<TC>(st, partc, S, static_cast<int64_t>(n) * Lp, Lp, n, l, dst, Lp);
+    };
+
+    // Alg. subspace_iter: q rounds of orth(Y); Z = orth(A^T Y); Y = A Z.
+    for (int it = 0; it < P.q; ++it) {
+        RSVD_TRY(orthonormalize<TC>(st, Y, Lp, m, l, Lp, P.sp.gram_m, partd, gram, rinv, nullptr, status, num_cu));
+        RSVD_TRY(aty(Z));
+        RSVD_TRY(orthonormalize<TC>(st, Z, Lp, n, l, Lp, P.sp.gram_n, partd, gram, rinv, nullptr, status, num_cu));
+        RSVD_TRY(ax(Z));
+    }
+    // Alg. rqb steps 9-10: Q = qr(Y); B^T = A^T Q.
+    RSVD_TRY(orthonormalize<TC>(st, Y, Lp, m, l, Lp, P.sp.gram_m, partd, gram, rinv, nullptr, status, num_cu));
+    RSVD_TRY(aty(Z));
+    // svd(B): B^T = Q_b R_b (Q_b overwrites Z), R_b = W S J^T by Jacobi.
+    RSVD_TRY(orthonormalize<TC>(st, Z, Lp, n, l, Lp, P.sp.gram_n, partd, gram, rinv, racc, status, num_cu));
+    {
+        static bool ready = false;
+        if (!ready) { RSVD_TRY(allow_lds(jacobi_kernel<TC>, JAC_LDS_LIMIT)); ready = true; }
+        JacobiArgs ja;
+        ja.R = racc; ja.ldr = l; ja.l = l; ja.k = k;
+        ja.gw = at<double>(work, P.jw); ja.gj = at<double>(work, P.jj);
+        ja.sigma = sigma; ja.xv = xv; ja.ldx = Lp; ja.xcols = P.kp; ja.jk = jk;
+        ja.status = status; ja.max_sweeps = 60; ja.tol = 1e-15;
+        const size_t mat = static_cast<size_t>(l) * l * 8;
+        const size_t lds = (2 * mat <= JAC_LDS_LIMIT) ? 2 * mat : (mat <= JAC_LDS_LIMIT ? mat : 0);
+        hipLaunchKernelGGL(jacobi_kernel<TC>, dim3(1), dim3(JAC_THREADS), lds, st, ja);
+        RSVD_TRY(hipGetLastError());
+    }
+    // V = Q_b W_k, sign rule, then U = Q (J_k D) with D = signs (x S for PCA).
+    TC* V = o.V ? static_cast<TC*>(o.V) : at<TC>(work, P.vtmp);
+    const int64_t ldv = o.V ? o.ldv : P.kp;
+    RSVD_TRY((launch_gemm<TC, TC, TC, MODE_NN>(st, Z, Lp, n, l, xv, P.kp, k, V, ldv, 1, 0, nullptr, nullptr, 0)));
+    hipLaunchKernelGGL(sign_lift_kernel<TC>, dim3(k), dim3(256), 0, st, V, ldv, n, l, k, jk, sigma, o.scale_u,
+                       xu, Lp, P.kp);
+    RSVD_TRY(hipGetLastError());
+    if (o.U)
+        RSVD_TRY((launch_gemm<TC, TC, TC, MODE_NN>(st, Y, Lp, m, l, xu, P.kp, k, static_cast<TC*>(o.U), o.ldu,
+                                                  1, 0, nullptr, nullptr, 0)));
+    {
+        const int64_t cnt = std::max<int64_t>(k, o.center_out ? n : 0);
+        hipLaunchKernelGGL(finalize_kernel<TC>, dim3(static_cast<unsigned>(cdiv(cnt, 256))), dim3(256), 0, st,
+                           sigma, k, o.S, o.eigvals, o.sdev, static_cast<double>(m - 1), mu, n,
+                           static_cast<TC*>(o.center_out), status, o.info, l, P.q, P.p);
+        RSVD_TRY(hipGetLastError());
+    }
+    return hipSuccess;
+}
+
+inline int hip_status(rsvd_handle_t h, hipError_t e) {
+    if (e == hipSuccess) return RSVD_OK;
+    h->last_hip_error = static_cast<int>(e);
+    return RSVD_ERR_HIP;
+}
+
+template <typename TA, typename TC>
+int run_typed(rsvd_handle_t h, const Plan& P, const void* A, int64_t lda, const rsvd_params* prm,
+              const SolveOut& o, void* work) {
+    return hip_status(h, solve<TA, TC>(h, P, static_cast<const TA*>(A), lda, prm, o, work));
+}
+
+int dispatch(rsvd_handle_t h, int32_t dtype, const Plan& P, const void* A, int64_t lda,
+             const rsvd_params* prm, const SolveOut& o, void* work) {
+    switch (dtype) {
+        case RSVD_F64: return run_typed<double, double>(h, P, A, lda, prm, o, work);
+        case RSVD_F32: return run_typed<float, float>(h, P, A, lda, prm, o, work);
+        case RSVD_BF16: return run_typed<bf16_t, float>(h, P, A, lda, prm, o, work);
+    }
+    return RSVD_ERR_UNSUPPORTED;
+}
+
+}  // namespace rsvd
+
+using namespace rsvd;
+
+extern "C" {
+
+void rsvd_default_params(rsvd_params* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->p = 10;
+    p->q = 2;
+    p->seed = 0;
+    p->stream_id = 0;
+    p->sdist = RSVD_NORMAL;
+    p->precision = RSVD_PREC_PLAIN;
+}
+
+int rsvd_create(rsvd_handle_t* handle, void* hip_stream) {
+    if (!handle) return RSVD_ERR_INVALID;
+    rsvd_handle_s* h = new rsvd_handle_s();
+    h->stream = static_cast<hipStream_t>(hip_stream);
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        h->dev.device = dev;
+        int cu = 0;
+        if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cu > 0)
+            h->dev.num_cu = cu;
+    }
+    *handle = h;
+    return RSVD_OK;
+}
+
+int rsvd_destroy(rsvd_handle_t handle) {
+    if (handle)
+        for (hipEvent_t e : handle->event_pool) (void)hipEventDestroy(e);
+    delete handle;
+    return RSVD_OK;
+}
+
+int rsvd_set_stream(rsvd_handle_t handle, void* hip_stream) {
+    if (!handle) return RSVD_ERR_INVALID;
+    handle->stream = static_cast<hipStream_t>(hip_stream);
+    return RSVD_OK;
+}
+
+int rsvd_last_hip_error(rsvd_handle_t handle) { return handle ? handle->last_hip_error : 0; }
+
+const char* rsvd_status_string(int status) {
+    switch (status) {
+        case RSVD_OK: return "ok";
+        case RSVD_ERR_INVALID: return "invalid argument";
+        case RSVD_ERR_UNSUPPORTED: return "unsupported dtype, mode or size";
+        case RSVD_ERR_HIP: return "HIP runtime error";
+        case RSVD_ERR_NONFINITE: return "non-finite values reached a Gram matrix";
+        case RSVD_ERR_BREAKDOWN: return "numerical breakdown after the shifted Cholesky";
+    }
+    return "unknown status";
+}
+
+int rsvd_workspace_size(rsvd_handle_t handle, int32_t dtype, int64_t m, int64_t n, int32_t k,
+                        const rsvd_params* params, size_t* bytes) {
+    if (!handle || !bytes) return RSVD_ERR_INVALID;
+    const int v = validate(dtype, m, n, k, params);
+    if (v != RSVD_OK) return v;
+    *bytes = make_plan(dtype, m, n, k, params, handle->dev.num_cu).bytes;
+    return RSVD_OK;
+}
+
+static int check_common(rsvd_handle_t handle, int32_t dtype, int64_t m, int64_t n, const void* A,
+                        int64_t lda, int32_t k, const rsvd_params* params, void* work,
+                        size_t work_bytes, Plan* plan) {
+    if (!handle) return RSVD_ERR_INVALID;
+    const int v = validate(dtype, m, n, k, params);
+    if (v != RSVD_OK) return v;
+    if (!A || lda < n || !work) return RSVD_ERR_INVALID;
+    if (reinterpret_cast<uintptr_t>(work) % kAlign != 0) return RSVD_ERR_INVALID;
+    *plan = make_plan(dtype, m, n, k, params, handle->dev.num_cu);
+    if (work_bytes < plan->bytes) return RSVD_ERR_INVALID;
+    return RSVD_OK;
+}
+
+int rsvd_run(rsvd_handle_t handle, int32_t dtype, int64_t m, int64_t n, const void* A, int64_t lda,
+             int32_t k, const rsvd_params* params, void* U, int64_t ldu, double* S, void* V,
+             int64_t ldv, void* work, size_t work_bytes, rsvd_info* info) {
+    Plan P;
+    const int c = check_common(handle, dtype, m, n, A, lda, k, params, work, work_bytes, &P);
+    if (c != RSVD_OK) return c;
+    if (!S || (U && ldu < k) || (V && ldv < k)) return RSVD_ERR_INVALID;
+    SolveOut o{};
+    o.U = U; o.ldu = ldu; o.V = V; o.ldv = ldv; o.S = S;
+    o.scale_u = 0; o.center = 0; o.info = info;
+    return dispatch(handle, dtype, P, A, lda, params, o, work);
+}
+
+int rpca_run(rsvd_handle_t handle, int32_t dtype, int64_t m, int64_t n, const void* A, int64_t lda,
+             int32_t k, int32_t center, const rsvd_params* params, void* rotation, int64_t ldr,
+             double* eigvals, double* sdev, void* x, int64_t ldx, void* center_out, void* work,
+             size_t work_bytes, rsvd_info* info) {
+    Plan P;
+    const int c = check_common(handle, dtype, m, n, A, lda, k, params, work, work_bytes, &P);
+    if (c != RSVD_OK) return c;
+    if (!rotation || ldr < k || !eigvals || (x && ldx < k)) return RSVD_ERR_INVALID;
+    SolveOut o{};
+    o.U = x; o.ldu = ldx; o.V = rotation; o.ldv = ldr; o.S = nullptr;
+    o.eigvals = eigvals; o.sdev = sdev; o.center_out = center_out;
+    o.scale_u = 1; o.center = center ? 1 : 0; o.info = info;
+    return dispatch(handle, dtype, P, A, lda, params, o, work);
+}
+
+int rsvd_sync_info(rsvd_handle_t handle, const rsvd_info* dinfo, rsvd_info* hinfo) {
+    if (!handle || !dinfo || !hinfo) return RSVD_ERR_INVALID;
+    hipError_t e = hipMemcpyAsync(hinfo, dinfo, sizeof(rsvd_info), hipMemcpyDeviceToHost, handle->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(handle->stream);
+    if (e != hipSuccess) return hip_status(handle, e);
+    if (hinfo->flags & RSVD_FLAG_NONFINITE) return RSVD_ERR_NONFINITE;
+    if (hinfo->flags & RSVD_FLAG_DEGENERATE) return RSVD_ERR_BREAKDOWN;
+    return RSVD_OK;
+}
+
+int rsvd_profile_enable(rsvd_handle_t handle, int32_t enable) {
+    if (!handle) return RSVD_ERR_INVALID;
+    handle->profiling = enable != 0;
+    return RSVD_OK;
+}
+
+int rsvd_profile_collect(rsvd_handle_t handle, rsvd_kernel_stat* out) {
+    if (!handle || !out) return RSVD_ERR_INVALID;
+    for (int k = 0; k < RSVD_PROFILE_KINDS; ++k) out[k] = rsvd_kernel_stat{0, 0, 0.0, 0.0, 0.0};
+    hipError_t e = hipStreamSynchronize(handle->stream);
+    for (const ProfRecord& r : handle->prof) {
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.start, r.stop);
+        if (r.kind < 0 || r.kind >= RSVD_PROFILE_KINDS) continue;
+        rsvd_kernel_stat& s = out[r.kind];
+        s.count += 1;
+        s.total_ms += ms;
+        s.flops += r.flops;
+        s.bytes += r.bytes;
+    }
+    handle->prof.clear();
+    handle->pool_used = 0;
+    return hip_status(handle, e);
+}
+
+// ---------------------------------------------------------- building blocks
+
+int rsvd_philox_words(rsvd_handle_t handle, int64_t n, int32_t groups, uint64_t seed, uint32_t stream_id,
+                      uint32_t* out) {
+    if (!handle || n < 1 || groups < 1 || !out) return RSVD_ERR_INVALID;
+    const int64_t total = n * groups;
+    hipLaunchKernelGGL(philox_words_kernel, dim3(static_cast<unsigned>(cdiv(total, 256))), dim3(256), 0,
+                       handle->stream, n, groups, seed, stream_id, out);
+    return hip_status(handle, hipGetLastError());
+}
+
+int rsvd_test_matrix(rsvd_handle_t handle, int32_t dtype, int64_t n, int32_t l, uint64_t seed,
+                     uint32_t stream_id, int32_t sdist, void* out, int64_t ldo) {
+    if (!handle || n < 1 || l < 1 || !out || ldo < l) return RSVD_ERR_INVALID;
+    if (sdist < RSVD_NORMAL || sdist > RSVD_RADEMACHER) return RSVD_ERR_INVALID;
+    const int groups = (l + 3) / 4;
+    const int64_t total = n * groups;
+    if (dtype == RSVD_F64)
+        hipLaunchKernelGGL(omega_kernel<double>, dim3(static_cast<unsigned>(cdiv(total, 256))), dim3(256), 0,
+                           handle->stream, n, l, l, seed, stream_id, sdist, static_cast<double*>(out), ldo);
+    else
+        hipLaunchKernelGGL(omega_kernel<float>, dim3(static_cast<unsigned>(cdiv(total, 256))), dim3(256), 0,
+                           handle->stream, n, l, l, seed, stream_id, sdist, static_cast<float*>(out), ldo);
+    return hip_status(handle, hipGetLastError());
+}
+
+static Plan block_plan(int32_t dtype, int64_t m, int64_t n, int32_t c, int num_cu) {
+    rsvd_params prm;
+    rsvd_default_params(&prm);
+    prm.p = 0;
+    Plan P;
+    P.dtype = dtype; P.m = m; P.n = n; P.l = c; P.Lp = tile_cols(c);
+    P.sp = make_splits(m, n, num_cu);
+    const size_t cs = comp_size(dtype);
+    Layout L;
+    P.status = L.take(kAlign);
+    P.part = L.take(std::max(static_cast<size_t>(P.sp.tn) * n * P.Lp * cs,
+                             static_cast<size_t>(std::max(P.sp.gram_m, P.sp.gram_n)) * P.Lp * P.Lp * 8));
+    P.gram = L.take(static_cast<size_t>(P.Lp) * P.Lp * 8);
+    P.rinv = L.take(static_cast<size_t>(P.Lp) * P.Lp * cs);
+    P.jw = L.take(static_cast<size_t>(P.Lp) * P.Lp * 8);
+    P.jj = L.take(static_cast<size_t>(P.Lp) * P.Lp * 8);
+    P.jk = L.take(static_cast<size_t>(P.Lp) * P.Lp * 8);
+    P.bytes = L.off;
+    (void)prm;
+    return P;
+}
+
+int rsvd_block_workspace_size(rsvd_handle_t handle, int32_t dtype, int64_t m, int64_t n, int32_t c,
+                              size_t* bytes) {
+    if (!handle || !bytes || m < 1 || n < 1 || c < 1 || c > RSVD_MAX_L) return RSVD_ERR_INVALID;
+    *bytes = block_plan(dtype, m, n, c, handle->dev.num_cu).bytes;
+    return RSVD_OK;
+}
+
+}  // extern "C"
+
+template <typename TA, typename TC>
+static hipError_t gemm_nn_typed(hipStream_t st, int64_t m, int64_t K, int c, const void* A, int64_t lda,
+                                const void* X, int64_t ldx, void* Y, int64_t ldy) {
+    return launch_gemm<TA, TC, TC, MODE_NN>(st, static_cast<const TA*>(A), lda, m, K, static_cast<const TC*>(X),
+                                            ldx, c, static_cast<TC*>(Y), ldy, 1, 0, nullptr, nullptr, 0);
+}
+
+extern "C" {
+
+int rsvd_gemm_nn(rsvd_handle_t handle, int32_t dtype, int64_t m, int64_t K, int32_t c, const void* A,
+                 int64_t lda, const void* X, int64_t ldx, void* Y, int64_t ldy, void* work, size_t work_bytes) {
+    (void)work; (void)work_bytes;
+    if (!handle || m < 1 || K < 1 || c < 1 || c > RSVD_MAX_L || !A || !X || !Y) return RSVD_ERR_INVALID;
+    if (lda < K || ldx < c || ldy < c) return RSVD_ERR_INVALID;
+    hipError_t e;
+    switch (dtype) {
+        case RSVD_F64: e = gemm_nn_typed<double, double>(handle->stream, m, K, c, A, lda, X, ldx, Y, ldy); break;
+        case RSVD_F32: e = gemm_nn_typed<float, float>(handle->stream, m, K, c, A, lda, X, ldx, Y, ldy); break;
+        case RSVD_BF16: e = gemm_nn_typed<bf16_t, float>(handle->stream, m, K, c, A, lda, X, ldx, Y, ldy); break;
+        default: return RSVD_ERR_UNSUPPORTED;
+    }
+    return hip_status(handle, e);
+}
+
+}  // extern "C"
+
+template <typename TA, typename TC>
+static hipError_t gemm_tn_typed(rsvd_handle_t h, const Plan& P, int64_t m, int64_t n, int c, const void* A,
+                                int64_t lda, const void* Q, int64_t ldq, void* Z, int64_t ldz, void* work) {
+    hipStream_t st = h->stream;
+    const int S = P.sp.tn;
+    TC* part = at<TC>(work, P.part);
+    if (S == 1)
+        return launch_gemm<TA, TC, TC, MODE_TN>(st, static_cast<const TA*>(A), lda, n, m, static_cast<const TC*>(Q),
+                                                ldq, c, static_cast<TC*>(Z), ldz, 1, 0, nullptr, nullptr, 0);
+    RSVD_TRY((launch_gemm<TA, TC, TC, MODE_TN>(st, static_cast<const TA*>(A), lda, n, m, static_cast<const TC*>(Q),
+                                              ldq, c, part, P.Lp, S, static_cast<int64_t>(n) * P.Lp, nullptr,
+                                              nullptr, 0)));
+    return launch_reduce<TC>(st, part, S, static_cast<int64_t>(n) * P.Lp, P.Lp, n, c, static_cast<TC*>(Z), ldz);
+}
+
+extern "C" {
+
+int rsvd_gemm_tn(rsvd_handle_t handle, int32_t dtype, int64_t m, int64_t n, int32_t c, const void* A,
+                 int64_t lda, const void* Q, int64_t ldq, void* Z, int64_t ldz, void* work, size_t work_bytes) {
+    if (!handle || m < 1 || n < 1 || c < 1 || c > RSVD_MAX_L || !A || !Q || !Z || !work) return RSVD_ERR_INVALID;
+    if (lda < n || ldq < c || ldz < c) return RSVD_ERR_INVALID;
+    const Plan P = block_plan(dtype, m, n, c, handle->dev.num_cu);
+    if (work_bytes < P.bytes) return RSVD_ERR_INVALID;
+    hipError_t e;
+    switch (dtype) {
+        case RSVD_F64: e = gemm_tn_typed<double, double>(handle, P, m, n, c, A, lda, Q, ldq, Z, ldz, work); break;
+        case RSVD_F32: e = gemm_tn_typed<float, float>(handle, P, m, n, c, A, lda, Q, ldq, Z, ldz, work); break;
+        case RSVD_BF16: e = gemm_tn_typed<bf16_t, float>(handle, P, m, n, c, A, lda, Q, ldq, Z, ldz, work); break;
+        default: return RSVD_ERR_UNSUPPORTED;
+    }
+    return hip_status(handle, e);
+}
+
+int rsvd_orthonormalize(rsvd_handle_t handle, int32_t dtype, int64_t m, int32_t c, void* Y, int64_t ldy,
+                        double* R, uint32_t* flags, void* work, size_t work_bytes) {
+    if (!handle || m < 1 || c < 1 || c > RSVD_MAX_L || c > m || !Y || ldy < c || !R || !work)
+        return RSVD_ERR_INVALID;
+    if (dtype != RSVD_F64 && dtype != RSVD_F32) return RSVD_ERR_UNSUPPORTED;
+    const Plan P = block_plan(dtype, m, m, c, handle->dev.num_cu);
+    if (work_bytes < P.bytes) return RSVD_ERR_INVALID;
+    hipStream_t st = handle->stream;
+    uint32_t* status = at<uint32_t>(work, P.status);
+    hipLaunchKernelGGL(clear_u32_kernel, dim3(1), dim3(64), 0, st, status, 1);
+    hipError_t e = hipGetLastError();
+    const int S = gram_split(m, handle->dev.num_cu);
+    if (e == hipSuccess) {
+        if (dtype == RSVD_F64)
+            e = orthonormalize<double>(st, static_cast<double*>(Y), ldy, m, c, P.Lp, S, at<double>(work, P.part),
+                                       at<double>(work, P.gram), at<double>(work, P.rinv), R, status,
+                                       handle->dev.num_cu);
+        else
+            e = orthonormalize<float>(st, static_cast<float*>(Y), ldy, m, c, P.Lp, S, at<double>(work, P.part),
+                                      at<double>(work, P.gram), at<float>(work, P.rinv), R, status,
+                                      handle->dev.num_cu);
+    }
+    if (e == hipSuccess && flags) e = hipMemcpyAsync(flags, status, sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
+    return hip_status(handle, e);
+}
+
+int rsvd_small_svd(rsvd_handle_t handle, int32_t c, const double* R, double* s, double* W, double* J,
+                   uint32_t* flags, void* work, size_t work_bytes) {
+    if (!handle || c < 1 || c > RSVD_MAX_L || !R || !s || !W || !J || !work) return RSVD_ERR_INVALID;
+    const Plan P = block_plan(RSVD_F64, c, c, c, handle->dev.num_cu);
+    if (work_bytes < P.bytes) return RSVD_ERR_INVALID;
+    hipStream_t st = handle->stream;
+    uint32_t* status = at<uint32_t>(work, P.status);
+    hipLaunchKernelGGL(clear_u32_kernel, dim3(1), dim3(64), 0, st, status, 1);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_status(handle, e);
+    static bool ready = false;
+    if (!ready) {
+        e = allow_lds(jacobi_kernel<double>, JAC_LDS_LIMIT);
+        if (e != hipSuccess) return hip_status(handle, e);
+        ready = true;
+    }
+    JacobiArgs ja;
+    ja.R = R; ja.ldr = c; ja.l = c; ja.k = c;
+    ja.gw = at<double>(work, P.jw); ja.gj = at<double>(work, P.jj);
+    ja.sigma = s; ja.xv = W; ja.ldx = c; ja.xcols = c; ja.jk = J;
+    ja.status = status; ja.max_sweeps = 60; ja.tol = 1e-15;
+    const size_t mat = static_cast<size_t>(c) * c * 8;
+    const size_t lds = (2 * mat <= JAC_LDS_LIMIT) ? 2 * mat : (mat <= JAC_LDS_LIMIT ? mat : 0);
+    hipLaunchKernelGGL(jacobi_kernel<double>, dim3(1), dim3(JAC_THREADS), lds, st, ja);
+    e = hipGetLastError();
+    if (e == hipSuccess && flags) e = hipMemcpyAsync(flags, status, sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
+    return hip_status(handle, e);
+}
+
+}  // extern "C"

@@ -1,0 +1,91 @@
+// Internal declarations shared by the HIP translation units of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include <vector>
+
+#include "../../include/rsvd_mi355x.h"
+
+namespace rsvd {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// bf16 storage as raw 16-bit words; conversion to f32 is exact (shift by 16).
+struct bf16_t { uint16_t bits; };
+
+__device__ __forceinline__ float to_f32(bf16_t x) {
+    return __uint_as_float(static_cast<uint32_t>(x.bits) << 16);
+}
+
+template <typename T> struct Conv;
+template <> struct Conv<double> {
+    __device__ static double to(double x) { return x; }
+    __device__ static double to(float x) { return static_cast<double>(x); }
+    __device__ static double to(bf16_t x) { return static_cast<double>(to_f32(x)); }
+};
+template <> struct Conv<float> {
+    __device__ static float to(double x) { return static_cast<float>(x); }
+    __device__ static float to(float x) { return x; }
+    __device__ static float to(bf16_t x) { return to_f32(x); }
+};
+
+// 16x16x4 matrix-core step D += A B for f32 and f64.  Operands: A(i, k) comes
+// from lane i + 16 k and B(k, j) from lane j + 16 k for both types.  Result:
+// lane j + 16 g holds, in accumulator element r, D(row(g, r), j) with
+//   f32: row = 4 g + r        f64: row = g + 4 r
+// (the f64 layout interleaves rows across lane groups; measured on gfx950).
+template <typename T> struct Mfma;
+template <> struct Mfma<float> {
+    typedef v4f acc_t;
+    __device__ __forceinline__ static int row(int g, int r) { return 4 * g + r; }
+    __device__ __forceinline__ static acc_t step(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct Mfma<double> {
+    typedef v4d acc_t;
+    __device__ __forceinline__ static int row(int g, int r) { return g + 4 * r; }
+    __device__ __forceinline__ static acc_t step(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+
+__host__ __device__ constexpr int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+__host__ __device__ constexpr int64_t rup(int64_t a, int64_t b) { return cdiv(a, b) * b; }
+
+// Status word bits kept in the workspace (a superset of RSVD_FLAG_*).
+enum : uint32_t {
+    ST_SHIFT_PENDING = 1u << 16,   // current orthonormalisation needs a 3rd pass
+};
+
+// Per-device properties cached by the handle.
+struct DeviceInfo {
+    int num_cu = 256;
+    int device = 0;
+};
+
+}  // namespace rsvd
+
+namespace rsvd {
+// One recorded launch interval (optional profiling).
+struct ProfRecord {
+    int kind;
+    hipEvent_t start, stop;
+    double flops, bytes;
+};
+}  // namespace rsvd
+
+struct rsvd_handle_s {
+    hipStream_t stream = nullptr;
+    int last_hip_error = 0;
+    rsvd::DeviceInfo dev;
+    bool profiling = false;
+    std::vector<rsvd::ProfRecord> prof;        // recorded intervals
+    std::vector<hipEvent_t> event_pool;        // reusable events
+    size_t pool_used = 0;
+};

@@ -1,0 +1,106 @@
+"""ctypes binding of ``librsvd_mi355x.so`` (argument marshalling only).
+
+The shared library is built in-tree by ``paper_1608_02148_amd.build``.  There
+is no fallback: if the library is missing or fails to load, ``load()`` raises.
+"""
+import ctypes
+import os
+
+from .build import LIB_PATH
+
+c_int32, c_int64, c_uint32, c_uint64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64
+c_void_p, c_size_t, c_double = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_double
+
+RSVD_F64, RSVD_F32, RSVD_BF16 = 0, 1, 2
+SDIST = {"normal": 0, "unif": 1, "rademacher": 2}
+PRECISION = {"plain": 0, "bf16_mixed": 1}
+
+STATUS = {
+    0: "ok", -1: "invalid argument", -2: "unsupported dtype, mode or size",
+    -3: "HIP runtime error", -4: "non-finite values reached a Gram matrix",
+    -5: "numerical breakdown after the shifted Cholesky",
+}
+FLAG_CHOL_SHIFT, FLAG_DEGENERATE, FLAG_NONFINITE, FLAG_JACOBI_SLOW = 1, 2, 4, 8
+MAX_L = 128
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("p", c_int32), ("q", c_int32), ("seed", c_uint64), ("stream_id", c_uint32),
+                ("sdist", c_int32), ("precision", c_int32), ("reserved", c_int32 * 3)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("l", c_int32), ("q", c_int32), ("p", c_int32), ("flags", c_uint32),
+                ("est_err", c_double)]
+
+
+class KernelStat(ctypes.Structure):
+    _fields_ = [("count", c_int32), ("reserved", c_int32), ("total_ms", c_double),
+                ("flops", c_double), ("bytes", c_double)]
+
+
+PROFILE_KINDS = 2
+PROFILE_NAMES = ("A_X", "AT_Q")
+
+
+class RsvdError(RuntimeError):
+    def __init__(self, status, where=""):
+        self.status = status
+        super().__init__(f"{where}: {STATUS.get(status, 'unknown status')} ({status})")
+
+
+_PROTOS = {
+    "rsvd_default_params": (None, [c_void_p]),
+    "rsvd_create": (c_int32, [c_void_p, c_void_p]),
+    "rsvd_destroy": (c_int32, [c_void_p]),
+    "rsvd_set_stream": (c_int32, [c_void_p, c_void_p]),
+    "rsvd_last_hip_error": (c_int32, [c_void_p]),
+    "rsvd_status_string": (ctypes.c_char_p, [c_int32]),
+    "rsvd_workspace_size": (c_int32, [c_void_p, c_int32, c_int64, c_int64, c_int32, c_void_p, c_void_p]),
+    "rsvd_run": (c_int32, [c_void_p, c_int32, c_int64, c_int64, c_void_p, c_int64, c_int32, c_void_p,
+                           c_void_p, c_int64, c_void_p, c_void_p, c_int64, c_void_p, c_size_t, c_void_p]),
+    "rpca_run": (c_int32, [c_void_p, c_int32, c_int64, c_int64, c_void_p, c_int64, c_int32, c_int32,
+                           c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_int64, c_void_p,
+                           c_void_p, c_size_t, c_void_p]),
+    "rsvd_sync_info": (c_int32, [c_void_p, c_void_p, c_void_p]),
+    "rsvd_profile_enable": (c_int32, [c_void_p, c_int32]),
+    "rsvd_profile_collect": (c_int32, [c_void_p, c_void_p]),
+    "rsvd_philox_words": (c_int32, [c_void_p, c_int64, c_int32, c_uint64, c_uint32, c_void_p]),
+    "rsvd_test_matrix": (c_int32, [c_void_p, c_int32, c_int64, c_int32, c_uint64, c_uint32, c_int32,
+                                   c_void_p, c_int64]),
+    "rsvd_gemm_nn": (c_int32, [c_void_p, c_int32, c_int64, c_int64, c_int32, c_void_p, c_int64, c_void_p,
+                               c_int64, c_void_p, c_int64, c_void_p, c_size_t]),
+    "rsvd_gemm_tn": (c_int32, [c_void_p, c_int32, c_int64, c_int64, c_int32, c_void_p, c_int64, c_void_p,
+                               c_int64, c_void_p, c_int64, c_void_p, c_size_t]),
+    "rsvd_orthonormalize": (c_int32, [c_void_p, c_int32, c_int64, c_int32, c_void_p, c_int64, c_void_p,
+                                      c_void_p, c_void_p, c_size_t]),
+    "rsvd_block_workspace_size": (c_int32, [c_void_p, c_int32, c_int64, c_int64, c_int32, c_void_p]),
+    "rsvd_small_svd": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                 c_void_p, c_size_t]),
+}
+
+EXPORTED = tuple(_PROTOS)
+
+_LIB = None
+
+
+def load(path=None):
+    """Load the library once and attach argument types.  Raises if missing."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = path or LIB_PATH
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run `python -m paper_1608_02148_amd.build`")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _PROTOS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _LIB = lib
+    return lib
+
+
+def check(status, where):
+    if status != 0:
+        raise RsvdError(status, where)

@@ -1,0 +1,121 @@
+"""C ABI checks that need no GPU: the library loads, exports every symbol the
+public header declares, and rejects bad arguments before any launch."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1608_02148_amd import lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rsvd_mi355x.h")
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rsvd_\w+|rpca_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return L.load()
+
+
+def test_library_exports_every_declared_symbol(lib):
+    names = header_functions()
+    assert len(names) >= 16
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(L.EXPORTED)
+
+
+def test_struct_layouts_match_header():
+    assert ctypes.sizeof(L.Params) == 40
+    assert ctypes.sizeof(L.Info) == 24
+
+
+def test_default_params_are_the_papers(lib):
+    prm = L.Params()
+    lib.rsvd_default_params(ctypes.byref(prm))
+    assert (prm.p, prm.q, prm.sdist, prm.precision) == (10, 2, 0, 0)
+
+
+def test_status_strings(lib):
+    for code in (0, -1, -2, -3, -4, -5):
+        assert lib.rsvd_status_string(code).decode() == L.STATUS[code]
+
+
+@pytest.fixture(scope="module")
+def handle(lib):
+    h = ctypes.c_void_p()
+    assert lib.rsvd_create(ctypes.byref(h), None) == 0
+    yield h
+    lib.rsvd_destroy(h)
+
+
+def _ws(lib, h, dtype, m, n, k, p=10, q=2, **kw):
+    prm = L.Params()
+    lib.rsvd_default_params(ctypes.byref(prm))
+    prm.p, prm.q = p, q
+    for key, v in kw.items():
+        setattr(prm, key, v)
+    out = ctypes.c_size_t(0)
+    st = lib.rsvd_workspace_size(h, dtype, m, n, k, ctypes.byref(prm), ctypes.byref(out))
+    return st, out.value
+
+
+@pytest.mark.parametrize("m,n,k,p,q,want", [
+    (100, 50, 0, 10, 2, -1),     # k < 1
+    (100, 50, 50, 10, 2, -1),    # k >= min(m, n)
+    (100, 50, 60, 10, 2, -1),
+    (0, 50, 5, 10, 2, -1),
+    (100, 50, 5, -1, 2, -1),     # p < 0
+    (100, 50, 5, 10, -1, -1),    # q < 0
+    (100000, 5000, 200, 20, 2, -2),   # l = 220 exceeds the single-solve limit
+    (100, 50, 5, 10, 2, 0),
+    (100, 50, 45, 10, 2, 0),     # l clamped to min(m, n) = 50
+])
+def test_workspace_argument_rules(lib, handle, m, n, k, p, q, want):
+    st, nbytes = _ws(lib, handle, L.RSVD_F32, m, n, k, p, q)
+    assert st == want
+    if want == 0:
+        assert nbytes > 0 and nbytes % 256 == 0
+
+
+def test_bad_dtype_and_mode_are_unsupported(lib, handle):
+    assert _ws(lib, handle, 7, 100, 50, 5)[0] == -2
+    assert _ws(lib, handle, L.RSVD_F32, 100, 50, 5, sdist=9)[0] == -1
+
+
+def test_run_rejects_null_and_small_workspace_before_launch(lib, handle):
+    prm = L.Params()
+    lib.rsvd_default_params(ctypes.byref(prm))
+    fake = ctypes.c_void_p(256)        # never dereferenced: checks fail first
+    S = ctypes.c_void_p(512)
+    # NULL A
+    assert lib.rsvd_run(handle, L.RSVD_F32, 100, 50, None, 50, 5, ctypes.byref(prm),
+                        None, 0, S, None, 0, fake, 1 << 30, None) == -1
+    # lda < n
+    assert lib.rsvd_run(handle, L.RSVD_F32, 100, 50, fake, 49, 5, ctypes.byref(prm),
+                        None, 0, S, None, 0, fake, 1 << 30, None) == -1
+    # workspace too small
+    assert lib.rsvd_run(handle, L.RSVD_F32, 100, 50, fake, 50, 5, ctypes.byref(prm),
+                        None, 0, S, None, 0, fake, 16, None) == -1
+    # misaligned workspace
+    assert lib.rsvd_run(handle, L.RSVD_F32, 100, 50, fake, 50, 5, ctypes.byref(prm),
+                        None, 0, S, None, 0, ctypes.c_void_p(264), 1 << 30, None) == -1
+    # NULL S
+    assert lib.rsvd_run(handle, L.RSVD_F32, 100, 50, fake, 50, 5, ctypes.byref(prm),
+                        None, 0, None, None, 0, fake, 1 << 30, None) == -1
+    # ldu < k
+    assert lib.rsvd_run(handle, L.RSVD_F32, 100, 50, fake, 50, 5, ctypes.byref(prm),
+                        fake, 4, S, None, 0, fake, 1 << 30, None) == -1
+    # PCA needs rotation and eigvals
+    assert lib.rpca_run(handle, L.RSVD_F32, 100, 50, fake, 50, 5, 1, ctypes.byref(prm),
+                        None, 5, S, None, None, 0, None, fake, 1 << 30, None) == -1
+
+
+def test_precision_mode_unknown_is_rejected(lib, handle):
+    assert _ws(lib, handle, L.RSVD_F32, 100, 50, 5, precision=5)[0] == -2

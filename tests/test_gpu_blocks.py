@@ -1,0 +1,140 @@
+"""Kernel-level parity of the HIP building blocks against the oracle (GPU).
+
+Exact-arithmetic inputs (small integers) make every product exact in f64, f32
+and bf16 whatever the summation order, so those comparisons are bitwise.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import philox as oph
+from oracle import rsvd as orc
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+@pytest.mark.parametrize("n,groups,seed,sid", [(1000, 8, 2148, 0), (257, 33, 2**40 + 12345, 7),
+                                               (5, 1, 0, 2**32 - 1)])
+def test_philox_words_bit_exact(gpu_lib, n, groups, seed, sid):
+    from paper_1608_02148_amd import api
+    got = _np(api.philox_words(n, groups, seed, sid)).astype(np.int64) & 0xFFFFFFFF
+    want = oph.raw_words(n, 4 * groups, seed, sid).astype(np.int64)
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("sdist", ["normal", "unif", "rademacher"])
+def test_test_matrix_matches_oracle(gpu_lib, sdist):
+    from paper_1608_02148_amd import api
+    n, l = 3001, 37
+    want = oph.test_matrix(n, l, 2148, 3, sdist)
+    got64 = _np(api.test_matrix(n, l, 2148, 3, sdist, torch.float64))
+    got32 = _np(api.test_matrix(n, l, 2148, 3, sdist, torch.float32))
+    if sdist == "rademacher":
+        assert np.array_equal(got64, want) and np.array_equal(got32, want)
+    else:
+        np.testing.assert_allclose(got64, want, rtol=0, atol=2e-14)
+        np.testing.assert_allclose(got32, want, rtol=0, atol=3e-6)
+
+
+def _int_matrix(rng, shape, lo=-8, hi=8):
+    return rng.integers(lo, hi + 1, size=shape).astype(np.float64)
+
+
+DT = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("m,K,c", [(300, 257, 5), (129, 64, 30), (1000, 515, 64), (517, 1000, 100),
+                                   (64, 33, 128), (1, 7, 3)])
+def test_gemm_nn_exact_integers(gpu_lib, dt, m, K, c):
+    from paper_1608_02148_amd import api
+    rng = np.random.default_rng(m * 7 + K + c)
+    A = _int_matrix(rng, (m, K))
+    X = _int_matrix(rng, (K, c), -4, 4)
+    xdt = torch.float64 if dt == "f64" else torch.float32
+    Ag = torch.tensor(A, dtype=DT[dt], device=DEV)
+    Xg = torch.tensor(X, dtype=xdt, device=DEV)
+    Y = _np(api.gemm_nn(Ag, Xg))
+    assert np.array_equal(Y, A @ X)
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("m,n,c", [(300, 257, 5), (5000, 129, 30), (20000, 300, 100), (77, 1000, 64),
+                                   (3, 5, 2)])
+def test_gemm_tn_exact_integers(gpu_lib, dt, m, n, c):
+    from paper_1608_02148_amd import api
+    rng = np.random.default_rng(m + 3 * n + c)
+    A = _int_matrix(rng, (m, n), -4, 4)
+    Q = _int_matrix(rng, (m, c), -3, 3)
+    xdt = torch.float64 if dt == "f64" else torch.float32
+    Z = _np(api.gemm_tn(torch.tensor(A, dtype=DT[dt], device=DEV), torch.tensor(Q, dtype=xdt, device=DEV)))
+    assert np.array_equal(Z, A.T @ Q)
+
+
+def test_gemm_random_f64_accuracy_and_strided_input(gpu_lib):
+    from paper_1608_02148_amd import api
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((700, 333))
+    big = np.zeros((700, 340))
+    big[:, :333] = A
+    Ag = torch.tensor(big, device=DEV)[:, :333]          # lda = 340 > n
+    X = rng.standard_normal((333, 40))
+    Y = _np(api.gemm_nn(Ag, torch.tensor(X, device=DEV)))
+    np.testing.assert_allclose(Y, A @ X, rtol=0, atol=1e-12 * np.abs(A).max() * np.abs(X).max() * 333)
+    Q = rng.standard_normal((700, 40))
+    Z = _np(api.gemm_tn(Ag, torch.tensor(Q, device=DEV)))
+    np.testing.assert_allclose(Z, A.T @ Q, rtol=0, atol=1e-12 * 700 * 4)
+
+
+@pytest.mark.parametrize("dt,tol", [("f64", 1e-13), ("f32", 2e-6)])
+@pytest.mark.parametrize("m,c", [(5000, 30), (1000, 128), (33, 17), (20000, 100)])
+def test_orthonormalize_matches_householder(gpu_lib, dt, tol, m, c):
+    from paper_1608_02148_amd import api
+    rng = np.random.default_rng(m + c)
+    Y = rng.standard_normal((m, c)) @ np.diag(np.logspace(0, -3, c))
+    Yd = DT[dt]
+    Yg = torch.tensor(Y, dtype=Yd, device=DEV)
+    Yin = _np(Yg).astype(np.float64)
+    Qg, Rg, flags = api.orthonormalize(Yg)
+    Q, R = _np(Qg).astype(np.float64), _np(Rg)
+    np.testing.assert_allclose(Q.T @ Q, np.eye(c), atol=tol * 10)
+    assert np.allclose(np.tril(R, -1), 0) and np.all(np.diag(R) > 0)
+    np.testing.assert_allclose(Q @ R, Yin, atol=tol * np.abs(Yin).max() * 10)
+    Qh, Rh = orc.hqr(Yin)
+    np.testing.assert_allclose(R, Rh, rtol=0, atol=(3e-5 if dt == "f32" else 1e-11) * np.abs(Rh).max())
+
+
+def test_orthonormalize_rank_deficient_uses_shift(gpu_lib):
+    from paper_1608_02148_amd import api
+    rng = np.random.default_rng(1)
+    base = rng.standard_normal((4000, 10))
+    Y = np.concatenate([base, base[:, :5] * 2.0, base[:, :5] + 1e-14 * rng.standard_normal((4000, 5))], axis=1)
+    Qg, Rg, flags = api.orthonormalize(torch.tensor(Y, device=DEV))
+    Q = _np(Qg)
+    assert np.all(np.isfinite(Q)) and np.all(np.isfinite(_np(Rg)))
+    assert int(_np(flags)[0]) & 1          # shifted Cholesky was needed
+    # the range of Y is contained in the range of Q
+    resid = Y - Q @ (Q.T @ Y)
+    assert np.abs(resid).max() < 1e-10
+
+
+@pytest.mark.parametrize("c", [1, 2, 7, 30, 64, 89, 100, 128])
+def test_small_svd_matches_lapack(gpu_lib, c):
+    from paper_1608_02148_amd import api
+    rng = np.random.default_rng(c)
+    R = np.triu(rng.standard_normal((c, c)))
+    R[np.diag_indices(c)] = np.abs(R[np.diag_indices(c)]) + 0.1
+    s, W, J, flags = api.small_svd(torch.tensor(R, device=DEV))
+    s, W, J = _np(s), _np(W), _np(J)
+    se = np.linalg.svd(R, compute_uv=False)
+    np.testing.assert_allclose(s, se, rtol=1e-12, atol=1e-14 * se[0])
+    np.testing.assert_allclose(W.T @ W, np.eye(c), atol=1e-12)
+    np.testing.assert_allclose(J.T @ J, np.eye(c), atol=1e-12)
+    np.testing.assert_allclose((W * s) @ J.T, R, atol=1e-12 * se[0])
+    assert int(_np(flags)[0]) & 8 == 0
