@@ -148,6 +148,10 @@ def main():
                 "other_kernel_avg_ms": {kname: round(v["total_ms"] / max(v["count"], 1), 4)
                                         for kname, v in prof.items() if kname != dom_name}}
 
+    info = api.new_info(dev)
+    api.rsvd(A, k, p=p, q=q, seed=args.seed, work=work, out=out, info=info)
+    st, hinfo = api.sync_info(info)
+    log(f"info: status {st} flags 0x{hinfo.flags & 0xFFFF:x} jacobi sweeps {hinfo.flags >> 24}")
     U, S, V = out
     err = excess_error(A, U, S, V, sigma_next)
     log(f"excess spectral error {err:.3e}")

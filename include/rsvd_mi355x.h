@@ -80,6 +80,9 @@ typedef struct {
 #define RSVD_FLAG_DEGENERATE   2u  /* a column was numerically zero after shifting */
 #define RSVD_FLAG_NONFINITE    4u  /* NaN or Inf reached a Gram matrix             */
 #define RSVD_FLAG_JACOBI_SLOW  8u  /* small SVD stopped at its sweep limit         */
+/* Bits 24..31 of rsvd_info.flags hold the number of Jacobi sweeps the small SVD
+ * of B took (diagnostic). */
+#define RSVD_FLAG_SWEEPS_SHIFT 24
 
 /* Status codes. */
 #define RSVD_OK               0
@@ -206,7 +209,9 @@ int rsvd_block_workspace_size(rsvd_handle_t handle, int32_t dtype, int64_t m,
 
 /* SVD of a small square upper-triangular R (c x c, f64, row-major, ld c):
  * R = W diag(s) J^T with s descending.  W and J are c x c (f64, row-major,
- * ld c).  One-sided Jacobi, one workgroup. */
+ * ld c).  One-sided Jacobi on the columns of R (one workgroup) gives W and s;
+ * J is recovered as J_i = R^T w_i / s_i, so column i of J is accurate to about
+ * u s_1 / s_i (u = 2^-53) and is zero when s_i = 0. */
 int rsvd_small_svd(rsvd_handle_t handle, int32_t c, const double* R, double* s,
                    double* W, double* J, uint32_t* flags, void* work, size_t work_bytes);
 

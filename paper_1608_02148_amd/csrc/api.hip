@@ -34,14 +34,17 @@ struct Splits {
     int colsum;  // row split of the column-mean pass
 };
 
+// Gram matrices: one split per CU at most, at least 256 rows per split.
 inline int gram_split(int64_t rows, int num_cu) {
-    return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(cdiv(rows, 256), 2 * num_cu)));
+    return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(cdiv(rows, 256), num_cu)));
 }
 
+// A^T Q: as many splits as fit the 2 resident workgroups per CU in one round
+// (a partly filled second round would idle most CUs), at least 256 rows each.
 inline Splits make_splits(int64_t m, int64_t n, int num_cu) {
     Splits s;
     const int64_t tn_tiles = cdiv(n, 128);
-    s.tn = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(cdiv(2 * num_cu, tn_tiles), cdiv(m, 256))));
+    s.tn = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>((2 * num_cu) / tn_tiles, cdiv(m, 256))));
     s.gram_m = gram_split(m, num_cu);
     s.gram_n = gram_split(n, num_cu);
     const int64_t cs_cols = cdiv(n, 256);
@@ -54,8 +57,8 @@ struct Plan {
     int64_t m = 0, n = 0;
     int k = 0, p = 0, q = 0, l = 0, Lp = 0, kp = 0;
     Splits sp{};
-    size_t Y = 0, Z = 0, Om = 0, part = 0, gram = 0, rinv = 0, racc = 0, jw = 0, jj = 0, sigma = 0,
-           xv = 0, xu = 0, jk = 0, vtmp = 0, mu = 0, mupart = 0, status = 0, bytes = 0;
+    size_t Y = 0, Z = 0, Om = 0, part = 0, gram = 0, rinv = 0, racc = 0, sigma = 0,
+           xv = 0, xu = 0, jk = 0, wks = 0, vtmp = 0, mu = 0, mupart = 0, status = 0, bytes = 0;
 };
 
 inline int validate(int32_t dtype, int64_t m, int64_t n, int32_t k, const rsvd_params* prm) {
@@ -89,13 +92,12 @@ inline Plan make_plan(int dtype, int64_t m, int64_t n, int k, const rsvd_params*
     P.part = L.take(std::max(part_tn, part_g));
     P.gram = L.take(static_cast<size_t>(P.Lp) * P.Lp * 8);
     P.rinv = L.take(static_cast<size_t>(P.Lp) * P.Lp * cs);
-    P.racc = L.take(static_cast<size_t>(P.Lp) * P.Lp * 8);
-    P.jw = L.take(static_cast<size_t>(P.Lp) * P.Lp * 8);
-    P.jj = L.take(static_cast<size_t>(P.Lp) * P.Lp * 8);
+    P.racc = L.take(4 * static_cast<size_t>(P.Lp) * P.Lp * 8);
     P.sigma = L.take(static_cast<size_t>(P.Lp) * 8);
     P.xv = L.take(static_cast<size_t>(P.Lp) * P.kp * cs);
     P.xu = L.take(static_cast<size_t>(P.Lp) * P.kp * cs);
     P.jk = L.take(static_cast<size_t>(P.Lp) * P.kp * 8);
+    P.wks = L.take(static_cast<size_t>(P.Lp) * P.kp * 8);
     P.vtmp = L.take(static_cast<size_t>(n) * P.kp * cs);
     P.mu = L.take(static_cast<size_t>(n) * 8);
     P.mupart = L.take(static_cast<size_t>(P.sp.colsum) * n * 8);
@@ -115,33 +117,47 @@ template <typename T> inline T* at(void* work, size_t off) {
 
 // In-place orthonormalisation of M (rows x l, ld ldm, precision TC):
 // CholeskyQR2, with a shifted first pass and a third pass when needed.
-// racc (optional, f64 l x l) receives the product of the R factors.
+// adaptive = true (bases inside the power scheme, whose span is all that the
+// next product uses) runs the second pass only when the first pass shows an
+// ill-conditioned Gram matrix.
+// rfac (optional, f64, 4 consecutive l x l blocks) receives R1, R2, R3 (R3 = I
+// when the third pass is skipped) and, in the fourth block, R = R3 R2 R1.
 template <typename TC>
 hipError_t orthonormalize(hipStream_t st, TC* M, int64_t ldm, int64_t rows, int l, int Lp, int S,
-                          double* part, double* gram, TC* rinv, double* racc, uint32_t* status,
-                          int num_cu) {
+                          double* part, double* gram, TC* rinv, double* rfac, uint32_t* status,
+                          int num_cu, bool adaptive = false) {
     (void)num_cu;
     static bool ready = false;
-    const size_t lds = (static_cast<size_t>(l) * (l + 1) + 2 * l) * sizeof(double);
+    const size_t lds = chol_lds_bytes(l);
     if (!ready) {
-        RSVD_TRY(allow_lds(chol_kernel<TC>, (static_cast<size_t>(CHOL_MAX_L) * (CHOL_MAX_L + 1) + 2 * CHOL_MAX_L) * 8));
+        RSVD_TRY(allow_lds(chol_kernel<TC>, chol_lds_bytes(CHOL_MAX_L)));
         ready = true;
     }
     for (int pass = 1; pass <= 3; ++pass) {
-        const uint32_t* skip = (pass == 3) ? status : nullptr;
+        const bool conditional = (pass == 3) || (pass == 2 && adaptive);
+        const uint32_t* skip = conditional ? status : nullptr;
+        const uint32_t need = (pass == 2) ? ST_NEED_P2 : ST_NEED_P3;
         RSVD_TRY((launch_gemm<TC, TC, double, MODE_TN>(st, M, ldm, l, rows, M, ldm, l, part, Lp, S,
                                                       static_cast<int64_t>(Lp) * Lp, nullptr, skip,
-                                                      ST_SHIFT_PENDING)));
+                                                      need)));
         if (S > 1) RSVD_TRY(launch_reduce<double>(st, part, S, static_cast<int64_t>(Lp) * Lp, Lp, l, l,
-                                                  gram, Lp, skip, ST_SHIFT_PENDING));
+                                                  gram, Lp, skip, need));
         CholArgs ca;
         ca.part = (S > 1) ? gram : part; ca.S = 1; ca.part_stride = 0; ca.ldp = Lp;
-        ca.l = l; ca.mrows = rows; ca.rinv = rinv; ca.ldr = Lp; ca.rout = nullptr;
-        ca.racc = racc; ca.status = status; ca.pass = pass; ca.skip_unless_pending = (pass == 3);
+        ca.l = l; ca.mrows = rows; ca.rinv = rinv; ca.ldr = Lp;
+        ca.rout = rfac ? rfac + static_cast<size_t>(pass - 1) * l * l : nullptr;
+        ca.status = status; ca.pass = pass; ca.skip_unless_pending = conditional; ca.adaptive = adaptive;
         hipLaunchKernelGGL(chol_kernel<TC>, dim3(1), dim3(CHOL_THREADS), lds, st, ca);
         RSVD_TRY(hipGetLastError());
         RSVD_TRY((launch_gemm<TC, TC, TC, MODE_NN>(st, M, ldm, rows, l, rinv, Lp, l, M, ldm, 1, 0,
-                                                  nullptr, skip, ST_SHIFT_PENDING)));
+                                                  nullptr, skip, need)));
+    }
+    if (rfac) {   // R = R3 (R2 R1); the product R2 R1 goes through the gram scratch
+        const size_t ll = static_cast<size_t>(l) * l;
+        RSVD_TRY((launch_gemm<double, double, double, MODE_NN>(st, rfac + ll, l, l, l, rfac, l, l, gram, l, 1, 0,
+                                                              nullptr, nullptr, 0)));
+        RSVD_TRY((launch_gemm<double, double, double, MODE_NN>(st, rfac + 2 * ll, l, l, l, gram, l, l,
+                                                              rfac + 3 * ll, l, 1, 0, nullptr, nullptr, 0)));
     }
     return hipSuccess;
 }
@@ -252,9 +268,11 @@ hipError_t solve(rsvd_handle_t h, const Plan& P, const TA* A, int64_t lda, const
 
     // Alg. subspace_iter: q rounds of orth(Y); Z = orth(A^T Y); Y = A Z.
     for (int it = 0; it < P.q; ++it) {
-        RSVD_TRY(orthonormalize<TC>(st, Y, Lp, m, l, Lp, P.sp.gram_m, partd, gram, rinv, nullptr, status, num_cu));
+        RSVD_TRY(orthonormalize<TC>(st, Y, Lp, m, l, Lp, P.sp.gram_m, partd, gram, rinv, nullptr, status, num_cu,
+                                    true));
         RSVD_TRY(aty(Z));
-        RSVD_TRY(orthonormalize<TC>(st, Z, Lp, n, l, Lp, P.sp.gram_n, partd, gram, rinv, nullptr, status, num_cu));
+        RSVD_TRY(orthonormalize<TC>(st, Z, Lp, n, l, Lp, P.sp.gram_n, partd, gram, rinv, nullptr, status, num_cu,
+                                    true));
         RSVD_TRY(ax(Z));
     }
     // Alg. rqb steps 9-10: Q = qr(Y); B^T = A^T Q.
@@ -262,18 +280,20 @@ hipError_t solve(rsvd_handle_t h, const Plan& P, const TA* A, int64_t lda, const
     RSVD_TRY(aty(Z));
     // svd(B): B^T = Q_b R_b (Q_b overwrites Z), R_b = W S J^T by Jacobi.
     RSVD_TRY(orthonormalize<TC>(st, Z, Lp, n, l, Lp, P.sp.gram_n, partd, gram, rinv, racc, status, num_cu));
+    racc += 3 * static_cast<size_t>(l) * l;       // R_b = R3 R2 R1
     {
         static bool ready = false;
-        if (!ready) { RSVD_TRY(allow_lds(jacobi_kernel<TC>, JAC_LDS_LIMIT)); ready = true; }
+        if (!ready) { RSVD_TRY(allow_lds(jacobi_kernel<TC>, jacobi_lds_bytes(CHOL_MAX_L))); ready = true; }
         JacobiArgs ja;
         ja.R = racc; ja.ldr = l; ja.l = l; ja.k = k;
-        ja.gw = at<double>(work, P.jw); ja.gj = at<double>(work, P.jj);
-        ja.sigma = sigma; ja.xv = xv; ja.ldx = Lp; ja.xcols = P.kp; ja.jk = jk;
-        ja.status = status; ja.max_sweeps = 60; ja.tol = 1e-15;
-        const size_t mat = static_cast<size_t>(l) * l * 8;
-        const size_t lds = (2 * mat <= JAC_LDS_LIMIT) ? 2 * mat : (mat <= JAC_LDS_LIMIT ? mat : 0);
-        hipLaunchKernelGGL(jacobi_kernel<TC>, dim3(1), dim3(JAC_THREADS), lds, st, ja);
+        double* wks = at<double>(work, P.wks);
+        ja.sigma = sigma; ja.xv = xv; ja.ldx = Lp; ja.xcols = P.kp; ja.wks = wks;
+        ja.status = status; ja.max_sweeps = 60; ja.tol = jacobi_tol(ja.l);
+        hipLaunchKernelGGL(jacobi_kernel<TC>, dim3(1), dim3(JAC_THREADS), jacobi_lds_bytes(l), st, ja);
         RSVD_TRY(hipGetLastError());
+        // J_k = R_b^T (W_k / sigma)
+        RSVD_TRY((launch_gemm<double, double, double, MODE_TN>(st, racc, l, l, l, wks, k, k, jk, k, 1, 0,
+                                                              nullptr, nullptr, 0)));
     }
     // V = Q_b W_k, sign rule, then U = Q (J_k D) with D = signs (x S for PCA).
     TC* V = o.V ? static_cast<TC*>(o.V) : at<TC>(work, P.vtmp);
@@ -501,8 +521,7 @@ static Plan block_plan(int32_t dtype, int64_t m, int64_t n, int32_t c, int num_c
                              static_cast<size_t>(std::max(P.sp.gram_m, P.sp.gram_n)) * P.Lp * P.Lp * 8));
     P.gram = L.take(static_cast<size_t>(P.Lp) * P.Lp * 8);
     P.rinv = L.take(static_cast<size_t>(P.Lp) * P.Lp * cs);
-    P.jw = L.take(static_cast<size_t>(P.Lp) * P.Lp * 8);
-    P.jj = L.take(static_cast<size_t>(P.Lp) * P.Lp * 8);
+    P.racc = L.take(4 * static_cast<size_t>(P.Lp) * P.Lp * 8);
     P.jk = L.take(static_cast<size_t>(P.Lp) * P.Lp * 8);
     P.bytes = L.off;
     (void)prm;
@@ -592,13 +611,16 @@ int rsvd_orthonormalize(rsvd_handle_t handle, int32_t dtype, int64_t m, int32_t 
     if (e == hipSuccess) {
         if (dtype == RSVD_F64)
             e = orthonormalize<double>(st, static_cast<double*>(Y), ldy, m, c, P.Lp, S, at<double>(work, P.part),
-                                       at<double>(work, P.gram), at<double>(work, P.rinv), R, status,
-                                       handle->dev.num_cu);
+                                       at<double>(work, P.gram), at<double>(work, P.rinv), at<double>(work, P.racc),
+                                       status, handle->dev.num_cu);
         else
             e = orthonormalize<float>(st, static_cast<float*>(Y), ldy, m, c, P.Lp, S, at<double>(work, P.part),
-                                      at<double>(work, P.gram), at<float>(work, P.rinv), R, status,
-                                      handle->dev.num_cu);
+                                      at<double>(work, P.gram), at<float>(work, P.rinv), at<double>(work, P.racc),
+                                      status, handle->dev.num_cu);
     }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(R, at<double>(work, P.racc) + 3 * static_cast<size_t>(c) * c,
+                           static_cast<size_t>(c) * c * sizeof(double), hipMemcpyDeviceToDevice, st);
     if (e == hipSuccess && flags) e = hipMemcpyAsync(flags, status, sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
     return hip_status(handle, e);
 }
@@ -615,19 +637,19 @@ int rsvd_small_svd(rsvd_handle_t handle, int32_t c, const double* R, double* s, 
     if (e != hipSuccess) return hip_status(handle, e);
     static bool ready = false;
     if (!ready) {
-        e = allow_lds(jacobi_kernel<double>, JAC_LDS_LIMIT);
+        e = allow_lds(jacobi_kernel<double>, jacobi_lds_bytes(CHOL_MAX_L));
         if (e != hipSuccess) return hip_status(handle, e);
         ready = true;
     }
     JacobiArgs ja;
     ja.R = R; ja.ldr = c; ja.l = c; ja.k = c;
-    ja.gw = at<double>(work, P.jw); ja.gj = at<double>(work, P.jj);
-    ja.sigma = s; ja.xv = W; ja.ldx = c; ja.xcols = c; ja.jk = J;
-    ja.status = status; ja.max_sweeps = 60; ja.tol = 1e-15;
-    const size_t mat = static_cast<size_t>(c) * c * 8;
-    const size_t lds = (2 * mat <= JAC_LDS_LIMIT) ? 2 * mat : (mat <= JAC_LDS_LIMIT ? mat : 0);
-    hipLaunchKernelGGL(jacobi_kernel<double>, dim3(1), dim3(JAC_THREADS), lds, st, ja);
+    double* wks = at<double>(work, P.gram);
+    ja.sigma = s; ja.xv = W; ja.ldx = c; ja.xcols = c; ja.wks = wks;
+    ja.status = status; ja.max_sweeps = 60; ja.tol = jacobi_tol(ja.l);
+    hipLaunchKernelGGL(jacobi_kernel<double>, dim3(1), dim3(JAC_THREADS), jacobi_lds_bytes(c), st, ja);
     e = hipGetLastError();
+    if (e == hipSuccess)
+        e = launch_gemm<double, double, double, MODE_TN>(st, R, c, c, c, wks, c, c, J, c, 1, 0, nullptr, nullptr, 0);
     if (e == hipSuccess && flags) e = hipMemcpyAsync(flags, status, sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
     return hip_status(handle, e);
 }

@@ -60,7 +60,10 @@ __host__ __device__ constexpr int64_t rup(int64_t a, int64_t b) { return cdiv(a,
 
 // Status word bits kept in the workspace (a superset of RSVD_FLAG_*).
 enum : uint32_t {
-    ST_SHIFT_PENDING = 1u << 16,   // current orthonormalisation needs a 3rd pass
+    ST_NEED_P2 = 1u << 16,         // pass 2 of the current orthonormalisation must run
+    ST_SHIFTED = 1u << 17,         // its first pass used the shifted Cholesky
+    ST_NEED_P3 = 1u << 18,         // pass 3 must run
+    ST_SWEEPS_SHIFT = 24,          // bits 24..31: Jacobi sweeps of the last small SVD
 };
 
 // Per-device properties cached by the handle.

@@ -6,16 +6,24 @@
 //                                                  and Alg. rqb step 10 (B^T)
 //
 // Both share one tile engine.  A workgroup owns a BM x NC block of the output
-// and walks the reduction dimension in steps of BK.  The A tile is staged in
-// LDS k-major (As[k][r]) in both modes -- NN transposes while staging, TN
-// reads A in its natural row order -- so the matrix-core fragment reads are
-// the same: lane i + 16 kk reads As[kk][i] and Xs[kk][j].  LDS is double
-// buffered; the next tile's global loads are in flight while the current tile
-// is multiplied, with a single barrier per step.
+// and walks the reduction dimension k in steps of BK.  Lane (i, g) of a
+// 16x16xKV*4 group feeds matrix-core step v with k = KV*g + v for both
+// operands, so the reduction covers every k exactly once.
+//   - X is staged k-contiguous, Xs[j][k]: one 16-byte LDS read gives a lane
+//     its operands for KV steps.  Neighbouring lanes load neighbouring
+//     columns of X, so each (scalar) global load instruction is coalesced.
+//   - NN stages A k-contiguous too, As[r][k]: each thread loads KV
+//     consecutive k of one row of A with one vector load and stores them with
+//     one 16-byte LDS write; fragments are 16-byte LDS reads.
+//   - TN stages A in its natural order, As[k][r]: each thread loads KV
+//     consecutive columns of one row of A (one vector load, 16-byte LDS
+//     write); a fragment is KV 4/8-byte LDS reads of 16 consecutive r.
+// LDS is double buffered; the next tile's global loads are in flight while the
+// current tile is multiplied, with a single barrier per step.
 //
-// Split-K: grid.y = S splits the reduction dimension into S contiguous chunks.
-// With S > 1 every split writes its own partial block and a separate kernel
-// sums the partials in split order, so results are deterministic (no atomics).
+// Split-K: grid.y = S splits the reduction into S contiguous chunks.  With
+// S > 1 every split writes its own partial block and a separate kernel sums the
+// partials in split order, so results are deterministic (no atomics).
 //
 // Optional implicit centring: when mu != nullptr every staged element of A is
 // replaced by A(i, j) - mu[j] (j = column of A), which is how the PCA path
@@ -44,35 +52,49 @@ struct GemmArgs {
     const double* mu;    // optional column means of A (implicit centring)
     const uint32_t* skip_flag;  // optional: run only if (*skip_flag & skip_mask)
     uint32_t skip_mask;
-    int32_t a_vec;       // 1 when A rows are 16-byte aligned (vector loads)
-    int32_t x_vec;       // 1 when X rows are 16-byte aligned
+    int32_t a_vec;       // 1 when A rows allow aligned vector loads
+    int32_t x_vec;       // unused (X is read with scalar loads)
 };
 
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-template <typename TA, typename TC>
-__device__ __forceinline__ TC load_elem(const TA* p, const double* mu, int64_t col) {
-    if (mu) return Conv<TC>::to(Conv<double>::to(*p) - mu[col]);
-    return Conv<TC>::to(*p);
-}
-
-template <typename TA, typename TC, int N>
-__device__ __forceinline__ void unpack16(const u32x4 raw, TC (&dst)[N]) {
-    if constexpr (sizeof(TA) == 8) {
-        static_assert(N == 2, "");
-        dst[0] = Conv<TC>::to(__hiloint2double(raw[1], raw[0]));
-        dst[1] = Conv<TC>::to(__hiloint2double(raw[3], raw[2]));
-    } else if constexpr (sizeof(TA) == 4) {
-        static_assert(N == 4, "");
+// KV consecutive elements of TA starting at p (KV * sizeof(TA) bytes,
+// naturally aligned), converted to TC.
+template <typename TA, typename TC, int KV>
+__device__ __forceinline__ void load_vec(const TA* p, TC (&dst)[KV]) {
+    constexpr int BYTES = KV * sizeof(TA);
+    if constexpr (BYTES == 16) {
+        const u32x4 raw = *reinterpret_cast<const u32x4*>(p);
+        if constexpr (sizeof(TA) == 8) {
+            dst[0] = Conv<TC>::to(__hiloint2double(raw[1], raw[0]));
+            dst[1] = Conv<TC>::to(__hiloint2double(raw[3], raw[2]));
+        } else if constexpr (sizeof(TA) == 4) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) dst[e] = Conv<TC>::to(__uint_as_float(raw[e]));
-    } else {
-        static_assert(N == 8, "");
+            for (int e = 0; e < 4; ++e) dst[e] = Conv<TC>::to(__uint_as_float(raw[e]));
+        } else {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            dst[2 * e] = Conv<TC>::to(__uint_as_float(raw[e] << 16));
-            dst[2 * e + 1] = Conv<TC>::to(__uint_as_float(raw[e] & 0xFFFF0000u));
+            for (int e = 0; e < 4; ++e) {
+                dst[2 * e] = Conv<TC>::to(__uint_as_float(raw[e] << 16));
+                dst[2 * e + 1] = Conv<TC>::to(__uint_as_float(raw[e] & 0xFFFF0000u));
+            }
         }
+    } else if constexpr (BYTES == 8) {
+        const u32x2 raw = *reinterpret_cast<const u32x2*>(p);
+        if constexpr (sizeof(TA) == 4) {
+            dst[0] = Conv<TC>::to(__uint_as_float(raw[0]));
+            dst[1] = Conv<TC>::to(__uint_as_float(raw[1]));
+        } else {
+            static_assert(sizeof(TA) == 2, "");
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                dst[2 * e] = Conv<TC>::to(__uint_as_float(raw[e] << 16));
+                dst[2 * e + 1] = Conv<TC>::to(__uint_as_float(raw[e] & 0xFFFF0000u));
+            }
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < KV; ++e) dst[e] = Conv<TC>::to(p[e]);
     }
 }
 
@@ -81,23 +103,18 @@ struct GemmTile {
     static constexpr int BM = 16 * WR * WGM;
     static constexpr int NC = 16 * WC * WGN;
     static constexpr int NT = 64 * WGM * WGN;
-    static constexpr int PAD = 64 / sizeof(TC);   // row stride = 16 mod 32 banks
-    static constexpr int SA = BM + PAD;           // As row stride (elements)
-    static constexpr int SX = NC + PAD;           // Xs row stride
-    static constexpr int VA = 16 / sizeof(TA);    // A elements per 16-byte load
-    static constexpr int VX = 16 / sizeof(TX);
-    // A tile: NN reads BM rows x BK columns, TN reads BK rows x BM columns.
-    static constexpr int A_TPR = (MODE == MODE_NN ? BK : BM) / VA;   // threads per A row
-    static constexpr int A_RPP = NT / A_TPR;                         // A rows per pass
-    static constexpr int A_ROWS = (MODE == MODE_NN ? BM : BK);        // A rows per tile
-    static constexpr int A_PASSES = (A_ROWS + A_RPP - 1) / A_RPP;
-    static constexpr int X_TPR = NC / VX;
-    static constexpr int X_RPP = NT / X_TPR;
-    static constexpr int X_PASSES = (BK + X_RPP - 1) / X_RPP;
-    static_assert(NT % A_TPR == 0 && NT % X_TPR == 0, "");
-    static_assert(A_ROWS % A_RPP == 0 || A_PASSES == 1, "");
-    static_assert(BK % X_RPP == 0 || X_PASSES == 1, "");
-    static constexpr size_t LDS_BYTES = 2ull * BK * (SA + SX) * sizeof(TC);
+    static constexpr int KV = 16 / sizeof(TC);          // k values per 16-byte LDS read
+    static constexpr int KG = 4 * KV;                   // k covered by one read group
+    static constexpr int SK = BK + 16 / sizeof(TC);     // LDS row stride (elements)
+    static constexpr int KVECS = BK / KV;               // k-vectors per row and tile
+    static constexpr int A_ITEMS = BM * KVECS;        // NN: rows x k-vectors; TN: k rows x r-vectors
+    static constexpr int X_ITEMS = NC * KVECS;
+    static constexpr int A_PASSES = (A_ITEMS + NT - 1) / NT;
+    static constexpr int X_PASSES = (X_ITEMS + NT - 1) / NT;
+    static_assert(BK % KG == 0, "BK must cover whole read groups");
+    static constexpr int SR = BM + 16 / sizeof(TC);     // TN: As row stride (elements)
+    static constexpr size_t A_LDS = (MODE == MODE_NN ? BM * SK : BK * SR);
+    static constexpr size_t LDS_BYTES = 2ull * (A_LDS + NC * SK) * sizeof(TC);
 };
 
 template <typename TA, typename TX, typename TC, int MODE, int WR, int WC, int WGM, int WGN, int BK>
@@ -105,11 +122,13 @@ __global__ __launch_bounds__(64 * WGM * WGN)
 void gemm_tile_kernel(GemmArgs<TA, TX, TC> g) {
     typedef GemmTile<TA, TX, TC, MODE, WR, WC, WGM, WGN, BK> T;
     typedef typename Mfma<TC>::acc_t acc_t;
+    constexpr int KV = T::KV, SK = T::SK, KVECS = T::KVECS;
+    typedef TC vec_t __attribute__((ext_vector_type(KV)));
     if (g.skip_flag && ((*g.skip_flag & g.skip_mask) == 0u)) return;
 
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    TC* As = reinterpret_cast<TC*>(smem_raw);            // [2][BK][SA]
-    TC* Xs = As + 2 * BK * T::SA;                         // [2][BK][SX]
+    TC* As = reinterpret_cast<TC*>(smem_raw);            // [2][A_LDS]
+    TC* Xs = As + 2 * T::A_LDS;                           // [2][NC][SK]
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -120,83 +139,105 @@ void gemm_tile_kernel(GemmArgs<TA, TX, TC> g) {
     const int col0 = blockIdx.z * T::NC;
     const int64_t kbeg = static_cast<int64_t>(split) * g.kchunk;
     const int64_t kend = min(g.K, kbeg + g.kchunk);
-    const TX* X = g.X + col0;
 
-    // ---- global -> register prefetch buffers
-    TC ra[T::A_PASSES][T::VA];
-    TC rx[T::X_PASSES][T::VX];
+    TC ra[T::A_PASSES][KV];
+    TC rx[T::X_PASSES][KV];
 
+    // Item -> (row, k-vector) for NN, (k row, r-vector) for TN; in both the
+    // vectors adjacent in global memory go to adjacent threads.
+    constexpr int RVECS = T::BM / KV;
+    auto a_item = [&](int it, int& r, int& kv) {
+        if (MODE == MODE_NN) { r = it / KVECS; kv = it % KVECS; }
+        else                 { kv = it / RVECS; r = (it % RVECS) * KV; }   // kv = k row here
+    };
     auto load_a = [&](int64_t k0) {
 #pragma unroll
         for (int p = 0; p < T::A_PASSES; ++p) {
-            const int arow = p * T::A_RPP + tid / T::A_TPR;
-            const int acol = (tid % T::A_TPR) * T::VA;
-            if (arow >= T::A_ROWS) break;
-            int64_t gr, gc;          // global row / column of A
-            bool row_ok;
-            int64_t col_lim;
+            const int it = p * T::NT + tid;
+            if (it >= T::A_ITEMS) break;
+            int r, kv;
+            a_item(it, r, kv);
+            const int64_t gk = k0 + kv * KV;
+            const int64_t gr = r0 + r;
             if (MODE == MODE_NN) {
-                gr = r0 + arow; gc = k0 + acol; row_ok = gr < g.rows; col_lim = kend;
-            } else {
-                gr = k0 + arow; gc = r0 + acol; row_ok = gr < kend; col_lim = g.rows;
-            }
-            const TA* src = g.A + gr * g.lda + gc;
-            if (row_ok && g.a_vec && gc + T::VA <= col_lim) {
-                const u32x4 raw = *reinterpret_cast<const u32x4*>(src);
-                unpack16<TA, TC>(raw, ra[p]);
-                if (g.mu) {
+                const TA* src = g.A + gr * g.lda + gk;
+                if (gr < g.rows && g.a_vec && gk + KV <= kend) {
+                    load_vec<TA, TC, KV>(src, ra[p]);
+                    if (g.mu) {
 #pragma unroll
-                    for (int e = 0; e < T::VA; ++e)
-                        ra[p][e] = Conv<TC>::to(Conv<double>::to(ra[p][e]) - g.mu[gc + e]);
+                        for (int e = 0; e < KV; ++e)
+                            ra[p][e] = Conv<TC>::to(Conv<double>::to(ra[p][e]) - g.mu[gk + e]);
+                    }
+                } else {
+#pragma unroll
+                    for (int e = 0; e < KV; ++e) {
+                        TC v = TC(0);
+                        if (gr < g.rows && gk + e < kend)
+                            v = g.mu ? Conv<TC>::to(Conv<double>::to(src[e]) - g.mu[gk + e]) : Conv<TC>::to(src[e]);
+                        ra[p][e] = v;
+                    }
                 }
             } else {
+                // TN: kv is a row of A (k), gr the first of KV columns (r).
+                const int64_t ak = k0 + kv;
+                const TA* src = g.A + ak * g.lda + gr;
+                if (ak < kend && g.a_vec && gr + KV <= g.rows) {
+                    load_vec<TA, TC, KV>(src, ra[p]);
+                    if (g.mu) {
 #pragma unroll
-                for (int e = 0; e < T::VA; ++e)
-                    ra[p][e] = (row_ok && gc + e < col_lim) ? load_elem<TA, TC>(src + e, g.mu, gc + e)
-                                                            : TC(0);
+                        for (int e = 0; e < KV; ++e)
+                            ra[p][e] = Conv<TC>::to(Conv<double>::to(ra[p][e]) - g.mu[gr + e]);
+                    }
+                } else {
+#pragma unroll
+                    for (int e = 0; e < KV; ++e) {
+                        TC v = TC(0);
+                        if (ak < kend && gr + e < g.rows)
+                            v = g.mu ? Conv<TC>::to(Conv<double>::to(src[e]) - g.mu[gr + e]) : Conv<TC>::to(src[e]);
+                        ra[p][e] = v;
+                    }
+                }
             }
         }
     };
     auto load_x = [&](int64_t k0) {
 #pragma unroll
         for (int p = 0; p < T::X_PASSES; ++p) {
-            const int xr = p * T::X_RPP + tid / T::X_TPR;
-            const int xc = (tid % T::X_TPR) * T::VX;
-            if (xr >= BK) break;
-            const int64_t gk = k0 + xr;
-            const int gcol = col0 + xc;          // column of X
-            const TX* src = X + gk * g.ldx + xc;
-            if (gk < kend && g.x_vec && gcol + T::VX <= g.ncols) {
-                const u32x4 raw = *reinterpret_cast<const u32x4*>(src);
-                unpack16<TX, TC>(raw, rx[p]);
-            } else {
+            const int it = p * T::NT + tid;
+            if (it >= T::X_ITEMS) break;
+            const int j = it % T::NC, kv = it / T::NC;
+            const int64_t gk = k0 + kv * KV;
+            const int gc = col0 + j;
+            const bool ok = gc < g.ncols;
 #pragma unroll
-                for (int e = 0; e < T::VX; ++e)
-                    rx[p][e] = (gk < kend && gcol + e < g.ncols) ? Conv<TC>::to(src[e]) : TC(0);
-            }
+            for (int e = 0; e < KV; ++e)
+                rx[p][e] = (ok && gk + e < kend) ? Conv<TC>::to(g.X[(gk + e) * g.ldx + gc]) : TC(0);
         }
     };
     auto store_tiles = [&](int buf) {
-        TC* as = As + buf * BK * T::SA;
-        TC* xs = Xs + buf * BK * T::SX;
+        TC* as = As + buf * T::A_LDS;
+        TC* xs = Xs + buf * T::NC * SK;
 #pragma unroll
         for (int p = 0; p < T::A_PASSES; ++p) {
-            const int arow = p * T::A_RPP + tid / T::A_TPR;
-            const int acol = (tid % T::A_TPR) * T::VA;
-            if (arow >= T::A_ROWS) break;
+            const int it = p * T::NT + tid;
+            if (it >= T::A_ITEMS) break;
+            int r, kv;
+            a_item(it, r, kv);
+            vec_t v;
 #pragma unroll
-            for (int e = 0; e < T::VA; ++e) {
-                if (MODE == MODE_NN) as[(acol + e) * T::SA + arow] = ra[p][e];   // transpose
-                else                 as[arow * T::SA + acol + e] = ra[p][e];
-            }
+            for (int e = 0; e < KV; ++e) v[e] = ra[p][e];
+            if (MODE == MODE_NN) *reinterpret_cast<vec_t*>(as + r * SK + kv * KV) = v;
+            else                 *reinterpret_cast<vec_t*>(as + kv * T::SR + r) = v;
         }
 #pragma unroll
         for (int p = 0; p < T::X_PASSES; ++p) {
-            const int xr = p * T::X_RPP + tid / T::X_TPR;
-            const int xc = (tid % T::X_TPR) * T::VX;
-            if (xr >= BK) break;
+            const int it = p * T::NT + tid;
+            if (it >= T::X_ITEMS) break;
+            const int j = it % T::NC, kv = it / T::NC;
+            vec_t v;
 #pragma unroll
-            for (int e = 0; e < T::VX; ++e) xs[xr * T::SX + xc + e] = rx[p][e];
+            for (int e = 0; e < KV; ++e) v[e] = rx[p][e];
+            *reinterpret_cast<vec_t*>(xs + j * SK + kv * KV) = v;
         }
     };
 
@@ -217,19 +258,29 @@ void gemm_tile_kernel(GemmArgs<TA, TX, TC> g) {
             store_tiles(buf);
             __syncthreads();
             if (k0 + BK < kend) { load_a(k0 + BK); load_x(k0 + BK); }
-            const TC* as = As + buf * BK * T::SA;
-            const TC* xs = Xs + buf * BK * T::SX;
+            const TC* as = As + buf * T::A_LDS;
+            const TC* xs = Xs + buf * T::NC * SK;
 #pragma unroll
-            for (int kk = 0; kk < BK / 4; ++kk) {
-                TC a[WR], b[WC];
+            for (int kg = 0; kg < BK; kg += T::KG) {
+                vec_t a[WR], b[WC];
 #pragma unroll
-                for (int i = 0; i < WR; ++i) a[i] = as[(4 * kk + lk) * T::SA + wr0 + 16 * i + li];
+                for (int i = 0; i < WR; ++i) {
+                    if (MODE == MODE_NN) {
+                        a[i] = *reinterpret_cast<const vec_t*>(as + (wr0 + 16 * i + li) * SK + kg + KV * lk);
+                    } else {
 #pragma unroll
-                for (int j = 0; j < WC; ++j) b[j] = xs[(4 * kk + lk) * T::SX + wc0 + 16 * j + li];
+                        for (int v = 0; v < KV; ++v) a[i][v] = as[(kg + KV * lk + v) * T::SR + wr0 + 16 * i + li];
+                    }
+                }
 #pragma unroll
-                for (int i = 0; i < WR; ++i)
+                for (int j = 0; j < WC; ++j)
+                    b[j] = *reinterpret_cast<const vec_t*>(xs + (wc0 + 16 * j + li) * SK + kg + KV * lk);
 #pragma unroll
-                    for (int j = 0; j < WC; ++j) acc[i][j] = Mfma<TC>::step(a[i], b[j], acc[i][j]);
+                for (int v = 0; v < KV; ++v)
+#pragma unroll
+                    for (int i = 0; i < WR; ++i)
+#pragma unroll
+                        for (int j = 0; j < WC; ++j) acc[i][j] = Mfma<TC>::step(a[i][v], b[j][v], acc[i][j]);
             }
             buf ^= 1;
         }

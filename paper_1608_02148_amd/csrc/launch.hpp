@@ -56,8 +56,11 @@ hipError_t launch_gemm(hipStream_t st, const TA* A, int64_t lda, int64_t rows, i
     g.kchunk = rup(cdiv(K, S), BK);
     g.X = X; g.ldx = ldx; g.ncols = ncols; g.out = out; g.ldo = ldo;
     g.part_stride = part_stride; g.mu = mu; g.skip_flag = skip_flag; g.skip_mask = skip_mask;
-    g.a_vec = aligned16(A, lda, sizeof(TA));
-    g.x_vec = aligned16(X, ldx, sizeof(TX));
+    {   // vector loads of 16 / sizeof(TC) consecutive elements of A
+        const size_t vb = (16 / sizeof(TC)) * sizeof(TA);
+        g.a_vec = (reinterpret_cast<uintptr_t>(A) % vb == 0) && ((lda * sizeof(TA)) % vb == 0);
+    }
+    g.x_vec = 0;
     // splits past the end of K find an empty range and write zero partials
     const int tc = tile_cols(ncols);
     if (tc == 32) return launch_gemm_cfg<TA, TX, TC, MODE, 2, 2, 4, 1>(st, g, S);

@@ -15,6 +15,8 @@
 #include "common.hpp"
 #include "philox.hpp"
 
+#include <algorithm>
+
 namespace rsvd {
 
 // Status words are cleared by a kernel rather than a memset node, so the whole
@@ -97,17 +99,30 @@ __global__ __launch_bounds__(256) void philox_words_kernel(int64_t n, int groups
 }
 
 // ------------------------------------------------------- Cholesky + inverse
-// One workgroup.  G = sum of the S partial Gram blocks (ldp x ldp, f64), of
-// which the leading l x l block is used.  Computes G = R^T R (R upper
-// triangular), writes R^{-1} (ld ldr, zero outside l x l) in precision TC and
-// optionally R (f64, ld l) and Racc <- R Racc.
+// One workgroup of 512 threads.  G = sum of the S partial Gram blocks (ldp x
+// ldp, f64), of which the leading l x l block (l <= 128) is used.  Computes
+// G = R^T R (R upper triangular) and writes R^{-1} (ld ldr, zero outside
+// l x l) in precision TC and optionally R (f64, ld l).
+//
+// Register tiles: thread (tx, ty) holds rows 4ty..4ty+3 and columns
+// 8tx..8tx+7 of the matrix.  Factorisation step j: the owners of row j publish
+// it in LDS, one barrier, then every thread applies the rank-1 update
+// g_a g_b / d_j to its own entries with a > j, b >= a; the owners turn row j
+// into row j of R.  The inverse is a column sweep over [R | I] with the same
+// tiles: step j publishes row j of the accumulator and column j of R.
 //
 // Pass policy (CholeskyQR2 with shifted CholeskyQR3 fallback):
 //   pass 1: if a pivot fails (d_j <= 100 u G_jj, d_j not finite), restart on
-//           G + s I with s = 11 (m l + l (l + 1)) u tr(G) and request a 3rd pass;
-//   pass 2: request a 3rd pass when the Gram is still far from the identity
+//           G + s I with s = 11 (m l + l (l + 1)) u tr(G); that requires two
+//           more passes.  In adaptive mode (a basis for the next product, not
+//           the final Q) a second pass is requested only then, or when some
+//           pivot ratio d_j / G_jj < 1e-6 (condition number above ~1e3);
+//   pass 2: runs always (final mode) or when requested; requests a third pass
+//           after a shift or when the Gram is still far from the identity
 //           (some d_j < G_jj / 2);
 //   pass 3: runs only when requested.
+// A skipped pass still writes R = I when R is requested, so products of the
+// per-pass factors stay valid.
 // A pivot that still fails (a numerically zero column) gets a zero row in R
 // and a zero column in R^{-1}; DEGENERATE is raised.
 struct CholArgs {
@@ -116,203 +131,260 @@ struct CholArgs {
     int64_t mrows;
     void* rinv; int ldr;
     double* rout;             // optional R (ld l)
-    double* racc;             // optional accumulated product (ld l)
     uint32_t* status;
     int pass;                 // 1, 2 or 3
-    int skip_unless_pending;  // pass 3: return unless ST_SHIFT_PENDING
+    int skip_unless_pending;  // skip unless this pass was requested (ST_NEED_P2 / P3)
+    int adaptive;             // pass 1 may leave out pass 2 (see above)
 };
 
 constexpr int CHOL_MAX_L = RSVD_MAX_L;
-constexpr int CHOL_THREADS = 1024;
+constexpr int CHOL_THREADS = 512;
+constexpr int CT_R = 4, CT_C = 8;                 // register tile per thread
+constexpr int CT_TX = CHOL_MAX_L / CT_C;          // 16 thread columns
+static_assert((CHOL_MAX_L / CT_R) * CT_TX == CHOL_THREADS, "tiles must cover the matrix");
+
+inline size_t chol_lds_bytes(int) { return 0; }
 
 template <typename TC>
 __global__ __launch_bounds__(CHOL_THREADS) void chol_kernel(CholArgs a) {
+    const int l = a.l, tid = threadIdx.x;
+    const int tx = tid % CT_TX, ty = tid / CT_TX;
+    const int a0 = CT_R * ty, b0 = CT_C * tx;
+    const uint32_t need_bit = (a.pass == 2) ? ST_NEED_P2 : ST_NEED_P3;
+    if (a.skip_unless_pending && ((*a.status & need_bit) == 0u)) {
+        if (a.rout)
+            for (int i = 0; i < CT_R; ++i)
+                for (int q = 0; q < CT_C; ++q)
+                    if (a0 + i < l && b0 + q < l) a.rout[(a0 + i) * l + b0 + q] = (a0 + i == b0 + q) ? 1.0 : 0.0;
+        return;
+    }
+    __shared__ double rowbuf[2][CHOL_MAX_L];
+    __shared__ double colbuf[2][CHOL_MAX_L];
+    __shared__ double diag0[CHOL_MAX_L];
+    __shared__ double dinv[CHOL_MAX_L];
     __shared__ uint32_t s_flags;
-    if (a.skip_unless_pending && ((*a.status & ST_SHIFT_PENDING) == 0u)) return;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int l = a.l, ld = l + 1;
-    double* G = reinterpret_cast<double*>(smem_raw);         // l x ld
-    double* diag0 = G + l * ld;                               // l
-    double* dinv = diag0 + l;                                 // l
-    __shared__ double s_scalar[4];
-    __shared__ int s_fail;
-    const int tid = threadIdx.x, nt = blockDim.x;
+    __shared__ double s_trace;
+    double g[CT_R][CT_C];
 
     if (tid == 0) {
         uint32_t st = *a.status;
-        if (a.pass == 1) st &= ~ST_SHIFT_PENDING;
+        if (a.pass == 1) st &= ~(ST_NEED_P2 | ST_NEED_P3 | ST_SHIFTED);
         s_flags = st;
     }
-
-    auto load_gram = [&]() {
-        for (int idx = tid; idx < l * l; idx += nt) {
-            const int i = idx / l, j = idx - i * l;
-            double v = 0.0;
-            for (int s = 0; s < a.S; ++s) v += a.part[s * a.part_stride + static_cast<int64_t>(i) * a.ldp + j];
-            G[i * ld + j] = v;
-        }
-        __syncthreads();
-        if (tid < l) diag0[tid] = G[tid * ld + tid];
+    auto load = [&](double shift) {
+#pragma unroll
+        for (int i = 0; i < CT_R; ++i)
+#pragma unroll
+            for (int q = 0; q < CT_C; ++q) {
+                const int r = a0 + i, c = b0 + q;
+                double v = 0.0;
+                if (r < l && c < l) {
+                    for (int s = 0; s < a.S; ++s) v += a.part[s * a.part_stride + static_cast<int64_t>(r) * a.ldp + c];
+                    if (r == c) { diag0[r] = v; v += shift; }
+                }
+                g[i][q] = v;
+            }
         __syncthreads();
     };
 
-    load_gram();
+    load(0.0);
     if (tid == 0) {
         double tr = 0.0;
         for (int j = 0; j < l; ++j) tr += diag0[j];
-        s_scalar[0] = tr;
+        s_trace = tr;
     }
     __syncthreads();
-    const double trace = s_scalar[0];
+    const double trace = s_trace;
     const bool nonfinite = !isfinite(trace);
     const bool zero = (trace == 0.0);
     constexpr double u = 1.1102230246251565e-16;   // unit roundoff of the f64 Gram
 
     double min_ratio = 1.0;
-    bool shifted = false;
+    bool shifted = false, dead_any = false;
     if (!nonfinite && !zero) {
         for (int attempt = 0; attempt < 2; ++attempt) {
-            if (attempt == 1) {       // shifted restart
-                load_gram();
-                const double sh = 11.0 * (static_cast<double>(a.mrows) * l + static_cast<double>(l) * (l + 1)) * u * trace;
-                if (tid < l) G[tid * ld + tid] += sh;
-                __syncthreads();
+            if (attempt == 1) {
+                load(11.0 * (static_cast<double>(a.mrows) * l + static_cast<double>(l) * (l + 1)) * u * trace);
                 shifted = true;
             }
-            if (tid == 0) s_fail = 0;
+            bool fail = false;
             min_ratio = 1.0;
+            dead_any = false;
             for (int j = 0; j < l; ++j) {
-                if (tid == 0) {
-                    const double d = G[j * ld + j];
-                    const bool fail_pass1 = !(d > 100.0 * u * diag0[j]) || !isfinite(d);
-                    const bool dead = !(d > 1e-30 * diag0[j]) || !isfinite(d) || diag0[j] == 0.0;
-                    double r;
-                    if (a.pass == 1 && attempt == 0 && fail_pass1) {
-                        s_fail = 1; r = 0.0;
-                    } else if (dead) {
-                        r = 0.0;                         // numerically zero column
-                        s_flags |= RSVD_FLAG_DEGENERATE;
-                    } else {
-                        r = sqrt(d);
-                        min_ratio = fmin(min_ratio, d / diag0[j]);
+                const int buf = j & 1;
+                if (ty == j / CT_R) {
+#pragma unroll
+                    for (int i = 0; i < CT_R; ++i)
+                        if (i == j % CT_R)
+#pragma unroll
+                            for (int q = 0; q < CT_C; ++q) rowbuf[buf][b0 + q] = g[i][q];
+                }
+                __syncthreads();
+                const double d = rowbuf[buf][j];
+                const double d0 = diag0[j];
+                if (a.pass == 1 && attempt == 0 && (!(d > 100.0 * u * d0) || !isfinite(d))) {
+                    fail = true;
+                    break;                                   // uniform: every thread saw d
+                }
+                const bool dead = !(d > 1e-30 * d0) || !isfinite(d) || d0 == 0.0;
+                const double sq = dead ? 0.0 : sqrt(d);
+                const double inv_sq = dead ? 0.0 : 1.0 / sq;
+                const double inv_d = inv_sq * inv_sq;
+                if (dead) dead_any = true;
+                else min_ratio = fmin(min_ratio, d / d0);
+                if (tid == 0) dinv[j] = inv_sq;
+                double rb[CT_C];
+#pragma unroll
+                for (int q = 0; q < CT_C; ++q) rb[q] = rowbuf[buf][b0 + q];
+#pragma unroll
+                for (int i = 0; i < CT_R; ++i) {
+                    const int r = a0 + i;
+                    if (r == j) {                            // row j of R
+#pragma unroll
+                        for (int q = 0; q < CT_C; ++q) {
+                            const int c = b0 + q;
+                            g[i][q] = (c > j) ? g[i][q] * inv_sq : (c == j ? sq : 0.0);
+                        }
+                    } else if (r > j && !dead) {
+                        const double fa = rowbuf[buf][r] * inv_d;
+#pragma unroll
+                        for (int q = 0; q < CT_C; ++q)
+                            if (b0 + q >= r) g[i][q] -= fa * rb[q];
                     }
-                    G[j * ld + j] = r;
-                    dinv[j] = (r > 0.0) ? 1.0 / r : 0.0;
-                    s_scalar[1] = min_ratio;
                 }
-                __syncthreads();
-                if (s_fail) break;
-                const double rinv = dinv[j];
-                for (int t = j + 1 + tid; t < l; t += nt) G[j * ld + t] *= rinv;
-                __syncthreads();
-                const int w = l - j - 1;
-                for (int idx = tid; idx < w * w; idx += nt) {
-                    const int aa = j + 1 + idx / w, bb = j + 1 + idx % w;
-                    if (aa <= bb) G[aa * ld + bb] -= G[j * ld + aa] * G[j * ld + bb];
-                }
-                __syncthreads();
             }
+            if (!fail) break;
             __syncthreads();
-            if (!s_fail) break;
         }
-        min_ratio = s_scalar[1];
     } else {
-        // zero or non-finite Gram: R = 0, R^{-1} = 0
-        for (int idx = tid; idx < l * ld; idx += nt) G[idx] = 0.0;
-        if (tid < l) dinv[tid] = 0.0;
-        if (tid == 0) s_flags |= nonfinite ? RSVD_FLAG_NONFINITE : RSVD_FLAG_DEGENERATE;
-        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < CT_R; ++i)
+#pragma unroll
+            for (int q = 0; q < CT_C; ++q) g[i][q] = 0.0;
+        for (int j = tid; j < l; j += CHOL_THREADS) dinv[j] = 0.0;
     }
     if (tid == 0) {
-        if (shifted) s_flags |= RSVD_FLAG_CHOL_SHIFT | ST_SHIFT_PENDING;
-        if (a.pass == 2 && min_ratio < 0.5) s_flags |= ST_SHIFT_PENDING;
+        uint32_t f = s_flags;
+        if (nonfinite) f |= RSVD_FLAG_NONFINITE;
+        if (zero || dead_any) f |= RSVD_FLAG_DEGENERATE;
+        // The request bits stay set until the next orthonormalisation starts,
+        // so the Gram, Cholesky and apply kernels of a pass all see them.
+        if (a.pass == 1) {
+            if (shifted) f |= RSVD_FLAG_CHOL_SHIFT | ST_SHIFTED | ST_NEED_P2;
+            else if (a.adaptive && min_ratio < 1e-6) f |= ST_NEED_P2;
+        } else if (a.pass == 2) {
+            if ((f & ST_SHIFTED) || min_ratio < 0.5) f |= ST_NEED_P3;
+        }
+        s_flags = f;
     }
-    // Upper triangle of G (incl. diagonal) now holds R.  Inverse X = R^{-1}:
-    // X[i][j] = -dinv[i] * sum_{t=i+1..j} R[i][t] X[t][j], X[j][j] = dinv[j];
-    // X[t][j] for t < j is kept in the lower triangle at G[j][t].
     __syncthreads();
-    {
-        constexpr int PARTS = 8;
-        const int j = tid / PARTS, part = tid % PARTS;
-        for (int i = l - 2; i >= 0; --i) {
-            double acc = 0.0;
-            if (j > i && j < l) {
-                for (int t = i + 1 + part; t <= j; t += PARTS) {
-                    const double x = (t == j) ? dinv[j] : G[j * ld + t];
-                    acc += G[i * ld + t] * x;
-                }
-            }
+    // Inverse by a column sweep: B = I; for j = l-1..1, with X[j][.] = dinv[j] B[j][.],
+    // B[i][c] -= R[i][j] X[j][c] for i < j, c >= j.  Finally X = diag(dinv) B.
+    double x[CT_R][CT_C];
 #pragma unroll
-            for (int off = PARTS / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, PARTS);
-            if (j > i && j < l && part == 0) G[j * ld + i] = -dinv[i] * acc;
-            __syncthreads();
+    for (int i = 0; i < CT_R; ++i)
+#pragma unroll
+        for (int q = 0; q < CT_C; ++q) x[i][q] = (a0 + i == b0 + q && a0 + i < l) ? 1.0 : 0.0;
+    for (int j = l - 1; j > 0; --j) {
+        const int buf = j & 1;
+        if (ty == j / CT_R) {
+#pragma unroll
+            for (int i = 0; i < CT_R; ++i)
+                if (i == j % CT_R)
+#pragma unroll
+                    for (int q = 0; q < CT_C; ++q) rowbuf[buf][b0 + q] = x[i][q];
         }
-    }
-    // Write R^{-1} (TC) and optional R / accumulated product.
-    TC* rinv = static_cast<TC*>(a.rinv);
-    for (int idx = tid; idx < a.ldr * a.ldr; idx += nt) {
-        const int i = idx / a.ldr, j = idx - i * a.ldr;
-        double v = 0.0;
-        if (i < l && j < l) v = (i == j) ? dinv[i] : (i < j ? G[j * ld + i] : 0.0);
-        rinv[idx] = static_cast<TC>(v);
-    }
-    if (a.rout) {
-        for (int idx = tid; idx < l * l; idx += nt) {
-            const int i = idx / l, j = idx - i * l;
-            a.rout[idx] = (i <= j) ? G[i * ld + j] : 0.0;
-        }
-    }
-    if (a.racc) {
-        // Racc <- R * Racc (both upper triangular).  Read everything first.
-        constexpr int PER = (CHOL_MAX_L * CHOL_MAX_L + CHOL_THREADS - 1) / CHOL_THREADS;
-        double nv[PER];
-        int cnt = 0;
-        for (int idx = tid; idx < l * l; idx += nt, ++cnt) {
-            const int i = idx / l, j = idx - i * l;
-            double v = 0.0;
-            if (a.pass == 1) {
-                v = (i <= j) ? G[i * ld + j] : 0.0;
-            } else if (i <= j) {
-                for (int t = i; t <= j; ++t) v += G[i * ld + t] * a.racc[t * l + j];
-            }
-            nv[cnt] = v;
+        if (tx == j / CT_C) {
+#pragma unroll
+            for (int q = 0; q < CT_C; ++q)
+                if (q == j % CT_C)
+#pragma unroll
+                    for (int i = 0; i < CT_R; ++i) colbuf[buf][a0 + i] = g[i][q];
         }
         __syncthreads();
-        cnt = 0;
-        for (int idx = tid; idx < l * l; idx += nt, ++cnt) a.racc[idx] = nv[cnt];
+        const double sj = dinv[j];
+        if (sj != 0.0) {
+            double xr[CT_C];
+#pragma unroll
+            for (int q = 0; q < CT_C; ++q) xr[q] = rowbuf[buf][b0 + q] * sj;
+#pragma unroll
+            for (int i = 0; i < CT_R; ++i) {
+                if (a0 + i < j) {
+                    const double rij = colbuf[buf][a0 + i];
+#pragma unroll
+                    for (int q = 0; q < CT_C; ++q)
+                        if (b0 + q >= j) x[i][q] -= rij * xr[q];
+                }
+            }
+        }
     }
-    __syncthreads();
+    TC* rinv = static_cast<TC*>(a.rinv);
+#pragma unroll
+    for (int i = 0; i < CT_R; ++i) {
+        const int r = a0 + i;
+        const double di = (r < l) ? dinv[r] : 0.0;
+#pragma unroll
+        for (int q = 0; q < CT_C; ++q) {
+            const int c = b0 + q;
+            if (r < a.ldr && c < a.ldr)
+                rinv[r * a.ldr + c] = static_cast<TC>((r < l && c < l && c >= r) ? x[i][q] * di : 0.0);
+            if (a.rout && r < l && c < l) a.rout[r * l + c] = (c >= r) ? g[i][q] : 0.0;
+        }
+    }
     if (tid == 0) *a.status = s_flags;
 }
 
 // ------------------------------------------------------ one-sided Jacobi SVD
-// R (l x l, f64, ld ldr) = W diag(sigma) J^T.  Columns of W and J live
-// column-major (column c at offset c * l) in LDS when they fit, otherwise in
-// the global scratch provided.  Pairs are visited in round-robin order so that
-// every round rotates l/2 disjoint column pairs in parallel, one 32-lane group
-// per pair.  A pair is rotated when |w_a . w_b| > tol sqrt(|w_a|^2 |w_b|^2).
-// Outputs (sorted by descending sigma, ties by index):
-//   sigma[0..l), xv (ldx x kp, TC): xv[t][i] = W[t][perm[i]] for i < k,
-//   jk (f64, l x k, ld k): jk[t][i] = J[t][perm[i]].
+// R (l x l upper triangular, f64, ld ldr) = W diag(sigma) J^T.  The columns of
+// W (column-major, column c at W + c*ldw) live in LDS; l/2 disjoint column pairs
+// are rotated per round (round-robin order), one 16-lane group per pair with
+// the two columns held in registers during the rotation.  A
+// pair is rotated when |w_a . w_b| > tol sqrt(|w_a|^2 |w_b|^2).  J is not
+// accumulated: since R^T W = J diag(sigma), the needed columns are recovered
+// as J_i = R^T w_i / sigma_i, whose error relative to 1 is about
+// u sigma_1 / sigma_i -- small for the k leading columns that are kept.
+// Outputs (sorted by descending sigma, ties by lower index):
+//   sigma[0..l), xv (ldx x xcols, TC): xv[t][i] = W[t][perm[i]] for i < k,
+//   wks (f64, l x k, ld k): wks[t][i] = W[t][perm[i]] / sigma_i, from which
+//   J_k = R^T wks is formed by a product kernel.
 struct JacobiArgs {
     const double* R; int ldr; int l; int k;
-    double* gw;          // global scratch for W (l*l) when LDS is too small
-    double* gj;          // global scratch for J (l*l)
     double* sigma;       // l
     void* xv; int ldx; int xcols;
-    double* jk;          // l x k
+    double* wks;         // l x k
     uint32_t* status;
     int max_sweeps;
     double tol;
 };
 
 constexpr int JAC_THREADS = 1024;
-constexpr int JAC_GROUP = 32;
-constexpr size_t JAC_LDS_LIMIT = 150 * 1024;
+constexpr int JAC_GROUP = 16;      // lanes per column pair (one DPP row)
 
+// Column stride of W in LDS: l rounded up to a multiple of 16 doubles plus
+// one 64-bit bank pair, so that the columns read by the groups of a wave
+// start on different banks.
+__host__ __device__ inline int jacobi_ldw(int l) { return ((l + 15) / 16) * 16 + 1; }
+inline size_t jacobi_lds_bytes(int l) { return static_cast<size_t>(jacobi_ldw(l)) * l * sizeof(double); }
+
+// Rotation threshold: a rotated pair keeps |w_a . w_b| of order u sqrt(l)
+// |w_a| |w_b| after rounding, so asking for less than l u would never settle.
+inline double jacobi_tol(int l) { return std::max(1e-15, 2.220446049250313e-16 * l); }
+
+constexpr int JAC_PER_LANE = CHOL_MAX_L / JAC_GROUP;
+
+// Sum over the 16 lanes of a DPP row: quad exchanges (xor 1, xor 2), then the
+// half-row and row mirrors; every lane ends with the full sum.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
 __device__ __forceinline__ double group_sum(double v) {
-#pragma unroll
-    for (int off = JAC_GROUP / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, JAC_GROUP);
+    v += dpp_f64<0xB1>(v);    // quad_perm [1,0,3,2]
+    v += dpp_f64<0x4E>(v);    // quad_perm [2,3,0,1]
+    v += dpp_f64<0x141>(v);   // row_half_mirror
+    v += dpp_f64<0x140>(v);   // row_mirror
     return v;
 }
 
@@ -323,23 +395,11 @@ __global__ __launch_bounds__(JAC_THREADS) void jacobi_kernel(JacobiArgs a) {
     __shared__ int s_perm[CHOL_MAX_L];
     __shared__ double s_sig[CHOL_MAX_L];
     const int l = a.l, tid = threadIdx.x, nt = blockDim.x;
-    const size_t mat = static_cast<size_t>(l) * l * sizeof(double);
-    double* W;
-    double* J;
-    if (2 * mat <= JAC_LDS_LIMIT) {
-        W = reinterpret_cast<double*>(smem_raw);
-        J = W + l * l;
-    } else if (mat <= JAC_LDS_LIMIT) {
-        W = reinterpret_cast<double*>(smem_raw);
-        J = a.gj;
-    } else {
-        W = a.gw;
-        J = a.gj;
-    }
+    const int ldw = jacobi_ldw(l);
+    double* W = reinterpret_cast<double*>(smem_raw);     // column c at W + c * ldw
     for (int idx = tid; idx < l * l; idx += nt) {
         const int c = idx / l, r = idx - c * l;
-        W[idx] = a.R[r * a.ldr + c];
-        J[idx] = (r == c) ? 1.0 : 0.0;
+        W[c * ldw + r] = a.R[r * a.ldr + c];
     }
     __syncthreads();
 
@@ -357,29 +417,32 @@ __global__ __launch_bounds__(JAC_THREADS) void jacobi_kernel(JacobiArgs a) {
                 if (p == 0) { ca = round; cb = lp - 1; }
                 else { ca = (round + p) % (lp - 1); cb = (round - p + lp - 1) % (lp - 1); }
                 if (ca >= l || cb >= l) continue;
-                double* wa = W + ca * l;
-                double* wb = W + cb * l;
+                double* wa = W + ca * ldw;
+                double* wb = W + cb * ldw;
+                double xa[JAC_PER_LANE], xb[JAC_PER_LANE];
+#pragma unroll
+                for (int q = 0; q < JAC_PER_LANE; ++q) {
+                    const int r = gl + JAC_GROUP * q;
+                    xa[q] = (r < l) ? wa[r] : 0.0;
+                    xb[q] = (r < l) ? wb[r] : 0.0;
+                }
                 double al = 0.0, be = 0.0, ga = 0.0;
-                for (int r = gl; r < l; r += JAC_GROUP) {
-                    const double x = wa[r], y = wb[r];
-                    al += x * x; be += y * y; ga += x * y;
+#pragma unroll
+                for (int q = 0; q < JAC_PER_LANE; ++q) {
+                    al += xa[q] * xa[q]; be += xb[q] * xb[q]; ga += xa[q] * xb[q];
                 }
                 al = group_sum(al); be = group_sum(be); ga = group_sum(ga);
                 if (ga != 0.0 && fabs(ga) > a.tol * sqrt(al * be)) {
                     const double zeta = (be - al) / (2.0 * ga);
                     const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
                     const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-                    for (int r = gl; r < l; r += JAC_GROUP) {
-                        const double x = wa[r], y = wb[r];
-                        wa[r] = c * x - s * y;
-                        wb[r] = s * x + c * y;
-                    }
-                    double* ja = J + ca * l;
-                    double* jb = J + cb * l;
-                    for (int r = gl; r < l; r += JAC_GROUP) {
-                        const double x = ja[r], y = jb[r];
-                        ja[r] = c * x - s * y;
-                        jb[r] = s * x + c * y;
+#pragma unroll
+                    for (int q = 0; q < JAC_PER_LANE; ++q) {
+                        const int r = gl + JAC_GROUP * q;
+                        if (r < l) {
+                            wa[r] = c * xa[q] - s * xb[q];
+                            wb[r] = s * xa[q] + c * xb[q];
+                        }
                     }
                     if (gl == 0) s_rotated = 1;
                 }
@@ -389,21 +452,23 @@ __global__ __launch_bounds__(JAC_THREADS) void jacobi_kernel(JacobiArgs a) {
         if (!s_rotated) break;
         __syncthreads();
     }
-    if (tid == 0 && sweep >= a.max_sweeps) atomicOr(a.status, RSVD_FLAG_JACOBI_SLOW);
+    if (tid == 0) {   // record the sweep count (bits 24..31) and the limit flag
+        const uint32_t sw = static_cast<uint32_t>(min(sweep + 1, 255)) << 24;
+        atomicOr(a.status, sw | (sweep >= a.max_sweeps ? RSVD_FLAG_JACOBI_SLOW : 0u));
+    }
 
     // sigma_c = |W[:, c]|; normalise the columns of W.
     for (int c = group; c < l; c += ngroups) {
-        double* wc = W + c * l;
+        double* wc = W + c * ldw;
         double ss = 0.0;
         for (int r = gl; r < l; r += JAC_GROUP) ss += wc[r] * wc[r];
         ss = group_sum(ss);
         const double sg = sqrt(ss);
         const double inv = (sg > 0.0) ? 1.0 / sg : 0.0;
         for (int r = gl; r < l; r += JAC_GROUP) wc[r] *= inv;
-        if (gl == 0) s_sig[c] = sg;     // unsorted for now
+        if (gl == 0) s_sig[c] = sg;
     }
     __syncthreads();
-    // rank of each value: strictly larger ones, then equal ones with lower index
     if (tid < l) {
         const double sv = s_sig[tid];
         int rank = 0;
@@ -419,12 +484,16 @@ __global__ __launch_bounds__(JAC_THREADS) void jacobi_kernel(JacobiArgs a) {
     for (int idx = tid; idx < a.ldx * a.xcols; idx += nt) {
         const int t = idx / a.xcols, i = idx - t * a.xcols;
         double v = 0.0;
-        if (t < l && i < a.k) v = W[s_perm[i] * l + t];
+        if (t < l && i < a.k) v = W[s_perm[i] * ldw + t];
         xv[t * a.xcols + i] = static_cast<TC>(v);
     }
+    // W_k diag(1/sigma) in f64 for J_k = R^T W_k / sigma (a product kernel
+    // forms it); zero for a zero singular value.
     for (int idx = tid; idx < l * a.k; idx += nt) {
         const int t = idx / a.k, i = idx - t * a.k;
-        a.jk[idx] = J[s_perm[i] * l + t];
+        const int c = s_perm[i];
+        const double sg = s_sig[c];
+        a.wks[idx] = (sg > 0.0) ? W[c * ldw + t] / sg : 0.0;
     }
 }
 
@@ -489,7 +558,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(const double* sigma, int 
     if (center_out && tid < n) center_out[tid] = static_cast<TC>(mu ? mu[tid] : 0.0);
     if (info && tid == 0) {
         info->l = l; info->q = q; info->p = p;
-        info->flags = *status & 0xFFFFu;
+        info->flags = *status & 0xFF00FFFFu;   // RSVD_FLAG_* and the sweep count
         info->est_err = 0.0;
     }
 }
