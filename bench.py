@@ -107,54 +107,69 @@ def main():
     sig = syn.c2_sigma()
     sigma_next = float(sig[k]) if k < len(sig) else float("nan")
 
-    prm = api.make_params(p, q, args.seed)
-    work = api.workspace(api.workspace_size(A, k, prm), dev)
-    out = (torch.empty(m, k, device=dev), torch.empty(k, dtype=torch.float64, device=dev),
-           torch.empty(n, k, device=dev))
+    def run_arm(precision):
+        """Time one arm: warm-up, then exactly args.steps solves between syncs."""
+        prm = api.make_params(p, q, args.seed, precision=precision)
+        work = api.workspace(api.workspace_size(A, k, prm), dev)
+        out = (torch.empty(m, k, device=dev), torch.empty(k, dtype=torch.float64, device=dev),
+               torch.empty(n, k, device=dev))
 
-    def step():
-        api.rsvd(A, k, p=p, q=q, seed=args.seed, work=work, out=out)
+        def step():
+            api.rsvd(A, k, p=p, q=q, seed=args.seed, precision=precision, work=work, out=out)
 
-    log(f"warmup {args.warmup} steps")
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
+        log(f"[{precision}] warmup {args.warmup} steps")
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        api.profile_enable(True, dev)
+        api.profile_collect(dev)                       # clear
+        log(f"[{precision}] timing {args.steps} steps")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        prof = api.profile_collect(dev)
+        api.profile_enable(False, dev)
+        ms = (t1 - t0) * 1000.0 / args.steps
+        info = api.new_info(dev)
+        api.rsvd(A, k, p=p, q=q, seed=args.seed, precision=precision, work=work, out=out, info=info)
+        st, hinfo = api.sync_info(info)
+        U, S, V = out
+        err = excess_error(A, U, S, V, sigma_next)
+        log(f"[{precision}] {ms:.3f} ms/solve; status {st} flags 0x{hinfo.flags & 0xFFFF:x} "
+            f"jacobi sweeps {hinfo.flags >> 24}; excess spectral error {err:.3e}; kernels {prof}")
+        return ms, prof, err, hinfo
 
-    api.profile_enable(True, dev)
-    api.profile_collect(dev)                       # clear
-    log(f"timing {args.steps} steps")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = api.profile_collect(dev)
-    api.profile_enable(False, dev)
-    ms = (t1 - t0) * 1000.0 / args.steps
     flops = (2 * q + 2) * 2.0 * m * n * l
-    tflops = flops / (ms / 1000.0) / 1e12
-    log(f"{ms:.3f} ms/solve, {tflops:.2f} TFLOP/s; kernels {prof}")
 
-    dom_name = max(prof, key=lambda kname: prof[kname]["total_ms"])
-    d = prof[dom_name]
-    avg_ms = d["total_ms"] / max(d["count"], 1)
-    per_launch_flops = d["flops"] / max(d["count"], 1)
-    achieved = per_launch_flops / (avg_ms / 1000.0) / 1e12
-    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAKS["f32_mfma_tflops"],
-                "unit": "TFLOP/s", "frac": round(achieved / PEAKS["f32_mfma_tflops"], 4),
-                "traffic": None, "kernel": "gemm_tile_kernel " + ("A^T Q" if dom_name == "AT_Q" else "A X"),
+    def roofline_of(prof, bound):
+        dom_name = max(prof, key=lambda kname: prof[kname]["total_ms"])
+        d = prof[dom_name]
+        cnt = max(d["count"], 1)
+        avg_ms = d["total_ms"] / cnt
+        kern = "gemm_tile_kernel" if bound == "mfma" else "gemm_bf16_kernel"
+        kern += " A^T Q" if dom_name == "AT_Q" else " A X"
+        if bound == "mfma":
+            achieved = d["flops"] / cnt / (avg_ms / 1000.0) / 1e12
+            peak, unit = PEAKS["f32_mfma_tflops"], "TFLOP/s"
+        else:
+            achieved = d["bytes"] / cnt / (avg_ms / 1000.0) / 1e9
+            peak, unit = PEAKS["hbm_gbs"], "GB/s"
+        return {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
+                "frac": round(achieved / peak, 4), "traffic": None, "kernel": kern,
                 "avg_launch_ms": round(avg_ms, 4), "launches": d["count"],
                 "other_kernel_avg_ms": {kname: round(v["total_ms"] / max(v["count"], 1), 4)
                                         for kname, v in prof.items() if kname != dom_name}}
 
-    info = api.new_info(dev)
-    api.rsvd(A, k, p=p, q=q, seed=args.seed, work=work, out=out, info=info)
-    st, hinfo = api.sync_info(info)
-    log(f"info: status {st} flags 0x{hinfo.flags & 0xFFFF:x} jacobi sweeps {hinfo.flags >> 24}")
-    U, S, V = out
-    err = excess_error(A, U, S, V, sigma_next)
-    log(f"excess spectral error {err:.3e}")
+    ms, prof, err, _ = run_arm("plain")
+    tflops = flops / (ms / 1000.0) / 1e12
+    roofline = roofline_of(prof, "mfma")
+    ms_bf, prof_bf, err_bf, _ = run_arm("bf16_mixed")
+    bf16_arm = {"ms_per_step": round(ms_bf, 4), "value": round(flops / (ms_bf / 1000.0) / 1e12, 3),
+                "unit": "TFLOP/s (same algorithmic flops)", "excess_err_spectral": round(err_bf, 6),
+                "speedup_vs_f32_plain": round(ms / ms_bf, 3), "roofline": roofline_of(prof_bf, "hbm")}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -172,6 +187,7 @@ def main():
         "excess_err_spectral": round(err, 6),
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "bf16_mixed": bf16_arm,
     }
     print(json.dumps(rec), flush=True)
 

@@ -50,10 +50,11 @@ typedef enum { RSVD_NORMAL = 0, RSVD_UNIF = 1, RSVD_RADEMACHER = 2 } rsvd_sdist;
 /* Arithmetic of the passes over A.
  * RSVD_PREC_PLAIN: products in the storage precision of A (f64 MFMA for f64,
  *   f32 MFMA for f32 and bf16).
- * RSVD_PREC_BF16_MIXED: the products with A run on bf16 MFMA with f32
- *   accumulation; the final projection B = Q^T A is recovered to f32 accuracy
- *   by splitting Q into two bf16 terms.  Gram matrices, Cholesky factors and
- *   the small SVD stay f64 in every mode. */
+ * RSVD_PREC_BF16_MIXED (A in f32 or bf16): the early passes (the sketch and
+ *   the power iterations except the last half-step) run on bf16 MFMA with f32
+ *   accumulation; the last sketch and the projection B = Q^T A are
+ *   near-f32-accurate by splitting the operands into bf16 hi + lo terms.
+ *   Gram matrices, Cholesky factors and the small SVD stay f64 in every mode. */
 typedef enum { RSVD_PREC_PLAIN = 0, RSVD_PREC_BF16_MIXED = 1 } rsvd_precision;
 
 /* Parameters of Alg. rqb / Alg. RSVDalgorithm. */
@@ -182,16 +183,25 @@ int rsvd_test_matrix(rsvd_handle_t handle, int32_t dtype, int64_t n, int32_t l,
                      uint64_t seed, uint32_t stream_id, int32_t sdist,
                      void* out, int64_t ldo);
 
+/* Arithmetic of the kernel-level products below: 0 = storage precision (f64
+ * matrix cores for RSVD_F64, f32 otherwise), 1 = bf16 matrix cores (operands
+ * rounded to bf16, f32 accumulation), 2 = split bf16 (A_hi X_hi + A_hi X_lo +
+ * A_lo X_hi; error per product about 2^-18 |a||x|, near f32 rounding).  1 and 2
+ * are rejected for RSVD_F64. */
+#define RSVD_ARITH_STORAGE 0
+#define RSVD_ARITH_BF16    1
+#define RSVD_ARITH_SPLIT   2
+
 /* Y = A X (Alg. rqb step 3, Alg. subspace_iter step 4): A m x K (dtype,
  * lda), X K x c (f64 for RSVD_F64 else f32, ldx), Y m x c (same type as X,
  * ldy).  c <= RSVD_MAX_L. */
-int rsvd_gemm_nn(rsvd_handle_t handle, int32_t dtype, int64_t m, int64_t K, int32_t c,
+int rsvd_gemm_nn(rsvd_handle_t handle, int32_t dtype, int32_t arith, int64_t m, int64_t K, int32_t c,
                  const void* A, int64_t lda, const void* X, int64_t ldx,
                  void* Y, int64_t ldy, void* work, size_t work_bytes);
 
 /* Z = A^T Q (Alg. subspace_iter step 3; Alg. rqb step 10 gives B^T): A m x n
  * (dtype, lda), Q m x c (f64/f32, ldq), Z n x c (ldz).  c <= RSVD_MAX_L. */
-int rsvd_gemm_tn(rsvd_handle_t handle, int32_t dtype, int64_t m, int64_t n, int32_t c,
+int rsvd_gemm_tn(rsvd_handle_t handle, int32_t dtype, int32_t arith, int64_t m, int64_t n, int32_t c,
                  const void* A, int64_t lda, const void* Q, int64_t ldq,
                  void* Z, int64_t ldz, void* work, size_t work_bytes);
 

@@ -177,25 +177,25 @@ def _block_ws(dt, m, n, c, device):
     return workspace(nbytes.value, device)
 
 
-def gemm_nn(A, X):
-    """Y = A X with the library's product kernel."""
+def gemm_nn(A, X, arith="storage"):
+    """Y = A X with the library's product kernel (arith: storage, bf16, split)."""
     dt = _check_matrix(A)
     m, K = A.shape
     c = X.shape[1]
     Y = torch.empty(m, c, dtype=out_dtype(A), device=A.device)
-    L.check(L.load().rsvd_gemm_nn(handle(A.device), dt, m, K, c, _ptr(A), A.stride(0), _ptr(X),
+    L.check(L.load().rsvd_gemm_nn(handle(A.device), dt, L.ARITH[arith], m, K, c, _ptr(A), A.stride(0), _ptr(X),
                                   X.stride(0), _ptr(Y), Y.stride(0), None, 0), "rsvd_gemm_nn")
     return Y
 
 
-def gemm_tn(A, Q):
-    """Z = A^T Q with the library's split-K product kernel."""
+def gemm_tn(A, Q, arith="storage"):
+    """Z = A^T Q with the library's split-K product kernel (arith: storage, bf16, split)."""
     dt = _check_matrix(A)
     m, n = A.shape
     c = Q.shape[1]
     Z = torch.empty(n, c, dtype=out_dtype(A), device=A.device)
     work = _block_ws(dt, m, n, c, A.device)
-    L.check(L.load().rsvd_gemm_tn(handle(A.device), dt, m, n, c, _ptr(A), A.stride(0), _ptr(Q),
+    L.check(L.load().rsvd_gemm_tn(handle(A.device), dt, L.ARITH[arith], m, n, c, _ptr(A), A.stride(0), _ptr(Q),
                                   Q.stride(0), _ptr(Z), Z.stride(0), _ptr(work), work.numel()),
             "rsvd_gemm_tn")
     return Z

@@ -66,7 +66,8 @@ inline int validate(int32_t dtype, int64_t m, int64_t n, int32_t k, const rsvd_p
     if (m < 1 || n < 1 || k < 1 || k >= std::min(m, n)) return RSVD_ERR_INVALID;
     if (!prm || prm->p < 0 || prm->q < 0) return RSVD_ERR_INVALID;
     if (prm->sdist < RSVD_NORMAL || prm->sdist > RSVD_RADEMACHER) return RSVD_ERR_INVALID;
-    if (prm->precision != RSVD_PREC_PLAIN) return RSVD_ERR_UNSUPPORTED;
+    if (prm->precision != RSVD_PREC_PLAIN && prm->precision != RSVD_PREC_BF16_MIXED) return RSVD_ERR_UNSUPPORTED;
+    if (prm->precision == RSVD_PREC_BF16_MIXED && dtype == RSVD_F64) return RSVD_ERR_UNSUPPORTED;
     if (m > (int64_t(1) << 32) || n > (int64_t(1) << 32)) return RSVD_ERR_UNSUPPORTED;
     const int64_t l = std::min<int64_t>(static_cast<int64_t>(k) + prm->p, std::min(m, n));
     if (l > RSVD_MAX_L) return RSVD_ERR_UNSUPPORTED;
@@ -246,22 +247,29 @@ hipError_t solve(rsvd_handle_t h, const Plan& P, const TA* A, int64_t lda, const
     const double a_bytes = static_cast<double>(m) * n * sizeof(TA);
     const double nn_bytes = a_bytes + (static_cast<double>(n) + m) * l * sizeof(TC);
     const double tn_bytes = a_bytes + (static_cast<double>(m) + n) * l * sizeof(TC);
-    auto ax = [&](const TC* X) -> hipError_t {     // Y (m x Lp) = A X
+    // Arithmetic of each pass: storage precision, or in the mixed mode bf16
+    // for the early passes and split bf16 (f32-accurate) for the last sketch
+    // and the projection (precision escalation).
+    const bool mixed = prm->precision == RSVD_PREC_BF16_MIXED;
+    const int early = mixed ? 1 : 0, late = mixed ? 2 : 0;
+    auto ax = [&](const TC* X, int arith) -> hipError_t {     // Y (m x Lp) = A X
         return timed(h, 0, pass_flops, nn_bytes, [&] {
-            return launch_gemm<TA, TC, TC, MODE_NN>(st, A, lda, m, n, X, Lp, l, Y, Lp, 1, 0, mu, nullptr, 0);
+            return launch_gemm_arith<TA, TC, MODE_NN>(st, arith, A, lda, m, n, X, Lp, l, Y, Lp, 1, 0, mu,
+                                                      nullptr, 0);
         });
     };
-    RSVD_TRY(ax(Om));
+    RSVD_TRY(ax(Om, P.q == 0 ? late : early));
 
-    auto aty = [&](TC* dst) -> hipError_t {     // dst (n x Lp) = A^T Y
+    auto aty = [&](TC* dst, int arith) -> hipError_t {     // dst (n x Lp) = A^T Y
         const int S = P.sp.tn;
         if (S == 1)
             return timed(h, 1, pass_flops, tn_bytes, [&] {
-                return launch_gemm<TA, TC, TC, MODE_TN>(st, A, lda, n, m, Y, Lp, l, dst, Lp, 1, 0, mu, nullptr, 0);
+                return launch_gemm_arith<TA, TC, MODE_TN>(st, arith, A, lda, n, m, Y, Lp, l, dst, Lp, 1, 0, mu,
+                                                          nullptr, 0);
             });
         RSVD_TRY(timed(h, 1, pass_flops, tn_bytes, [&] {
-            return launch_gemm<TA, TC, TC, MODE_TN>(st, A, lda, n, m, Y, Lp, l, partc, Lp, S,
-                                                    static_cast<int64_t>(n) * Lp, mu, nullptr, 0);
+            return launch_gemm_arith<TA, TC, MODE_TN>(st, arith, A, lda, n, m, Y, Lp, l, partc, Lp, S,
+                                                      static_cast<int64_t>(n) * Lp, mu, nullptr, 0);
         }));
         return launch_reduce<TC>(st, partc, S, static_cast<int64_t>(n) * Lp, Lp, n, l, dst, Lp);
     };
@@ -270,14 +278,14 @@ hipError_t solve(rsvd_handle_t h, const Plan& P, const TA* A, int64_t lda, const
     for (int it = 0; it < P.q; ++it) {
         RSVD_TRY(orthonormalize<TC>(st, Y, Lp, m, l, Lp, P.sp.gram_m, partd, gram, rinv, nullptr, status, num_cu,
                                     true));
-        RSVD_TRY(aty(Z));
+        RSVD_TRY(aty(Z, early));
         RSVD_TRY(orthonormalize<TC>(st, Z, Lp, n, l, Lp, P.sp.gram_n, partd, gram, rinv, nullptr, status, num_cu,
                                     true));
-        RSVD_TRY(ax(Z));
+        RSVD_TRY(ax(Z, it == P.q - 1 ? late : early));
     }
     // Alg. rqb steps 9-10: Q = qr(Y); B^T = A^T Q.
     RSVD_TRY(orthonormalize<TC>(st, Y, Lp, m, l, Lp, P.sp.gram_m, partd, gram, rinv, nullptr, status, num_cu));
-    RSVD_TRY(aty(Z));
+    RSVD_TRY(aty(Z, late));
     // svd(B): B^T = Q_b R_b (Q_b overwrites Z), R_b = W S J^T by Jacobi.
     RSVD_TRY(orthonormalize<TC>(st, Z, Lp, n, l, Lp, P.sp.gram_n, partd, gram, rinv, racc, status, num_cu));
     racc += 3 * static_cast<size_t>(l) * l;       // R_b = R3 R2 R1
@@ -538,24 +546,27 @@ int rsvd_block_workspace_size(rsvd_handle_t handle, int32_t dtype, int64_t m, in
 }  // extern "C"
 
 template <typename TA, typename TC>
-static hipError_t gemm_nn_typed(hipStream_t st, int64_t m, int64_t K, int c, const void* A, int64_t lda,
+static hipError_t gemm_nn_typed(hipStream_t st, int arith, int64_t m, int64_t K, int c, const void* A, int64_t lda,
                                 const void* X, int64_t ldx, void* Y, int64_t ldy) {
-    return launch_gemm<TA, TC, TC, MODE_NN>(st, static_cast<const TA*>(A), lda, m, K, static_cast<const TC*>(X),
-                                            ldx, c, static_cast<TC*>(Y), ldy, 1, 0, nullptr, nullptr, 0);
+    return launch_gemm_arith<TA, TC, MODE_NN>(st, arith, static_cast<const TA*>(A), lda, m, K,
+                                              static_cast<const TC*>(X), ldx, c, static_cast<TC*>(Y), ldy, 1, 0,
+                                              nullptr, nullptr, 0);
 }
 
 extern "C" {
 
-int rsvd_gemm_nn(rsvd_handle_t handle, int32_t dtype, int64_t m, int64_t K, int32_t c, const void* A,
-                 int64_t lda, const void* X, int64_t ldx, void* Y, int64_t ldy, void* work, size_t work_bytes) {
+int rsvd_gemm_nn(rsvd_handle_t handle, int32_t dtype, int32_t arith, int64_t m, int64_t K, int32_t c,
+                 const void* A, int64_t lda, const void* X, int64_t ldx, void* Y, int64_t ldy, void* work,
+                 size_t work_bytes) {
     (void)work; (void)work_bytes;
     if (!handle || m < 1 || K < 1 || c < 1 || c > RSVD_MAX_L || !A || !X || !Y) return RSVD_ERR_INVALID;
-    if (lda < K || ldx < c || ldy < c) return RSVD_ERR_INVALID;
+    if (lda < K || ldx < c || ldy < c || arith < 0 || arith > 2) return RSVD_ERR_INVALID;
+    if (arith != 0 && dtype == RSVD_F64) return RSVD_ERR_UNSUPPORTED;
     hipError_t e;
     switch (dtype) {
-        case RSVD_F64: e = gemm_nn_typed<double, double>(handle->stream, m, K, c, A, lda, X, ldx, Y, ldy); break;
-        case RSVD_F32: e = gemm_nn_typed<float, float>(handle->stream, m, K, c, A, lda, X, ldx, Y, ldy); break;
-        case RSVD_BF16: e = gemm_nn_typed<bf16_t, float>(handle->stream, m, K, c, A, lda, X, ldx, Y, ldy); break;
+        case RSVD_F64: e = gemm_nn_typed<double, double>(handle->stream, arith, m, K, c, A, lda, X, ldx, Y, ldy); break;
+        case RSVD_F32: e = gemm_nn_typed<float, float>(handle->stream, arith, m, K, c, A, lda, X, ldx, Y, ldy); break;
+        case RSVD_BF16: e = gemm_nn_typed<bf16_t, float>(handle->stream, arith, m, K, c, A, lda, X, ldx, Y, ldy); break;
         default: return RSVD_ERR_UNSUPPORTED;
     }
     return hip_status(handle, e);
@@ -564,33 +575,36 @@ int rsvd_gemm_nn(rsvd_handle_t handle, int32_t dtype, int64_t m, int64_t K, int3
 }  // extern "C"
 
 template <typename TA, typename TC>
-static hipError_t gemm_tn_typed(rsvd_handle_t h, const Plan& P, int64_t m, int64_t n, int c, const void* A,
+static hipError_t gemm_tn_typed(rsvd_handle_t h, int arith, const Plan& P, int64_t m, int64_t n, int c, const void* A,
                                 int64_t lda, const void* Q, int64_t ldq, void* Z, int64_t ldz, void* work) {
     hipStream_t st = h->stream;
     const int S = P.sp.tn;
     TC* part = at<TC>(work, P.part);
     if (S == 1)
-        return launch_gemm<TA, TC, TC, MODE_TN>(st, static_cast<const TA*>(A), lda, n, m, static_cast<const TC*>(Q),
-                                                ldq, c, static_cast<TC*>(Z), ldz, 1, 0, nullptr, nullptr, 0);
-    RSVD_TRY((launch_gemm<TA, TC, TC, MODE_TN>(st, static_cast<const TA*>(A), lda, n, m, static_cast<const TC*>(Q),
-                                              ldq, c, part, P.Lp, S, static_cast<int64_t>(n) * P.Lp, nullptr,
-                                              nullptr, 0)));
+        return launch_gemm_arith<TA, TC, MODE_TN>(st, arith, static_cast<const TA*>(A), lda, n, m,
+                                                  static_cast<const TC*>(Q), ldq, c, static_cast<TC*>(Z), ldz, 1, 0,
+                                                  nullptr, nullptr, 0);
+    RSVD_TRY((launch_gemm_arith<TA, TC, MODE_TN>(st, arith, static_cast<const TA*>(A), lda, n, m,
+                                                static_cast<const TC*>(Q), ldq, c, part, P.Lp, S,
+                                                static_cast<int64_t>(n) * P.Lp, nullptr, nullptr, 0)));
     return launch_reduce<TC>(st, part, S, static_cast<int64_t>(n) * P.Lp, P.Lp, n, c, static_cast<TC*>(Z), ldz);
 }
 
 extern "C" {
 
-int rsvd_gemm_tn(rsvd_handle_t handle, int32_t dtype, int64_t m, int64_t n, int32_t c, const void* A,
-                 int64_t lda, const void* Q, int64_t ldq, void* Z, int64_t ldz, void* work, size_t work_bytes) {
+int rsvd_gemm_tn(rsvd_handle_t handle, int32_t dtype, int32_t arith, int64_t m, int64_t n, int32_t c,
+                 const void* A, int64_t lda, const void* Q, int64_t ldq, void* Z, int64_t ldz, void* work,
+                 size_t work_bytes) {
     if (!handle || m < 1 || n < 1 || c < 1 || c > RSVD_MAX_L || !A || !Q || !Z || !work) return RSVD_ERR_INVALID;
-    if (lda < n || ldq < c || ldz < c) return RSVD_ERR_INVALID;
+    if (lda < n || ldq < c || ldz < c || arith < 0 || arith > 2) return RSVD_ERR_INVALID;
+    if (arith != 0 && dtype == RSVD_F64) return RSVD_ERR_UNSUPPORTED;
     const Plan P = block_plan(dtype, m, n, c, handle->dev.num_cu);
     if (work_bytes < P.bytes) return RSVD_ERR_INVALID;
     hipError_t e;
     switch (dtype) {
-        case RSVD_F64: e = gemm_tn_typed<double, double>(handle, P, m, n, c, A, lda, Q, ldq, Z, ldz, work); break;
-        case RSVD_F32: e = gemm_tn_typed<float, float>(handle, P, m, n, c, A, lda, Q, ldq, Z, ldz, work); break;
-        case RSVD_BF16: e = gemm_tn_typed<bf16_t, float>(handle, P, m, n, c, A, lda, Q, ldq, Z, ldz, work); break;
+        case RSVD_F64: e = gemm_tn_typed<double, double>(handle, arith, P, m, n, c, A, lda, Q, ldq, Z, ldz, work); break;
+        case RSVD_F32: e = gemm_tn_typed<float, float>(handle, arith, P, m, n, c, A, lda, Q, ldq, Z, ldz, work); break;
+        case RSVD_BF16: e = gemm_tn_typed<bf16_t, float>(handle, arith, P, m, n, c, A, lda, Q, ldq, Z, ldz, work); break;
         default: return RSVD_ERR_UNSUPPORTED;
     }
     return hip_status(handle, e);

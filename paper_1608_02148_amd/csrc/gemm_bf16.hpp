@@ -1,0 +1,266 @@
+// Tall-skinny products with A on the bf16 matrix cores (f32 accumulation).
+//
+// Same problem and tiling as gemm.hpp (NN: Y = A X, TN: Z = A^T Q), used by the
+// mixed-precision mode:
+//   - SPLIT = false: A and X are rounded to bf16 (round to nearest even, the
+//     hardware pack-convert) while they are staged in LDS; one
+//     v_mfma_f32_16x16x32_bf16 per 32 k.  Used for the early passes of the
+//     power scheme, whose rounding errors the later iterations damp out.
+//   - SPLIT = true: X = X_hi + X_lo and (for f32-stored A) A = A_hi + A_lo with
+//     bf16 terms; A_hi X_hi + A_hi X_lo + A_lo X_hi is accumulated in f32.  Each
+//     bf16 x bf16 product is exact in f32; the dropped A_lo X_lo term bounds
+//     the error per product near 2^-18 |a||x| (a few times plain f32
+//     rounding), far below bf16's 2^-9.  Used for the last sketch and for the
+//     projection B^T = A^T Q.
+// Both operands live in LDS k-contiguous (As[r][k], Xs[j][k]); lane (i, g) of a
+// 16x16x32 step reads its 8 consecutive k with one 16-byte LDS read.  The
+// 16-byte k-octets of a row are XOR-swizzled with (row / 8) so that the
+// staging writes and the operand reads spread over the LDS banks.
+//   - NN A: a thread loads 8 consecutive k of one row and writes one octet.
+//   - TN A and X: a thread loads a 4 (k) x 8 (columns) block with four vector
+//     loads (neighbouring threads take neighbouring column blocks, so the loads
+//     are coalesced) and writes it transposed as eight 8-byte k-quads.
+#pragma once
+
+#include "common.hpp"
+#include "gemm.hpp"
+
+namespace rsvd {
+
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef __bf16 v4bf __attribute__((ext_vector_type(4)));
+
+template <typename TA, int MODE, bool SPLIT, int WR, int WC, int WGM, int WGN, int BK>
+struct Bf16Tile {
+    static constexpr int BM = 16 * WR * WGM;
+    static constexpr int NC = 16 * WC * WGN;
+    static constexpr int NT = 64 * WGM * WGN;
+    static constexpr int SK = BK + 8;                // LDS row stride (bf16 elements)
+    static constexpr int OCT = BK / 8;               // k-octets per row and tile
+    static constexpr bool A_LO = SPLIT && (sizeof(TA) > 2);   // bf16-stored A is exact
+    // NN A items: (row, octet).  TN A / X items: (k-quad, 8-column block).
+    static constexpr int A_ITEMS = (MODE == MODE_NN) ? BM * OCT : (BK / 4) * (BM / 8);
+    static constexpr int X_ITEMS = (BK / 4) * (NC / 8);
+    static constexpr int A_PASSES = (A_ITEMS + NT - 1) / NT;
+    static constexpr int X_PASSES = (X_ITEMS + NT - 1) / NT;
+    static constexpr int A_VALS = (MODE == MODE_NN) ? 8 : 32;   // floats per A item
+    static constexpr int A_PLANES = A_LO ? 2 : 1;
+    static constexpr int X_PLANES = SPLIT ? 2 : 1;
+    static constexpr size_t A_LDS = static_cast<size_t>(BM) * SK;
+    static constexpr size_t X_LDS = static_cast<size_t>(NC) * SK;
+    static constexpr size_t STAGE = A_PLANES * A_LDS + X_PLANES * X_LDS;
+    static constexpr size_t LDS_BYTES = 2ull * STAGE * sizeof(__bf16);
+    static_assert(BK % 32 == 0 && (OCT & (OCT - 1)) == 0, "BK: multiple of 32, power-of-two octets");
+};
+
+// Element offset of (row r, k) in a swizzled k-contiguous plane.
+template <int SK, int OCT>
+__device__ __forceinline__ int swz(int r, int k) {
+    return r * SK + ((((k >> 3) ^ (r >> 3)) & (OCT - 1)) << 3) + (k & 7);
+}
+
+template <typename TA>
+__device__ __forceinline__ void load8(const TA* p, bool vec, int valid, float (&v)[8]) {
+    if (vec && valid >= 8) {
+        if constexpr (sizeof(TA) == 4) {
+            float a[4], b[4];
+            load_vec<TA, float, 4>(p, a);
+            load_vec<TA, float, 4>(p + 4, b);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) { v[e] = a[e]; v[4 + e] = b[e]; }
+        } else {
+            load_vec<TA, float, 8>(p, v);
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = (e < valid) ? Conv<float>::to(p[e]) : 0.0f;
+    }
+}
+
+template <typename TA, int MODE, bool SPLIT, int WR, int WC, int WGM, int WGN, int BK>
+__global__ __launch_bounds__(64 * WGM * WGN)
+void gemm_bf16_kernel(GemmArgs<TA, float, float> g) {
+    typedef Bf16Tile<TA, MODE, SPLIT, WR, WC, WGM, WGN, BK> T;
+    constexpr int SK = T::SK, OCT = T::OCT;
+    if (g.skip_flag && ((*g.skip_flag & g.skip_mask) == 0u)) return;
+
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __bf16* lds = reinterpret_cast<__bf16*>(smem_raw);
+    auto a_plane = [&](int buf, int pl) { return lds + buf * T::STAGE + pl * T::A_LDS; };
+    auto x_plane = [&](int buf, int pl) { return lds + buf * T::STAGE + T::A_PLANES * T::A_LDS + pl * T::X_LDS; };
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wm = wave % WGM, wn = wave / WGM;
+    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * T::BM;
+    const int split = blockIdx.y;
+    const int col0 = blockIdx.z * T::NC;
+    const int64_t kbeg = static_cast<int64_t>(split) * g.kchunk;
+    const int64_t kend = min(g.K, kbeg + g.kchunk);
+
+    float ra[T::A_PASSES][T::A_VALS];
+    float rx[T::X_PASSES][32];
+
+    auto load_a = [&](int64_t k0) {
+#pragma unroll
+        for (int p = 0; p < T::A_PASSES; ++p) {
+            const int it = p * T::NT + tid;
+            if (it >= T::A_ITEMS) break;
+            if (MODE == MODE_NN) {
+                const int r = it / OCT, o = it % OCT;
+                const int64_t gr = r0 + r, gk = k0 + 8 * o;
+                const int valid = (gr < g.rows) ? static_cast<int>(max<int64_t>(0, min<int64_t>(8, kend - gk))) : 0;
+                float v[8];
+                load8<TA>(g.A + gr * g.lda + gk, g.a_vec, valid, v);
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    float x = v[e];
+                    if (g.mu && e < valid) x = static_cast<float>(static_cast<double>(x) - g.mu[gk + e]);
+                    ra[p][e] = x;
+                }
+            } else {
+                const int cb = it % (T::BM / 8), kq = it / (T::BM / 8);
+                const int64_t gc = r0 + 8 * cb;          // first of 8 columns of A
+                const int cvalid = static_cast<int>(max<int64_t>(0, min<int64_t>(8, g.rows - gc)));
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int64_t ak = k0 + 4 * kq + q;
+                    float v[8];
+                    load8<TA>(g.A + ak * g.lda + gc, g.a_vec, ak < kend ? cvalid : 0, v);
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        float x = v[e];
+                        if (g.mu && ak < kend && e < cvalid) x = static_cast<float>(static_cast<double>(x) - g.mu[gc + e]);
+                        ra[p][q * 8 + e] = x;
+                    }
+                }
+            }
+        }
+    };
+    auto load_x = [&](int64_t k0) {
+#pragma unroll
+        for (int p = 0; p < T::X_PASSES; ++p) {
+            const int it = p * T::NT + tid;
+            if (it >= T::X_ITEMS) break;
+            const int cb = it % (T::NC / 8), kq = it / (T::NC / 8);
+            const int gc = col0 + 8 * cb;
+            const int cvalid = max(0, min(8, g.ncols - gc));
+            const bool xv = ((g.ldx & 3) == 0) && ((reinterpret_cast<uintptr_t>(g.X) & 15) == 0);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t gk = k0 + 4 * kq + q;
+                float v[8];
+                load8<float>(g.X + gk * g.ldx + gc, xv, gk < kend ? cvalid : 0, v);
+#pragma unroll
+                for (int e = 0; e < 8; ++e) rx[p][q * 8 + e] = v[e];
+            }
+        }
+    };
+    // Transposed 4 (k) x 8 (rows) block: row rr+e gets k-quad kq of the tile.
+    auto store_block = [&](__bf16* hi_plane, __bf16* lo_plane, bool lo_on, int rr, int kq, const float* v) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            v4bf h, lo;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float x = v[q * 8 + e];
+                h[q] = static_cast<__bf16>(x);
+                if (lo_on) lo[q] = static_cast<__bf16>(x - static_cast<float>(h[q]));
+            }
+            const int off = swz<SK, OCT>(rr + e, 4 * kq);
+            *reinterpret_cast<v4bf*>(hi_plane + off) = h;
+            if (lo_on) *reinterpret_cast<v4bf*>(lo_plane + off) = lo;
+        }
+    };
+    auto store_tiles = [&](int buf) {
+#pragma unroll
+        for (int p = 0; p < T::A_PASSES; ++p) {
+            const int it = p * T::NT + tid;
+            if (it >= T::A_ITEMS) break;
+            if (MODE == MODE_NN) {
+                const int r = it / OCT, o = it % OCT;
+                v8bf h, lo;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    h[e] = static_cast<__bf16>(ra[p][e]);
+                    if (T::A_LO) lo[e] = static_cast<__bf16>(ra[p][e] - static_cast<float>(h[e]));
+                }
+                const int off = swz<SK, OCT>(r, 8 * o);
+                *reinterpret_cast<v8bf*>(a_plane(buf, 0) + off) = h;
+                if (T::A_LO) *reinterpret_cast<v8bf*>(a_plane(buf, 1) + off) = lo;
+            } else {
+                const int cb = it % (T::BM / 8), kq = it / (T::BM / 8);
+                store_block(a_plane(buf, 0), a_plane(buf, T::A_LO ? 1 : 0), T::A_LO, 8 * cb, kq, ra[p]);
+            }
+        }
+#pragma unroll
+        for (int p = 0; p < T::X_PASSES; ++p) {
+            const int it = p * T::NT + tid;
+            if (it >= T::X_ITEMS) break;
+            const int cb = it % (T::NC / 8), kq = it / (T::NC / 8);
+            store_block(x_plane(buf, 0), x_plane(buf, SPLIT ? 1 : 0), SPLIT, 8 * cb, kq, rx[p]);
+        }
+    };
+
+    v4f acc[WR][WC];
+#pragma unroll
+    for (int i = 0; i < WR; ++i)
+#pragma unroll
+        for (int j = 0; j < WC; ++j) acc[i][j] = v4f{0, 0, 0, 0};
+
+    const int li = lane & 15, lk = lane >> 4;
+    const int wr0 = wm * WR * 16, wc0 = wn * WC * 16;
+
+    if (kbeg < kend) {
+        load_a(kbeg);
+        load_x(kbeg);
+        int buf = 0;
+        for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
+            store_tiles(buf);
+            __syncthreads();
+            if (k0 + BK < kend) { load_a(k0 + BK); load_x(k0 + BK); }
+#pragma unroll
+            for (int kg = 0; kg < BK; kg += 32) {
+                v8bf ah[WR], bh[WC], al[WR], bl[WC];
+#pragma unroll
+                for (int i = 0; i < WR; ++i) {
+                    const int off = swz<SK, OCT>(wr0 + 16 * i + li, kg + 8 * lk);
+                    ah[i] = *reinterpret_cast<const v8bf*>(a_plane(buf, 0) + off);
+                    if (T::A_LO) al[i] = *reinterpret_cast<const v8bf*>(a_plane(buf, 1) + off);
+                }
+#pragma unroll
+                for (int j = 0; j < WC; ++j) {
+                    const int off = swz<SK, OCT>(wc0 + 16 * j + li, kg + 8 * lk);
+                    bh[j] = *reinterpret_cast<const v8bf*>(x_plane(buf, 0) + off);
+                    if (SPLIT) bl[j] = *reinterpret_cast<const v8bf*>(x_plane(buf, 1) + off);
+                }
+#pragma unroll
+                for (int i = 0; i < WR; ++i)
+#pragma unroll
+                    for (int j = 0; j < WC; ++j) {
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+                        if (SPLIT) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+                        if (T::A_LO) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+                    }
+            }
+            buf ^= 1;
+        }
+    }
+
+    float* out = g.out + static_cast<int64_t>(split) * g.part_stride;
+#pragma unroll
+    for (int i = 0; i < WR; ++i) {
+#pragma unroll
+        for (int j = 0; j < WC; ++j) {
+            const int c = col0 + wc0 + 16 * j + li;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t r = r0 + wr0 + 16 * i + 4 * lk + e;
+                if (r < g.rows && c < g.ncols) out[r * g.ldo + c] = acc[i][j][e];
+            }
+        }
+    }
+}
+
+}  // namespace rsvd

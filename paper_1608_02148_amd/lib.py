@@ -14,6 +14,7 @@ c_void_p, c_size_t, c_double = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_double
 RSVD_F64, RSVD_F32, RSVD_BF16 = 0, 1, 2
 SDIST = {"normal": 0, "unif": 1, "rademacher": 2}
 PRECISION = {"plain": 0, "bf16_mixed": 1}
+ARITH = {"storage": 0, "bf16": 1, "split": 2}
 
 STATUS = {
     0: "ok", -1: "invalid argument", -2: "unsupported dtype, mode or size",
@@ -68,10 +69,10 @@ _PROTOS = {
     "rsvd_philox_words": (c_int32, [c_void_p, c_int64, c_int32, c_uint64, c_uint32, c_void_p]),
     "rsvd_test_matrix": (c_int32, [c_void_p, c_int32, c_int64, c_int32, c_uint64, c_uint32, c_int32,
                                    c_void_p, c_int64]),
-    "rsvd_gemm_nn": (c_int32, [c_void_p, c_int32, c_int64, c_int64, c_int32, c_void_p, c_int64, c_void_p,
-                               c_int64, c_void_p, c_int64, c_void_p, c_size_t]),
-    "rsvd_gemm_tn": (c_int32, [c_void_p, c_int32, c_int64, c_int64, c_int32, c_void_p, c_int64, c_void_p,
-                               c_int64, c_void_p, c_int64, c_void_p, c_size_t]),
+    "rsvd_gemm_nn": (c_int32, [c_void_p, c_int32, c_int32, c_int64, c_int64, c_int32, c_void_p, c_int64,
+                               c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_size_t]),
+    "rsvd_gemm_tn": (c_int32, [c_void_p, c_int32, c_int32, c_int64, c_int64, c_int32, c_void_p, c_int64,
+                               c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_size_t]),
     "rsvd_orthonormalize": (c_int32, [c_void_p, c_int32, c_int64, c_int32, c_void_p, c_int64, c_void_p,
                                       c_void_p, c_void_p, c_size_t]),
     "rsvd_block_workspace_size": (c_int32, [c_void_p, c_int32, c_int64, c_int64, c_int32, c_void_p]),

@@ -16,7 +16,8 @@ DEV = "cuda"
 
 
 def _np(t):
-    return t.detach().cpu().numpy()
+    t = t.detach().cpu()
+    return (t.to(torch.float64) if t.dtype == torch.bfloat16 else t).numpy()
 
 
 @pytest.mark.parametrize("n,groups,seed,sid", [(1000, 8, 2148, 0), (257, 33, 2**40 + 12345, 7),
@@ -145,3 +146,45 @@ def test_small_svd_matches_lapack(gpu_lib, c):
         if sep > 1e-6:           # well separated: the vectors are unique up to sign
             np.testing.assert_allclose(abs(J[:, i] @ Vte[i]), 1.0, atol=tol / sep)
             np.testing.assert_allclose(abs(W[:, i] @ Ue[:, i]), 1.0, atol=1e-12 / sep)
+
+
+@pytest.mark.parametrize("arith", ["bf16", "split"])
+@pytest.mark.parametrize("dt", ["f32", "bf16"])
+@pytest.mark.parametrize("m,K,c", [(300, 257, 5), (517, 1000, 100), (64, 33, 128), (2000, 640, 30)])
+def test_bf16_products_exact_integers(gpu_lib, arith, dt, m, K, c):
+    """Integers of magnitude <= 8 are exact in bf16, so both bf16 modes are exact."""
+    from paper_1608_02148_amd import api
+    rng = np.random.default_rng(m + K + c)
+    A = _int_matrix(rng, (m, K))
+    X = _int_matrix(rng, (K, c), -4, 4)
+    Y = _np(api.gemm_nn(torch.tensor(A, dtype=DT[dt], device=DEV), torch.tensor(X, dtype=torch.float32,
+                                                                                 device=DEV), arith))
+    assert np.array_equal(Y, A @ X)
+    Q = _int_matrix(rng, (m, c), -3, 3)
+    Z = _np(api.gemm_tn(torch.tensor(A, dtype=DT[dt], device=DEV), torch.tensor(Q, dtype=torch.float32,
+                                                                                device=DEV), arith))
+    assert np.array_equal(Z, A.T @ Q)
+
+
+@pytest.mark.parametrize("dt", ["f32", "bf16"])
+def test_split_bf16_is_f32_accurate(gpu_lib, dt):
+    """Split products: the dropped A_lo X_lo term bounds the error near 2^-18 of
+    |A||X| per product (a few times plain f32); plain bf16 products are ~2^-9."""
+    from paper_1608_02148_amd import api
+    rng = np.random.default_rng(7)
+    m, K, c = 3000, 700, 64
+    Ag = torch.tensor(rng.standard_normal((m, K)), dtype=DT[dt], device=DEV)
+    A = _np(Ag).astype(np.float64)
+    Xg = torch.tensor(rng.standard_normal((K, c)), dtype=torch.float32, device=DEV)
+    X = _np(Xg).astype(np.float64)
+    ref = A @ X
+    scale = np.abs(A).max() * np.abs(X).max() * np.sqrt(K)
+    err_split = np.abs(_np(api.gemm_nn(Ag, Xg, "split")) - ref).max() / scale
+    err_bf16 = np.abs(_np(api.gemm_nn(Ag, Xg, "bf16")) - ref).max() / scale
+    err_f32 = np.abs(_np(api.gemm_nn(Ag, Xg)) - ref).max() / scale
+    assert err_split < 2e-6 and err_split < 10 * max(err_f32, 1e-7)
+    assert err_bf16 > 30 * err_split
+    Qg = torch.tensor(rng.standard_normal((m, c)), dtype=torch.float32, device=DEV)
+    refz = A.T @ _np(Qg).astype(np.float64)
+    sz = np.abs(A).max() * np.sqrt(m) * 4
+    assert np.abs(_np(api.gemm_tn(Ag, Qg, "split")) - refz).max() / sz < 1e-6

@@ -200,3 +200,35 @@ def test_invalid_arguments_raise():
         api.rsvd(A, 20)
     with pytest.raises(lib.RsvdError):
         api.rsvd(A, 0)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+@pytest.mark.parametrize("m,n,k,p,q", [(6000, 800, 40, 10, 2), (3000, 1200, 60, 20, 1)])
+def test_bf16_mixed_mode(dtype, m, n, k, p, q):
+    """Mixed mode: bf16 early passes, f32-accurate last sketch and projection.
+
+    Checked against the FP64 oracle on the same stored instance: leading
+    singular values (well separated from the tail) to 1e-4 relative, all k
+    values normwise to 2e-3 sigma_1, and the rank-k residual within 1% of the
+    oracle's.
+    """
+    from paper_1608_02148_amd import api
+    sig = syn.spectrum("exp", min(m, n), tau=20.0)
+    A = syn.planted(m, n, sig, m + 7 * n)
+    Ag = torch.tensor(A, dtype=dtype, device=DEV)
+    A_inst = _np(Ag)
+    U, S, V = api.rsvd(Ag, k, p=p, q=q, seed=5, precision="bf16_mixed")
+    Uo, so, Vo = orc.rsvd(A_inst, k, p=p, q=q, seed=5)
+    s = _np(S)
+    np.testing.assert_allclose(s[: k // 2], so[: k // 2], rtol=1e-4)
+    assert np.max(np.abs(s - so)) <= 2e-3 * so[0]
+    r_gpu = orc.lowrank_residual(A_inst, _np(U), s, _np(V))
+    r_ora = orc.lowrank_residual(A_inst, Uo, so, Vo)
+    assert r_gpu <= 1.01 * r_ora
+
+
+def test_bf16_mixed_rejected_for_f64():
+    from paper_1608_02148_amd import api, lib
+    A = torch.zeros(100, 50, dtype=torch.float64, device=DEV)
+    with pytest.raises(lib.RsvdError):
+        api.rsvd(A, 5, precision="bf16_mixed")
