@@ -10,7 +10,12 @@ Also reported:
   roofline      -- the dominant product kernel, timed with HIP events on the
                    library's stream inside the timed region;
   excess_err    -- ||A - U S V^T||_2 / sigma_{k+1} - 1 of the last solve;
-  cpu_baseline  -- the FP64 oracle on the host cores for a row sample.
+  cpu_baseline  -- the FP64 oracle on the host cores (same matrix, repeated
+                   for about 10 s);
+  bf16_mixed    -- the same workload in the bf16 mixed-precision mode;
+  batched       -- 4096 ragged f32 matrices (m in [256, 4096], n in
+                   [64, 1024], k in [8, 64], p=10, q=2, sigma_i = i^-alpha)
+                   as one captured graph: solves/s, p50 / p99 latency.
 
 Usage: python bench.py [--gpus 1] [--steps 10] [--warmup 3]
 """
@@ -60,16 +65,77 @@ def cpu_baseline(A, k, p, q, seed, rows):
     from oracle import rsvd as orc
     sample = A[:rows].double().cpu().numpy()
     n = sample.shape[1]
+    reps = 0
     t0 = time.perf_counter()
-    orc.rsvd(sample, k, p=p, q=q, seed=seed)
-    dt = time.perf_counter() - t0
+    while True:            # repeat the solve until about 10 s of host work
+        orc.rsvd(sample, k, p=p, q=q, seed=seed)
+        reps += 1
+        if time.perf_counter() - t0 >= 10.0 or reps >= 20:
+            break
+    dt = (time.perf_counter() - t0) / reps
     l = min(k + p, rows, n)
     flops = (2 * q + 2) * 2.0 * rows * n * l
     threads = max([t.get("num_threads", 1) for t in threadpool_info() if t.get("user_api") == "blas"] or [1])
     del np
     return dict(value=flops / dt / 1e12, unit="TFLOP/s", cores=int(threads), kind="oracle",
-                seconds=dt,
-                sample=f"first {rows} of {A.shape[0]} rows, n={n}, k={k}, p={p}, q={q}, float64 numpy oracle")
+                seconds=dt * reps,
+                sample=f"first {rows} of {A.shape[0]} rows, n={n}, k={k}, p={p}, q={q}, float64 numpy oracle, "
+                       f"mean of {reps} solves")
+
+
+def batched_arm(steps, warmup, precision="plain"):
+    """C4: 4096 ragged f32 matrices, p=10, q=2, one captured graph per run.
+
+    Returns solves/s over `steps` graph replays, algorithmic TFLOP/s and GB/s
+    of the batch, and p50 / p99 of the per-solve latency (device clock from a
+    solve's first step to its last) in the last replay.
+    """
+    import numpy as np
+    import torch
+
+    from paper_1608_02148_amd import api
+    from synth import matrices as syn
+
+    c = syn.CONFIGS["c4"]
+    log(f"[c4] generating {c['batch']} ragged matrices")
+    data = syn.c4_torch(device="cuda", batch=c["batch"], seed=c["gen_seed"])
+    torch.cuda.synchronize()
+    ks = [int(x) for x in data["k"]]
+    m, n = data["m"].astype(np.float64), data["n"].astype(np.float64)
+    l = np.minimum(np.array(ks) + c["p"], np.minimum(m, n))
+    flops = float(np.sum((2 * c["q"] + 2) * 2.0 * m * n * l))
+    a_bytes = float(np.sum(m * n * 4.0)) * (2 * c["q"] + 2)
+    log(f"[c4] planning; {flops / 1e12:.3f} TFLOP and {a_bytes / 1e9:.1f} GB of A reads per batch")
+    bt = api.Batch(data["A"], ks, p=c["p"], q=c["q"], seed=c["omega_seed"], precision=precision,
+                   graph=True, stamps=True)
+    for _ in range(warmup):
+        bt.run()
+    torch.cuda.synchronize()
+    log(f"[c4] timing {steps} graph replays")
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        bt.run()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    st, hz = bt.stamps()
+    lat_ms = (st[:, 1] - st[:, 0]) / hz * 1e3
+    out = {
+        "workload": f"{c['batch']} ragged f32 matrices, m~U[256,4096], n~U[64,1024], k~U[8,64], p={c['p']}, "
+                    f"q={c['q']}, sigma_i=i^-alpha, alpha~U[0.5,3]",
+        "precision": precision,
+        "solves_per_s": round(c["batch"] / dt, 1), "ms_per_batch": round(dt * 1e3, 3),
+        "tflops": round(flops / dt / 1e12, 3), "a_read_gbs": round(a_bytes / dt / 1e9, 1),
+        "mfma_frac": round(flops / dt / 1e12 / PEAKS["f32_mfma_tflops"], 4),
+        "hbm_frac": round(a_bytes / dt / 1e9 / PEAKS["hbm_gbs"], 4),
+        "latency_ms_p50": round(float(np.percentile(lat_ms, 50)), 3),
+        "latency_ms_p99": round(float(np.percentile(lat_ms, 99)), 3),
+        "work_bytes": bt.work_bytes,
+    }
+    log(f"[c4] {out}")
+    bt.close()
+    del data
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -83,8 +149,10 @@ def main():
     ap.add_argument("--p", type=int, default=20)
     ap.add_argument("--q", type=int, default=2)
     ap.add_argument("--seed", type=int, default=2148)
-    ap.add_argument("--cpu-rows", type=int, default=25000)
+    ap.add_argument("--cpu-rows", type=int, default=100000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-only", action="store_true")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -99,6 +167,9 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.batched_only:
+        print(json.dumps({"batched": batched_arm(args.steps, args.warmup)}), flush=True)
+        return
     m, n, k, p, q = args.m, args.n, args.k, args.p, args.q
     log(f"generating A {m}x{n} float32 (planted exp(-i/50) spectrum + noise floor)")
     A = syn.c2_matrix(device=dev, m=m, n=n)
@@ -176,6 +247,9 @@ def main():
         log(f"cpu baseline: oracle on {args.cpu_rows} rows")
         cpu = cpu_baseline(A, k, p, q, args.seed, min(args.cpu_rows, m))
         log(f"cpu baseline {cpu['value']:.4f} TFLOP/s in {cpu['seconds']:.1f} s on {cpu['cores']} threads")
+    del A
+    torch.cuda.empty_cache()
+    batched = None if args.no_batched else batched_arm(args.steps, args.warmup)
 
     rec = {
         "metric": "rSVD TFLOP/s (FP32 plain, C2)",
@@ -188,6 +262,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "bf16_mixed": bf16_arm,
+        "batched": batched,
     }
     print(json.dumps(rec), flush=True)
 

@@ -147,6 +147,61 @@ int rpca_run(rsvd_handle_t handle, int32_t dtype, int64_t m, int64_t n,
  * stayed numerically zero after the shifted Cholesky, else RSVD_OK. */
 int rsvd_sync_info(rsvd_handle_t handle, const rsvd_info* dinfo, rsvd_info* hinfo);
 
+/* ---- Ragged batches ------------------------------------------------------
+ * Many independent randomized SVDs (Alg. RSVDalgorithm, one per matrix, all
+ * with the same rsvd_params except the Omega stream), run as one sequence of
+ * grouped launches: each step of the solve is a single launch over every
+ * matrix of the batch, so thousands of small solves fill the device.
+ *
+ * Life cycle: rsvd_batch_create (host; sizes the workspace) ->
+ * rsvd_batch_bind (uploads the launch tables into the workspace; synchronises
+ * the handle's stream once; with RSVD_BATCH_GRAPH also captures the whole
+ * launch sequence in a HIP graph) -> rsvd_batch_run, any number of times
+ * (asynchronous on the handle's stream; no allocation, no host
+ * synchronisation; without RSVD_BATCH_GRAPH a caller may capture it in its
+ * own graph) -> rsvd_batch_destroy.  The handle must outlive the batch.
+ *
+ * Results: matrix b gets the solve that rsvd_run computes for it with
+ * params.stream_id = desc[b].stream_id (same steps and kernels); products here
+ * never split their reduction into partial sums, so the rounding can differ
+ * from rsvd_run's, within the same accuracy.
+ * Rules: every matrix has the same dtype; either every U is NULL or none is;
+ * l_b = min(k_b + p, m_b, n_b) <= RSVD_MAX_L.  Argument errors in any entry
+ * fail the whole create call. */
+typedef struct {
+    const void* A;       /* m x n (dtype, lda >= n), read-only          */
+    int64_t lda;
+    int64_t m, n;
+    int32_t k;           /* 1 <= k < min(m, n)                          */
+    uint32_t stream_id;  /* Omega counter word 2 for this matrix        */
+    void* U;             /* m x k (ldu >= k) or NULL                    */
+    int64_t ldu;
+    double* S;           /* k singular values, descending               */
+    void* V;             /* n x k (ldv >= k) or NULL                    */
+    int64_t ldv;
+    rsvd_info* info;     /* device record or NULL                       */
+} rsvd_batch_desc;
+
+typedef struct rsvd_batch_s* rsvd_batch_t;
+
+#define RSVD_BATCH_GRAPH  1   /* bind captures the launches in a HIP graph     */
+#define RSVD_BATCH_STAMPS 2   /* record device-clock stamps per matrix          */
+
+/* descs: HOST array of `count` entries (their pointers are device pointers,
+ * recorded at bind time).  *work_bytes receives the workspace size. */
+int rsvd_batch_create(rsvd_handle_t handle, int32_t dtype, int32_t count,
+                      const rsvd_batch_desc* descs, const rsvd_params* params,
+                      int32_t flags, rsvd_batch_t* batch, size_t* work_bytes);
+/* work: device buffer of >= work_bytes, 256-byte aligned, owned by the caller
+ * and reserved for this batch until it is destroyed or bound again. */
+int rsvd_batch_bind(rsvd_batch_t batch, void* work, size_t work_bytes);
+int rsvd_batch_run(rsvd_batch_t batch);
+/* With RSVD_BATCH_STAMPS: synchronise and copy the device-clock stamps of the
+ * last run, host[2b] = when matrix b's first step ran, host[2b+1] = when its
+ * last step ran; *ticks_per_second receives the clock rate. */
+int rsvd_batch_stamps(rsvd_batch_t batch, uint64_t* host, double* ticks_per_second);
+int rsvd_batch_destroy(rsvd_batch_t batch);
+
 /* ---- Optional per-kernel timing ------------------------------------------
  * When enabled, every product with A (the passes of Alg. rqb and
  * Alg. subspace_iter) is bracketed by HIP events on the handle's stream, so a

@@ -129,6 +129,98 @@ def rpca(A, k, center=True, retx=True, p=10, q=2, seed=0, stream_id=0, sdist="no
     return dict(rotation=rot, eigvals=ev, sdev=sd, x=x, center=ctr)
 
 
+class Batch:
+    """A ragged batch of randomized SVDs run as grouped launches (rsvd_batch_*).
+
+    ``As``: list of 2-D row-major tensors on one device, one dtype (views into
+    one buffer are fine).  ``ks``: target rank per matrix.  ``stream_ids``:
+    Omega stream per matrix (default: the matrix index).  Outputs live in
+    ``U``, ``S``, ``V`` (lists of views into three flat buffers) after
+    ``run()`` and the stream completing.  ``graph=True`` replays one captured
+    HIP graph per run; ``stamps=True`` records device-clock stamps per matrix.
+    """
+
+    def __init__(self, As, ks, p=10, q=2, seed=0, stream_ids=None, sdist="normal", precision="plain",
+                 compute_u=True, compute_v=True, graph=True, stamps=False, infos=False):
+        if len(As) == 0 or len(As) != len(ks):
+            raise ValueError("As and ks must be non-empty lists of equal length")
+        dts = {_check_matrix(A) for A in As}
+        if len(dts) != 1:
+            raise ValueError("every matrix of a batch must have the same dtype")
+        self.dtype = dts.pop()
+        dev = As[0].device
+        self.device = dev
+        self.count = len(As)
+        od = out_dtype(As[0])
+        shapes = [(int(A.shape[0]), int(A.shape[1]), int(k)) for A, k in zip(As, ks)]
+        u_off, v_off, s_off = [0], [0], [0]
+        for m, n, k in shapes:
+            u_off.append(u_off[-1] + m * k)
+            v_off.append(v_off[-1] + n * k)
+            s_off.append(s_off[-1] + k)
+        self.u_flat = torch.empty(max(u_off[-1], 1), dtype=od, device=dev) if compute_u else None
+        self.v_flat = torch.empty(max(v_off[-1], 1), dtype=od, device=dev) if compute_v else None
+        self.s_flat = torch.empty(s_off[-1], dtype=torch.float64, device=dev)
+        self.info = (torch.zeros(self.count, ctypes.sizeof(L.Info), dtype=torch.uint8, device=dev)
+                     if infos else None)
+        self.U, self.S, self.V = [], [], []
+        descs = (L.BatchDesc * self.count)()
+        sids = list(range(self.count)) if stream_ids is None else [int(x) for x in stream_ids]
+        for b, (A, (m, n, k)) in enumerate(zip(As, shapes)):
+            U = self.u_flat[u_off[b]:u_off[b + 1]].view(m, k) if compute_u else None
+            V = self.v_flat[v_off[b]:v_off[b + 1]].view(n, k) if compute_v else None
+            S = self.s_flat[s_off[b]:s_off[b + 1]]
+            self.U.append(U); self.S.append(S); self.V.append(V)
+            d = descs[b]
+            d.A, d.lda, d.m, d.n, d.k, d.stream_id = A.data_ptr(), A.stride(0), m, n, k, sids[b]
+            d.U, d.ldu = (U.data_ptr(), k) if U is not None else (None, 0)
+            d.S = S.data_ptr()
+            d.V, d.ldv = (V.data_ptr(), k) if V is not None else (None, 0)
+            d.info = self.info[b].data_ptr() if infos else None
+        self._As = list(As)            # keep the inputs alive as long as the batch
+        prm = make_params(p, q, seed, 0, sdist, precision)
+        flags = (L.BATCH_GRAPH if graph else 0) | (L.BATCH_STAMPS if stamps else 0)
+        self._lib = L.load()
+        self._h = handle(dev)
+        self._b = ctypes.c_void_p()
+        nbytes = ctypes.c_size_t()
+        L.check(self._lib.rsvd_batch_create(self._h, self.dtype, self.count, descs, ctypes.byref(prm), flags,
+                                            ctypes.byref(self._b), ctypes.byref(nbytes)), "rsvd_batch_create")
+        self.work_bytes = nbytes.value
+        self.work = workspace(nbytes.value, dev)
+        L.check(self._lib.rsvd_batch_bind(self._b, _ptr(self.work), self.work.numel()), "rsvd_batch_bind")
+
+    def run(self):
+        handle(self.device)            # follow torch's current stream
+        L.check(self._lib.rsvd_batch_run(self._b), "rsvd_batch_run")
+
+    def stamps(self):
+        """(count x 2 int64 numpy array of device-clock stamps, ticks per second)."""
+        import numpy as np
+        out = np.zeros((self.count, 2), dtype=np.uint64)
+        hz = ctypes.c_double()
+        L.check(self._lib.rsvd_batch_stamps(self._b, out.ctypes.data_as(ctypes.c_void_p), ctypes.byref(hz)),
+                "rsvd_batch_stamps")
+        return out.astype(np.int64), hz.value
+
+    def infos(self):
+        """Decode the per-matrix info records (synchronises)."""
+        torch.cuda.synchronize(self.device)
+        raw = self.info.cpu().numpy()
+        return [L.Info.from_buffer_copy(raw[b].tobytes()) for b in range(self.count)]
+
+    def close(self):
+        if getattr(self, "_b", None) is not None and self._b.value:
+            self._lib.rsvd_batch_destroy(self._b)
+            self._b = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def new_info(device):
     return torch.zeros(ctypes.sizeof(L.Info), dtype=torch.uint8, device=device)
 

@@ -56,6 +56,7 @@ struct Plan {
     int dtype = 0;
     int64_t m = 0, n = 0;
     int k = 0, p = 0, q = 0, l = 0, Lp = 0, kp = 0;
+    int tile = 0;       // forced output tile width of every product (0: chosen per product)
     Splits sp{};
     size_t Y = 0, Z = 0, Om = 0, part = 0, gram = 0, rinv = 0, racc = 0, sigma = 0,
            xv = 0, xu = 0, jk = 0, wks = 0, vtmp = 0, mu = 0, mupart = 0, status = 0, bytes = 0;
@@ -74,21 +75,25 @@ inline int validate(int32_t dtype, int64_t m, int64_t n, int32_t k, const rsvd_p
     return RSVD_OK;
 }
 
-inline Plan make_plan(int dtype, int64_t m, int64_t n, int k, const rsvd_params* prm, int num_cu) {
+// batch = true: one problem of a grouped batch, whose parallelism comes from
+// the batch, so no product splits its reduction (every problem then issues
+// the same sequence of steps).
+inline Plan make_plan(int dtype, int64_t m, int64_t n, int k, const rsvd_params* prm, int num_cu,
+                      bool batch = false) {
     Plan P;
     P.dtype = dtype; P.m = m; P.n = n; P.k = k; P.q = prm->q;
     P.l = static_cast<int>(std::min<int64_t>(static_cast<int64_t>(k) + prm->p, std::min(m, n)));
     P.p = P.l - k;
     P.Lp = tile_cols(P.l);
     P.kp = tile_cols(k);
-    P.sp = make_splits(m, n, num_cu);
+    P.sp = batch ? Splits{1, 1, 1, 1} : make_splits(m, n, num_cu);
     const size_t cs = comp_size(dtype);
     Layout L;
     P.status = L.take(kAlign);
     P.Y = L.take(static_cast<size_t>(m) * P.Lp * cs);
     P.Z = L.take(static_cast<size_t>(n) * P.Lp * cs);
     P.Om = L.take(static_cast<size_t>(n) * P.Lp * cs);
-    const size_t part_tn = static_cast<size_t>(P.sp.tn) * n * P.Lp * cs;
+    const size_t part_tn = P.sp.tn > 1 ? static_cast<size_t>(P.sp.tn) * n * P.Lp * cs : 0;
     const size_t part_g = static_cast<size_t>(std::max(P.sp.gram_m, P.sp.gram_n)) * P.Lp * P.Lp * 8;
     P.part = L.take(std::max(part_tn, part_g));
     P.gram = L.take(static_cast<size_t>(P.Lp) * P.Lp * 8);
@@ -123,41 +128,32 @@ template <typename T> inline T* at(void* work, size_t off) {
 // ill-conditioned Gram matrix.
 // rfac (optional, f64, 4 consecutive l x l blocks) receives R1, R2, R3 (R3 = I
 // when the third pass is skipped) and, in the fourth block, R = R3 R2 R1.
-template <typename TC>
-hipError_t orthonormalize(hipStream_t st, TC* M, int64_t ldm, int64_t rows, int l, int Lp, int S,
+template <typename TC, class Ex>
+hipError_t orthonormalize(Ex& ex, int tile, TC* M, int64_t ldm, int64_t rows, int l, int Lp, int S,
                           double* part, double* gram, TC* rinv, double* rfac, uint32_t* status,
-                          int num_cu, bool adaptive = false) {
-    (void)num_cu;
-    static bool ready = false;
-    const size_t lds = chol_lds_bytes(l);
-    if (!ready) {
-        RSVD_TRY(allow_lds(chol_kernel<TC>, chol_lds_bytes(CHOL_MAX_L)));
-        ready = true;
-    }
+                          bool adaptive = false) {
     for (int pass = 1; pass <= 3; ++pass) {
         const bool conditional = (pass == 3) || (pass == 2 && adaptive);
         const uint32_t* skip = conditional ? status : nullptr;
         const uint32_t need = (pass == 2) ? ST_NEED_P2 : ST_NEED_P3;
-        RSVD_TRY((launch_gemm<TC, TC, double, MODE_TN>(st, M, ldm, l, rows, M, ldm, l, part, Lp, S,
-                                                      static_cast<int64_t>(Lp) * Lp, nullptr, skip,
-                                                      need)));
-        if (S > 1) RSVD_TRY(launch_reduce<double>(st, part, S, static_cast<int64_t>(Lp) * Lp, Lp, l, l,
-                                                  gram, Lp, skip, need));
+        RSVD_TRY((gemm_plain<TC, TC, double, MODE_TN>(ex, tile, M, ldm, l, rows, M, ldm, l, part, Lp, S,
+                                                      static_cast<int64_t>(Lp) * Lp, nullptr, skip, need)));
+        if (S > 1) RSVD_TRY(reduce_step<double>(ex, part, S, static_cast<int64_t>(Lp) * Lp, Lp, l, l, gram, Lp,
+                                                skip, need));
         CholArgs ca;
         ca.part = (S > 1) ? gram : part; ca.S = 1; ca.part_stride = 0; ca.ldp = Lp;
         ca.l = l; ca.mrows = rows; ca.rinv = rinv; ca.ldr = Lp;
         ca.rout = rfac ? rfac + static_cast<size_t>(pass - 1) * l * l : nullptr;
         ca.status = status; ca.pass = pass; ca.skip_unless_pending = conditional; ca.adaptive = adaptive;
-        hipLaunchKernelGGL(chol_kernel<TC>, dim3(1), dim3(CHOL_THREADS), lds, st, ca);
-        RSVD_TRY(hipGetLastError());
-        RSVD_TRY((launch_gemm<TC, TC, TC, MODE_NN>(st, M, ldm, rows, l, rinv, Lp, l, M, ldm, 1, 0,
-                                                  nullptr, skip, need)));
+        RSVD_TRY(ex.template run<CholBody<TC>>(ca));
+        RSVD_TRY((gemm_plain<TC, TC, TC, MODE_NN>(ex, tile, M, ldm, rows, l, rinv, Lp, l, M, ldm, 1, 0, nullptr,
+                                                  skip, need)));
     }
     if (rfac) {   // R = R3 (R2 R1); the product R2 R1 goes through the gram scratch
         const size_t ll = static_cast<size_t>(l) * l;
-        RSVD_TRY((launch_gemm<double, double, double, MODE_NN>(st, rfac + ll, l, l, l, rfac, l, l, gram, l, 1, 0,
-                                                              nullptr, nullptr, 0)));
-        RSVD_TRY((launch_gemm<double, double, double, MODE_NN>(st, rfac + 2 * ll, l, l, l, gram, l, l,
+        RSVD_TRY((gemm_plain<double, double, double, MODE_NN>(ex, tile, rfac + ll, l, l, l, rfac, l, l, gram, l, 1,
+                                                              0, nullptr, nullptr, 0)));
+        RSVD_TRY((gemm_plain<double, double, double, MODE_NN>(ex, tile, rfac + 2 * ll, l, l, l, gram, l, l,
                                                               rfac + 3 * ll, l, 1, 0, nullptr, nullptr, 0)));
     }
     return hipSuccess;
@@ -173,9 +169,10 @@ inline hipEvent_t pool_event(rsvd_handle_t h) {
     return h->event_pool[h->pool_used++];
 }
 
+// h == nullptr (recorded batch steps) or profiling off: just issue the step.
 template <typename F>
 hipError_t timed(rsvd_handle_t h, int kind, double flops, double bytes, F&& launch) {
-    if (!h->profiling) return launch();
+    if (!h || !h->profiling) return launch();
     ProfRecord r;
     r.kind = kind; r.flops = flops; r.bytes = bytes;
     r.start = pool_event(h);
@@ -197,14 +194,17 @@ struct SolveOut {
     int scale_u;               // 1: U columns scaled by sigma (PCA x = U S)
     int center;
     rsvd_info* info;
+    uint64_t* stamps;          // optional [first step, last step] device clock
 };
 
-template <typename TA, typename TC>
-hipError_t solve(rsvd_handle_t h, const Plan& P, const TA* A, int64_t lda, const rsvd_params* prm,
-                 const SolveOut& o, void* work) {
-    hipStream_t st = h->stream;
+// Every step of one solve, issued through the executor: launched at once for
+// a single solve, or recorded as this problem's share of grouped batch steps.
+// prof (may be null) receives the event timings of the products with A.
+template <typename TA, typename TC, class Ex>
+hipError_t solve_steps(Ex& ex, rsvd_handle_t prof, const Plan& P, const TA* A, int64_t lda,
+                       const rsvd_params* prm, uint32_t stream_id, const SolveOut& o, void* work) {
     const int64_t m = P.m, n = P.n;
-    const int l = P.l, Lp = P.Lp, k = P.k;
+    const int l = P.l, Lp = P.Lp, k = P.k, tile = P.tile;
     uint32_t* status = at<uint32_t>(work, P.status);
     TC* Y = at<TC>(work, P.Y);
     TC* Z = at<TC>(work, P.Z);
@@ -219,30 +219,20 @@ hipError_t solve(rsvd_handle_t h, const Plan& P, const TA* A, int64_t lda, const
     TC* xu = at<TC>(work, P.xu);
     double* jk = at<double>(work, P.jk);
     double* mu = o.center ? at<double>(work, P.mu) : nullptr;
-    const int num_cu = h->dev.num_cu;
 
-    hipLaunchKernelGGL(clear_u32_kernel, dim3(1), dim3(64), 0, st, status, 1);
-    RSVD_TRY(hipGetLastError());
+    if (o.stamps) RSVD_TRY(ex.template run<StampBody>(StampBody::Args{o.stamps}));
+    RSVD_TRY(ex.template run<ClearBody>(ClearBody::Args{status, 1}));
 
     if (mu) {   // column means (implicit centring, Sec. 4.2)
         const int S = P.sp.colsum;
-        const int64_t rps = cdiv(m, S);
         double* mp = at<double>(work, P.mupart);
-        hipLaunchKernelGGL(colsum_partial_kernel<TA>, dim3(static_cast<unsigned>(cdiv(n, 256)), S), dim3(256), 0,
-                           st, A, lda, m, n, rps, mp);
-        hipLaunchKernelGGL(colmean_finish_kernel, dim3(static_cast<unsigned>(cdiv(n, 256))), dim3(256), 0, st,
-                           mp, S, m, n, mu);
-        RSVD_TRY(hipGetLastError());
+        RSVD_TRY(ex.template run<ColsumBody<TA>>(typename ColsumBody<TA>::Args{A, lda, m, n, cdiv(m, S), S, mp}));
+        RSVD_TRY(ex.template run<ColmeanBody>(ColmeanBody::Args{mp, S, m, n, mu}));
     }
 
     // Alg. rqb steps 2-3: Omega and the sketch Y = A Omega.
-    {
-        const int groups = Lp / 4;
-        const int64_t total = n * groups;
-        hipLaunchKernelGGL(omega_kernel<TC>, dim3(static_cast<unsigned>(cdiv(total, 256))), dim3(256), 0, st,
-                           n, l, Lp, prm->seed, prm->stream_id, prm->sdist, Om, static_cast<int64_t>(Lp));
-        RSVD_TRY(hipGetLastError());
-    }
+    RSVD_TRY(ex.template run<OmegaBody<TC>>(typename OmegaBody<TC>::Args{
+        n, l, Lp, prm->seed, stream_id, prm->sdist, Om, static_cast<int64_t>(Lp)}));
     const double pass_flops = 2.0 * static_cast<double>(m) * n * l;
     const double a_bytes = static_cast<double>(m) * n * sizeof(TA);
     const double nn_bytes = a_bytes + (static_cast<double>(n) + m) * l * sizeof(TC);
@@ -253,9 +243,9 @@ hipError_t solve(rsvd_handle_t h, const Plan& P, const TA* A, int64_t lda, const
     const bool mixed = prm->precision == RSVD_PREC_BF16_MIXED;
     const int early = mixed ? 1 : 0, late = mixed ? 2 : 0;
     auto ax = [&](const TC* X, int arith) -> hipError_t {     // Y (m x Lp) = A X
-        return timed(h, 0, pass_flops, nn_bytes, [&] {
-            return launch_gemm_arith<TA, TC, MODE_NN>(st, arith, A, lda, m, n, X, Lp, l, Y, Lp, 1, 0, mu,
-                                                      nullptr, 0);
+        return timed(prof, 0, pass_flops, nn_bytes, [&] {
+            return gemm_step<TA, TC, MODE_NN>(ex, arith, tile, A, lda, m, n, X, Lp, l, Y, Lp, 1, 0, mu, nullptr,
+                                              0);
         });
     };
     RSVD_TRY(ax(Om, P.q == 0 ? late : early));
@@ -263,63 +253,57 @@ hipError_t solve(rsvd_handle_t h, const Plan& P, const TA* A, int64_t lda, const
     auto aty = [&](TC* dst, int arith) -> hipError_t {     // dst (n x Lp) = A^T Y
         const int S = P.sp.tn;
         if (S == 1)
-            return timed(h, 1, pass_flops, tn_bytes, [&] {
-                return launch_gemm_arith<TA, TC, MODE_TN>(st, arith, A, lda, n, m, Y, Lp, l, dst, Lp, 1, 0, mu,
-                                                          nullptr, 0);
+            return timed(prof, 1, pass_flops, tn_bytes, [&] {
+                return gemm_step<TA, TC, MODE_TN>(ex, arith, tile, A, lda, n, m, Y, Lp, l, dst, Lp, 1, 0, mu,
+                                                  nullptr, 0);
             });
-        RSVD_TRY(timed(h, 1, pass_flops, tn_bytes, [&] {
-            return launch_gemm_arith<TA, TC, MODE_TN>(st, arith, A, lda, n, m, Y, Lp, l, partc, Lp, S,
-                                                      static_cast<int64_t>(n) * Lp, mu, nullptr, 0);
+        RSVD_TRY(timed(prof, 1, pass_flops, tn_bytes, [&] {
+            return gemm_step<TA, TC, MODE_TN>(ex, arith, tile, A, lda, n, m, Y, Lp, l, partc, Lp, S,
+                                              static_cast<int64_t>(n) * Lp, mu, nullptr, 0);
         }));
-        return launch_reduce<TC>(st, partc, S, static_cast<int64_t>(n) * Lp, Lp, n, l, dst, Lp);
+        return reduce_step<TC>(ex, partc, S, static_cast<int64_t>(n) * Lp, Lp, n, l, dst, Lp);
     };
 
     // Alg. subspace_iter: q rounds of orth(Y); Z = orth(A^T Y); Y = A Z.
     for (int it = 0; it < P.q; ++it) {
-        RSVD_TRY(orthonormalize<TC>(st, Y, Lp, m, l, Lp, P.sp.gram_m, partd, gram, rinv, nullptr, status, num_cu,
+        RSVD_TRY(orthonormalize<TC>(ex, tile, Y, Lp, m, l, Lp, P.sp.gram_m, partd, gram, rinv, nullptr, status,
                                     true));
         RSVD_TRY(aty(Z, early));
-        RSVD_TRY(orthonormalize<TC>(st, Z, Lp, n, l, Lp, P.sp.gram_n, partd, gram, rinv, nullptr, status, num_cu,
+        RSVD_TRY(orthonormalize<TC>(ex, tile, Z, Lp, n, l, Lp, P.sp.gram_n, partd, gram, rinv, nullptr, status,
                                     true));
         RSVD_TRY(ax(Z, it == P.q - 1 ? late : early));
     }
     // Alg. rqb steps 9-10: Q = qr(Y); B^T = A^T Q.
-    RSVD_TRY(orthonormalize<TC>(st, Y, Lp, m, l, Lp, P.sp.gram_m, partd, gram, rinv, nullptr, status, num_cu));
+    RSVD_TRY(orthonormalize<TC>(ex, tile, Y, Lp, m, l, Lp, P.sp.gram_m, partd, gram, rinv, nullptr, status));
     RSVD_TRY(aty(Z, late));
     // svd(B): B^T = Q_b R_b (Q_b overwrites Z), R_b = W S J^T by Jacobi.
-    RSVD_TRY(orthonormalize<TC>(st, Z, Lp, n, l, Lp, P.sp.gram_n, partd, gram, rinv, racc, status, num_cu));
+    RSVD_TRY(orthonormalize<TC>(ex, tile, Z, Lp, n, l, Lp, P.sp.gram_n, partd, gram, rinv, racc, status));
     racc += 3 * static_cast<size_t>(l) * l;       // R_b = R3 R2 R1
     {
-        static bool ready = false;
-        if (!ready) { RSVD_TRY(allow_lds(jacobi_kernel<TC>, jacobi_lds_bytes(CHOL_MAX_L))); ready = true; }
         JacobiArgs ja;
         ja.R = racc; ja.ldr = l; ja.l = l; ja.k = k;
         double* wks = at<double>(work, P.wks);
         ja.sigma = sigma; ja.xv = xv; ja.ldx = Lp; ja.xcols = P.kp; ja.wks = wks;
         ja.status = status; ja.max_sweeps = 60; ja.tol = jacobi_tol(ja.l);
-        hipLaunchKernelGGL(jacobi_kernel<TC>, dim3(1), dim3(JAC_THREADS), jacobi_lds_bytes(l), st, ja);
-        RSVD_TRY(hipGetLastError());
+        RSVD_TRY(ex.template run<JacobiBody<TC>>(ja));
         // J_k = R_b^T (W_k / sigma)
-        RSVD_TRY((launch_gemm<double, double, double, MODE_TN>(st, racc, l, l, l, wks, k, k, jk, k, 1, 0,
+        RSVD_TRY((gemm_plain<double, double, double, MODE_TN>(ex, tile, racc, l, l, l, wks, k, k, jk, k, 1, 0,
                                                               nullptr, nullptr, 0)));
     }
     // V = Q_b W_k, sign rule, then U = Q (J_k D) with D = signs (x S for PCA).
     TC* V = o.V ? static_cast<TC*>(o.V) : at<TC>(work, P.vtmp);
     const int64_t ldv = o.V ? o.ldv : P.kp;
-    RSVD_TRY((launch_gemm<TC, TC, TC, MODE_NN>(st, Z, Lp, n, l, xv, P.kp, k, V, ldv, 1, 0, nullptr, nullptr, 0)));
-    hipLaunchKernelGGL(sign_lift_kernel<TC>, dim3(k), dim3(256), 0, st, V, ldv, n, l, k, jk, sigma, o.scale_u,
-                       xu, Lp, P.kp);
-    RSVD_TRY(hipGetLastError());
+    RSVD_TRY((gemm_plain<TC, TC, TC, MODE_NN>(ex, tile, Z, Lp, n, l, xv, P.kp, k, V, ldv, 1, 0, nullptr, nullptr,
+                                              0)));
+    RSVD_TRY(ex.template run<SignLiftBody<TC>>(typename SignLiftBody<TC>::Args{
+        V, ldv, n, l, k, jk, sigma, o.scale_u, xu, Lp, P.kp}));
     if (o.U)
-        RSVD_TRY((launch_gemm<TC, TC, TC, MODE_NN>(st, Y, Lp, m, l, xu, P.kp, k, static_cast<TC*>(o.U), o.ldu,
+        RSVD_TRY((gemm_plain<TC, TC, TC, MODE_NN>(ex, tile, Y, Lp, m, l, xu, P.kp, k, static_cast<TC*>(o.U), o.ldu,
                                                   1, 0, nullptr, nullptr, 0)));
-    {
-        const int64_t cnt = std::max<int64_t>(k, o.center_out ? n : 0);
-        hipLaunchKernelGGL(finalize_kernel<TC>, dim3(static_cast<unsigned>(cdiv(cnt, 256))), dim3(256), 0, st,
-                           sigma, k, o.S, o.eigvals, o.sdev, static_cast<double>(m - 1), mu, n,
-                           static_cast<TC*>(o.center_out), status, o.info, l, P.q, P.p);
-        RSVD_TRY(hipGetLastError());
-    }
+    RSVD_TRY(ex.template run<FinalizeBody<TC>>(typename FinalizeBody<TC>::Args{
+        sigma, k, o.S, o.eigvals, o.sdev, static_cast<double>(m - 1), mu, n, static_cast<TC*>(o.center_out),
+        status, o.info, l, P.q, P.p}));
+    if (o.stamps) RSVD_TRY(ex.template run<StampBody>(StampBody::Args{o.stamps + 1}));
     return hipSuccess;
 }
 
@@ -332,7 +316,9 @@ inline int hip_status(rsvd_handle_t h, hipError_t e) {
 template <typename TA, typename TC>
 int run_typed(rsvd_handle_t h, const Plan& P, const void* A, int64_t lda, const rsvd_params* prm,
               const SolveOut& o, void* work) {
-    return hip_status(h, solve<TA, TC>(h, P, static_cast<const TA*>(A), lda, prm, o, work));
+    SingleExec ex{h->stream};
+    return hip_status(h, solve_steps<TA, TC>(ex, h, P, static_cast<const TA*>(A), lda, prm, prm->stream_id, o,
+                                             work));
 }
 
 int dispatch(rsvd_handle_t h, int32_t dtype, const Plan& P, const void* A, int64_t lda,
@@ -506,13 +492,13 @@ int rsvd_test_matrix(rsvd_handle_t handle, int32_t dtype, int64_t n, int32_t l, 
     if (sdist < RSVD_NORMAL || sdist > RSVD_RADEMACHER) return RSVD_ERR_INVALID;
     const int groups = (l + 3) / 4;
     const int64_t total = n * groups;
+    (void)total;
+    SingleExec ex{handle->stream};
     if (dtype == RSVD_F64)
-        hipLaunchKernelGGL(omega_kernel<double>, dim3(static_cast<unsigned>(cdiv(total, 256))), dim3(256), 0,
-                           handle->stream, n, l, l, seed, stream_id, sdist, static_cast<double*>(out), ldo);
-    else
-        hipLaunchKernelGGL(omega_kernel<float>, dim3(static_cast<unsigned>(cdiv(total, 256))), dim3(256), 0,
-                           handle->stream, n, l, l, seed, stream_id, sdist, static_cast<float*>(out), ldo);
-    return hip_status(handle, hipGetLastError());
+        return hip_status(handle, ex.run<OmegaBody<double>>(OmegaBody<double>::Args{
+                                      n, l, l, seed, stream_id, sdist, static_cast<double*>(out), ldo}));
+    return hip_status(handle, ex.run<OmegaBody<float>>(OmegaBody<float>::Args{
+                                  n, l, l, seed, stream_id, sdist, static_cast<float*>(out), ldo}));
 }
 
 static Plan block_plan(int32_t dtype, int64_t m, int64_t n, int32_t c, int num_cu) {
@@ -548,9 +534,9 @@ int rsvd_block_workspace_size(rsvd_handle_t handle, int32_t dtype, int64_t m, in
 template <typename TA, typename TC>
 static hipError_t gemm_nn_typed(hipStream_t st, int arith, int64_t m, int64_t K, int c, const void* A, int64_t lda,
                                 const void* X, int64_t ldx, void* Y, int64_t ldy) {
-    return launch_gemm_arith<TA, TC, MODE_NN>(st, arith, static_cast<const TA*>(A), lda, m, K,
-                                              static_cast<const TC*>(X), ldx, c, static_cast<TC*>(Y), ldy, 1, 0,
-                                              nullptr, nullptr, 0);
+    SingleExec ex{st};
+    return gemm_step<TA, TC, MODE_NN>(ex, arith, 0, static_cast<const TA*>(A), lda, m, K, static_cast<const TC*>(X),
+                                      ldx, c, static_cast<TC*>(Y), ldy, 1, 0, nullptr, nullptr, 0);
 }
 
 extern "C" {
@@ -577,17 +563,17 @@ int rsvd_gemm_nn(rsvd_handle_t handle, int32_t dtype, int32_t arith, int64_t m, 
 template <typename TA, typename TC>
 static hipError_t gemm_tn_typed(rsvd_handle_t h, int arith, const Plan& P, int64_t m, int64_t n, int c, const void* A,
                                 int64_t lda, const void* Q, int64_t ldq, void* Z, int64_t ldz, void* work) {
-    hipStream_t st = h->stream;
+    SingleExec ex{h->stream};
     const int S = P.sp.tn;
     TC* part = at<TC>(work, P.part);
     if (S == 1)
-        return launch_gemm_arith<TA, TC, MODE_TN>(st, arith, static_cast<const TA*>(A), lda, n, m,
-                                                  static_cast<const TC*>(Q), ldq, c, static_cast<TC*>(Z), ldz, 1, 0,
-                                                  nullptr, nullptr, 0);
-    RSVD_TRY((launch_gemm_arith<TA, TC, MODE_TN>(st, arith, static_cast<const TA*>(A), lda, n, m,
-                                                static_cast<const TC*>(Q), ldq, c, part, P.Lp, S,
-                                                static_cast<int64_t>(n) * P.Lp, nullptr, nullptr, 0)));
-    return launch_reduce<TC>(st, part, S, static_cast<int64_t>(n) * P.Lp, P.Lp, n, c, static_cast<TC*>(Z), ldz);
+        return gemm_step<TA, TC, MODE_TN>(ex, arith, 0, static_cast<const TA*>(A), lda, n, m,
+                                          static_cast<const TC*>(Q), ldq, c, static_cast<TC*>(Z), ldz, 1, 0, nullptr,
+                                          nullptr, 0);
+    RSVD_TRY((gemm_step<TA, TC, MODE_TN>(ex, arith, 0, static_cast<const TA*>(A), lda, n, m,
+                                        static_cast<const TC*>(Q), ldq, c, part, P.Lp, S,
+                                        static_cast<int64_t>(n) * P.Lp, nullptr, nullptr, 0)));
+    return reduce_step<TC>(ex, part, S, static_cast<int64_t>(n) * P.Lp, P.Lp, n, c, static_cast<TC*>(Z), ldz);
 }
 
 extern "C" {
@@ -618,19 +604,19 @@ int rsvd_orthonormalize(rsvd_handle_t handle, int32_t dtype, int64_t m, int32_t 
     const Plan P = block_plan(dtype, m, m, c, handle->dev.num_cu);
     if (work_bytes < P.bytes) return RSVD_ERR_INVALID;
     hipStream_t st = handle->stream;
+    SingleExec ex{st};
     uint32_t* status = at<uint32_t>(work, P.status);
-    hipLaunchKernelGGL(clear_u32_kernel, dim3(1), dim3(64), 0, st, status, 1);
-    hipError_t e = hipGetLastError();
+    hipError_t e = ex.run<ClearBody>(ClearBody::Args{status, 1});
     const int S = gram_split(m, handle->dev.num_cu);
     if (e == hipSuccess) {
         if (dtype == RSVD_F64)
-            e = orthonormalize<double>(st, static_cast<double*>(Y), ldy, m, c, P.Lp, S, at<double>(work, P.part),
+            e = orthonormalize<double>(ex, 0, static_cast<double*>(Y), ldy, m, c, P.Lp, S, at<double>(work, P.part),
                                        at<double>(work, P.gram), at<double>(work, P.rinv), at<double>(work, P.racc),
-                                       status, handle->dev.num_cu);
+                                       status);
         else
-            e = orthonormalize<float>(st, static_cast<float*>(Y), ldy, m, c, P.Lp, S, at<double>(work, P.part),
+            e = orthonormalize<float>(ex, 0, static_cast<float*>(Y), ldy, m, c, P.Lp, S, at<double>(work, P.part),
                                       at<double>(work, P.gram), at<float>(work, P.rinv), at<double>(work, P.racc),
-                                      status, handle->dev.num_cu);
+                                      status);
     }
     if (e == hipSuccess)
         e = hipMemcpyAsync(R, at<double>(work, P.racc) + 3 * static_cast<size_t>(c) * c,
@@ -645,27 +631,212 @@ int rsvd_small_svd(rsvd_handle_t handle, int32_t c, const double* R, double* s, 
     const Plan P = block_plan(RSVD_F64, c, c, c, handle->dev.num_cu);
     if (work_bytes < P.bytes) return RSVD_ERR_INVALID;
     hipStream_t st = handle->stream;
+    SingleExec ex{st};
     uint32_t* status = at<uint32_t>(work, P.status);
-    hipLaunchKernelGGL(clear_u32_kernel, dim3(1), dim3(64), 0, st, status, 1);
-    hipError_t e = hipGetLastError();
+    hipError_t e = ex.run<ClearBody>(ClearBody::Args{status, 1});
     if (e != hipSuccess) return hip_status(handle, e);
-    static bool ready = false;
-    if (!ready) {
-        e = allow_lds(jacobi_kernel<double>, jacobi_lds_bytes(CHOL_MAX_L));
-        if (e != hipSuccess) return hip_status(handle, e);
-        ready = true;
-    }
     JacobiArgs ja;
     ja.R = R; ja.ldr = c; ja.l = c; ja.k = c;
     double* wks = at<double>(work, P.gram);
     ja.sigma = s; ja.xv = W; ja.ldx = c; ja.xcols = c; ja.wks = wks;
     ja.status = status; ja.max_sweeps = 60; ja.tol = jacobi_tol(ja.l);
-    hipLaunchKernelGGL(jacobi_kernel<double>, dim3(1), dim3(JAC_THREADS), jacobi_lds_bytes(c), st, ja);
-    e = hipGetLastError();
+    e = ex.run<JacobiBody<double>>(ja);
     if (e == hipSuccess)
-        e = launch_gemm<double, double, double, MODE_TN>(st, R, c, c, c, wks, c, c, J, c, 1, 0, nullptr, nullptr, 0);
+        e = gemm_plain<double, double, double, MODE_TN>(ex, 0, R, c, c, c, wks, c, c, J, c, 1, 0, nullptr, nullptr, 0);
     if (e == hipSuccess && flags) e = hipMemcpyAsync(flags, status, sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
     return hip_status(handle, e);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- batches
+// A ragged batch runs every step of the solve as one grouped launch over all
+// of its matrices (exec.hpp).  Matrices are grouped by the output tile width
+// their sketch width needs (32, 64, 128 columns), each group runs its solves
+// as one sequence of grouped launches, largest group tile first, and inside a
+// group the matrices are ordered by descending work (m n l) so that the
+// largest tiles are dispatched first.
+
+namespace rsvd {
+
+struct BatchGroup {
+    int tile = 0;
+    std::vector<int> members;
+    BatchRecorder rec;
+    size_t table_off = 0;
+};
+
+}  // namespace rsvd
+
+struct rsvd_batch_s {
+    rsvd_handle_t h = nullptr;
+    int dtype = 0;
+    int flags = 0;
+    rsvd_params prm{};
+    std::vector<rsvd_batch_desc> desc;
+    std::vector<rsvd::Plan> plans;
+    std::vector<size_t> offs;
+    std::vector<rsvd::BatchGroup> groups;
+    size_t stamps_off = 0, bytes = 0;
+    void* work = nullptr;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace rsvd {
+
+template <typename TA, typename TC>
+hipError_t record_group(rsvd_batch_s* B, BatchGroup& g, void* base) {
+    g.rec.clear();
+    const bool stamps = (B->flags & RSVD_BATCH_STAMPS) != 0;
+    for (int i : g.members) {
+        const rsvd_batch_desc& d = B->desc[i];
+        SolveOut o{};
+        o.U = d.U; o.ldu = d.ldu; o.V = d.V; o.ldv = d.ldv; o.S = d.S; o.info = d.info;
+        o.stamps = stamps ? at<uint64_t>(base, B->stamps_off) + 2 * static_cast<size_t>(i) : nullptr;
+        g.rec.begin_problem();
+        RSVD_TRY((solve_steps<TA, TC>(g.rec, nullptr, B->plans[i], static_cast<const TA*>(d.A), d.lda, &B->prm,
+                                      d.stream_id, o, at<unsigned char>(base, B->offs[i]))));
+        if (!g.rec.complete()) return hipErrorInvalidValue;
+    }
+    return hipSuccess;
+}
+
+inline hipError_t record_all(rsvd_batch_s* B, void* base) {
+    for (BatchGroup& g : B->groups) {
+        hipError_t e = hipErrorInvalidValue;
+        switch (B->dtype) {
+            case RSVD_F64: e = record_group<double, double>(B, g, base); break;
+            case RSVD_F32: e = record_group<float, float>(B, g, base); break;
+            case RSVD_BF16: e = record_group<bf16_t, float>(B, g, base); break;
+        }
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+inline hipError_t launch_all(const rsvd_batch_s* B, hipStream_t st) {
+    for (const BatchGroup& g : B->groups)
+        RSVD_TRY(g.rec.launch(static_cast<unsigned char*>(B->work) + g.table_off, st));
+    return hipSuccess;
+}
+
+inline void drop_graph(rsvd_batch_s* B) {
+    if (B->exec) (void)hipGraphExecDestroy(B->exec);
+    if (B->graph) (void)hipGraphDestroy(B->graph);
+    B->exec = nullptr;
+    B->graph = nullptr;
+}
+
+}  // namespace rsvd
+
+extern "C" {
+
+int rsvd_batch_create(rsvd_handle_t handle, int32_t dtype, int32_t count, const rsvd_batch_desc* descs,
+                      const rsvd_params* params, int32_t flags, rsvd_batch_t* batch, size_t* work_bytes) {
+    if (!handle || count < 1 || !descs || !params || !batch || !work_bytes) return RSVD_ERR_INVALID;
+    if (flags & ~(RSVD_BATCH_GRAPH | RSVD_BATCH_STAMPS)) return RSVD_ERR_INVALID;
+    const bool with_u = descs[0].U != nullptr;
+    for (int32_t i = 0; i < count; ++i) {
+        const rsvd_batch_desc& d = descs[i];
+        const int v = validate(dtype, d.m, d.n, d.k, params);
+        if (v != RSVD_OK) return v;
+        if (!d.A || d.lda < d.n || !d.S) return RSVD_ERR_INVALID;
+        if ((d.U != nullptr) != with_u || (d.U && d.ldu < d.k) || (d.V && d.ldv < d.k)) return RSVD_ERR_INVALID;
+    }
+    rsvd_batch_s* B = new rsvd_batch_s();
+    B->h = handle; B->dtype = dtype; B->flags = flags; B->prm = *params;
+    B->desc.assign(descs, descs + count);
+    B->plans.resize(count);
+    for (int32_t i = 0; i < count; ++i)
+        B->plans[i] = make_plan(dtype, descs[i].m, descs[i].n, descs[i].k, params, handle->dev.num_cu, true);
+    for (int tile : {128, 64, 32}) {
+        BatchGroup g;
+        g.tile = tile;
+        for (int32_t i = 0; i < count; ++i)
+            if (B->plans[i].Lp == tile) { B->plans[i].tile = tile; g.members.push_back(i); }
+        if (g.members.empty()) continue;
+        std::stable_sort(g.members.begin(), g.members.end(), [&](int a, int b) {
+            const Plan &pa = B->plans[a], &pb = B->plans[b];
+            return static_cast<double>(pa.m) * pa.n * pa.l > static_cast<double>(pb.m) * pb.n * pb.l;
+        });
+        B->groups.push_back(std::move(g));
+    }
+    // Size the step tables with a dry recording (their size does not depend
+    // on the addresses recorded in them).
+    void* fake = reinterpret_cast<void*>(static_cast<uintptr_t>(1) << 44);
+    B->offs.assign(count, 0);
+    if (record_all(B, fake) != hipSuccess) { delete B; return RSVD_ERR_UNSUPPORTED; }
+    Layout L;
+    for (BatchGroup& g : B->groups) g.table_off = L.take(g.rec.packed_bytes());
+    B->stamps_off = L.take(2 * sizeof(uint64_t) * static_cast<size_t>(count));
+    for (int32_t i = 0; i < count; ++i) B->offs[i] = L.take(B->plans[i].bytes);
+    B->bytes = L.off;
+    *batch = B;
+    *work_bytes = B->bytes;
+    return RSVD_OK;
+}
+
+int rsvd_batch_bind(rsvd_batch_t batch, void* work, size_t work_bytes) {
+    if (!batch || !work || work_bytes < batch->bytes) return RSVD_ERR_INVALID;
+    if (reinterpret_cast<uintptr_t>(work) % kAlign != 0) return RSVD_ERR_INVALID;
+    rsvd_handle_t h = batch->h;
+    drop_graph(batch);
+    batch->work = nullptr;
+    hipError_t e = record_all(batch, work);
+    if (e != hipSuccess) return RSVD_ERR_UNSUPPORTED;
+    for (BatchGroup& g : batch->groups) {
+        e = g.rec.upload(static_cast<unsigned char*>(work) + g.table_off, h->stream);
+        if (e == hipSuccess) e = g.rec.prepare();
+        if (e != hipSuccess) return hip_status(h, e);
+    }
+    batch->work = work;
+    if (batch->flags & RSVD_BATCH_GRAPH) {
+        if (!batch->cap) {
+            e = hipStreamCreateWithFlags(&batch->cap, hipStreamNonBlocking);
+            if (e != hipSuccess) { batch->work = nullptr; return hip_status(h, e); }
+        }
+        e = hipStreamBeginCapture(batch->cap, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            const hipError_t le = launch_all(batch, batch->cap);
+            e = hipStreamEndCapture(batch->cap, &batch->graph);
+            if (le != hipSuccess) e = le;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&batch->exec, batch->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) { drop_graph(batch); batch->work = nullptr; return hip_status(h, e); }
+    }
+    return RSVD_OK;
+}
+
+int rsvd_batch_run(rsvd_batch_t batch) {
+    if (!batch || !batch->work) return RSVD_ERR_INVALID;
+    rsvd_handle_t h = batch->h;
+    if (batch->exec) return hip_status(h, hipGraphLaunch(batch->exec, h->stream));
+    return hip_status(h, launch_all(batch, h->stream));
+}
+
+int rsvd_batch_stamps(rsvd_batch_t batch, uint64_t* host, double* ticks_per_second) {
+    if (!batch || !batch->work || !host || !(batch->flags & RSVD_BATCH_STAMPS)) return RSVD_ERR_INVALID;
+    rsvd_handle_t h = batch->h;
+    const size_t bytes = 2 * sizeof(uint64_t) * batch->desc.size();
+    hipError_t e = hipMemcpyAsync(host, static_cast<unsigned char*>(batch->work) + batch->stamps_off, bytes,
+                                  hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e == hipSuccess && ticks_per_second) {
+        int khz = 0;
+        e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, h->dev.device);
+        *ticks_per_second = 1e3 * khz;
+    }
+    return hip_status(h, e);
+}
+
+int rsvd_batch_destroy(rsvd_batch_t batch) {
+    if (!batch) return RSVD_OK;
+    drop_graph(batch);
+    if (batch->cap) (void)hipStreamDestroy(batch->cap);
+    delete batch;
+    return RSVD_OK;
 }
 
 }  // extern "C"

@@ -43,6 +43,7 @@ struct GemmArgs {
     int64_t rows;        // output rows (NN: m, TN: n)
     int64_t K;           // reduction length (NN: n, TN: m)
     int64_t kchunk;      // reduction elements per split (multiple of BK)
+    int32_t splits;      // number of splits S (grid extent along the reduction)
     const TX* X;         // K x (col tiles * NC) operand
     int64_t ldx;
     int32_t ncols;       // valid output columns (all column tiles together)
@@ -117,9 +118,9 @@ struct GemmTile {
     static constexpr size_t LDS_BYTES = 2ull * (A_LDS + NC * SK) * sizeof(TC);
 };
 
+// Tile (bx, by, bz) = (row tile, split, column tile) of the product g.
 template <typename TA, typename TX, typename TC, int MODE, int WR, int WC, int WGM, int WGN, int BK>
-__global__ __launch_bounds__(64 * WGM * WGN)
-void gemm_tile_kernel(GemmArgs<TA, TX, TC> g) {
+__device__ __forceinline__ void gemm_tile_body(const GemmArgs<TA, TX, TC>& g, int bx, int by, int bz) {
     typedef GemmTile<TA, TX, TC, MODE, WR, WC, WGM, WGN, BK> T;
     typedef typename Mfma<TC>::acc_t acc_t;
     constexpr int KV = T::KV, SK = T::SK, KVECS = T::KVECS;
@@ -134,9 +135,9 @@ void gemm_tile_kernel(GemmArgs<TA, TX, TC> g) {
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int wm = wave % WGM, wn = wave / WGM;
-    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * T::BM;
-    const int split = blockIdx.y;
-    const int col0 = blockIdx.z * T::NC;
+    const int64_t r0 = static_cast<int64_t>(bx) * T::BM;
+    const int split = by;
+    const int col0 = bz * T::NC;
     const int64_t kbeg = static_cast<int64_t>(split) * g.kchunk;
     const int64_t kend = min(g.K, kbeg + g.kchunk);
 
@@ -300,6 +301,12 @@ void gemm_tile_kernel(GemmArgs<TA, TX, TC> g) {
             }
         }
     }
+}
+
+template <typename TA, typename TX, typename TC, int MODE, int WR, int WC, int WGM, int WGN, int BK>
+__global__ __launch_bounds__(64 * WGM * WGN)
+void gemm_tile_kernel(GemmArgs<TA, TX, TC> g) {
+    gemm_tile_body<TA, TX, TC, MODE, WR, WC, WGM, WGN, BK>(g, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 }  // namespace rsvd

@@ -78,8 +78,7 @@ __device__ __forceinline__ void load8(const TA* p, bool vec, int valid, float (&
 }
 
 template <typename TA, int MODE, bool SPLIT, int WR, int WC, int WGM, int WGN, int BK>
-__global__ __launch_bounds__(64 * WGM * WGN)
-void gemm_bf16_kernel(GemmArgs<TA, float, float> g) {
+__device__ __forceinline__ void gemm_bf16_body(const GemmArgs<TA, float, float>& g, int bx, int by, int bz) {
     typedef Bf16Tile<TA, MODE, SPLIT, WR, WC, WGM, WGN, BK> T;
     constexpr int SK = T::SK, OCT = T::OCT;
     if (g.skip_flag && ((*g.skip_flag & g.skip_mask) == 0u)) return;
@@ -93,9 +92,9 @@ void gemm_bf16_kernel(GemmArgs<TA, float, float> g) {
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int wm = wave % WGM, wn = wave / WGM;
-    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * T::BM;
-    const int split = blockIdx.y;
-    const int col0 = blockIdx.z * T::NC;
+    const int64_t r0 = static_cast<int64_t>(bx) * T::BM;
+    const int split = by;
+    const int col0 = bz * T::NC;
     const int64_t kbeg = static_cast<int64_t>(split) * g.kchunk;
     const int64_t kend = min(g.K, kbeg + g.kchunk);
 
@@ -261,6 +260,12 @@ void gemm_bf16_kernel(GemmArgs<TA, float, float> g) {
             }
         }
     }
+}
+
+template <typename TA, int MODE, bool SPLIT, int WR, int WC, int WGM, int WGN, int BK>
+__global__ __launch_bounds__(64 * WGM * WGN)
+void gemm_bf16_kernel(GemmArgs<TA, float, float> g) {
+    gemm_bf16_body<TA, MODE, SPLIT, WR, WC, WGM, WGN, BK>(g, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 }  // namespace rsvd

@@ -21,70 +21,110 @@ namespace rsvd {
 
 // Status words are cleared by a kernel rather than a memset node, so the whole
 // launch sequence stays safe to capture in a HIP graph.
-__global__ void clear_u32_kernel(uint32_t* p, int count) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < count) p[i] = 0u;
-}
+struct ClearBody {
+    struct Args { uint32_t* p; int count; };
+    static constexpr int THREADS = 64;
+    static int blocks(const Args& a) { return static_cast<int>(cdiv(a.count, THREADS)); }
+    static size_t lds(const Args&) { return 0; }
+    static __device__ void run(const Args& a, int b) {
+        const int i = b * THREADS + threadIdx.x;
+        if (i < a.count) a.p[i] = 0u;
+    }
+};
+
+// Device clock reading (constant-rate wall clock) into *t: marks when a
+// problem's first and last steps ran, for per-solve latency in batches.
+struct StampBody {
+    struct Args { uint64_t* t; };
+    static constexpr int THREADS = 64;
+    static int blocks(const Args& a) { return a.t ? 1 : 0; }
+    static size_t lds(const Args&) { return 0; }
+    static __device__ void run(const Args& a, int) {
+        if (threadIdx.x == 0) a.t[0] = wall_clock64();
+    }
+};
 
 // ---------------------------------------------------------------- reduction
 // out[r][c] = sum_s part[s][r][c] for r < rows, c < ncols (split order fixed).
 template <typename T>
-__global__ __launch_bounds__(256) void reduce_partials_kernel(
-        const T* __restrict__ part, int S, int64_t part_stride, int64_t ldp, int64_t rows,
-        int ncols, T* __restrict__ out, int64_t ldo, const uint32_t* skip_flag, uint32_t skip_mask) {
-    if (skip_flag && ((*skip_flag & skip_mask) == 0u)) return;
-    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int64_t r = idx / ncols;
-    const int c = static_cast<int>(idx - r * ncols);
-    if (r >= rows) return;
-    T s = part[r * ldp + c];
-    for (int k = 1; k < S; ++k) s += part[k * part_stride + r * ldp + c];
-    out[r * ldo + c] = s;
-}
+struct ReduceBody {
+    struct Args {
+        const T* part; int S; int64_t part_stride; int64_t ldp; int64_t rows; int ncols;
+        T* out; int64_t ldo; const uint32_t* skip_flag; uint32_t skip_mask;
+    };
+    static constexpr int THREADS = 256;
+    static int blocks(const Args& a) { return static_cast<int>(cdiv(a.rows * a.ncols, THREADS)); }
+    static size_t lds(const Args&) { return 0; }
+    static __device__ void run(const Args& a, int b) {
+        if (a.skip_flag && ((*a.skip_flag & a.skip_mask) == 0u)) return;
+        const int64_t idx = static_cast<int64_t>(b) * THREADS + threadIdx.x;
+        const int64_t r = idx / a.ncols;
+        const int c = static_cast<int>(idx - r * a.ncols);
+        if (r >= a.rows) return;
+        T s = a.part[r * a.ldp + c];
+        for (int k = 1; k < a.S; ++k) s += a.part[k * a.part_stride + r * a.ldp + c];
+        a.out[r * a.ldo + c] = s;
+    }
+};
 
 // ------------------------------------------------------------- column means
-// Partial column sums over a chunk of rows: part[s][j] = sum_{i in chunk s} A[i][j].
+// Partial column sums over S chunks of rows: part[s][j] = sum_{i in chunk s} A[i][j],
+// then mu[j] = sum_s part[s][j] / m in split order.
 template <typename TA>
-__global__ __launch_bounds__(256) void colsum_partial_kernel(
-        const TA* __restrict__ A, int64_t lda, int64_t m, int64_t n, int64_t rows_per_split,
-        double* __restrict__ part) {
-    const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int s = blockIdx.y;
-    if (j >= n) return;
-    const int64_t i0 = s * rows_per_split, i1 = min(m, i0 + rows_per_split);
-    double acc = 0.0;
-    for (int64_t i = i0; i < i1; ++i) acc += Conv<double>::to(A[i * lda + j]);
-    part[s * n + j] = acc;
-}
+struct ColsumBody {
+    struct Args { const TA* A; int64_t lda; int64_t m; int64_t n; int64_t rows_per_split; int S; double* part; };
+    static constexpr int THREADS = 256;
+    static int blocks(const Args& a) { return static_cast<int>(cdiv(a.n, THREADS)) * a.S; }
+    static size_t lds(const Args&) { return 0; }
+    static __device__ void run(const Args& a, int b) {
+        const int cb = static_cast<int>(cdiv(a.n, THREADS));
+        const int64_t j = static_cast<int64_t>(b % cb) * THREADS + threadIdx.x;
+        const int s = b / cb;
+        if (j >= a.n) return;
+        const int64_t i0 = s * a.rows_per_split, i1 = min(a.m, i0 + a.rows_per_split);
+        double acc = 0.0;
+        for (int64_t i = i0; i < i1; ++i) acc += Conv<double>::to(a.A[i * a.lda + j]);
+        a.part[s * a.n + j] = acc;
+    }
+};
 
-__global__ __launch_bounds__(256) void colmean_finish_kernel(
-        const double* __restrict__ part, int S, int64_t m, int64_t n, double* __restrict__ mu) {
-    const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (j >= n) return;
-    double acc = 0.0;
-    for (int s = 0; s < S; ++s) acc += part[s * n + j];
-    mu[j] = acc / static_cast<double>(m);
-}
+struct ColmeanBody {
+    struct Args { const double* part; int S; int64_t m; int64_t n; double* mu; };
+    static constexpr int THREADS = 256;
+    static int blocks(const Args& a) { return static_cast<int>(cdiv(a.n, THREADS)); }
+    static size_t lds(const Args&) { return 0; }
+    static __device__ void run(const Args& a, int b) {
+        const int64_t j = static_cast<int64_t>(b) * THREADS + threadIdx.x;
+        if (j >= a.n) return;
+        double acc = 0.0;
+        for (int s = 0; s < a.S; ++s) acc += a.part[s * a.n + j];
+        a.mu[j] = acc / static_cast<double>(a.m);
+    }
+};
 
 // ------------------------------------------------------------------ Omega
 // Omega[j][c] for j < n, c < ncols_out (entries c >= l written as zero).
 template <typename T>
-__global__ __launch_bounds__(256) void omega_kernel(int64_t n, int l, int ncols_out,
-                                                    uint64_t seed, uint32_t stream_id, int sdist,
-                                                    T* __restrict__ out, int64_t ldo) {
-    const int groups = (ncols_out + 3) / 4;
-    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int64_t j = idx / groups;
-    const int c = static_cast<int>(idx - j * groups);
-    if (j >= n) return;
-    T v[4];
-    omega_group<T>(static_cast<uint32_t>(j), static_cast<uint32_t>(c), seed, stream_id, sdist, v);
+struct OmegaBody {
+    struct Args { int64_t n; int l; int ncols_out; uint64_t seed; uint32_t stream_id; int sdist; T* out; int64_t ldo; };
+    static constexpr int THREADS = 256;
+    static int blocks(const Args& a) { return static_cast<int>(cdiv(a.n * ((a.ncols_out + 3) / 4), THREADS)); }
+    static size_t lds(const Args&) { return 0; }
+    static __device__ void run(const Args& a, int b) {
+        const int groups = (a.ncols_out + 3) / 4;
+        const int64_t idx = static_cast<int64_t>(b) * THREADS + threadIdx.x;
+        const int64_t j = idx / groups;
+        const int c = static_cast<int>(idx - j * groups);
+        if (j >= a.n) return;
+        T v[4];
+        omega_group<T>(static_cast<uint32_t>(j), static_cast<uint32_t>(c), a.seed, a.stream_id, a.sdist, v);
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        const int col = 4 * c + t;
-        if (col < ncols_out) out[j * ldo + col] = (col < l) ? v[t] : T(0);
+        for (int t = 0; t < 4; ++t) {
+            const int col = 4 * c + t;
+            if (col < a.ncols_out) a.out[j * a.ldo + col] = (col < a.l) ? v[t] : T(0);
+        }
     }
-}
+};
 
 __global__ __launch_bounds__(256) void philox_words_kernel(int64_t n, int groups, uint64_t seed,
                                                            uint32_t stream_id, uint32_t* out) {
@@ -146,7 +186,7 @@ static_assert((CHOL_MAX_L / CT_R) * CT_TX == CHOL_THREADS, "tiles must cover the
 inline size_t chol_lds_bytes(int) { return 0; }
 
 template <typename TC>
-__global__ __launch_bounds__(CHOL_THREADS) void chol_kernel(CholArgs a) {
+__device__ __forceinline__ void chol_body(const CholArgs& a) {
     const int l = a.l, tid = threadIdx.x;
     const int tx = tid % CT_TX, ty = tid / CT_TX;
     const int a0 = CT_R * ty, b0 = CT_C * tx;
@@ -334,6 +374,15 @@ __global__ __launch_bounds__(CHOL_THREADS) void chol_kernel(CholArgs a) {
     if (tid == 0) *a.status = s_flags;
 }
 
+template <typename TC>
+struct CholBody {
+    typedef CholArgs Args;
+    static constexpr int THREADS = CHOL_THREADS;
+    static int blocks(const Args&) { return 1; }
+    static size_t lds(const Args&) { return 0; }
+    static __device__ void run(const Args& a, int) { chol_body<TC>(a); }
+};
+
 // ------------------------------------------------------ one-sided Jacobi SVD
 // R (l x l upper triangular, f64, ld ldr) = W diag(sigma) J^T.  The columns of
 // W (column-major, column c at W + c*ldw) live in LDS; l/2 disjoint column pairs
@@ -389,7 +438,7 @@ __device__ __forceinline__ double group_sum(double v) {
 }
 
 template <typename TC>
-__global__ __launch_bounds__(JAC_THREADS) void jacobi_kernel(JacobiArgs a) {
+__device__ __forceinline__ void jacobi_body(const JacobiArgs& a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ int s_rotated;
     __shared__ int s_perm[CHOL_MAX_L];
@@ -497,70 +546,93 @@ __global__ __launch_bounds__(JAC_THREADS) void jacobi_kernel(JacobiArgs a) {
     }
 }
 
+template <typename TC>
+struct JacobiBody {
+    typedef JacobiArgs Args;
+    static constexpr int THREADS = JAC_THREADS;
+    static int blocks(const Args&) { return 1; }
+    static size_t lds(const Args& a) { return jacobi_lds_bytes(a.l); }
+    static __device__ void run(const Args& a, int) { jacobi_body<TC>(a); }
+};
+
 // ------------------------------------------------------------- sign rule
 // One workgroup per column i < k of V (n x k, ld ldv): find the entry of
 // largest magnitude (lowest row on ties); if negative flip the column; then
 // write the lift matrix xu[t][i] = jk[t][i] * sign * (scale ? sigma_i : 1).
 template <typename TC>
-__global__ __launch_bounds__(256) void sign_lift_kernel(TC* V, int64_t ldv, int64_t n, int l, int k,
-                                                        const double* jk, const double* sigma,
-                                                        int scale, TC* xu, int ldxu, int xcols) {
-    const int i = blockIdx.x;
-    const int tid = threadIdx.x;
-    __shared__ double s_val[256];
-    __shared__ int64_t s_idx[256];
-    double best = -1.0;
-    int64_t bidx = 0;
-    for (int64_t r = tid; r < n; r += blockDim.x) {
-        const double v = fabs(static_cast<double>(V[r * ldv + i]));
-        if (v > best) { best = v; bidx = r; }
-    }
-    s_val[tid] = best; s_idx[tid] = bidx;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if (tid < off) {
-            const double ov = s_val[tid + off];
-            const int64_t oi = s_idx[tid + off];
-            if (ov > s_val[tid] || (ov == s_val[tid] && oi < s_idx[tid])) { s_val[tid] = ov; s_idx[tid] = oi; }
+struct SignLiftBody {
+    struct Args {
+        TC* V; int64_t ldv; int64_t n; int l; int k; const double* jk; const double* sigma;
+        int scale; TC* xu; int ldxu; int xcols;
+    };
+    static constexpr int THREADS = 256;
+    static int blocks(const Args& a) { return a.k; }
+    static size_t lds(const Args&) { return 0; }
+    static __device__ void run(const Args& a, int i) {
+        const int tid = threadIdx.x;
+        __shared__ double s_val[THREADS];
+        __shared__ int64_t s_idx[THREADS];
+        __shared__ double s_sgn;
+        double best = -1.0;
+        int64_t bidx = 0;
+        for (int64_t r = tid; r < a.n; r += THREADS) {
+            const double v = fabs(static_cast<double>(a.V[r * a.ldv + i]));
+            if (v > best) { best = v; bidx = r; }
         }
+        s_val[tid] = best; s_idx[tid] = bidx;
         __syncthreads();
-    }
-    __shared__ double s_sgn;
-    if (tid == 0) s_sgn = (static_cast<double>(V[s_idx[0] * ldv + i]) < 0.0) ? -1.0 : 1.0;
-    __syncthreads();
-    const double sgn = s_sgn;
-    if (sgn < 0.0)
-        for (int64_t r = tid; r < n; r += blockDim.x) V[r * ldv + i] = -V[r * ldv + i];
-    const double f = sgn * (scale ? sigma[i] : 1.0);
-    for (int t = tid; t < ldxu; t += blockDim.x)
-        xu[t * xcols + i] = static_cast<TC>(t < l ? jk[t * k + i] * f : 0.0);
-    if (i == 0)     // zero the padding columns of the lift matrix
-        for (int idx = tid; idx < ldxu * (xcols - k); idx += blockDim.x) {
-            const int t = idx / (xcols - k), c = k + idx % (xcols - k);
-            xu[t * xcols + c] = TC(0);
+        for (int off = THREADS / 2; off > 0; off >>= 1) {
+            if (tid < off) {
+                const double ov = s_val[tid + off];
+                const int64_t oi = s_idx[tid + off];
+                if (ov > s_val[tid] || (ov == s_val[tid] && oi < s_idx[tid])) { s_val[tid] = ov; s_idx[tid] = oi; }
+            }
+            __syncthreads();
         }
-}
+        if (tid == 0) s_sgn = (static_cast<double>(a.V[s_idx[0] * a.ldv + i]) < 0.0) ? -1.0 : 1.0;
+        __syncthreads();
+        const double sgn = s_sgn;
+        if (sgn < 0.0)
+            for (int64_t r = tid; r < a.n; r += THREADS) a.V[r * a.ldv + i] = -a.V[r * a.ldv + i];
+        const double f = sgn * (a.scale ? a.sigma[i] : 1.0);
+        for (int t = tid; t < a.ldxu; t += THREADS)
+            a.xu[t * a.xcols + i] = static_cast<TC>(t < a.l ? a.jk[t * a.k + i] * f : 0.0);
+        if (i == 0)     // zero the padding columns of the lift matrix
+            for (int idx = tid; idx < a.ldxu * (a.xcols - a.k); idx += THREADS) {
+                const int t = idx / (a.xcols - a.k), c = a.k + idx % (a.xcols - a.k);
+                a.xu[t * a.xcols + c] = TC(0);
+            }
+    }
+};
 
 // ------------------------------------------------------------- finalize
 template <typename TC>
-__global__ __launch_bounds__(256) void finalize_kernel(const double* sigma, int k, double* S,
-                                                       double* eigvals, double* sdev, double denom,
-                                                       const double* mu, int64_t n, TC* center_out,
-                                                       const uint32_t* status, rsvd_info* info,
-                                                       int l, int q, int p) {
-    const int64_t tid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (tid < k) {
-        const double s = sigma[tid];
-        if (S) S[tid] = s;
-        if (eigvals) eigvals[tid] = s * s / denom;
-        if (sdev) sdev[tid] = sqrt(s * s / denom);
+struct FinalizeBody {
+    struct Args {
+        const double* sigma; int k; double* S; double* eigvals; double* sdev; double denom;
+        const double* mu; int64_t n; TC* center_out; const uint32_t* status; rsvd_info* info;
+        int l; int q; int p;
+    };
+    static constexpr int THREADS = 256;
+    static int blocks(const Args& a) {
+        return static_cast<int>(cdiv(std::max<int64_t>(a.k, a.center_out ? a.n : 0), THREADS));
     }
-    if (center_out && tid < n) center_out[tid] = static_cast<TC>(mu ? mu[tid] : 0.0);
-    if (info && tid == 0) {
-        info->l = l; info->q = q; info->p = p;
-        info->flags = *status & 0xFF00FFFFu;   // RSVD_FLAG_* and the sweep count
-        info->est_err = 0.0;
+    static size_t lds(const Args&) { return 0; }
+    static __device__ void run(const Args& a, int b) {
+        const int64_t tid = static_cast<int64_t>(b) * THREADS + threadIdx.x;
+        if (tid < a.k) {
+            const double s = a.sigma[tid];
+            if (a.S) a.S[tid] = s;
+            if (a.eigvals) a.eigvals[tid] = s * s / a.denom;
+            if (a.sdev) a.sdev[tid] = sqrt(s * s / a.denom);
+        }
+        if (a.center_out && tid < a.n) a.center_out[tid] = static_cast<TC>(a.mu ? a.mu[tid] : 0.0);
+        if (a.info && tid == 0) {
+            a.info->l = a.l; a.info->q = a.q; a.info->p = a.p;
+            a.info->flags = *a.status & 0xFF00FFFFu;   // RSVD_FLAG_* and the sweep count
+            a.info->est_err = 0.0;
+        }
     }
-}
+};
 
 }  // namespace rsvd

@@ -40,6 +40,14 @@ class KernelStat(ctypes.Structure):
                 ("flops", c_double), ("bytes", c_double)]
 
 
+class BatchDesc(ctypes.Structure):
+    _fields_ = [("A", c_void_p), ("lda", c_int64), ("m", c_int64), ("n", c_int64), ("k", c_int32),
+                ("stream_id", c_uint32), ("U", c_void_p), ("ldu", c_int64), ("S", c_void_p),
+                ("V", c_void_p), ("ldv", c_int64), ("info", c_void_p)]
+
+
+BATCH_GRAPH, BATCH_STAMPS = 1, 2
+
 PROFILE_KINDS = 2
 PROFILE_NAMES = ("A_X", "AT_Q")
 
@@ -64,6 +72,12 @@ _PROTOS = {
                            c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_int64, c_void_p,
                            c_void_p, c_size_t, c_void_p]),
     "rsvd_sync_info": (c_int32, [c_void_p, c_void_p, c_void_p]),
+    "rsvd_batch_create": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_int32, c_void_p,
+                                    c_void_p]),
+    "rsvd_batch_bind": (c_int32, [c_void_p, c_void_p, c_size_t]),
+    "rsvd_batch_run": (c_int32, [c_void_p]),
+    "rsvd_batch_stamps": (c_int32, [c_void_p, c_void_p, c_void_p]),
+    "rsvd_batch_destroy": (c_int32, [c_void_p]),
     "rsvd_profile_enable": (c_int32, [c_void_p, c_int32]),
     "rsvd_profile_collect": (c_int32, [c_void_p, c_void_p]),
     "rsvd_philox_words": (c_int32, [c_void_p, c_int64, c_int32, c_uint64, c_uint32, c_void_p]),

@@ -164,6 +164,55 @@ def c4_batch(batch=4096, seed=4096, **shape_kw):
     return out
 
 
+def _haar_torch(rows, r, g, device):
+    """rows x r Haar-distributed orthonormal columns on a torch device.
+
+    Q = X R^-1 from the Cholesky factor R of X^T X (twice), X Gaussian: with
+    R's positive diagonal this is the Q of the QR of X, hence Haar.  Falls back
+    to Householder QR (sign-fixed) when X is too ill-conditioned for it.
+    """
+    import torch
+    X = torch.randn(rows, r, generator=g, device=device, dtype=torch.float64)
+    Q = X
+    for _ in range(2):
+        R, info = torch.linalg.cholesky_ex(Q.t() @ Q, upper=True)
+        if int(info) != 0:
+            q, rr = torch.linalg.qr(X, mode="reduced")
+            sgn = torch.sign(torch.diagonal(rr))
+            sgn[sgn == 0] = 1.0
+            return q * sgn[None, :]
+        Q = torch.linalg.solve_triangular(R, Q, upper=True, left=False)
+    return Q
+
+
+def c4_torch(device="cuda", batch=4096, seed=4096, out_dtype=None, **shape_kw):
+    """C4 batch on a torch device: A_b = U_b diag(i^-alpha_b) V_b^T with Haar
+    U_b, V_b over all min(m_b, n_b) values, rounded once to ``out_dtype``
+    (default float32) into one ragged buffer.
+
+    Returns dict(buffer, A (list of row-major views), m, n, k, alpha).
+    """
+    import torch
+    out_dtype = out_dtype or torch.float32
+    m, n, k, alpha = c4_shapes(batch, seed, **shape_kw)
+    sizes = (m.astype(np.int64) * n.astype(np.int64))
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    buf = torch.empty(int(offs[-1]), dtype=out_dtype, device=device)
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    views = []
+    for b in range(batch):
+        mb, nb = int(m[b]), int(n[b])
+        r = min(mb, nb)
+        sig = torch.arange(1, r + 1, device=device, dtype=torch.float64) ** (-float(alpha[b]))
+        U = _haar_torch(mb, r, g, device)
+        V = _haar_torch(nb, r, g, device)
+        view = buf[int(offs[b]):int(offs[b + 1])].view(mb, nb)
+        view.copy_((U * sig[None, :]) @ V.t())
+        views.append(view)
+    return dict(buffer=buf, A=views, m=m, n=n, k=k, alpha=alpha)
+
+
 def paper_lowrank_product(m, n, rank=200, seed=1135):
     """Rank-``rank`` product of two Gaussian matrices (float64)."""
     rng = np.random.default_rng(seed)

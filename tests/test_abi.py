@@ -34,6 +34,7 @@ def test_library_exports_every_declared_symbol(lib):
 def test_struct_layouts_match_header():
     assert ctypes.sizeof(L.Params) == 40
     assert ctypes.sizeof(L.Info) == 24
+    assert ctypes.sizeof(L.BatchDesc) == 88
 
 
 def test_default_params_are_the_papers(lib):
@@ -119,3 +120,78 @@ def test_run_rejects_null_and_small_workspace_before_launch(lib, handle):
 
 def test_precision_mode_unknown_is_rejected(lib, handle):
     assert _ws(lib, handle, L.RSVD_F32, 100, 50, 5, precision=5)[0] == -2
+
+
+def _descs(shapes, U=True):
+    arr = (L.BatchDesc * len(shapes))()
+    for b, (m, n, k) in enumerate(shapes):
+        d = arr[b]
+        d.A, d.lda, d.m, d.n, d.k, d.stream_id = 4096 * (b + 1), n, m, n, k, b
+        d.U, d.ldu = (1 << 20, k) if U else (None, 0)
+        d.S, d.V, d.ldv, d.info = 1 << 21, 1 << 22, k, None
+    return arr
+
+
+def _create(lib, handle, shapes, dtype=L.RSVD_F32, flags=0, descs=None, **kw):
+    prm = L.Params()
+    lib.rsvd_default_params(ctypes.byref(prm))
+    for key, v in kw.items():
+        setattr(prm, key, v)
+    descs = descs if descs is not None else _descs(shapes)
+    b = ctypes.c_void_p()
+    nbytes = ctypes.c_size_t(0)
+    st = lib.rsvd_batch_create(handle, dtype, len(shapes), descs, ctypes.byref(prm), flags, ctypes.byref(b),
+                               ctypes.byref(nbytes))
+    return st, b, nbytes.value
+
+
+def test_batch_create_is_host_only_and_sizes_the_workspace(lib, handle):
+    """Planning a batch records its steps on the host; nothing is launched."""
+    shapes = [(300, 200, 10), (1000, 100, 50), (64, 40, 1), (700, 1300, 118)]
+    st, b, nbytes = _create(lib, handle, shapes, flags=L.BATCH_GRAPH | L.BATCH_STAMPS)
+    assert st == 0 and b.value
+    singles = sum(_ws(lib, handle, L.RSVD_F32, m, n, k)[1] for m, n, k in shapes)
+    assert nbytes % 256 == 0
+    # per-matrix workspaces (no split partials) plus the launch tables
+    assert nbytes > 2 * 8 * len(shapes)
+    assert nbytes < 2 * singles + (1 << 24)
+    # run before bind, stamps before bind: invalid
+    assert lib.rsvd_batch_run(b) == -1
+    assert lib.rsvd_batch_stamps(b, ctypes.c_void_p(8), None) == -1
+    # bind with a too small or misaligned buffer fails before any copy
+    assert lib.rsvd_batch_bind(b, ctypes.c_void_p(256), nbytes - 1) == -1
+    assert lib.rsvd_batch_bind(b, ctypes.c_void_p(264), nbytes) == -1
+    assert lib.rsvd_batch_destroy(b) == 0
+
+
+@pytest.mark.parametrize("shapes,want", [
+    ([(100, 50, 50)], -1),                    # k >= min(m, n)
+    ([(100, 50, 5), (100, 50, 0)], -1),       # k < 1 in a later entry
+    ([(400, 300, 125)], -2),                  # l = 135 > RSVD_MAX_L
+    ([(100, 50, 5)] * 3, 0),
+])
+def test_batch_argument_rules(lib, handle, shapes, want):
+    st, b, _ = _create(lib, handle, shapes)
+    assert st == want
+    lib.rsvd_batch_destroy(b)
+
+
+def test_batch_rejects_mixed_outputs_flags_and_lda(lib, handle):
+    shapes = [(100, 50, 5), (120, 60, 6)]
+    d = _descs(shapes)
+    d[1].U = None
+    assert _create(lib, handle, shapes, descs=d)[0] == -1      # U given for some entries only
+    d = _descs(shapes)
+    d[0].lda = 49
+    assert _create(lib, handle, shapes, descs=d)[0] == -1
+    d = _descs(shapes)
+    d[1].S = None
+    assert _create(lib, handle, shapes, descs=d)[0] == -1
+    assert _create(lib, handle, shapes, flags=8)[0] == -1
+    assert _create(lib, handle, shapes, dtype=L.RSVD_F64, precision=1)[0] == -2
+    prm = L.Params()
+    lib.rsvd_default_params(ctypes.byref(prm))
+    b = ctypes.c_void_p()
+    nbytes = ctypes.c_size_t(0)
+    assert lib.rsvd_batch_create(handle, L.RSVD_F32, 0, _descs(shapes), ctypes.byref(prm), 0, ctypes.byref(b),
+                                 ctypes.byref(nbytes)) == -1
