@@ -9,14 +9,12 @@
 #include "gemm.hpp"
 #include "gemm_bf16.hpp"
 #include "linalg.hpp"
+#include "plan.hpp"
 
 namespace rsvd {
 
 template <typename T> constexpr int gemm_bk() { return sizeof(T) == 8 ? 16 : 32; }
 
-// Output tile width for c output columns: 32, 64 or 128 (column tiles of 128
-// beyond that).
-inline int tile_cols(int c) { return c <= 32 ? 32 : (c <= 64 ? 64 : 128); }
 
 // Storage-precision product (f32 / f64 matrix cores).  Workgroup b of a
 // problem covers row tile b % gx, split (b / gx) % S, column tile b / (gx S).
@@ -74,50 +72,70 @@ GemmArgs<TA, TX, TC> gemm_args(const TA* A, int64_t lda, int64_t rows, int64_t K
     return g;
 }
 
-// Storage-precision product; tile_class 0 picks the output tile width from
-// ncols, otherwise it is forced (one grouped batch step needs one shape).
+// Output tile shapes.  Tall tiles (128 output rows per workgroup) for
+// products with many output rows, NC = cls columns: 32, 64, 128 for every
+// compute type plus 48, 80, 96 for f32 compute (finer classes waste fewer
+// matrix-core columns when l is just above a power of two).  Square tiles
+// (BM = NC = 32, 64 or 128) for products with at most that many output rows:
+// Gram matrices and the l x l factors.  cls = 0 picks the tall class from
+// ncols; a grouped batch step passes one class for all of its problems.
 template <typename TA, typename TX, typename TC, int MODE, class Ex>
-hipError_t gemm_plain(Ex& ex, int tile_class, const TA* A, int64_t lda, int64_t rows, int64_t K, const TX* X,
-                      int64_t ldx, int ncols, TC* out, int64_t ldo, int S, int64_t part_stride,
+hipError_t gemm_plain(Ex& ex, int cls, bool square, const TA* A, int64_t lda, int64_t rows, int64_t K,
+                      const TX* X, int64_t ldx, int ncols, TC* out, int64_t ldo, int S, int64_t part_stride,
                       const double* mu, const uint32_t* skip_flag, uint32_t skip_mask) {
     const size_t vb = (16 / sizeof(TC)) * sizeof(TA);    // 16 / sizeof(TC) consecutive elements of A
     const auto g = gemm_args<TA, TX, TC>(A, lda, rows, K, X, ldx, ncols, out, ldo, S, part_stride, mu, skip_flag,
                                          skip_mask, gemm_bk<TC>(), vb);
-    const int tc = tile_class ? tile_class : tile_cols(ncols);
+    if (square) {
+        const int sc = tile_cols(static_cast<int>(std::max<int64_t>(rows, ncols)));
+        if (sc == 32) return ex.template run<GemmBody<TA, TX, TC, MODE, 1, 1, 2, 2>>(g);
+        if (sc == 64) return ex.template run<GemmBody<TA, TX, TC, MODE, 2, 2, 2, 2>>(g);
+        return ex.template run<GemmBody<TA, TX, TC, MODE, 4, 4, 2, 2>>(g);
+    }
+    const int tc = cls ? cls : tile_cols(ncols);
+    if constexpr (sizeof(TC) == 4) {
+        if (tc == 48) return ex.template run<GemmBody<TA, TX, TC, MODE, 2, 3, 4, 1>>(g);
+        if (tc == 80) return ex.template run<GemmBody<TA, TX, TC, MODE, 2, 5, 4, 1>>(g);
+        if (tc == 96) return ex.template run<GemmBody<TA, TX, TC, MODE, 4, 3, 2, 2>>(g);
+    }
     if (tc == 32) return ex.template run<GemmBody<TA, TX, TC, MODE, 2, 2, 4, 1>>(g);
     if (tc == 64) return ex.template run<GemmBody<TA, TX, TC, MODE, 4, 2, 2, 2>>(g);
     return ex.template run<GemmBody<TA, TX, TC, MODE, 4, 4, 2, 2>>(g);
 }
 
+template <typename TA, int MODE, bool SPLIT, class Ex>
+hipError_t gemm_bf16_cls(Ex& ex, int tc, const GemmArgs<TA, float, float>& g) {
+    if (tc == 32) return ex.template run<Bf16Body<TA, MODE, SPLIT, 2, 2, 4, 1>>(g);
+    if (tc == 48) return ex.template run<Bf16Body<TA, MODE, SPLIT, 2, 3, 4, 1>>(g);
+    if (tc == 64) return ex.template run<Bf16Body<TA, MODE, SPLIT, 4, 2, 2, 2>>(g);
+    if (tc == 80) return ex.template run<Bf16Body<TA, MODE, SPLIT, 2, 5, 4, 1>>(g);
+    if (tc == 96) return ex.template run<Bf16Body<TA, MODE, SPLIT, 4, 3, 2, 2>>(g);
+    return ex.template run<Bf16Body<TA, MODE, SPLIT, 4, 4, 2, 2>>(g);
+}
+
 template <typename TA, int MODE, class Ex>
-hipError_t gemm_bf16(Ex& ex, bool split, int tile_class, const TA* A, int64_t lda, int64_t rows, int64_t K,
+hipError_t gemm_bf16(Ex& ex, bool split, int cls, const TA* A, int64_t lda, int64_t rows, int64_t K,
                      const float* X, int64_t ldx, int ncols, float* out, int64_t ldo, int S, int64_t part_stride,
                      const double* mu, const uint32_t* skip_flag, uint32_t skip_mask) {
     const auto g = gemm_args<TA, float, float>(A, lda, rows, K, X, ldx, ncols, out, ldo, S, part_stride, mu,
                                                skip_flag, skip_mask, 64, 16);
-    const int tc = tile_class ? tile_class : tile_cols(ncols);
-    if (split) {
-        if (tc == 32) return ex.template run<Bf16Body<TA, MODE, true, 2, 2, 4, 1>>(g);
-        if (tc == 64) return ex.template run<Bf16Body<TA, MODE, true, 4, 2, 2, 2>>(g);
-        return ex.template run<Bf16Body<TA, MODE, true, 4, 4, 2, 2>>(g);
-    }
-    if (tc == 32) return ex.template run<Bf16Body<TA, MODE, false, 2, 2, 4, 1>>(g);
-    if (tc == 64) return ex.template run<Bf16Body<TA, MODE, false, 4, 2, 2, 2>>(g);
-    return ex.template run<Bf16Body<TA, MODE, false, 4, 4, 2, 2>>(g);
+    const int tc = cls ? cls : tile_cols(ncols);
+    if (split) return gemm_bf16_cls<TA, MODE, true>(ex, tc, g);
+    return gemm_bf16_cls<TA, MODE, false>(ex, tc, g);
 }
 
 // One product with A in the requested arithmetic: 0 = storage precision
 // (f32 / f64 matrix cores), 1 = bf16, 2 = split bf16 (near-f32-accurate).
 template <typename TA, typename TC, int MODE, class Ex>
-hipError_t gemm_step(Ex& ex, int arith, int tile_class, const TA* A, int64_t lda, int64_t rows, int64_t K,
+hipError_t gemm_step(Ex& ex, int arith, int cls, const TA* A, int64_t lda, int64_t rows, int64_t K,
                      const TC* X, int64_t ldx, int ncols, TC* out, int64_t ldo, int S, int64_t part_stride,
                      const double* mu, const uint32_t* skip_flag, uint32_t skip_mask) {
     if constexpr (std::is_same<TC, float>::value) {
         if (arith != 0)
-            return gemm_bf16<TA, MODE>(ex, arith == 2, tile_class, A, lda, rows, K, X, ldx, ncols, out, ldo, S,
+            return gemm_bf16<TA, MODE>(ex, arith == 2, cls, A, lda, rows, K, X, ldx, ncols, out, ldo, S,
                                        part_stride, mu, skip_flag, skip_mask);
     }
-    return gemm_plain<TA, TC, TC, MODE>(ex, tile_class, A, lda, rows, K, X, ldx, ncols, out, ldo, S, part_stride,
+    return gemm_plain<TA, TC, TC, MODE>(ex, cls, false, A, lda, rows, K, X, ldx, ncols, out, ldo, S, part_stride,
                                         mu, skip_flag, skip_mask);
 }
 

@@ -126,17 +126,6 @@ struct OmegaBody {
     }
 };
 
-__global__ __launch_bounds__(256) void philox_words_kernel(int64_t n, int groups, uint64_t seed,
-                                                           uint32_t stream_id, uint32_t* out) {
-    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int64_t j = idx / groups;
-    const int c = static_cast<int>(idx - j * groups);
-    if (j >= n) return;
-    const Philox4 w = philox4x32_10(static_cast<uint32_t>(j), static_cast<uint32_t>(c), stream_id, 0u,
-                                    static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32));
-#pragma unroll
-    for (int t = 0; t < 4; ++t) out[idx * 4 + t] = w.x[t];
-}
 
 // ------------------------------------------------------- Cholesky + inverse
 // One workgroup of 512 threads.  G = sum of the S partial Gram blocks (ldp x

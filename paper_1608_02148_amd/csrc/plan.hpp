@@ -1,0 +1,190 @@
+// Workspace plans, argument rules and the typed solve entry points shared by
+// the translation units of the library.
+#pragma once
+
+#include <algorithm>
+#include <cstring>
+
+#include "common.hpp"
+#include "exec.hpp"
+
+namespace rsvd {
+
+// Output tile width for c output columns: 32, 64 or 128 (column tiles of 128
+// beyond that); also the padded column count of the skinny work matrices.
+inline int tile_cols(int c) { return c <= 32 ? 32 : (c <= 64 ? 64 : 128); }
+
+// Column class of the tall product tiles for sketch width c: 32, 64, 128, and
+// with fine = true (f32 compute) also 48, 80, 96.
+inline int tile_class(int c, bool fine) {
+    if (!fine) return tile_cols(c);
+    return c <= 32 ? 32 : c <= 48 ? 48 : c <= 64 ? 64 : c <= 80 ? 80 : c <= 96 ? 96 : 128;
+}
+
+constexpr size_t kAlign = 256;
+
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+    size_t off = 0;
+    size_t take(size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; }
+};
+
+inline size_t elem_size(int dtype) { return dtype == RSVD_F64 ? 8 : (dtype == RSVD_F32 ? 4 : 2); }
+inline size_t comp_size(int dtype) { return dtype == RSVD_F64 ? 8 : 4; }
+
+// Work split heuristics (deterministic for a given device and shape).
+struct Splits {
+    int tn;      // split of the m-reduction in A^T Q
+    int gram_m;  // split of the m-reduction of an m x l Gram matrix
+    int gram_n;  // split of the n-reduction of an n x l Gram matrix
+    int colsum;  // row split of the column-mean pass
+};
+
+// Gram matrices: one split per CU at most, at least 256 rows per split.
+inline int gram_split(int64_t rows, int num_cu) {
+    return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(cdiv(rows, 256), num_cu)));
+}
+
+// A^T Q: as many splits as fit the 2 resident workgroups per CU in one round
+// (a partly filled second round would idle most CUs), at least 256 rows each.
+inline Splits make_splits(int64_t m, int64_t n, int num_cu) {
+    Splits s;
+    const int64_t tn_tiles = cdiv(n, 128);
+    s.tn = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>((2 * num_cu) / tn_tiles, cdiv(m, 256))));
+    s.gram_m = gram_split(m, num_cu);
+    s.gram_n = gram_split(n, num_cu);
+    const int64_t cs_cols = cdiv(n, 256);
+    s.colsum = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(cdiv(2 * num_cu, cs_cols), cdiv(m, 64))));
+    return s;
+}
+
+struct Plan {
+    int dtype = 0;
+    int64_t m = 0, n = 0;
+    int k = 0, p = 0, q = 0, l = 0, Lp = 0, kp = 0;
+    int tile = 0;       // column class of the tall product tiles (tile_class of l)
+    Splits sp{};
+    size_t Y = 0, Z = 0, Om = 0, part = 0, gram = 0, rinv = 0, racc = 0, sigma = 0,
+           xv = 0, xu = 0, jk = 0, wks = 0, vtmp = 0, mu = 0, mupart = 0, status = 0, bytes = 0;
+};
+
+inline int validate(int32_t dtype, int64_t m, int64_t n, int32_t k, const rsvd_params* prm) {
+    if (dtype != RSVD_F64 && dtype != RSVD_F32 && dtype != RSVD_BF16) return RSVD_ERR_UNSUPPORTED;
+    if (m < 1 || n < 1 || k < 1 || k >= std::min(m, n)) return RSVD_ERR_INVALID;
+    if (!prm || prm->p < 0 || prm->q < 0) return RSVD_ERR_INVALID;
+    if (prm->sdist < RSVD_NORMAL || prm->sdist > RSVD_RADEMACHER) return RSVD_ERR_INVALID;
+    if (prm->precision != RSVD_PREC_PLAIN && prm->precision != RSVD_PREC_BF16_MIXED) return RSVD_ERR_UNSUPPORTED;
+    if (prm->precision == RSVD_PREC_BF16_MIXED && dtype == RSVD_F64) return RSVD_ERR_UNSUPPORTED;
+    if (m > (int64_t(1) << 32) || n > (int64_t(1) << 32)) return RSVD_ERR_UNSUPPORTED;
+    const int64_t l = std::min<int64_t>(static_cast<int64_t>(k) + prm->p, std::min(m, n));
+    if (l > RSVD_MAX_L) return RSVD_ERR_UNSUPPORTED;
+    return RSVD_OK;
+}
+
+// batch = true: one problem of a grouped batch, whose parallelism comes from
+// the batch, so no product splits its reduction (every problem then issues
+// the same sequence of steps).
+inline Plan make_plan(int dtype, int64_t m, int64_t n, int k, const rsvd_params* prm, int num_cu,
+                      bool batch = false) {
+    Plan P;
+    P.dtype = dtype; P.m = m; P.n = n; P.k = k; P.q = prm->q;
+    P.l = static_cast<int>(std::min<int64_t>(static_cast<int64_t>(k) + prm->p, std::min(m, n)));
+    P.p = P.l - k;
+    P.Lp = tile_cols(P.l);
+    P.kp = tile_cols(k);
+    P.tile = tile_class(P.l, dtype != RSVD_F64);
+    P.sp = batch ? Splits{1, 1, 1, 1} : make_splits(m, n, num_cu);
+    const size_t cs = comp_size(dtype);
+    Layout L;
+    P.status = L.take(kAlign);
+    P.Y = L.take(static_cast<size_t>(m) * P.Lp * cs);
+    P.Z = L.take(static_cast<size_t>(n) * P.Lp * cs);
+    P.Om = L.take(static_cast<size_t>(n) * P.Lp * cs);
+    const size_t part_tn = P.sp.tn > 1 ? static_cast<size_t>(P.sp.tn) * n * P.Lp * cs : 0;
+    const size_t part_g = static_cast<size_t>(std::max(P.sp.gram_m, P.sp.gram_n)) * P.Lp * P.Lp * 8;
+    P.part = L.take(std::max(part_tn, part_g));
+    P.gram = L.take(static_cast<size_t>(P.Lp) * P.Lp * 8);
+    P.rinv = L.take(static_cast<size_t>(P.Lp) * P.Lp * cs);
+    P.racc = L.take(4 * static_cast<size_t>(P.Lp) * P.Lp * 8);
+    P.sigma = L.take(static_cast<size_t>(P.Lp) * 8);
+    P.xv = L.take(static_cast<size_t>(P.Lp) * P.kp * cs);
+    P.xu = L.take(static_cast<size_t>(P.Lp) * P.kp * cs);
+    P.jk = L.take(static_cast<size_t>(P.Lp) * P.kp * 8);
+    P.wks = L.take(static_cast<size_t>(P.Lp) * P.kp * 8);
+    P.vtmp = L.take(static_cast<size_t>(n) * P.kp * cs);
+    P.mu = L.take(static_cast<size_t>(n) * 8);
+    P.mupart = L.take(static_cast<size_t>(P.sp.colsum) * n * 8);
+    P.bytes = L.off;
+    return P;
+}
+
+template <typename T> inline T* at(void* work, size_t off) {
+    return reinterpret_cast<T*>(static_cast<unsigned char*>(work) + off);
+}
+
+#define RSVD_TRY(expr)                                   \
+    do {                                                 \
+        hipError_t _e = (expr);                          \
+        if (_e != hipSuccess) return _e;                 \
+    } while (0)
+
+// In-place orthonormalisation of M (rows x l, ld ldm, precision TC):
+// CholeskyQR2, with a shifted first pass and a third pass when needed.
+// adaptive = true (bases inside the power scheme, whose span is all that the
+// next product uses) runs the second pass only when the first pass shows an
+// ill-conditioned Gram matrix.
+// rfac (optional, f64, 4 consecutive l x l blocks) receives R1, R2, R3 (R3 = I
+
+struct SolveOut {
+    void* U; int64_t ldu;      // m x k or null
+    void* V; int64_t ldv;      // n x k or null (then workspace)
+    double* S;                 // k
+    double* eigvals; double* sdev;   // PCA extras or null
+    void* center_out;
+    int scale_u;               // 1: U columns scaled by sigma (PCA x = U S)
+    int center;
+    rsvd_info* info;
+    uint64_t* stamps;          // optional [first step, last step] device clock
+};
+
+inline int hip_status(rsvd_handle_t h, hipError_t e) {
+    if (e == hipSuccess) return RSVD_OK;
+    h->last_hip_error = static_cast<int>(e);
+    return RSVD_ERR_HIP;
+}
+
+// Workspace of the kernel-level building blocks (products, orthonormalisation,
+// small SVD) at these sizes.
+inline Plan block_plan(int32_t dtype, int64_t m, int64_t n, int32_t c, int num_cu) {
+    Plan P;
+    P.dtype = dtype; P.m = m; P.n = n; P.l = c; P.Lp = tile_cols(c);
+    P.sp = make_splits(m, n, num_cu);
+    const size_t cs = comp_size(dtype);
+    Layout L;
+    P.status = L.take(kAlign);
+    P.part = L.take(std::max(static_cast<size_t>(P.sp.tn) * n * P.Lp * cs,
+                             static_cast<size_t>(std::max(P.sp.gram_m, P.sp.gram_n)) * P.Lp * P.Lp * 8));
+    P.gram = L.take(static_cast<size_t>(P.Lp) * P.Lp * 8);
+    P.rinv = L.take(static_cast<size_t>(P.Lp) * P.Lp * cs);
+    P.racc = L.take(4 * static_cast<size_t>(P.Lp) * P.Lp * 8);
+    P.jk = L.take(static_cast<size_t>(P.Lp) * P.Lp * 8);
+    P.bytes = L.off;
+    return P;
+}
+
+// One solve of Alg. RSVDalgorithm / Alg. RPCAalgorithm for each storage type
+// (f64, f32, bf16 with f32 compute): launched at once on the handle's stream,
+// or recorded as one problem of a grouped batch.
+#define RSVD_DECLARE_SOLVE(NAME)                                                                       \
+    hipError_t solve_single_##NAME(rsvd_handle_t h, const Plan& P, const void* A, int64_t lda,         \
+                                   const rsvd_params* prm, const SolveOut& o, void* work);              \
+    hipError_t solve_record_##NAME(BatchRecorder& rec, const Plan& P, const void* A, int64_t lda,      \
+                                   const rsvd_params* prm, uint32_t stream_id, const SolveOut& o,       \
+                                   void* work);
+RSVD_DECLARE_SOLVE(f64)
+RSVD_DECLARE_SOLVE(f32)
+RSVD_DECLARE_SOLVE(bf16)
+#undef RSVD_DECLARE_SOLVE
+
+}  // namespace rsvd

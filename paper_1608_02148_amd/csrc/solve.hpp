@@ -1,0 +1,191 @@
+// The steps of one solve (templates over the storage / compute types and the
+// executor), compiled once per storage type in its own translation unit.
+#pragma once
+
+#include "launch.hpp"
+#include "plan.hpp"
+
+namespace rsvd {
+
+template <typename TC, class Ex>
+hipError_t orthonormalize(Ex& ex, int tile, TC* M, int64_t ldm, int64_t rows, int l, int Lp, int S,
+                          double* part, double* gram, TC* rinv, double* rfac, uint32_t* status,
+                          bool adaptive = false) {
+    for (int pass = 1; pass <= 3; ++pass) {
+        const bool conditional = (pass == 3) || (pass == 2 && adaptive);
+        const uint32_t* skip = conditional ? status : nullptr;
+        const uint32_t need = (pass == 2) ? ST_NEED_P2 : ST_NEED_P3;
+        RSVD_TRY((gemm_plain<TC, TC, double, MODE_TN>(ex, 0, true, M, ldm, l, rows, M, ldm, l, part, Lp, S,
+                                                      static_cast<int64_t>(Lp) * Lp, nullptr, skip, need)));
+        if (S > 1) RSVD_TRY(reduce_step<double>(ex, part, S, static_cast<int64_t>(Lp) * Lp, Lp, l, l, gram, Lp,
+                                                skip, need));
+        CholArgs ca;
+        ca.part = (S > 1) ? gram : part; ca.S = 1; ca.part_stride = 0; ca.ldp = Lp;
+        ca.l = l; ca.mrows = rows; ca.rinv = rinv; ca.ldr = Lp;
+        ca.rout = rfac ? rfac + static_cast<size_t>(pass - 1) * l * l : nullptr;
+        ca.status = status; ca.pass = pass; ca.skip_unless_pending = conditional; ca.adaptive = adaptive;
+        RSVD_TRY(ex.template run<CholBody<TC>>(ca));
+        RSVD_TRY((gemm_plain<TC, TC, TC, MODE_NN>(ex, tile, false, M, ldm, rows, l, rinv, Lp, l, M, ldm, 1, 0, nullptr,
+                                                  skip, need)));
+    }
+    if (rfac) {   // R = R3 (R2 R1); the product R2 R1 goes through the gram scratch
+        const size_t ll = static_cast<size_t>(l) * l;
+        RSVD_TRY((gemm_plain<double, double, double, MODE_NN>(ex, 0, true, rfac + ll, l, l, l, rfac, l, l, gram, l, 1,
+                                                              0, nullptr, nullptr, 0)));
+        RSVD_TRY((gemm_plain<double, double, double, MODE_NN>(ex, 0, true, rfac + 2 * ll, l, l, l, gram, l, l,
+                                                              rfac + 3 * ll, l, 1, 0, nullptr, nullptr, 0)));
+    }
+    return hipSuccess;
+}
+
+// Optional event bracketing of the products with A (rsvd_profile_enable).
+inline hipEvent_t pool_event(rsvd_handle_t h) {
+    if (h->pool_used == h->event_pool.size()) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        h->event_pool.push_back(e);
+    }
+    return h->event_pool[h->pool_used++];
+}
+
+// h == nullptr (recorded batch steps) or profiling off: just issue the step.
+template <typename F>
+hipError_t timed(rsvd_handle_t h, int kind, double flops, double bytes, F&& launch) {
+    if (!h || !h->profiling) return launch();
+    ProfRecord r;
+    r.kind = kind; r.flops = flops; r.bytes = bytes;
+    r.start = pool_event(h);
+    r.stop = pool_event(h);
+    if (!r.start || !r.stop) return hipErrorOutOfMemory;
+    RSVD_TRY(hipEventRecord(r.start, h->stream));
+    RSVD_TRY(launch());
+    RSVD_TRY(hipEventRecord(r.stop, h->stream));
+    h->prof.push_back(r);
+    return hipSuccess;
+}
+
+// Every step of one solve, issued through the executor: launched at once for
+// a single solve, or recorded as this problem's share of grouped batch steps.
+// prof (may be null) receives the event timings of the products with A.
+template <typename TA, typename TC, class Ex>
+hipError_t solve_steps(Ex& ex, rsvd_handle_t prof, const Plan& P, const TA* A, int64_t lda,
+                       const rsvd_params* prm, uint32_t stream_id, const SolveOut& o, void* work) {
+    const int64_t m = P.m, n = P.n;
+    const int l = P.l, Lp = P.Lp, k = P.k, tile = P.tile;
+    uint32_t* status = at<uint32_t>(work, P.status);
+    TC* Y = at<TC>(work, P.Y);
+    TC* Z = at<TC>(work, P.Z);
+    TC* Om = at<TC>(work, P.Om);
+    TC* partc = at<TC>(work, P.part);
+    double* partd = at<double>(work, P.part);
+    double* gram = at<double>(work, P.gram);
+    TC* rinv = at<TC>(work, P.rinv);
+    double* racc = at<double>(work, P.racc);
+    double* sigma = at<double>(work, P.sigma);
+    TC* xv = at<TC>(work, P.xv);
+    TC* xu = at<TC>(work, P.xu);
+    double* jk = at<double>(work, P.jk);
+    double* mu = o.center ? at<double>(work, P.mu) : nullptr;
+
+    if (o.stamps) RSVD_TRY(ex.template run<StampBody>(StampBody::Args{o.stamps}));
+    RSVD_TRY(ex.template run<ClearBody>(ClearBody::Args{status, 1}));
+
+    if (mu) {   // column means (implicit centring, Sec. 4.2)
+        const int S = P.sp.colsum;
+        double* mp = at<double>(work, P.mupart);
+        RSVD_TRY(ex.template run<ColsumBody<TA>>(typename ColsumBody<TA>::Args{A, lda, m, n, cdiv(m, S), S, mp}));
+        RSVD_TRY(ex.template run<ColmeanBody>(ColmeanBody::Args{mp, S, m, n, mu}));
+    }
+
+    // Alg. rqb steps 2-3: Omega and the sketch Y = A Omega.
+    RSVD_TRY(ex.template run<OmegaBody<TC>>(typename OmegaBody<TC>::Args{
+        n, l, Lp, prm->seed, stream_id, prm->sdist, Om, static_cast<int64_t>(Lp)}));
+    const double pass_flops = 2.0 * static_cast<double>(m) * n * l;
+    const double a_bytes = static_cast<double>(m) * n * sizeof(TA);
+    const double nn_bytes = a_bytes + (static_cast<double>(n) + m) * l * sizeof(TC);
+    const double tn_bytes = a_bytes + (static_cast<double>(m) + n) * l * sizeof(TC);
+    // Arithmetic of each pass: storage precision, or in the mixed mode bf16
+    // for the early passes and split bf16 (f32-accurate) for the last sketch
+    // and the projection (precision escalation).
+    const bool mixed = prm->precision == RSVD_PREC_BF16_MIXED;
+    const int early = mixed ? 1 : 0, late = mixed ? 2 : 0;
+    auto ax = [&](const TC* X, int arith) -> hipError_t {     // Y (m x Lp) = A X
+        return timed(prof, 0, pass_flops, nn_bytes, [&] {
+            return gemm_step<TA, TC, MODE_NN>(ex, arith, tile, A, lda, m, n, X, Lp, l, Y, Lp, 1, 0, mu, nullptr,
+                                              0);
+        });
+    };
+    RSVD_TRY(ax(Om, P.q == 0 ? late : early));
+
+    auto aty = [&](TC* dst, int arith) -> hipError_t {     // dst (n x Lp) = A^T Y
+        const int S = P.sp.tn;
+        if (S == 1)
+            return timed(prof, 1, pass_flops, tn_bytes, [&] {
+                return gemm_step<TA, TC, MODE_TN>(ex, arith, tile, A, lda, n, m, Y, Lp, l, dst, Lp, 1, 0, mu,
+                                                  nullptr, 0);
+            });
+        RSVD_TRY(timed(prof, 1, pass_flops, tn_bytes, [&] {
+            return gemm_step<TA, TC, MODE_TN>(ex, arith, tile, A, lda, n, m, Y, Lp, l, partc, Lp, S,
+                                              static_cast<int64_t>(n) * Lp, mu, nullptr, 0);
+        }));
+        return reduce_step<TC>(ex, partc, S, static_cast<int64_t>(n) * Lp, Lp, n, l, dst, Lp);
+    };
+
+    // Alg. subspace_iter: q rounds of orth(Y); Z = orth(A^T Y); Y = A Z.
+    for (int it = 0; it < P.q; ++it) {
+        RSVD_TRY(orthonormalize<TC>(ex, tile, Y, Lp, m, l, Lp, P.sp.gram_m, partd, gram, rinv, nullptr, status,
+                                    true));
+        RSVD_TRY(aty(Z, early));
+        RSVD_TRY(orthonormalize<TC>(ex, tile, Z, Lp, n, l, Lp, P.sp.gram_n, partd, gram, rinv, nullptr, status,
+                                    true));
+        RSVD_TRY(ax(Z, it == P.q - 1 ? late : early));
+    }
+    // Alg. rqb steps 9-10: Q = qr(Y); B^T = A^T Q.
+    RSVD_TRY(orthonormalize<TC>(ex, tile, Y, Lp, m, l, Lp, P.sp.gram_m, partd, gram, rinv, nullptr, status));
+    RSVD_TRY(aty(Z, late));
+    // svd(B): B^T = Q_b R_b (Q_b overwrites Z), R_b = W S J^T by Jacobi.
+    RSVD_TRY(orthonormalize<TC>(ex, tile, Z, Lp, n, l, Lp, P.sp.gram_n, partd, gram, rinv, racc, status));
+    racc += 3 * static_cast<size_t>(l) * l;       // R_b = R3 R2 R1
+    {
+        JacobiArgs ja;
+        ja.R = racc; ja.ldr = l; ja.l = l; ja.k = k;
+        double* wks = at<double>(work, P.wks);
+        ja.sigma = sigma; ja.xv = xv; ja.ldx = Lp; ja.xcols = P.kp; ja.wks = wks;
+        ja.status = status; ja.max_sweeps = 60; ja.tol = jacobi_tol(ja.l);
+        RSVD_TRY(ex.template run<JacobiBody<TC>>(ja));
+        // J_k = R_b^T (W_k / sigma)
+        RSVD_TRY((gemm_plain<double, double, double, MODE_TN>(ex, 0, true, racc, l, l, l, wks, k, k, jk, k, 1, 0,
+                                                              nullptr, nullptr, 0)));
+    }
+    // V = Q_b W_k, sign rule, then U = Q (J_k D) with D = signs (x S for PCA).
+    TC* V = o.V ? static_cast<TC*>(o.V) : at<TC>(work, P.vtmp);
+    const int64_t ldv = o.V ? o.ldv : P.kp;
+    RSVD_TRY((gemm_plain<TC, TC, TC, MODE_NN>(ex, tile, false, Z, Lp, n, l, xv, P.kp, k, V, ldv, 1, 0, nullptr, nullptr,
+                                              0)));
+    RSVD_TRY(ex.template run<SignLiftBody<TC>>(typename SignLiftBody<TC>::Args{
+        V, ldv, n, l, k, jk, sigma, o.scale_u, xu, Lp, P.kp}));
+    if (o.U)
+        RSVD_TRY((gemm_plain<TC, TC, TC, MODE_NN>(ex, tile, false, Y, Lp, m, l, xu, P.kp, k, static_cast<TC*>(o.U), o.ldu,
+                                                  1, 0, nullptr, nullptr, 0)));
+    RSVD_TRY(ex.template run<FinalizeBody<TC>>(typename FinalizeBody<TC>::Args{
+        sigma, k, o.S, o.eigvals, o.sdev, static_cast<double>(m - 1), mu, n, static_cast<TC*>(o.center_out),
+        status, o.info, l, P.q, P.p}));
+    if (o.stamps) RSVD_TRY(ex.template run<StampBody>(StampBody::Args{o.stamps + 1}));
+    return hipSuccess;
+}
+
+#define RSVD_DEFINE_SOLVE(NAME, TA, TC)                                                                 \
+    hipError_t solve_single_##NAME(rsvd_handle_t h, const Plan& P, const void* A, int64_t lda,         \
+                                   const rsvd_params* prm, const SolveOut& o, void* work) {             \
+        SingleExec ex{h->stream};                                                                      \
+        return solve_steps<TA, TC>(ex, h, P, static_cast<const TA*>(A), lda, prm, prm->stream_id, o,   \
+                                   work);                                                              \
+    }                                                                                                  \
+    hipError_t solve_record_##NAME(BatchRecorder& rec, const Plan& P, const void* A, int64_t lda,      \
+                                   const rsvd_params* prm, uint32_t stream_id, const SolveOut& o,       \
+                                   void* work) {                                                       \
+        return solve_steps<TA, TC>(rec, nullptr, P, static_cast<const TA*>(A), lda, prm, stream_id, o, \
+                                   work);                                                              \
+    }
+
+}  // namespace rsvd
