@@ -184,12 +184,20 @@ typedef struct {
     void* V;             /* n x k (ldv >= k) or NULL                    */
     int64_t ldv;
     rsvd_info* info;     /* device record or NULL                       */
+    float* features;     /* RSVD_BATCH_FEATURES: 131 selector inputs    */
+    int32_t q, p;        /* RSVD_BATCH_OWN_QP: this matrix's q and p    */
 } rsvd_batch_desc;
 
 typedef struct rsvd_batch_s* rsvd_batch_t;
 
-#define RSVD_BATCH_GRAPH  1   /* bind captures the launches in a HIP graph     */
-#define RSVD_BATCH_STAMPS 2   /* record device-clock stamps per matrix          */
+#define RSVD_BATCH_GRAPH    1  /* bind captures the launches in a HIP graph    */
+#define RSVD_BATCH_STAMPS   2  /* record device-clock stamps per matrix         */
+#define RSVD_BATCH_FEATURES 4  /* run only the q = 0 sketch of each matrix and
+                                  write its selector inputs (desc.features,
+                                  see the selector network below); S, U, V
+                                  are not written                               */
+#define RSVD_BATCH_OWN_QP   8  /* take q and p from each desc instead of
+                                  params (matrices are grouped by q too)       */
 
 /* descs: HOST array of `count` entries (their pointers are device pointers,
  * recorded at bind time).  *work_bytes receives the workspace size. */
@@ -205,6 +213,60 @@ int rsvd_batch_run(rsvd_batch_t batch);
  * last step ran; *ticks_per_second receives the clock rate. */
 int rsvd_batch_stamps(rsvd_batch_t batch, uint64_t* host, double* ticks_per_second);
 int rsvd_batch_destroy(rsvd_batch_t batch);
+
+/* Learned choice of (q, p) for each matrix of a batch (see the selector
+ * network below): runs the q = 0 sketches as an RSVD_BATCH_FEATURES batch,
+ * the network on their features, and writes the chosen q and p of matrix b
+ * to the HOST arrays q_out[b], p_out[b] (and the features to features_out,
+ * a device array of count x 131 floats, when not NULL).  Synchronises the
+ * handle's stream once.  Only A, lda, m, n, k and stream_id of each desc are
+ * read; params gives the seed, test matrix and precision.  The Omega columns
+ * of the sketch are a prefix-compatible subset of the later solve's (same
+ * seed, same stream). */
+int rsvd_select_workspace_size(rsvd_handle_t handle, int32_t dtype, int32_t count,
+                               const rsvd_batch_desc* descs, const rsvd_params* params,
+                               size_t* bytes);
+int rsvd_select(rsvd_handle_t handle, int32_t dtype, int32_t count, const rsvd_batch_desc* descs,
+                const rsvd_params* params, const float* theta, int32_t* q_out, int32_t* p_out,
+                float* features_out, void* work, size_t work_bytes);
+
+/* ---- Learned choice of (q, p): the selector network ---------------------
+ * A three-layer perceptron reads 131 features of a matrix (the singular values
+ * of its q = 0 sketch Y0 = A Omega[:, :l0], l0 = min(max(2k, k + 20), m, n,
+ * 128), divided by the largest and zero-padded to 128, then log2(m)/12,
+ * log2(n)/12, log2(k)/12) and scores 15 classes c = 3 q + j, q = 0..4,
+ * p = (5, 10, 20)[j].  The paper fixes no rule for q and p beyond its defaults
+ * (Sec. 3.6) and the advice to iterate more on slowly decaying spectra
+ * (Sec. 2.2); the network learns the cheapest pair that meets an accuracy
+ * target.  Layers 131 -> 64 -> 64 -> 15, ReLU, softmax; parameters are one
+ * f32 device vector of RSVD_MLP_PARAMS values in the order W1 (131 x 64,
+ * row-major), b1, W2 (64 x 64), b2, W3 (64 x 15), b3. */
+#define RSVD_MLP_INPUTS  131
+#define RSVD_MLP_HIDDEN  64
+#define RSVD_MLP_CLASSES 15
+#define RSVD_MLP_PARAMS  13583
+
+/* Workspace bytes of rsvd_mlp_train_step for `batch` samples. */
+int rsvd_mlp_workspace_size(int32_t batch, size_t* bytes);
+/* He-uniform weights (U(-a, a), a = sqrt(6 / fan_in), from Philox under
+ * `seed`), zero biases. */
+int rsvd_mlp_init(rsvd_handle_t handle, float* theta, uint64_t seed);
+/* Forward pass of `batch` samples x (batch x 131, f32, row-major): prob
+ * (batch x 15 softmax, or NULL) and cls (batch int32 argmax, lowest index on
+ * ties, or NULL; not both NULL). */
+int rsvd_mlp_forward(rsvd_handle_t handle, const float* theta, int32_t batch,
+                     const float* x, float* prob, int32_t* cls);
+/* One training step on the mean cross-entropy of labels (batch int32 classes):
+ * forward, back-propagation, gradient (written to grad if not NULL) and loss
+ * (device f32 scalar if not NULL); then, for step >= 1, one Adam update
+ * (beta1 0.9, beta2 0.999, eps 1e-8, bias correction for step t = step) of
+ * theta, adam_m and adam_v (zero-initialised by the caller before step 1).
+ * step = 0 computes the gradient and loss only.  Sums run in a fixed order:
+ * the result is deterministic. */
+int rsvd_mlp_train_step(rsvd_handle_t handle, float* theta, float* adam_m, float* adam_v,
+                        int32_t step, float lr, int32_t batch, const float* x,
+                        const int32_t* labels, float* grad, float* loss,
+                        void* work, size_t work_bytes);
 
 /* ---- Optional per-kernel timing ------------------------------------------
  * When enabled, every product with A (the passes of Alg. rqb and

@@ -138,10 +138,14 @@ class Batch:
     ``U``, ``S``, ``V`` (lists of views into three flat buffers) after
     ``run()`` and the stream completing.  ``graph=True`` replays one captured
     HIP graph per run; ``stamps=True`` records device-clock stamps per matrix.
+    ``qs`` / ``ps``: per-matrix q and p (lists) instead of ``q`` / ``p``.
+    ``features=True``: run only the q = 0 sketches and fill ``features``
+    (count x 131) with the selector inputs.
     """
 
     def __init__(self, As, ks, p=10, q=2, seed=0, stream_ids=None, sdist="normal", precision="plain",
-                 compute_u=True, compute_v=True, graph=True, stamps=False, infos=False):
+                 compute_u=True, compute_v=True, graph=True, stamps=False, infos=False, qs=None, ps=None,
+                 features=False):
         if len(As) == 0 or len(As) != len(ks):
             raise ValueError("As and ks must be non-empty lists of equal length")
         dts = {_check_matrix(A) for A in As}
@@ -153,6 +157,10 @@ class Batch:
         self.count = len(As)
         od = out_dtype(As[0])
         shapes = [(int(A.shape[0]), int(A.shape[1]), int(k)) for A, k in zip(As, ks)]
+        if features:
+            compute_u = compute_v = False
+        self.features = (torch.zeros(self.count, L.MLP_INPUTS, dtype=torch.float32, device=dev)
+                         if features else None)
         u_off, v_off, s_off = [0], [0], [0]
         for m, n, k in shapes:
             u_off.append(u_off[-1] + m * k)
@@ -177,9 +185,13 @@ class Batch:
             d.S = S.data_ptr()
             d.V, d.ldv = (V.data_ptr(), k) if V is not None else (None, 0)
             d.info = self.info[b].data_ptr() if infos else None
+            d.features = self.features[b].data_ptr() if features else None
+            d.q = int(qs[b]) if qs is not None else int(q)
+            d.p = int(ps[b]) if ps is not None else int(p)
         self._As = list(As)            # keep the inputs alive as long as the batch
         prm = make_params(p, q, seed, 0, sdist, precision)
         flags = (L.BATCH_GRAPH if graph else 0) | (L.BATCH_STAMPS if stamps else 0)
+        flags |= (L.BATCH_FEATURES if features else 0) | (L.BATCH_OWN_QP if (qs is not None or ps is not None) else 0)
         self._lib = L.load()
         self._h = handle(dev)
         self._b = ctypes.c_void_p()
@@ -317,3 +329,94 @@ def small_svd(R):
     L.check(L.load().rsvd_small_svd(handle(R.device), c, _ptr(R), _ptr(s), _ptr(W), _ptr(J), _ptr(flags),
                                     _ptr(work), work.numel()), "rsvd_small_svd")
     return s, W, J, flags
+
+
+# ---------------------------------------------------------------- selector network
+
+def mlp_init(seed=0, device="cuda"):
+    """Fresh selector-network parameters (f32 vector of MLP_PARAMS values)."""
+    theta = torch.empty(L.MLP_PARAMS, dtype=torch.float32, device=device)
+    L.check(L.load().rsvd_mlp_init(handle(device), _ptr(theta), int(seed)), "rsvd_mlp_init")
+    return theta
+
+
+def _mlp_x(X):
+    if X.dtype != torch.float32 or X.dim() != 2 or X.shape[1] != L.MLP_INPUTS or not X.is_contiguous():
+        raise ValueError("features must be a contiguous float32 tensor of shape (batch, 131)")
+    return X
+
+
+def mlp_forward(theta, X):
+    """(prob batch x 15, class batch) of the selector network."""
+    X = _mlp_x(X)
+    B = X.shape[0]
+    prob = torch.empty(B, L.MLP_CLASSES, dtype=torch.float32, device=X.device)
+    cls = torch.empty(B, dtype=torch.int32, device=X.device)
+    L.check(L.load().rsvd_mlp_forward(handle(X.device), _ptr(theta), B, _ptr(X), _ptr(prob), _ptr(cls)),
+            "rsvd_mlp_forward")
+    return prob, cls
+
+
+class MlpTrainer:
+    """Adam training of the selector network through rsvd_mlp_train_step."""
+
+    def __init__(self, theta, lr=1e-3):
+        self.theta = theta
+        self.m = torch.zeros_like(theta)
+        self.v = torch.zeros_like(theta)
+        self.step_no = 0
+        self.lr = float(lr)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=theta.device)
+        self.grad = torch.zeros_like(theta)
+        self._work = None
+
+    def _ws(self, B):
+        nbytes = ctypes.c_size_t()
+        L.check(L.load().rsvd_mlp_workspace_size(B, ctypes.byref(nbytes)), "rsvd_mlp_workspace_size")
+        if self._work is None or self._work.numel() < nbytes.value:
+            self._work = workspace(nbytes.value, self.theta.device)
+        return self._work
+
+    def step(self, X, y, update=True):
+        """One step on (X batch x 131, y batch int32); returns the loss tensor."""
+        X = _mlp_x(X)
+        y = y.to(torch.int32).contiguous()
+        B = X.shape[0]
+        work = self._ws(B)
+        if update:
+            self.step_no += 1
+        L.check(L.load().rsvd_mlp_train_step(handle(X.device), _ptr(self.theta), _ptr(self.m), _ptr(self.v),
+                                             self.step_no if update else 0, self.lr, B, _ptr(X), _ptr(y),
+                                             _ptr(self.grad), _ptr(self.loss), _ptr(work), work.numel()),
+                "rsvd_mlp_train_step")
+        return self.loss
+
+
+def select(As, ks, theta, seed=0, stream_ids=None, sdist="normal", precision="plain"):
+    """Learned (q, p) per matrix (rsvd_select): returns (qs, ps, features)."""
+    import numpy as np
+    dts = {_check_matrix(A) for A in As}
+    if len(dts) != 1:
+        raise ValueError("every matrix must have the same dtype")
+    dt = dts.pop()
+    dev = As[0].device
+    n = len(As)
+    descs = (L.BatchDesc * n)()
+    sids = list(range(n)) if stream_ids is None else [int(x) for x in stream_ids]
+    for b, (A, k) in enumerate(zip(As, ks)):
+        d = descs[b]
+        d.A, d.lda, d.m, d.n, d.k, d.stream_id = A.data_ptr(), A.stride(0), A.shape[0], A.shape[1], int(k), sids[b]
+    prm = make_params(10, 0, seed, 0, sdist, precision)
+    lib = L.load()
+    h = handle(dev)
+    nbytes = ctypes.c_size_t()
+    L.check(lib.rsvd_select_workspace_size(h, dt, n, descs, ctypes.byref(prm), ctypes.byref(nbytes)),
+            "rsvd_select_workspace_size")
+    work = workspace(nbytes.value, dev)
+    feats = torch.empty(n, L.MLP_INPUTS, dtype=torch.float32, device=dev)
+    qs = np.zeros(n, dtype=np.int32)
+    ps = np.zeros(n, dtype=np.int32)
+    L.check(lib.rsvd_select(h, dt, n, descs, ctypes.byref(prm), _ptr(theta),
+                            qs.ctypes.data_as(ctypes.c_void_p), ps.ctypes.data_as(ctypes.c_void_p),
+                            _ptr(feats), _ptr(work), work.numel()), "rsvd_select")
+    return qs, ps, feats

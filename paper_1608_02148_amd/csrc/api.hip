@@ -175,16 +175,17 @@ int rsvd_profile_collect(rsvd_handle_t handle, rsvd_kernel_stat* out) {
 // ---------------------------------------------------------------- batches
 // A ragged batch runs every step of the solve as one grouped launch over all
 // of its matrices.  Matrices are grouped by the column class of their product
-// tiles (tile_class of l: 32, 48, 64, 80, 96, 128); each group runs its solves
-// as one sequence of grouped launches on a stream of its own (forked from and
-// joined back to the caller's stream), and inside a group the matrices are
-// ordered by descending work (m n l) so that the largest tiles are dispatched
-// first.
+// tiles (tile_class of l: 32, 48, 64, 80, 96, 128) and by q (the number of
+// steps); each group runs its solves as one sequence of grouped launches, the
+// groups spread over up to six streams (the caller's and side streams forked
+// from it and joined back), and inside a group the matrices are ordered by
+// descending work (m n l) so that the largest tiles are dispatched first.
 
 namespace rsvd {
 
 struct BatchGroup {
     int tile = 0;
+    int q = 0;
     std::vector<int> members;
     BatchRecorder rec;
     size_t table_off = 0;
@@ -224,6 +225,7 @@ hipError_t record_group(rsvd_batch_s* B, BatchGroup& g, void* base) {
         SolveOut o{};
         o.U = d.U; o.ldu = d.ldu; o.V = d.V; o.ldv = d.ldv; o.S = d.S; o.info = d.info;
         o.stamps = stamps ? at<uint64_t>(base, B->stamps_off) + 2 * static_cast<size_t>(i) : nullptr;
+        if (B->flags & RSVD_BATCH_FEATURES) { o.features = d.features; o.feat_k = d.k; o.S = nullptr; o.U = nullptr; }
         g.rec.begin_problem();
         void* w = at<unsigned char>(base, B->offs[i]);
         hipError_t e = hipErrorInvalidValue;
@@ -243,22 +245,30 @@ inline hipError_t record_all(rsvd_batch_s* B, void* base) {
     return hipSuccess;
 }
 
+// Group g runs on lane g % lanes: lane 0 is the caller's stream, the others
+// are side streams forked from it and joined back with events.
+constexpr size_t kMaxLanes = 6;
+
+inline size_t lanes_of(const rsvd_batch_s* B) { return std::min(B->groups.size(), kMaxLanes); }
+
 inline hipError_t launch_all(const rsvd_batch_s* B, hipStream_t st) {
     const unsigned char* base = static_cast<const unsigned char*>(B->work);
-    const size_t ng = B->groups.size();
-    if (ng > 1) RSVD_TRY(hipEventRecord(B->fork, st));
-    for (size_t i = 1; i < ng; ++i) {
-        RSVD_TRY(hipStreamWaitEvent(B->side[i - 1], B->fork, 0));
-        RSVD_TRY(B->groups[i].rec.launch(base + B->groups[i].table_off, B->side[i - 1]));
-        RSVD_TRY(hipEventRecord(B->done[i - 1], B->side[i - 1]));
+    const size_t lanes = lanes_of(B);
+    if (lanes > 1) RSVD_TRY(hipEventRecord(B->fork, st));
+    for (size_t s = 1; s < lanes; ++s) RSVD_TRY(hipStreamWaitEvent(B->side[s - 1], B->fork, 0));
+    for (size_t g = 0; g < B->groups.size(); ++g) {
+        hipStream_t ls = (g % lanes == 0) ? st : B->side[g % lanes - 1];
+        RSVD_TRY(B->groups[g].rec.launch(base + B->groups[g].table_off, ls));
     }
-    RSVD_TRY(B->groups[0].rec.launch(base + B->groups[0].table_off, st));
-    for (size_t i = 1; i < ng; ++i) RSVD_TRY(hipStreamWaitEvent(st, B->done[i - 1], 0));
+    for (size_t s = 1; s < lanes; ++s) {
+        RSVD_TRY(hipEventRecord(B->done[s - 1], B->side[s - 1]));
+        RSVD_TRY(hipStreamWaitEvent(st, B->done[s - 1], 0));
+    }
     return hipSuccess;
 }
 
 inline hipError_t make_side_streams(rsvd_batch_s* B) {
-    const size_t need = B->groups.empty() ? 0 : B->groups.size() - 1;
+    const size_t need = lanes_of(B) > 0 ? lanes_of(B) - 1 : 0;
     if (need && !B->fork) RSVD_TRY(hipEventCreateWithFlags(&B->fork, hipEventDisableTiming));
     while (B->side.size() < need) {
         hipStream_t s = nullptr;
@@ -285,32 +295,55 @@ extern "C" {
 int rsvd_batch_create(rsvd_handle_t handle, int32_t dtype, int32_t count, const rsvd_batch_desc* descs,
                       const rsvd_params* params, int32_t flags, rsvd_batch_t* batch, size_t* work_bytes) {
     if (!handle || count < 1 || !descs || !params || !batch || !work_bytes) return RSVD_ERR_INVALID;
-    if (flags & ~(RSVD_BATCH_GRAPH | RSVD_BATCH_STAMPS)) return RSVD_ERR_INVALID;
-    const bool with_u = descs[0].U != nullptr;
+    if (flags & ~(RSVD_BATCH_GRAPH | RSVD_BATCH_STAMPS | RSVD_BATCH_FEATURES | RSVD_BATCH_OWN_QP))
+        return RSVD_ERR_INVALID;
+    const bool feat = (flags & RSVD_BATCH_FEATURES) != 0;
+    const bool with_u = !feat && descs[0].U != nullptr;
+    std::vector<rsvd_params> prm(count, *params);
     for (int32_t i = 0; i < count; ++i) {
         const rsvd_batch_desc& d = descs[i];
-        const int v = validate(dtype, d.m, d.n, d.k, params);
+        if (feat) {             // q = 0 sketch of width l0 = min(max(2k, k + 20), m, n, RSVD_MAX_L)
+            prm[i].q = 0;
+            const int64_t l0 = std::min<int64_t>(std::min<int64_t>(std::max(2 * d.k, d.k + 20), RSVD_MAX_L),
+                                                 std::min(d.m, d.n));
+            prm[i].p = static_cast<int32_t>(std::max<int64_t>(0, l0 - d.k));
+        } else if (flags & RSVD_BATCH_OWN_QP) {
+            prm[i].q = d.q;
+            prm[i].p = d.p;
+        }
+        const int v = validate(dtype, d.m, d.n, d.k, &prm[i]);
         if (v != RSVD_OK) return v;
-        if (!d.A || d.lda < d.n || !d.S) return RSVD_ERR_INVALID;
+        if (!d.A || d.lda < d.n) return RSVD_ERR_INVALID;
+        if (feat) {
+            if (!d.features) return RSVD_ERR_INVALID;
+            continue;
+        }
+        if (!d.S) return RSVD_ERR_INVALID;
         if ((d.U != nullptr) != with_u || (d.U && d.ldu < d.k) || (d.V && d.ldv < d.k)) return RSVD_ERR_INVALID;
     }
     rsvd_batch_s* B = new rsvd_batch_s();
     B->h = handle; B->dtype = dtype; B->flags = flags; B->prm = *params;
     B->desc.assign(descs, descs + count);
     B->plans.resize(count);
-    for (int32_t i = 0; i < count; ++i)
-        B->plans[i] = make_plan(dtype, descs[i].m, descs[i].n, descs[i].k, params, handle->dev.num_cu, true);
+    int qmax = 0;
+    for (int32_t i = 0; i < count; ++i) {
+        B->plans[i] = make_plan(dtype, descs[i].m, descs[i].n, descs[i].k, &prm[i], handle->dev.num_cu, true);
+        qmax = std::max(qmax, B->plans[i].q);
+    }
     for (int tile : {128, 96, 80, 64, 48, 32}) {
-        BatchGroup g;
-        g.tile = tile;
-        for (int32_t i = 0; i < count; ++i)
-            if (B->plans[i].tile == tile) g.members.push_back(i);
-        if (g.members.empty()) continue;
-        std::stable_sort(g.members.begin(), g.members.end(), [&](int a, int b) {
-            const Plan &pa = B->plans[a], &pb = B->plans[b];
-            return static_cast<double>(pa.m) * pa.n * pa.l > static_cast<double>(pb.m) * pb.n * pb.l;
-        });
-        B->groups.push_back(std::move(g));
+        for (int q = qmax; q >= 0; --q) {
+            BatchGroup g;
+            g.tile = tile;
+            g.q = q;
+            for (int32_t i = 0; i < count; ++i)
+                if (B->plans[i].tile == tile && B->plans[i].q == q) g.members.push_back(i);
+            if (g.members.empty()) continue;
+            std::stable_sort(g.members.begin(), g.members.end(), [&](int a, int b) {
+                const Plan &pa = B->plans[a], &pb = B->plans[b];
+                return static_cast<double>(pa.m) * pa.n * pa.l > static_cast<double>(pb.m) * pb.n * pb.l;
+            });
+            B->groups.push_back(std::move(g));
+        }
     }
     // Size the step tables with a dry recording (their size does not depend
     // on the addresses recorded in them).
@@ -390,6 +423,93 @@ int rsvd_batch_destroy(rsvd_batch_t batch) {
     for (hipEvent_t e : batch->done) (void)hipEventDestroy(e);
     if (batch->fork) (void)hipEventDestroy(batch->fork);
     delete batch;
+    return RSVD_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------- learned (q, p)
+
+namespace {
+
+const int kPChoices[3] = {5, 10, 20};
+
+struct SelectLayout {
+    size_t batch_bytes = 0, feat_off = 0, cls_off = 0, bytes = 0;
+};
+
+int select_plan(rsvd_handle_t handle, int32_t dtype, int32_t count, const rsvd_batch_desc* descs,
+                const rsvd_params* params, float* feat, std::vector<rsvd_batch_desc>& fd, rsvd_batch_t* b,
+                SelectLayout* lay) {
+    fd.assign(descs, descs + count);
+    for (int32_t i = 0; i < count; ++i) {
+        fd[i].features = feat ? feat + static_cast<size_t>(i) * RSVD_MLP_INPUTS
+                              : reinterpret_cast<float*>(static_cast<uintptr_t>(256));
+        fd[i].U = nullptr; fd[i].V = nullptr; fd[i].S = nullptr; fd[i].info = nullptr;
+    }
+    size_t bb = 0;
+    const int st = rsvd_batch_create(handle, dtype, count, fd.data(), params, RSVD_BATCH_FEATURES, b, &bb);
+    if (st != RSVD_OK) return st;
+    Layout L;
+    L.take(bb);
+    lay->batch_bytes = bb;
+    lay->feat_off = L.take(static_cast<size_t>(count) * RSVD_MLP_INPUTS * sizeof(float));
+    lay->cls_off = L.take(static_cast<size_t>(count) * sizeof(int32_t));
+    lay->bytes = L.off;
+    return RSVD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rsvd_select_workspace_size(rsvd_handle_t handle, int32_t dtype, int32_t count, const rsvd_batch_desc* descs,
+                               const rsvd_params* params, size_t* bytes) {
+    if (!bytes) return RSVD_ERR_INVALID;
+    std::vector<rsvd_batch_desc> fd;
+    rsvd_batch_t b = nullptr;
+    SelectLayout lay;
+    const int st = select_plan(handle, dtype, count, descs, params, nullptr, fd, &b, &lay);
+    if (st != RSVD_OK) return st;
+    rsvd_batch_destroy(b);
+    *bytes = lay.bytes;
+    return RSVD_OK;
+}
+
+int rsvd_select(rsvd_handle_t handle, int32_t dtype, int32_t count, const rsvd_batch_desc* descs,
+                const rsvd_params* params, const float* theta, int32_t* q_out, int32_t* p_out,
+                float* features_out, void* work, size_t work_bytes) {
+    if (!handle || !theta || !q_out || !p_out || !work || count < 1 || !descs) return RSVD_ERR_INVALID;
+    if (reinterpret_cast<uintptr_t>(work) % kAlign != 0) return RSVD_ERR_INVALID;
+    // first pass sizes the workspace, second records with the real buffers
+    std::vector<rsvd_batch_desc> fd;
+    rsvd_batch_t b = nullptr;
+    SelectLayout lay;
+    int st = select_plan(handle, dtype, count, descs, params, nullptr, fd, &b, &lay);
+    if (st != RSVD_OK) return st;
+    rsvd_batch_destroy(b);
+    if (work_bytes < lay.bytes) return RSVD_ERR_INVALID;
+    float* feat = features_out ? features_out : at<float>(work, lay.feat_off);
+    int32_t* cls = at<int32_t>(work, lay.cls_off);
+    st = select_plan(handle, dtype, count, descs, params, feat, fd, &b, &lay);
+    if (st != RSVD_OK) return st;
+    st = rsvd_batch_bind(b, work, lay.batch_bytes);
+    if (st == RSVD_OK) st = rsvd_batch_run(b);
+    if (st == RSVD_OK) st = rsvd_mlp_forward(handle, theta, count, feat, nullptr, cls);
+    std::vector<int32_t> host(count);
+    if (st == RSVD_OK) {
+        hipError_t e = hipMemcpyAsync(host.data(), cls, sizeof(int32_t) * count, hipMemcpyDeviceToHost,
+                                      handle->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(handle->stream);
+        st = hip_status(handle, e);
+    }
+    rsvd_batch_destroy(b);
+    if (st != RSVD_OK) return st;
+    for (int32_t i = 0; i < count; ++i) {
+        const int c = std::min(std::max(host[i], 0), RSVD_MLP_CLASSES - 1);
+        q_out[i] = c / 3;
+        p_out[i] = kPChoices[c % 3];
+    }
     return RSVD_OK;
 }
 

@@ -624,4 +624,25 @@ struct FinalizeBody {
     }
 };
 
+// ------------------------------------------------------------- features
+// Selector inputs of one matrix from the singular values sigma (descending,
+// l of them) of its q = 0 sketch: sigma_i / sigma_0 zero-padded to 128, then
+// log2(m)/12, log2(n)/12, log2(k)/12.
+struct FeatureBody {
+    struct Args { const double* sigma; int l; int64_t m; int64_t n; int k; float* out; };
+    static constexpr int THREADS = 128;
+    static int blocks(const Args&) { return 1; }
+    static size_t lds(const Args&) { return 0; }
+    static __device__ void run(const Args& a, int) {
+        const int i = threadIdx.x;
+        const double s0 = a.sigma[0];
+        a.out[i] = (i < a.l && s0 > 0.0) ? static_cast<float>(a.sigma[i] / s0) : 0.0f;
+        if (i < 3) {
+            const double v = (i == 0) ? static_cast<double>(a.m) : (i == 1) ? static_cast<double>(a.n)
+                                                                             : static_cast<double>(a.k);
+            a.out[128 + i] = static_cast<float>(log2(v) / 12.0);
+        }
+    }
+};
+
 }  // namespace rsvd

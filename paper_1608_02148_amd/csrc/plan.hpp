@@ -146,6 +146,8 @@ struct SolveOut {
     int center;
     rsvd_info* info;
     uint64_t* stamps;          // optional [first step, last step] device clock
+    float* features;           // non-null: stop after the sketch and write the 131 selector inputs
+    int feat_k;                // target rank used in the features
 };
 
 inline int hip_status(rsvd_handle_t h, hipError_t e) {

@@ -117,6 +117,18 @@ hipError_t solve_steps(Ex& ex, rsvd_handle_t prof, const Plan& P, const TA* A, i
     };
     RSVD_TRY(ax(Om, P.q == 0 ? late : early));
 
+    if (o.features) {   // selector inputs: singular values of the sketch via its R factor
+        RSVD_TRY(orthonormalize<TC>(ex, tile, Y, Lp, m, l, Lp, P.sp.gram_m, partd, gram, rinv, racc, status));
+        JacobiArgs ja;
+        ja.R = racc + 3 * static_cast<size_t>(l) * l; ja.ldr = l; ja.l = l; ja.k = 1;
+        ja.sigma = sigma; ja.xv = xv; ja.ldx = Lp; ja.xcols = P.kp; ja.wks = at<double>(work, P.wks);
+        ja.status = status; ja.max_sweeps = 60; ja.tol = jacobi_tol(ja.l);
+        RSVD_TRY(ex.template run<JacobiBody<TC>>(ja));
+        RSVD_TRY(ex.template run<FeatureBody>(FeatureBody::Args{sigma, l, m, n, o.feat_k, o.features}));
+        if (o.stamps) RSVD_TRY(ex.template run<StampBody>(StampBody::Args{o.stamps + 1}));
+        return hipSuccess;
+    }
+
     auto aty = [&](TC* dst, int arith) -> hipError_t {     // dst (n x Lp) = A^T Y
         const int S = P.sp.tn;
         if (S == 1)

@@ -43,10 +43,12 @@ class KernelStat(ctypes.Structure):
 class BatchDesc(ctypes.Structure):
     _fields_ = [("A", c_void_p), ("lda", c_int64), ("m", c_int64), ("n", c_int64), ("k", c_int32),
                 ("stream_id", c_uint32), ("U", c_void_p), ("ldu", c_int64), ("S", c_void_p),
-                ("V", c_void_p), ("ldv", c_int64), ("info", c_void_p)]
+                ("V", c_void_p), ("ldv", c_int64), ("info", c_void_p), ("features", c_void_p),
+                ("q", c_int32), ("p", c_int32)]
 
 
-BATCH_GRAPH, BATCH_STAMPS = 1, 2
+BATCH_GRAPH, BATCH_STAMPS, BATCH_FEATURES, BATCH_OWN_QP = 1, 2, 4, 8
+MLP_INPUTS, MLP_HIDDEN, MLP_CLASSES, MLP_PARAMS = 131, 64, 15, 13583
 
 PROFILE_KINDS = 2
 PROFILE_NAMES = ("A_X", "AT_Q")
@@ -78,6 +80,14 @@ _PROTOS = {
     "rsvd_batch_run": (c_int32, [c_void_p]),
     "rsvd_batch_stamps": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "rsvd_batch_destroy": (c_int32, [c_void_p]),
+    "rsvd_select_workspace_size": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p]),
+    "rsvd_select": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                              c_void_p, c_void_p, c_size_t]),
+    "rsvd_mlp_workspace_size": (c_int32, [c_int32, c_void_p]),
+    "rsvd_mlp_init": (c_int32, [c_void_p, c_void_p, c_uint64]),
+    "rsvd_mlp_forward": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
+    "rsvd_mlp_train_step": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, ctypes.c_float, c_int32,
+                                      c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t]),
     "rsvd_profile_enable": (c_int32, [c_void_p, c_int32]),
     "rsvd_profile_collect": (c_int32, [c_void_p, c_void_p]),
     "rsvd_philox_words": (c_int32, [c_void_p, c_int64, c_int32, c_uint64, c_uint32, c_void_p]),

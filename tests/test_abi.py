@@ -34,7 +34,7 @@ def test_library_exports_every_declared_symbol(lib):
 def test_struct_layouts_match_header():
     assert ctypes.sizeof(L.Params) == 40
     assert ctypes.sizeof(L.Info) == 24
-    assert ctypes.sizeof(L.BatchDesc) == 88
+    assert ctypes.sizeof(L.BatchDesc) == 104
 
 
 def test_default_params_are_the_papers(lib):
@@ -129,6 +129,7 @@ def _descs(shapes, U=True):
         d.A, d.lda, d.m, d.n, d.k, d.stream_id = 4096 * (b + 1), n, m, n, k, b
         d.U, d.ldu = (1 << 20, k) if U else (None, 0)
         d.S, d.V, d.ldv, d.info = 1 << 21, 1 << 22, k, None
+        d.features, d.q, d.p = None, -1, -1
     return arr
 
 
@@ -195,3 +196,38 @@ def test_batch_rejects_mixed_outputs_flags_and_lda(lib, handle):
     nbytes = ctypes.c_size_t(0)
     assert lib.rsvd_batch_create(handle, L.RSVD_F32, 0, _descs(shapes), ctypes.byref(prm), 0, ctypes.byref(b),
                                  ctypes.byref(nbytes)) == -1
+
+
+def test_batch_feature_and_own_qp_rules(lib, handle):
+    shapes = [(300, 200, 10), (1000, 100, 50)]
+    d = _descs(shapes)
+    # features mode needs a features pointer per matrix; S is not needed
+    assert _create(lib, handle, shapes, flags=L.BATCH_FEATURES, descs=d)[0] == -1
+    for b in range(2):
+        d[b].features, d[b].S = 1 << 23, None
+    st, b, nbytes = _create(lib, handle, shapes, flags=L.BATCH_FEATURES, descs=d)
+    assert st == 0 and nbytes > 0
+    lib.rsvd_batch_destroy(b)
+    # own q / p: taken from each desc and checked like params
+    d = _descs(shapes)
+    d[0].q, d[0].p, d[1].q, d[1].p = 3, 5, 0, 20
+    st, b, _ = _create(lib, handle, shapes, flags=L.BATCH_OWN_QP, descs=d)
+    assert st == 0
+    lib.rsvd_batch_destroy(b)
+    d[1].q = -1
+    assert _create(lib, handle, shapes, flags=L.BATCH_OWN_QP, descs=d)[0] == -1
+    d[1].q = 1
+    d[0].q, d[0].p = 1, 125                # l = min(135, 200) > RSVD_MAX_L
+    assert _create(lib, handle, shapes, flags=L.BATCH_OWN_QP, descs=d)[0] == -2
+
+
+def test_select_workspace_is_host_only(lib, handle):
+    shapes = [(300, 200, 10), (4000, 1000, 64)]
+    prm = L.Params()
+    lib.rsvd_default_params(ctypes.byref(prm))
+    nbytes = ctypes.c_size_t(0)
+    assert lib.rsvd_select_workspace_size(handle, L.RSVD_F32, 2, _descs(shapes), ctypes.byref(prm),
+                                          ctypes.byref(nbytes)) == 0
+    assert nbytes.value >= 2 * 131 * 4
+    assert lib.rsvd_select(handle, L.RSVD_F32, 2, _descs(shapes), ctypes.byref(prm), None, None, None, None,
+                           ctypes.c_void_p(256), nbytes.value) == -1
