@@ -15,7 +15,10 @@ Also reported:
   bf16_mixed    -- the same workload in the bf16 mixed-precision mode;
   batched       -- 4096 ragged f32 matrices (m in [256, 4096], n in
                    [64, 1024], k in [8, 64], p=10, q=2, sigma_i = i^-alpha)
-                   as one captured graph: solves/s, p50 / p99 latency.
+                   as one captured graph: solves/s, p50 / p99 latency;
+  learned       -- held-out generated matrices: FP32 plain (q=2, p=10 and
+                   q=4, p=20) against bf16 + learned (q, p): solves/s and the
+                   exact fraction within 1 % excess error.
 
 Usage: python bench.py [--gpus 1] [--steps 10] [--warmup 3]
 """
@@ -138,6 +141,39 @@ def batched_arm(steps, warmup, precision="plain"):
     return out
 
 
+def learned_arm(count, reps=3):
+    """Held-out generated matrices (selector workload): FP32 plain at q=2,
+    p=10 and at q=4, p=20 against bf16 mixed precision with the learned
+    (q, p), timed end to end; exact fraction within 1 % excess error."""
+    import numpy as np
+    import torch
+
+    from paper_1608_02148_amd import learned as L
+    from synth import learned_data as ld
+
+    theta, hdr = L.load_checkpoint(device="cuda")
+    log(f"[learned] generating {count} held-out matrices")
+    data = ld.build(count, "test")
+    torch.cuda.synchronize()
+    res = L.evaluate_arms(data, theta, reps=reps)
+    ok = {k: np.asarray(v["errors"]) <= L.TOL for k, v in res.items()}
+    feasible = ok["fp32_fixed_q4_p20"] | ok["fp32_default_q2_p10"]
+    out = {"workload": f"{count} generated f32 matrices (batch-workload shapes; poly/exp spectra with a "
+                       f"spectral floor), seed 5103", "checkpoint_step": hdr["step"],
+           "n_train": hdr["n_train"], "precision_infeasible": int(np.sum(~feasible))}
+    for k, v in res.items():
+        out[k] = {"solves_per_s": round(v["solves_per_s"], 1), "ms": round(v["ms"], 3),
+                  "frac_within_1pct": round(float(ok[k].mean()), 4),
+                  "frac_within_1pct_feasible": round(float(ok[k][feasible].mean()), 4)}
+        for extra in ("select_ms", "solve_ms", "q_hist", "p_hist"):
+            if extra in v:
+                out[k][extra] = v[extra] if not isinstance(v[extra], float) else round(v[extra], 3)
+    log(f"[learned] {out}")
+    del data
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -153,6 +189,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-only", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--learned-only", action="store_true")
+    ap.add_argument("--learned-count", type=int, default=2048)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -169,6 +208,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.batched_only:
         print(json.dumps({"batched": batched_arm(args.steps, args.warmup)}), flush=True)
+        return
+    if args.learned_only:
+        print(json.dumps({"learned": learned_arm(args.learned_count)}), flush=True)
         return
     m, n, k, p, q = args.m, args.n, args.k, args.p, args.q
     log(f"generating A {m}x{n} float32 (planted exp(-i/50) spectrum + noise floor)")
@@ -250,6 +292,7 @@ def main():
     del A
     torch.cuda.empty_cache()
     batched = None if args.no_batched else batched_arm(args.steps, args.warmup)
+    learned = None if args.no_learned else learned_arm(args.learned_count)
 
     rec = {
         "metric": "rSVD TFLOP/s (FP32 plain, C2)",
@@ -263,6 +306,7 @@ def main():
         "cpu_baseline": cpu,
         "bf16_mixed": bf16_arm,
         "batched": batched,
+        "learned": learned,
     }
     print(json.dumps(rec), flush=True)
 
