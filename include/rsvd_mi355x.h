@@ -197,7 +197,9 @@ typedef struct rsvd_batch_s* rsvd_batch_t;
                                   see the selector network below); S, U, V
                                   are not written                               */
 #define RSVD_BATCH_OWN_QP   8  /* take q and p from each desc instead of
-                                  params (matrices are grouped by q too)       */
+                                  params (a group runs its largest q; each
+                                  member's extra iterations are switched off
+                                  on the device)                               */
 
 /* descs: HOST array of `count` entries (their pointers are device pointers,
  * recorded at bind time).  *work_bytes receives the workspace size. */
@@ -215,20 +217,24 @@ int rsvd_batch_stamps(rsvd_batch_t batch, uint64_t* host, double* ticks_per_seco
 int rsvd_batch_destroy(rsvd_batch_t batch);
 
 /* Learned choice of (q, p) for each matrix of a batch (see the selector
- * network below): runs the q = 0 sketches as an RSVD_BATCH_FEATURES batch,
- * the network on their features, and writes the chosen q and p of matrix b
- * to the HOST arrays q_out[b], p_out[b] (and the features to features_out,
- * a device array of count x 131 floats, when not NULL).  Synchronises the
- * handle's stream once.  Only A, lda, m, n, k and stream_id of each desc are
- * read; params gives the seed, test matrix and precision.  The Omega columns
- * of the sketch are a prefix-compatible subset of the later solve's (same
- * seed, same stream). */
+ * network below): runs the q = 0 sketches as an RSVD_BATCH_FEATURES batch and
+ * the network on their features, then picks per matrix, from the network's
+ * distribution P over the cheapest sufficient class, the cheapest class c
+ * (cost (2q + 2)(k + p), ties to the lower index) whose estimated chance of
+ * sufficing -- the mass of P on the classes that c dominates (no larger q, no
+ * larger p) -- is at least tau; tau <= 0 takes the most probable class.  The
+ * chosen q and p of matrix b go to the HOST arrays q_out[b], p_out[b] (the
+ * features to features_out, a device array of count x 131 floats, when not
+ * NULL).  Synchronises the handle's stream once.  Only A, lda, m, n, k and
+ * stream_id of each desc are read; params gives the seed, test matrix and
+ * precision.  The sketch's Omega columns are a prefix of the later solve's
+ * (same seed, same stream). */
 int rsvd_select_workspace_size(rsvd_handle_t handle, int32_t dtype, int32_t count,
                                const rsvd_batch_desc* descs, const rsvd_params* params,
                                size_t* bytes);
 int rsvd_select(rsvd_handle_t handle, int32_t dtype, int32_t count, const rsvd_batch_desc* descs,
-                const rsvd_params* params, const float* theta, int32_t* q_out, int32_t* p_out,
-                float* features_out, void* work, size_t work_bytes);
+                const rsvd_params* params, const float* theta, float tau, int32_t* q_out,
+                int32_t* p_out, float* features_out, void* work, size_t work_bytes);
 
 /* ---- Learned choice of (q, p): the selector network ---------------------
  * A three-layer perceptron reads 131 features of a matrix (the singular values

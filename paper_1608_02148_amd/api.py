@@ -392,8 +392,10 @@ class MlpTrainer:
         return self.loss
 
 
-def select(As, ks, theta, seed=0, stream_ids=None, sdist="normal", precision="plain"):
-    """Learned (q, p) per matrix (rsvd_select): returns (qs, ps, features)."""
+def select(As, ks, theta, seed=0, stream_ids=None, sdist="normal", precision="plain", tau=0.0):
+    """Learned (q, p) per matrix (rsvd_select): returns (qs, ps, features).
+    tau <= 0: the network's most probable class; otherwise the cheapest class
+    whose dominated probability mass reaches tau."""
     import numpy as np
     dts = {_check_matrix(A) for A in As}
     if len(dts) != 1:
@@ -416,7 +418,7 @@ def select(As, ks, theta, seed=0, stream_ids=None, sdist="normal", precision="pl
     feats = torch.empty(n, L.MLP_INPUTS, dtype=torch.float32, device=dev)
     qs = np.zeros(n, dtype=np.int32)
     ps = np.zeros(n, dtype=np.int32)
-    L.check(lib.rsvd_select(h, dt, n, descs, ctypes.byref(prm), _ptr(theta),
+    L.check(lib.rsvd_select(h, dt, n, descs, ctypes.byref(prm), _ptr(theta), float(tau),
                             qs.ctypes.data_as(ctypes.c_void_p), ps.ctypes.data_as(ctypes.c_void_p),
                             _ptr(feats), _ptr(work), work.numel()), "rsvd_select")
     return qs, ps, feats

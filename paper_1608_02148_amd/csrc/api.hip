@@ -175,17 +175,18 @@ int rsvd_profile_collect(rsvd_handle_t handle, rsvd_kernel_stat* out) {
 // ---------------------------------------------------------------- batches
 // A ragged batch runs every step of the solve as one grouped launch over all
 // of its matrices.  Matrices are grouped by the column class of their product
-// tiles (tile_class of l: 32, 48, 64, 80, 96, 128) and by q (the number of
-// steps); each group runs its solves as one sequence of grouped launches, the
-// groups spread over up to six streams (the caller's and side streams forked
-// from it and joined back), and inside a group the matrices are ordered by
-// descending work (m n l) so that the largest tiles are dispatched first.
+// tiles (tile_class of l: 32, 48, 64, 80, 96, 128); each group runs its solves
+// as one sequence of grouped launches with as many power iterations as its
+// largest q (a member's iterations beyond its own q are switched off on the
+// device), the groups spread over up to six streams (the caller's and side
+// streams forked from it and joined back), and inside a group the matrices
+// are ordered by descending work so that the largest tiles start first.
 
 namespace rsvd {
 
 struct BatchGroup {
     int tile = 0;
-    int q = 0;
+    int q = 0;          // largest q of the members (iterations issued)
     std::vector<int> members;
     BatchRecorder rec;
     size_t table_off = 0;
@@ -325,25 +326,25 @@ int rsvd_batch_create(rsvd_handle_t handle, int32_t dtype, int32_t count, const 
     B->h = handle; B->dtype = dtype; B->flags = flags; B->prm = *params;
     B->desc.assign(descs, descs + count);
     B->plans.resize(count);
-    int qmax = 0;
-    for (int32_t i = 0; i < count; ++i) {
+    for (int32_t i = 0; i < count; ++i)
         B->plans[i] = make_plan(dtype, descs[i].m, descs[i].n, descs[i].k, &prm[i], handle->dev.num_cu, true);
-        qmax = std::max(qmax, B->plans[i].q);
-    }
     for (int tile : {128, 96, 80, 64, 48, 32}) {
-        for (int q = qmax; q >= 0; --q) {
-            BatchGroup g;
-            g.tile = tile;
-            g.q = q;
-            for (int32_t i = 0; i < count; ++i)
-                if (B->plans[i].tile == tile && B->plans[i].q == q) g.members.push_back(i);
-            if (g.members.empty()) continue;
-            std::stable_sort(g.members.begin(), g.members.end(), [&](int a, int b) {
-                const Plan &pa = B->plans[a], &pb = B->plans[b];
-                return static_cast<double>(pa.m) * pa.n * pa.l > static_cast<double>(pb.m) * pb.n * pb.l;
-            });
-            B->groups.push_back(std::move(g));
-        }
+        BatchGroup g;
+        g.tile = tile;
+        for (int32_t i = 0; i < count; ++i)
+            if (B->plans[i].tile == tile) {
+                g.members.push_back(i);
+                g.q = std::max(g.q, B->plans[i].q);
+            }
+        if (g.members.empty()) continue;
+        for (int i : g.members) B->plans[i].qmax = g.q;
+        // most work first: passes over A times the sketch width
+        std::stable_sort(g.members.begin(), g.members.end(), [&](int a, int b) {
+            const Plan &pa = B->plans[a], &pb = B->plans[b];
+            return static_cast<double>(pa.m) * pa.n * pa.l * (pa.q + 1) >
+                   static_cast<double>(pb.m) * pb.n * pb.l * (pb.q + 1);
+        });
+        B->groups.push_back(std::move(g));
     }
     // Size the step tables with a dry recording (their size does not depend
     // on the addresses recorded in them).
@@ -434,14 +435,46 @@ namespace {
 
 const int kPChoices[3] = {5, 10, 20};
 
+int pair_cost(int k, int c) { return (2 * (c / 3) + 2) * (k + kPChoices[c % 3]); }
+
+// Pair a dominates pair b when it has at least as many power iterations and
+// at least as much oversampling.
+bool dominated(int a, int b) { return a / 3 <= b / 3 && a % 3 <= b % 3; }
+
+// Class for one matrix from the network's distribution over the cheapest
+// sufficient pair: the cheapest class c (ties: lower index) whose estimated
+// chance of sufficing, the probability mass of the pairs it dominates,
+// reaches tau; tau <= 0 takes the most probable class.
+int decide(const float* prob, int k, float tau) {
+    if (tau <= 0.0f) {
+        int best = 0;
+        for (int c = 1; c < RSVD_MLP_CLASSES; ++c) if (prob[c] > prob[best]) best = c;
+        return best;
+    }
+    int pick = -1, pick_cost = 0;
+    for (int c = 0; c < RSVD_MLP_CLASSES; ++c) {
+        double cum = 0.0;
+        for (int a = 0; a < RSVD_MLP_CLASSES; ++a) if (dominated(a, c)) cum += prob[a];
+        if (cum < tau) continue;
+        const int cost = pair_cost(k, c);
+        if (pick < 0 || cost < pick_cost) { pick = c; pick_cost = cost; }   // c ascends: ties keep the lower
+    }
+    return pick < 0 ? RSVD_MLP_CLASSES - 1 : pick;
+}
+
+// Workspace: features (count x 131 f32), probabilities (count x 15 f32),
+// then the sketch batch's own workspace.
 struct SelectLayout {
-    size_t batch_bytes = 0, feat_off = 0, cls_off = 0, bytes = 0;
+    size_t feat_off = 0, prob_off = 0, batch_off = 0, batch_bytes = 0, bytes = 0;
 };
 
 int select_plan(rsvd_handle_t handle, int32_t dtype, int32_t count, const rsvd_batch_desc* descs,
-                const rsvd_params* params, float* feat, std::vector<rsvd_batch_desc>& fd, rsvd_batch_t* b,
-                SelectLayout* lay) {
-    fd.assign(descs, descs + count);
+                const rsvd_params* params, float* feat, rsvd_batch_t* b, SelectLayout* lay) {
+    Layout L;
+    lay->feat_off = L.take(static_cast<size_t>(count) * RSVD_MLP_INPUTS * sizeof(float));
+    lay->prob_off = L.take(static_cast<size_t>(count) * RSVD_MLP_CLASSES * sizeof(float));
+    lay->batch_off = L.off;
+    std::vector<rsvd_batch_desc> fd(descs, descs + count);
     for (int32_t i = 0; i < count; ++i) {
         fd[i].features = feat ? feat + static_cast<size_t>(i) * RSVD_MLP_INPUTS
                               : reinterpret_cast<float*>(static_cast<uintptr_t>(256));
@@ -450,12 +483,8 @@ int select_plan(rsvd_handle_t handle, int32_t dtype, int32_t count, const rsvd_b
     size_t bb = 0;
     const int st = rsvd_batch_create(handle, dtype, count, fd.data(), params, RSVD_BATCH_FEATURES, b, &bb);
     if (st != RSVD_OK) return st;
-    Layout L;
-    L.take(bb);
     lay->batch_bytes = bb;
-    lay->feat_off = L.take(static_cast<size_t>(count) * RSVD_MLP_INPUTS * sizeof(float));
-    lay->cls_off = L.take(static_cast<size_t>(count) * sizeof(int32_t));
-    lay->bytes = L.off;
+    lay->bytes = lay->batch_off + bb;
     return RSVD_OK;
 }
 
@@ -465,11 +494,10 @@ extern "C" {
 
 int rsvd_select_workspace_size(rsvd_handle_t handle, int32_t dtype, int32_t count, const rsvd_batch_desc* descs,
                                const rsvd_params* params, size_t* bytes) {
-    if (!bytes) return RSVD_ERR_INVALID;
-    std::vector<rsvd_batch_desc> fd;
+    if (!bytes || !descs || count < 1) return RSVD_ERR_INVALID;
     rsvd_batch_t b = nullptr;
     SelectLayout lay;
-    const int st = select_plan(handle, dtype, count, descs, params, nullptr, fd, &b, &lay);
+    const int st = select_plan(handle, dtype, count, descs, params, nullptr, &b, &lay);
     if (st != RSVD_OK) return st;
     rsvd_batch_destroy(b);
     *bytes = lay.bytes;
@@ -477,28 +505,24 @@ int rsvd_select_workspace_size(rsvd_handle_t handle, int32_t dtype, int32_t coun
 }
 
 int rsvd_select(rsvd_handle_t handle, int32_t dtype, int32_t count, const rsvd_batch_desc* descs,
-                const rsvd_params* params, const float* theta, int32_t* q_out, int32_t* p_out,
+                const rsvd_params* params, const float* theta, float tau, int32_t* q_out, int32_t* p_out,
                 float* features_out, void* work, size_t work_bytes) {
     if (!handle || !theta || !q_out || !p_out || !work || count < 1 || !descs) return RSVD_ERR_INVALID;
     if (reinterpret_cast<uintptr_t>(work) % kAlign != 0) return RSVD_ERR_INVALID;
-    // first pass sizes the workspace, second records with the real buffers
-    std::vector<rsvd_batch_desc> fd;
-    rsvd_batch_t b = nullptr;
     SelectLayout lay;
-    int st = select_plan(handle, dtype, count, descs, params, nullptr, fd, &b, &lay);
+    float* feat_ws = at<float>(work, 0);                 // feat_off is 0
+    float* feat = features_out ? features_out : feat_ws;
+    rsvd_batch_t b = nullptr;
+    int st = select_plan(handle, dtype, count, descs, params, feat, &b, &lay);
     if (st != RSVD_OK) return st;
-    rsvd_batch_destroy(b);
-    if (work_bytes < lay.bytes) return RSVD_ERR_INVALID;
-    float* feat = features_out ? features_out : at<float>(work, lay.feat_off);
-    int32_t* cls = at<int32_t>(work, lay.cls_off);
-    st = select_plan(handle, dtype, count, descs, params, feat, fd, &b, &lay);
-    if (st != RSVD_OK) return st;
-    st = rsvd_batch_bind(b, work, lay.batch_bytes);
+    if (work_bytes < lay.bytes) { rsvd_batch_destroy(b); return RSVD_ERR_INVALID; }
+    float* prob = at<float>(work, lay.prob_off);
+    st = rsvd_batch_bind(b, static_cast<unsigned char*>(work) + lay.batch_off, lay.batch_bytes);
     if (st == RSVD_OK) st = rsvd_batch_run(b);
-    if (st == RSVD_OK) st = rsvd_mlp_forward(handle, theta, count, feat, nullptr, cls);
-    std::vector<int32_t> host(count);
+    if (st == RSVD_OK) st = rsvd_mlp_forward(handle, theta, count, feat, prob, nullptr);
+    std::vector<float> host(static_cast<size_t>(count) * RSVD_MLP_CLASSES);
     if (st == RSVD_OK) {
-        hipError_t e = hipMemcpyAsync(host.data(), cls, sizeof(int32_t) * count, hipMemcpyDeviceToHost,
+        hipError_t e = hipMemcpyAsync(host.data(), prob, sizeof(float) * host.size(), hipMemcpyDeviceToHost,
                                       handle->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(handle->stream);
         st = hip_status(handle, e);
@@ -506,7 +530,7 @@ int rsvd_select(rsvd_handle_t handle, int32_t dtype, int32_t count, const rsvd_b
     rsvd_batch_destroy(b);
     if (st != RSVD_OK) return st;
     for (int32_t i = 0; i < count; ++i) {
-        const int c = std::min(std::max(host[i], 0), RSVD_MLP_CLASSES - 1);
+        const int c = decide(host.data() + static_cast<size_t>(i) * RSVD_MLP_CLASSES, descs[i].k, tau);
         q_out[i] = c / 3;
         p_out[i] = kPChoices[c % 3];
     }

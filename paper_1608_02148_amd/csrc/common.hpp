@@ -58,6 +58,24 @@ template <> struct Mfma<double> {
 __host__ __device__ constexpr int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 __host__ __device__ constexpr int64_t rup(int64_t a, int64_t b) { return cdiv(a, b) * b; }
 
+// Optional launch condition: a kernel with a gate runs only if (*w & mask).
+struct Gate { const uint32_t* w = nullptr; uint32_t mask = 0u; };
+
+// Second status word of a solve in a batch group whose members have different
+// q (the group runs max q iterations; each member's own are switched on here):
+// bit it: iteration it runs and is not the member's last; bit 8 + it: it is the
+// last; bit 16: q = 0 (the first sketch is the last); bit 17: q > 0.
+enum : uint32_t { IT_LAST_SHIFT = 8, IT_Q0 = 1u << 16, IT_QPOS = 1u << 17 };
+
+__host__ inline uint32_t iteration_word(int q, int qmax) {
+    uint32_t w = q == 0 ? IT_Q0 : IT_QPOS;
+    for (int it = 0; it < qmax; ++it) {
+        if (it < q - 1) w |= 1u << it;
+        else if (it == q - 1) w |= 1u << (IT_LAST_SHIFT + it);
+    }
+    return w;
+}
+
 // Status word bits kept in the workspace (a superset of RSVD_FLAG_*).
 enum : uint32_t {
     ST_NEED_P2 = 1u << 16,         // pass 2 of the current orthonormalisation must run

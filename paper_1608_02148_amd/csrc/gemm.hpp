@@ -53,6 +53,8 @@ struct GemmArgs {
     const double* mu;    // optional column means of A (implicit centring)
     const uint32_t* skip_flag;  // optional: run only if (*skip_flag & skip_mask)
     uint32_t skip_mask;
+    const uint32_t* gate;       // optional second condition: run only if (*gate & gate_mask)
+    uint32_t gate_mask;
     int32_t a_vec;       // 1 when A rows allow aligned vector loads
     int32_t x_vec;       // unused (X is read with scalar loads)
 };
@@ -126,6 +128,7 @@ __device__ __forceinline__ void gemm_tile_body(const GemmArgs<TA, TX, TC>& g, in
     constexpr int KV = T::KV, SK = T::SK, KVECS = T::KVECS;
     typedef TC vec_t __attribute__((ext_vector_type(KV)));
     if (g.skip_flag && ((*g.skip_flag & g.skip_mask) == 0u)) return;
+    if (g.gate && ((*g.gate & g.gate_mask) == 0u)) return;
 
     extern __shared__ __align__(16) unsigned char smem_raw[];
     TC* As = reinterpret_cast<TC*>(smem_raw);            // [2][A_LDS]

@@ -82,6 +82,7 @@ __device__ __forceinline__ void gemm_bf16_body(const GemmArgs<TA, float, float>&
     typedef Bf16Tile<TA, MODE, SPLIT, WR, WC, WGM, WGN, BK> T;
     constexpr int SK = T::SK, OCT = T::OCT;
     if (g.skip_flag && ((*g.skip_flag & g.skip_mask) == 0u)) return;
+    if (g.gate && ((*g.gate & g.gate_mask) == 0u)) return;
 
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __bf16* lds = reinterpret_cast<__bf16*>(smem_raw);

@@ -59,7 +59,7 @@ template <typename TA, typename TX, typename TC>
 GemmArgs<TA, TX, TC> gemm_args(const TA* A, int64_t lda, int64_t rows, int64_t K, const TX* X, int64_t ldx,
                                int ncols, TC* out, int64_t ldo, int S, int64_t part_stride, const double* mu,
                                const uint32_t* skip_flag, uint32_t skip_mask, int kchunk_multiple,
-                               size_t vec_bytes) {
+                               size_t vec_bytes, Gate gate = {}) {
     GemmArgs<TA, TX, TC> g;
     g.A = A; g.lda = lda; g.rows = rows; g.K = K;
     S = S < 1 ? 1 : S;
@@ -67,6 +67,7 @@ GemmArgs<TA, TX, TC> gemm_args(const TA* A, int64_t lda, int64_t rows, int64_t K
     g.splits = S;
     g.X = X; g.ldx = ldx; g.ncols = ncols; g.out = out; g.ldo = ldo;
     g.part_stride = part_stride; g.mu = mu; g.skip_flag = skip_flag; g.skip_mask = skip_mask;
+    g.gate = gate.w; g.gate_mask = gate.mask;
     g.a_vec = (reinterpret_cast<uintptr_t>(A) % vec_bytes == 0) && ((lda * sizeof(TA)) % vec_bytes == 0);
     g.x_vec = 0;
     return g;
@@ -82,10 +83,10 @@ GemmArgs<TA, TX, TC> gemm_args(const TA* A, int64_t lda, int64_t rows, int64_t K
 template <typename TA, typename TX, typename TC, int MODE, class Ex>
 hipError_t gemm_plain(Ex& ex, int cls, bool square, const TA* A, int64_t lda, int64_t rows, int64_t K,
                       const TX* X, int64_t ldx, int ncols, TC* out, int64_t ldo, int S, int64_t part_stride,
-                      const double* mu, const uint32_t* skip_flag, uint32_t skip_mask) {
+                      const double* mu, const uint32_t* skip_flag, uint32_t skip_mask, Gate gate = {}) {
     const size_t vb = (16 / sizeof(TC)) * sizeof(TA);    // 16 / sizeof(TC) consecutive elements of A
     const auto g = gemm_args<TA, TX, TC>(A, lda, rows, K, X, ldx, ncols, out, ldo, S, part_stride, mu, skip_flag,
-                                         skip_mask, gemm_bk<TC>(), vb);
+                                         skip_mask, gemm_bk<TC>(), vb, gate);
     if (square) {
         const int sc = tile_cols(static_cast<int>(std::max<int64_t>(rows, ncols)));
         if (sc == 32) return ex.template run<GemmBody<TA, TX, TC, MODE, 1, 1, 2, 2>>(g);
@@ -116,9 +117,9 @@ hipError_t gemm_bf16_cls(Ex& ex, int tc, const GemmArgs<TA, float, float>& g) {
 template <typename TA, int MODE, class Ex>
 hipError_t gemm_bf16(Ex& ex, bool split, int cls, const TA* A, int64_t lda, int64_t rows, int64_t K,
                      const float* X, int64_t ldx, int ncols, float* out, int64_t ldo, int S, int64_t part_stride,
-                     const double* mu, const uint32_t* skip_flag, uint32_t skip_mask) {
+                     const double* mu, const uint32_t* skip_flag, uint32_t skip_mask, Gate gate = {}) {
     const auto g = gemm_args<TA, float, float>(A, lda, rows, K, X, ldx, ncols, out, ldo, S, part_stride, mu,
-                                               skip_flag, skip_mask, 64, 16);
+                                               skip_flag, skip_mask, 64, 16, gate);
     const int tc = cls ? cls : tile_cols(ncols);
     if (split) return gemm_bf16_cls<TA, MODE, true>(ex, tc, g);
     return gemm_bf16_cls<TA, MODE, false>(ex, tc, g);
@@ -129,20 +130,21 @@ hipError_t gemm_bf16(Ex& ex, bool split, int cls, const TA* A, int64_t lda, int6
 template <typename TA, typename TC, int MODE, class Ex>
 hipError_t gemm_step(Ex& ex, int arith, int cls, const TA* A, int64_t lda, int64_t rows, int64_t K,
                      const TC* X, int64_t ldx, int ncols, TC* out, int64_t ldo, int S, int64_t part_stride,
-                     const double* mu, const uint32_t* skip_flag, uint32_t skip_mask) {
+                     const double* mu, const uint32_t* skip_flag, uint32_t skip_mask, Gate gate = {}) {
     if constexpr (std::is_same<TC, float>::value) {
         if (arith != 0)
             return gemm_bf16<TA, MODE>(ex, arith == 2, cls, A, lda, rows, K, X, ldx, ncols, out, ldo, S,
-                                       part_stride, mu, skip_flag, skip_mask);
+                                       part_stride, mu, skip_flag, skip_mask, gate);
     }
     return gemm_plain<TA, TC, TC, MODE>(ex, cls, false, A, lda, rows, K, X, ldx, ncols, out, ldo, S, part_stride,
-                                        mu, skip_flag, skip_mask);
+                                        mu, skip_flag, skip_mask, gate);
 }
 
 template <typename T, class Ex>
 hipError_t reduce_step(Ex& ex, const T* part, int S, int64_t part_stride, int64_t ldp, int64_t rows, int ncols,
-                       T* out, int64_t ldo, const uint32_t* skip_flag = nullptr, uint32_t skip_mask = 0) {
-    typename ReduceBody<T>::Args a{part, S, part_stride, ldp, rows, ncols, out, ldo, skip_flag, skip_mask};
+                       T* out, int64_t ldo, const uint32_t* skip_flag = nullptr, uint32_t skip_mask = 0,
+                       Gate gate = {}) {
+    typename ReduceBody<T>::Args a{part, S, part_stride, ldp, rows, ncols, out, ldo, skip_flag, skip_mask, gate};
     return ex.template run<ReduceBody<T>>(a);
 }
 

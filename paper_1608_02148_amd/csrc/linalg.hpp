@@ -21,14 +21,15 @@ namespace rsvd {
 
 // Status words are cleared by a kernel rather than a memset node, so the whole
 // launch sequence stays safe to capture in a HIP graph.
+// p[0] = 0 and, when count = 2, p[1] = v1 (the iteration word).
 struct ClearBody {
-    struct Args { uint32_t* p; int count; };
+    struct Args { uint32_t* p; int count; uint32_t v1; };
     static constexpr int THREADS = 64;
     static int blocks(const Args& a) { return static_cast<int>(cdiv(a.count, THREADS)); }
     static size_t lds(const Args&) { return 0; }
     static __device__ void run(const Args& a, int b) {
         const int i = b * THREADS + threadIdx.x;
-        if (i < a.count) a.p[i] = 0u;
+        if (i < a.count) a.p[i] = (i == 1) ? a.v1 : 0u;
     }
 };
 
@@ -51,12 +52,14 @@ struct ReduceBody {
     struct Args {
         const T* part; int S; int64_t part_stride; int64_t ldp; int64_t rows; int ncols;
         T* out; int64_t ldo; const uint32_t* skip_flag; uint32_t skip_mask;
+        Gate gate;
     };
     static constexpr int THREADS = 256;
     static int blocks(const Args& a) { return static_cast<int>(cdiv(a.rows * a.ncols, THREADS)); }
     static size_t lds(const Args&) { return 0; }
     static __device__ void run(const Args& a, int b) {
         if (a.skip_flag && ((*a.skip_flag & a.skip_mask) == 0u)) return;
+        if (a.gate.w && ((*a.gate.w & a.gate.mask) == 0u)) return;
         const int64_t idx = static_cast<int64_t>(b) * THREADS + threadIdx.x;
         const int64_t r = idx / a.ncols;
         const int c = static_cast<int>(idx - r * a.ncols);
@@ -164,6 +167,7 @@ struct CholArgs {
     int pass;                 // 1, 2 or 3
     int skip_unless_pending;  // skip unless this pass was requested (ST_NEED_P2 / P3)
     int adaptive;             // pass 1 may leave out pass 2 (see above)
+    Gate gate;                // optional: the whole kernel runs only if the gate is open
 };
 
 constexpr int CHOL_MAX_L = RSVD_MAX_L;
@@ -180,6 +184,7 @@ __device__ __forceinline__ void chol_body(const CholArgs& a) {
     const int tx = tid % CT_TX, ty = tid / CT_TX;
     const int a0 = CT_R * ty, b0 = CT_C * tx;
     const uint32_t need_bit = (a.pass == 2) ? ST_NEED_P2 : ST_NEED_P3;
+    if (a.gate.w && ((*a.gate.w & a.gate.mask) == 0u)) return;
     if (a.skip_unless_pending && ((*a.status & need_bit) == 0u)) {
         if (a.rout)
             for (int i = 0; i < CT_R; ++i)

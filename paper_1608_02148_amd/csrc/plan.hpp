@@ -64,6 +64,8 @@ struct Plan {
     int64_t m = 0, n = 0;
     int k = 0, p = 0, q = 0, l = 0, Lp = 0, kp = 0;
     int tile = 0;       // column class of the tall product tiles (tile_class of l)
+    int qmax = 0;       // gated: power iterations issued for the whole batch group
+    bool gated = false; // batch member: iterations beyond q switched off on the device
     Splits sp{};
     size_t Y = 0, Z = 0, Om = 0, part = 0, gram = 0, rinv = 0, racc = 0, sigma = 0,
            xv = 0, xu = 0, jk = 0, wks = 0, vtmp = 0, mu = 0, mupart = 0, status = 0, bytes = 0;
@@ -94,6 +96,8 @@ inline Plan make_plan(int dtype, int64_t m, int64_t n, int k, const rsvd_params*
     P.Lp = tile_cols(P.l);
     P.kp = tile_cols(k);
     P.tile = tile_class(P.l, dtype != RSVD_F64);
+    P.qmax = P.q;
+    P.gated = batch;
     P.sp = batch ? Splits{1, 1, 1, 1} : make_splits(m, n, num_cu);
     const size_t cs = comp_size(dtype);
     Layout L;

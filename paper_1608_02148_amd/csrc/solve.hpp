@@ -10,23 +10,24 @@ namespace rsvd {
 template <typename TC, class Ex>
 hipError_t orthonormalize(Ex& ex, int tile, TC* M, int64_t ldm, int64_t rows, int l, int Lp, int S,
                           double* part, double* gram, TC* rinv, double* rfac, uint32_t* status,
-                          bool adaptive = false) {
+                          bool adaptive = false, Gate gate = {}) {
     for (int pass = 1; pass <= 3; ++pass) {
         const bool conditional = (pass == 3) || (pass == 2 && adaptive);
         const uint32_t* skip = conditional ? status : nullptr;
         const uint32_t need = (pass == 2) ? ST_NEED_P2 : ST_NEED_P3;
         RSVD_TRY((gemm_plain<TC, TC, double, MODE_TN>(ex, 0, true, M, ldm, l, rows, M, ldm, l, part, Lp, S,
-                                                      static_cast<int64_t>(Lp) * Lp, nullptr, skip, need)));
+                                                      static_cast<int64_t>(Lp) * Lp, nullptr, skip, need, gate)));
         if (S > 1) RSVD_TRY(reduce_step<double>(ex, part, S, static_cast<int64_t>(Lp) * Lp, Lp, l, l, gram, Lp,
-                                                skip, need));
+                                                skip, need, gate));
         CholArgs ca;
         ca.part = (S > 1) ? gram : part; ca.S = 1; ca.part_stride = 0; ca.ldp = Lp;
         ca.l = l; ca.mrows = rows; ca.rinv = rinv; ca.ldr = Lp;
         ca.rout = rfac ? rfac + static_cast<size_t>(pass - 1) * l * l : nullptr;
         ca.status = status; ca.pass = pass; ca.skip_unless_pending = conditional; ca.adaptive = adaptive;
+        ca.gate = gate;
         RSVD_TRY(ex.template run<CholBody<TC>>(ca));
         RSVD_TRY((gemm_plain<TC, TC, TC, MODE_NN>(ex, tile, false, M, ldm, rows, l, rinv, Lp, l, M, ldm, 1, 0, nullptr,
-                                                  skip, need)));
+                                                  skip, need, gate)));
     }
     if (rfac) {   // R = R3 (R2 R1); the product R2 R1 goes through the gram scratch
         const size_t ll = static_cast<size_t>(l) * l;
@@ -87,8 +88,13 @@ hipError_t solve_steps(Ex& ex, rsvd_handle_t prof, const Plan& P, const TA* A, i
     double* jk = at<double>(work, P.jk);
     double* mu = o.center ? at<double>(work, P.mu) : nullptr;
 
+    // Batch members run their group's qmax iterations with the ones beyond
+    // their own q switched off by the iteration word (status[1]).
+    const bool gated = P.gated;
+    const int qmax = gated ? P.qmax : P.q;
+    const uint32_t* itw = status + 1;
     if (o.stamps) RSVD_TRY(ex.template run<StampBody>(StampBody::Args{o.stamps}));
-    RSVD_TRY(ex.template run<ClearBody>(ClearBody::Args{status, 1}));
+    RSVD_TRY(ex.template run<ClearBody>(ClearBody::Args{status, gated ? 2 : 1, iteration_word(P.q, qmax)}));
 
     if (mu) {   // column means (implicit centring, Sec. 4.2)
         const int S = P.sp.colsum;
@@ -109,18 +115,38 @@ hipError_t solve_steps(Ex& ex, rsvd_handle_t prof, const Plan& P, const TA* A, i
     // and the projection (precision escalation).
     const bool mixed = prm->precision == RSVD_PREC_BF16_MIXED;
     const int early = mixed ? 1 : 0, late = mixed ? 2 : 0;
-    auto ax = [&](const TC* X, int arith) -> hipError_t {     // Y (m x Lp) = A X
+    auto ax = [&](const TC* X, int arith, Gate gt) -> hipError_t {     // Y (m x Lp) = A X
         return timed(prof, 0, pass_flops, nn_bytes, [&] {
             return gemm_step<TA, TC, MODE_NN>(ex, arith, tile, A, lda, m, n, X, Lp, l, Y, Lp, 1, 0, mu, nullptr,
-                                              0);
+                                              0, gt);
         });
     };
-    RSVD_TRY(ax(Om, P.q == 0 ? late : early));
+    // The last sketch of a member (after its q-th iteration) uses the late
+    // arithmetic; with gates both variants are issued and the iteration word
+    // picks one per member.
+    auto ax_step = [&](const TC* X, bool last_if_ungated, uint32_t early_bit, uint32_t late_bit) -> hipError_t {
+        if (!gated) return ax(X, last_if_ungated ? late : early, Gate{});
+        if (early == late) return ax(X, early, Gate{itw, early_bit | late_bit});
+        RSVD_TRY(ax(X, early, Gate{itw, early_bit}));
+        return ax(X, late, Gate{itw, late_bit});
+    };
+    RSVD_TRY(ax_step(Om, P.q == 0, IT_QPOS, IT_Q0));
 
-    if (o.features) {   // selector inputs: singular values of the sketch via its R factor
-        RSVD_TRY(orthonormalize<TC>(ex, tile, Y, Lp, m, l, Lp, P.sp.gram_m, partd, gram, rinv, racc, status));
+    if (o.features) {
+        // Selector inputs: the singular values of the sketch are those of the
+        // Cholesky factor R of its f64 Gram matrix (one pass; the features
+        // only need the spectrum, not an orthonormal basis).
+        const int S = P.sp.gram_m;
+        RSVD_TRY((gemm_plain<TC, TC, double, MODE_TN>(ex, 0, true, Y, Lp, l, m, Y, Lp, l, partd, Lp, S,
+                                                      static_cast<int64_t>(Lp) * Lp, nullptr, nullptr, 0)));
+        if (S > 1) RSVD_TRY(reduce_step<double>(ex, partd, S, static_cast<int64_t>(Lp) * Lp, Lp, l, l, gram, Lp));
+        CholArgs ca;
+        ca.part = (S > 1) ? gram : partd; ca.S = 1; ca.part_stride = 0; ca.ldp = Lp;
+        ca.l = l; ca.mrows = m; ca.rinv = rinv; ca.ldr = Lp; ca.rout = racc;
+        ca.status = status; ca.pass = 1; ca.skip_unless_pending = 0; ca.adaptive = 0;
+        RSVD_TRY(ex.template run<CholBody<TC>>(ca));
         JacobiArgs ja;
-        ja.R = racc + 3 * static_cast<size_t>(l) * l; ja.ldr = l; ja.l = l; ja.k = 1;
+        ja.R = racc; ja.ldr = l; ja.l = l; ja.k = 1;
         ja.sigma = sigma; ja.xv = xv; ja.ldx = Lp; ja.xcols = P.kp; ja.wks = at<double>(work, P.wks);
         ja.status = status; ja.max_sweeps = 60; ja.tol = jacobi_tol(ja.l);
         RSVD_TRY(ex.template run<JacobiBody<TC>>(ja));
@@ -129,32 +155,34 @@ hipError_t solve_steps(Ex& ex, rsvd_handle_t prof, const Plan& P, const TA* A, i
         return hipSuccess;
     }
 
-    auto aty = [&](TC* dst, int arith) -> hipError_t {     // dst (n x Lp) = A^T Y
+    auto aty = [&](TC* dst, int arith, Gate gt) -> hipError_t {     // dst (n x Lp) = A^T Y
         const int S = P.sp.tn;
         if (S == 1)
             return timed(prof, 1, pass_flops, tn_bytes, [&] {
                 return gemm_step<TA, TC, MODE_TN>(ex, arith, tile, A, lda, n, m, Y, Lp, l, dst, Lp, 1, 0, mu,
-                                                  nullptr, 0);
+                                                  nullptr, 0, gt);
             });
         RSVD_TRY(timed(prof, 1, pass_flops, tn_bytes, [&] {
             return gemm_step<TA, TC, MODE_TN>(ex, arith, tile, A, lda, n, m, Y, Lp, l, partc, Lp, S,
-                                              static_cast<int64_t>(n) * Lp, mu, nullptr, 0);
+                                              static_cast<int64_t>(n) * Lp, mu, nullptr, 0, gt);
         }));
-        return reduce_step<TC>(ex, partc, S, static_cast<int64_t>(n) * Lp, Lp, n, l, dst, Lp);
+        return reduce_step<TC>(ex, partc, S, static_cast<int64_t>(n) * Lp, Lp, n, l, dst, Lp, nullptr, 0, gt);
     };
 
     // Alg. subspace_iter: q rounds of orth(Y); Z = orth(A^T Y); Y = A Z.
-    for (int it = 0; it < P.q; ++it) {
+    for (int it = 0; it < qmax; ++it) {
+        const uint32_t run_bit = 1u << it, last_bit = 1u << (IT_LAST_SHIFT + it);
+        const Gate act = gated ? Gate{itw, run_bit | last_bit} : Gate{};
         RSVD_TRY(orthonormalize<TC>(ex, tile, Y, Lp, m, l, Lp, P.sp.gram_m, partd, gram, rinv, nullptr, status,
-                                    true));
-        RSVD_TRY(aty(Z, early));
+                                    true, act));
+        RSVD_TRY(aty(Z, early, act));
         RSVD_TRY(orthonormalize<TC>(ex, tile, Z, Lp, n, l, Lp, P.sp.gram_n, partd, gram, rinv, nullptr, status,
-                                    true));
-        RSVD_TRY(ax(Z, it == P.q - 1 ? late : early));
+                                    true, act));
+        RSVD_TRY(ax_step(Z, it == P.q - 1, run_bit, last_bit));
     }
     // Alg. rqb steps 9-10: Q = qr(Y); B^T = A^T Q.
     RSVD_TRY(orthonormalize<TC>(ex, tile, Y, Lp, m, l, Lp, P.sp.gram_m, partd, gram, rinv, nullptr, status));
-    RSVD_TRY(aty(Z, late));
+    RSVD_TRY(aty(Z, late, Gate{}));
     // svd(B): B^T = Q_b R_b (Q_b overwrites Z), R_b = W S J^T by Jacobi.
     RSVD_TRY(orthonormalize<TC>(ex, tile, Z, Lp, n, l, Lp, P.sp.gram_n, partd, gram, rinv, racc, status));
     racc += 3 * static_cast<size_t>(l) * l;       // R_b = R3 R2 R1

@@ -261,11 +261,7 @@ def choose(theta, As, ks, seed=2148, precision="plain", tau=DEFAULT_TAU):
     n = len(As)
     if theta is None:
         return np.full(n, FALLBACK_Q, dtype=np.int32), np.full(n, 10, dtype=np.int32)
-    _, _, F = api.select(As, ks, theta, seed=seed, precision=precision)
-    prob, _ = api.mlp_forward(theta, F)
-    pick = decide(prob.cpu().numpy(), ks, tau)
-    qs = np.array([CLASS_PAIRS[c][0] for c in pick], dtype=np.int32)
-    ps = np.array([CLASS_PAIRS[c][1] for c in pick], dtype=np.int32)
+    qs, ps, _ = api.select(As, ks, theta, seed=seed, precision=precision, tau=tau)
     return qs, ps
 
 

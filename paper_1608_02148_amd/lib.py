@@ -81,8 +81,8 @@ _PROTOS = {
     "rsvd_batch_stamps": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "rsvd_batch_destroy": (c_int32, [c_void_p]),
     "rsvd_select_workspace_size": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p]),
-    "rsvd_select": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
-                              c_void_p, c_void_p, c_size_t]),
+    "rsvd_select": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p, ctypes.c_float, c_void_p,
+                              c_void_p, c_void_p, c_void_p, c_size_t]),
     "rsvd_mlp_workspace_size": (c_int32, [c_int32, c_void_p]),
     "rsvd_mlp_init": (c_int32, [c_void_p, c_void_p, c_uint64]),
     "rsvd_mlp_forward": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),

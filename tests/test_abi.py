@@ -229,5 +229,5 @@ def test_select_workspace_is_host_only(lib, handle):
     assert lib.rsvd_select_workspace_size(handle, L.RSVD_F32, 2, _descs(shapes), ctypes.byref(prm),
                                           ctypes.byref(nbytes)) == 0
     assert nbytes.value >= 2 * 131 * 4
-    assert lib.rsvd_select(handle, L.RSVD_F32, 2, _descs(shapes), ctypes.byref(prm), None, None, None, None,
-                           ctypes.c_void_p(256), nbytes.value) == -1
+    assert lib.rsvd_select(handle, L.RSVD_F32, 2, _descs(shapes), ctypes.byref(prm), None, 0.8, None, None,
+                           None, ctypes.c_void_p(256), nbytes.value) == -1

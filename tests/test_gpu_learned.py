@@ -83,3 +83,16 @@ def test_select_picks_network_argmax():
     # the features it used are the sketch features
     for b, (A, k) in enumerate(zip(As, ks)):
         np.testing.assert_allclose(F[b], lrn.features(_np(A), k, seed=17, stream_id=b), rtol=0, atol=2e-5)
+
+
+def test_select_decision_rule_matches_host_rule():
+    from paper_1608_02148_amd import api
+    from paper_1608_02148_amd import learned as L
+    As = _mats(torch.float32, 90)
+    ks = [k for _, _, k in SHAPES]
+    theta, _ = L.load_checkpoint(device=DEV)
+    for tau in (0.5, 0.8, 0.95):
+        qs, ps, feats = api.select(As, ks, theta, seed=4, tau=tau)
+        prob, _ = api.mlp_forward(theta, feats)
+        pick = L.decide(prob.cpu().numpy(), ks, tau)
+        assert [(int(q), int(p)) for q, p in zip(qs, ps)] == [L.CLASS_PAIRS[c] for c in pick]
