@@ -38,6 +38,27 @@ PEAKS = {  # MI355X published dense peaks
 }
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_c2_f32_traffic.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1608_02148_amd", "csrc", f) for f in ("gemm.hpp", "exec.hpp", "launch.hpp")]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the f32 products from the committed counter
+    runs, or {} when the kernel sources changed since they were taken."""
+    import hashlib
+    import re
+    if not os.path.exists(TRAFFIC_FILE):
+        return {}
+    text = open(TRAFFIC_FILE).read()
+    vals = dict(re.findall(r"^(\w+): (\S+)$", text, flags=re.M))
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    if vals.get("kernel_sources_sha256") != h.hexdigest()[:16]:
+        return {}
+    return {"AT_Q": float(vals["AT_Q_hbm_bytes"]), "A_X": float(vals["A_X_hbm_bytes"])}
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -190,8 +211,14 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-only", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-bf16-arm", action="store_true")
+    ap.add_argument("--gaussian-fill", action="store_true",
+                    help="fill A with Gaussian entries instead of the planted matrix (for hardware-counter runs: "
+                         "a kernel's memory traffic depends on the shapes, not the values)")
     ap.add_argument("--learned-only", action="store_true")
     ap.add_argument("--learned-count", type=int, default=2048)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 1 GiB device copy (reference for hardware byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -206,6 +233,15 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.copy_calibration:
+        # a plain streaming kernel of known traffic: dst = -src over 1 GiB
+        # (reads 1 GiB, writes 1 GiB per launch)
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     if args.batched_only:
         print(json.dumps({"batched": batched_arm(args.steps, args.warmup)}), flush=True)
         return
@@ -213,8 +249,14 @@ def main():
         print(json.dumps({"learned": learned_arm(args.learned_count)}), flush=True)
         return
     m, n, k, p, q = args.m, args.n, args.k, args.p, args.q
-    log(f"generating A {m}x{n} float32 (planted exp(-i/50) spectrum + noise floor)")
-    A = syn.c2_matrix(device=dev, m=m, n=n)
+    if args.gaussian_fill:
+        log(f"filling A {m}x{n} float32 with Gaussian entries")
+        g = torch.Generator(device=dev)
+        g.manual_seed(5000)
+        A = torch.randn(m, n, generator=g, device=dev, dtype=torch.float32)
+    else:
+        log(f"generating A {m}x{n} float32 (planted exp(-i/50) spectrum + noise floor)")
+        A = syn.c2_matrix(device=dev, m=m, n=n)
     torch.cuda.synchronize()
     l = min(k + p, m, n)
     sig = syn.c2_sigma()
@@ -257,21 +299,29 @@ def main():
 
     flops = (2 * q + 2) * 2.0 * m * n * l
 
+    traffic_of = measured_traffic() if (m, n, k, p, q) == (100000, 5000, 100, 20, 2) else {}
+
     def roofline_of(prof, bound):
         dom_name = max(prof, key=lambda kname: prof[kname]["total_ms"])
         d = prof[dom_name]
         cnt = max(d["count"], 1)
         avg_ms = d["total_ms"] / cnt
-        kern = "gemm_tile_kernel" if bound == "mfma" else "gemm_bf16_kernel"
-        kern += " A^T Q" if dom_name == "AT_Q" else " A X"
+        mode = 1 if dom_name == "AT_Q" else 0
+        if bound == "mfma":
+            kern = f"single_kernel<GemmBody<float, float, float, {mode}, 4, 4, 2, 2>>"
+        else:
+            kern = f"single_kernel<Bf16Body<float, {mode}, false, 4, 4, 2, 2>>"
+        kern += " (A^T Q)" if dom_name == "AT_Q" else " (A X)"
         if bound == "mfma":
             achieved = d["flops"] / cnt / (avg_ms / 1000.0) / 1e12
             peak, unit = PEAKS["f32_mfma_tflops"], "TFLOP/s"
         else:
             achieved = d["bytes"] / cnt / (avg_ms / 1000.0) / 1e9
             peak, unit = PEAKS["hbm_gbs"], "GB/s"
+        traffic = traffic_of.get(dom_name) if bound == "mfma" else None
         return {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
-                "frac": round(achieved / peak, 4), "traffic": None, "kernel": kern,
+                "frac": round(achieved / peak, 4), "traffic": traffic,
+                "traffic_unit": "bytes per launch (HBM, counter-calibrated)", "kernel": kern,
                 "avg_launch_ms": round(avg_ms, 4), "launches": d["count"],
                 "other_kernel_avg_ms": {kname: round(v["total_ms"] / max(v["count"], 1), 4)
                                         for kname, v in prof.items() if kname != dom_name}}
@@ -279,10 +329,12 @@ def main():
     ms, prof, err, _ = run_arm("plain")
     tflops = flops / (ms / 1000.0) / 1e12
     roofline = roofline_of(prof, "mfma")
-    ms_bf, prof_bf, err_bf, _ = run_arm("bf16_mixed")
-    bf16_arm = {"ms_per_step": round(ms_bf, 4), "value": round(flops / (ms_bf / 1000.0) / 1e12, 3),
-                "unit": "TFLOP/s (same algorithmic flops)", "excess_err_spectral": round(err_bf, 6),
-                "speedup_vs_f32_plain": round(ms / ms_bf, 3), "roofline": roofline_of(prof_bf, "hbm")}
+    bf16_arm = None
+    if not args.no_bf16_arm:
+        ms_bf, prof_bf, err_bf, _ = run_arm("bf16_mixed")
+        bf16_arm = {"ms_per_step": round(ms_bf, 4), "value": round(flops / (ms_bf / 1000.0) / 1e12, 3),
+                    "unit": "TFLOP/s (same algorithmic flops)", "excess_err_spectral": round(err_bf, 6),
+                    "speedup_vs_f32_plain": round(ms / ms_bf, 3), "roofline": roofline_of(prof_bf, "hbm")}
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -18,15 +18,27 @@
 
 namespace rsvd {
 
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2): hardware block b runs on XCD b % 8.  The logical index gives each XCD
+// one contiguous range of logical blocks, so the tiles that share an operand
+// chunk (the row tiles of one split, the tiles of one problem) share an L2.
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ int xcd_block(int b, int total) {
+    const int xcd = b % kXcds, slot = b / kXcds;
+    const int per = total / kXcds, rem = total % kXcds;
+    return xcd < rem ? xcd * (per + 1) + slot : rem * (per + 1) + (xcd - rem) * per + slot;
+}
+
 template <class Body>
 __global__ __launch_bounds__(Body::THREADS) void single_kernel(typename Body::Args a) {
-    Body::run(a, blockIdx.x);
+    Body::run(a, xcd_block(blockIdx.x, gridDim.x));
 }
 
 template <class Body>
 __global__ __launch_bounds__(Body::THREADS) void grouped_kernel(const typename Body::Args* args, const int* prefix,
                                                                int nprob) {
-    const int t = blockIdx.x;
+    const int t = xcd_block(blockIdx.x, gridDim.x);
     int lo = 0, hi = nprob;               // largest lo with prefix[lo] <= t
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
