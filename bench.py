@@ -300,6 +300,8 @@ def main():
     flops = (2 * q + 2) * 2.0 * m * n * l
 
     traffic_of = measured_traffic() if (m, n, k, p, q) == (100000, 5000, 100, 20, 2) else {}
+    from paper_1608_02148_amd import autotune
+    api_variants = autotune.get_variants(dev)
 
     def roofline_of(prof, bound):
         dom_name = max(prof, key=lambda kname: prof[kname]["total_ms"])
@@ -308,7 +310,9 @@ def main():
         avg_ms = d["total_ms"] / cnt
         mode = 1 if dom_name == "AT_Q" else 0
         if bound == "mfma":
-            kern = f"single_kernel<GemmBody<float, float, float, {mode}, 4, 4, 2, 2>>"
+            var = api_variants[6 * mode + 5]
+            shape = {0: "4, 4, 2, 2", 1: "4, 2, 2, 4", 2: "2, 2, 4, 4"}[var]
+            kern = f"single_kernel<GemmBody<float, float, float, {mode}, {shape}>>"
         else:
             kern = f"single_kernel<Bf16Body<float, {mode}, false, 4, 4, 2, 2>>"
         kern += " (A^T Q)" if dom_name == "AT_Q" else " (A X)"

@@ -105,6 +105,16 @@ int rsvd_create(rsvd_handle_t* handle, void* hip_stream);
 int rsvd_destroy(rsvd_handle_t handle);
 int rsvd_set_stream(rsvd_handle_t handle, void* hip_stream);
 int rsvd_last_hip_error(rsvd_handle_t handle);
+/* Tile variants of the f32-compute products, one per (mode, column class):
+ * variants[0..5] for Y = A X and variants[6..11] for Z = A^T Q, classes
+ * 32, 48, 64, 80, 96, 128 columns (the class of a solve is the smallest that
+ * holds l).  0 = 4 waves per workgroup, 1 = 8 waves, 2 = 16 waves over the
+ * same 128 x class output tile.  Results do not depend on the variant (the
+ * reduction order per output element is the same); only the speed does.
+ * Plans made after the call use the new table; an autotuner that times the
+ * variants writes the table the Python binding applies. */
+int rsvd_set_tile_variants(rsvd_handle_t handle, const int32_t* variants);
+int rsvd_get_tile_variants(rsvd_handle_t handle, int32_t* variants);
 const char* rsvd_status_string(int status);
 
 /* Workspace bytes needed by rsvd_run / rpca_run for this problem.

@@ -26,10 +26,29 @@ def handle(device=None):
         with torch.cuda.device(idx):
             L.check(lib.rsvd_create(ctypes.byref(h), None), "rsvd_create")
         _handles[idx] = h
+        _apply_tuned_variants(lib, h, idx)
     with torch.cuda.device(idx):
         stream = torch.cuda.current_stream(idx).cuda_stream
     L.check(lib.rsvd_set_stream(h, ctypes.c_void_p(stream)), "rsvd_set_stream")
     return h
+
+
+def _apply_tuned_variants(lib, h, idx):
+    """Apply the autotuned tile variants for this GPU's architecture, if the
+    cache (paper_1608_02148_amd/tile_variants.json or $RSVD_TILE_VARIANTS)
+    has an entry for it; otherwise the library's defaults stay."""
+    import json
+    import os
+    path = os.environ.get("RSVD_TILE_VARIANTS",
+                          os.path.join(os.path.dirname(os.path.abspath(__file__)), "tile_variants.json"))
+    try:
+        arch = torch.cuda.get_device_properties(idx).gcnArchName.split(":")[0]
+        table = json.load(open(path))[arch]["f32"]
+        if len(table) == 12:
+            v = (ctypes.c_int32 * 12)(*[int(x) for x in table])
+            lib.rsvd_set_tile_variants(h, v)
+    except (OSError, KeyError, ValueError, TypeError):
+        pass
 
 
 def make_params(p=10, q=2, seed=0, stream_id=0, sdist="normal", precision="plain"):

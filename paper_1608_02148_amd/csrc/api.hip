@@ -73,6 +73,20 @@ int rsvd_set_stream(rsvd_handle_t handle, void* hip_stream) {
 
 int rsvd_last_hip_error(rsvd_handle_t handle) { return handle ? handle->last_hip_error : 0; }
 
+int rsvd_set_tile_variants(rsvd_handle_t handle, const int32_t* variants) {
+    if (!handle || !variants) return RSVD_ERR_INVALID;
+    for (int i = 0; i < 12; ++i)
+        if (variants[i] < 0 || variants[i] > 2) return RSVD_ERR_INVALID;
+    for (int i = 0; i < 12; ++i) handle->variants[i] = variants[i];
+    return RSVD_OK;
+}
+
+int rsvd_get_tile_variants(rsvd_handle_t handle, int32_t* variants) {
+    if (!handle || !variants) return RSVD_ERR_INVALID;
+    for (int i = 0; i < 12; ++i) variants[i] = handle->variants[i];
+    return RSVD_OK;
+}
+
 const char* rsvd_status_string(int status) {
     switch (status) {
         case RSVD_OK: return "ok";
@@ -102,7 +116,7 @@ static int check_common(rsvd_handle_t handle, int32_t dtype, int64_t m, int64_t 
     if (v != RSVD_OK) return v;
     if (!A || lda < n || !work) return RSVD_ERR_INVALID;
     if (reinterpret_cast<uintptr_t>(work) % kAlign != 0) return RSVD_ERR_INVALID;
-    *plan = make_plan(dtype, m, n, k, params, handle->dev.num_cu);
+    *plan = make_plan(dtype, m, n, k, params, handle->dev.num_cu, false, handle->variants);
     if (work_bytes < plan->bytes) return RSVD_ERR_INVALID;
     return RSVD_OK;
 }
@@ -327,7 +341,8 @@ int rsvd_batch_create(rsvd_handle_t handle, int32_t dtype, int32_t count, const 
     B->desc.assign(descs, descs + count);
     B->plans.resize(count);
     for (int32_t i = 0; i < count; ++i)
-        B->plans[i] = make_plan(dtype, descs[i].m, descs[i].n, descs[i].k, &prm[i], handle->dev.num_cu, true);
+        B->plans[i] = make_plan(dtype, descs[i].m, descs[i].n, descs[i].k, &prm[i], handle->dev.num_cu, true,
+                                handle->variants);
     for (int tile : {128, 96, 80, 64, 48, 32}) {
         BatchGroup g;
         g.tile = tile;

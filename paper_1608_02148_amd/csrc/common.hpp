@@ -109,4 +109,7 @@ struct rsvd_handle_s {
     std::vector<rsvd::ProfRecord> prof;        // recorded intervals
     std::vector<hipEvent_t> event_pool;        // reusable events
     size_t pool_used = 0;
+    // f32 tall-tile variant per (mode, column class): NN 32..128, then TN
+    // (rsvd_set_tile_variants; defaults measured at 100000 x 5000, l = 120)
+    int variants[12] = {0, 0, 0, 0, 0, 1, 0, 0, 0, 0, 0, 2};
 };

@@ -19,9 +19,11 @@
 namespace rsvd {
 
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
-// L2): hardware block b runs on XCD b % 8.  The logical index gives each XCD
-// one contiguous range of logical blocks, so the tiles that share an operand
-// chunk (the row tiles of one split, the tiles of one problem) share an L2.
+// L2): hardware block b runs on XCD b % 8.  For one product the logical index
+// gives each XCD one contiguous range of tiles, so the row tiles of one split
+// (which read the same chunk of the skinny operand) share an L2.  Grouped
+// launches keep the round-robin order: their blocks are sorted by problem
+// size, and contiguous ranges would give one XCD all the largest problems.
 constexpr int kXcds = 8;
 
 __device__ __forceinline__ int xcd_block(int b, int total) {
@@ -38,7 +40,7 @@ __global__ __launch_bounds__(Body::THREADS) void single_kernel(typename Body::Ar
 template <class Body>
 __global__ __launch_bounds__(Body::THREADS) void grouped_kernel(const typename Body::Args* args, const int* prefix,
                                                                int nprob) {
-    const int t = xcd_block(blockIdx.x, gridDim.x);
+    const int t = blockIdx.x;
     int lo = 0, hi = nprob;               // largest lo with prefix[lo] <= t
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;

@@ -80,6 +80,38 @@ GemmArgs<TA, TX, TC> gemm_args(const TA* A, int64_t lda, int64_t rows, int64_t K
 // (BM = NC = 32, 64 or 128) for products with at most that many output rows:
 // Gram matrices and the l x l factors.  cls = 0 picks the tall class from
 // ncols; a grouped batch step passes one class for all of its problems.
+// Tall f32 tiles come in up to three variants per column class: 0 = 4 waves,
+// 1 = 8 waves, 2 = 16 waves over the same 128 x NC output tile (more waves
+// hide more latency, fewer keep more operands per wave); `cls` carries the
+// variant in its upper 16 bits (the plan's autotuned choice).
+template <typename TA, typename TX, typename TC, int MODE, class Ex>
+hipError_t gemm_tall_f32(Ex& ex, int tc, int var, const GemmArgs<TA, TX, TC>& g) {
+    switch (tc) {
+        case 32:
+            if (var == 1) return ex.template run<GemmBody<TA, TX, TC, MODE, 2, 1, 4, 2>>(g);
+            if (var == 2) return ex.template run<GemmBody<TA, TX, TC, MODE, 1, 1, 8, 2>>(g);
+            return ex.template run<GemmBody<TA, TX, TC, MODE, 2, 2, 4, 1>>(g);
+        case 48:
+            if (var != 0) return ex.template run<GemmBody<TA, TX, TC, MODE, 1, 3, 8, 1>>(g);
+            return ex.template run<GemmBody<TA, TX, TC, MODE, 2, 3, 4, 1>>(g);
+        case 64:
+            if (var == 1) return ex.template run<GemmBody<TA, TX, TC, MODE, 4, 1, 2, 4>>(g);
+            if (var == 2) return ex.template run<GemmBody<TA, TX, TC, MODE, 2, 1, 4, 4>>(g);
+            return ex.template run<GemmBody<TA, TX, TC, MODE, 4, 2, 2, 2>>(g);
+        case 80:
+            if (var != 0) return ex.template run<GemmBody<TA, TX, TC, MODE, 1, 5, 8, 1>>(g);
+            return ex.template run<GemmBody<TA, TX, TC, MODE, 2, 5, 4, 1>>(g);
+        case 96:
+            if (var == 1) return ex.template run<GemmBody<TA, TX, TC, MODE, 2, 3, 4, 2>>(g);
+            if (var == 2) return ex.template run<GemmBody<TA, TX, TC, MODE, 1, 3, 8, 2>>(g);
+            return ex.template run<GemmBody<TA, TX, TC, MODE, 4, 3, 2, 2>>(g);
+        default:
+            if (var == 1) return ex.template run<GemmBody<TA, TX, TC, MODE, 4, 2, 2, 4>>(g);
+            if (var == 2) return ex.template run<GemmBody<TA, TX, TC, MODE, 2, 2, 4, 4>>(g);
+            return ex.template run<GemmBody<TA, TX, TC, MODE, 4, 4, 2, 2>>(g);
+    }
+}
+
 template <typename TA, typename TX, typename TC, int MODE, class Ex>
 hipError_t gemm_plain(Ex& ex, int cls, bool square, const TA* A, int64_t lda, int64_t rows, int64_t K,
                       const TX* X, int64_t ldx, int ncols, TC* out, int64_t ldo, int S, int64_t part_stride,
@@ -93,12 +125,8 @@ hipError_t gemm_plain(Ex& ex, int cls, bool square, const TA* A, int64_t lda, in
         if (sc == 64) return ex.template run<GemmBody<TA, TX, TC, MODE, 2, 2, 2, 2>>(g);
         return ex.template run<GemmBody<TA, TX, TC, MODE, 4, 4, 2, 2>>(g);
     }
-    const int tc = cls ? cls : tile_cols(ncols);
-    if constexpr (sizeof(TC) == 4) {
-        if (tc == 48) return ex.template run<GemmBody<TA, TX, TC, MODE, 2, 3, 4, 1>>(g);
-        if (tc == 80) return ex.template run<GemmBody<TA, TX, TC, MODE, 2, 5, 4, 1>>(g);
-        if (tc == 96) return ex.template run<GemmBody<TA, TX, TC, MODE, 4, 3, 2, 2>>(g);
-    }
+    const int tc = (cls & 0xFFFF) ? (cls & 0xFFFF) : tile_cols(ncols);
+    if constexpr (sizeof(TC) == 4) return gemm_tall_f32<TA, TX, TC, MODE>(ex, tc, cls >> 16, g);
     if (tc == 32) return ex.template run<GemmBody<TA, TX, TC, MODE, 2, 2, 4, 1>>(g);
     if (tc == 64) return ex.template run<GemmBody<TA, TX, TC, MODE, 4, 2, 2, 2>>(g);
     return ex.template run<GemmBody<TA, TX, TC, MODE, 4, 4, 2, 2>>(g);
@@ -120,7 +148,7 @@ hipError_t gemm_bf16(Ex& ex, bool split, int cls, const TA* A, int64_t lda, int6
                      const double* mu, const uint32_t* skip_flag, uint32_t skip_mask, Gate gate = {}) {
     const auto g = gemm_args<TA, float, float>(A, lda, rows, K, X, ldx, ncols, out, ldo, S, part_stride, mu,
                                                skip_flag, skip_mask, 64, 16, gate);
-    const int tc = cls ? cls : tile_cols(ncols);
+    const int tc = (cls & 0xFFFF) ? (cls & 0xFFFF) : tile_cols(ncols);
     if (split) return gemm_bf16_cls<TA, MODE, true>(ex, tc, g);
     return gemm_bf16_cls<TA, MODE, false>(ex, tc, g);
 }

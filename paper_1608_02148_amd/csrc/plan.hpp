@@ -35,6 +35,7 @@ inline size_t comp_size(int dtype) { return dtype == RSVD_F64 ? 8 : 4; }
 
 // Work split heuristics (deterministic for a given device and shape).
 struct Splits {
+    int nn;      // split of the n-reduction in A X
     int tn;      // split of the m-reduction in A^T Q
     int gram_m;  // split of the m-reduction of an m x l Gram matrix
     int gram_n;  // split of the n-reduction of an n x l Gram matrix
@@ -48,8 +49,26 @@ inline int gram_split(int64_t rows, int num_cu) {
 
 // A^T Q: as many splits as fit the 2 resident workgroups per CU in one round
 // (a partly filled second round would idle most CUs), at least 256 rows each.
+// A X: split the n-reduction when the row tiles (128 rows each) leave the last
+// round of resident workgroups (2 per CU) mostly empty: up to 4 splits of at
+// least 1024 columns, taken only when the filled fraction of the rounds rises
+// by more than 0.1 (partial blocks cost one extra write and read of m x l).
+inline int nn_split(int64_t m, int64_t n, int num_cu) {
+    const int64_t tiles = cdiv(m, 128), cap = 2 * static_cast<int64_t>(num_cu);
+    auto filled = [&](int64_t S) {
+        const int64_t t = tiles * S;
+        return static_cast<double>(t) / static_cast<double>(cdiv(t, cap) * cap);
+    };
+    int best = 1;
+    double be = filled(1);
+    for (int S = 2; S <= 4 && n / S >= 1024; ++S)
+        if (filled(S) > be + 0.1) { best = S; be = filled(S); }
+    return best;
+}
+
 inline Splits make_splits(int64_t m, int64_t n, int num_cu) {
     Splits s;
+    s.nn = nn_split(m, n, num_cu);
     const int64_t tn_tiles = cdiv(n, 128);
     s.tn = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>((2 * num_cu) / tn_tiles, cdiv(m, 256))));
     s.gram_m = gram_split(m, num_cu);
@@ -64,6 +83,7 @@ struct Plan {
     int64_t m = 0, n = 0;
     int k = 0, p = 0, q = 0, l = 0, Lp = 0, kp = 0;
     int tile = 0;       // column class of the tall product tiles (tile_class of l)
+    int var_nn = 0, var_tn = 0;   // tile variants of the NN / TN products (tile_variant_index)
     int qmax = 0;       // gated: power iterations issued for the whole batch group
     bool gated = false; // batch member: iterations beyond q switched off on the device
     Splits sp{};
@@ -84,11 +104,17 @@ inline int validate(int32_t dtype, int64_t m, int64_t n, int32_t k, const rsvd_p
     return RSVD_OK;
 }
 
+// Index of a tall-tile class in a variant table (6 classes per mode).
+inline int tile_variant_index(int cls) {
+    return cls <= 32 ? 0 : cls <= 48 ? 1 : cls <= 64 ? 2 : cls <= 80 ? 3 : cls <= 96 ? 4 : 5;
+}
+
 // batch = true: one problem of a grouped batch, whose parallelism comes from
 // the batch, so no product splits its reduction (every problem then issues
-// the same sequence of steps).
+// the same sequence of steps).  variants: 12 ints (NN then TN, one per tall
+// class) choosing the f32 tile variant, or null for the defaults.
 inline Plan make_plan(int dtype, int64_t m, int64_t n, int k, const rsvd_params* prm, int num_cu,
-                      bool batch = false) {
+                      bool batch = false, const int* variants = nullptr) {
     Plan P;
     P.dtype = dtype; P.m = m; P.n = n; P.k = k; P.q = prm->q;
     P.l = static_cast<int>(std::min<int64_t>(static_cast<int64_t>(k) + prm->p, std::min(m, n)));
@@ -96,16 +122,21 @@ inline Plan make_plan(int dtype, int64_t m, int64_t n, int k, const rsvd_params*
     P.Lp = tile_cols(P.l);
     P.kp = tile_cols(k);
     P.tile = tile_class(P.l, dtype != RSVD_F64);
+    if (variants && dtype != RSVD_F64) {
+        P.var_nn = variants[tile_variant_index(P.tile)];
+        P.var_tn = variants[6 + tile_variant_index(P.tile)];
+    }
     P.qmax = P.q;
     P.gated = batch;
-    P.sp = batch ? Splits{1, 1, 1, 1} : make_splits(m, n, num_cu);
+    P.sp = batch ? Splits{1, 1, 1, 1, 1} : make_splits(m, n, num_cu);
     const size_t cs = comp_size(dtype);
     Layout L;
     P.status = L.take(kAlign);
     P.Y = L.take(static_cast<size_t>(m) * P.Lp * cs);
     P.Z = L.take(static_cast<size_t>(n) * P.Lp * cs);
     P.Om = L.take(static_cast<size_t>(n) * P.Lp * cs);
-    const size_t part_tn = P.sp.tn > 1 ? static_cast<size_t>(P.sp.tn) * n * P.Lp * cs : 0;
+    const size_t part_tn = std::max(P.sp.tn > 1 ? static_cast<size_t>(P.sp.tn) * n * P.Lp * cs : 0,
+                                    P.sp.nn > 1 ? static_cast<size_t>(P.sp.nn) * m * P.Lp * cs : 0);
     const size_t part_g = static_cast<size_t>(std::max(P.sp.gram_m, P.sp.gram_n)) * P.Lp * P.Lp * 8;
     P.part = L.take(std::max(part_tn, part_g));
     P.gram = L.take(static_cast<size_t>(P.Lp) * P.Lp * 8);

@@ -72,7 +72,8 @@ template <typename TA, typename TC, class Ex>
 hipError_t solve_steps(Ex& ex, rsvd_handle_t prof, const Plan& P, const TA* A, int64_t lda,
                        const rsvd_params* prm, uint32_t stream_id, const SolveOut& o, void* work) {
     const int64_t m = P.m, n = P.n;
-    const int l = P.l, Lp = P.Lp, k = P.k, tile = P.tile;
+    const int l = P.l, Lp = P.Lp, k = P.k;
+    const int tile = P.tile | (P.var_nn << 16), tile_tn = P.tile | (P.var_tn << 16);
     uint32_t* status = at<uint32_t>(work, P.status);
     TC* Y = at<TC>(work, P.Y);
     TC* Z = at<TC>(work, P.Z);
@@ -116,10 +117,17 @@ hipError_t solve_steps(Ex& ex, rsvd_handle_t prof, const Plan& P, const TA* A, i
     const bool mixed = prm->precision == RSVD_PREC_BF16_MIXED;
     const int early = mixed ? 1 : 0, late = mixed ? 2 : 0;
     auto ax = [&](const TC* X, int arith, Gate gt) -> hipError_t {     // Y (m x Lp) = A X
-        return timed(prof, 0, pass_flops, nn_bytes, [&] {
-            return gemm_step<TA, TC, MODE_NN>(ex, arith, tile, A, lda, m, n, X, Lp, l, Y, Lp, 1, 0, mu, nullptr,
-                                              0, gt);
-        });
+        const int S = P.sp.nn;
+        if (S == 1)
+            return timed(prof, 0, pass_flops, nn_bytes, [&] {
+                return gemm_step<TA, TC, MODE_NN>(ex, arith, tile, A, lda, m, n, X, Lp, l, Y, Lp, 1, 0, mu,
+                                                  nullptr, 0, gt);
+            });
+        RSVD_TRY(timed(prof, 0, pass_flops, nn_bytes, [&] {
+            return gemm_step<TA, TC, MODE_NN>(ex, arith, tile, A, lda, m, n, X, Lp, l, partc, Lp, S,
+                                              static_cast<int64_t>(m) * Lp, mu, nullptr, 0, gt);
+        }));
+        return reduce_step<TC>(ex, partc, S, static_cast<int64_t>(m) * Lp, Lp, m, l, Y, Lp, nullptr, 0, gt);
     };
     // The last sketch of a member (after its q-th iteration) uses the late
     // arithmetic; with gates both variants are issued and the iteration word
@@ -159,11 +167,11 @@ hipError_t solve_steps(Ex& ex, rsvd_handle_t prof, const Plan& P, const TA* A, i
         const int S = P.sp.tn;
         if (S == 1)
             return timed(prof, 1, pass_flops, tn_bytes, [&] {
-                return gemm_step<TA, TC, MODE_TN>(ex, arith, tile, A, lda, n, m, Y, Lp, l, dst, Lp, 1, 0, mu,
+                return gemm_step<TA, TC, MODE_TN>(ex, arith, tile_tn, A, lda, n, m, Y, Lp, l, dst, Lp, 1, 0, mu,
                                                   nullptr, 0, gt);
             });
         RSVD_TRY(timed(prof, 1, pass_flops, tn_bytes, [&] {
-            return gemm_step<TA, TC, MODE_TN>(ex, arith, tile, A, lda, n, m, Y, Lp, l, partc, Lp, S,
+            return gemm_step<TA, TC, MODE_TN>(ex, arith, tile_tn, A, lda, n, m, Y, Lp, l, partc, Lp, S,
                                               static_cast<int64_t>(n) * Lp, mu, nullptr, 0, gt);
         }));
         return reduce_step<TC>(ex, partc, S, static_cast<int64_t>(n) * Lp, Lp, n, l, dst, Lp, nullptr, 0, gt);

@@ -66,6 +66,8 @@ _PROTOS = {
     "rsvd_destroy": (c_int32, [c_void_p]),
     "rsvd_set_stream": (c_int32, [c_void_p, c_void_p]),
     "rsvd_last_hip_error": (c_int32, [c_void_p]),
+    "rsvd_set_tile_variants": (c_int32, [c_void_p, c_void_p]),
+    "rsvd_get_tile_variants": (c_int32, [c_void_p, c_void_p]),
     "rsvd_status_string": (ctypes.c_char_p, [c_int32]),
     "rsvd_workspace_size": (c_int32, [c_void_p, c_int32, c_int64, c_int64, c_int32, c_void_p, c_void_p]),
     "rsvd_run": (c_int32, [c_void_p, c_int32, c_int64, c_int64, c_void_p, c_int64, c_int32, c_void_p,
