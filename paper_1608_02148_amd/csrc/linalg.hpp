@@ -192,13 +192,21 @@ __device__ __forceinline__ void chol_body(const CholArgs& a) {
                     if (a0 + i < l && b0 + q < l) a.rout[(a0 + i) * l + b0 + q] = (a0 + i == b0 + q) ? 1.0 : 0.0;
         return;
     }
-    __shared__ double rowbuf[2][CHOL_MAX_L];
-    __shared__ double colbuf[2][CHOL_MAX_L];
+    // Panels of CT_R = 4 rows: the 16 threads of row group ty = P own rows
+    // 4P .. 4P+3 in registers and factor them alone (their lanes lie in one
+    // wave; values move by lane shuffles), then publish the panel's R rows in
+    // LDS and one barrier later every thread applies the rank-4 update to its
+    // trailing rows.  The inverse runs the same way from the last panel up.
+    __shared__ double panel[2][CT_R][CHOL_MAX_L];   // R rows (factor) / X rows (inverse)
+    __shared__ double pcol[2][CT_R][CHOL_MAX_L];    // R columns 4P .. 4P+3 (inverse)
     __shared__ double diag0[CHOL_MAX_L];
     __shared__ double dinv[CHOL_MAX_L];
     __shared__ uint32_t s_flags;
     __shared__ double s_trace;
+    __shared__ int s_fail, s_dead;
+    __shared__ double s_min_ratio;
     double g[CT_R][CT_C];
+    const int npanel = (l + CT_R - 1) / CT_R;
 
     if (tid == 0) {
         uint32_t st = *a.status;
@@ -220,6 +228,8 @@ __device__ __forceinline__ void chol_body(const CholArgs& a) {
             }
         __syncthreads();
     };
+    // value v of the lane holding column c in this row group (16-lane segment)
+    auto from_col = [&](double v, int c) { return __shfl(v, c / CT_C, CT_TX); };
 
     load(0.0);
     if (tid == 0) {
@@ -233,62 +243,89 @@ __device__ __forceinline__ void chol_body(const CholArgs& a) {
     const bool zero = (trace == 0.0);
     constexpr double u = 1.1102230246251565e-16;   // unit roundoff of the f64 Gram
 
-    double min_ratio = 1.0;
-    bool shifted = false, dead_any = false;
+    bool shifted = false;
     if (!nonfinite && !zero) {
         for (int attempt = 0; attempt < 2; ++attempt) {
             if (attempt == 1) {
                 load(11.0 * (static_cast<double>(a.mrows) * l + static_cast<double>(l) * (l + 1)) * u * trace);
                 shifted = true;
             }
-            bool fail = false;
-            min_ratio = 1.0;
-            dead_any = false;
-            for (int j = 0; j < l; ++j) {
-                const int buf = j & 1;
-                if (ty == j / CT_R) {
+            if (tid == 0) { s_fail = 0; s_dead = 0; s_min_ratio = 1.0; }
+            __syncthreads();
+            for (int P = 0; P < npanel; ++P) {
+                const int j0 = CT_R * P, buf = P & 1;
+                if (ty == P) {
+                    bool fail = false, dead_any = false;
+                    double min_ratio = 1.0;
 #pragma unroll
-                    for (int i = 0; i < CT_R; ++i)
-                        if (i == j % CT_R)
+                    for (int t = 0; t < CT_R; ++t) {
+                        const int j = j0 + t;
+                        if (j >= l || fail) break;
+                        double piv = 0.0;
 #pragma unroll
-                            for (int q = 0; q < CT_C; ++q) rowbuf[buf][b0 + q] = g[i][q];
+                        for (int q = 0; q < CT_C; ++q) if (b0 + q == j) piv = g[t][q];
+                        const double d = from_col(piv, j);
+                        const double d0 = diag0[j];
+                        if (a.pass == 1 && attempt == 0 && (!(d > 100.0 * u * d0) || !isfinite(d))) {
+                            fail = true;                      // uniform over the group
+                            break;
+                        }
+                        const bool dead = !(d > 1e-30 * d0) || !isfinite(d) || d0 == 0.0;
+                        const double sq = dead ? 0.0 : sqrt(d);
+                        const double inv_sq = dead ? 0.0 : 1.0 / sq;
+                        if (dead) dead_any = true;
+                        else min_ratio = fmin(min_ratio, d / d0);
+                        if (tx == 0) dinv[j] = inv_sq;
+#pragma unroll
+                        for (int q = 0; q < CT_C; ++q) {         // row j of R
+                            const int c = b0 + q;
+                            g[t][q] = (c > j) ? g[t][q] * inv_sq : (c == j ? sq : 0.0);
+                        }
+#pragma unroll
+                        for (int t2 = t + 1; t2 < CT_R; ++t2) {  // remaining panel rows
+                            const int r = j0 + t2;
+                            double rjr = 0.0;
+#pragma unroll
+                            for (int q = 0; q < CT_C; ++q) if (b0 + q == r) rjr = g[t][q];
+                            const double f = from_col(rjr, r);   // R[j][r]
+                            if (!dead && r < l) {
+#pragma unroll
+                                for (int q = 0; q < CT_C; ++q)
+                                    if (b0 + q >= r) g[t2][q] -= f * g[t][q];
+                            }
+                        }
+                    }
+                    if (tx == 0) {
+                        if (fail) s_fail = 1;
+                        if (dead_any) s_dead = 1;
+                        s_min_ratio = fmin(s_min_ratio, min_ratio);
+                    }
+#pragma unroll
+                    for (int t = 0; t < CT_R; ++t)
+#pragma unroll
+                        for (int q = 0; q < CT_C; ++q) panel[buf][t][b0 + q] = g[t][q];
                 }
                 __syncthreads();
-                const double d = rowbuf[buf][j];
-                const double d0 = diag0[j];
-                if (a.pass == 1 && attempt == 0 && (!(d > 100.0 * u * d0) || !isfinite(d))) {
-                    fail = true;
-                    break;                                   // uniform: every thread saw d
-                }
-                const bool dead = !(d > 1e-30 * d0) || !isfinite(d) || d0 == 0.0;
-                const double sq = dead ? 0.0 : sqrt(d);
-                const double inv_sq = dead ? 0.0 : 1.0 / sq;
-                const double inv_d = inv_sq * inv_sq;
-                if (dead) dead_any = true;
-                else min_ratio = fmin(min_ratio, d / d0);
-                if (tid == 0) dinv[j] = inv_sq;
-                double rb[CT_C];
+                if (s_fail) break;                          // uniform after the barrier
+                if (ty > P) {                               // trailing rows: G -= R_p^T R_p
 #pragma unroll
-                for (int q = 0; q < CT_C; ++q) rb[q] = rowbuf[buf][b0 + q];
+                    for (int t = 0; t < CT_R; ++t) {
+                        double pc[CT_C];
 #pragma unroll
-                for (int i = 0; i < CT_R; ++i) {
-                    const int r = a0 + i;
-                    if (r == j) {                            // row j of R
+                        for (int q = 0; q < CT_C; ++q) pc[q] = panel[buf][t][b0 + q];
 #pragma unroll
-                        for (int q = 0; q < CT_C; ++q) {
-                            const int c = b0 + q;
-                            g[i][q] = (c > j) ? g[i][q] * inv_sq : (c == j ? sq : 0.0);
+                        for (int i = 0; i < CT_R; ++i) {
+                            const double pr = panel[buf][t][a0 + i];
+#pragma unroll
+                            for (int q = 0; q < CT_C; ++q)
+                                if (b0 + q >= a0 + i) g[i][q] -= pr * pc[q];
                         }
-                    } else if (r > j && !dead) {
-                        const double fa = rowbuf[buf][r] * inv_d;
-#pragma unroll
-                        for (int q = 0; q < CT_C; ++q)
-                            if (b0 + q >= r) g[i][q] -= fa * rb[q];
                     }
                 }
             }
-            if (!fail) break;
+            const bool failed = s_fail != 0;
             __syncthreads();
+            if (!failed) break;
         }
     } else {
 #pragma unroll
@@ -298,6 +335,8 @@ __device__ __forceinline__ void chol_body(const CholArgs& a) {
         for (int j = tid; j < l; j += CHOL_THREADS) dinv[j] = 0.0;
     }
     if (tid == 0) {
+        const bool dead_any = !nonfinite && !zero && s_dead;
+        const double min_ratio = (!nonfinite && !zero) ? s_min_ratio : 1.0;
         uint32_t f = s_flags;
         if (nonfinite) f |= RSVD_FLAG_NONFINITE;
         if (zero || dead_any) f |= RSVD_FLAG_DEGENERATE;
@@ -312,42 +351,63 @@ __device__ __forceinline__ void chol_body(const CholArgs& a) {
         s_flags = f;
     }
     __syncthreads();
-    // Inverse by a column sweep: B = I; for j = l-1..1, with X[j][.] = dinv[j] B[j][.],
-    // B[i][c] -= R[i][j] X[j][c] for i < j, c >= j.  Finally X = diag(dinv) B.
+    // Inverse X = R^{-1} by panels from the bottom: the panel's group solves its
+    // 4 rows (X[j] = B[j] / R_jj, B[j'] -= R[j'][j] X[j] inside the panel),
+    // publishes them with the panel's R columns, and the rows above subtract
+    // R[i][4P..4P+3] X[4P..4P+3][.] after one barrier.
     double x[CT_R][CT_C];
 #pragma unroll
     for (int i = 0; i < CT_R; ++i)
 #pragma unroll
         for (int q = 0; q < CT_C; ++q) x[i][q] = (a0 + i == b0 + q && a0 + i < l) ? 1.0 : 0.0;
-    for (int j = l - 1; j > 0; --j) {
-        const int buf = j & 1;
-        if (ty == j / CT_R) {
+    for (int P = npanel - 1; P >= 0; --P) {
+        const int j0 = CT_R * P, buf = P & 1;
+        if (ty == P) {
 #pragma unroll
-            for (int i = 0; i < CT_R; ++i)
-                if (i == j % CT_R)
+            for (int t = CT_R - 1; t >= 0; --t) {
+                const int j = j0 + t;
+                if (j >= l) continue;
+                const double sj = dinv[j];
 #pragma unroll
-                    for (int q = 0; q < CT_C; ++q) rowbuf[buf][b0 + q] = x[i][q];
-        }
-        if (tx == j / CT_C) {
+                for (int q = 0; q < CT_C; ++q) x[t][q] *= sj;          // X[j] = B[j] / R_jj
 #pragma unroll
-            for (int q = 0; q < CT_C; ++q)
-                if (q == j % CT_C)
+                for (int t2 = 0; t2 < t; ++t2) {                       // B[j0+t2] -= R[j0+t2][j] X[j]
+                    double rv = 0.0;
 #pragma unroll
-                    for (int i = 0; i < CT_R; ++i) colbuf[buf][a0 + i] = g[i][q];
-        }
-        __syncthreads();
-        const double sj = dinv[j];
-        if (sj != 0.0) {
-            double xr[CT_C];
-#pragma unroll
-            for (int q = 0; q < CT_C; ++q) xr[q] = rowbuf[buf][b0 + q] * sj;
-#pragma unroll
-            for (int i = 0; i < CT_R; ++i) {
-                if (a0 + i < j) {
-                    const double rij = colbuf[buf][a0 + i];
+                    for (int q = 0; q < CT_C; ++q) if (b0 + q == j) rv = g[t2][q];
+                    const double rij = from_col(rv, j);
 #pragma unroll
                     for (int q = 0; q < CT_C; ++q)
-                        if (b0 + q >= j) x[i][q] -= rij * xr[q];
+                        if (b0 + q >= j) x[t2][q] -= rij * x[t][q];
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < CT_R; ++t)
+#pragma unroll
+                for (int q = 0; q < CT_C; ++q) panel[buf][t][b0 + q] = x[t][q];
+        }
+        if (tx == j0 / CT_C) {                                         // R[i][j0 .. j0+3], all rows i
+#pragma unroll
+            for (int t = 0; t < CT_R; ++t)
+#pragma unroll
+                for (int q = 0; q < CT_C; ++q)
+                    if (b0 + q == j0 + t)
+#pragma unroll
+                        for (int i = 0; i < CT_R; ++i) pcol[buf][t][a0 + i] = g[i][q];
+        }
+        __syncthreads();
+        if (ty < P) {
+#pragma unroll
+            for (int t = 0; t < CT_R; ++t) {
+                double xr[CT_C];
+#pragma unroll
+                for (int q = 0; q < CT_C; ++q) xr[q] = panel[buf][t][b0 + q];
+#pragma unroll
+                for (int i = 0; i < CT_R; ++i) {
+                    const double rij = pcol[buf][t][a0 + i];
+#pragma unroll
+                    for (int q = 0; q < CT_C; ++q)
+                        if (b0 + q >= j0) x[i][q] -= rij * xr[q];
                 }
             }
         }
@@ -356,12 +416,11 @@ __device__ __forceinline__ void chol_body(const CholArgs& a) {
 #pragma unroll
     for (int i = 0; i < CT_R; ++i) {
         const int r = a0 + i;
-        const double di = (r < l) ? dinv[r] : 0.0;
 #pragma unroll
         for (int q = 0; q < CT_C; ++q) {
             const int c = b0 + q;
             if (r < a.ldr && c < a.ldr)
-                rinv[r * a.ldr + c] = static_cast<TC>((r < l && c < l && c >= r) ? x[i][q] * di : 0.0);
+                rinv[r * a.ldr + c] = static_cast<TC>((r < l && c < l && c >= r) ? x[i][q] : 0.0);
             if (a.rout && r < l && c < l) a.rout[r * l + c] = (c >= r) ? g[i][q] : 0.0;
         }
     }
