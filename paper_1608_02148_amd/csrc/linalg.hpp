@@ -509,9 +509,24 @@ __device__ __forceinline__ void jacobi_body(const JacobiArgs& a) {
     const int npairs = lp / 2;
     const int group = tid / JAC_GROUP, gl = tid % JAC_GROUP;
     const int ngroups = nt / JAC_GROUP;
+    // Squared column norms: recomputed at the start of every sweep and
+    // updated through each rotation (|w_a'|^2 = alpha - t gamma,
+    // |w_b'|^2 = beta + t gamma), so a pair needs one inner product, not three.
+    __shared__ double s_norm[CHOL_MAX_L];
     int sweep = 0;
     for (; sweep < a.max_sweeps; ++sweep) {
         if (tid == 0) s_rotated = 0;
+        for (int c = group; c < l; c += ngroups) {
+            const double* wc = W + c * ldw;
+            double ss = 0.0;
+#pragma unroll
+            for (int q = 0; q < JAC_PER_LANE; ++q) {
+                const int r = gl + JAC_GROUP * q;
+                if (r < l) ss += wc[r] * wc[r];
+            }
+            ss = group_sum(ss);
+            if (gl == 0) s_norm[c] = ss;
+        }
         __syncthreads();
         for (int round = 0; round < lp - 1; ++round) {
             for (int p = group; p < npairs; p += ngroups) {
@@ -528,16 +543,19 @@ __device__ __forceinline__ void jacobi_body(const JacobiArgs& a) {
                     xa[q] = (r < l) ? wa[r] : 0.0;
                     xb[q] = (r < l) ? wb[r] : 0.0;
                 }
-                double al = 0.0, be = 0.0, ga = 0.0;
+                const double al = s_norm[ca], be = s_norm[cb];
+                double ga = 0.0;
 #pragma unroll
-                for (int q = 0; q < JAC_PER_LANE; ++q) {
-                    al += xa[q] * xa[q]; be += xb[q] * xb[q]; ga += xa[q] * xb[q];
-                }
-                al = group_sum(al); be = group_sum(be); ga = group_sum(ga);
+                for (int q = 0; q < JAC_PER_LANE; ++q) ga += xa[q] * xb[q];
+                ga = group_sum(ga);
                 if (ga != 0.0 && fabs(ga) > a.tol * sqrt(al * be)) {
                     const double zeta = (be - al) / (2.0 * ga);
                     const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
                     const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+                    if (gl == 0) {
+                        s_norm[ca] = fmax(al - t * ga, 0.0);
+                        s_norm[cb] = be + t * ga;
+                    }
 #pragma unroll
                     for (int q = 0; q < JAC_PER_LANE; ++q) {
                         const int r = gl + JAC_GROUP * q;
