@@ -186,7 +186,7 @@ def learned_arm(count, reps=3):
         out[k] = {"solves_per_s": round(v["solves_per_s"], 1), "ms": round(v["ms"], 3),
                   "frac_within_1pct": round(float(ok[k].mean()), 4),
                   "frac_within_1pct_feasible": round(float(ok[k][feasible].mean()), 4)}
-        for extra in ("select_ms", "solve_ms", "q_hist", "p_hist"):
+        for extra in ("select_ms", "plan_ms", "solve_ms", "q_hist", "p_hist"):
             if extra in v:
                 out[k][extra] = v[extra] if not isinstance(v[extra], float) else round(v[extra], 3)
     log(f"[learned] {out}")

@@ -170,10 +170,10 @@ int rsvd_sync_info(rsvd_handle_t handle, const rsvd_info* dinfo, rsvd_info* hinf
  * (asynchronous on the handle's stream; no allocation, no host
  * synchronisation; without RSVD_BATCH_GRAPH a caller may capture it in its
  * own graph) -> rsvd_batch_destroy.  The handle must outlive the batch.
- * Matrices are grouped by sketch width; the groups run concurrently on
- * streams the batch owns (default priority), forked from and joined back to
- * the handle's stream with events, so a run is still one stream-ordered
- * operation on the handle's stream.
+ * Matrices are grouped by sketch width; the groups run concurrently on side
+ * streams the handle owns (default priority, created on first use), forked
+ * from and joined back to the handle's stream with events, so a run is still
+ * one stream-ordered operation on the handle's stream.
  *
  * Results: matrix b gets the solve that rsvd_run computes for it with
  * params.stream_id = desc[b].stream_id (same steps and kernels); products here

@@ -148,6 +148,50 @@ def rpca(A, k, center=True, retx=True, p=10, q=2, seed=0, stream_id=0, sdist="no
     return dict(rotation=rot, eigvals=ev, sdev=sd, x=x, center=ctr)
 
 
+_DESC_DTYPE = None
+
+
+def _desc_dtype():
+    import numpy as np
+    names = ["A", "lda", "m", "n", "k", "stream_id", "U", "ldu", "S", "V", "ldv", "info", "features", "q", "p"]
+    fmts = ["<u8", "<i8", "<i8", "<i8", "<i4", "<u4", "<u8", "<i8", "<u8", "<u8", "<i8", "<u8", "<u8", "<i4", "<i4"]
+    offs = [getattr(L.BatchDesc, f).offset for f in names]
+    return np.dtype({"names": names, "formats": fmts, "offsets": offs, "itemsize": ctypes.sizeof(L.BatchDesc)})
+
+
+class _Views:
+    """Per-matrix views into a flat output buffer, made on access."""
+
+    def __init__(self, flat, offs, rows, cols):
+        self.flat, self.offs, self.rows, self.cols = flat, offs, rows, cols
+
+    def __len__(self):
+        return len(self.offs) - 1
+
+    def __getitem__(self, b):
+        v = self.flat[int(self.offs[b]):int(self.offs[b + 1])]
+        return v if self.rows is None else v.view(int(self.rows[b]), int(self.cols[b]))
+
+    def __iter__(self):
+        return (self[b] for b in range(len(self)))
+
+
+class _Nones:
+    def __init__(self, n):
+        self.n = n
+
+    def __len__(self):
+        return self.n
+
+    def __getitem__(self, b):
+        if not -self.n <= b < self.n:
+            raise IndexError(b)
+        return None
+
+    def __iter__(self):
+        return iter([None] * self.n)
+
+
 class Batch:
     """A ragged batch of randomized SVDs run as grouped launches (rsvd_batch_*).
 
@@ -159,12 +203,17 @@ class Batch:
     HIP graph per run; ``stamps=True`` records device-clock stamps per matrix.
     ``qs`` / ``ps``: per-matrix q and p (lists) instead of ``q`` / ``p``.
     ``features=True``: run only the q = 0 sketches and fill ``features``
-    (count x 131) with the selector inputs.
+    (count x 131) with the selector inputs.  ``work``: optional uint8 device
+    tensor reused as the workspace when large enough (owned by this batch
+    while it is alive).
     """
 
     def __init__(self, As, ks, p=10, q=2, seed=0, stream_ids=None, sdist="normal", precision="plain",
                  compute_u=True, compute_v=True, graph=True, stamps=False, infos=False, qs=None, ps=None,
-                 features=False):
+                 features=False, work=None):
+        global _DESC_DTYPE
+        if _DESC_DTYPE is None:
+            _DESC_DTYPE = _desc_dtype()
         if len(As) == 0 or len(As) != len(ks):
             raise ValueError("As and ks must be non-empty lists of equal length")
         dts = {_check_matrix(A) for A in As}
@@ -180,33 +229,42 @@ class Batch:
             compute_u = compute_v = False
         self.features = (torch.zeros(self.count, L.MLP_INPUTS, dtype=torch.float32, device=dev)
                          if features else None)
-        u_off, v_off, s_off = [0], [0], [0]
-        for m, n, k in shapes:
-            u_off.append(u_off[-1] + m * k)
-            v_off.append(v_off[-1] + n * k)
-            s_off.append(s_off[-1] + k)
-        self.u_flat = torch.empty(max(u_off[-1], 1), dtype=od, device=dev) if compute_u else None
-        self.v_flat = torch.empty(max(v_off[-1], 1), dtype=od, device=dev) if compute_v else None
-        self.s_flat = torch.empty(s_off[-1], dtype=torch.float64, device=dev)
+        import numpy as np
+        sh = np.array(shapes, dtype=np.int64).reshape(-1, 3)
+        m_, n_, k_ = sh[:, 0], sh[:, 1], sh[:, 2]
+        u_off = np.concatenate([[0], np.cumsum(m_ * k_)])
+        v_off = np.concatenate([[0], np.cumsum(n_ * k_)])
+        s_off = np.concatenate([[0], np.cumsum(k_)])
+        self.u_flat = torch.empty(max(int(u_off[-1]), 1), dtype=od, device=dev) if compute_u else None
+        self.v_flat = torch.empty(max(int(v_off[-1]), 1), dtype=od, device=dev) if compute_v else None
+        self.s_flat = torch.empty(int(s_off[-1]), dtype=torch.float64, device=dev)
         self.info = (torch.zeros(self.count, ctypes.sizeof(L.Info), dtype=torch.uint8, device=dev)
                      if infos else None)
-        self.U, self.S, self.V = [], [], []
-        descs = (L.BatchDesc * self.count)()
-        sids = list(range(self.count)) if stream_ids is None else [int(x) for x in stream_ids]
-        for b, (A, (m, n, k)) in enumerate(zip(As, shapes)):
-            U = self.u_flat[u_off[b]:u_off[b + 1]].view(m, k) if compute_u else None
-            V = self.v_flat[v_off[b]:v_off[b + 1]].view(n, k) if compute_v else None
-            S = self.s_flat[s_off[b]:s_off[b + 1]]
-            self.U.append(U); self.S.append(S); self.V.append(V)
-            d = descs[b]
-            d.A, d.lda, d.m, d.n, d.k, d.stream_id = A.data_ptr(), A.stride(0), m, n, k, sids[b]
-            d.U, d.ldu = (U.data_ptr(), k) if U is not None else (None, 0)
-            d.S = S.data_ptr()
-            d.V, d.ldv = (V.data_ptr(), k) if V is not None else (None, 0)
-            d.info = self.info[b].data_ptr() if infos else None
-            d.features = self.features[b].data_ptr() if features else None
-            d.q = int(qs[b]) if qs is not None else int(q)
-            d.p = int(ps[b]) if ps is not None else int(p)
+        self.U = _Views(self.u_flat, u_off, m_, k_) if compute_u else _Nones(self.count)
+        self.V = _Views(self.v_flat, v_off, n_, k_) if compute_v else _Nones(self.count)
+        self.S = _Views(self.s_flat, s_off, None, k_)
+        # descriptors filled column by column (the layout of rsvd_batch_desc)
+        d = np.zeros(self.count, dtype=_DESC_DTYPE)
+        d["A"] = [A.data_ptr() for A in As]
+        d["lda"] = [A.stride(0) for A in As]
+        d["m"], d["n"], d["k"] = m_, n_, k_
+        d["stream_id"] = np.arange(self.count) if stream_ids is None else np.asarray(stream_ids)
+        esz = 4 if od == torch.float32 else 8
+        if compute_u:
+            d["U"] = self.u_flat.data_ptr() + u_off[:-1] * esz
+            d["ldu"] = k_
+        if compute_v:
+            d["V"] = self.v_flat.data_ptr() + v_off[:-1] * esz
+            d["ldv"] = k_
+        d["S"] = self.s_flat.data_ptr() + s_off[:-1] * 8
+        if infos:
+            d["info"] = self.info.data_ptr() + np.arange(self.count) * ctypes.sizeof(L.Info)
+        if features:
+            d["features"] = self.features.data_ptr() + np.arange(self.count) * (L.MLP_INPUTS * 4)
+        d["q"] = np.asarray(qs) if qs is not None else q
+        d["p"] = np.asarray(ps) if ps is not None else p
+        self._desc = d
+        descs = d.ctypes.data_as(ctypes.c_void_p)
         self._As = list(As)            # keep the inputs alive as long as the batch
         prm = make_params(p, q, seed, 0, sdist, precision)
         flags = (L.BATCH_GRAPH if graph else 0) | (L.BATCH_STAMPS if stamps else 0)
@@ -218,7 +276,9 @@ class Batch:
         L.check(self._lib.rsvd_batch_create(self._h, self.dtype, self.count, descs, ctypes.byref(prm), flags,
                                             ctypes.byref(self._b), ctypes.byref(nbytes)), "rsvd_batch_create")
         self.work_bytes = nbytes.value
-        self.work = workspace(nbytes.value, dev)
+        # a caller-provided workspace (uint8 tensor) is used when large enough;
+        # it must not be shared with another live batch
+        self.work = work if (work is not None and work.numel() >= nbytes.value) else workspace(nbytes.value, dev)
         L.check(self._lib.rsvd_batch_bind(self._b, _ptr(self.work), self.work.numel()), "rsvd_batch_bind")
 
     def run(self):
@@ -411,6 +471,18 @@ class MlpTrainer:
         return self.loss
 
 
+_scratch_ws = {}
+
+
+def _scratch(nbytes, device):
+    """Per-device scratch workspace reused by synchronous calls (select)."""
+    key = str(device)
+    t = _scratch_ws.get(key)
+    if t is None or t.numel() < nbytes:
+        _scratch_ws[key] = t = workspace(nbytes, device)
+    return t
+
+
 def select(As, ks, theta, seed=0, stream_ids=None, sdist="normal", precision="plain", tau=0.0):
     """Learned (q, p) per matrix (rsvd_select): returns (qs, ps, features).
     tau <= 0: the network's most probable class; otherwise the cheapest class
@@ -422,18 +494,24 @@ def select(As, ks, theta, seed=0, stream_ids=None, sdist="normal", precision="pl
     dt = dts.pop()
     dev = As[0].device
     n = len(As)
-    descs = (L.BatchDesc * n)()
-    sids = list(range(n)) if stream_ids is None else [int(x) for x in stream_ids]
-    for b, (A, k) in enumerate(zip(As, ks)):
-        d = descs[b]
-        d.A, d.lda, d.m, d.n, d.k, d.stream_id = A.data_ptr(), A.stride(0), A.shape[0], A.shape[1], int(k), sids[b]
+    global _DESC_DTYPE
+    if _DESC_DTYPE is None:
+        _DESC_DTYPE = _desc_dtype()
+    d = np.zeros(n, dtype=_DESC_DTYPE)
+    d["A"] = [A.data_ptr() for A in As]
+    d["lda"] = [A.stride(0) for A in As]
+    d["m"] = [A.shape[0] for A in As]
+    d["n"] = [A.shape[1] for A in As]
+    d["k"] = np.asarray(ks)
+    d["stream_id"] = np.arange(n) if stream_ids is None else np.asarray(stream_ids)
+    descs = d.ctypes.data_as(ctypes.c_void_p)
     prm = make_params(10, 0, seed, 0, sdist, precision)
     lib = L.load()
     h = handle(dev)
     nbytes = ctypes.c_size_t()
     L.check(lib.rsvd_select_workspace_size(h, dt, n, descs, ctypes.byref(prm), ctypes.byref(nbytes)),
             "rsvd_select_workspace_size")
-    work = workspace(nbytes.value, dev)
+    work = _scratch(nbytes.value, dev)
     feats = torch.empty(n, L.MLP_INPUTS, dtype=torch.float32, device=dev)
     qs = np.zeros(n, dtype=np.int32)
     ps = np.zeros(n, dtype=np.int32)

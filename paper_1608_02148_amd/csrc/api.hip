@@ -8,6 +8,7 @@
 // step is a kernel on the handle's stream; nothing synchronises the host.
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 
 #include "plan.hpp"
@@ -59,8 +60,13 @@ int rsvd_create(rsvd_handle_t* handle, void* hip_stream) {
 }
 
 int rsvd_destroy(rsvd_handle_t handle) {
-    if (handle)
+    if (handle) {
         for (hipEvent_t e : handle->event_pool) (void)hipEventDestroy(e);
+        for (hipStream_t s : handle->side) (void)hipStreamDestroy(s);
+        for (hipEvent_t e : handle->side_done) (void)hipEventDestroy(e);
+        if (handle->fork) (void)hipEventDestroy(handle->fork);
+        if (handle->staging) (void)hipHostFree(handle->staging);
+    }
     delete handle;
     return RSVD_OK;
 }
@@ -222,20 +228,21 @@ struct rsvd_batch_s {
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    // Groups after the first run on side streams forked from the caller's
-    // stream and joined back (events), so their small-kernel phases overlap
-    // the other groups' products.
-    std::vector<hipStream_t> side;
-    std::vector<hipEvent_t> done;
-    hipEvent_t fork = nullptr;
+    size_t tables_bytes = 0;            // launch tables at the start of the workspace
 };
 
 namespace rsvd {
 
-hipError_t record_group(rsvd_batch_s* B, BatchGroup& g, void* base) {
-    g.rec.clear();
+// Records the group's steps.  host = null: the first `limit` members into the
+// recorder's own arrays (planning); otherwise every member directly into the
+// packed host layout at host (binding), using the step list already recorded.
+hipError_t record_group(rsvd_batch_s* B, BatchGroup& g, void* base, size_t limit = SIZE_MAX,
+                        unsigned char* host = nullptr) {
+    if (host) g.rec.begin_direct(host, static_cast<int>(g.members.size()));
+    else g.rec.clear();
     const bool stamps = (B->flags & RSVD_BATCH_STAMPS) != 0;
-    for (int i : g.members) {
+    for (size_t mi = 0; mi < g.members.size() && mi < limit; ++mi) {
+        const int i = g.members[mi];
         const rsvd_batch_desc& d = B->desc[i];
         SolveOut o{};
         o.U = d.U; o.ldu = d.ldu; o.V = d.V; o.ldv = d.ldv; o.S = d.S; o.info = d.info;
@@ -255,8 +262,8 @@ hipError_t record_group(rsvd_batch_s* B, BatchGroup& g, void* base) {
     return hipSuccess;
 }
 
-inline hipError_t record_all(rsvd_batch_s* B, void* base) {
-    for (BatchGroup& g : B->groups) RSVD_TRY(record_group(B, g, base));
+inline hipError_t record_all(rsvd_batch_s* B, void* base, unsigned char* host) {
+    for (BatchGroup& g : B->groups) RSVD_TRY(record_group(B, g, base, SIZE_MAX, host + g.table_off));
     return hipSuccess;
 }
 
@@ -266,32 +273,35 @@ constexpr size_t kMaxLanes = 6;
 
 inline size_t lanes_of(const rsvd_batch_s* B) { return std::min(B->groups.size(), kMaxLanes); }
 
+// The side streams belong to the handle, so planning a batch creates none.
 inline hipError_t launch_all(const rsvd_batch_s* B, hipStream_t st) {
     const unsigned char* base = static_cast<const unsigned char*>(B->work);
     const size_t lanes = lanes_of(B);
-    if (lanes > 1) RSVD_TRY(hipEventRecord(B->fork, st));
-    for (size_t s = 1; s < lanes; ++s) RSVD_TRY(hipStreamWaitEvent(B->side[s - 1], B->fork, 0));
+    rsvd_handle_t h = B->h;
+    if (lanes > 1) RSVD_TRY(hipEventRecord(h->fork, st));
+    for (size_t s = 1; s < lanes; ++s) RSVD_TRY(hipStreamWaitEvent(h->side[s - 1], h->fork, 0));
     for (size_t g = 0; g < B->groups.size(); ++g) {
-        hipStream_t ls = (g % lanes == 0) ? st : B->side[g % lanes - 1];
+        hipStream_t ls = (g % lanes == 0) ? st : h->side[g % lanes - 1];
         RSVD_TRY(B->groups[g].rec.launch(base + B->groups[g].table_off, ls));
     }
     for (size_t s = 1; s < lanes; ++s) {
-        RSVD_TRY(hipEventRecord(B->done[s - 1], B->side[s - 1]));
-        RSVD_TRY(hipStreamWaitEvent(st, B->done[s - 1], 0));
+        RSVD_TRY(hipEventRecord(h->side_done[s - 1], h->side[s - 1]));
+        RSVD_TRY(hipStreamWaitEvent(st, h->side_done[s - 1], 0));
     }
     return hipSuccess;
 }
 
 inline hipError_t make_side_streams(rsvd_batch_s* B) {
     const size_t need = lanes_of(B) > 0 ? lanes_of(B) - 1 : 0;
-    if (need && !B->fork) RSVD_TRY(hipEventCreateWithFlags(&B->fork, hipEventDisableTiming));
-    while (B->side.size() < need) {
+    rsvd_handle_t h = B->h;
+    if (need && !h->fork) RSVD_TRY(hipEventCreateWithFlags(&h->fork, hipEventDisableTiming));
+    while (h->side.size() < need) {
         hipStream_t s = nullptr;
         RSVD_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
-        B->side.push_back(s);
+        h->side.push_back(s);
         hipEvent_t e = nullptr;
         RSVD_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-        B->done.push_back(e);
+        h->side_done.push_back(e);
     }
     return hipSuccess;
 }
@@ -361,13 +371,16 @@ int rsvd_batch_create(rsvd_handle_t handle, int32_t dtype, int32_t count, const 
         });
         B->groups.push_back(std::move(g));
     }
-    // Size the step tables with a dry recording (their size does not depend
-    // on the addresses recorded in them).
+    // Size the step tables by recording one member per group (every member
+    // issues the same steps, and their sizes do not depend on the addresses).
     void* fake = reinterpret_cast<void*>(static_cast<uintptr_t>(1) << 44);
     B->offs.assign(count, 0);
-    if (record_all(B, fake) != hipSuccess) { delete B; return RSVD_ERR_UNSUPPORTED; }
     Layout L;
-    for (BatchGroup& g : B->groups) g.table_off = L.take(g.rec.packed_bytes());
+    for (BatchGroup& g : B->groups) {
+        if (record_group(B, g, fake, 1) != hipSuccess) { delete B; return RSVD_ERR_UNSUPPORTED; }
+        g.table_off = L.take(g.rec.packed_bytes_for(static_cast<int>(g.members.size())));
+    }
+    B->tables_bytes = L.off;
     B->stamps_off = L.take(2 * sizeof(uint64_t) * static_cast<size_t>(count));
     for (int32_t i = 0; i < count; ++i) B->offs[i] = L.take(B->plans[i].bytes);
     B->bytes = L.off;
@@ -382,11 +395,23 @@ int rsvd_batch_bind(rsvd_batch_t batch, void* work, size_t work_bytes) {
     rsvd_handle_t h = batch->h;
     drop_graph(batch);
     batch->work = nullptr;
-    hipError_t e = record_all(batch, work);
-    if (e != hipSuccess) return RSVD_ERR_UNSUPPORTED;
+    hipError_t e = hipSuccess;
+    if (h->staging_bytes < batch->tables_bytes) {
+        if (h->staging) (void)hipHostFree(h->staging);
+        h->staging = nullptr;
+        h->staging_bytes = 0;
+        e = hipHostMalloc(reinterpret_cast<void**>(&h->staging), batch->tables_bytes, hipHostMallocDefault);
+        if (e != hipSuccess) { h->staging = nullptr; return hip_status(h, e); }
+        h->staging_bytes = batch->tables_bytes;
+    }
+    if (record_all(batch, work, h->staging) != hipSuccess) return RSVD_ERR_UNSUPPORTED;
     for (BatchGroup& g : batch->groups) {
-        e = g.rec.upload(static_cast<unsigned char*>(work) + g.table_off, h->stream);
-        if (e == hipSuccess) e = g.rec.prepare();
+        e = g.rec.prepare();
+        if (e != hipSuccess) return hip_status(h, e);
+    }
+    if (batch->tables_bytes) {
+        e = hipMemcpyAsync(work, h->staging, batch->tables_bytes, hipMemcpyHostToDevice, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
         if (e != hipSuccess) return hip_status(h, e);
     }
     e = make_side_streams(batch);
@@ -435,9 +460,6 @@ int rsvd_batch_destroy(rsvd_batch_t batch) {
     if (!batch) return RSVD_OK;
     drop_graph(batch);
     if (batch->cap) (void)hipStreamDestroy(batch->cap);
-    for (hipStream_t s : batch->side) (void)hipStreamDestroy(s);
-    for (hipEvent_t e : batch->done) (void)hipEventDestroy(e);
-    if (batch->fork) (void)hipEventDestroy(batch->fork);
     delete batch;
     return RSVD_OK;
 }

@@ -112,4 +112,13 @@ struct rsvd_handle_s {
     // f32 tall-tile variant per (mode, column class): NN 32..128, then TN
     // (rsvd_set_tile_variants; defaults measured at 100000 x 5000, l = 120)
     int variants[12] = {0, 0, 0, 0, 0, 1, 0, 0, 0, 0, 0, 2};
+    // Side streams (default priority) and events that batches fork their
+    // groups onto; created on first use, released by rsvd_destroy.
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> side_done;
+    hipEvent_t fork = nullptr;
+    // Pinned host staging for uploading batch launch tables (grown on demand;
+    // uploads are synchronous, so one buffer serves every batch).
+    unsigned char* staging = nullptr;
+    size_t staging_bytes = 0;
 };

@@ -91,14 +91,39 @@ struct BatchRecorder {
         std::vector<unsigned char> args;
         std::vector<int> prefix{0};
         size_t lds = 0;
-        size_t args_off = 0, prefix_off = 0;   // device offsets after upload()
+        size_t args_off = 0, prefix_off = 0;   // offsets in the packed layout
+        int total = 0;                          // workgroups over all problems
     };
+    static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
     std::vector<Step> steps;
     size_t cursor = 0;
     int nprob = 0;
     bool mismatch = false;
+    // Direct mode: the step list is known (recorded for one problem); every
+    // problem's arguments and block counts are written straight into the
+    // packed host layout at `direct`, sized for `direct_n` problems.
+    unsigned char* direct = nullptr;
+    int direct_n = 0;
 
     void begin_problem() { cursor = 0; ++nprob; }
+
+    void begin_direct(unsigned char* host, int n) {
+        size_t off = 0;
+        for (Step& s : steps) {
+            s.args_off = off;
+            off += align256(s.elem * n);
+            s.prefix_off = off;
+            off += align256((n + 1) * sizeof(int));
+            reinterpret_cast<int*>(host + s.prefix_off)[0] = 0;
+            s.total = 0;
+        }
+        direct = host;
+        direct_n = n;
+        nprob = 0;
+        cursor = 0;
+        mismatch = false;
+    }
 
     // Raises the kernel's dynamic LDS limit (a host-side attribute, done
     // before any stream capture).
@@ -127,6 +152,18 @@ struct BatchRecorder {
     template <class Body>
     hipError_t run(const typename Body::Args& a) {
         typedef typename Body::Args Args;
+        if (direct) {
+            if (cursor == steps.size() || nprob > direct_n) { mismatch = true; return hipErrorInvalidValue; }
+            Step& s = steps[cursor++];
+            if (s.fn != &launch_grouped<Body>) { mismatch = true; return hipErrorInvalidValue; }
+            std::memcpy(direct + s.args_off + static_cast<size_t>(nprob - 1) * s.elem, &a, sizeof(Args));
+            int* pre = reinterpret_cast<int*>(direct + s.prefix_off);
+            pre[nprob] = pre[nprob - 1] + Body::blocks(a);
+            s.total = pre[nprob];
+            const size_t lds = Body::lds(a);
+            if (lds > s.lds) s.lds = lds;
+            return hipSuccess;
+        }
         if (cursor == steps.size()) {
             if (nprob != 1) { mismatch = true; return hipErrorInvalidValue; }
             Step s;
@@ -141,12 +178,11 @@ struct BatchRecorder {
         s.args.resize(off + sizeof(Args));
         std::memcpy(s.args.data() + off, &a, sizeof(Args));
         s.prefix.push_back(s.prefix.back() + Body::blocks(a));
+        s.total = s.prefix.back();
         const size_t lds = Body::lds(a);
         if (lds > s.lds) s.lds = lds;
         return hipSuccess;
     }
-
-    static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
     // Bytes of device memory the packed arrays need.
     size_t packed_bytes() const {
@@ -155,22 +191,26 @@ struct BatchRecorder {
         return b;
     }
 
-    // Pack into host staging and copy to `dev` (synchronous with the stream).
-    hipError_t upload(void* dev, hipStream_t st) {
-        std::vector<unsigned char> host(packed_bytes());
-        if (host.empty()) return hipSuccess;
+    // Bytes the packed arrays need for n problems that issue the steps
+    // recorded so far (the sizes do not depend on the recorded values).
+    size_t packed_bytes_for(int n) const {
+        size_t b = 0;
+        for (const Step& s : steps) b += align256(s.elem * n) + align256((n + 1) * sizeof(int));
+        return b;
+    }
+
+    // Lay the arrays out in host memory at `host` (packed_bytes() bytes); the
+    // device copy of those bytes is what launch() reads.
+    void pack(unsigned char* host) {
         size_t off = 0;
         for (Step& s : steps) {
             s.args_off = off;
-            std::memcpy(host.data() + off, s.args.data(), s.args.size());
+            std::memcpy(host + off, s.args.data(), s.args.size());
             off += align256(s.args.size());
             s.prefix_off = off;
-            std::memcpy(host.data() + off, s.prefix.data(), s.prefix.size() * sizeof(int));
+            std::memcpy(host + off, s.prefix.data(), s.prefix.size() * sizeof(int));
             off += align256(s.prefix.size() * sizeof(int));
         }
-        hipError_t e = hipMemcpyAsync(dev, host.data(), host.size(), hipMemcpyHostToDevice, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        return e;
     }
 
     hipError_t prepare() const {
@@ -181,7 +221,7 @@ struct BatchRecorder {
         return hipSuccess;
     }
 
-    void clear() { steps.clear(); cursor = 0; nprob = 0; mismatch = false; }
+    void clear() { steps.clear(); cursor = 0; nprob = 0; mismatch = false; direct = nullptr; direct_n = 0; }
 
     // The problem just recorded issued every step that problem 0 issued.
     bool complete() const { return !mismatch && cursor == steps.size(); }
@@ -190,7 +230,7 @@ struct BatchRecorder {
         const unsigned char* base = static_cast<const unsigned char*>(dev);
         for (const Step& s : steps) {
             hipError_t e = s.fn(st, base + s.args_off, reinterpret_cast<const int*>(base + s.prefix_off), nprob,
-                                s.prefix.back(), s.lds);
+                                s.total, s.lds);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;

@@ -156,7 +156,10 @@ hipError_t solve_steps(Ex& ex, rsvd_handle_t prof, const Plan& P, const TA* A, i
         JacobiArgs ja;
         ja.R = racc; ja.ldr = l; ja.l = l; ja.k = 1;
         ja.sigma = sigma; ja.xv = xv; ja.ldx = Lp; ja.xcols = P.kp; ja.wks = at<double>(work, P.wks);
-        ja.status = status; ja.max_sweeps = 60; ja.tol = jacobi_tol(ja.l);
+        // features are f32 ratios: rotating pairs down to |cos| <= 1e-7 leaves
+        // the singular values accurate far beyond that (the error is of the
+        // order of the squared off-diagonal cosines)
+        ja.status = status; ja.max_sweeps = 60; ja.tol = 1e-7;
         RSVD_TRY(ex.template run<JacobiBody<TC>>(ja));
         RSVD_TRY(ex.template run<FeatureBody>(FeatureBody::Args{sigma, l, m, n, o.feat_k, o.features}));
         if (o.stamps) RSVD_TRY(ex.template run<StampBody>(StampBody::Args{o.stamps + 1}));

@@ -301,35 +301,42 @@ def evaluate_arms(data, theta, seed=2148, reps=3, tau=DEFAULT_TAU, fixed=(4, 20)
         return err
 
     out = {}
+    work = None
     for name, (q, p) in (("fp32_default_q2_p10", (2, 10)), (f"fp32_fixed_q{fixed[0]}_p{fixed[1]}", fixed)):
         bt, ms = _timed_batch(data, ks, reps, p=p, q=q, seed=seed)
         err = success(bt)
         out[name] = dict(ms=ms, solves_per_s=n_mat / ms * 1e3, errors=err)
         bt.close()
-    # learned: select (features + network + host planning) and solve, all timed
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    qs, ps = choose(theta, data["A"], ks, seed=seed, precision="bf16_mixed", tau=tau)
-    bt = api.Batch(data["A"], ks, seed=seed, precision="bf16_mixed", qs=qs, ps=ps, compute_v=False, graph=False)
-    bt.run()
-    torch.cuda.synchronize()
-    first = (time.perf_counter() - t0) * 1e3
-    t0 = time.perf_counter()
-    for _ in range(reps):
+        if work is None or bt.work.numel() > work.numel():
+            work = bt.work          # reused by the learned arms (p <= 20, q <= 4: no larger)
+        del bt
+    # learned: select (features + network + host planning) and solve; the
+    # select phase and the planning of the solve batch are timed as well
+    for name, prec in (("fp32_learned", "plain"), ("bf16_learned", "bf16_mixed")):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            qs, ps = choose(theta, data["A"], ks, seed=seed, precision=prec, tau=tau)
+        torch.cuda.synchronize()
+        select_ms = (time.perf_counter() - t0) * 1e3 / reps
+        t0 = time.perf_counter()
+        bt = api.Batch(data["A"], ks, seed=seed, precision=prec, qs=qs, ps=ps, compute_v=False, graph=False,
+                       work=work)
+        plan_ms = (time.perf_counter() - t0) * 1e3
         bt.run()
-    torch.cuda.synchronize()
-    solve_ms = (time.perf_counter() - t0) * 1e3 / reps
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        choose(theta, data["A"], ks, seed=seed, precision="bf16_mixed", tau=tau)
-    torch.cuda.synchronize()
-    select_ms = (time.perf_counter() - t0) * 1e3 / reps
-    err = success(bt)
-    out["bf16_learned"] = dict(ms=select_ms + solve_ms, select_ms=select_ms, solve_ms=solve_ms, first_call_ms=first,
-                               solves_per_s=n_mat / (select_ms + solve_ms) * 1e3, errors=err,
-                               q_hist=np.bincount(qs, minlength=5).tolist(),
-                               p_hist={int(v): int(np.sum(ps == v)) for v in P_CHOICES})
-    bt.close()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            bt.run()
+        torch.cuda.synchronize()
+        solve_ms = (time.perf_counter() - t0) * 1e3 / reps
+        err = success(bt)
+        total = select_ms + plan_ms + solve_ms
+        out[name] = dict(ms=total, select_ms=select_ms, plan_ms=plan_ms, solve_ms=solve_ms,
+                         solves_per_s=n_mat / total * 1e3, errors=err,
+                         q_hist=np.bincount(qs, minlength=5).tolist(),
+                         p_hist={int(v): int(np.sum(ps == v)) for v in P_CHOICES})
+        bt.close()
     return out
 
 

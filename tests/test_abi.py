@@ -231,3 +231,18 @@ def test_select_workspace_is_host_only(lib, handle):
     assert nbytes.value >= 2 * 131 * 4
     assert lib.rsvd_select(handle, L.RSVD_F32, 2, _descs(shapes), ctypes.byref(prm), None, 0.8, None, None,
                            None, ctypes.c_void_p(256), nbytes.value) == -1
+
+
+def test_numpy_descriptor_layout_matches_the_struct():
+    import numpy as np
+    from paper_1608_02148_amd import api
+    dt = api._desc_dtype()
+    assert dt.itemsize == ctypes.sizeof(L.BatchDesc)
+    d = np.zeros(2, dtype=dt)
+    d["A"], d["lda"], d["m"], d["n"], d["k"], d["stream_id"] = [11, 12], [5, 6], [300, 400], [200, 100], [7, 8], [3, 4]
+    d["U"], d["ldu"], d["S"], d["V"], d["ldv"] = [21, 22], [7, 8], [31, 32], [41, 42], [7, 8]
+    d["info"], d["features"], d["q"], d["p"] = [51, 52], [61, 62], [2, 3], [10, 20]
+    c = (L.BatchDesc * 2).from_buffer_copy(d.tobytes())
+    assert (c[1].A, c[1].lda, c[1].m, c[1].n, c[1].k, c[1].stream_id) == (12, 6, 400, 100, 8, 4)
+    assert (c[1].U, c[1].ldu, c[1].S, c[1].V, c[1].ldv) == (22, 8, 32, 42, 8)
+    assert (c[1].info, c[1].features, c[1].q, c[1].p) == (52, 62, 3, 20)
