@@ -120,9 +120,17 @@ hipError_t gemm_plain(Ex& ex, int cls, bool square, const TA* A, int64_t lda, in
     const auto g = gemm_args<TA, TX, TC>(A, lda, rows, K, X, ldx, ncols, out, ldo, S, part_stride, mu, skip_flag,
                                          skip_mask, gemm_bk<TC>(), vb, gate);
     if (square) {
-        const int sc = tile_cols(static_cast<int>(std::max<int64_t>(rows, ncols)));
+        // square tiles: the smallest that holds max(rows, ncols), so little
+        // of the f64 matrix cores' work is padding -- 32, 48, 64, 80, 96 or
+        // 128 for the Gram of an f32 basis, 32 / 64 / 128 otherwise (the same
+        // coarser classes the f64 solves and their batch groups use)
+        const int extent = static_cast<int>(std::max<int64_t>(rows, ncols));
+        const int sc = tile_class(extent, sizeof(TA) == 4);
         if (sc == 32) return ex.template run<GemmBody<TA, TX, TC, MODE, 1, 1, 2, 2>>(g);
+        if (sc == 48) return ex.template run<GemmBody<TA, TX, TC, MODE, 1, 3, 3, 1>>(g);
         if (sc == 64) return ex.template run<GemmBody<TA, TX, TC, MODE, 2, 2, 2, 2>>(g);
+        if (sc == 80) return ex.template run<GemmBody<TA, TX, TC, MODE, 1, 5, 5, 1>>(g);
+        if (sc == 96) return ex.template run<GemmBody<TA, TX, TC, MODE, 2, 3, 3, 2>>(g);
         return ex.template run<GemmBody<TA, TX, TC, MODE, 4, 4, 2, 2>>(g);
     }
     const int tc = (cls & 0xFFFF) ? (cls & 0xFFFF) : tile_cols(ncols);

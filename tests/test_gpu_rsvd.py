@@ -86,6 +86,9 @@ def test_c1_fp64_parity():
     (800, 300, 20, 0, 2, 15),     # no oversampling
     (4000, 700, 100, 28, 3, 16),  # l = 128, the largest tile
     (64, 40, 1, 2, 2, 17),        # k = 1
+    (3000, 600, 85, 10, 2, 18),   # l = 95: square 96 tiles for the l x l products
+    (2500, 400, 40, 5, 1, 19),    # l = 45: square 48 tiles
+    (2500, 700, 66, 10, 1, 20),   # l = 76: square 80 tiles
 ])
 def test_fp64_shapes(m, n, k, p, q, seed):
     sig = syn.spectrum("poly", min(m, n), alpha=1.0)
