@@ -65,7 +65,9 @@ typedef struct {
     uint32_t stream_id;  /* Philox counter word 2 of Omega (batch index)        */
     int32_t  sdist;      /* rsvd_sdist                                           */
     int32_t  precision;  /* rsvd_precision                                       */
-    int32_t  reserved[3];
+    int32_t  probes;     /* r > 0: a-posteriori error bound from r Gaussian probes
+                            (rsvd_info.est_err; 0..16, default 0 = off)           */
+    int32_t  reserved[2];
 } rsvd_params;
 
 /* Device-side outcome record (optional; written by the last kernel). */
@@ -74,7 +76,13 @@ typedef struct {
     int32_t  q;          /* subspace iterations performed                         */
     int32_t  p;          /* oversampling actually used (l - k)                    */
     uint32_t flags;      /* RSVD_FLAG_* bits                                      */
-    double   est_err;    /* reserved for the a-posteriori error estimate          */
+    double   est_err;    /* with params.probes = r > 0: 10 sqrt(2/pi) max_i
+                            ||(A - U S V^T) w_i||_2 over r Gaussian probes w_i
+                            (Philox, counter word 2 = stream_id ^ 0x80000000),
+                            an upper bound of ||A - U S V^T||_2 with probability
+                            at least 1 - 10^-r (Halko, Martinsson & Tropp, SIAM
+                            Review 2011, Sec. 4.3); for rpca_run the centred
+                            matrix and x V^T.  0 when probes = 0.               */
 } rsvd_info;
 
 #define RSVD_FLAG_CHOL_SHIFT   1u  /* a Gram matrix needed the shifted Cholesky    */

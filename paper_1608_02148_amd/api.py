@@ -51,10 +51,11 @@ def _apply_tuned_variants(lib, h, idx):
         pass
 
 
-def make_params(p=10, q=2, seed=0, stream_id=0, sdist="normal", precision="plain"):
+def make_params(p=10, q=2, seed=0, stream_id=0, sdist="normal", precision="plain", probes=0):
     prm = L.Params()
     L.load().rsvd_default_params(ctypes.byref(prm))
     prm.p, prm.q, prm.seed, prm.stream_id = int(p), int(q), int(seed), int(stream_id)
+    prm.probes = int(probes)
     prm.sdist = L.SDIST[sdist]
     prm.precision = L.PRECISION[precision]
     return prm
@@ -92,16 +93,17 @@ def workspace(nbytes, device):
 
 
 def rsvd(A, k, p=10, q=2, seed=0, stream_id=0, sdist="normal", precision="plain",
-         compute_u=True, compute_v=True, work=None, out=None, info=None):
+         compute_u=True, compute_v=True, work=None, out=None, info=None, probes=0):
     """Randomized SVD (Alg. RSVDalgorithm).  Returns (U m x k, S k, V n x k).
 
     U / V are None when not requested.  ``work`` (uint8 tensor) and ``out``
     (tuple U, S, V) may be passed to reuse buffers; ``info`` may be a 24-byte
-    uint8 device tensor receiving the device-side record.
+    uint8 device tensor receiving the device-side record; with ``probes`` > 0
+    its est_err holds the a-posteriori bound on ||A - U S V^T||_2.
     """
     dt = _check_matrix(A)
     m, n = A.shape
-    prm = make_params(p, q, seed, stream_id, sdist, precision)
+    prm = make_params(p, q, seed, stream_id, sdist, precision, probes)
     h = handle(A.device)
     nbytes = workspace_size(A, k, prm)
     if work is None or work.numel() < nbytes:
@@ -122,14 +124,14 @@ def rsvd(A, k, p=10, q=2, seed=0, stream_id=0, sdist="normal", precision="plain"
 
 
 def rpca(A, k, center=True, retx=True, p=10, q=2, seed=0, stream_id=0, sdist="normal",
-         precision="plain", work=None, info=None):
+         precision="plain", work=None, info=None, probes=0):
     """Randomized PCA (Alg. RPCAalgorithm) with implicit centring.
 
     Returns a dict: rotation (n x k), eigvals, sdev, x (m x k or None), center.
     """
     dt = _check_matrix(A)
     m, n = A.shape
-    prm = make_params(p, q, seed, stream_id, sdist, precision)
+    prm = make_params(p, q, seed, stream_id, sdist, precision, probes)
     h = handle(A.device)
     nbytes = workspace_size(A, k, prm)
     if work is None or work.numel() < nbytes:
@@ -205,12 +207,13 @@ class Batch:
     ``features=True``: run only the q = 0 sketches and fill ``features``
     (count x 131) with the selector inputs.  ``work``: optional uint8 device
     tensor reused as the workspace when large enough (owned by this batch
-    while it is alive).
+    while it is alive).  ``probes`` > 0: each info record's est_err receives
+    the a-posteriori error bound (needs ``infos=True`` to be read).
     """
 
     def __init__(self, As, ks, p=10, q=2, seed=0, stream_ids=None, sdist="normal", precision="plain",
                  compute_u=True, compute_v=True, graph=True, stamps=False, infos=False, qs=None, ps=None,
-                 features=False, work=None):
+                 features=False, work=None, probes=0):
         global _DESC_DTYPE
         if _DESC_DTYPE is None:
             _DESC_DTYPE = _desc_dtype()
@@ -266,7 +269,7 @@ class Batch:
         self._desc = d
         descs = d.ctypes.data_as(ctypes.c_void_p)
         self._As = list(As)            # keep the inputs alive as long as the batch
-        prm = make_params(p, q, seed, 0, sdist, precision)
+        prm = make_params(p, q, seed, 0, sdist, precision, 0 if features else probes)
         flags = (L.BATCH_GRAPH if graph else 0) | (L.BATCH_STAMPS if stamps else 0)
         flags |= (L.BATCH_FEATURES if features else 0) | (L.BATCH_OWN_QP if (qs is not None or ps is not None) else 0)
         self._lib = L.load()

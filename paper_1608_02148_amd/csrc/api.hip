@@ -517,8 +517,11 @@ int select_plan(rsvd_handle_t handle, int32_t dtype, int32_t count, const rsvd_b
                               : reinterpret_cast<float*>(static_cast<uintptr_t>(256));
         fd[i].U = nullptr; fd[i].V = nullptr; fd[i].S = nullptr; fd[i].info = nullptr;
     }
+    rsvd_params pp{};
+    if (params) { pp = *params; pp.probes = 0; }    // features need no error estimate
     size_t bb = 0;
-    const int st = rsvd_batch_create(handle, dtype, count, fd.data(), params, RSVD_BATCH_FEATURES, b, &bb);
+    const int st = rsvd_batch_create(handle, dtype, count, fd.data(), params ? &pp : nullptr, RSVD_BATCH_FEATURES,
+                                     b, &bb);
     if (st != RSVD_OK) return st;
     lay->batch_bytes = bb;
     lay->bytes = lay->batch_off + bb;

@@ -683,6 +683,7 @@ struct FinalizeBody {
         const double* sigma; int k; double* S; double* eigvals; double* sdev; double denom;
         const double* mu; int64_t n; TC* center_out; const uint32_t* status; rsvd_info* info;
         int l; int q; int p;
+        const double* est;        // a-posteriori bound or null
     };
     static constexpr int THREADS = 256;
     static int blocks(const Args& a) {
@@ -701,7 +702,75 @@ struct FinalizeBody {
         if (a.info && tid == 0) {
             a.info->l = a.l; a.info->q = a.q; a.info->p = a.p;
             a.info->flags = *a.status & 0xFF00FFFFu;   // RSVD_FLAG_* and the sweep count
-            a.info->est_err = 0.0;
+            a.info->est_err = a.est ? *a.est : 0.0;
+        }
+    }
+};
+
+// --------------------------------------------- a-posteriori error estimate
+// T[i][c] *= sigma_i for i < k, c < r (S V^T probes from V^T probes).
+template <typename TC>
+struct ScaleRowsBody {
+    struct Args { TC* T; int ldt; int k; int r; const double* sigma; };
+    static constexpr int THREADS = 256;
+    static int blocks(const Args& a) { return static_cast<int>(cdiv(static_cast<int64_t>(a.k) * 32, THREADS)); }
+    static size_t lds(const Args&) { return 0; }
+    static __device__ void run(const Args& a, int b) {
+        const int idx = b * THREADS + threadIdx.x;
+        const int i = idx / 32, c = idx % 32;
+        if (i < a.k && c < a.r) a.T[i * a.ldt + c] = static_cast<TC>(static_cast<double>(a.T[i * a.ldt + c]) * a.sigma[i]);
+    }
+};
+
+// part[b][c] = sum over rows of chunk b of (Y[i][c] - W[i][c])^2 (c < r <= 32),
+// rows of a chunk in a fixed order (8 row lanes, then a fixed tree).
+template <typename TC>
+struct DiffNormBody {
+    struct Args { const TC* Y; const TC* W; int ld; int64_t m; int r; int S; double* part; };
+    static constexpr int THREADS = 256;
+    static int blocks(const Args& a) { return a.S; }
+    static size_t lds(const Args&) { return 0; }
+    static __device__ void run(const Args& a, int b) {
+        __shared__ double acc[8][32];
+        const int c = threadIdx.x % 32, j = threadIdx.x / 32;
+        const int64_t rows = cdiv(a.m, a.S), r0 = static_cast<int64_t>(b) * rows, r1 = min(a.m, r0 + rows);
+        double s = 0.0;
+        if (c < a.r)
+            for (int64_t i = r0 + j; i < r1; i += 8) {
+                const double d = static_cast<double>(a.Y[i * a.ld + c]) - static_cast<double>(a.W[i * a.ld + c]);
+                s += d * d;
+            }
+        acc[j][c] = s;
+        __syncthreads();
+        if (j == 0) {
+            double t = 0.0;
+            for (int q = 0; q < 8; ++q) t += acc[q][c];
+            a.part[static_cast<int64_t>(b) * 32 + c] = t;
+        }
+    }
+};
+
+// est = 10 sqrt(2/pi) max_c sqrt(sum_b part[b][c]) (Halko, Martinsson &
+// Tropp 2011, Sec. 4.3).
+struct EstBody {
+    struct Args { const double* part; int S; int r; double* est; };
+    static constexpr int THREADS = 64;
+    static int blocks(const Args&) { return 1; }
+    static size_t lds(const Args&) { return 0; }
+    static __device__ void run(const Args& a, int) {
+        __shared__ double nrm[32];
+        const int c = threadIdx.x;
+        if (c < 32) {
+            double t = 0.0;
+            if (c < a.r)
+                for (int b = 0; b < a.S; ++b) t += a.part[static_cast<int64_t>(b) * 32 + c];
+            nrm[c] = sqrt(t);
+        }
+        __syncthreads();
+        if (c == 0) {
+            double mx = 0.0;
+            for (int q = 0; q < a.r; ++q) mx = fmax(mx, nrm[q]);
+            *a.est = 10.0 * sqrt(2.0 / 3.14159265358979323846) * mx;
         }
     }
 };

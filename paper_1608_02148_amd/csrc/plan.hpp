@@ -89,6 +89,10 @@ struct Plan {
     Splits sp{};
     size_t Y = 0, Z = 0, Om = 0, part = 0, gram = 0, rinv = 0, racc = 0, sigma = 0,
            xv = 0, xu = 0, jk = 0, wks = 0, vtmp = 0, mu = 0, mupart = 0, status = 0, bytes = 0;
+    // a-posteriori estimate (probes > 0): probes n x 32, A probes and U (S V^T
+    // probes) m x 32, V^T probes k x 32, U scratch m x k, column partial sums
+    int probes = 0, est_split = 1;
+    size_t eOm = 0, eY = 0, eT = 0, eW = 0, eU = 0, epart = 0, est = 0;
 };
 
 inline int validate(int32_t dtype, int64_t m, int64_t n, int32_t k, const rsvd_params* prm) {
@@ -98,6 +102,7 @@ inline int validate(int32_t dtype, int64_t m, int64_t n, int32_t k, const rsvd_p
     if (prm->sdist < RSVD_NORMAL || prm->sdist > RSVD_RADEMACHER) return RSVD_ERR_INVALID;
     if (prm->precision != RSVD_PREC_PLAIN && prm->precision != RSVD_PREC_BF16_MIXED) return RSVD_ERR_UNSUPPORTED;
     if (prm->precision == RSVD_PREC_BF16_MIXED && dtype == RSVD_F64) return RSVD_ERR_UNSUPPORTED;
+    if (prm->probes < 0 || prm->probes > 16) return RSVD_ERR_INVALID;
     if (m > (int64_t(1) << 32) || n > (int64_t(1) << 32)) return RSVD_ERR_UNSUPPORTED;
     const int64_t l = std::min<int64_t>(static_cast<int64_t>(k) + prm->p, std::min(m, n));
     if (l > RSVD_MAX_L) return RSVD_ERR_UNSUPPORTED;
@@ -150,6 +155,17 @@ inline Plan make_plan(int dtype, int64_t m, int64_t n, int k, const rsvd_params*
     P.vtmp = L.take(static_cast<size_t>(n) * P.kp * cs);
     P.mu = L.take(static_cast<size_t>(n) * 8);
     P.mupart = L.take(static_cast<size_t>(P.sp.colsum) * n * 8);
+    P.probes = prm->probes;
+    if (P.probes > 0) {
+        P.est_split = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(cdiv(m, 2048), 256)));
+        P.eOm = L.take(static_cast<size_t>(n) * 32 * cs);
+        P.eY = L.take(static_cast<size_t>(m) * 32 * cs);
+        P.eT = L.take(static_cast<size_t>(P.kp) * 32 * cs);
+        P.eW = L.take(static_cast<size_t>(m) * 32 * cs);
+        P.eU = L.take(static_cast<size_t>(m) * P.kp * cs);
+        P.epart = L.take(static_cast<size_t>(std::max(P.est_split, P.sp.gram_n)) * 32 * P.kp * 8);
+        P.est = L.take(sizeof(double));
+    }
     P.bytes = L.off;
     return P;
 }

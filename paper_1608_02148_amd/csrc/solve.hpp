@@ -218,9 +218,49 @@ hipError_t solve_steps(Ex& ex, rsvd_handle_t prof, const Plan& P, const TA* A, i
     if (o.U)
         RSVD_TRY((gemm_plain<TC, TC, TC, MODE_NN>(ex, tile, false, Y, Lp, m, l, xu, P.kp, k, static_cast<TC*>(o.U), o.ldu,
                                                   1, 0, nullptr, nullptr, 0)));
+    // A-posteriori bound from r Gaussian probes w (Halko, Martinsson & Tropp
+    // 2011, Sec. 4.3): one more pass over A for A w, then U (S (V^T w)).
+    double* est = nullptr;
+    if (P.probes > 0) {
+        const int r = P.probes;
+        TC* eOm = at<TC>(work, P.eOm);
+        TC* eY = at<TC>(work, P.eY);
+        TC* eT = at<TC>(work, P.eT);
+        TC* eW = at<TC>(work, P.eW);
+        double* epart = at<double>(work, P.epart);
+        est = at<double>(work, P.est);
+        const TC* Uu = static_cast<const TC*>(o.U);
+        int64_t ldu = o.ldu;
+        if (!o.U) {
+            RSVD_TRY((gemm_plain<TC, TC, TC, MODE_NN>(ex, tile, false, Y, Lp, m, l, xu, P.kp, k, at<TC>(work, P.eU),
+                                                      P.kp, 1, 0, nullptr, nullptr, 0)));
+            Uu = at<TC>(work, P.eU);
+            ldu = P.kp;
+        }
+        RSVD_TRY(ex.template run<OmegaBody<TC>>(typename OmegaBody<TC>::Args{
+            n, r, 32, prm->seed, stream_id ^ 0x80000000u, RSVD_NORMAL, eOm, 32}));
+        RSVD_TRY((gemm_step<TA, TC, MODE_NN>(ex, late, 32, A, lda, m, n, eOm, 32, r, eY, 32, 1, 0, mu, nullptr, 0)));
+        const int S = P.sp.gram_n;
+        if (S == 1) {
+            RSVD_TRY((gemm_plain<TC, TC, TC, MODE_TN>(ex, 32, false, V, ldv, k, n, eOm, 32, r, eT, 32, 1, 0, nullptr,
+                                                      nullptr, 0)));
+        } else {
+            TC* tp = reinterpret_cast<TC*>(epart);
+            RSVD_TRY((gemm_plain<TC, TC, TC, MODE_TN>(ex, 32, false, V, ldv, k, n, eOm, 32, r, tp, 32, S,
+                                                      static_cast<int64_t>(P.kp) * 32, nullptr, nullptr, 0)));
+            RSVD_TRY(reduce_step<TC>(ex, tp, S, static_cast<int64_t>(P.kp) * 32, 32, k, r, eT, 32));
+        }
+        if (!o.scale_u)
+            RSVD_TRY(ex.template run<ScaleRowsBody<TC>>(typename ScaleRowsBody<TC>::Args{eT, 32, k, r, sigma}));
+        RSVD_TRY((gemm_plain<TC, TC, TC, MODE_NN>(ex, 32, false, Uu, ldu, m, k, eT, 32, r, eW, 32, 1, 0, nullptr,
+                                                  nullptr, 0)));
+        RSVD_TRY(ex.template run<DiffNormBody<TC>>(typename DiffNormBody<TC>::Args{eY, eW, 32, m, r, P.est_split,
+                                                                                  epart}));
+        RSVD_TRY(ex.template run<EstBody>(EstBody::Args{epart, P.est_split, r, est}));
+    }
     RSVD_TRY(ex.template run<FinalizeBody<TC>>(typename FinalizeBody<TC>::Args{
         sigma, k, o.S, o.eigvals, o.sdev, static_cast<double>(m - 1), mu, n, static_cast<TC*>(o.center_out),
-        status, o.info, l, P.q, P.p}));
+        status, o.info, l, P.q, P.p, est}));
     if (o.stamps) RSVD_TRY(ex.template run<StampBody>(StampBody::Args{o.stamps + 1}));
     return hipSuccess;
 }

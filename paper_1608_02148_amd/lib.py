@@ -27,7 +27,7 @@ MAX_L = 128
 
 class Params(ctypes.Structure):
     _fields_ = [("p", c_int32), ("q", c_int32), ("seed", c_uint64), ("stream_id", c_uint32),
-                ("sdist", c_int32), ("precision", c_int32), ("reserved", c_int32 * 3)]
+                ("sdist", c_int32), ("precision", c_int32), ("probes", c_int32), ("reserved", c_int32 * 2)]
 
 
 class Info(ctypes.Structure):
