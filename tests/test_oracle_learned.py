@@ -18,6 +18,7 @@ import numpy as np
 import pytest
 
 from oracle import learned as lrn
+from oracle import philox
 from oracle import mlp
 from oracle import rsvd as orc
 from synth import matrices as syn
@@ -143,3 +144,18 @@ def test_posterior_estimate_bounds_the_error():
     true = np.linalg.norm(A - (U * s[None, :]) @ V.T, 2)
     hits = sum(lrn.posterior_estimate(A, U, s, V, r=10, seed=100 + t) >= true for t in range(20))
     assert hits == 20
+
+
+def test_posterior_estimate_rank_one_residual_closed_form():
+    """R = A - U S V^T = sigma a b^T gives ||R w_i|| = sigma ||a|| |b^T w_i|
+    exactly, so the estimate is 10 sqrt(2/pi) sigma ||a|| max_i |b^T w_i|."""
+    rng = np.random.default_rng(4)
+    m, n, k, r = 60, 40, 5, 7
+    U = np.linalg.qr(rng.standard_normal((m, k)))[0]
+    V = np.linalg.qr(rng.standard_normal((n, k)))[0]
+    s = np.sort(rng.uniform(1, 3, k))[::-1]
+    a, b, sig = rng.standard_normal(m), rng.standard_normal(n), 0.37
+    A = (U * s) @ V.T + sig * np.outer(a, b)
+    W = philox.test_matrix(n, r, 12, 34)
+    want = 10.0 * np.sqrt(2.0 / np.pi) * sig * np.linalg.norm(a) * np.max(np.abs(b @ W))
+    assert lrn.posterior_estimate(A, U, s, V, r=r, seed=12, stream_id=34) == pytest.approx(want, rel=1e-12)
