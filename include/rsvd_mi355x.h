@@ -254,6 +254,38 @@ int rsvd_select(rsvd_handle_t handle, int32_t dtype, int32_t count, const rsvd_b
                 const rsvd_params* params, const float* theta, float tau, int32_t* q_out,
                 int32_t* p_out, float* features_out, void* work, size_t work_bytes);
 
+/* Learned batch: the selector and the solves in one stream-ordered launch
+ * sequence with no host round trip (one graph with RSVD_BATCH_GRAPH).  A run
+ * takes three phases: (1) for every matrix the q = 0 sketch Y0 = A Omega[:, :l0]
+ * (l0 as for the selector features below) and its 131 features; (2) the
+ * network on all features and, per matrix, q_b = the fewest power iterations
+ * whose classes (q' <= q_b, any p') hold at least tau of the network's
+ * probability mass (tau <= 0: the q of the most probable class); theta = NULL
+ * skips the network and takes q_b = RSVD_LEARNED_FALLBACK_Q for every matrix;
+ * (3) every solve with its own q_b (<= RSVD_LEARNED_QMAX; the extra
+ * iterations of its group are switched off on the device) and p = params->p
+ * (0..RSVD_LEARNED_PMAX), starting from the leading l = min(k + p, m, n)
+ * columns of Y0 instead of a new sketch: Omega's entries do not depend on its
+ * width, so these are the columns of the solve's own A Omega.  Sec. 3.6 fixes
+ * only defaults for q and p and Sec. 2.2 advises more iterations for slowly
+ * decaying spectra; the network supplies the per-matrix choice.
+ * descs: as rsvd_batch_create (q, p and features are not read); params: seed,
+ * test matrix, precision, p and probes (params.q is not read); flags:
+ * RSVD_BATCH_GRAPH and RSVD_BATCH_STAMPS only (stamps span all three phases).
+ * theta: device vector of RSVD_MLP_PARAMS floats or NULL, read at every run.
+ * Life cycle and workspace: as rsvd_batch_create / bind / run / destroy.
+ * info records report q_b and l. */
+#define RSVD_LEARNED_QMAX       4
+#define RSVD_LEARNED_PMAX       20
+#define RSVD_LEARNED_FALLBACK_Q 3
+int rsvd_batch_create_learned(rsvd_handle_t handle, int32_t dtype, int32_t count,
+                              const rsvd_batch_desc* descs, const rsvd_params* params,
+                              const float* theta, float tau, int32_t flags,
+                              rsvd_batch_t* batch, size_t* work_bytes);
+/* Learned batches: synchronise and copy the q chosen for each matrix by the
+ * last run into the HOST array q_host (count int32). */
+int rsvd_batch_choices(rsvd_batch_t batch, int32_t* q_host);
+
 /* ---- Learned choice of (q, p): the selector network ---------------------
  * A three-layer perceptron reads 131 features of a matrix (the singular values
  * of its q = 0 sketch Y0 = A Omega[:, :l0], l0 = min(max(2k, k + 20), m, n,

@@ -209,11 +209,17 @@ class Batch:
     tensor reused as the workspace when large enough (owned by this batch
     while it is alive).  ``probes`` > 0: each info record's est_err receives
     the a-posteriori error bound (needs ``infos=True`` to be read).
+    ``learned=True`` (rsvd_batch_create_learned): q chosen per matrix on the
+    device by the selector network ``theta`` (a device f32 tensor of
+    MLP_PARAMS values, or None for q = LEARNED_FALLBACK_Q everywhere) with
+    threshold ``tau``, every solve with oversampling ``p`` (<= LEARNED_PMAX)
+    and starting from its q = 0 sketch; ``q``, ``qs``, ``ps`` are not used and
+    ``choices()`` returns the q of the last run.
     """
 
     def __init__(self, As, ks, p=10, q=2, seed=0, stream_ids=None, sdist="normal", precision="plain",
                  compute_u=True, compute_v=True, graph=True, stamps=False, infos=False, qs=None, ps=None,
-                 features=False, work=None, probes=0):
+                 features=False, work=None, probes=0, learned=False, theta=None, tau=0.8):
         global _DESC_DTYPE
         if _DESC_DTYPE is None:
             _DESC_DTYPE = _desc_dtype()
@@ -276,8 +282,18 @@ class Batch:
         self._h = handle(dev)
         self._b = ctypes.c_void_p()
         nbytes = ctypes.c_size_t()
-        L.check(self._lib.rsvd_batch_create(self._h, self.dtype, self.count, descs, ctypes.byref(prm), flags,
-                                            ctypes.byref(self._b), ctypes.byref(nbytes)), "rsvd_batch_create")
+        self.learned = bool(learned)
+        if self.learned:
+            if features or qs is not None or ps is not None:
+                raise ValueError("a learned batch chooses q itself and computes its own features")
+            self._theta = theta            # read by every run: keep it alive
+            flags &= L.BATCH_GRAPH | L.BATCH_STAMPS
+            L.check(self._lib.rsvd_batch_create_learned(self._h, self.dtype, self.count, descs, ctypes.byref(prm),
+                                                        _ptr(theta), float(tau), flags, ctypes.byref(self._b),
+                                                        ctypes.byref(nbytes)), "rsvd_batch_create_learned")
+        else:
+            L.check(self._lib.rsvd_batch_create(self._h, self.dtype, self.count, descs, ctypes.byref(prm), flags,
+                                                ctypes.byref(self._b), ctypes.byref(nbytes)), "rsvd_batch_create")
         self.work_bytes = nbytes.value
         # a caller-provided workspace (uint8 tensor) is used when large enough;
         # it must not be shared with another live batch
@@ -296,6 +312,13 @@ class Batch:
         L.check(self._lib.rsvd_batch_stamps(self._b, out.ctypes.data_as(ctypes.c_void_p), ctypes.byref(hz)),
                 "rsvd_batch_stamps")
         return out.astype(np.int64), hz.value
+
+    def choices(self):
+        """Learned batches: the q chosen for each matrix by the last run (synchronises)."""
+        import numpy as np
+        out = np.zeros(self.count, dtype=np.int32)
+        L.check(self._lib.rsvd_batch_choices(self._b, out.ctypes.data_as(ctypes.c_void_p)), "rsvd_batch_choices")
+        return out
 
     def infos(self):
         """Decode the per-matrix info records (synchronises)."""

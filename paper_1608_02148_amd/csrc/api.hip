@@ -223,6 +223,17 @@ struct rsvd_batch_s {
     std::vector<rsvd::Plan> plans;
     std::vector<size_t> offs;
     std::vector<rsvd::BatchGroup> groups;
+    // learned batches: a first phase of q = 0 sketches and selector features
+    // (plans0 / groups0, workspaces at offs0), the network and the choice of
+    // q on the device, then the solves (plans / groups), which start from the
+    // first phase's sketches
+    bool learned = false;
+    std::vector<rsvd::Plan> plans0;
+    std::vector<size_t> offs0;
+    std::vector<rsvd::BatchGroup> groups0;
+    const float* theta = nullptr;
+    float tau = 0.8f;
+    size_t feat_off = 0, prob_off = 0, q_off = 0;
     size_t stamps_off = 0, bytes = 0;
     void* work = nullptr;
     hipStream_t cap = nullptr;
@@ -236,11 +247,14 @@ namespace rsvd {
 // Records the group's steps.  host = null: the first `limit` members into the
 // recorder's own arrays (planning); otherwise every member directly into the
 // packed host layout at host (binding), using the step list already recorded.
-hipError_t record_group(rsvd_batch_s* B, BatchGroup& g, void* base, size_t limit = SIZE_MAX,
+// phase 0: the features phase of a learned batch; phase 1: the solves.
+hipError_t record_group(rsvd_batch_s* B, BatchGroup& g, int phase, void* base, size_t limit = SIZE_MAX,
                         unsigned char* host = nullptr) {
     if (host) g.rec.begin_direct(host, static_cast<int>(g.members.size()));
     else g.rec.clear();
     const bool stamps = (B->flags & RSVD_BATCH_STAMPS) != 0;
+    const std::vector<Plan>& plans = phase == 0 ? B->plans0 : B->plans;
+    const std::vector<size_t>& offs = phase == 0 ? B->offs0 : B->offs;
     for (size_t mi = 0; mi < g.members.size() && mi < limit; ++mi) {
         const int i = g.members[mi];
         const rsvd_batch_desc& d = B->desc[i];
@@ -248,13 +262,22 @@ hipError_t record_group(rsvd_batch_s* B, BatchGroup& g, void* base, size_t limit
         o.U = d.U; o.ldu = d.ldu; o.V = d.V; o.ldv = d.ldv; o.S = d.S; o.info = d.info;
         o.stamps = stamps ? at<uint64_t>(base, B->stamps_off) + 2 * static_cast<size_t>(i) : nullptr;
         if (B->flags & RSVD_BATCH_FEATURES) { o.features = d.features; o.feat_k = d.k; o.S = nullptr; o.U = nullptr; }
+        if (B->learned && phase == 0) {
+            o.features = at<float>(base, B->feat_off) + static_cast<size_t>(i) * RSVD_MLP_INPUTS;
+            o.feat_k = d.k; o.S = nullptr; o.U = nullptr; o.V = nullptr; o.info = nullptr;
+            o.stamp_sel = 1;
+        } else if (B->learned) {
+            o.qsrc = at<int32_t>(base, B->q_off) + i;
+            o.y0 = at<unsigned char>(base, B->offs0[i] + B->plans0[i].Y);
+            o.stamp_sel = 2;
+        }
         g.rec.begin_problem();
-        void* w = at<unsigned char>(base, B->offs[i]);
+        void* w = at<unsigned char>(base, offs[i]);
         hipError_t e = hipErrorInvalidValue;
         switch (B->dtype) {
-            case RSVD_F64: e = solve_record_f64(g.rec, B->plans[i], d.A, d.lda, &B->prm, d.stream_id, o, w); break;
-            case RSVD_F32: e = solve_record_f32(g.rec, B->plans[i], d.A, d.lda, &B->prm, d.stream_id, o, w); break;
-            case RSVD_BF16: e = solve_record_bf16(g.rec, B->plans[i], d.A, d.lda, &B->prm, d.stream_id, o, w); break;
+            case RSVD_F64: e = solve_record_f64(g.rec, plans[i], d.A, d.lda, &B->prm, d.stream_id, o, w); break;
+            case RSVD_F32: e = solve_record_f32(g.rec, plans[i], d.A, d.lda, &B->prm, d.stream_id, o, w); break;
+            case RSVD_BF16: e = solve_record_bf16(g.rec, plans[i], d.A, d.lda, &B->prm, d.stream_id, o, w); break;
         }
         RSVD_TRY(e);
         if (!g.rec.complete()) return hipErrorInvalidValue;
@@ -263,32 +286,51 @@ hipError_t record_group(rsvd_batch_s* B, BatchGroup& g, void* base, size_t limit
 }
 
 inline hipError_t record_all(rsvd_batch_s* B, void* base, unsigned char* host) {
-    for (BatchGroup& g : B->groups) RSVD_TRY(record_group(B, g, base, SIZE_MAX, host + g.table_off));
+    for (BatchGroup& g : B->groups0) RSVD_TRY(record_group(B, g, 0, base, SIZE_MAX, host + g.table_off));
+    for (BatchGroup& g : B->groups) RSVD_TRY(record_group(B, g, 1, base, SIZE_MAX, host + g.table_off));
     return hipSuccess;
 }
+
+constexpr int kLearnedFallbackQ = RSVD_LEARNED_FALLBACK_Q;
 
 // Group g runs on lane g % lanes: lane 0 is the caller's stream, the others
 // are side streams forked from it and joined back with events.
 constexpr size_t kMaxLanes = 6;
 
-inline size_t lanes_of(const rsvd_batch_s* B) { return std::min(B->groups.size(), kMaxLanes); }
+inline size_t lanes_of(const rsvd_batch_s* B) {
+    return std::min(std::max(B->groups.size(), B->groups0.size()), kMaxLanes);
+}
 
-// The side streams belong to the handle, so planning a batch creates none.
-inline hipError_t launch_all(const rsvd_batch_s* B, hipStream_t st) {
+// One phase: fork the lanes from st, groups round-robin over them, join back.
+inline hipError_t launch_groups(const rsvd_batch_s* B, const std::vector<BatchGroup>& groups, hipStream_t st) {
     const unsigned char* base = static_cast<const unsigned char*>(B->work);
-    const size_t lanes = lanes_of(B);
+    const size_t lanes = std::min(groups.size(), kMaxLanes);
     rsvd_handle_t h = B->h;
     if (lanes > 1) RSVD_TRY(hipEventRecord(h->fork, st));
     for (size_t s = 1; s < lanes; ++s) RSVD_TRY(hipStreamWaitEvent(h->side[s - 1], h->fork, 0));
-    for (size_t g = 0; g < B->groups.size(); ++g) {
+    for (size_t g = 0; g < groups.size(); ++g) {
         hipStream_t ls = (g % lanes == 0) ? st : h->side[g % lanes - 1];
-        RSVD_TRY(B->groups[g].rec.launch(base + B->groups[g].table_off, ls));
+        RSVD_TRY(groups[g].rec.launch(base + groups[g].table_off, ls));
     }
     for (size_t s = 1; s < lanes; ++s) {
         RSVD_TRY(hipEventRecord(h->side_done[s - 1], h->side[s - 1]));
         RSVD_TRY(hipStreamWaitEvent(st, h->side_done[s - 1], 0));
     }
     return hipSuccess;
+}
+
+// The side streams belong to the handle, so planning a batch creates none.
+// A learned batch runs its features phase, then the network and the choice
+// of q for every matrix, then the solves, all stream-ordered on st.
+inline hipError_t launch_all(const rsvd_batch_s* B, hipStream_t st) {
+    if (B->learned) {
+        unsigned char* base = static_cast<unsigned char*>(B->work);
+        RSVD_TRY(launch_groups(B, B->groups0, st));
+        RSVD_TRY(learned_choose_q(st, B->theta, static_cast<int>(B->desc.size()), at<float>(base, B->feat_off),
+                                  at<float>(base, B->prob_off), B->tau, kLearnedFallbackQ,
+                                  at<int32_t>(base, B->q_off)));
+    }
+    return launch_groups(B, B->groups, st);
 }
 
 inline hipError_t make_side_streams(rsvd_batch_s* B) {
@@ -304,6 +346,41 @@ inline hipError_t make_side_streams(rsvd_batch_s* B) {
         h->side_done.push_back(e);
     }
     return hipSuccess;
+}
+
+// Groups of one phase by tile class; each group issues its largest q.
+inline void build_groups(std::vector<Plan>& plans, std::vector<BatchGroup>& out) {
+    const int count = static_cast<int>(plans.size());
+    for (int tile : {128, 96, 80, 64, 48, 32}) {
+        BatchGroup g;
+        g.tile = tile;
+        for (int32_t i = 0; i < count; ++i)
+            if (plans[i].tile == tile) {
+                g.members.push_back(i);
+                g.q = std::max(g.q, plans[i].q);
+            }
+        if (g.members.empty()) continue;
+        for (int i : g.members) plans[i].qmax = g.q;
+        // most work first: passes over A times the sketch width
+        std::stable_sort(g.members.begin(), g.members.end(), [&](int a, int b) {
+            const Plan &pa = plans[a], &pb = plans[b];
+            return static_cast<double>(pa.m) * pa.n * pa.l * (pa.q + 1) >
+                   static_cast<double>(pb.m) * pb.n * pb.l * (pb.q + 1);
+        });
+        out.push_back(std::move(g));
+    }
+}
+
+// Sizes the step tables of one phase by recording one member per group
+// (every member issues the same steps, and their sizes do not depend on the
+// addresses), placing them in L.
+inline bool size_tables(rsvd_batch_s* B, std::vector<BatchGroup>& groups, int phase, Layout& L) {
+    void* fake = reinterpret_cast<void*>(static_cast<uintptr_t>(1) << 44);
+    for (BatchGroup& g : groups) {
+        if (record_group(B, g, phase, fake, 1) != hipSuccess) return false;
+        g.table_off = L.take(g.rec.packed_bytes_for(static_cast<int>(g.members.size())));
+    }
+    return true;
 }
 
 inline void drop_graph(rsvd_batch_s* B) {
@@ -353,33 +430,10 @@ int rsvd_batch_create(rsvd_handle_t handle, int32_t dtype, int32_t count, const 
     for (int32_t i = 0; i < count; ++i)
         B->plans[i] = make_plan(dtype, descs[i].m, descs[i].n, descs[i].k, &prm[i], handle->dev.num_cu, true,
                                 handle->variants);
-    for (int tile : {128, 96, 80, 64, 48, 32}) {
-        BatchGroup g;
-        g.tile = tile;
-        for (int32_t i = 0; i < count; ++i)
-            if (B->plans[i].tile == tile) {
-                g.members.push_back(i);
-                g.q = std::max(g.q, B->plans[i].q);
-            }
-        if (g.members.empty()) continue;
-        for (int i : g.members) B->plans[i].qmax = g.q;
-        // most work first: passes over A times the sketch width
-        std::stable_sort(g.members.begin(), g.members.end(), [&](int a, int b) {
-            const Plan &pa = B->plans[a], &pb = B->plans[b];
-            return static_cast<double>(pa.m) * pa.n * pa.l * (pa.q + 1) >
-                   static_cast<double>(pb.m) * pb.n * pb.l * (pb.q + 1);
-        });
-        B->groups.push_back(std::move(g));
-    }
-    // Size the step tables by recording one member per group (every member
-    // issues the same steps, and their sizes do not depend on the addresses).
-    void* fake = reinterpret_cast<void*>(static_cast<uintptr_t>(1) << 44);
+    build_groups(B->plans, B->groups);
     B->offs.assign(count, 0);
     Layout L;
-    for (BatchGroup& g : B->groups) {
-        if (record_group(B, g, fake, 1) != hipSuccess) { delete B; return RSVD_ERR_UNSUPPORTED; }
-        g.table_off = L.take(g.rec.packed_bytes_for(static_cast<int>(g.members.size())));
-    }
+    if (!size_tables(B, B->groups, 1, L)) { delete B; return RSVD_ERR_UNSUPPORTED; }
     B->tables_bytes = L.off;
     B->stamps_off = L.take(2 * sizeof(uint64_t) * static_cast<size_t>(count));
     for (int32_t i = 0; i < count; ++i) B->offs[i] = L.take(B->plans[i].bytes);
@@ -387,6 +441,78 @@ int rsvd_batch_create(rsvd_handle_t handle, int32_t dtype, int32_t count, const 
     *batch = B;
     *work_bytes = B->bytes;
     return RSVD_OK;
+}
+
+int rsvd_batch_create_learned(rsvd_handle_t handle, int32_t dtype, int32_t count, const rsvd_batch_desc* descs,
+                              const rsvd_params* params, const float* theta, float tau, int32_t flags,
+                              rsvd_batch_t* batch, size_t* work_bytes) {
+    if (!handle || count < 1 || !descs || !params || !batch || !work_bytes) return RSVD_ERR_INVALID;
+    if (flags & ~(RSVD_BATCH_GRAPH | RSVD_BATCH_STAMPS)) return RSVD_ERR_INVALID;
+    if (params->p < 0 || params->p > RSVD_LEARNED_PMAX || !(tau <= 1.0f)) return RSVD_ERR_INVALID;
+    const bool with_u = descs[0].U != nullptr;
+    std::vector<rsvd_params> prm0(count, *params), prm1(count, *params);
+    for (int32_t i = 0; i < count; ++i) {
+        const rsvd_batch_desc& d = descs[i];
+        // features phase: q = 0 sketch of width l0 = min(max(2k, k + 20), m, n, RSVD_MAX_L);
+        // solves: q chosen on the device (at most RSVD_LEARNED_QMAX), p = params->p
+        prm0[i].q = 0;
+        prm0[i].probes = 0;
+        const int64_t l0 = std::min<int64_t>(std::min<int64_t>(std::max(2 * d.k, d.k + 20), RSVD_MAX_L),
+                                             std::min(d.m, d.n));
+        prm0[i].p = static_cast<int32_t>(std::max<int64_t>(0, l0 - d.k));
+        prm1[i].q = RSVD_LEARNED_QMAX;
+        int v = validate(dtype, d.m, d.n, d.k, &prm0[i]);
+        if (v == RSVD_OK) v = validate(dtype, d.m, d.n, d.k, &prm1[i]);
+        if (v != RSVD_OK) return v;
+        if (!d.A || d.lda < d.n || !d.S) return RSVD_ERR_INVALID;
+        if ((d.U != nullptr) != with_u || (d.U && d.ldu < d.k) || (d.V && d.ldv < d.k)) return RSVD_ERR_INVALID;
+    }
+    rsvd_batch_s* B = new rsvd_batch_s();
+    B->h = handle; B->dtype = dtype; B->flags = flags; B->prm = *params;
+    B->learned = true; B->theta = theta; B->tau = tau;
+    B->desc.assign(descs, descs + count);
+    B->plans0.resize(count);
+    B->plans.resize(count);
+    for (int32_t i = 0; i < count; ++i) {
+        const rsvd_batch_desc& d = descs[i];
+        B->plans0[i] = make_plan(dtype, d.m, d.n, d.k, &prm0[i], handle->dev.num_cu, true, handle->variants);
+        // the solve's bases share the sketch's leading dimension, so its
+        // first l columns are the solve's Y as they stand
+        B->plans[i] = make_plan(dtype, d.m, d.n, d.k, &prm1[i], handle->dev.num_cu, true, handle->variants,
+                                B->plans0[i].Lp);
+        if (B->plans[i].l > B->plans0[i].l || B->plans[i].Lp != B->plans0[i].Lp) { delete B; return RSVD_ERR_UNSUPPORTED; }
+    }
+    build_groups(B->plans0, B->groups0);
+    build_groups(B->plans, B->groups);
+    B->offs0.assign(count, 0);
+    B->offs.assign(count, 0);
+    Layout L;
+    if (!size_tables(B, B->groups0, 0, L) || !size_tables(B, B->groups, 1, L)) {
+        delete B;
+        return RSVD_ERR_UNSUPPORTED;
+    }
+    B->tables_bytes = L.off;
+    B->stamps_off = L.take(2 * sizeof(uint64_t) * static_cast<size_t>(count));
+    B->feat_off = L.take(static_cast<size_t>(count) * RSVD_MLP_INPUTS * sizeof(float));
+    B->prob_off = L.take(static_cast<size_t>(count) * RSVD_MLP_CLASSES * sizeof(float));
+    B->q_off = L.take(static_cast<size_t>(count) * sizeof(int32_t));
+    for (int32_t i = 0; i < count; ++i) {
+        B->offs0[i] = L.take(B->plans0[i].bytes);
+        B->offs[i] = L.take(B->plans[i].bytes);
+    }
+    B->bytes = L.off;
+    *batch = B;
+    *work_bytes = B->bytes;
+    return RSVD_OK;
+}
+
+int rsvd_batch_choices(rsvd_batch_t batch, int32_t* q_host) {
+    if (!batch || !batch->work || !batch->learned || !q_host) return RSVD_ERR_INVALID;
+    rsvd_handle_t h = batch->h;
+    hipError_t e = hipMemcpyAsync(q_host, static_cast<unsigned char*>(batch->work) + batch->q_off,
+                                  sizeof(int32_t) * batch->desc.size(), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    return hip_status(h, e);
 }
 
 int rsvd_batch_bind(rsvd_batch_t batch, void* work, size_t work_bytes) {

@@ -67,7 +67,7 @@ struct Gate { const uint32_t* w = nullptr; uint32_t mask = 0u; };
 // last; bit 16: q = 0 (the first sketch is the last); bit 17: q > 0.
 enum : uint32_t { IT_LAST_SHIFT = 8, IT_Q0 = 1u << 16, IT_QPOS = 1u << 17 };
 
-__host__ inline uint32_t iteration_word(int q, int qmax) {
+__host__ __device__ inline uint32_t iteration_word(int q, int qmax) {
     uint32_t w = q == 0 ? IT_Q0 : IT_QPOS;
     for (int it = 0; it < qmax; ++it) {
         if (it < q - 1) w |= 1u << it;
@@ -89,6 +89,13 @@ struct DeviceInfo {
     int num_cu = 256;
     int device = 0;
 };
+
+// Learned q per matrix, on stream st (defined with the selector network):
+// network forward on feat (count x 131) into prob (count x 15), then q[b] =
+// the fewest iterations whose (q', p') pairs hold mass >= tau.  theta null:
+// q[b] = fallback_q and neither feat nor prob is read.
+hipError_t learned_choose_q(hipStream_t st, const float* theta, int count, const float* feat, float* prob,
+                            float tau, int fallback_q, int32_t* q);
 
 }  // namespace rsvd
 

@@ -21,15 +21,16 @@ namespace rsvd {
 
 // Status words are cleared by a kernel rather than a memset node, so the whole
 // launch sequence stays safe to capture in a HIP graph.
-// p[0] = 0 and, when count = 2, p[1] = v1 (the iteration word).
+// p[0] = 0 and, when count = 2, p[1] = v1 (the iteration word), or with qsrc
+// the word for q = *qsrc out of qmax (q chosen on the device).
 struct ClearBody {
-    struct Args { uint32_t* p; int count; uint32_t v1; };
+    struct Args { uint32_t* p; int count; uint32_t v1; const int32_t* qsrc; int qmax; };
     static constexpr int THREADS = 64;
     static int blocks(const Args& a) { return static_cast<int>(cdiv(a.count, THREADS)); }
     static size_t lds(const Args&) { return 0; }
     static __device__ void run(const Args& a, int b) {
         const int i = b * THREADS + threadIdx.x;
-        if (i < a.count) a.p[i] = (i == 1) ? a.v1 : 0u;
+        if (i < a.count) a.p[i] = (i == 1) ? (a.qsrc ? iteration_word(*a.qsrc, a.qmax) : a.v1) : 0u;
     }
 };
 
@@ -684,6 +685,7 @@ struct FinalizeBody {
         const double* mu; int64_t n; TC* center_out; const uint32_t* status; rsvd_info* info;
         int l; int q; int p;
         const double* est;        // a-posteriori bound or null
+        const int32_t* qsrc;      // q chosen on the device, or null (q above)
     };
     static constexpr int THREADS = 256;
     static int blocks(const Args& a) {
@@ -700,7 +702,7 @@ struct FinalizeBody {
         }
         if (a.center_out && tid < a.n) a.center_out[tid] = static_cast<TC>(a.mu ? a.mu[tid] : 0.0);
         if (a.info && tid == 0) {
-            a.info->l = a.l; a.info->q = a.q; a.info->p = a.p;
+            a.info->l = a.l; a.info->q = a.qsrc ? *a.qsrc : a.q; a.info->p = a.p;
             a.info->flags = *a.status & 0xFF00FFFFu;   // RSVD_FLAG_* and the sweep count
             a.info->est_err = a.est ? *a.est : 0.0;
         }

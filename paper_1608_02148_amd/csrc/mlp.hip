@@ -127,6 +127,31 @@ __global__ __launch_bounds__(NH) void mlp_fwd_bwd_kernel(const float* __restrict
     w.d1[static_cast<size_t>(b) * NH + j] = (h1 > 0.0f) ? d1 : 0.0f;
 }
 
+// q per matrix from the network's distribution when every solve runs with the
+// largest oversampling: pair (q', p') is covered by (q, p_max) when q' <= q, so
+// q_b is the fewest iterations whose pairs hold probability mass >= tau (tau
+// <= 0: the q of the most probable pair).  No network: fallback_q for all.
+__global__ __launch_bounds__(256) void mlp_choose_q_kernel(const float* __restrict__ prob, int B, float tau,
+                                                           int fallback_q, int32_t* q) {
+    const int b = blockIdx.x * 256 + threadIdx.x;
+    if (b >= B) return;
+    if (!prob) { q[b] = fallback_q; return; }
+    const float* pb = prob + static_cast<size_t>(b) * NO;
+    int pick = NO / 3 - 1;
+    if (tau <= 0.0f) {
+        int best = 0;
+        for (int c = 1; c < NO; ++c) if (pb[c] > pb[best]) best = c;
+        pick = best / 3;
+    } else {
+        double cum = 0.0;
+        for (int qq = 0; qq < NO / 3; ++qq) {
+            for (int c = 3 * qq; c < 3 * qq + 3; ++c) cum += pb[c];
+            if (cum >= tau) { pick = qq; break; }
+        }
+    }
+    q[b] = pick;
+}
+
 // Gradient of parameter t: sum over samples of (layer input) x (layer delta).
 __global__ __launch_bounds__(256) void mlp_grad_kernel(int B, const float* __restrict__ X, MlpWork w,
                                                        float* grad) {
@@ -185,6 +210,24 @@ int status_of(rsvd_handle_t h, hipError_t e) {
 }
 
 }  // namespace
+
+namespace rsvd {
+
+hipError_t learned_choose_q(hipStream_t st, const float* theta, int count, const float* feat, float* prob,
+                            float tau, int fallback_q, int32_t* q) {
+    if (theta) {
+        MlpWork w{};
+        hipLaunchKernelGGL(mlp_fwd_bwd_kernel, dim3(count), dim3(NH), 0, st, theta, count, feat, nullptr, w, prob,
+                           nullptr);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(mlp_choose_q_kernel, dim3((count + 255) / 256), dim3(256), 0, st, theta ? prob : nullptr,
+                       count, tau, fallback_q, q);
+    return hipGetLastError();
+}
+
+}  // namespace rsvd
 
 extern "C" {
 

@@ -114,17 +114,19 @@ inline int tile_variant_index(int cls) {
     return cls <= 32 ? 0 : cls <= 48 ? 1 : cls <= 64 ? 2 : cls <= 80 ? 3 : cls <= 96 ? 4 : 5;
 }
 
+// min_Lp: pad the column count of the bases to at least this (a sketch
+// shared with a wider plan keeps that plan's leading dimension).
 // batch = true: one problem of a grouped batch, whose parallelism comes from
 // the batch, so no product splits its reduction (every problem then issues
 // the same sequence of steps).  variants: 12 ints (NN then TN, one per tall
 // class) choosing the f32 tile variant, or null for the defaults.
 inline Plan make_plan(int dtype, int64_t m, int64_t n, int k, const rsvd_params* prm, int num_cu,
-                      bool batch = false, const int* variants = nullptr) {
+                      bool batch = false, const int* variants = nullptr, int min_Lp = 0) {
     Plan P;
     P.dtype = dtype; P.m = m; P.n = n; P.k = k; P.q = prm->q;
     P.l = static_cast<int>(std::min<int64_t>(static_cast<int64_t>(k) + prm->p, std::min(m, n)));
     P.p = P.l - k;
-    P.Lp = tile_cols(P.l);
+    P.Lp = std::max(tile_cols(P.l), min_Lp);
     P.kp = tile_cols(k);
     P.tile = tile_class(P.l, dtype != RSVD_F64);
     if (variants && dtype != RSVD_F64) {
@@ -199,6 +201,9 @@ struct SolveOut {
     uint64_t* stamps;          // optional [first step, last step] device clock
     float* features;           // non-null: stop after the sketch and write the 131 selector inputs
     int feat_k;                // target rank used in the features
+    const int32_t* qsrc;       // non-null: q read on the device (gated plans, q <= qmax)
+    const void* y0;            // non-null: the sketch A Omega[:, :l] already computed (ld Lp)
+    int stamp_sel;             // which of the two stamps this call writes: 1 first, 2 last, 3 both
 };
 
 inline int hip_status(rsvd_handle_t h, hipError_t e) {

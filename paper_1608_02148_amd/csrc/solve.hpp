@@ -75,7 +75,7 @@ hipError_t solve_steps(Ex& ex, rsvd_handle_t prof, const Plan& P, const TA* A, i
     const int l = P.l, Lp = P.Lp, k = P.k;
     const int tile = P.tile | (P.var_nn << 16), tile_tn = P.tile | (P.var_tn << 16);
     uint32_t* status = at<uint32_t>(work, P.status);
-    TC* Y = at<TC>(work, P.Y);
+    TC* Y = o.y0 ? const_cast<TC*>(static_cast<const TC*>(o.y0)) : at<TC>(work, P.Y);
     TC* Z = at<TC>(work, P.Z);
     TC* Om = at<TC>(work, P.Om);
     TC* partc = at<TC>(work, P.part);
@@ -94,8 +94,10 @@ hipError_t solve_steps(Ex& ex, rsvd_handle_t prof, const Plan& P, const TA* A, i
     const bool gated = P.gated;
     const int qmax = gated ? P.qmax : P.q;
     const uint32_t* itw = status + 1;
-    if (o.stamps) RSVD_TRY(ex.template run<StampBody>(StampBody::Args{o.stamps}));
-    RSVD_TRY(ex.template run<ClearBody>(ClearBody::Args{status, gated ? 2 : 1, iteration_word(P.q, qmax)}));
+    const int stamp_sel = o.stamp_sel ? o.stamp_sel : 3;
+    if (o.stamps && (stamp_sel & 1)) RSVD_TRY(ex.template run<StampBody>(StampBody::Args{o.stamps}));
+    RSVD_TRY(ex.template run<ClearBody>(ClearBody::Args{status, gated ? 2 : 1, iteration_word(P.q, qmax), o.qsrc,
+                                                        qmax}));
 
     if (mu) {   // column means (implicit centring, Sec. 4.2)
         const int S = P.sp.colsum;
@@ -104,9 +106,12 @@ hipError_t solve_steps(Ex& ex, rsvd_handle_t prof, const Plan& P, const TA* A, i
         RSVD_TRY(ex.template run<ColmeanBody>(ColmeanBody::Args{mp, S, m, n, mu}));
     }
 
-    // Alg. rqb steps 2-3: Omega and the sketch Y = A Omega.
-    RSVD_TRY(ex.template run<OmegaBody<TC>>(typename OmegaBody<TC>::Args{
-        n, l, Lp, prm->seed, stream_id, prm->sdist, Om, static_cast<int64_t>(Lp)}));
+    // Alg. rqb steps 2-3: Omega and the sketch Y = A Omega (unless a wider
+    // sketch under the same seed and stream already holds it in its leading
+    // l columns: Omega's entries do not depend on l).
+    if (!o.y0)
+        RSVD_TRY(ex.template run<OmegaBody<TC>>(typename OmegaBody<TC>::Args{
+            n, l, Lp, prm->seed, stream_id, prm->sdist, Om, static_cast<int64_t>(Lp)}));
     const double pass_flops = 2.0 * static_cast<double>(m) * n * l;
     const double a_bytes = static_cast<double>(m) * n * sizeof(TA);
     const double nn_bytes = a_bytes + (static_cast<double>(n) + m) * l * sizeof(TC);
@@ -138,7 +143,7 @@ hipError_t solve_steps(Ex& ex, rsvd_handle_t prof, const Plan& P, const TA* A, i
         RSVD_TRY(ax(X, early, Gate{itw, early_bit}));
         return ax(X, late, Gate{itw, late_bit});
     };
-    RSVD_TRY(ax_step(Om, P.q == 0, IT_QPOS, IT_Q0));
+    if (!o.y0) RSVD_TRY(ax_step(Om, P.q == 0, IT_QPOS, IT_Q0));
 
     if (o.features) {
         // Selector inputs: the singular values of the sketch are those of the
@@ -162,7 +167,7 @@ hipError_t solve_steps(Ex& ex, rsvd_handle_t prof, const Plan& P, const TA* A, i
         ja.status = status; ja.max_sweeps = 60; ja.tol = 1e-7;
         RSVD_TRY(ex.template run<JacobiBody<TC>>(ja));
         RSVD_TRY(ex.template run<FeatureBody>(FeatureBody::Args{sigma, l, m, n, o.feat_k, o.features}));
-        if (o.stamps) RSVD_TRY(ex.template run<StampBody>(StampBody::Args{o.stamps + 1}));
+        if (o.stamps && (stamp_sel & 2)) RSVD_TRY(ex.template run<StampBody>(StampBody::Args{o.stamps + 1}));
         return hipSuccess;
     }
 
@@ -260,8 +265,8 @@ hipError_t solve_steps(Ex& ex, rsvd_handle_t prof, const Plan& P, const TA* A, i
     }
     RSVD_TRY(ex.template run<FinalizeBody<TC>>(typename FinalizeBody<TC>::Args{
         sigma, k, o.S, o.eigvals, o.sdev, static_cast<double>(m - 1), mu, n, static_cast<TC*>(o.center_out),
-        status, o.info, l, P.q, P.p, est}));
-    if (o.stamps) RSVD_TRY(ex.template run<StampBody>(StampBody::Args{o.stamps + 1}));
+        status, o.info, l, P.q, P.p, est, o.qsrc}));
+    if (o.stamps && (stamp_sel & 2)) RSVD_TRY(ex.template run<StampBody>(StampBody::Args{o.stamps + 1}));
     return hipSuccess;
 }
 

@@ -310,8 +310,20 @@ def evaluate_arms(data, theta, seed=2148, reps=3, tau=DEFAULT_TAU, fixed=(4, 20)
         if work is None or bt.work.numel() > work.numel():
             work = bt.work          # reused by the learned arms (p <= 20, q <= 4: no larger)
         del bt
-    # learned: select (features + network + host planning) and solve; the
-    # select phase and the planning of the solve batch are timed as well
+    # learned on the device (one graph: q = 0 sketches, features, network,
+    # choice of q, then the solves from those sketches; p = 20 for every
+    # matrix, which covers every class of the label set at the chosen q)
+    for name, prec in (("fp32_learned_graph", "plain"), ("bf16_learned_graph", "bf16_mixed")):
+        bt, ms = _timed_batch(data, ks, reps, p=P_CHOICES[-1], seed=seed, precision=prec, learned=True,
+                              theta=theta, tau=tau)
+        q = bt.choices()
+        err = success(bt)
+        out[name] = dict(ms=ms, solves_per_s=n_mat / ms * 1e3, errors=err,
+                         q_hist=np.bincount(q, minlength=5).tolist())
+        bt.close()
+        del bt
+    # learned through the host: select (features + network) returns (q, p),
+    # then a batch is planned with them; selection and planning are timed too
     for name, prec in (("fp32_learned", "plain"), ("bf16_learned", "bf16_mixed")):
         torch.cuda.synchronize()
         t0 = time.perf_counter()

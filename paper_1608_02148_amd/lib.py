@@ -49,6 +49,7 @@ class BatchDesc(ctypes.Structure):
 
 BATCH_GRAPH, BATCH_STAMPS, BATCH_FEATURES, BATCH_OWN_QP = 1, 2, 4, 8
 MLP_INPUTS, MLP_HIDDEN, MLP_CLASSES, MLP_PARAMS = 131, 64, 15, 13583
+LEARNED_QMAX, LEARNED_PMAX, LEARNED_FALLBACK_Q = 4, 20, 3
 
 PROFILE_KINDS = 2
 PROFILE_NAMES = ("A_X", "AT_Q")
@@ -82,6 +83,9 @@ _PROTOS = {
     "rsvd_batch_run": (c_int32, [c_void_p]),
     "rsvd_batch_stamps": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "rsvd_batch_destroy": (c_int32, [c_void_p]),
+    "rsvd_batch_create_learned": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p,
+                                            ctypes.c_float, c_int32, c_void_p, c_void_p]),
+    "rsvd_batch_choices": (c_int32, [c_void_p, c_void_p]),
     "rsvd_select_workspace_size": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p]),
     "rsvd_select": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p, ctypes.c_float, c_void_p,
                               c_void_p, c_void_p, c_void_p, c_size_t]),

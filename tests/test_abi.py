@@ -221,6 +221,49 @@ def test_batch_feature_and_own_qp_rules(lib, handle):
     assert _create(lib, handle, shapes, flags=L.BATCH_OWN_QP, descs=d)[0] == -2
 
 
+def _create_learned(lib, handle, shapes, descs=None, flags=L.BATCH_GRAPH, tau=0.8, **prm_kw):
+    prm = L.Params()
+    lib.rsvd_default_params(ctypes.byref(prm))
+    for key, v in prm_kw.items():
+        setattr(prm, key, v)
+    descs = descs if descs is not None else _descs(shapes)
+    b = ctypes.c_void_p()
+    nbytes = ctypes.c_size_t(0)
+    st = lib.rsvd_batch_create_learned(handle, L.RSVD_F32, len(shapes), descs, ctypes.byref(prm), None,
+                                       ctypes.c_float(tau), flags, ctypes.byref(b), ctypes.byref(nbytes))
+    return st, b, nbytes.value
+
+
+def test_learned_batch_rules(lib, handle):
+    """Learned batches: host-only planning; p bounded by the largest class's
+    oversampling; flags limited to graph and stamps; like rsvd_batch_create
+    otherwise."""
+    shapes = [(300, 200, 10), (1000, 100, 50), (700, 1300, 108), (64, 40, 1)]
+    st, b, nbytes = _create_learned(lib, handle, shapes, p=20)
+    assert st == 0 and nbytes > 0
+    # two workspaces per matrix (sketch phase and solve) exceed the plain batch
+    st2, b2, plain = _create(lib, handle, shapes)
+    assert st2 == 0 and nbytes > plain
+    assert lib.rsvd_batch_run(b) == -1                       # not bound
+    assert lib.rsvd_batch_choices(b, ctypes.c_void_p(8)) == -1
+    assert lib.rsvd_batch_choices(b2, ctypes.c_void_p(8)) == -1   # not a learned batch
+    lib.rsvd_batch_destroy(b)
+    lib.rsvd_batch_destroy(b2)
+    assert _create_learned(lib, handle, shapes, p=21)[0] == -1
+    assert _create_learned(lib, handle, shapes, p=-1)[0] == -1
+    assert _create_learned(lib, handle, shapes, tau=float("nan"))[0] == -1
+    assert _create_learned(lib, handle, shapes, tau=1.5)[0] == -1
+    assert _create_learned(lib, handle, shapes, flags=L.BATCH_FEATURES)[0] == -1
+    assert _create_learned(lib, handle, shapes, flags=L.BATCH_OWN_QP)[0] == -1
+    assert _create_learned(lib, handle, [(100, 50, 50)])[0] == -1
+    d = _descs(shapes)
+    d[2].S = None
+    assert _create_learned(lib, handle, shapes, descs=d)[0] == -1
+    st, b, _ = _create_learned(lib, handle, shapes, precision=1, p=10)
+    assert st == 0
+    lib.rsvd_batch_destroy(b)
+
+
 def test_select_workspace_is_host_only(lib, handle):
     shapes = [(300, 200, 10), (4000, 1000, 64)]
     prm = L.Params()
