@@ -172,15 +172,18 @@ struct CholArgs {
 };
 
 constexpr int CHOL_MAX_L = RSVD_MAX_L;
-constexpr int CHOL_THREADS = 512;
 constexpr int CT_R = 4, CT_C = 8;                 // register tile per thread
-constexpr int CT_TX = CHOL_MAX_L / CT_C;          // 16 thread columns
-static_assert((CHOL_MAX_L / CT_R) * CT_TX == CHOL_THREADS, "tiles must cover the matrix");
+// The kernel instance for l <= LM: (LM / 4) x (LM / 8) threads cover LM x LM,
+// so small problems take small workgroups and more of them fit on a CU.
+template <int LM> constexpr int chol_threads() { return (LM / CT_R) * (LM / CT_C); }
+static_assert(chol_threads<CHOL_MAX_L>() == 512, "tiles must cover the matrix");
 
 inline size_t chol_lds_bytes(int) { return 0; }
 
-template <typename TC>
+template <typename TC, int LM>
 __device__ __forceinline__ void chol_body(const CholArgs& a) {
+    constexpr int CT_TX = LM / CT_C;              // thread columns (a power of two)
+    constexpr int NT = chol_threads<LM>();
     const int l = a.l, tid = threadIdx.x;
     const int tx = tid % CT_TX, ty = tid / CT_TX;
     const int a0 = CT_R * ty, b0 = CT_C * tx;
@@ -198,10 +201,10 @@ __device__ __forceinline__ void chol_body(const CholArgs& a) {
     // wave; values move by lane shuffles), then publish the panel's R rows in
     // LDS and one barrier later every thread applies the rank-4 update to its
     // trailing rows.  The inverse runs the same way from the last panel up.
-    __shared__ double panel[2][CT_R][CHOL_MAX_L];   // R rows (factor) / X rows (inverse)
-    __shared__ double pcol[2][CT_R][CHOL_MAX_L];    // R columns 4P .. 4P+3 (inverse)
-    __shared__ double diag0[CHOL_MAX_L];
-    __shared__ double dinv[CHOL_MAX_L];
+    __shared__ double panel[2][CT_R][LM];   // R rows (factor) / X rows (inverse)
+    __shared__ double pcol[2][CT_R][LM];    // R columns 4P .. 4P+3 (inverse)
+    __shared__ double diag0[LM];
+    __shared__ double dinv[LM];
     __shared__ uint32_t s_flags;
     __shared__ double s_trace;
     __shared__ int s_fail, s_dead;
@@ -333,7 +336,7 @@ __device__ __forceinline__ void chol_body(const CholArgs& a) {
         for (int i = 0; i < CT_R; ++i)
 #pragma unroll
             for (int q = 0; q < CT_C; ++q) g[i][q] = 0.0;
-        for (int j = tid; j < l; j += CHOL_THREADS) dinv[j] = 0.0;
+        for (int j = tid; j < l; j += NT) dinv[j] = 0.0;
     }
     if (tid == 0) {
         const bool dead_any = !nonfinite && !zero && s_dead;
@@ -428,14 +431,17 @@ __device__ __forceinline__ void chol_body(const CholArgs& a) {
     if (tid == 0) *a.status = s_flags;
 }
 
-template <typename TC>
+template <typename TC, int LM = CHOL_MAX_L>
 struct CholBody {
     typedef CholArgs Args;
-    static constexpr int THREADS = CHOL_THREADS;
+    static constexpr int THREADS = chol_threads<LM>();
     static int blocks(const Args&) { return 1; }
     static size_t lds(const Args&) { return 0; }
-    static __device__ void run(const Args& a, int) { chol_body<TC>(a); }
+    static __device__ void run(const Args& a, int) { chol_body<TC, LM>(a); }
 };
+
+// Size class of the small dense kernels for an l x l problem.
+inline int small_lm(int l) { return l <= 32 ? 32 : (l <= 64 ? 64 : CHOL_MAX_L); }
 
 // ------------------------------------------------------ one-sided Jacobi SVD
 // R (l x l upper triangular, f64, ld ldr) = W diag(sigma) J^T.  The columns of
@@ -460,7 +466,6 @@ struct JacobiArgs {
     double tol;
 };
 
-constexpr int JAC_THREADS = 1024;
 constexpr int JAC_GROUP = 16;      // lanes per column pair (one DPP row)
 
 // Column stride of W in LDS: l rounded up to a multiple of 16 doubles plus
@@ -473,7 +478,6 @@ inline size_t jacobi_lds_bytes(int l) { return static_cast<size_t>(jacobi_ldw(l)
 // |w_a| |w_b| after rounding, so asking for less than l u would never settle.
 inline double jacobi_tol(int l) { return std::max(1e-15, 2.220446049250313e-16 * l); }
 
-constexpr int JAC_PER_LANE = CHOL_MAX_L / JAC_GROUP;
 
 // Sum over the 16 lanes of a DPP row: quad exchanges (xor 1, xor 2), then the
 // half-row and row mirrors; every lane ends with the full sum.
@@ -491,12 +495,13 @@ __device__ __forceinline__ double group_sum(double v) {
     return v;
 }
 
-template <typename TC>
+template <typename TC, int LM>
 __device__ __forceinline__ void jacobi_body(const JacobiArgs& a) {
+    constexpr int JAC_PER_LANE = LM / JAC_GROUP;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ int s_rotated;
-    __shared__ int s_perm[CHOL_MAX_L];
-    __shared__ double s_sig[CHOL_MAX_L];
+    __shared__ int s_perm[LM];
+    __shared__ double s_sig[LM];
     const int l = a.l, tid = threadIdx.x, nt = blockDim.x;
     const int ldw = jacobi_ldw(l);
     double* W = reinterpret_cast<double*>(smem_raw);     // column c at W + c * ldw
@@ -513,7 +518,7 @@ __device__ __forceinline__ void jacobi_body(const JacobiArgs& a) {
     // Squared column norms: recomputed at the start of every sweep and
     // updated through each rotation (|w_a'|^2 = alpha - t gamma,
     // |w_b'|^2 = beta + t gamma), so a pair needs one inner product, not three.
-    __shared__ double s_norm[CHOL_MAX_L];
+    __shared__ double s_norm[LM];
     int sweep = 0;
     for (; sweep < a.max_sweeps; ++sweep) {
         if (tid == 0) s_rotated = 0;
@@ -618,14 +623,34 @@ __device__ __forceinline__ void jacobi_body(const JacobiArgs& a) {
     }
 }
 
-template <typename TC>
+// Instance for l <= LM: one 16-lane group per column pair of a round (LM / 2
+// groups).
+template <typename TC, int LM = CHOL_MAX_L>
 struct JacobiBody {
     typedef JacobiArgs Args;
-    static constexpr int THREADS = JAC_THREADS;
+    static constexpr int THREADS = JAC_GROUP * (LM / 2);
     static int blocks(const Args&) { return 1; }
     static size_t lds(const Args& a) { return jacobi_lds_bytes(a.l); }
-    static __device__ void run(const Args& a, int) { jacobi_body<TC>(a); }
+    static __device__ void run(const Args& a, int) { jacobi_body<TC, LM>(a); }
 };
+
+template <typename TC, class Ex>
+hipError_t run_chol(Ex& ex, const CholArgs& a) {
+    switch (small_lm(a.l)) {
+        case 32: return ex.template run<CholBody<TC, 32>>(a);
+        case 64: return ex.template run<CholBody<TC, 64>>(a);
+        default: return ex.template run<CholBody<TC, CHOL_MAX_L>>(a);
+    }
+}
+
+template <typename TC, class Ex>
+hipError_t run_jacobi(Ex& ex, const JacobiArgs& a) {
+    switch (small_lm(a.l)) {
+        case 32: return ex.template run<JacobiBody<TC, 32>>(a);
+        case 64: return ex.template run<JacobiBody<TC, 64>>(a);
+        default: return ex.template run<JacobiBody<TC, CHOL_MAX_L>>(a);
+    }
+}
 
 // ------------------------------------------------------------- sign rule
 // One workgroup per column i < k of V (n x k, ld ldv): find the entry of

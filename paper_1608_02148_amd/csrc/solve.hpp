@@ -25,7 +25,7 @@ hipError_t orthonormalize(Ex& ex, int tile, TC* M, int64_t ldm, int64_t rows, in
         ca.rout = rfac ? rfac + static_cast<size_t>(pass - 1) * l * l : nullptr;
         ca.status = status; ca.pass = pass; ca.skip_unless_pending = conditional; ca.adaptive = adaptive;
         ca.gate = gate;
-        RSVD_TRY(ex.template run<CholBody<TC>>(ca));
+        RSVD_TRY(run_chol<TC>(ex, ca));
         RSVD_TRY((gemm_plain<TC, TC, TC, MODE_NN>(ex, tile, false, M, ldm, rows, l, rinv, Lp, l, M, ldm, 1, 0, nullptr,
                                                   skip, need, gate)));
     }
@@ -157,7 +157,7 @@ hipError_t solve_steps(Ex& ex, rsvd_handle_t prof, const Plan& P, const TA* A, i
         ca.part = (S > 1) ? gram : partd; ca.S = 1; ca.part_stride = 0; ca.ldp = Lp;
         ca.l = l; ca.mrows = m; ca.rinv = rinv; ca.ldr = Lp; ca.rout = racc;
         ca.status = status; ca.pass = 1; ca.skip_unless_pending = 0; ca.adaptive = 0;
-        RSVD_TRY(ex.template run<CholBody<TC>>(ca));
+        RSVD_TRY(run_chol<TC>(ex, ca));
         JacobiArgs ja;
         ja.R = racc; ja.ldr = l; ja.l = l; ja.k = 1;
         ja.sigma = sigma; ja.xv = xv; ja.ldx = Lp; ja.xcols = P.kp; ja.wks = at<double>(work, P.wks);
@@ -165,7 +165,7 @@ hipError_t solve_steps(Ex& ex, rsvd_handle_t prof, const Plan& P, const TA* A, i
         // the singular values accurate far beyond that (the error is of the
         // order of the squared off-diagonal cosines)
         ja.status = status; ja.max_sweeps = 60; ja.tol = 1e-7;
-        RSVD_TRY(ex.template run<JacobiBody<TC>>(ja));
+        RSVD_TRY(run_jacobi<TC>(ex, ja));
         RSVD_TRY(ex.template run<FeatureBody>(FeatureBody::Args{sigma, l, m, n, o.feat_k, o.features}));
         if (o.stamps && (stamp_sel & 2)) RSVD_TRY(ex.template run<StampBody>(StampBody::Args{o.stamps + 1}));
         return hipSuccess;
@@ -208,7 +208,7 @@ hipError_t solve_steps(Ex& ex, rsvd_handle_t prof, const Plan& P, const TA* A, i
         double* wks = at<double>(work, P.wks);
         ja.sigma = sigma; ja.xv = xv; ja.ldx = Lp; ja.xcols = P.kp; ja.wks = wks;
         ja.status = status; ja.max_sweeps = 60; ja.tol = jacobi_tol(ja.l);
-        RSVD_TRY(ex.template run<JacobiBody<TC>>(ja));
+        RSVD_TRY(run_jacobi<TC>(ex, ja));
         // J_k = R_b^T (W_k / sigma)
         RSVD_TRY((gemm_plain<double, double, double, MODE_TN>(ex, 0, true, racc, l, l, l, wks, k, k, jk, k, 1, 0,
                                                               nullptr, nullptr, 0)));
