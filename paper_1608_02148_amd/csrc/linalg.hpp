@@ -802,6 +802,143 @@ struct EstBody {
     }
 };
 
+// ----------------------------------------------- singular values from a Gram
+// sigma (descending) = sqrt(max(lambda, 0)) for the eigenvalues lambda of the
+// symmetric l x l Gram matrix G = Y^T Y (f64, ld ldg; its upper triangle is
+// used): Householder reduction to tridiagonal form in LDS (Golub & Van Loan,
+// Matrix Computations, Sec. 8.3.1), then bisection on Sturm counts (Sec.
+// 8.4.1) with eight points per eigenvalue and step.  For selector features,
+// which need the spectrum only: an eigenvalue error of c l u lambda_1 moves
+// sigma_i by at most sqrt(c l u) sigma_1, and by c l u sigma_1^2 / (2 sigma_i)
+// when that is smaller.
+struct GramEigArgs { const double* G; int ldg; int l; double* sigma; };
+
+template <int LM>
+struct GramEigBody {
+    typedef GramEigArgs Args;
+    static constexpr int THREADS = 8 * LM;
+    static constexpr int NG = THREADS / JAC_GROUP;      // 16-lane groups
+    static int blocks(const Args&) { return 1; }
+    static int ldl(int l) { return l + 1; }
+    static size_t lds(const Args& a) { return static_cast<size_t>(a.l) * ldl(a.l) * sizeof(double); }
+    static __device__ void run(const Args& a, int) {
+        extern __shared__ __align__(16) unsigned char smem_raw[];
+        __shared__ double v[LM], w[LM], d[LM], e2[LM], pv[NG];
+        __shared__ double s_tau;
+        double* G = reinterpret_cast<double*>(smem_raw);
+        const int l = a.l, ld = l + 1, tid = threadIdx.x;
+        const int group = tid / JAC_GROUP, gl = tid % JAC_GROUP;
+        for (int idx = tid; idx < l * l; idx += THREADS) {     // symmetric copy of the upper triangle
+            const int r = idx / l, c = idx - r * l;
+            G[r * ld + c] = (c >= r) ? a.G[static_cast<int64_t>(r) * a.ldg + c] : a.G[static_cast<int64_t>(c) * a.ldg + r];
+        }
+        __syncthreads();
+        for (int j = 0; j + 2 < l; ++j) {
+            const int n1 = l - j - 1, o = j + 1;               // trailing block G[o.., o..]
+            if (group == 0) {                                  // reflector from column j below the diagonal
+                double s = 0.0;
+                for (int i = 1 + gl; i < n1; i += JAC_GROUP) {
+                    const double x = G[(o + i) * ld + j];
+                    s += x * x;
+                }
+                s = group_sum(s);
+                const double x0 = G[o * ld + j];
+                double tau = 0.0, beta = x0, scale = 0.0;
+                if (s > 0.0) {
+                    const double nrm = sqrt(x0 * x0 + s);
+                    beta = -copysign(nrm, x0);
+                    tau = (beta - x0) / beta;
+                    scale = 1.0 / (x0 - beta);
+                }
+                for (int i = gl; i < n1; i += JAC_GROUP) v[i] = (i == 0) ? 1.0 : G[(o + i) * ld + j] * scale;
+                if (gl == 0) { s_tau = tau; d[j] = G[j * ld + j]; e2[j] = beta * beta; }
+            }
+            __syncthreads();
+            const double tau = s_tau;
+            double acc = 0.0;                                  // p = tau G v, and the rows' p_i v_i
+            for (int i = group; i < n1; i += NG) {
+                const double* gr = G + (o + i) * ld + o;
+                double t = 0.0;
+                for (int c = gl; c < n1; c += JAC_GROUP) t += gr[c] * v[c];
+                t = group_sum(t) * tau;
+                if (gl == 0) w[i] = t;
+                acc += t * v[i];
+            }
+            if (gl == 0) pv[group] = acc;
+            __syncthreads();
+            if (tid < 64) {                                    // K = tau / 2 p^T v; w = p - K v
+                double t = 0.0;
+                for (int g = tid; g < NG; g += 64) t += pv[g];
+                for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+                const double K = 0.5 * tau * t;
+                for (int i = tid; i < n1; i += 64) w[i] -= K * v[i];
+            }
+            __syncthreads();
+            for (int i = group; i < n1; i += NG) {             // G -= v w^T + w v^T
+                double* gr = G + (o + i) * ld + o;
+                const double vi = v[i], wi = w[i];
+                for (int c = gl; c < n1; c += JAC_GROUP) gr[c] -= vi * w[c] + wi * v[c];
+            }
+            __syncthreads();
+        }
+        if (tid == 0) {
+            if (l >= 2) {
+                d[l - 2] = G[(l - 2) * ld + (l - 2)];
+                const double t = G[(l - 1) * ld + (l - 2)];
+                e2[l - 2] = t * t;
+            }
+            d[l - 1] = G[(l - 1) * ld + (l - 1)];
+        }
+        __syncthreads();
+        // Bisection: eight lanes per eigenvalue index i (ascending) narrow an
+        // interval (lo, hi] with count(lo) <= i < count(hi), where count(x) is
+        // the number of eigenvalues below x (negative pivots of T - x I).
+        const int i = tid / 8, sub = tid % 8;
+        double lo = 0.0, hi = 0.0, emax = 0.0;
+        for (int k = 0; k < l; ++k) {
+            const double r = (k > 0 ? sqrt(e2[k - 1]) : 0.0) + (k + 1 < l ? sqrt(e2[k]) : 0.0);
+            lo = (k == 0) ? d[k] - r : fmin(lo, d[k] - r);
+            hi = (k == 0) ? d[k] + r : fmax(hi, d[k] + r);
+            if (k + 1 < l) emax = fmax(emax, e2[k]);
+        }
+        const double span = fmax(hi - lo, 1e-300);
+        lo -= 1e-14 * span; hi += 1e-14 * span;
+        const double pivmin = 1e-290 * fmax(1.0, emax);
+        for (int step = 0; step < 18; ++step) {
+            const double x = lo + (hi - lo) * (sub + 1) / 9.0;
+            int cnt = 0;
+            double q = d[0] - x;
+            if (fabs(q) < pivmin) q = -pivmin;
+            cnt += q < 0.0;
+            for (int k = 1; k < l; ++k) {
+                q = (d[k] - x) - e2[k - 1] / q;
+                if (fabs(q) < pivmin) q = -pivmin;
+                cnt += q < 0.0;
+            }
+            // the eight counts of this eigenvalue's lanes: the new interval is
+            // between the last point with count <= i and the first above it
+            double nlo = lo, nhi = hi;
+            for (int t = 0; t < 8; ++t) {
+                const int ct = __shfl(cnt, t, 8);
+                const double xt = lo + (hi - lo) * (t + 1) / 9.0;
+                if (ct <= i) nlo = xt;
+                else if (nhi == hi) nhi = xt;
+            }
+            lo = nlo; hi = nhi;
+        }
+        if (sub == 0 && i < l) a.sigma[l - 1 - i] = sqrt(fmax(0.5 * (lo + hi), 0.0));
+    }
+};
+
+template <class Ex>
+hipError_t run_gram_eig(Ex& ex, const GramEigArgs& a) {
+    switch (small_lm(a.l)) {
+        case 32: return ex.template run<GramEigBody<32>>(a);
+        case 64: return ex.template run<GramEigBody<64>>(a);
+        default: return ex.template run<GramEigBody<CHOL_MAX_L>>(a);
+    }
+}
+
 // ------------------------------------------------------------- features
 // Selector inputs of one matrix from the singular values sigma (descending,
 // l of them) of its q = 0 sketch: sigma_i / sigma_0 zero-padded to 128, then

@@ -146,26 +146,14 @@ hipError_t solve_steps(Ex& ex, rsvd_handle_t prof, const Plan& P, const TA* A, i
     if (!o.y0) RSVD_TRY(ax_step(Om, P.q == 0, IT_QPOS, IT_Q0));
 
     if (o.features) {
-        // Selector inputs: the singular values of the sketch are those of the
-        // Cholesky factor R of its f64 Gram matrix (one pass; the features
-        // only need the spectrum, not an orthonormal basis).
+        // Selector inputs: the singular values of the sketch, from the
+        // eigenvalues of its f64 Gram matrix (one pass; the features need the
+        // spectrum only, as f32 ratios to the largest).
         const int S = P.sp.gram_m;
         RSVD_TRY((gemm_plain<TC, TC, double, MODE_TN>(ex, 0, true, Y, Lp, l, m, Y, Lp, l, partd, Lp, S,
                                                       static_cast<int64_t>(Lp) * Lp, nullptr, nullptr, 0)));
         if (S > 1) RSVD_TRY(reduce_step<double>(ex, partd, S, static_cast<int64_t>(Lp) * Lp, Lp, l, l, gram, Lp));
-        CholArgs ca;
-        ca.part = (S > 1) ? gram : partd; ca.S = 1; ca.part_stride = 0; ca.ldp = Lp;
-        ca.l = l; ca.mrows = m; ca.rinv = rinv; ca.ldr = Lp; ca.rout = racc;
-        ca.status = status; ca.pass = 1; ca.skip_unless_pending = 0; ca.adaptive = 0;
-        RSVD_TRY(run_chol<TC>(ex, ca));
-        JacobiArgs ja;
-        ja.R = racc; ja.ldr = l; ja.l = l; ja.k = 1;
-        ja.sigma = sigma; ja.xv = xv; ja.ldx = Lp; ja.xcols = P.kp; ja.wks = at<double>(work, P.wks);
-        // features are f32 ratios: rotating pairs down to |cos| <= 1e-7 leaves
-        // the singular values accurate far beyond that (the error is of the
-        // order of the squared off-diagonal cosines)
-        ja.status = status; ja.max_sweeps = 60; ja.tol = 1e-7;
-        RSVD_TRY(run_jacobi<TC>(ex, ja));
+        RSVD_TRY(run_gram_eig(ex, GramEigArgs{(S > 1) ? gram : partd, Lp, l, sigma}));
         RSVD_TRY(ex.template run<FeatureBody>(FeatureBody::Args{sigma, l, m, n, o.feat_k, o.features}));
         if (o.stamps && (stamp_sel & 2)) RSVD_TRY(ex.template run<StampBody>(StampBody::Args{o.stamps + 1}));
         return hipSuccess;
