@@ -16,9 +16,13 @@ Also reported:
   batched       -- 4096 ragged f32 matrices (m in [256, 4096], n in
                    [64, 1024], k in [8, 64], p=10, q=2, sigma_i = i^-alpha)
                    as one captured graph: solves/s, p50 / p99 latency;
+  bf16_storage  -- a 200000 x 20000 bfloat16 matrix (8 GB, sigma_i = i^-1.5
+                   for i <= 4096), k = 100, p = 20, q = 2: f32 arithmetic
+                   against the bf16 mixed-precision mode;
   learned       -- held-out generated matrices: FP32 plain (q=2, p=10 and
-                   q=4, p=20) against bf16 + learned (q, p): solves/s and the
-                   exact fraction within 1 % excess error.
+                   q=4, p=20) against learned q (one graph on the device,
+                   and through the host with learned (q, p)): solves/s and
+                   the exact fraction within 1 % excess error.
 
 Usage: python bench.py [--gpus 1] [--steps 10] [--warmup 3]
 """
@@ -162,6 +166,77 @@ def batched_arm(steps, warmup, precision="plain"):
     return out
 
 
+def bf16_storage_arm(steps, warmup, m=200000, n=20000, k=100, p=20, q=2, seed=2148):
+    """bfloat16-stored A of 8 GB: the f32-arithmetic path (f32 matrix cores on
+    the widened tiles) against the mixed mode (bf16 early passes, split-bf16
+    last sketch and projection), with the per-pass product kernels timed by
+    HIP events.  Accuracy: both runs' singular values against each other and
+    against the planted ones (bf16 rounding of A moves sigma_101 ~ 1e-3 by up
+    to about 1.2 %, Weyl)."""
+    import numpy as np
+    import torch
+
+    from paper_1608_02148_amd import api
+    from synth import matrices as syn
+
+    dev = torch.device("cuda", 0)
+    log(f"[bf16_storage] generating A {m}x{n} bfloat16")
+    A = syn.c3_shape_torch(device=dev, m=m, n=n)
+    torch.cuda.synchronize()
+    l = min(k + p, m, n)
+    flops = (2 * q + 2) * 2.0 * m * n * l
+    planted = syn.spectrum("poly", 4096, alpha=1.5)[:k]
+    out = {"workload": f"rsvd {m}x{n} bf16 k={k} p={p} q={q}, sigma_i=i^-1.5 (i <= 4096), rounded to bf16",
+           "a_bytes": m * n * 2}
+    svals = {}
+    for precision in ("plain", "bf16_mixed"):
+        prm = api.make_params(p, q, seed, precision=precision)
+        work = api.workspace(api.workspace_size(A, k, prm), dev)
+        res = (torch.empty(m, k, device=dev), torch.empty(k, dtype=torch.float64, device=dev),
+               torch.empty(n, k, device=dev))
+
+        def step():
+            api.rsvd(A, k, p=p, q=q, seed=seed, precision=precision, work=work, out=res)
+
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        api.profile_enable(True, dev)
+        api.profile_collect(dev)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        prof = api.profile_collect(dev)
+        api.profile_enable(False, dev)
+        dom = max(prof, key=lambda kname: prof[kname]["total_ms"])
+        d = prof[dom]
+        avg = d["total_ms"] / max(d["count"], 1)
+        if precision == "plain":
+            ach = d["flops"] / max(d["count"], 1) / (avg / 1e3) / 1e12
+            roof = {"bound": "mfma", "achieved": round(ach, 3), "peak": PEAKS["f32_mfma_tflops"],
+                    "unit": "TFLOP/s", "frac": round(ach / PEAKS["f32_mfma_tflops"], 4)}
+        else:
+            ach = d["bytes"] / max(d["count"], 1) / (avg / 1e3) / 1e9
+            roof = {"bound": "hbm", "achieved": round(ach, 3), "peak": PEAKS["hbm_gbs"], "unit": "GB/s",
+                    "frac": round(ach / PEAKS["hbm_gbs"], 4)}
+        roof.update({"kernel": dom, "avg_launch_ms": round(avg, 4), "launches": d["count"]})
+        svals[precision] = res[1].cpu().numpy()
+        out[precision] = {"ms_per_step": round(ms, 3), "tflops": round(flops / (ms / 1e3) / 1e12, 3),
+                          "a_read_gbs": round((2 * q + 2) * m * n * 2 / (ms / 1e3) / 1e9, 1), "roofline": roof}
+        log(f"[bf16_storage] {precision}: {ms:.3f} ms/solve, kernels {prof}")
+        del work, res
+        torch.cuda.empty_cache()
+    s_pl, s_bf = svals["plain"], svals["bf16_mixed"]
+    out["speedup_mixed_vs_plain"] = round(out["plain"]["ms_per_step"] / out["bf16_mixed"]["ms_per_step"], 3)
+    out["max_sigma_diff_mixed_vs_plain_rel_sigma1"] = float(np.max(np.abs(s_pl - s_bf)) / s_pl[0])
+    out["max_rel_dev_from_planted_sigma"] = float(np.max(np.abs(s_pl - planted) / planted))
+    del A
+    torch.cuda.empty_cache()
+    return out
+
+
 def learned_arm(count, reps=3):
     """Held-out generated matrices (selector workload): FP32 plain at q=2,
     p=10 and at q=4, p=20 against bf16 mixed precision with the learned
@@ -212,6 +287,8 @@ def main():
     ap.add_argument("--batched-only", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-bf16-arm", action="store_true")
+    ap.add_argument("--no-bf16-storage", action="store_true")
+    ap.add_argument("--bf16-storage-only", action="store_true")
     ap.add_argument("--gaussian-fill", action="store_true",
                     help="fill A with Gaussian entries instead of the planted matrix (for hardware-counter runs: "
                          "a kernel's memory traffic depends on the shapes, not the values)")
@@ -247,6 +324,9 @@ def main():
         return
     if args.learned_only:
         print(json.dumps({"learned": learned_arm(args.learned_count)}), flush=True)
+        return
+    if args.bf16_storage_only:
+        print(json.dumps({"bf16_storage": bf16_storage_arm(args.steps, args.warmup)}), flush=True)
         return
     m, n, k, p, q = args.m, args.n, args.k, args.p, args.q
     if args.gaussian_fill:
@@ -347,6 +427,7 @@ def main():
         log(f"cpu baseline {cpu['value']:.4f} TFLOP/s in {cpu['seconds']:.1f} s on {cpu['cores']} threads")
     del A
     torch.cuda.empty_cache()
+    bf16_storage = None if args.no_bf16_storage else bf16_storage_arm(min(args.steps, 5), 1)
     batched = None if args.no_batched else batched_arm(args.steps, args.warmup)
     learned = None if args.no_learned else learned_arm(args.learned_count)
 
@@ -361,6 +442,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "bf16_mixed": bf16_arm,
+        "bf16_storage": bf16_storage,
         "batched": batched,
         "learned": learned,
     }

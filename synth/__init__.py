@@ -7,5 +7,5 @@ of the method.
 """
 from .matrices import (  # noqa: F401
     haar, planted, planted_torch, spectrum, CONFIGS, c1_matrix, c2_matrix,
-    c2_offsets, c3_matrix_torch, c4_batch, paper_lowrank_product,
+    c2_offsets, c3_shape_torch, c4_batch, paper_lowrank_product,
 )

@@ -129,15 +129,37 @@ def c2_offsets(n, m, seed=5001):
     return rng.standard_normal(n) * (c2_sigma()[0] / math.sqrt(m))
 
 
-def c3_matrix_torch(device="cuda", m=None, n=None, rank=4096):
-    """C3 instance rounded to bfloat16 (torch tensor on ``device``)."""
+def c3_shape_torch(device="cuda", m=200000, n=20000, rank=4096, seed=20000, chunk_rows=8192,
+                   dtype=None):
+    """A matrix of C3's shape and spectrum (sigma_i = i^-1.5, i <= rank),
+    rounded once to ``dtype`` (default bfloat16).  The orthonormal factors
+    are polar factors of Gaussian blocks, computed with matrix products only
+    (Newton-Schulz iteration X <- X (3 I - X^T X) / 2 from the block scaled
+    below its largest singular value; the polar factor of a Gaussian block is
+    Haar distributed).  Formed in float64 row chunks."""
     import torch
-    c = CONFIGS["c3"]
-    m = m or c["m"]
-    n = n or c["n"]
-    sig = spectrum("poly", min(m, n, rank), alpha=1.5)
-    return planted_torch(m, n, sig, c["gen_seed"], device=device,
-                         out_dtype=torch.bfloat16, chunk_rows=8192)
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    f64 = torch.float64
+    dtype = dtype or torch.bfloat16
+
+    def _orth(rows):
+        X = torch.randn(rows, rank, generator=g, device=device, dtype=f64)
+        X /= math.sqrt(rows) + math.sqrt(rank) + 10.0          # sigma_max(G) bound (Gaussian block)
+        eye = torch.eye(rank, dtype=f64, device=device)
+        for _ in range(10):
+            X = X @ (1.5 * eye - 0.5 * (X.t() @ X))
+        return X
+
+    sig = torch.as_tensor(spectrum("poly", rank, alpha=1.5), device=device)
+    Vt = _orth(n).t().contiguous()
+    US = _orth(m)
+    US *= sig[None, :]
+    A = torch.empty(m, n, dtype=dtype, device=device)
+    for r0 in range(0, m, chunk_rows):
+        r1 = min(m, r0 + chunk_rows)
+        A[r0:r1] = (US[r0:r1] @ Vt).to(dtype)
+    return A
 
 
 def c4_shapes(batch=4096, seed=4096, m_range=(256, 4096), n_range=(64, 1024),
