@@ -99,15 +99,60 @@ __device__ __forceinline__ void gemm_bf16_body(const GemmArgs<TA, float, float>&
     const int64_t kbeg = static_cast<int64_t>(split) * g.kchunk;
     const int64_t kend = min(g.K, kbeg + g.kchunk);
 
-    float ra[T::A_PASSES][T::A_VALS];
+    // bf16-stored A moves as raw 16-bit words from global memory to LDS (no
+    // widening and re-rounding), except where the column means are
+    // subtracted (rounded once, as in the f32 path).
+    constexpr bool RAW = sizeof(TA) == 2;
+    float ra[RAW ? 1 : T::A_PASSES][RAW ? 1 : T::A_VALS];
+    uint32_t rb[RAW ? T::A_PASSES : 1][RAW ? T::A_VALS / 2 : 1];
     float rx[T::X_PASSES][32];
+    // 8 bf16 words of A at p (vec: one 16-byte load), zero past `valid`,
+    // minus mu[0..8) when mu is given (then rounded to bf16).
+    auto load_raw8 = [&](const TA* p, int valid, const double* mu, uint32_t* w) {
+        if (g.a_vec && valid >= 8) {
+            const u32x4 v = *reinterpret_cast<const u32x4*>(p);
+#pragma unroll
+            for (int d = 0; d < 4; ++d) w[d] = v[d];
+        } else {
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                const uint32_t lo = (2 * d < valid) ? *reinterpret_cast<const uint16_t*>(p + 2 * d) : 0u;
+                const uint32_t hi = (2 * d + 1 < valid) ? *reinterpret_cast<const uint16_t*>(p + 2 * d + 1) : 0u;
+                w[d] = lo | (hi << 16);
+            }
+        }
+        if (mu) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                if (e >= valid) continue;
+                const uint32_t bits = (w[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
+                const float x = static_cast<float>(static_cast<double>(__uint_as_float(bits << 16)) - mu[e]);
+                const uint32_t nb = __builtin_bit_cast(uint16_t, static_cast<__bf16>(x));
+                w[e >> 1] = (e & 1) ? ((w[e >> 1] & 0x0000FFFFu) | (nb << 16)) : ((w[e >> 1] & 0xFFFF0000u) | nb);
+            }
+        }
+    };
 
     auto load_a = [&](int64_t k0) {
 #pragma unroll
         for (int p = 0; p < T::A_PASSES; ++p) {
             const int it = p * T::NT + tid;
             if (it >= T::A_ITEMS) break;
-            if (MODE == MODE_NN) {
+            if constexpr (MODE == MODE_NN && RAW) {
+                const int r = it / OCT, o = it % OCT;
+                const int64_t gr = r0 + r, gk = k0 + 8 * o;
+                const int valid = (gr < g.rows) ? static_cast<int>(max<int64_t>(0, min<int64_t>(8, kend - gk))) : 0;
+                load_raw8(g.A + gr * g.lda + gk, valid, g.mu ? g.mu + gk : nullptr, rb[p]);
+            } else if constexpr (MODE != MODE_NN && RAW) {
+                const int cb = it % (T::BM / 8), kq = it / (T::BM / 8);
+                const int64_t gc = r0 + 8 * cb;
+                const int cvalid = static_cast<int>(max<int64_t>(0, min<int64_t>(8, g.rows - gc)));
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int64_t ak = k0 + 4 * kq + q;
+                    load_raw8(g.A + ak * g.lda + gc, ak < kend ? cvalid : 0, g.mu ? g.mu + gc : nullptr, rb[p] + 4 * q);
+                }
+            } else if constexpr (MODE == MODE_NN) {
                 const int r = it / OCT, o = it % OCT;
                 const int64_t gr = r0 + r, gk = k0 + 8 * o;
                 const int valid = (gr < g.rows) ? static_cast<int>(max<int64_t>(0, min<int64_t>(8, kend - gk))) : 0;
@@ -178,7 +223,23 @@ __device__ __forceinline__ void gemm_bf16_body(const GemmArgs<TA, float, float>&
         for (int p = 0; p < T::A_PASSES; ++p) {
             const int it = p * T::NT + tid;
             if (it >= T::A_ITEMS) break;
-            if (MODE == MODE_NN) {
+            if constexpr (MODE == MODE_NN && RAW) {
+                const int r = it / OCT, o = it % OCT;
+                const int off = swz<SK, OCT>(r, 8 * o);
+                *reinterpret_cast<u32x4*>(a_plane(buf, 0) + off) = u32x4{rb[p][0], rb[p][1], rb[p][2], rb[p][3]};
+            } else if constexpr (MODE != MODE_NN && RAW) {
+                // 4 (k) x 8 (rows of the tile) words: row 8 cb + e gets the
+                // k-quad (w_0[e], w_1[e], w_2[e], w_3[e])
+                const int cb = it % (T::BM / 8), kq = it / (T::BM / 8);
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int d = e >> 1, sh = 16 * (e & 1);
+                    const uint32_t v0 = (rb[p][d] >> sh) & 0xFFFFu, v1 = (rb[p][4 + d] >> sh) & 0xFFFFu;
+                    const uint32_t v2 = (rb[p][8 + d] >> sh) & 0xFFFFu, v3 = (rb[p][12 + d] >> sh) & 0xFFFFu;
+                    const int off = swz<SK, OCT>(8 * cb + e, 4 * kq);
+                    *reinterpret_cast<u32x2*>(a_plane(buf, 0) + off) = u32x2{v0 | (v1 << 16), v2 | (v3 << 16)};
+                }
+            } else if constexpr (MODE == MODE_NN) {
                 const int r = it / OCT, o = it % OCT;
                 v8bf h, lo;
 #pragma unroll

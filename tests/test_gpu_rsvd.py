@@ -151,6 +151,27 @@ def test_rpca_matches_explicit_centring():
     np.testing.assert_allclose(_np(res["x"]), ora["x"], atol=1e-9)
 
 
+@pytest.mark.parametrize("precision", ["plain", "bf16_mixed"])
+def test_rpca_bf16_storage_matches_explicit_centring(precision):
+    """bf16-stored data with column offsets: implicit centring subtracts the
+    f64 means from the stored values (rounded back to bf16 in the mixed
+    mode's early passes).  Against the oracle on the stored instance with
+    explicit centring: sqrt(eigvals) normwise 1e-4 (f32 arithmetic) / 2e-3
+    (mixed) of the largest."""
+    from paper_1608_02148_amd import api
+    m, n, k = 2500, 333, 10
+    A = syn.planted(m, n, syn.spectrum("exp", n, tau=12.0), 77)
+    mu = np.random.default_rng(6).standard_normal(n) * 0.05
+    Xg = torch.tensor(A + mu[None, :], dtype=torch.bfloat16, device=DEV)
+    X = _np(Xg)
+    res = api.rpca(Xg, k, p=10, q=2, seed=3, precision=precision)
+    ora = orc.rpca(X, k, p=10, q=2, seed=3)
+    np.testing.assert_allclose(_np(res["center"]), ora["center"], rtol=1e-6, atol=1e-7)
+    sd, sdo = np.sqrt(_np(res["eigvals"])), np.sqrt(ora["eigvals"])
+    tol = 1e-4 if precision == "plain" else 2e-3
+    assert np.max(np.abs(sd - sdo)) <= tol * sdo[0]
+
+
 def test_rpca_fp32_without_centring():
     from paper_1608_02148_amd import api
     A = syn.planted(2000, 300, syn.spectrum("exp", 300, tau=10.0), 41)
