@@ -371,7 +371,10 @@ int rsvd_test_matrix(rsvd_handle_t handle, int32_t dtype, int64_t n, int32_t l,
 
 /* Y = A X (Alg. rqb step 3, Alg. subspace_iter step 4): A m x K (dtype,
  * lda), X K x c (f64 for RSVD_F64 else f32, ldx), Y m x c (same type as X,
- * ldy).  c <= RSVD_MAX_L. */
+ * ldy).  c <= RSVD_MAX_L.  work: ignored (may be NULL) for
+ * RSVD_ARITH_STORAGE; the bf16 arithmetics pack X into bf16 there and need
+ * rsvd_block_workspace_size(dtype, m, K, c) bytes (RSVD_ERR_INVALID
+ * otherwise). */
 int rsvd_gemm_nn(rsvd_handle_t handle, int32_t dtype, int32_t arith, int64_t m, int64_t K, int32_t c,
                  const void* A, int64_t lda, const void* X, int64_t ldx,
                  void* Y, int64_t ldy, void* work, size_t work_bytes);

@@ -392,8 +392,10 @@ def gemm_nn(A, X, arith="storage"):
     m, K = A.shape
     c = X.shape[1]
     Y = torch.empty(m, c, dtype=out_dtype(A), device=A.device)
+    work = _block_ws(dt, m, K, c, A.device) if arith != "storage" else None
     L.check(L.load().rsvd_gemm_nn(handle(A.device), dt, L.ARITH[arith], m, K, c, _ptr(A), A.stride(0), _ptr(X),
-                                  X.stride(0), _ptr(Y), Y.stride(0), None, 0), "rsvd_gemm_nn")
+                                  X.stride(0), _ptr(Y), Y.stride(0), _ptr(work), work.numel() if work is not None
+                                  else 0), "rsvd_gemm_nn")
     return Y
 
 

@@ -58,12 +58,16 @@ int rsvd_block_workspace_size(rsvd_handle_t handle, int32_t dtype, int64_t m, in
 
 }  // extern "C"
 
+inline XPack xpack_of(const Plan& P, void* work) {
+    return XPack{work ? at<uint16_t>(work, P.xpack) : nullptr, P.ldxp, P.xplane};
+}
+
 template <typename TA, typename TC>
 static hipError_t gemm_nn_typed(hipStream_t st, int arith, int64_t m, int64_t K, int c, const void* A, int64_t lda,
-                                const void* X, int64_t ldx, void* Y, int64_t ldy) {
+                                const void* X, int64_t ldx, void* Y, int64_t ldy, XPack xp) {
     SingleExec ex{st};
     return gemm_step<TA, TC, MODE_NN>(ex, arith, 0, static_cast<const TA*>(A), lda, m, K, static_cast<const TC*>(X),
-                                      ldx, c, static_cast<TC*>(Y), ldy, 1, 0, nullptr, nullptr, 0);
+                                      ldx, c, static_cast<TC*>(Y), ldy, 1, 0, nullptr, nullptr, 0, Gate{}, xp);
 }
 
 extern "C" {
@@ -71,15 +75,17 @@ extern "C" {
 int rsvd_gemm_nn(rsvd_handle_t handle, int32_t dtype, int32_t arith, int64_t m, int64_t K, int32_t c,
                  const void* A, int64_t lda, const void* X, int64_t ldx, void* Y, int64_t ldy, void* work,
                  size_t work_bytes) {
-    (void)work; (void)work_bytes;
     if (!handle || m < 1 || K < 1 || c < 1 || c > RSVD_MAX_L || !A || !X || !Y) return RSVD_ERR_INVALID;
     if (lda < K || ldx < c || ldy < c || arith < 0 || arith > 2) return RSVD_ERR_INVALID;
     if (arith != 0 && dtype == RSVD_F64) return RSVD_ERR_UNSUPPORTED;
+    const Plan P = block_plan(dtype, m, K, c, handle->dev.num_cu);
+    if (arith != 0 && (!work || work_bytes < P.bytes)) return RSVD_ERR_INVALID;   // packed-X scratch
+    const XPack xp = xpack_of(P, arith != 0 ? work : nullptr);
     hipError_t e;
     switch (dtype) {
-        case RSVD_F64: e = gemm_nn_typed<double, double>(handle->stream, arith, m, K, c, A, lda, X, ldx, Y, ldy); break;
-        case RSVD_F32: e = gemm_nn_typed<float, float>(handle->stream, arith, m, K, c, A, lda, X, ldx, Y, ldy); break;
-        case RSVD_BF16: e = gemm_nn_typed<bf16_t, float>(handle->stream, arith, m, K, c, A, lda, X, ldx, Y, ldy); break;
+        case RSVD_F64: e = gemm_nn_typed<double, double>(handle->stream, arith, m, K, c, A, lda, X, ldx, Y, ldy, xp); break;
+        case RSVD_F32: e = gemm_nn_typed<float, float>(handle->stream, arith, m, K, c, A, lda, X, ldx, Y, ldy, xp); break;
+        case RSVD_BF16: e = gemm_nn_typed<bf16_t, float>(handle->stream, arith, m, K, c, A, lda, X, ldx, Y, ldy, xp); break;
         default: return RSVD_ERR_UNSUPPORTED;
     }
     return hip_status(handle, e);
@@ -93,13 +99,14 @@ static hipError_t gemm_tn_typed(rsvd_handle_t h, int arith, const Plan& P, int64
     SingleExec ex{h->stream};
     const int S = P.sp.tn;
     TC* part = at<TC>(work, P.part);
+    const XPack xp = xpack_of(P, work);
     if (S == 1)
         return gemm_step<TA, TC, MODE_TN>(ex, arith, 0, static_cast<const TA*>(A), lda, n, m,
                                           static_cast<const TC*>(Q), ldq, c, static_cast<TC*>(Z), ldz, 1, 0, nullptr,
-                                          nullptr, 0);
+                                          nullptr, 0, Gate{}, xp);
     RSVD_TRY((gemm_step<TA, TC, MODE_TN>(ex, arith, 0, static_cast<const TA*>(A), lda, n, m,
                                         static_cast<const TC*>(Q), ldq, c, part, P.Lp, S,
-                                        static_cast<int64_t>(n) * P.Lp, nullptr, nullptr, 0)));
+                                        static_cast<int64_t>(n) * P.Lp, nullptr, nullptr, 0, Gate{}, xp)));
     return reduce_step<TC>(ex, part, S, static_cast<int64_t>(n) * P.Lp, P.Lp, n, c, static_cast<TC*>(Z), ldz);
 }
 

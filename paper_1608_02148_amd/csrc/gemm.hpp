@@ -57,6 +57,9 @@ struct GemmArgs {
     uint32_t gate_mask;
     int32_t a_vec;       // 1 when A rows allow aligned vector loads
     int32_t x_vec;       // unused (X is read with scalar loads)
+    const uint16_t* xb;  // bf16 products: X packed by XPackBody, bf16 planes [column][k]
+    int64_t ldxb;        // k stride of a packed column (a multiple of 8)
+    int64_t xb_plane;    // elements from the hi plane to the lo plane
 };
 
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));

@@ -30,6 +30,50 @@ namespace rsvd {
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef __bf16 v4bf __attribute__((ext_vector_type(4)));
 
+// Scratch for packed X planes (see XPackBody).
+struct XPack { uint16_t* p = nullptr; int64_t ld = 0; int64_t plane = 0; };
+
+// X (K x ncols f32, ldx) -> bf16 planes P[c][k] (ld ldp): hi = bf16(x) and,
+// with split, lo = bf16(x - hi) at P + plane; columns ncols..cols-1 and k in
+// [K, K rounded up to 8) are zero.  One thread per (column, k-octet), the
+// threads of a k-octet on consecutive columns (coalesced reads of X).
+struct XPackArgs {
+    const float* X; int64_t ldx; int64_t K; int ncols; int cols; uint16_t* P; int64_t ldp; int64_t plane;
+    int split; const uint32_t* skip_flag; uint32_t skip_mask; Gate gate;
+};
+struct XPackBody {
+    typedef XPackArgs Args;
+    static constexpr int THREADS = 256;
+    static int blocks(const Args& a) { return static_cast<int>(cdiv(static_cast<int64_t>(a.cols) * cdiv(a.K, 8), THREADS)); }
+    static size_t lds(const Args&) { return 0; }
+    static __device__ void run(const Args& a, int b) {
+        if (a.skip_flag && ((*a.skip_flag & a.skip_mask) == 0u)) return;
+        if (a.gate.w && ((*a.gate.w & a.gate.mask) == 0u)) return;
+        const int64_t idx = static_cast<int64_t>(b) * THREADS + threadIdx.x;
+        const int c = static_cast<int>(idx % a.cols);
+        const int64_t k0 = 8 * (idx / a.cols);
+        if (k0 >= a.K) return;
+        uint32_t hi[4], lo[4];
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            uint32_t h2 = 0, l2 = 0;
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                const int64_t k = k0 + 2 * d + t;
+                const float x = (c < a.ncols && k < a.K) ? a.X[k * a.ldx + c] : 0.0f;
+                const __bf16 h = static_cast<__bf16>(x);
+                const __bf16 l = static_cast<__bf16>(x - static_cast<float>(h));
+                h2 |= static_cast<uint32_t>(__builtin_bit_cast(uint16_t, h)) << (16 * t);
+                l2 |= static_cast<uint32_t>(__builtin_bit_cast(uint16_t, l)) << (16 * t);
+            }
+            hi[d] = h2; lo[d] = l2;
+        }
+        uint16_t* dst = a.P + static_cast<int64_t>(c) * a.ldp + k0;
+        *reinterpret_cast<u32x4*>(dst) = u32x4{hi[0], hi[1], hi[2], hi[3]};
+        if (a.split) *reinterpret_cast<u32x4*>(dst + a.plane) = u32x4{lo[0], lo[1], lo[2], lo[3]};
+    }
+};
+
 template <typename TA, int MODE, bool SPLIT, int WR, int WC, int WGM, int WGN, int BK>
 struct Bf16Tile {
     static constexpr int BM = 16 * WR * WGM;
@@ -40,7 +84,7 @@ struct Bf16Tile {
     static constexpr bool A_LO = SPLIT && (sizeof(TA) > 2);   // bf16-stored A is exact
     // NN A items: (row, octet).  TN A / X items: (k-quad, 8-column block).
     static constexpr int A_ITEMS = (MODE == MODE_NN) ? BM * OCT : (BK / 4) * (BM / 8);
-    static constexpr int X_ITEMS = (BK / 4) * (NC / 8);
+    static constexpr int X_ITEMS = NC * OCT;          // (column, k-octet) of the packed X
     static constexpr int A_PASSES = (A_ITEMS + NT - 1) / NT;
     static constexpr int X_PASSES = (X_ITEMS + NT - 1) / NT;
     static constexpr int A_VALS = (MODE == MODE_NN) ? 8 : 32;   // floats per A item
@@ -105,7 +149,7 @@ __device__ __forceinline__ void gemm_bf16_body(const GemmArgs<TA, float, float>&
     constexpr bool RAW = sizeof(TA) == 2;
     float ra[RAW ? 1 : T::A_PASSES][RAW ? 1 : T::A_VALS];
     uint32_t rb[RAW ? T::A_PASSES : 1][RAW ? T::A_VALS / 2 : 1];
-    float rx[T::X_PASSES][32];
+    uint32_t rx[T::X_PASSES][SPLIT ? 8 : 4];
     // 8 bf16 words of A at p (vec: one 16-byte load), zero past `valid`,
     // minus mu[0..8) when mu is given (then rounded to bf16).
     auto load_raw8 = [&](const TA* p, int valid, const double* mu, uint32_t* w) {
@@ -183,22 +227,32 @@ __device__ __forceinline__ void gemm_bf16_body(const GemmArgs<TA, float, float>&
             }
         }
     };
+    // Packed X: item (column j, k-octet o), eight threads per 128 contiguous
+    // bytes of a column; k past the split's end reads as zero.
     auto load_x = [&](int64_t k0) {
 #pragma unroll
         for (int p = 0; p < T::X_PASSES; ++p) {
             const int it = p * T::NT + tid;
             if (it >= T::X_ITEMS) break;
-            const int cb = it % (T::NC / 8), kq = it / (T::NC / 8);
-            const int gc = col0 + 8 * cb;
-            const int cvalid = max(0, min(8, g.ncols - gc));
-            const bool xv = ((g.ldx & 3) == 0) && ((reinterpret_cast<uintptr_t>(g.X) & 15) == 0);
+            const int j = it / OCT, o = it % OCT;
+            const int64_t gk = k0 + 8 * o;
+            const int valid = static_cast<int>(max<int64_t>(0, min<int64_t>(8, kend - gk)));
+            const uint16_t* src = g.xb + static_cast<int64_t>(col0 + j) * g.ldxb + gk;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int64_t gk = k0 + 4 * kq + q;
-                float v[8];
-                load8<float>(g.X + gk * g.ldx + gc, xv, gk < kend ? cvalid : 0, v);
+            for (int pl = 0; pl < (SPLIT ? 2 : 1); ++pl) {
+                const uint16_t* s = src + pl * g.xb_plane;
+                if (valid == 8) {
+                    const u32x4 v = *reinterpret_cast<const u32x4*>(s);
 #pragma unroll
-                for (int e = 0; e < 8; ++e) rx[p][q * 8 + e] = v[e];
+                    for (int d = 0; d < 4; ++d) rx[p][4 * pl + d] = v[d];
+                } else {
+#pragma unroll
+                    for (int d = 0; d < 4; ++d) {
+                        const uint32_t lo = (2 * d < valid) ? s[2 * d] : 0u;
+                        const uint32_t hi = (2 * d + 1 < valid) ? s[2 * d + 1] : 0u;
+                        rx[p][4 * pl + d] = lo | (hi << 16);
+                    }
+                }
             }
         }
     };
@@ -259,8 +313,11 @@ __device__ __forceinline__ void gemm_bf16_body(const GemmArgs<TA, float, float>&
         for (int p = 0; p < T::X_PASSES; ++p) {
             const int it = p * T::NT + tid;
             if (it >= T::X_ITEMS) break;
-            const int cb = it % (T::NC / 8), kq = it / (T::NC / 8);
-            store_block(x_plane(buf, 0), x_plane(buf, SPLIT ? 1 : 0), SPLIT, 8 * cb, kq, rx[p]);
+            const int j = it / OCT, o = it % OCT;
+            const int off = swz<SK, OCT>(j, 8 * o);
+            *reinterpret_cast<u32x4*>(x_plane(buf, 0) + off) = u32x4{rx[p][0], rx[p][1], rx[p][2], rx[p][3]};
+            if constexpr (SPLIT)
+                *reinterpret_cast<u32x4*>(x_plane(buf, 1) + off) = u32x4{rx[p][4], rx[p][5], rx[p][6], rx[p][7]};
         }
     };
 

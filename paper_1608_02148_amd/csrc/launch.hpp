@@ -70,6 +70,7 @@ GemmArgs<TA, TX, TC> gemm_args(const TA* A, int64_t lda, int64_t rows, int64_t K
     g.gate = gate.w; g.gate_mask = gate.mask;
     g.a_vec = (reinterpret_cast<uintptr_t>(A) % vec_bytes == 0) && ((lda * sizeof(TA)) % vec_bytes == 0);
     g.x_vec = 0;
+    g.xb = nullptr; g.ldxb = 0; g.xb_plane = 0;
     return g;
 }
 
@@ -150,13 +151,24 @@ hipError_t gemm_bf16_cls(Ex& ex, int tc, const GemmArgs<TA, float, float>& g) {
     return ex.template run<Bf16Body<TA, MODE, SPLIT, 4, 4, 2, 2>>(g);
 }
 
+// The bf16 products read X packed once per product into bf16 planes (hi, and
+// lo for the split arithmetic) laid out [column][k], so that no workgroup
+// converts or transposes X itself: xp gives the scratch, ld >= K rounded up
+// to 8, plane >= (column tiles x NC) x ld elements.
 template <typename TA, int MODE, class Ex>
 hipError_t gemm_bf16(Ex& ex, bool split, int cls, const TA* A, int64_t lda, int64_t rows, int64_t K,
                      const float* X, int64_t ldx, int ncols, float* out, int64_t ldo, int S, int64_t part_stride,
-                     const double* mu, const uint32_t* skip_flag, uint32_t skip_mask, Gate gate = {}) {
-    const auto g = gemm_args<TA, float, float>(A, lda, rows, K, X, ldx, ncols, out, ldo, S, part_stride, mu,
-                                               skip_flag, skip_mask, 64, 16, gate);
+                     const double* mu, const uint32_t* skip_flag, uint32_t skip_mask, Gate gate, XPack xp) {
+    auto g = gemm_args<TA, float, float>(A, lda, rows, K, X, ldx, ncols, out, ldo, S, part_stride, mu,
+                                         skip_flag, skip_mask, 64, 16, gate);
     const int tc = (cls & 0xFFFF) ? (cls & 0xFFFF) : tile_cols(ncols);
+    const int cols = static_cast<int>(cdiv(ncols, tc) * tc);
+    if (!xp.p || xp.ld < rup(K, 8) || xp.ld % 8 != 0 || xp.plane < static_cast<int64_t>(cols) * xp.ld)
+        return hipErrorInvalidValue;
+    const hipError_t e = ex.template run<XPackBody>(XPackArgs{X, ldx, K, ncols, cols, xp.p, xp.ld, xp.plane,
+                                                              split ? 1 : 0, skip_flag, skip_mask, gate});
+    if (e != hipSuccess) return e;
+    g.xb = xp.p; g.ldxb = xp.ld; g.xb_plane = xp.plane;
     if (split) return gemm_bf16_cls<TA, MODE, true>(ex, tc, g);
     return gemm_bf16_cls<TA, MODE, false>(ex, tc, g);
 }
@@ -166,11 +178,12 @@ hipError_t gemm_bf16(Ex& ex, bool split, int cls, const TA* A, int64_t lda, int6
 template <typename TA, typename TC, int MODE, class Ex>
 hipError_t gemm_step(Ex& ex, int arith, int cls, const TA* A, int64_t lda, int64_t rows, int64_t K,
                      const TC* X, int64_t ldx, int ncols, TC* out, int64_t ldo, int S, int64_t part_stride,
-                     const double* mu, const uint32_t* skip_flag, uint32_t skip_mask, Gate gate = {}) {
+                     const double* mu, const uint32_t* skip_flag, uint32_t skip_mask, Gate gate = {},
+                     XPack xp = {}) {
     if constexpr (std::is_same<TC, float>::value) {
         if (arith != 0)
             return gemm_bf16<TA, MODE>(ex, arith == 2, cls, A, lda, rows, K, X, ldx, ncols, out, ldo, S,
-                                       part_stride, mu, skip_flag, skip_mask, gate);
+                                       part_stride, mu, skip_flag, skip_mask, gate, xp);
     }
     return gemm_plain<TA, TC, TC, MODE>(ex, cls, false, A, lda, rows, K, X, ldx, ncols, out, ldo, S, part_stride,
                                         mu, skip_flag, skip_mask, gate);

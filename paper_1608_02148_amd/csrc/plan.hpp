@@ -93,6 +93,10 @@ struct Plan {
     // probes) m x 32, V^T probes k x 32, U scratch m x k, column partial sums
     int probes = 0, est_split = 1;
     size_t eOm = 0, eY = 0, eT = 0, eW = 0, eU = 0, epart = 0, est = 0;
+    // bf16 products (mixed precision): X packed into bf16 hi / lo planes of
+    // Lp columns x ldxp (max(m, n) rounded up to 8) each
+    size_t xpack = 0;
+    int64_t ldxp = 0, xplane = 0;
 };
 
 inline int validate(int32_t dtype, int64_t m, int64_t n, int32_t k, const rsvd_params* prm) {
@@ -157,6 +161,11 @@ inline Plan make_plan(int dtype, int64_t m, int64_t n, int k, const rsvd_params*
     P.vtmp = L.take(static_cast<size_t>(n) * P.kp * cs);
     P.mu = L.take(static_cast<size_t>(n) * 8);
     P.mupart = L.take(static_cast<size_t>(P.sp.colsum) * n * 8);
+    if (prm->precision == RSVD_PREC_BF16_MIXED) {
+        P.ldxp = rup(std::max(m, n), 8);
+        P.xplane = static_cast<int64_t>(P.Lp) * P.ldxp;
+        P.xpack = L.take(2 * static_cast<size_t>(P.xplane) * sizeof(uint16_t));
+    }
     P.probes = prm->probes;
     if (P.probes > 0) {
         P.est_split = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(cdiv(m, 2048), 256)));
@@ -227,6 +236,9 @@ inline Plan block_plan(int32_t dtype, int64_t m, int64_t n, int32_t c, int num_c
     P.rinv = L.take(static_cast<size_t>(P.Lp) * P.Lp * cs);
     P.racc = L.take(4 * static_cast<size_t>(P.Lp) * P.Lp * 8);
     P.jk = L.take(static_cast<size_t>(P.Lp) * P.Lp * 8);
+    P.ldxp = rup(std::max(m, n), 8);
+    P.xplane = static_cast<int64_t>(P.Lp) * P.ldxp;
+    P.xpack = L.take(2 * static_cast<size_t>(P.xplane) * sizeof(uint16_t));
     P.bytes = L.off;
     return P;
 }

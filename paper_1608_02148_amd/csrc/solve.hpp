@@ -121,16 +121,17 @@ hipError_t solve_steps(Ex& ex, rsvd_handle_t prof, const Plan& P, const TA* A, i
     // and the projection (precision escalation).
     const bool mixed = prm->precision == RSVD_PREC_BF16_MIXED;
     const int early = mixed ? 1 : 0, late = mixed ? 2 : 0;
+    const XPack xp{P.ldxp ? at<uint16_t>(work, P.xpack) : nullptr, P.ldxp, P.xplane};   // bf16 products
     auto ax = [&](const TC* X, int arith, Gate gt) -> hipError_t {     // Y (m x Lp) = A X
         const int S = P.sp.nn;
         if (S == 1)
             return timed(prof, 0, pass_flops, nn_bytes, [&] {
                 return gemm_step<TA, TC, MODE_NN>(ex, arith, tile, A, lda, m, n, X, Lp, l, Y, Lp, 1, 0, mu,
-                                                  nullptr, 0, gt);
+                                                  nullptr, 0, gt, xp);
             });
         RSVD_TRY(timed(prof, 0, pass_flops, nn_bytes, [&] {
             return gemm_step<TA, TC, MODE_NN>(ex, arith, tile, A, lda, m, n, X, Lp, l, partc, Lp, S,
-                                              static_cast<int64_t>(m) * Lp, mu, nullptr, 0, gt);
+                                              static_cast<int64_t>(m) * Lp, mu, nullptr, 0, gt, xp);
         }));
         return reduce_step<TC>(ex, partc, S, static_cast<int64_t>(m) * Lp, Lp, m, l, Y, Lp, nullptr, 0, gt);
     };
@@ -164,11 +165,11 @@ hipError_t solve_steps(Ex& ex, rsvd_handle_t prof, const Plan& P, const TA* A, i
         if (S == 1)
             return timed(prof, 1, pass_flops, tn_bytes, [&] {
                 return gemm_step<TA, TC, MODE_TN>(ex, arith, tile_tn, A, lda, n, m, Y, Lp, l, dst, Lp, 1, 0, mu,
-                                                  nullptr, 0, gt);
+                                                  nullptr, 0, gt, xp);
             });
         RSVD_TRY(timed(prof, 1, pass_flops, tn_bytes, [&] {
             return gemm_step<TA, TC, MODE_TN>(ex, arith, tile_tn, A, lda, n, m, Y, Lp, l, partc, Lp, S,
-                                              static_cast<int64_t>(n) * Lp, mu, nullptr, 0, gt);
+                                              static_cast<int64_t>(n) * Lp, mu, nullptr, 0, gt, xp);
         }));
         return reduce_step<TC>(ex, partc, S, static_cast<int64_t>(n) * Lp, Lp, n, l, dst, Lp, nullptr, 0, gt);
     };
@@ -232,7 +233,8 @@ hipError_t solve_steps(Ex& ex, rsvd_handle_t prof, const Plan& P, const TA* A, i
         }
         RSVD_TRY(ex.template run<OmegaBody<TC>>(typename OmegaBody<TC>::Args{
             n, r, 32, prm->seed, stream_id ^ 0x80000000u, RSVD_NORMAL, eOm, 32}));
-        RSVD_TRY((gemm_step<TA, TC, MODE_NN>(ex, late, 32, A, lda, m, n, eOm, 32, r, eY, 32, 1, 0, mu, nullptr, 0)));
+        RSVD_TRY((gemm_step<TA, TC, MODE_NN>(ex, late, 32, A, lda, m, n, eOm, 32, r, eY, 32, 1, 0, mu, nullptr, 0,
+                                             Gate{}, xp)));
         const int S = P.sp.gram_n;
         if (S == 1) {
             RSVD_TRY((gemm_plain<TC, TC, TC, MODE_TN>(ex, 32, false, V, ldv, k, n, eOm, 32, r, eT, 32, 1, 0, nullptr,
