@@ -101,8 +101,12 @@ typedef struct {
 #define RSVD_ERR_NONFINITE   -4   /* reported by rsvd_sync_info only              */
 #define RSVD_ERR_BREAKDOWN   -5   /* reported by rsvd_sync_info only              */
 
-/* Largest sketch width l = k + p supported by the single-solve path. */
+/* Largest sketch width l = k + p: RSVD_MAX_L for batches and the kernel-level
+ * entry points, RSVD_MAX_L_SINGLE for rsvd_run / rpca_run (widths above
+ * RSVD_MAX_L take a blocked Cholesky and a Jacobi with its matrix in the
+ * workspace instead of LDS). */
 #define RSVD_MAX_L 128
+#define RSVD_MAX_L_SINGLE 256
 
 /* Fill *p with the paper's defaults: p = 10, q = 2, Gaussian Omega, seed 0. */
 void rsvd_default_params(rsvd_params* p);
@@ -133,7 +137,7 @@ int rsvd_workspace_size(rsvd_handle_t handle, int32_t dtype, int64_t m, int64_t 
 /* Randomized SVD, Alg. RSVDalgorithm (Sec. 3.3):
  *   [Q, B] = rqb(A, k, p, q); [U~, S, V] = svd(B); U = Q U~; truncate to k.
  * A      : m x n, leading dimension lda >= n, dtype `dtype`.
- * k      : target rank, 1 <= k < min(m, n).  l = min(k + p, m, n) <= RSVD_MAX_L.
+ * k      : target rank, 1 <= k < min(m, n).  l = min(k + p, m, n) <= RSVD_MAX_L_SINGLE.
  * U      : m x k (ldu >= k) or NULL (left vectors not wanted).
  * S      : k singular values, descending (f64, required).
  * V      : n x k (ldv >= k) or NULL (right vectors not wanted).

@@ -413,7 +413,7 @@ int rsvd_batch_create(rsvd_handle_t handle, int32_t dtype, int32_t count, const 
             prm[i].q = d.q;
             prm[i].p = d.p;
         }
-        const int v = validate(dtype, d.m, d.n, d.k, &prm[i]);
+        const int v = validate(dtype, d.m, d.n, d.k, &prm[i], RSVD_MAX_L);
         if (v != RSVD_OK) return v;
         if (!d.A || d.lda < d.n) return RSVD_ERR_INVALID;
         if (feat) {
@@ -461,8 +461,8 @@ int rsvd_batch_create_learned(rsvd_handle_t handle, int32_t dtype, int32_t count
                                              std::min(d.m, d.n));
         prm0[i].p = static_cast<int32_t>(std::max<int64_t>(0, l0 - d.k));
         prm1[i].q = RSVD_LEARNED_QMAX;
-        int v = validate(dtype, d.m, d.n, d.k, &prm0[i]);
-        if (v == RSVD_OK) v = validate(dtype, d.m, d.n, d.k, &prm1[i]);
+        int v = validate(dtype, d.m, d.n, d.k, &prm0[i], RSVD_MAX_L);
+        if (v == RSVD_OK) v = validate(dtype, d.m, d.n, d.k, &prm1[i], RSVD_MAX_L);
         if (v != RSVD_OK) return v;
         if (!d.A || d.lda < d.n || !d.S) return RSVD_ERR_INVALID;
         if ((d.U != nullptr) != with_u || (d.U && d.ldu < d.k) || (d.V && d.ldv < d.k)) return RSVD_ERR_INVALID;

@@ -169,6 +169,7 @@ struct CholArgs {
     int skip_unless_pending;  // skip unless this pass was requested (ST_NEED_P2 / P3)
     int adaptive;             // pass 1 may leave out pass 2 (see above)
     Gate gate;                // optional: the whole kernel runs only if the gate is open
+    int keep_flags;           // second block of a blocked factorisation: pass 1 keeps the request bits
 };
 
 constexpr int CHOL_MAX_L = RSVD_MAX_L;
@@ -214,7 +215,7 @@ __device__ __forceinline__ void chol_body(const CholArgs& a) {
 
     if (tid == 0) {
         uint32_t st = *a.status;
-        if (a.pass == 1) st &= ~(ST_NEED_P2 | ST_NEED_P3 | ST_SHIFTED);
+        if (a.pass == 1 && !a.keep_flags) st &= ~(ST_NEED_P2 | ST_NEED_P3 | ST_SHIFTED);
         s_flags = st;
     }
     auto load = [&](double shift) {
@@ -440,8 +441,9 @@ struct CholBody {
     static __device__ void run(const Args& a, int) { chol_body<TC, LM>(a); }
 };
 
-// Size class of the small dense kernels for an l x l problem.
-inline int small_lm(int l) { return l <= 32 ? 32 : (l <= 64 ? 64 : CHOL_MAX_L); }
+// Size class of the small dense kernels for an l x l problem (256: the
+// Jacobi with its matrix in global memory; the Cholesky is blocked there).
+inline int small_lm(int l) { return l <= 32 ? 32 : (l <= 64 ? 64 : (l <= CHOL_MAX_L ? CHOL_MAX_L : 2 * CHOL_MAX_L)); }
 
 // ------------------------------------------------------ one-sided Jacobi SVD
 // R (l x l upper triangular, f64, ld ldr) = W diag(sigma) J^T.  The columns of
@@ -464,6 +466,7 @@ struct JacobiArgs {
     uint32_t* status;
     int max_sweeps;
     double tol;
+    double* wglob;       // l > 128: W in global memory (l x jacobi_ldw(l) f64)
 };
 
 constexpr int JAC_GROUP = 16;      // lanes per column pair (one DPP row)
@@ -504,7 +507,9 @@ __device__ __forceinline__ void jacobi_body(const JacobiArgs& a) {
     __shared__ double s_sig[LM];
     const int l = a.l, tid = threadIdx.x, nt = blockDim.x;
     const int ldw = jacobi_ldw(l);
-    double* W = reinterpret_cast<double*>(smem_raw);     // column c at W + c * ldw
+    // column c at W + c * ldw: in LDS, or for l > 128 in global memory (it
+    // stays in L2; the barriers order its reads and writes within the group)
+    double* W = (LM > CHOL_MAX_L) ? a.wglob : reinterpret_cast<double*>(smem_raw);
     for (int idx = tid; idx < l * l; idx += nt) {
         const int c = idx / l, r = idx - c * l;
         W[c * ldw + r] = a.R[r * a.ldr + c];
@@ -628,9 +633,9 @@ __device__ __forceinline__ void jacobi_body(const JacobiArgs& a) {
 template <typename TC, int LM = CHOL_MAX_L>
 struct JacobiBody {
     typedef JacobiArgs Args;
-    static constexpr int THREADS = JAC_GROUP * (LM / 2);
+    static constexpr int THREADS = JAC_GROUP * (LM / 2) > 1024 ? 1024 : JAC_GROUP * (LM / 2);
     static int blocks(const Args&) { return 1; }
-    static size_t lds(const Args& a) { return jacobi_lds_bytes(a.l); }
+    static size_t lds(const Args& a) { return LM > CHOL_MAX_L ? 0 : jacobi_lds_bytes(a.l); }
     static __device__ void run(const Args& a, int) { jacobi_body<TC, LM>(a); }
 };
 
@@ -639,16 +644,71 @@ hipError_t run_chol(Ex& ex, const CholArgs& a) {
     switch (small_lm(a.l)) {
         case 32: return ex.template run<CholBody<TC, 32>>(a);
         case 64: return ex.template run<CholBody<TC, 64>>(a);
-        default: return ex.template run<CholBody<TC, CHOL_MAX_L>>(a);
+        case CHOL_MAX_L: return ex.template run<CholBody<TC, CHOL_MAX_L>>(a);
+        default: return hipErrorInvalidValue;      // l > 128: chol_blocked
     }
 }
+
+// Blocked factorisation pieces for 128 < l <= 256 (G = [G11 G12; G12^T G22],
+// G11 128 x 128): S = G22 - R12^T R12 (T holds R12^T R12 on entry, ld 128).
+struct SchurArgs { const double* G; int ldg; double* T; int l2; const uint32_t* skip_flag; uint32_t skip_mask; Gate gate; };
+struct SchurBody {
+    typedef SchurArgs Args;
+    static constexpr int THREADS = 256;
+    static int blocks(const Args& a) { return static_cast<int>(cdiv(static_cast<int64_t>(a.l2) * a.l2, THREADS)); }
+    static size_t lds(const Args&) { return 0; }
+    static __device__ void run(const Args& a, int b) {
+        if (a.skip_flag && ((*a.skip_flag & a.skip_mask) == 0u)) return;
+        if (a.gate.w && ((*a.gate.w & a.gate.mask) == 0u)) return;
+        const int idx = b * THREADS + threadIdx.x;
+        if (idx >= a.l2 * a.l2) return;
+        const int i = idx / a.l2, j = idx - i * a.l2;
+        a.T[i * 128 + j] = a.G[static_cast<int64_t>(128 + i) * a.ldg + 128 + j] - a.T[i * 128 + j];
+    }
+};
+
+// R^{-1} = [I11, -X12; 0, I22] (X12 = I11 R12 I22) into rinv (TC, ldr, zero
+// outside l x l) and R = [R11, R12; 0, R22] into rout (f64, ld l) if given.
+// A skipped pass leaves rinv and writes the identity to rout, as the
+// one-block kernel does.
+template <typename TC>
+struct CholAssembleBody {
+    struct Args {
+        const double* R11; const double* I11; const double* R12; const double* X12; const double* R22;
+        const double* I22; int l; TC* rinv; int ldr; double* rout; const uint32_t* skip_flag; uint32_t skip_mask;
+        Gate gate;
+    };
+    static constexpr int THREADS = 256;
+    static int blocks(const Args& a) { return static_cast<int>(cdiv(static_cast<int64_t>(a.ldr) * a.ldr, THREADS)); }
+    static size_t lds(const Args&) { return 0; }
+    static __device__ void run(const Args& a, int b) {
+        if (a.gate.w && ((*a.gate.w & a.gate.mask) == 0u)) return;
+        const int idx = b * THREADS + threadIdx.x;
+        if (idx >= a.ldr * a.ldr) return;
+        const int i = idx / a.ldr, j = idx - i * a.ldr;
+        const bool skip = a.skip_flag && ((*a.skip_flag & a.skip_mask) == 0u);
+        if (skip) {
+            if (a.rout && i < a.l && j < a.l) a.rout[i * a.l + j] = (i == j) ? 1.0 : 0.0;
+            return;
+        }
+        double x = 0.0, r = 0.0;
+        if (i < a.l && j < a.l && j >= i) {
+            if (j < 128) { x = a.I11[i * 128 + j]; r = a.R11[i * 128 + j]; }
+            else if (i < 128) { x = -a.X12[i * 128 + (j - 128)]; r = a.R12[i * 128 + (j - 128)]; }
+            else { x = a.I22[(i - 128) * 128 + (j - 128)]; r = a.R22[(i - 128) * (a.l - 128) + (j - 128)]; }
+        }
+        a.rinv[i * a.ldr + j] = static_cast<TC>(x);
+        if (a.rout && i < a.l && j < a.l) a.rout[i * a.l + j] = r;
+    }
+};
 
 template <typename TC, class Ex>
 hipError_t run_jacobi(Ex& ex, const JacobiArgs& a) {
     switch (small_lm(a.l)) {
         case 32: return ex.template run<JacobiBody<TC, 32>>(a);
         case 64: return ex.template run<JacobiBody<TC, 64>>(a);
-        default: return ex.template run<JacobiBody<TC, CHOL_MAX_L>>(a);
+        case CHOL_MAX_L: return ex.template run<JacobiBody<TC, CHOL_MAX_L>>(a);
+        default: return a.wglob ? ex.template run<JacobiBody<TC, 2 * CHOL_MAX_L>>(a) : hipErrorInvalidValue;
     }
 }
 

@@ -12,13 +12,13 @@ namespace rsvd {
 
 // Output tile width for c output columns: 32, 64 or 128 (column tiles of 128
 // beyond that); also the padded column count of the skinny work matrices.
-inline int tile_cols(int c) { return c <= 32 ? 32 : (c <= 64 ? 64 : 128); }
+inline int tile_cols(int c) { return c <= 32 ? 32 : (c <= 64 ? 64 : (c <= 128 ? 128 : 256)); }
 
 // Column class of the tall product tiles for sketch width c: 32, 64, 128, and
 // with fine = true (f32 compute) also 48, 80, 96.
 inline int tile_class(int c, bool fine) {
-    if (!fine) return tile_cols(c);
-    return c <= 32 ? 32 : c <= 48 ? 48 : c <= 64 ? 64 : c <= 80 ? 80 : c <= 96 ? 96 : 128;
+    if (!fine) return std::min(tile_cols(c), 128);
+    return c <= 32 ? 32 : c <= 48 ? 48 : c <= 64 ? 64 : c <= 80 ? 80 : c <= 96 ? 96 : 128;   // > 128: two tiles
 }
 
 constexpr size_t kAlign = 256;
@@ -93,13 +93,17 @@ struct Plan {
     // probes) m x 32, V^T probes k x 32, U scratch m x k, column partial sums
     int probes = 0, est_split = 1;
     size_t eOm = 0, eY = 0, eT = 0, eW = 0, eU = 0, epart = 0, est = 0;
+    // l > 128: scratch of the blocked Cholesky (7 blocks of 128 x 128 f64) and
+    // the Jacobi matrix W (l x (l rounded up to 16, plus 1), f64)
+    size_t cholx = 0, wglob = 0;
     // bf16 products (mixed precision): X packed into bf16 hi / lo planes of
     // Lp columns x ldxp (max(m, n) rounded up to 8) each
     size_t xpack = 0;
     int64_t ldxp = 0, xplane = 0;
 };
 
-inline int validate(int32_t dtype, int64_t m, int64_t n, int32_t k, const rsvd_params* prm) {
+inline int validate(int32_t dtype, int64_t m, int64_t n, int32_t k, const rsvd_params* prm,
+                    int max_l = RSVD_MAX_L_SINGLE) {
     if (dtype != RSVD_F64 && dtype != RSVD_F32 && dtype != RSVD_BF16) return RSVD_ERR_UNSUPPORTED;
     if (m < 1 || n < 1 || k < 1 || k >= std::min(m, n)) return RSVD_ERR_INVALID;
     if (!prm || prm->p < 0 || prm->q < 0) return RSVD_ERR_INVALID;
@@ -109,7 +113,7 @@ inline int validate(int32_t dtype, int64_t m, int64_t n, int32_t k, const rsvd_p
     if (prm->probes < 0 || prm->probes > 16) return RSVD_ERR_INVALID;
     if (m > (int64_t(1) << 32) || n > (int64_t(1) << 32)) return RSVD_ERR_UNSUPPORTED;
     const int64_t l = std::min<int64_t>(static_cast<int64_t>(k) + prm->p, std::min(m, n));
-    if (l > RSVD_MAX_L) return RSVD_ERR_UNSUPPORTED;
+    if (l > max_l) return RSVD_ERR_UNSUPPORTED;
     return RSVD_OK;
 }
 
@@ -161,6 +165,10 @@ inline Plan make_plan(int dtype, int64_t m, int64_t n, int k, const rsvd_params*
     P.vtmp = L.take(static_cast<size_t>(n) * P.kp * cs);
     P.mu = L.take(static_cast<size_t>(n) * 8);
     P.mupart = L.take(static_cast<size_t>(P.sp.colsum) * n * 8);
+    if (P.l > 128) {
+        P.cholx = L.take(7 * 128 * 128 * sizeof(double));
+        P.wglob = L.take(static_cast<size_t>(P.l) * (rup(P.l, 16) + 1) * sizeof(double));
+    }
     if (prm->precision == RSVD_PREC_BF16_MIXED) {
         P.ldxp = rup(std::max(m, n), 8);
         P.xplane = static_cast<int64_t>(P.Lp) * P.ldxp;

@@ -7,10 +7,42 @@
 
 namespace rsvd {
 
+// Cholesky with inverse for 128 < l <= 256 from the one-block kernel on
+// 128-blocks (all f64): R11 = chol(G11); R12 = R11^{-T} G12;
+// R22 = chol(G22 - R12^T R12); R^{-1} = [R11^{-1}, -R11^{-1} R12 R22^{-1}; 0, R22^{-1}].
+// x: 7 scratch blocks of 128 x 128 f64.  The second block keeps the status
+// bits the first one set (shift, breakdown, further passes requested).
+template <typename TC, class Ex>
+hipError_t chol_blocked(Ex& ex, const CholArgs& ca, double* x) {
+    const int l = ca.l, l2 = l - 128;
+    const size_t B = 128 * 128;
+    double *R11 = x, *I11 = x + B, *R12 = x + 2 * B, *T = x + 3 * B, *R22 = x + 4 * B, *I22 = x + 5 * B,
+           *T1 = x + 6 * B;
+    const uint32_t need = (ca.pass == 2) ? ST_NEED_P2 : ST_NEED_P3;
+    const uint32_t* skip = ca.skip_unless_pending ? ca.status : nullptr;
+    CholArgs c1 = ca;
+    c1.l = 128; c1.rinv = I11; c1.ldr = 128; c1.rout = R11;
+    RSVD_TRY((ex.template run<CholBody<double, CHOL_MAX_L>>(c1)));
+    RSVD_TRY((gemm_plain<double, double, double, MODE_TN>(ex, 0, true, I11, 128, 128, 128, ca.part + 128, ca.ldp, l2,
+                                                          R12, 128, 1, 0, nullptr, skip, need, ca.gate)));
+    RSVD_TRY((gemm_plain<double, double, double, MODE_TN>(ex, 0, true, R12, 128, l2, 128, R12, 128, l2, T, 128, 1, 0,
+                                                          nullptr, skip, need, ca.gate)));
+    RSVD_TRY(ex.template run<SchurBody>(SchurArgs{ca.part, ca.ldp, T, l2, skip, need, ca.gate}));
+    CholArgs c2 = ca;
+    c2.part = T; c2.ldp = 128; c2.l = l2; c2.rinv = I22; c2.ldr = 128; c2.rout = R22; c2.keep_flags = 1;
+    RSVD_TRY(run_chol<double>(ex, c2));
+    RSVD_TRY((gemm_plain<double, double, double, MODE_NN>(ex, 0, true, I11, 128, 128, 128, R12, 128, l2, T1, 128, 1,
+                                                          0, nullptr, skip, need, ca.gate)));
+    RSVD_TRY((gemm_plain<double, double, double, MODE_NN>(ex, 0, true, T1, 128, 128, l2, I22, 128, l2, T, 128, 1, 0,
+                                                          nullptr, skip, need, ca.gate)));
+    return ex.template run<CholAssembleBody<TC>>(typename CholAssembleBody<TC>::Args{
+        R11, I11, R12, T, R22, I22, l, static_cast<TC*>(ca.rinv), ca.ldr, ca.rout, skip, need, ca.gate});
+}
+
 template <typename TC, class Ex>
 hipError_t orthonormalize(Ex& ex, int tile, TC* M, int64_t ldm, int64_t rows, int l, int Lp, int S,
                           double* part, double* gram, TC* rinv, double* rfac, uint32_t* status,
-                          bool adaptive = false, Gate gate = {}) {
+                          bool adaptive = false, Gate gate = {}, double* cholx = nullptr) {
     for (int pass = 1; pass <= 3; ++pass) {
         const bool conditional = (pass == 3) || (pass == 2 && adaptive);
         const uint32_t* skip = conditional ? status : nullptr;
@@ -25,7 +57,13 @@ hipError_t orthonormalize(Ex& ex, int tile, TC* M, int64_t ldm, int64_t rows, in
         ca.rout = rfac ? rfac + static_cast<size_t>(pass - 1) * l * l : nullptr;
         ca.status = status; ca.pass = pass; ca.skip_unless_pending = conditional; ca.adaptive = adaptive;
         ca.gate = gate;
-        RSVD_TRY(run_chol<TC>(ex, ca));
+        ca.keep_flags = 0;
+        if (l > CHOL_MAX_L) {
+            if (!cholx) return hipErrorInvalidValue;
+            RSVD_TRY(chol_blocked<TC>(ex, ca, cholx));
+        } else {
+            RSVD_TRY(run_chol<TC>(ex, ca));
+        }
         RSVD_TRY((gemm_plain<TC, TC, TC, MODE_NN>(ex, tile, false, M, ldm, rows, l, rinv, Lp, l, M, ldm, 1, 0, nullptr,
                                                   skip, need, gate)));
     }
@@ -88,6 +126,7 @@ hipError_t solve_steps(Ex& ex, rsvd_handle_t prof, const Plan& P, const TA* A, i
     TC* xu = at<TC>(work, P.xu);
     double* jk = at<double>(work, P.jk);
     double* mu = o.center ? at<double>(work, P.mu) : nullptr;
+    double* cholx = P.cholx ? at<double>(work, P.cholx) : nullptr;     // l > 128
 
     // Batch members run their group's qmax iterations with the ones beyond
     // their own q switched off by the iteration word (status[1]).
@@ -179,17 +218,19 @@ hipError_t solve_steps(Ex& ex, rsvd_handle_t prof, const Plan& P, const TA* A, i
         const uint32_t run_bit = 1u << it, last_bit = 1u << (IT_LAST_SHIFT + it);
         const Gate act = gated ? Gate{itw, run_bit | last_bit} : Gate{};
         RSVD_TRY(orthonormalize<TC>(ex, tile, Y, Lp, m, l, Lp, P.sp.gram_m, partd, gram, rinv, nullptr, status,
-                                    true, act));
+                                    true, act, cholx));
         RSVD_TRY(aty(Z, early, act));
         RSVD_TRY(orthonormalize<TC>(ex, tile, Z, Lp, n, l, Lp, P.sp.gram_n, partd, gram, rinv, nullptr, status,
-                                    true, act));
+                                    true, act, cholx));
         RSVD_TRY(ax_step(Z, it == P.q - 1, run_bit, last_bit));
     }
     // Alg. rqb steps 9-10: Q = qr(Y); B^T = A^T Q.
-    RSVD_TRY(orthonormalize<TC>(ex, tile, Y, Lp, m, l, Lp, P.sp.gram_m, partd, gram, rinv, nullptr, status));
+    RSVD_TRY(orthonormalize<TC>(ex, tile, Y, Lp, m, l, Lp, P.sp.gram_m, partd, gram, rinv, nullptr, status, false,
+                                Gate{}, cholx));
     RSVD_TRY(aty(Z, late, Gate{}));
     // svd(B): B^T = Q_b R_b (Q_b overwrites Z), R_b = W S J^T by Jacobi.
-    RSVD_TRY(orthonormalize<TC>(ex, tile, Z, Lp, n, l, Lp, P.sp.gram_n, partd, gram, rinv, racc, status));
+    RSVD_TRY(orthonormalize<TC>(ex, tile, Z, Lp, n, l, Lp, P.sp.gram_n, partd, gram, rinv, racc, status, false,
+                                Gate{}, cholx));
     racc += 3 * static_cast<size_t>(l) * l;       // R_b = R3 R2 R1
     {
         JacobiArgs ja;
@@ -197,6 +238,7 @@ hipError_t solve_steps(Ex& ex, rsvd_handle_t prof, const Plan& P, const TA* A, i
         double* wks = at<double>(work, P.wks);
         ja.sigma = sigma; ja.xv = xv; ja.ldx = Lp; ja.xcols = P.kp; ja.wks = wks;
         ja.status = status; ja.max_sweeps = 60; ja.tol = jacobi_tol(ja.l);
+        ja.wglob = P.wglob ? at<double>(work, P.wglob) : nullptr;
         RSVD_TRY(run_jacobi<TC>(ex, ja));
         // J_k = R_b^T (W_k / sigma)
         RSVD_TRY((gemm_plain<double, double, double, MODE_TN>(ex, 0, true, racc, l, l, l, wks, k, k, jk, k, 1, 0,

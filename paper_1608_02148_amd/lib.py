@@ -22,7 +22,8 @@ STATUS = {
     -5: "numerical breakdown after the shifted Cholesky",
 }
 FLAG_CHOL_SHIFT, FLAG_DEGENERATE, FLAG_NONFINITE, FLAG_JACOBI_SLOW = 1, 2, 4, 8
-MAX_L = 128
+MAX_L = 128              # batches and kernel-level entry points
+MAX_L_SINGLE = 256       # rsvd_run / rpca_run
 
 
 class Params(ctypes.Structure):

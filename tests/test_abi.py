@@ -74,7 +74,8 @@ def _ws(lib, h, dtype, m, n, k, p=10, q=2, **kw):
     (0, 50, 5, 10, 2, -1),
     (100, 50, 5, -1, 2, -1),     # p < 0
     (100, 50, 5, 10, -1, -1),    # q < 0
-    (100000, 5000, 200, 20, 2, -2),   # l = 220 exceeds the single-solve limit
+    (100000, 5000, 240, 20, 2, -2),   # l = 260 exceeds the single-solve limit
+    (100000, 5000, 200, 20, 2, 0),    # l = 220: blocked Cholesky, Jacobi in global memory
     (100, 50, 5, 10, 2, 0),
     (100, 50, 45, 10, 2, 0),     # l clamped to min(m, n) = 50
 ])
@@ -289,3 +290,16 @@ def test_numpy_descriptor_layout_matches_the_struct():
     assert (c[1].A, c[1].lda, c[1].m, c[1].n, c[1].k, c[1].stream_id) == (12, 6, 400, 100, 8, 4)
     assert (c[1].U, c[1].ldu, c[1].S, c[1].V, c[1].ldv) == (22, 8, 32, 42, 8)
     assert (c[1].info, c[1].features, c[1].q, c[1].p) == (52, 62, 3, 20)
+
+
+def test_single_solve_width_limit(lib, handle):
+    """Single solves take sketch widths up to RSVD_MAX_L_SINGLE = 256 (batches
+    stay at RSVD_MAX_L = 128); the wider workspace includes the blocked
+    Cholesky's scratch and the Jacobi matrix."""
+    st, wide = _ws(lib, handle, L.RSVD_F32, 3000, 1000, 200)
+    assert st == 0
+    st, narrow = _ws(lib, handle, L.RSVD_F32, 3000, 1000, 100)
+    assert st == 0 and wide > narrow + 7 * 128 * 128 * 8
+    assert _ws(lib, handle, L.RSVD_F32, 3000, 1000, 236, p=20)[0] == 0      # l = 256
+    assert _ws(lib, handle, L.RSVD_F32, 3000, 1000, 237, p=20)[0] == -2     # l = 257
+    assert _create(lib, handle, [(3000, 1000, 200)])[0] == -2          # batches: l <= 128
