@@ -17,7 +17,7 @@ Also reported:
                    [64, 1024], k in [8, 64], p=10, q=2, sigma_i = i^-alpha)
                    as one captured graph: solves/s, p50 / p99 latency;
   bf16_storage  -- a 200000 x 20000 bfloat16 matrix (8 GB, sigma_i = i^-1.5
-                   for i <= 4096), k = 100, p = 20, q = 2: f32 arithmetic
+                   for i <= 4096), k = 200, p = 20, q = 2: f32 arithmetic
                    against the bf16 mixed-precision mode;
   learned       -- held-out generated matrices: FP32 plain (q=2, p=10 and
                    q=4, p=20) against learned q (one graph on the device,
@@ -166,13 +166,13 @@ def batched_arm(steps, warmup, precision="plain"):
     return out
 
 
-def bf16_storage_arm(steps, warmup, m=200000, n=20000, k=100, p=20, q=2, seed=2148):
+def bf16_storage_arm(steps, warmup, m=200000, n=20000, k=200, p=20, q=2, seed=2148):
     """bfloat16-stored A of 8 GB: the f32-arithmetic path (f32 matrix cores on
     the widened tiles) against the mixed mode (bf16 early passes, split-bf16
     last sketch and projection), with the per-pass product kernels timed by
     HIP events.  Accuracy: both runs' singular values against each other and
-    against the planted ones (bf16 rounding of A moves sigma_101 ~ 1e-3 by up
-    to about 1.2 %, Weyl)."""
+    against the planted ones (bf16 rounding of A, ||dA||_2 ~ 1.2e-5, moves
+    sigma_201 = 3.5e-4 by up to about 3 %, Weyl)."""
     import numpy as np
     import torch
 
@@ -231,7 +231,8 @@ def bf16_storage_arm(steps, warmup, m=200000, n=20000, k=100, p=20, q=2, seed=21
     s_pl, s_bf = svals["plain"], svals["bf16_mixed"]
     out["speedup_mixed_vs_plain"] = round(out["plain"]["ms_per_step"] / out["bf16_mixed"]["ms_per_step"], 3)
     out["max_sigma_diff_mixed_vs_plain_rel_sigma1"] = float(np.max(np.abs(s_pl - s_bf)) / s_pl[0])
-    out["max_rel_dev_from_planted_sigma"] = float(np.max(np.abs(s_pl - planted) / planted))
+    dev = np.abs(s_pl - planted) / planted
+    out["max_rel_dev_from_planted_sigma"] = {"top50": float(np.max(dev[:50])), f"all_{k}": float(np.max(dev))}
     del A
     torch.cuda.empty_cache()
     return out
