@@ -237,7 +237,12 @@ hipError_t solve_steps(Ex& ex, rsvd_handle_t prof, const Plan& P, const TA* A, i
         ja.R = racc; ja.ldr = l; ja.l = l; ja.k = k;
         double* wks = at<double>(work, P.wks);
         ja.sigma = sigma; ja.xv = xv; ja.ldx = Lp; ja.xcols = P.kp; ja.wks = wks;
-        ja.status = status; ja.max_sweeps = 60; ja.tol = jacobi_tol(ja.l);
+        // f32 outputs: pairs are rotated down to |cos| <= 1e-8, below f32
+        // rounding of the vectors; the singular values' error from the
+        // remaining cosines is second order (~1e-16 relative).  f64 outputs
+        // go to the rounding floor l u.
+        ja.status = status; ja.max_sweeps = 60;
+        ja.tol = sizeof(TC) == 4 ? std::max(1e-8, jacobi_tol(ja.l)) : jacobi_tol(ja.l);
         ja.wglob = P.wglob ? at<double>(work, P.wglob) : nullptr;
         RSVD_TRY(run_jacobi<TC>(ex, ja));
         // J_k = R_b^T (W_k / sigma)
