@@ -174,7 +174,7 @@ int rsvd_small_svd(rsvd_handle_t handle, int32_t c, const double* R, double* s, 
     double* wks = at<double>(work, P.gram);
     ja.sigma = s; ja.xv = W; ja.ldx = c; ja.xcols = c; ja.wks = wks;
     ja.status = status; ja.max_sweeps = 60; ja.tol = jacobi_tol(ja.l);
-    ja.wglob = nullptr;
+    ja.wglob = nullptr; ja.rot = nullptr; ja.outer = 0;
     e = run_jacobi<double>(ex, ja);
     if (e == hipSuccess)
         e = gemm_plain<double, double, double, MODE_TN>(ex, 0, true, R, c, c, c, wks, c, c, J, c, 1, 0, nullptr, nullptr, 0);

@@ -467,6 +467,8 @@ struct JacobiArgs {
     int max_sweeps;
     double tol;
     double* wglob;       // l > 128: W in global memory (l x jacobi_ldw(l) f64)
+    const uint32_t* rot; // non-null: W already holds the rotated columns (block
+    int outer;           // sweeps, see JacobiBlockBody); rot[s] = sweep s rotated
 };
 
 constexpr int JAC_GROUP = 16;      // lanes per column pair (one DPP row)
@@ -510,10 +512,12 @@ __device__ __forceinline__ void jacobi_body(const JacobiArgs& a) {
     // column c at W + c * ldw: in LDS, or for l > 128 in global memory (it
     // stays in L2; the barriers order its reads and writes within the group)
     double* W = (LM > CHOL_MAX_L) ? a.wglob : reinterpret_cast<double*>(smem_raw);
-    for (int idx = tid; idx < l * l; idx += nt) {
-        const int c = idx / l, r = idx - c * l;
-        W[c * ldw + r] = a.R[r * a.ldr + c];
-    }
+    const bool finish_only = a.rot != nullptr;
+    if (!finish_only)
+        for (int idx = tid; idx < l * l; idx += nt) {
+            const int c = idx / l, r = idx - c * l;
+            W[c * ldw + r] = a.R[r * a.ldr + c];
+        }
     __syncthreads();
 
     const int lp = l + (l & 1);
@@ -525,7 +529,7 @@ __device__ __forceinline__ void jacobi_body(const JacobiArgs& a) {
     // |w_b'|^2 = beta + t gamma), so a pair needs one inner product, not three.
     __shared__ double s_norm[LM];
     int sweep = 0;
-    for (; sweep < a.max_sweeps; ++sweep) {
+    for (; !finish_only && sweep < a.max_sweeps; ++sweep) {
         if (tid == 0) s_rotated = 0;
         for (int c = group; c < l; c += ngroups) {
             const double* wc = W + c * ldw;
@@ -584,8 +588,14 @@ __device__ __forceinline__ void jacobi_body(const JacobiArgs& a) {
         __syncthreads();
     }
     if (tid == 0) {   // record the sweep count (bits 24..31) and the limit flag
+        int limit = a.max_sweeps;
+        if (finish_only) {
+            sweep = 0;
+            while (sweep < a.outer && a.rot[sweep]) ++sweep;
+            limit = a.outer;
+        }
         const uint32_t sw = static_cast<uint32_t>(min(sweep + 1, 255)) << 24;
-        atomicOr(a.status, sw | (sweep >= a.max_sweeps ? RSVD_FLAG_JACOBI_SLOW : 0u));
+        atomicOr(a.status, sw | (sweep >= limit ? RSVD_FLAG_JACOBI_SLOW : 0u));
     }
 
     // sigma_c = |W[:, c]|; normalise the columns of W.
@@ -699,6 +709,121 @@ struct CholAssembleBody {
         }
         a.rinv[i * a.ldr + j] = static_cast<TC>(x);
         if (a.rout && i < a.l && j < a.l) a.rout[i * a.l + j] = r;
+    }
+};
+
+// ---------------------------------------------- block Jacobi for 128 < l <= 256
+// W (l x l, column c at W + c ldw, global memory) is split into JB = 8 column
+// blocks of bs = ceil(l / 8) <= 32.  One outer sweep takes JB - 1 rounds; in
+// round r the JB / 2 block pairs of the round-robin schedule go to JB / 2
+// workgroups, each of which loads its two blocks (<= 64 columns) into LDS,
+// rotates every pair of those columns once (one-sided Jacobi, same rotation
+// test as above), and writes them back.  rot[s] = 1 when outer sweep s rotated
+// any pair; a launch of sweep s > 0 exits at once when rot[s - 1] = 0.
+constexpr int JB = 8;
+constexpr int kJacobiOuter = 30;       // outer sweeps issued (converged ones exit at once)
+struct JacobiBlockArgs { double* W; int ldw; int l; int bs; int sweep; int round; uint32_t* rot; double tol; };
+struct JacobiPrepArgs { const double* R; int ldr; int l; double* W; int ldw; uint32_t* rot; int nrot; };
+
+// W[c][r] = R[r][c]; rot[0..nrot) = 0.
+struct JacobiPrepBody {
+    typedef JacobiPrepArgs Args;
+    static constexpr int THREADS = 256;
+    static int blocks(const Args& a) { return static_cast<int>(cdiv(static_cast<int64_t>(a.l) * a.l, THREADS)); }
+    static size_t lds(const Args&) { return 0; }
+    static __device__ void run(const Args& a, int b) {
+        const int idx = b * THREADS + threadIdx.x;
+        if (idx < a.nrot) a.rot[idx] = 0u;
+        if (idx >= a.l * a.l) return;
+        const int c = idx / a.l, r = idx - c * a.l;
+        a.W[c * a.ldw + r] = a.R[r * a.ldr + c];
+    }
+};
+
+struct JacobiBlockBody {
+    typedef JacobiBlockArgs Args;
+    static constexpr int NLOC = 64;                       // two blocks of <= 32 columns
+    static constexpr int THREADS = JAC_GROUP * (NLOC / 2);
+    static constexpr int PER_LANE = 2 * CHOL_MAX_L / JAC_GROUP;   // rows <= 256
+    static int blocks(const Args&) { return JB / 2; }
+    static size_t lds(const Args& a) { return static_cast<size_t>(NLOC) * a.ldw * sizeof(double); }
+    static __device__ void run(const Args& a, int p) {
+        if (a.sweep > 0 && a.rot[a.sweep - 1] == 0u) return;        // converged
+        extern __shared__ __align__(16) unsigned char smem_raw[];
+        double* Ws = reinterpret_cast<double*>(smem_raw);
+        __shared__ int s_gcol[NLOC];
+        __shared__ double s_norm[NLOC];
+        __shared__ int s_rotated;
+        const int tid = threadIdx.x, l = a.l, ldw = a.ldw;
+        int ba, bb;
+        if (p == 0) { ba = a.round; bb = JB - 1; }
+        else { ba = (a.round + p) % (JB - 1); bb = (a.round - p + JB - 1) % (JB - 1); }
+        const int a0 = ba * a.bs, a1 = min(l, a0 + a.bs), b0 = bb * a.bs, b1 = min(l, b0 + a.bs);
+        const int na = max(0, a1 - a0), nloc = na + max(0, b1 - b0);
+        if (tid < NLOC) s_gcol[tid] = (tid < na) ? a0 + tid : (tid < nloc ? b0 + tid - na : -1);
+        if (tid == 0) s_rotated = 0;
+        __syncthreads();
+        for (int idx = tid; idx < nloc * l; idx += THREADS) {
+            const int i = idx / l, r = idx - i * l;
+            Ws[i * ldw + r] = a.W[s_gcol[i] * ldw + r];
+        }
+        __syncthreads();
+        const int group = tid / JAC_GROUP, gl = tid % JAC_GROUP;
+        constexpr int NG = THREADS / JAC_GROUP;
+        for (int c = group; c < nloc; c += NG) {
+            double ss = 0.0;
+            for (int r = gl; r < l; r += JAC_GROUP) ss += Ws[c * ldw + r] * Ws[c * ldw + r];
+            ss = group_sum(ss);
+            if (gl == 0) s_norm[c] = ss;
+        }
+        __syncthreads();
+        const int lp = nloc + (nloc & 1), npairs = lp / 2;
+        for (int round = 0; round < lp - 1; ++round) {
+            for (int q = group; q < npairs; q += NG) {
+                int ca, cb;
+                if (q == 0) { ca = round; cb = lp - 1; }
+                else { ca = (round + q) % (lp - 1); cb = (round - q + lp - 1) % (lp - 1); }
+                if (ca >= nloc || cb >= nloc) continue;
+                double* wa = Ws + ca * ldw;
+                double* wb = Ws + cb * ldw;
+                double xa[PER_LANE], xb[PER_LANE];
+#pragma unroll
+                for (int t = 0; t < PER_LANE; ++t) {
+                    const int r = gl + JAC_GROUP * t;
+                    xa[t] = (r < l) ? wa[r] : 0.0;
+                    xb[t] = (r < l) ? wb[r] : 0.0;
+                }
+                const double al = s_norm[ca], be = s_norm[cb];
+                double ga = 0.0;
+#pragma unroll
+                for (int t = 0; t < PER_LANE; ++t) ga += xa[t] * xb[t];
+                ga = group_sum(ga);
+                if (ga != 0.0 && fabs(ga) > a.tol * sqrt(al * be)) {
+                    const double zeta = (be - al) / (2.0 * ga);
+                    const double tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                    const double c = 1.0 / sqrt(1.0 + tt * tt), sn = c * tt;
+                    if (gl == 0) {
+                        s_norm[ca] = fmax(al - tt * ga, 0.0);
+                        s_norm[cb] = be + tt * ga;
+                        s_rotated = 1;
+                    }
+#pragma unroll
+                    for (int t = 0; t < PER_LANE; ++t) {
+                        const int r = gl + JAC_GROUP * t;
+                        if (r < l) {
+                            wa[r] = c * xa[t] - sn * xb[t];
+                            wb[r] = sn * xa[t] + c * xb[t];
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        for (int idx = tid; idx < nloc * l; idx += THREADS) {
+            const int i = idx / l, r = idx - i * l;
+            a.W[s_gcol[i] * ldw + r] = Ws[i * ldw + r];
+        }
+        if (tid == 0 && s_rotated) a.rot[a.sweep] = 1u;
     }
 };
 

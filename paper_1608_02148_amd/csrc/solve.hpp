@@ -244,6 +244,19 @@ hipError_t solve_steps(Ex& ex, rsvd_handle_t prof, const Plan& P, const TA* A, i
         ja.status = status; ja.max_sweeps = 60;
         ja.tol = sizeof(TC) == 4 ? std::max(1e-8, jacobi_tol(ja.l)) : jacobi_tol(ja.l);
         ja.wglob = P.wglob ? at<double>(work, P.wglob) : nullptr;
+        ja.rot = nullptr; ja.outer = 0;
+        if (l > CHOL_MAX_L) {
+            // block sweeps over W in global memory, then the one-workgroup
+            // kernel only normalises, sorts and writes the outputs
+            uint32_t* rot = at<uint32_t>(work, P.jrot);
+            const int ldw = jacobi_ldw(l), bs = static_cast<int>(cdiv(l, JB));
+            RSVD_TRY(ex.template run<JacobiPrepBody>(JacobiPrepArgs{racc, l, l, ja.wglob, ldw, rot, kJacobiOuter}));
+            for (int s = 0; s < kJacobiOuter; ++s)
+                for (int r = 0; r < JB - 1; ++r)
+                    RSVD_TRY(ex.template run<JacobiBlockBody>(JacobiBlockArgs{ja.wglob, ldw, l, bs, s, r, rot,
+                                                                              ja.tol}));
+            ja.rot = rot; ja.outer = kJacobiOuter;
+        }
         RSVD_TRY(run_jacobi<TC>(ex, ja));
         // J_k = R_b^T (W_k / sigma)
         RSVD_TRY((gemm_plain<double, double, double, MODE_TN>(ex, 0, true, racc, l, l, l, wks, k, k, jk, k, 1, 0,
