@@ -17,7 +17,7 @@ template <typename T> constexpr int gemm_bk() { return sizeof(T) == 8 ? 16 : 32;
 
 
 // Storage-precision product (f32 / f64 matrix cores).  Workgroup b of a
-// problem covers row tile b % gx, split (b / gx) % S, column tile b / (gx S).
+// problem covers column tile b % C, row tile (b / C) % gx, split b / (C gx).
 template <typename TA, typename TX, typename TC, int MODE, int WR, int WC, int WGM, int WGN>
 struct GemmBody {
     static constexpr int BK = gemm_bk<TC>();
@@ -29,9 +29,12 @@ struct GemmBody {
     }
     static size_t lds(const Args&) { return T::LDS_BYTES; }
     static __device__ void run(const Args& g, int b) {
+        // column tiles vary fastest: the tiles that read the same rows of A
+        // run side by side (same XCD, same L2) when there are several
         const int gx = static_cast<int>(cdiv(g.rows, T::BM));
-        const int rest = b / gx;
-        gemm_tile_body<TA, TX, TC, MODE, WR, WC, WGM, WGN, BK>(g, b % gx, rest % g.splits, rest / g.splits);
+        const int nct = static_cast<int>(cdiv(g.ncols, T::NC));
+        const int rest = b / nct;
+        gemm_tile_body<TA, TX, TC, MODE, WR, WC, WGM, WGN, BK>(g, rest % gx, rest / gx, b % nct);
     }
 };
 
@@ -48,8 +51,9 @@ struct Bf16Body {
     static size_t lds(const Args&) { return T::LDS_BYTES; }
     static __device__ void run(const Args& g, int b) {
         const int gx = static_cast<int>(cdiv(g.rows, T::BM));
-        const int rest = b / gx;
-        gemm_bf16_body<TA, MODE, SPLIT, WR, WC, WGM, WGN, BK>(g, b % gx, rest % g.splits, rest / g.splits);
+        const int nct = static_cast<int>(cdiv(g.ncols, T::NC));
+        const int rest = b / nct;
+        gemm_bf16_body<TA, MODE, SPLIT, WR, WC, WGM, WGN, BK>(g, rest % gx, rest / gx, b % nct);
     }
 };
 
