@@ -375,7 +375,7 @@ int rsvd_test_matrix(rsvd_handle_t handle, int32_t dtype, int64_t n, int32_t l,
 
 /* Y = A X (Alg. rqb step 3, Alg. subspace_iter step 4): A m x K (dtype,
  * lda), X K x c (f64 for RSVD_F64 else f32, ldx), Y m x c (same type as X,
- * ldy).  c <= RSVD_MAX_L.  work: ignored (may be NULL) for
+ * ldy).  c <= RSVD_MAX_L_SINGLE.  work: ignored (may be NULL) for
  * RSVD_ARITH_STORAGE; the bf16 arithmetics pack X into bf16 there and need
  * rsvd_block_workspace_size(dtype, m, K, c) bytes (RSVD_ERR_INVALID
  * otherwise). */
@@ -384,7 +384,7 @@ int rsvd_gemm_nn(rsvd_handle_t handle, int32_t dtype, int32_t arith, int64_t m, 
                  void* Y, int64_t ldy, void* work, size_t work_bytes);
 
 /* Z = A^T Q (Alg. subspace_iter step 3; Alg. rqb step 10 gives B^T): A m x n
- * (dtype, lda), Q m x c (f64/f32, ldq), Z n x c (ldz).  c <= RSVD_MAX_L. */
+ * (dtype, lda), Q m x c (f64/f32, ldq), Z n x c (ldz).  c <= RSVD_MAX_L_SINGLE. */
 int rsvd_gemm_tn(rsvd_handle_t handle, int32_t dtype, int32_t arith, int64_t m, int64_t n, int32_t c,
                  const void* A, int64_t lda, const void* Q, int64_t ldq,
                  void* Z, int64_t ldz, void* work, size_t work_bytes);
@@ -397,7 +397,8 @@ int rsvd_orthonormalize(rsvd_handle_t handle, int32_t dtype, int64_t m, int32_t 
                         void* Y, int64_t ldy, double* R, uint32_t* flags,
                         void* work, size_t work_bytes);
 
-/* Workspace bytes for the three building blocks above at these sizes. */
+/* Workspace bytes for the three building blocks above at these sizes (c up to
+ * RSVD_MAX_L_SINGLE for the products, RSVD_MAX_L for the other two). */
 int rsvd_block_workspace_size(rsvd_handle_t handle, int32_t dtype, int64_t m,
                               int64_t n, int32_t c, size_t* bytes);
 

@@ -51,7 +51,7 @@ int rsvd_test_matrix(rsvd_handle_t handle, int32_t dtype, int64_t n, int32_t l, 
 
 int rsvd_block_workspace_size(rsvd_handle_t handle, int32_t dtype, int64_t m, int64_t n, int32_t c,
                               size_t* bytes) {
-    if (!handle || !bytes || m < 1 || n < 1 || c < 1 || c > RSVD_MAX_L) return RSVD_ERR_INVALID;
+    if (!handle || !bytes || m < 1 || n < 1 || c < 1 || c > RSVD_MAX_L_SINGLE) return RSVD_ERR_INVALID;
     *bytes = block_plan(dtype, m, n, c, handle->dev.num_cu).bytes;
     return RSVD_OK;
 }
@@ -75,7 +75,7 @@ extern "C" {
 int rsvd_gemm_nn(rsvd_handle_t handle, int32_t dtype, int32_t arith, int64_t m, int64_t K, int32_t c,
                  const void* A, int64_t lda, const void* X, int64_t ldx, void* Y, int64_t ldy, void* work,
                  size_t work_bytes) {
-    if (!handle || m < 1 || K < 1 || c < 1 || c > RSVD_MAX_L || !A || !X || !Y) return RSVD_ERR_INVALID;
+    if (!handle || m < 1 || K < 1 || c < 1 || c > RSVD_MAX_L_SINGLE || !A || !X || !Y) return RSVD_ERR_INVALID;
     if (lda < K || ldx < c || ldy < c || arith < 0 || arith > 2) return RSVD_ERR_INVALID;
     if (arith != 0 && dtype == RSVD_F64) return RSVD_ERR_UNSUPPORTED;
     const Plan P = block_plan(dtype, m, K, c, handle->dev.num_cu);
@@ -115,7 +115,7 @@ extern "C" {
 int rsvd_gemm_tn(rsvd_handle_t handle, int32_t dtype, int32_t arith, int64_t m, int64_t n, int32_t c,
                  const void* A, int64_t lda, const void* Q, int64_t ldq, void* Z, int64_t ldz, void* work,
                  size_t work_bytes) {
-    if (!handle || m < 1 || n < 1 || c < 1 || c > RSVD_MAX_L || !A || !Q || !Z || !work) return RSVD_ERR_INVALID;
+    if (!handle || m < 1 || n < 1 || c < 1 || c > RSVD_MAX_L_SINGLE || !A || !Q || !Z || !work) return RSVD_ERR_INVALID;
     if (lda < n || ldq < c || ldz < c || arith < 0 || arith > 2) return RSVD_ERR_INVALID;
     if (arith != 0 && dtype == RSVD_F64) return RSVD_ERR_UNSUPPORTED;
     const Plan P = block_plan(dtype, m, n, c, handle->dev.num_cu);

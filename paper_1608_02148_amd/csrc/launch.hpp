@@ -152,6 +152,7 @@ hipError_t gemm_bf16_cls(Ex& ex, int tc, const GemmArgs<TA, float, float>& g) {
     if (tc == 64) return ex.template run<Bf16Body<TA, MODE, SPLIT, 4, 2, 2, 2>>(g);
     if (tc == 80) return ex.template run<Bf16Body<TA, MODE, SPLIT, 2, 5, 4, 1>>(g);
     if (tc == 96) return ex.template run<Bf16Body<TA, MODE, SPLIT, 4, 3, 2, 2>>(g);
+    if (tc == 256) return ex.template run<Bf16Body<TA, MODE, SPLIT, 4, 4, 2, 4>>(g);
     return ex.template run<Bf16Body<TA, MODE, SPLIT, 4, 4, 2, 2>>(g);
 }
 
@@ -165,7 +166,8 @@ hipError_t gemm_bf16(Ex& ex, bool split, int cls, const TA* A, int64_t lda, int6
                      const double* mu, const uint32_t* skip_flag, uint32_t skip_mask, Gate gate, XPack xp) {
     auto g = gemm_args<TA, float, float>(A, lda, rows, K, X, ldx, ncols, out, ldo, S, part_stride, mu,
                                          skip_flag, skip_mask, 64, 16, gate);
-    const int tc = (cls & 0xFFFF) ? (cls & 0xFFFF) : tile_cols(ncols);
+    int tc = (cls & 0xFFFF) ? (cls & 0xFFFF) : tile_cols(ncols);
+    if (ncols > 128) tc = 256;      // one 256-column tile: each A tile is staged once
     const int cols = static_cast<int>(cdiv(ncols, tc) * tc);
     if (!xp.p || xp.ld < rup(K, 8) || xp.ld % 8 != 0 || xp.plane < static_cast<int64_t>(cols) * xp.ld)
         return hipErrorInvalidValue;

@@ -659,6 +659,26 @@ hipError_t run_chol(Ex& ex, const CholArgs& a) {
     }
 }
 
+// dst (rows x cols, ldd) = src (ld lds), under the same skip / gate conditions
+// as the product that wrote src.
+template <typename T>
+struct CopyColsBody {
+    struct Args { const T* src; int64_t lds; T* dst; int64_t ldd; int64_t rows; int cols;
+                  const uint32_t* skip_flag; uint32_t skip_mask; Gate gate; };
+    static constexpr int THREADS = 256;
+    static int blocks(const Args& a) { return static_cast<int>(cdiv(a.rows * a.cols, THREADS)); }
+    static size_t lds(const Args&) { return 0; }
+    static __device__ void run(const Args& a, int b) {
+        if (a.skip_flag && ((*a.skip_flag & a.skip_mask) == 0u)) return;
+        if (a.gate.w && ((*a.gate.w & a.gate.mask) == 0u)) return;
+        const int64_t idx = static_cast<int64_t>(b) * THREADS + threadIdx.x;
+        if (idx >= a.rows * a.cols) return;
+        const int64_t r = idx / a.cols;
+        const int c = static_cast<int>(idx - r * a.cols);
+        a.dst[r * a.ldd + c] = a.src[r * a.lds + c];
+    }
+};
+
 // Blocked factorisation pieces for 128 < l <= 256 (G = [G11 G12; G12^T G22],
 // G11 128 x 128): S = G22 - R12^T R12 (T holds R12^T R12 on entry, ld 128).
 struct SchurArgs { const double* G; int ldg; double* T; int l2; const uint32_t* skip_flag; uint32_t skip_mask; Gate gate; };

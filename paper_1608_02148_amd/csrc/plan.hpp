@@ -95,7 +95,7 @@ struct Plan {
     size_t eOm = 0, eY = 0, eT = 0, eW = 0, eU = 0, epart = 0, est = 0;
     // l > 128: scratch of the blocked Cholesky (7 blocks of 128 x 128 f64) and
     // the Jacobi matrix W (l x (l rounded up to 16, plus 1), f64)
-    size_t cholx = 0, wglob = 0, jrot = 0;
+    size_t cholx = 0, wglob = 0, jrot = 0, qtmp = 0;
     // bf16 products (mixed precision): X packed into bf16 hi / lo planes of
     // Lp columns x ldxp (max(m, n) rounded up to 8) each
     size_t xpack = 0;
@@ -169,6 +169,7 @@ inline Plan make_plan(int dtype, int64_t m, int64_t n, int k, const rsvd_params*
         P.cholx = L.take(7 * 128 * 128 * sizeof(double));
         P.wglob = L.take(static_cast<size_t>(P.l) * (rup(P.l, 16) + 1) * sizeof(double));
         P.jrot = L.take(64 * sizeof(uint32_t));
+        P.qtmp = L.take(static_cast<size_t>(std::max(m, n)) * P.Lp * cs);
     }
     if (prm->precision == RSVD_PREC_BF16_MIXED) {
         P.ldxp = rup(std::max(m, n), 8);

@@ -42,7 +42,7 @@ hipError_t chol_blocked(Ex& ex, const CholArgs& ca, double* x) {
 template <typename TC, class Ex>
 hipError_t orthonormalize(Ex& ex, int tile, TC* M, int64_t ldm, int64_t rows, int l, int Lp, int S,
                           double* part, double* gram, TC* rinv, double* rfac, uint32_t* status,
-                          bool adaptive = false, Gate gate = {}, double* cholx = nullptr) {
+                          bool adaptive = false, Gate gate = {}, double* cholx = nullptr, TC* qtmp = nullptr) {
     for (int pass = 1; pass <= 3; ++pass) {
         const bool conditional = (pass == 3) || (pass == 2 && adaptive);
         const uint32_t* skip = conditional ? status : nullptr;
@@ -64,8 +64,22 @@ hipError_t orthonormalize(Ex& ex, int tile, TC* M, int64_t ldm, int64_t rows, in
         } else {
             RSVD_TRY(run_chol<TC>(ex, ca));
         }
-        RSVD_TRY((gemm_plain<TC, TC, TC, MODE_NN>(ex, tile, false, M, ldm, rows, l, rinv, Lp, l, M, ldm, 1, 0, nullptr,
-                                                  skip, need, gate)));
+        // Q = M R^{-1} in place is safe while one column tile holds all l
+        // columns (each workgroup reads its rows before writing them); with
+        // two tiles (l > 128) one tile's writes would race the other's reads,
+        // so the product goes through qtmp (rows x Lp) and is copied back.
+        TC* out = M;
+        int64_t ldo = ldm;
+        if (l > CHOL_MAX_L) {
+            if (!qtmp) return hipErrorInvalidValue;
+            out = qtmp;
+            ldo = Lp;
+        }
+        RSVD_TRY((gemm_plain<TC, TC, TC, MODE_NN>(ex, tile, false, M, ldm, rows, l, rinv, Lp, l, out, ldo, 1, 0,
+                                                  nullptr, skip, need, gate)));
+        if (out != M)
+            RSVD_TRY(ex.template run<CopyColsBody<TC>>(typename CopyColsBody<TC>::Args{
+                out, ldo, M, ldm, rows, l, skip, need, gate}));
     }
     if (rfac) {   // R = R3 (R2 R1); the product R2 R1 goes through the gram scratch
         const size_t ll = static_cast<size_t>(l) * l;
@@ -127,6 +141,7 @@ hipError_t solve_steps(Ex& ex, rsvd_handle_t prof, const Plan& P, const TA* A, i
     double* jk = at<double>(work, P.jk);
     double* mu = o.center ? at<double>(work, P.mu) : nullptr;
     double* cholx = P.cholx ? at<double>(work, P.cholx) : nullptr;     // l > 128
+    TC* qtmp = P.qtmp ? at<TC>(work, P.qtmp) : nullptr;                   // l > 128
 
     // Batch members run their group's qmax iterations with the ones beyond
     // their own q switched off by the iteration word (status[1]).
@@ -218,19 +233,19 @@ hipError_t solve_steps(Ex& ex, rsvd_handle_t prof, const Plan& P, const TA* A, i
         const uint32_t run_bit = 1u << it, last_bit = 1u << (IT_LAST_SHIFT + it);
         const Gate act = gated ? Gate{itw, run_bit | last_bit} : Gate{};
         RSVD_TRY(orthonormalize<TC>(ex, tile, Y, Lp, m, l, Lp, P.sp.gram_m, partd, gram, rinv, nullptr, status,
-                                    true, act, cholx));
+                                    true, act, cholx, qtmp));
         RSVD_TRY(aty(Z, early, act));
         RSVD_TRY(orthonormalize<TC>(ex, tile, Z, Lp, n, l, Lp, P.sp.gram_n, partd, gram, rinv, nullptr, status,
-                                    true, act, cholx));
+                                    true, act, cholx, qtmp));
         RSVD_TRY(ax_step(Z, it == P.q - 1, run_bit, last_bit));
     }
     // Alg. rqb steps 9-10: Q = qr(Y); B^T = A^T Q.
     RSVD_TRY(orthonormalize<TC>(ex, tile, Y, Lp, m, l, Lp, P.sp.gram_m, partd, gram, rinv, nullptr, status, false,
-                                Gate{}, cholx));
+                                Gate{}, cholx, qtmp));
     RSVD_TRY(aty(Z, late, Gate{}));
     // svd(B): B^T = Q_b R_b (Q_b overwrites Z), R_b = W S J^T by Jacobi.
     RSVD_TRY(orthonormalize<TC>(ex, tile, Z, Lp, n, l, Lp, P.sp.gram_n, partd, gram, rinv, racc, status, false,
-                                Gate{}, cholx));
+                                Gate{}, cholx, qtmp));
     racc += 3 * static_cast<size_t>(l) * l;       // R_b = R3 R2 R1
     {
         JacobiArgs ja;

@@ -52,7 +52,7 @@ DT = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}
 
 @pytest.mark.parametrize("dt", ["f64", "f32", "bf16"])
 @pytest.mark.parametrize("m,K,c", [(300, 257, 5), (129, 64, 30), (1000, 515, 64), (517, 1000, 100),
-                                   (64, 33, 128), (1, 7, 3)])
+                                   (64, 33, 128), (1, 7, 3), (700, 333, 220)])
 def test_gemm_nn_exact_integers(gpu_lib, dt, m, K, c):
     from paper_1608_02148_amd import api
     rng = np.random.default_rng(m * 7 + K + c)
@@ -67,7 +67,7 @@ def test_gemm_nn_exact_integers(gpu_lib, dt, m, K, c):
 
 @pytest.mark.parametrize("dt", ["f64", "f32", "bf16"])
 @pytest.mark.parametrize("m,n,c", [(300, 257, 5), (5000, 129, 30), (20000, 300, 100), (77, 1000, 64),
-                                   (3, 5, 2)])
+                                   (3, 5, 2), (3000, 250, 256)])
 def test_gemm_tn_exact_integers(gpu_lib, dt, m, n, c):
     from paper_1608_02148_amd import api
     rng = np.random.default_rng(m + 3 * n + c)
@@ -150,7 +150,8 @@ def test_small_svd_matches_lapack(gpu_lib, c):
 
 @pytest.mark.parametrize("arith", ["bf16", "split"])
 @pytest.mark.parametrize("dt", ["f32", "bf16"])
-@pytest.mark.parametrize("m,K,c", [(300, 257, 5), (517, 1000, 100), (64, 33, 128), (2000, 640, 30)])
+@pytest.mark.parametrize("m,K,c", [(300, 257, 5), (517, 1000, 100), (64, 33, 128), (2000, 640, 30),
+                                   (700, 520, 200), (260, 300, 256)])
 def test_bf16_products_exact_integers(gpu_lib, arith, dt, m, K, c):
     """Integers of magnitude <= 8 are exact in bf16, so both bf16 modes are exact."""
     from paper_1608_02148_amd import api

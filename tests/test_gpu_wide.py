@@ -126,3 +126,15 @@ def test_widths_above_the_single_solve_limit_are_rejected():
     Ag = torch.zeros(1000, 600, device=DEV)
     with pytest.raises(lib.RsvdError):
         api.rsvd(Ag, 240, p=20)          # l = 260 > 256
+
+
+@pytest.mark.parametrize("dtype,k", [(torch.float32, 120), (torch.float32, 200), (torch.float64, 140)])
+def test_wide_solves_are_deterministic(dtype, k):
+    """Two solves of one matrix agree bitwise (with two column tiles the
+    orthonormalisation's product does not overwrite its own input)."""
+    from paper_1608_02148_amd import api
+    A = syn.planted(6000, 900, syn.spectrum("poly", 900, alpha=1.0), 17)
+    Ag = torch.tensor(A, dtype=dtype, device=DEV)
+    outs = [api.rsvd(Ag, k, p=20, q=1, seed=5) for _ in range(3)]
+    for U, S, V in outs[1:]:
+        assert torch.equal(S, outs[0][1]) and torch.equal(U, outs[0][0]) and torch.equal(V, outs[0][2])
