@@ -228,6 +228,24 @@ def bf16_storage_arm(steps, warmup, m=200000, n=20000, k=200, p=20, q=2, seed=21
         log(f"[bf16_storage] {precision}: {ms:.3f} ms/solve, kernels {prof}")
         del work, res
         torch.cuda.empty_cache()
+    # the mixed mode at the other power-iteration counts of the configuration
+    out["bf16_mixed_by_q"] = {}
+    for qq in (1, 3):
+        prm = api.make_params(p, qq, seed, precision="bf16_mixed")
+        work = api.workspace(api.workspace_size(A, k, prm), dev)
+        res = (torch.empty(m, k, device=dev), torch.empty(k, dtype=torch.float64, device=dev),
+               torch.empty(n, k, device=dev))
+        api.rsvd(A, k, p=p, q=qq, seed=seed, precision="bf16_mixed", work=work, out=res)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            api.rsvd(A, k, p=p, q=qq, seed=seed, precision="bf16_mixed", work=work, out=res)
+        torch.cuda.synchronize()
+        ms_q = (time.perf_counter() - t0) * 1e3 / steps
+        out["bf16_mixed_by_q"][str(qq)] = {"ms_per_step": round(ms_q, 3),
+                                           "tflops": round((2 * qq + 2) * 2.0 * m * n * l / (ms_q / 1e3) / 1e12, 3)}
+        del work, res
+        torch.cuda.empty_cache()
     s_pl, s_bf = svals["plain"], svals["bf16_mixed"]
     out["speedup_mixed_vs_plain"] = round(out["plain"]["ms_per_step"] / out["bf16_mixed"]["ms_per_step"], 3)
     out["max_sigma_diff_mixed_vs_plain_rel_sigma1"] = float(np.max(np.abs(s_pl - s_bf)) / s_pl[0])
