@@ -203,7 +203,6 @@ __device__ __forceinline__ void chol_body(const CholArgs& a) {
     // LDS and one barrier later every thread applies the rank-4 update to its
     // trailing rows.  The inverse runs the same way from the last panel up.
     __shared__ double panel[2][CT_R][LM];   // R rows (factor) / X rows (inverse)
-    __shared__ double pcol[2][CT_R][LM];    // R columns 4P .. 4P+3 (inverse)
     __shared__ double diag0[LM];
     __shared__ double dinv[LM];
     __shared__ uint32_t s_flags;
@@ -355,6 +354,15 @@ __device__ __forceinline__ void chol_body(const CholArgs& a) {
         }
         s_flags = f;
     }
+    // R goes to LDS (dynamic, LM x (LM + 1)): the inverse and the output read
+    // it there, so the factor's registers are free for the inverse's.
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double* Rs = reinterpret_cast<double*>(smem_raw);
+    constexpr int LDR = LM + 1;
+#pragma unroll
+    for (int i = 0; i < CT_R; ++i)
+#pragma unroll
+        for (int q = 0; q < CT_C; ++q) Rs[(a0 + i) * LDR + b0 + q] = (b0 + q >= a0 + i) ? g[i][q] : 0.0;
     __syncthreads();
     // Inverse X = R^{-1} by panels from the bottom: the panel's group solves its
     // 4 rows (X[j] = B[j] / R_jj, B[j'] -= R[j'][j] X[j] inside the panel),
@@ -377,10 +385,7 @@ __device__ __forceinline__ void chol_body(const CholArgs& a) {
                 for (int q = 0; q < CT_C; ++q) x[t][q] *= sj;          // X[j] = B[j] / R_jj
 #pragma unroll
                 for (int t2 = 0; t2 < t; ++t2) {                       // B[j0+t2] -= R[j0+t2][j] X[j]
-                    double rv = 0.0;
-#pragma unroll
-                    for (int q = 0; q < CT_C; ++q) if (b0 + q == j) rv = g[t2][q];
-                    const double rij = from_col(rv, j);
+                    const double rij = Rs[(j0 + t2) * LDR + j];
 #pragma unroll
                     for (int q = 0; q < CT_C; ++q)
                         if (b0 + q >= j) x[t2][q] -= rij * x[t][q];
@@ -391,15 +396,6 @@ __device__ __forceinline__ void chol_body(const CholArgs& a) {
 #pragma unroll
                 for (int q = 0; q < CT_C; ++q) panel[buf][t][b0 + q] = x[t][q];
         }
-        if (tx == j0 / CT_C) {                                         // R[i][j0 .. j0+3], all rows i
-#pragma unroll
-            for (int t = 0; t < CT_R; ++t)
-#pragma unroll
-                for (int q = 0; q < CT_C; ++q)
-                    if (b0 + q == j0 + t)
-#pragma unroll
-                        for (int i = 0; i < CT_R; ++i) pcol[buf][t][a0 + i] = g[i][q];
-        }
         __syncthreads();
         if (ty < P) {
 #pragma unroll
@@ -409,7 +405,7 @@ __device__ __forceinline__ void chol_body(const CholArgs& a) {
                 for (int q = 0; q < CT_C; ++q) xr[q] = panel[buf][t][b0 + q];
 #pragma unroll
                 for (int i = 0; i < CT_R; ++i) {
-                    const double rij = pcol[buf][t][a0 + i];
+                    const double rij = Rs[(a0 + i) * LDR + j0 + t];
 #pragma unroll
                     for (int q = 0; q < CT_C; ++q)
                         if (b0 + q >= j0) x[i][q] -= rij * xr[q];
@@ -426,7 +422,7 @@ __device__ __forceinline__ void chol_body(const CholArgs& a) {
             const int c = b0 + q;
             if (r < a.ldr && c < a.ldr)
                 rinv[r * a.ldr + c] = static_cast<TC>((r < l && c < l && c >= r) ? x[i][q] : 0.0);
-            if (a.rout && r < l && c < l) a.rout[r * l + c] = (c >= r) ? g[i][q] : 0.0;
+            if (a.rout && r < l && c < l) a.rout[r * l + c] = Rs[r * LDR + c];
         }
     }
     if (tid == 0) *a.status = s_flags;
@@ -437,7 +433,7 @@ struct CholBody {
     typedef CholArgs Args;
     static constexpr int THREADS = chol_threads<LM>();
     static int blocks(const Args&) { return 1; }
-    static size_t lds(const Args&) { return 0; }
+    static size_t lds(const Args&) { return static_cast<size_t>(LM) * (LM + 1) * sizeof(double); }
     static __device__ void run(const Args& a, int) { chol_body<TC, LM>(a); }
 };
 
