@@ -140,9 +140,14 @@ struct OmegaBody {
 // Register tiles: thread (tx, ty) holds rows 4ty..4ty+3 and columns
 // 8tx..8tx+7 of the matrix.  Factorisation step j: the owners of row j publish
 // it in LDS, one barrier, then every thread applies the rank-1 update
-// g_a g_b / d_j to its own entries with a > j, b >= a; the owners turn row j
-// into row j of R.  The inverse is a column sweep over [R | I] with the same
-// tiles: step j publishes row j of the accumulator and column j of R.
+// g_a g_b / d_j to its own entries with a > j; the owners turn row j into row
+// j of R.  The inverse is a column sweep over [R | I] with the same tiles:
+// step j publishes row j of the accumulator and column j of R.
+// Updates run over whole tiles, without triangle masks: row j of R is zero
+// left of its diagonal and the rows of X = R^{-1} are zero left of theirs, so
+// the entries above the diagonal only ever receive upper-triangle products;
+// what the unmasked updates leave below the diagonal is never read (R and
+// R^{-1} are written out with their lower parts zeroed).
 //
 // Pass policy (CholeskyQR2 with shifted CholeskyQR3 fallback):
 //   pass 1: if a pivot fails (d_j <= 100 u G_jj, d_j not finite), restart on
@@ -294,8 +299,7 @@ __device__ __forceinline__ void chol_body(const CholArgs& a) {
                             const double f = from_col(rjr, r);   // R[j][r]
                             if (!dead && r < l) {
 #pragma unroll
-                                for (int q = 0; q < CT_C; ++q)
-                                    if (b0 + q >= r) g[t2][q] -= f * g[t][q];
+                                for (int q = 0; q < CT_C; ++q) g[t2][q] -= f * g[t][q];
                             }
                         }
                     }
@@ -321,8 +325,7 @@ __device__ __forceinline__ void chol_body(const CholArgs& a) {
                         for (int i = 0; i < CT_R; ++i) {
                             const double pr = panel[buf][t][a0 + i];
 #pragma unroll
-                            for (int q = 0; q < CT_C; ++q)
-                                if (b0 + q >= a0 + i) g[i][q] -= pr * pc[q];
+                            for (int q = 0; q < CT_C; ++q) g[i][q] -= pr * pc[q];
                         }
                     }
                 }
@@ -387,8 +390,7 @@ __device__ __forceinline__ void chol_body(const CholArgs& a) {
                 for (int t2 = 0; t2 < t; ++t2) {                       // B[j0+t2] -= R[j0+t2][j] X[j]
                     const double rij = Rs[(j0 + t2) * LDR + j];
 #pragma unroll
-                    for (int q = 0; q < CT_C; ++q)
-                        if (b0 + q >= j) x[t2][q] -= rij * x[t][q];
+                    for (int q = 0; q < CT_C; ++q) x[t2][q] -= rij * x[t][q];
                 }
             }
 #pragma unroll
@@ -407,8 +409,7 @@ __device__ __forceinline__ void chol_body(const CholArgs& a) {
                 for (int i = 0; i < CT_R; ++i) {
                     const double rij = Rs[(a0 + i) * LDR + j0 + t];
 #pragma unroll
-                    for (int q = 0; q < CT_C; ++q)
-                        if (b0 + q >= j0) x[i][q] -= rij * xr[q];
+                    for (int q = 0; q < CT_C; ++q) x[i][q] -= rij * xr[q];
                 }
             }
         }
@@ -444,9 +445,9 @@ inline int small_lm(int l) { return l <= 32 ? 32 : (l <= 64 ? 64 : (l <= CHOL_MA
 // ------------------------------------------------------ one-sided Jacobi SVD
 // R (l x l upper triangular, f64, ld ldr) = W diag(sigma) J^T.  The columns of
 // W (column-major, column c at W + c*ldw) live in LDS; l/2 disjoint column pairs
-// are rotated per round (round-robin order), one 16-lane group per pair with
+// are rotated per round (round-robin order), one 8-lane group per pair with
 // the two columns held in registers during the rotation.  A
-// pair is rotated when |w_a . w_b| > tol sqrt(|w_a|^2 |w_b|^2).  J is not
+// pair is rotated when (w_a . w_b)^2 > tol^2 |w_a|^2 |w_b|^2.  J is not
 // accumulated: since R^T W = J diag(sigma), the needed columns are recovered
 // as J_i = R^T w_i / sigma_i, whose error relative to 1 is about
 // u sigma_1 / sigma_i -- small for the k leading columns that are kept.
@@ -495,94 +496,229 @@ __device__ __forceinline__ double group_sum(double v) {
     v += dpp_f64<0x140>(v);   // row_mirror
     return v;
 }
+// The same over the 8 lanes of a half row (quad exchanges, half-row mirror).
+__device__ __forceinline__ double half_group_sum(double v) {
+    v += dpp_f64<0xB1>(v);
+    v += dpp_f64<0x4E>(v);
+    v += dpp_f64<0x141>(v);
+    return v;
+}
+template <int G>
+__device__ __forceinline__ double lane_group_sum(double v) {
+    static_assert(G == 8 || G == 16, "8- or 16-lane groups");
+    return G == 8 ? half_group_sum(v) : group_sum(v);
+}
 
-template <typename TC, int LM>
-__device__ __forceinline__ void jacobi_body(const JacobiArgs& a) {
-    constexpr int JAC_PER_LANE = LM / JAC_GROUP;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ int s_rotated;
-    __shared__ int s_perm[LM];
-    __shared__ double s_sig[LM];
-    const int l = a.l, tid = threadIdx.x, nt = blockDim.x;
-    const int ldw = jacobi_ldw(l);
-    // column c at W + c * ldw: in LDS, or for l > 128 in global memory (it
-    // stays in L2; the barriers order its reads and writes within the group)
-    double* W = (LM > CHOL_MAX_L) ? a.wglob : reinterpret_cast<double*>(smem_raw);
-    const bool finish_only = a.rot != nullptr;
-    if (!finish_only)
-        for (int idx = tid; idx < l * l; idx += nt) {
-            const int c = idx / l, r = idx - c * l;
-            W[c * ldw + r] = a.R[r * a.ldr + c];
+// 1/sqrt(x) for x in [1/4, 8]: the hardware estimate, then two Newton steps
+// y <- y (3/2 - x y^2 / 2), each squaring the relative error, so the result
+// is within a few ulp of the f64 value.
+__device__ __forceinline__ double rsqrt_f64(double x) {
+    const double hx = 0.5 * x;
+    double y = __builtin_amdgcn_rsq(x);
+    y = y * fma(-hx * y, y, 1.5);
+    y = y * fma(-hx * y, y, 1.5);
+    return y;
+}
+
+// Rotation [c -s; s c] that makes two columns with |a|^2 = al, |b|^2 = be,
+// a . b = ga (ga != 0) orthogonal, by the smaller of the two angles:
+// tan(theta) = sgn(d) h / (|d| + r), d = be - al, h = 2 ga, r = sqrt(d^2 + h^2).
+// With D = |d| + r, c = D / sqrt(D^2 + h^2) and s = sgn(d) h / sqrt(D^2 + h^2),
+// so c^2 + s^2 = 1 to rounding whatever the accuracy of r (r only sets the
+// angle).  d and h are first scaled by a power of two to max(|d|, |h|) in
+// [1/2, 1), so that no square overflows or underflows.
+__device__ __forceinline__ void jacobi_cs(double al, double be, double ga, double& c, double& s) {
+    const double d = be - al, h = 2.0 * ga;
+    int e;
+    (void)frexp(fmax(fabs(d), fabs(h)), &e);
+    const double ds = ldexp(d, -e), hs = ldexp(h, -e);
+    const double q = fma(ds, ds, hs * hs);            // [1/4, 2)
+    const double r = q * rsqrt_f64(q);
+    const double D = fabs(ds) + r;                     // [1/2, 1 + sqrt 2)
+    const double inv = rsqrt_f64(fma(D, D, hs * hs));  // argument in [1/4, 7]
+    c = D * inv;
+    s = (d < 0.0 ? -hs : hs) * inv;
+}
+
+// Block-cyclic ordering (l <= 128): the columns form blocks of 4, and the
+// blocks are paired round-robin; per round a 16-lane group takes one block
+// pair (8 columns) into registers, rotates all 16 cross pairs in 4 sub-rounds
+// of 4 disjoint pairs -- in a sweep's first round also the 6 pairs inside
+// each of its two blocks -- and writes the 8 columns back.  A sweep still
+// visits every pair once; per rotation it moves a quarter of the LDS data of
+// a pair-at-a-time ordering and takes a quarter of the barriers.
+constexpr int JBS = 4;                 // columns per block
+constexpr int JAC_LANES = 16;          // lanes per block pair (one DPP row)
+
+template <int LM> constexpr int jacobi_threads() {
+    return LM > CHOL_MAX_L ? 1024 : JAC_LANES * (LM / (2 * JBS));
+}
+// W in LDS for l <= LM: 4 * (blocks rounded up to even) columns of LM + 1
+// doubles (rows l..LM-1 and the padding columns are zero).
+__host__ __device__ inline int jacobi_blocks(int l) {
+    const int nb = (l + JBS - 1) / JBS;
+    return nb + (nb & 1);
+}
+template <int LM> inline size_t jacobi_block_lds_bytes(int l) {
+    return static_cast<size_t>(JBS) * jacobi_blocks(l) * (LM + 1) * sizeof(double);
+}
+
+// One sub-round: rotations of the 4 disjoint register columns (I_k, J_k).
+// Returns whether any pair was rotated.  Pairs below the threshold get the
+// identity (c, s) = (1, 0), so the update is branch-free across the group.
+template <int VPL, int I0, int J0, int I1, int J1, int I2, int J2, int I3, int J3>
+__device__ __forceinline__ bool jacobi_sub_round(double (&x)[2 * JBS][VPL], double (&nrm)[2 * JBS], double tol2) {
+    constexpr int I[4] = {I0, I1, I2, I3};
+    constexpr int J[4] = {J0, J1, J2, J3};
+    double ga[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < VPL; ++q) acc = fma(x[I[k]][q], x[J[k]][q], acc);
+        ga[k] = acc;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) ga[k] = group_sum(ga[k]);
+    bool rot[4], any = false;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        rot[k] = ga[k] != 0.0 && ga[k] * ga[k] > tol2 * (nrm[I[k]] * nrm[J[k]]);
+        any = any || rot[k];
+    }
+    if (!any) return false;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double al = nrm[I[k]], be = nrm[J[k]], g = rot[k] ? ga[k] : 0.0;
+        double c, s;
+        jacobi_cs(al, be, rot[k] ? ga[k] : 1.0, c, s);
+        if (!rot[k]) { c = 1.0; s = 0.0; }
+        const double x2 = 2.0 * c * s * g, cc = c * c, ss = s * s;   // |c a - s b|^2, |s a + c b|^2
+        nrm[I[k]] = fmax(fma(cc, al, fma(ss, be, -x2)), 0.0);
+        nrm[J[k]] = fmax(fma(ss, al, fma(cc, be, x2)), 0.0);
+#pragma unroll
+        for (int q = 0; q < VPL; ++q) {
+            const double xa = x[I[k]][q], xb = x[J[k]][q];
+            x[I[k]][q] = fma(c, xa, -s * xb);
+            x[J[k]][q] = fma(s, xa, c * xb);
         }
-    __syncthreads();
+    }
+    return true;
+}
 
-    const int lp = l + (l & 1);
-    const int npairs = lp / 2;
-    const int group = tid / JAC_GROUP, gl = tid % JAC_GROUP;
-    const int ngroups = nt / JAC_GROUP;
-    // Squared column norms: recomputed at the start of every sweep and
-    // updated through each rotation (|w_a'|^2 = alpha - t gamma,
-    // |w_b'|^2 = beta + t gamma), so a pair needs one inner product, not three.
-    __shared__ double s_norm[LM];
+// Sweeps of the block-cyclic ordering over W (LDS, column c at W + c * ldw,
+// ldw = LM + 1); returns the number of sweeps run.  Every thread of the
+// workgroup calls it (the barriers are workgroup-wide).
+template <int LM>
+__device__ int jacobi_block_sweeps(double* W, int l, double tol2, int max_sweeps, int* s_rotated) {
+    constexpr int VPL = LM / JAC_LANES;
+    constexpr int ldw = LM + 1;
+    const int tid = threadIdx.x, group = tid / JAC_LANES, gl = tid % JAC_LANES;
+    const int nbp = jacobi_blocks(l), npairs = nbp / 2;
     int sweep = 0;
-    for (; !finish_only && sweep < a.max_sweeps; ++sweep) {
-        if (tid == 0) s_rotated = 0;
-        for (int c = group; c < l; c += ngroups) {
-            const double* wc = W + c * ldw;
-            double ss = 0.0;
-#pragma unroll
-            for (int q = 0; q < JAC_PER_LANE; ++q) {
-                const int r = gl + JAC_GROUP * q;
-                if (r < l) ss += wc[r] * wc[r];
-            }
-            ss = group_sum(ss);
-            if (gl == 0) s_norm[c] = ss;
-        }
+    for (; sweep < max_sweeps; ++sweep) {
+        if (tid == 0) *s_rotated = 0;
         __syncthreads();
-        for (int round = 0; round < lp - 1; ++round) {
-            for (int p = group; p < npairs; p += ngroups) {
-                int ca, cb;
-                if (p == 0) { ca = round; cb = lp - 1; }
-                else { ca = (round + p) % (lp - 1); cb = (round - p + lp - 1) % (lp - 1); }
-                if (ca >= l || cb >= l) continue;
-                double* wa = W + ca * ldw;
-                double* wb = W + cb * ldw;
-                double xa[JAC_PER_LANE], xb[JAC_PER_LANE];
+        bool rotated = false;
+        for (int round = 0; round < nbp - 1; ++round) {
+            if (group < npairs) {
+                int ba, bb;
+                if (group == 0) { ba = round; bb = nbp - 1; }
+                else { ba = (round + group) % (nbp - 1); bb = (round - group + nbp - 1) % (nbp - 1); }
+                double x[2 * JBS][VPL], nrm[2 * JBS];
 #pragma unroll
-                for (int q = 0; q < JAC_PER_LANE; ++q) {
-                    const int r = gl + JAC_GROUP * q;
-                    xa[q] = (r < l) ? wa[r] : 0.0;
-                    xb[q] = (r < l) ? wb[r] : 0.0;
+                for (int i = 0; i < 2 * JBS; ++i) {
+                    const double* wc = W + ((i < JBS ? ba : bb) * JBS + (i % JBS)) * ldw;
+                    double ss = 0.0;
+#pragma unroll
+                    for (int q = 0; q < VPL; ++q) {
+                        x[i][q] = wc[gl + JAC_LANES * q];
+                        ss = fma(x[i][q], x[i][q], ss);
+                    }
+                    nrm[i] = ss;
                 }
-                const double al = s_norm[ca], be = s_norm[cb];
-                double ga = 0.0;
 #pragma unroll
-                for (int q = 0; q < JAC_PER_LANE; ++q) ga += xa[q] * xb[q];
-                ga = group_sum(ga);
-                if (ga != 0.0 && fabs(ga) > a.tol * sqrt(al * be)) {
-                    const double zeta = (be - al) / (2.0 * ga);
-                    const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                    const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-                    if (gl == 0) {
-                        s_norm[ca] = fmax(al - t * ga, 0.0);
-                        s_norm[cb] = be + t * ga;
-                    }
+                for (int i = 0; i < 2 * JBS; ++i) nrm[i] = group_sum(nrm[i]);
+                bool changed = false;
+                if (round == 0) {   // pairs inside each block, once per sweep
+                    changed |= jacobi_sub_round<VPL, 0, 1, 2, 3, 4, 5, 6, 7>(x, nrm, tol2);
+                    changed |= jacobi_sub_round<VPL, 0, 2, 1, 3, 4, 6, 5, 7>(x, nrm, tol2);
+                    changed |= jacobi_sub_round<VPL, 0, 3, 1, 2, 4, 7, 5, 6>(x, nrm, tol2);
+                }
+                changed |= jacobi_sub_round<VPL, 0, 4, 1, 5, 2, 6, 3, 7>(x, nrm, tol2);
+                changed |= jacobi_sub_round<VPL, 0, 5, 1, 6, 2, 7, 3, 4>(x, nrm, tol2);
+                changed |= jacobi_sub_round<VPL, 0, 6, 1, 7, 2, 4, 3, 5>(x, nrm, tol2);
+                changed |= jacobi_sub_round<VPL, 0, 7, 1, 4, 2, 5, 3, 6>(x, nrm, tol2);
+                if (changed) {
 #pragma unroll
-                    for (int q = 0; q < JAC_PER_LANE; ++q) {
-                        const int r = gl + JAC_GROUP * q;
-                        if (r < l) {
-                            wa[r] = c * xa[q] - s * xb[q];
-                            wb[r] = s * xa[q] + c * xb[q];
-                        }
+                    for (int i = 0; i < 2 * JBS; ++i) {
+                        double* wc = W + ((i < JBS ? ba : bb) * JBS + (i % JBS)) * ldw;
+#pragma unroll
+                        for (int q = 0; q < VPL; ++q) wc[gl + JAC_LANES * q] = x[i][q];
                     }
-                    if (gl == 0) s_rotated = 1;
+                    rotated = true;
                 }
             }
             __syncthreads();
         }
-        if (!s_rotated) break;
+        if (rotated && gl == 0) *s_rotated = 1;
         __syncthreads();
+        const bool again = *s_rotated != 0;
+        __syncthreads();
+        if (!again) break;
     }
+    return sweep;
+}
+
+template <typename TC, int LM>
+__device__ __forceinline__ void jacobi_body(const JacobiArgs& a) {
+    constexpr int JG = JAC_LANES;
+    constexpr bool BLOCKED = LM <= CHOL_MAX_L;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ int s_rotated;
+    __shared__ int s_perm[LM];
+    __shared__ double s_sig[LM];
+    __shared__ unsigned long long s_amax;
+    const int l = a.l, tid = threadIdx.x, nt = blockDim.x;
+    // column c at W + c * ldw: in LDS (block layout, l <= 128), or for l > 128
+    // in global memory, where the block sweeps left it
+    const int ldw = BLOCKED ? LM + 1 : jacobi_ldw(l);
+    double* W = BLOCKED ? reinterpret_cast<double*>(smem_raw) : a.wglob;
+    const bool finish_only = a.rot != nullptr;
+    // W = 2^-e R with 2^(e-1) <= max |R_ij| < 2^e (exact), so squared norms and
+    // their products stay far from overflow and underflow; sigma is scaled
+    // back by 2^e at the end.
+    int scale_e = 0;
+    int sweep = 0;
+    if (!finish_only) {
+        if (tid == 0) s_amax = 0ull;
+        __syncthreads();
+        double amax = 0.0;
+        for (int idx = tid; idx < l * l; idx += nt) {
+            const int c = idx / l, r = idx - c * l;
+            amax = fmax(amax, fabs(a.R[r * a.ldr + c]));
+        }
+        // non-negative doubles order like their bit patterns
+        atomicMax(&s_amax, static_cast<unsigned long long>(__double_as_longlong(amax)));
+        __syncthreads();
+        const double mx = __longlong_as_double(static_cast<long long>(s_amax));
+        if (mx > 0.0 && isfinite(mx)) (void)frexp(mx, &scale_e);
+        const int ncols = BLOCKED ? JBS * jacobi_blocks(l) : l;
+        const int nrows = BLOCKED ? LM : l;
+        for (int idx = tid; idx < ncols * nrows; idx += nt) {
+            const int c = idx / nrows, r = idx - c * nrows;
+            W[c * ldw + r] = (r < l && c < l) ? ldexp(a.R[r * a.ldr + c], -scale_e) : 0.0;
+        }
+        __syncthreads();
+        if constexpr (BLOCKED) {
+            sweep = jacobi_block_sweeps<LM>(W, l, a.tol * a.tol, a.max_sweeps, &s_rotated);
+        } else {
+            sweep = a.max_sweeps;    // l > 128 is swept by JacobiBlockBody
+        }
+    }
+    __syncthreads();
+    const int group = tid / JG, gl = tid % JG;
+    const int ngroups = nt / JG;
     if (tid == 0) {   // record the sweep count (bits 24..31) and the limit flag
         int limit = a.max_sweeps;
         if (finish_only) {
@@ -598,12 +734,12 @@ __device__ __forceinline__ void jacobi_body(const JacobiArgs& a) {
     for (int c = group; c < l; c += ngroups) {
         double* wc = W + c * ldw;
         double ss = 0.0;
-        for (int r = gl; r < l; r += JAC_GROUP) ss += wc[r] * wc[r];
-        ss = group_sum(ss);
+        for (int r = gl; r < l; r += JG) ss += wc[r] * wc[r];
+        ss = lane_group_sum<JG>(ss);
         const double sg = sqrt(ss);
         const double inv = (sg > 0.0) ? 1.0 / sg : 0.0;
-        for (int r = gl; r < l; r += JAC_GROUP) wc[r] *= inv;
-        if (gl == 0) s_sig[c] = sg;
+        for (int r = gl; r < l; r += JG) wc[r] *= inv;
+        if (gl == 0) s_sig[c] = ldexp(sg, scale_e);
     }
     __syncthreads();
     if (tid < l) {
@@ -634,14 +770,14 @@ __device__ __forceinline__ void jacobi_body(const JacobiArgs& a) {
     }
 }
 
-// Instance for l <= LM: one 16-lane group per column pair of a round (LM / 2
-// groups).
+// Instance for l <= LM: one 16-lane group per block pair of a round (LM / 8
+// groups); 1024 threads for the finishing pass of l = 256.
 template <typename TC, int LM = CHOL_MAX_L>
 struct JacobiBody {
     typedef JacobiArgs Args;
-    static constexpr int THREADS = JAC_GROUP * (LM / 2) > 1024 ? 1024 : JAC_GROUP * (LM / 2);
+    static constexpr int THREADS = jacobi_threads<LM>();
     static int blocks(const Args&) { return 1; }
-    static size_t lds(const Args& a) { return LM > CHOL_MAX_L ? 0 : jacobi_lds_bytes(a.l); }
+    static size_t lds(const Args& a) { return LM > CHOL_MAX_L ? 0 : jacobi_block_lds_bytes<LM>(a.l); }
     static __device__ void run(const Args& a, int) { jacobi_body<TC, LM>(a); }
 };
 
@@ -849,7 +985,8 @@ hipError_t run_jacobi(Ex& ex, const JacobiArgs& a) {
         case 32: return ex.template run<JacobiBody<TC, 32>>(a);
         case 64: return ex.template run<JacobiBody<TC, 64>>(a);
         case CHOL_MAX_L: return ex.template run<JacobiBody<TC, CHOL_MAX_L>>(a);
-        default: return a.wglob ? ex.template run<JacobiBody<TC, 2 * CHOL_MAX_L>>(a) : hipErrorInvalidValue;
+        // l > 128: only the finishing pass after the block sweeps (JacobiBlockBody)
+        default: return (a.wglob && a.rot) ? ex.template run<JacobiBody<TC, 2 * CHOL_MAX_L>>(a) : hipErrorInvalidValue;
     }
 }
 

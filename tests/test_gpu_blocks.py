@@ -128,7 +128,13 @@ def test_orthonormalize_rank_deficient_uses_shift(gpu_lib):
 @pytest.mark.parametrize("c", [1, 2, 7, 30, 64, 89, 100, 128])
 def test_small_svd_matches_lapack(gpu_lib, c):
     """W orthonormal and s to LAPACK accuracy; J_i = R^T w_i / s_i is accurate
-    to about u s_1 / s_i, so J is checked column by column on that scale."""
+    to about u s_1 / s_i, so J is checked column by column on that scale.
+
+    Random triangular R are exponentially ill-conditioned, and some of these
+    have singular values below the rounding level c u s_1.  There no SVD
+    method has relative accuracy (its backward error is u |R|), so s_i only
+    has to lie within the absolute bound, and J_i, which divides by s_i, is
+    checked only for s_i above that level."""
     from paper_1608_02148_amd import api
     rng = np.random.default_rng(c)
     R = np.triu(rng.standard_normal((c, c)))
@@ -139,7 +145,10 @@ def test_small_svd_matches_lapack(gpu_lib, c):
     np.testing.assert_allclose(s, se, rtol=1e-12, atol=1e-14 * se[0])
     np.testing.assert_allclose(W.T @ W, np.eye(c), atol=1e-12)
     assert int(_np(flags)[0]) & 8 == 0
+    floor = 10 * c * 2.0 ** -53 * se[0]
     for i in range(c):
+        if se[i] <= floor:
+            continue
         tol = 1e-13 * se[0] / se[i] * c
         sep = min([abs(se[i] - se[j]) for j in range(c) if j != i] + [se[0]]) / se[0]
         np.testing.assert_allclose(R @ J[:, i], W[:, i] * s[i], atol=tol * se[0])
