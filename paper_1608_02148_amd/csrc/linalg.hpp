@@ -48,6 +48,10 @@ struct StampBody {
 
 // ---------------------------------------------------------------- reduction
 // out[r][c] = sum_s part[s][r][c] for r < rows, c < ncols (split order fixed).
+// Few outputs over many splits (Gram partials: l^2 values, up to one split per
+// CU) take the sliced form: a workgroup sums 64 outputs, its 4 waves each a
+// quarter of the splits (s = w, w + 4, ...), and the 4 partial sums are added
+// in a fixed order; otherwise one thread sums one output over all splits.
 template <typename T>
 struct ReduceBody {
     struct Args {
@@ -56,11 +60,33 @@ struct ReduceBody {
         Gate gate;
     };
     static constexpr int THREADS = 256;
-    static int blocks(const Args& a) { return static_cast<int>(cdiv(a.rows * a.ncols, THREADS)); }
+    static constexpr int SLICES = 4, PER_BLOCK = THREADS / SLICES;
+    static bool sliced(const Args& a) { return a.S >= 8 && a.rows * a.ncols <= 65536; }
+    static int blocks(const Args& a) {
+        return static_cast<int>(cdiv(a.rows * a.ncols, sliced(a) ? PER_BLOCK : THREADS));
+    }
     static size_t lds(const Args&) { return 0; }
     static __device__ void run(const Args& a, int b) {
         if (a.skip_flag && ((*a.skip_flag & a.skip_mask) == 0u)) return;
         if (a.gate.w && ((*a.gate.w & a.gate.mask) == 0u)) return;
+        if (a.S >= 8 && a.rows * a.ncols <= 65536) {       // sliced (uniform per launch)
+            __shared__ T red[SLICES][PER_BLOCK];
+            const int e = threadIdx.x % PER_BLOCK, sl = threadIdx.x / PER_BLOCK;
+            const int64_t idx = static_cast<int64_t>(b) * PER_BLOCK + e;
+            const bool ok = idx < a.rows * a.ncols;
+            const int64_t r = ok ? idx / a.ncols : 0;
+            const int c = static_cast<int>(idx - r * a.ncols);
+            T acc = T(0);
+            if (ok) {
+                const T* src = a.part + r * a.ldp + c;
+#pragma unroll 8
+                for (int k = sl; k < a.S; k += SLICES) acc += src[k * a.part_stride];
+            }
+            red[sl][e] = acc;
+            __syncthreads();
+            if (sl == 0 && ok) a.out[r * a.ldo + c] = (red[0][e] + red[1][e]) + (red[2][e] + red[3][e]);
+            return;
+        }
         const int64_t idx = static_cast<int64_t>(b) * THREADS + threadIdx.x;
         const int64_t r = idx / a.ncols;
         const int c = static_cast<int>(idx - r * a.ncols);
@@ -138,12 +164,11 @@ struct OmegaBody {
 // l x l) in precision TC and optionally R (f64, ld l).
 //
 // Register tiles: thread (tx, ty) holds rows 4ty..4ty+3 and columns
-// 8tx..8tx+7 of the matrix.  Factorisation step j: the owners of row j publish
-// it in LDS, one barrier, then every thread applies the rank-1 update
-// g_a g_b / d_j to its own entries with a > j; the owners turn row j into row
-// j of R.  The inverse is a column sweep over [R | I] with the same tiles:
-// step j publishes row j of the accumulator and column j of R.
-// Updates run over whole tiles, without triangle masks: row j of R is zero
+// 8tx..8tx+7 of the matrix.  Factorisation by panels of 4 rows: the owners of
+// panel P turn its rows into rows of R (from the 4 x 4 diagonal block's factor
+// and inverse), publish them in LDS, and one barrier later every thread below
+// applies the rank-4 update.  The inverse X = R^{-1} runs over the same panels
+// from the bottom.  Updates run over whole tiles, without triangle masks: row j of R is zero
 // left of its diagonal and the rows of X = R^{-1} are zero left of theirs, so
 // the entries above the diagonal only ever receive upper-triangle products;
 // what the unmasked updates leave below the diagonal is never read (R and
@@ -203,13 +228,13 @@ __device__ __forceinline__ void chol_body(const CholArgs& a) {
         return;
     }
     // Panels of CT_R = 4 rows: the 16 threads of row group ty = P own rows
-    // 4P .. 4P+3 in registers and factor them alone (their lanes lie in one
-    // wave; values move by lane shuffles), then publish the panel's R rows in
-    // LDS and one barrier later every thread applies the rank-4 update to its
+    // 4P .. 4P+3 in registers and turn them into rows of R alone (their lanes
+    // lie in one wave; values move by lane shuffles), then publish them in LDS
+    // and one barrier later every thread applies the rank-4 update to its
     // trailing rows.  The inverse runs the same way from the last panel up.
     __shared__ double panel[2][CT_R][LM];   // R rows (factor) / X rows (inverse)
     __shared__ double diag0[LM];
-    __shared__ double dinv[LM];
+    __shared__ double xdiag[LM / CT_R][CT_R][CT_R];   // X_PP = R_PP^{-1} of each panel
     __shared__ uint32_t s_flags;
     __shared__ double s_trace;
     __shared__ int s_fail, s_dead;
@@ -237,8 +262,8 @@ __device__ __forceinline__ void chol_body(const CholArgs& a) {
             }
         __syncthreads();
     };
-    // value v of the lane holding column c in this row group (16-lane segment)
-    auto from_col = [&](double v, int c) { return __shfl(v, c / CT_C, CT_TX); };
+    // value v of lane src of this row group (16-lane segment)
+    auto from_lane = [&](double v, int src) { return __shfl(v, src, CT_TX); };
 
     load(0.0);
     if (tid == 0) {
@@ -264,49 +289,100 @@ __device__ __forceinline__ void chol_body(const CholArgs& a) {
             for (int P = 0; P < npanel; ++P) {
                 const int j0 = CT_R * P, buf = P & 1;
                 if (ty == P) {
+                    // The panel's 4 x 4 diagonal block lies in one lane (columns
+                    // j0..j0+3: lane j0 / 8, offset j0 % 8).  Its upper half is
+                    // broadcast to the group; every lane factors it (R_PP, pivot
+                    // rules above), inverts it (X_PP = R_PP^{-1}, zero row and
+                    // column for a dead pivot) and forms its own columns of the
+                    // panel rows as R_P = X_PP^T G_P: no step-by-step chain.
+                    const int dl = j0 / CT_C;
+                    const bool hi = (j0 % CT_C) != 0;
+                    double Gd[CT_R][CT_R], Rd[CT_R][CT_R], Xd[CT_R][CT_R], dv[CT_R] = {};
+                    // (two static copies: a select between g[t][v] and
+                    // g[t][4 + v] would become an indexed load from memory)
+                    if (hi) {
+#pragma unroll
+                        for (int t = 0; t < CT_R; ++t)
+#pragma unroll
+                            for (int v = 0; v < CT_R; ++v) Gd[t][v] = (v >= t) ? from_lane(g[t][CT_R + v], dl) : 0.0;
+                    } else {
+#pragma unroll
+                        for (int t = 0; t < CT_R; ++t)
+#pragma unroll
+                            for (int v = 0; v < CT_R; ++v) Gd[t][v] = (v >= t) ? from_lane(g[t][v], dl) : 0.0;
+                    }
+#pragma unroll
+                    for (int t = 0; t < CT_R; ++t)
+#pragma unroll
+                        for (int v = 0; v < CT_R; ++v) {
+                            Rd[t][v] = 0.0;
+                            Xd[t][v] = 0.0;
+                        }
                     bool fail = false, dead_any = false;
                     double min_ratio = 1.0;
 #pragma unroll
                     for (int t = 0; t < CT_R; ++t) {
+                        // rows past l stay zero; after a failed pivot the
+                        // attempt is restarted, so the rest is not needed
                         const int j = j0 + t;
-                        if (j >= l || fail) break;
-                        double piv = 0.0;
+                        const bool live = (j < l) && !fail;
+                        double d = Gd[t][t];
 #pragma unroll
-                        for (int q = 0; q < CT_C; ++q) if (b0 + q == j) piv = g[t][q];
-                        const double d = from_col(piv, j);
-                        const double d0 = diag0[j];
-                        if (a.pass == 1 && attempt == 0 && (!(d > 100.0 * u * d0) || !isfinite(d))) {
-                            fail = true;                      // uniform over the group
-                            break;
-                        }
+                        for (int i = 0; i < t; ++i) d -= Rd[i][t] * Rd[i][t];
+                        const double d0 = live ? diag0[j] : 1.0;
+                        const bool bad = live && a.pass == 1 && attempt == 0 && (!(d > 100.0 * u * d0) || !isfinite(d));
+                        fail = fail || bad;
                         const bool dead = !(d > 1e-30 * d0) || !isfinite(d) || d0 == 0.0;
-                        const double sq = dead ? 0.0 : sqrt(d);
-                        const double inv_sq = dead ? 0.0 : 1.0 / sq;
-                        if (dead) dead_any = true;
-                        else min_ratio = fmin(min_ratio, d / d0);
-                        if (tx == 0) dinv[j] = inv_sq;
-#pragma unroll
-                        for (int q = 0; q < CT_C; ++q) {         // row j of R
-                            const int c = b0 + q;
-                            g[t][q] = (c > j) ? g[t][q] * inv_sq : (c == j ? sq : 0.0);
+                        const bool use = live && !bad && !dead;
+                        const double sq = use ? sqrt(d) : 0.0;
+                        const double inv_sq = use ? 1.0 / sq : 0.0;
+                        if (live && !bad) {
+                            if (dead) dead_any = true;
+                            else min_ratio = fmin(min_ratio, d / d0);
                         }
+                        Rd[t][t] = sq;
+                        dv[t] = inv_sq;
 #pragma unroll
-                        for (int t2 = t + 1; t2 < CT_R; ++t2) {  // remaining panel rows
-                            const int r = j0 + t2;
-                            double rjr = 0.0;
+                        for (int v = t + 1; v < CT_R; ++v) {
+                            double w = Gd[t][v];
 #pragma unroll
-                            for (int q = 0; q < CT_C; ++q) if (b0 + q == r) rjr = g[t][q];
-                            const double f = from_col(rjr, r);   // R[j][r]
-                            if (!dead && r < l) {
+                            for (int i = 0; i < t; ++i) w -= Rd[i][t] * Rd[i][v];
+                            Rd[t][v] = w * inv_sq;
+                        }
+                    }
 #pragma unroll
-                                for (int q = 0; q < CT_C; ++q) g[t2][q] -= f * g[t][q];
-                            }
+                    for (int v = 0; v < CT_R; ++v) {          // R_PP X = I, column by column
+                        Xd[v][v] = dv[v];
+#pragma unroll
+                        for (int t = v - 1; t >= 0; --t) {
+                            double w = 0.0;
+#pragma unroll
+                            for (int i = t + 1; i <= v; ++i) w += Rd[t][i] * Xd[i][v];
+                            Xd[t][v] = -dv[t] * w;
+                        }
+                    }
+#pragma unroll
+                    for (int q = 0; q < CT_C; ++q) {          // rows j0..j0+3 of R
+                        const int c = b0 + q;
+                        double gc[CT_R];
+#pragma unroll
+                        for (int i = 0; i < CT_R; ++i) gc[i] = g[i][q];
+#pragma unroll
+                        for (int t = 0; t < CT_R; ++t) {
+                            double v = 0.0;
+#pragma unroll
+                            for (int i = 0; i <= t; ++i) v += Xd[i][t] * gc[i];
+                            g[t][q] = (c < j0 + t) ? 0.0 : v;
                         }
                     }
                     if (tx == 0) {
                         if (fail) s_fail = 1;
                         if (dead_any) s_dead = 1;
                         s_min_ratio = fmin(s_min_ratio, min_ratio);
+#pragma unroll
+                        for (int t = 0; t < CT_R; ++t)
+#pragma unroll
+                            for (int v = 0; v < CT_R; ++v) xdiag[P][t][v] = Xd[t][v];
                     }
 #pragma unroll
                     for (int t = 0; t < CT_R; ++t)
@@ -339,7 +415,7 @@ __device__ __forceinline__ void chol_body(const CholArgs& a) {
         for (int i = 0; i < CT_R; ++i)
 #pragma unroll
             for (int q = 0; q < CT_C; ++q) g[i][q] = 0.0;
-        for (int j = tid; j < l; j += NT) dinv[j] = 0.0;
+        for (int j = tid; j < npanel * CT_R * CT_R; j += NT) (&xdiag[0][0][0])[j] = 0.0;
     }
     if (tid == 0) {
         const bool dead_any = !nonfinite && !zero && s_dead;
@@ -367,10 +443,9 @@ __device__ __forceinline__ void chol_body(const CholArgs& a) {
 #pragma unroll
         for (int q = 0; q < CT_C; ++q) Rs[(a0 + i) * LDR + b0 + q] = (b0 + q >= a0 + i) ? g[i][q] : 0.0;
     __syncthreads();
-    // Inverse X = R^{-1} by panels from the bottom: the panel's group solves its
-    // 4 rows (X[j] = B[j] / R_jj, B[j'] -= R[j'][j] X[j] inside the panel),
-    // publishes them with the panel's R columns, and the rows above subtract
-    // R[i][4P..4P+3] X[4P..4P+3][.] after one barrier.
+    // Inverse X = R^{-1} by panels from the bottom: the panel's group forms its
+    // 4 rows as X_PP B_P (X_PP kept from the factorisation), publishes them, and
+    // the rows above subtract R[i][4P..4P+3] X[4P..4P+3][.] after one barrier.
     double x[CT_R][CT_C];
 #pragma unroll
     for (int i = 0; i < CT_R; ++i)
@@ -378,19 +453,18 @@ __device__ __forceinline__ void chol_body(const CholArgs& a) {
         for (int q = 0; q < CT_C; ++q) x[i][q] = (a0 + i == b0 + q && a0 + i < l) ? 1.0 : 0.0;
     for (int P = npanel - 1; P >= 0; --P) {
         const int j0 = CT_R * P, buf = P & 1;
-        if (ty == P) {
+        if (ty == P) {                  // X_P = X_PP B_P (B_P: rows j0..j0+3 so far)
 #pragma unroll
-            for (int t = CT_R - 1; t >= 0; --t) {
-                const int j = j0 + t;
-                if (j >= l) continue;
-                const double sj = dinv[j];
+            for (int q = 0; q < CT_C; ++q) {
+                double bq[CT_R];
 #pragma unroll
-                for (int q = 0; q < CT_C; ++q) x[t][q] *= sj;          // X[j] = B[j] / R_jj
+                for (int i = 0; i < CT_R; ++i) bq[i] = x[i][q];
 #pragma unroll
-                for (int t2 = 0; t2 < t; ++t2) {                       // B[j0+t2] -= R[j0+t2][j] X[j]
-                    const double rij = Rs[(j0 + t2) * LDR + j];
+                for (int t = 0; t < CT_R; ++t) {
+                    double v = 0.0;
 #pragma unroll
-                    for (int q = 0; q < CT_C; ++q) x[t2][q] -= rij * x[t][q];
+                    for (int i = t; i < CT_R; ++i) v += xdiag[P][t][i] * bq[i];
+                    x[t][q] = v;
                 }
             }
 #pragma unroll

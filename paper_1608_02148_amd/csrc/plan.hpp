@@ -42,9 +42,10 @@ struct Splits {
     int colsum;  // row split of the column-mean pass
 };
 
-// Gram matrices: one split per CU at most, at least 256 rows per split.
+// Gram matrices: one split per CU at most, at least 64 rows per split (a
+// short n x l Gram then still spreads over most CUs).
 inline int gram_split(int64_t rows, int num_cu) {
-    return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(cdiv(rows, 256), num_cu)));
+    return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(cdiv(rows, 64), num_cu)));
 }
 
 // A^T Q: as many splits as fit the 2 resident workgroups per CU in one round
