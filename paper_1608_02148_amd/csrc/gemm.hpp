@@ -60,6 +60,8 @@ struct GemmArgs {
     const uint16_t* xb;  // bf16 products: X packed by XPackBody, bf16 planes [column][k]
     int64_t ldxb;        // k stride of a packed column (a multiple of 8)
     int64_t xb_plane;    // elements from the hi plane to the lo plane
+    const TC* xk;        // optional: X in the compute type packed [column][k] (ld ldxk, a
+    int64_t ldxk;        // multiple of 16 / sizeof(TC)), read with one vector load per item
 };
 
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
@@ -207,12 +209,41 @@ __device__ __forceinline__ void gemm_tile_body(const GemmArgs<TA, TX, TC>& g, in
             }
         }
     };
+    // X item -> (column, k-vector): columns fastest for X itself (neighbouring
+    // lanes read neighbouring columns of a row), k-vectors fastest for the
+    // packed copy (neighbouring lanes read consecutive 16 bytes of a column).
+    auto x_item = [&](int it, int& j, int& kv) {
+        if (g.xk) { j = it / KVECS; kv = it % KVECS; }
+        else      { j = it % T::NC; kv = it / T::NC; }
+    };
     auto load_x = [&](int64_t k0) {
+        if (g.xk) {
+#pragma unroll
+            for (int p = 0; p < T::X_PASSES; ++p) {
+                const int it = p * T::NT + tid;
+                if (it >= T::X_ITEMS) break;
+                int j, kv;
+                x_item(it, j, kv);
+                const int64_t gk = k0 + kv * KV;
+                const int gc = col0 + j;
+                const TC* src = g.xk + static_cast<int64_t>(gc) * g.ldxk + gk;
+                if (gc < g.ncols && gk + KV <= kend) {
+                    const vec_t v = *reinterpret_cast<const vec_t*>(src);
+#pragma unroll
+                    for (int e = 0; e < KV; ++e) rx[p][e] = v[e];
+                } else {
+#pragma unroll
+                    for (int e = 0; e < KV; ++e) rx[p][e] = (gc < g.ncols && gk + e < kend) ? src[e] : TC(0);
+                }
+            }
+            return;
+        }
 #pragma unroll
         for (int p = 0; p < T::X_PASSES; ++p) {
             const int it = p * T::NT + tid;
             if (it >= T::X_ITEMS) break;
-            const int j = it % T::NC, kv = it / T::NC;
+            int j, kv;
+            x_item(it, j, kv);
             const int64_t gk = k0 + kv * KV;
             const int gc = col0 + j;
             const bool ok = gc < g.ncols;
@@ -240,7 +271,8 @@ __device__ __forceinline__ void gemm_tile_body(const GemmArgs<TA, TX, TC>& g, in
         for (int p = 0; p < T::X_PASSES; ++p) {
             const int it = p * T::NT + tid;
             if (it >= T::X_ITEMS) break;
-            const int j = it % T::NC, kv = it / T::NC;
+            int j, kv;
+            x_item(it, j, kv);
             vec_t v;
 #pragma unroll
             for (int e = 0; e < KV; ++e) v[e] = rx[p][e];

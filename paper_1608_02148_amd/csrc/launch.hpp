@@ -75,6 +75,7 @@ GemmArgs<TA, TX, TC> gemm_args(const TA* A, int64_t lda, int64_t rows, int64_t K
     g.a_vec = (reinterpret_cast<uintptr_t>(A) % vec_bytes == 0) && ((lda * sizeof(TA)) % vec_bytes == 0);
     g.x_vec = 0;
     g.xb = nullptr; g.ldxb = 0; g.xb_plane = 0;
+    g.xk = nullptr; g.ldxk = 0;
     return g;
 }
 
@@ -117,13 +118,55 @@ hipError_t gemm_tall_f32(Ex& ex, int tc, int var, const GemmArgs<TA, TX, TC>& g)
     }
 }
 
+// X (K x ncols, ldx) -> XK[c][k] (ld ldk, k-contiguous) in the compute type,
+// so that a product tile reads each k-vector of a column of X with one vector
+// load.  One thread per (column, k-vector), consecutive threads on
+// consecutive columns (coalesced reads of X).
+template <typename TC>
+struct XKPackBody {
+    struct Args {
+        const TC* X; int64_t ldx; int64_t K; int ncols; TC* XK; int64_t ldk;
+        const uint32_t* skip_flag; uint32_t skip_mask; Gate gate;
+    };
+    static constexpr int THREADS = 256;
+    static constexpr int KV = 16 / sizeof(TC);
+    static int blocks(const Args& a) { return static_cast<int>(cdiv(static_cast<int64_t>(a.ncols) * cdiv(a.K, KV), THREADS)); }
+    static size_t lds(const Args&) { return 0; }
+    static __device__ void run(const Args& a, int b) {
+        if (a.skip_flag && ((*a.skip_flag & a.skip_mask) == 0u)) return;
+        if (a.gate.w && ((*a.gate.w & a.gate.mask) == 0u)) return;
+        const int64_t idx = static_cast<int64_t>(b) * THREADS + threadIdx.x;
+        const int c = static_cast<int>(idx % a.ncols);
+        const int64_t k0 = KV * (idx / a.ncols);
+        if (k0 >= a.K) return;
+        typedef TC vec_t __attribute__((ext_vector_type(KV)));
+        vec_t v;
+#pragma unroll
+        for (int e = 0; e < KV; ++e) v[e] = (k0 + e < a.K) ? a.X[(k0 + e) * a.ldx + c] : TC(0);
+        *reinterpret_cast<vec_t*>(a.XK + static_cast<int64_t>(c) * a.ldk + k0) = v;
+    }
+};
+
 template <typename TA, typename TX, typename TC, int MODE, class Ex>
 hipError_t gemm_plain(Ex& ex, int cls, bool square, const TA* A, int64_t lda, int64_t rows, int64_t K,
                       const TX* X, int64_t ldx, int ncols, TC* out, int64_t ldo, int S, int64_t part_stride,
-                      const double* mu, const uint32_t* skip_flag, uint32_t skip_mask, Gate gate = {}) {
+                      const double* mu, const uint32_t* skip_flag, uint32_t skip_mask, Gate gate = {},
+                      TC* xk = nullptr, int64_t ldxk = 0) {
     const size_t vb = (16 / sizeof(TC)) * sizeof(TA);    // 16 / sizeof(TC) consecutive elements of A
-    const auto g = gemm_args<TA, TX, TC>(A, lda, rows, K, X, ldx, ncols, out, ldo, S, part_stride, mu, skip_flag,
-                                         skip_mask, gemm_bk<TC>(), vb, gate);
+    auto g = gemm_args<TA, TX, TC>(A, lda, rows, K, X, ldx, ncols, out, ldo, S, part_stride, mu, skip_flag,
+                                   skip_mask, gemm_bk<TC>(), vb, gate);
+    if constexpr (std::is_same<TX, TC>::value) {
+        // optional k-contiguous copy of X (scratch xk, ld ldxk >= K, a multiple
+        // of 16 / sizeof(TC)): one vector load per k-vector in the tiles
+        if (xk && !square) {
+            if (ldxk < K || ldxk % (16 / sizeof(TC)) != 0) return hipErrorInvalidValue;
+            const hipError_t e = ex.template run<XKPackBody<TC>>(typename XKPackBody<TC>::Args{
+                X, ldx, K, ncols, xk, ldxk, skip_flag, skip_mask, gate});
+            if (e != hipSuccess) return e;
+            g.xk = xk;
+            g.ldxk = ldxk;
+        }
+    }
     if (square) {
         // square tiles: the smallest that holds max(rows, ncols), so little
         // of the f64 matrix cores' work is padding -- 32, 48, 64, 80, 96 or
@@ -181,18 +224,20 @@ hipError_t gemm_bf16(Ex& ex, bool split, int cls, const TA* A, int64_t lda, int6
 
 // One product with A in the requested arithmetic: 0 = storage precision
 // (f32 / f64 matrix cores), 1 = bf16, 2 = split bf16 (near-f32-accurate).
+// xk / ldxk (optional): scratch for the k-contiguous copy of X that the
+// storage-precision tiles read (ncols x ldxk elements of TC).
 template <typename TA, typename TC, int MODE, class Ex>
 hipError_t gemm_step(Ex& ex, int arith, int cls, const TA* A, int64_t lda, int64_t rows, int64_t K,
                      const TC* X, int64_t ldx, int ncols, TC* out, int64_t ldo, int S, int64_t part_stride,
                      const double* mu, const uint32_t* skip_flag, uint32_t skip_mask, Gate gate = {},
-                     XPack xp = {}) {
+                     XPack xp = {}, TC* xk = nullptr, int64_t ldxk = 0) {
     if constexpr (std::is_same<TC, float>::value) {
         if (arith != 0)
             return gemm_bf16<TA, MODE>(ex, arith == 2, cls, A, lda, rows, K, X, ldx, ncols, out, ldo, S,
                                        part_stride, mu, skip_flag, skip_mask, gate, xp);
     }
     return gemm_plain<TA, TC, TC, MODE>(ex, cls, false, A, lda, rows, K, X, ldx, ncols, out, ldo, S, part_stride,
-                                        mu, skip_flag, skip_mask, gate);
+                                        mu, skip_flag, skip_mask, gate, xk, ldxk);
 }
 
 template <typename T, class Ex>

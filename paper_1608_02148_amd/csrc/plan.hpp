@@ -101,6 +101,10 @@ struct Plan {
     // Lp columns x ldxp (max(m, n) rounded up to 8) each
     size_t xpack = 0;
     int64_t ldxp = 0, xplane = 0;
+    // storage-precision products of a single solve: X copied k-contiguous,
+    // Lp columns x ldxk (max(m, n) rounded up to 8) in the compute type
+    size_t xk = 0;
+    int64_t ldxk = 0;
 };
 
 inline int validate(int32_t dtype, int64_t m, int64_t n, int32_t k, const rsvd_params* prm,
@@ -176,6 +180,9 @@ inline Plan make_plan(int dtype, int64_t m, int64_t n, int k, const rsvd_params*
         P.ldxp = rup(std::max(m, n), 8);
         P.xplane = static_cast<int64_t>(P.Lp) * P.ldxp;
         P.xpack = L.take(2 * static_cast<size_t>(P.xplane) * sizeof(uint16_t));
+    } else if (!batch) {
+        P.ldxk = rup(std::max(m, n), 8);
+        P.xk = L.take(static_cast<size_t>(P.Lp) * P.ldxk * cs);
     }
     P.probes = prm->probes;
     if (P.probes > 0) {
