@@ -20,6 +20,8 @@
 //     write); a fragment is KV 4/8-byte LDS reads of 16 consecutive r.
 // LDS is double buffered; the next tile's global loads are in flight while the
 // current tile is multiplied, with a single barrier per step.
+// X may come k-contiguous (g.xk, packed once per product), then each k-vector
+// of a column is one vector load.
 //
 // Split-K: grid.y = S splits the reduction into S contiguous chunks.  With
 // S > 1 every split writes its own partial block and a separate kernel sums the
@@ -296,11 +298,16 @@ __device__ __forceinline__ void gemm_tile_body(const GemmArgs<TA, TX, TC>& g, in
         for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
             store_tiles(buf);
             __syncthreads();
-            if (k0 + BK < kend) { load_a(k0 + BK); load_x(k0 + BK); }
+            // TN issues the next tile's global loads after its first group of
+            // fragment reads (measured faster there; NN is faster issuing them
+            // at once)
+            constexpr int LOAD_KG = (MODE == MODE_TN && BK > T::KG) ? T::KG : 0;
+            if (LOAD_KG == 0 && k0 + BK < kend) { load_a(k0 + BK); load_x(k0 + BK); }
             const TC* as = As + buf * T::A_LDS;
             const TC* xs = Xs + buf * T::NC * SK;
 #pragma unroll
             for (int kg = 0; kg < BK; kg += T::KG) {
+                if (LOAD_KG != 0 && kg == LOAD_KG && k0 + BK < kend) { load_a(k0 + BK); load_x(k0 + BK); }
                 vec_t a[WR], b[WC];
 #pragma unroll
                 for (int i = 0; i < WR; ++i) {
