@@ -128,7 +128,9 @@ struct GemmTile {
 };
 
 // Tile (bx, by, bz) = (row tile, split, column tile) of the product g.
-template <typename TA, typename TX, typename TC, int MODE, int WR, int WC, int WGM, int WGN, int BK>
+// XKP: X is read from the packed copy g.xk (a separate instance, so that the
+// tiles without it compile exactly as before).
+template <typename TA, typename TX, typename TC, int MODE, int WR, int WC, int WGM, int WGN, int BK, bool XKP = false>
 __device__ __forceinline__ void gemm_tile_body(const GemmArgs<TA, TX, TC>& g, int bx, int by, int bz) {
     typedef GemmTile<TA, TX, TC, MODE, WR, WC, WGM, WGN, BK> T;
     typedef typename Mfma<TC>::acc_t acc_t;
@@ -215,11 +217,11 @@ __device__ __forceinline__ void gemm_tile_body(const GemmArgs<TA, TX, TC>& g, in
     // lanes read neighbouring columns of a row), k-vectors fastest for the
     // packed copy (neighbouring lanes read consecutive 16 bytes of a column).
     auto x_item = [&](int it, int& j, int& kv) {
-        if (g.xk) { j = it / KVECS; kv = it % KVECS; }
-        else      { j = it % T::NC; kv = it / T::NC; }
+        if constexpr (XKP) { j = it / KVECS; kv = it % KVECS; }
+        else               { j = it % T::NC; kv = it / T::NC; }
     };
     auto load_x = [&](int64_t k0) {
-        if (g.xk) {
+        if constexpr (XKP) {
 #pragma unroll
             for (int p = 0; p < T::X_PASSES; ++p) {
                 const int it = p * T::NT + tid;
@@ -298,10 +300,11 @@ __device__ __forceinline__ void gemm_tile_body(const GemmArgs<TA, TX, TC>& g, in
         for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
             store_tiles(buf);
             __syncthreads();
-            // TN issues the next tile's global loads after its first group of
-            // fragment reads (measured faster there; NN is faster issuing them
-            // at once)
-            constexpr int LOAD_KG = (MODE == MODE_TN && BK > T::KG) ? T::KG : 0;
+            // 16-wave TN tiles (one workgroup per CU) issue the next tile's
+            // global loads after their first group of fragment reads; measured
+            // faster there, and slower for NN and for the 8-wave tiles (two
+            // workgroups per CU) of batches
+            constexpr int LOAD_KG = (MODE == MODE_TN && WGM * WGN >= 16 && BK > T::KG) ? T::KG : 0;
             if (LOAD_KG == 0 && k0 + BK < kend) { load_a(k0 + BK); load_x(k0 + BK); }
             const TC* as = As + buf * T::A_LDS;
             const TC* xs = Xs + buf * T::NC * SK;

@@ -18,7 +18,7 @@ template <typename T> constexpr int gemm_bk() { return sizeof(T) == 8 ? 16 : 32;
 
 // Storage-precision product (f32 / f64 matrix cores).  Workgroup b of a
 // problem covers column tile b % C, row tile (b / C) % gx, split b / (C gx).
-template <typename TA, typename TX, typename TC, int MODE, int WR, int WC, int WGM, int WGN>
+template <typename TA, typename TX, typename TC, int MODE, int WR, int WC, int WGM, int WGN, bool XKP = false>
 struct GemmBody {
     static constexpr int BK = gemm_bk<TC>();
     typedef GemmTile<TA, TX, TC, MODE, WR, WC, WGM, WGN, BK> T;
@@ -34,7 +34,7 @@ struct GemmBody {
         const int gx = static_cast<int>(cdiv(g.rows, T::BM));
         const int nct = static_cast<int>(cdiv(g.ncols, T::NC));
         const int rest = b / nct;
-        gemm_tile_body<TA, TX, TC, MODE, WR, WC, WGM, WGN, BK>(g, rest % gx, rest / gx, b % nct);
+        gemm_tile_body<TA, TX, TC, MODE, WR, WC, WGM, WGN, BK, XKP>(g, rest % gx, rest / gx, b % nct);
     }
 };
 
@@ -90,32 +90,41 @@ GemmArgs<TA, TX, TC> gemm_args(const TA* A, int64_t lda, int64_t rows, int64_t K
 // 1 = 8 waves, 2 = 16 waves over the same 128 x NC output tile (more waves
 // hide more latency, fewer keep more operands per wave); `cls` carries the
 // variant in its upper 16 bits (the plan's autotuned choice).
-template <typename TA, typename TX, typename TC, int MODE, class Ex>
+template <typename TA, typename TX, typename TC, int MODE, bool XKP, class Ex>
 hipError_t gemm_tall_f32(Ex& ex, int tc, int var, const GemmArgs<TA, TX, TC>& g) {
     switch (tc) {
         case 32:
-            if (var == 1) return ex.template run<GemmBody<TA, TX, TC, MODE, 2, 1, 4, 2>>(g);
-            if (var == 2) return ex.template run<GemmBody<TA, TX, TC, MODE, 1, 1, 8, 2>>(g);
-            return ex.template run<GemmBody<TA, TX, TC, MODE, 2, 2, 4, 1>>(g);
+            if (var == 1) return ex.template run<GemmBody<TA, TX, TC, MODE, 2, 1, 4, 2, XKP>>(g);
+            if (var == 2) return ex.template run<GemmBody<TA, TX, TC, MODE, 1, 1, 8, 2, XKP>>(g);
+            return ex.template run<GemmBody<TA, TX, TC, MODE, 2, 2, 4, 1, XKP>>(g);
         case 48:
-            if (var != 0) return ex.template run<GemmBody<TA, TX, TC, MODE, 1, 3, 8, 1>>(g);
-            return ex.template run<GemmBody<TA, TX, TC, MODE, 2, 3, 4, 1>>(g);
+            if (var != 0) return ex.template run<GemmBody<TA, TX, TC, MODE, 1, 3, 8, 1, XKP>>(g);
+            return ex.template run<GemmBody<TA, TX, TC, MODE, 2, 3, 4, 1, XKP>>(g);
         case 64:
-            if (var == 1) return ex.template run<GemmBody<TA, TX, TC, MODE, 4, 1, 2, 4>>(g);
-            if (var == 2) return ex.template run<GemmBody<TA, TX, TC, MODE, 2, 1, 4, 4>>(g);
-            return ex.template run<GemmBody<TA, TX, TC, MODE, 4, 2, 2, 2>>(g);
+            if (var == 1) return ex.template run<GemmBody<TA, TX, TC, MODE, 4, 1, 2, 4, XKP>>(g);
+            if (var == 2) return ex.template run<GemmBody<TA, TX, TC, MODE, 2, 1, 4, 4, XKP>>(g);
+            return ex.template run<GemmBody<TA, TX, TC, MODE, 4, 2, 2, 2, XKP>>(g);
         case 80:
-            if (var != 0) return ex.template run<GemmBody<TA, TX, TC, MODE, 1, 5, 8, 1>>(g);
-            return ex.template run<GemmBody<TA, TX, TC, MODE, 2, 5, 4, 1>>(g);
+            if (var != 0) return ex.template run<GemmBody<TA, TX, TC, MODE, 1, 5, 8, 1, XKP>>(g);
+            return ex.template run<GemmBody<TA, TX, TC, MODE, 2, 5, 4, 1, XKP>>(g);
         case 96:
-            if (var == 1) return ex.template run<GemmBody<TA, TX, TC, MODE, 2, 3, 4, 2>>(g);
-            if (var == 2) return ex.template run<GemmBody<TA, TX, TC, MODE, 1, 3, 8, 2>>(g);
-            return ex.template run<GemmBody<TA, TX, TC, MODE, 4, 3, 2, 2>>(g);
+            if (var == 1) return ex.template run<GemmBody<TA, TX, TC, MODE, 2, 3, 4, 2, XKP>>(g);
+            if (var == 2) return ex.template run<GemmBody<TA, TX, TC, MODE, 1, 3, 8, 2, XKP>>(g);
+            return ex.template run<GemmBody<TA, TX, TC, MODE, 4, 3, 2, 2, XKP>>(g);
         default:
-            if (var == 1) return ex.template run<GemmBody<TA, TX, TC, MODE, 4, 2, 2, 4>>(g);
-            if (var == 2) return ex.template run<GemmBody<TA, TX, TC, MODE, 2, 2, 4, 4>>(g);
-            return ex.template run<GemmBody<TA, TX, TC, MODE, 4, 4, 2, 2>>(g);
+            if (var == 1) return ex.template run<GemmBody<TA, TX, TC, MODE, 4, 2, 2, 4, XKP>>(g);
+            if (var == 2) return ex.template run<GemmBody<TA, TX, TC, MODE, 2, 2, 4, 4, XKP>>(g);
+            return ex.template run<GemmBody<TA, TX, TC, MODE, 4, 4, 2, 2, XKP>>(g);
     }
+}
+
+// Tall product tiles: the f32 column classes and variants, or the f64 ones.
+template <typename TA, typename TX, typename TC, int MODE, bool XKP, class Ex>
+hipError_t gemm_tall(Ex& ex, int tc, int var, const GemmArgs<TA, TX, TC>& g) {
+    if constexpr (sizeof(TC) == 4) return gemm_tall_f32<TA, TX, TC, MODE, XKP>(ex, tc, var, g);
+    if (tc == 32) return ex.template run<GemmBody<TA, TX, TC, MODE, 2, 2, 4, 1, XKP>>(g);
+    if (tc == 64) return ex.template run<GemmBody<TA, TX, TC, MODE, 4, 2, 2, 2, XKP>>(g);
+    return ex.template run<GemmBody<TA, TX, TC, MODE, 4, 4, 2, 2, XKP>>(g);
 }
 
 // X (K x ncols, ldx) -> XK[c][k] (ld ldk, k-contiguous) in the compute type,
@@ -182,10 +191,8 @@ hipError_t gemm_plain(Ex& ex, int cls, bool square, const TA* A, int64_t lda, in
         return ex.template run<GemmBody<TA, TX, TC, MODE, 4, 4, 2, 2>>(g);
     }
     const int tc = (cls & 0xFFFF) ? (cls & 0xFFFF) : tile_cols(ncols);
-    if constexpr (sizeof(TC) == 4) return gemm_tall_f32<TA, TX, TC, MODE>(ex, tc, cls >> 16, g);
-    if (tc == 32) return ex.template run<GemmBody<TA, TX, TC, MODE, 2, 2, 4, 1>>(g);
-    if (tc == 64) return ex.template run<GemmBody<TA, TX, TC, MODE, 4, 2, 2, 2>>(g);
-    return ex.template run<GemmBody<TA, TX, TC, MODE, 4, 4, 2, 2>>(g);
+    if (g.xk) return gemm_tall<TA, TX, TC, MODE, true>(ex, tc, cls >> 16, g);
+    return gemm_tall<TA, TX, TC, MODE, false>(ex, tc, cls >> 16, g);
 }
 
 template <typename TA, int MODE, bool SPLIT, class Ex>
