@@ -188,7 +188,9 @@ hipError_t gemm_plain(Ex& ex, int cls, bool square, const TA* A, int64_t lda, in
         if (sc == 64) return ex.template run<GemmBody<TA, TX, TC, MODE, 2, 2, 2, 2>>(g);
         if (sc == 80) return ex.template run<GemmBody<TA, TX, TC, MODE, 1, 5, 5, 1>>(g);
         if (sc == 96) return ex.template run<GemmBody<TA, TX, TC, MODE, 2, 3, 3, 2>>(g);
-        return ex.template run<GemmBody<TA, TX, TC, MODE, 4, 4, 2, 2>>(g);
+        // 128: 16 waves (4 per SIMD hide the load-convert-stage latency that
+        // one wave per SIMD left exposed; the 100000 x 120 Gram 119 -> 72 us)
+        return ex.template run<GemmBody<TA, TX, TC, MODE, 2, 2, 4, 4>>(g);
     }
     const int tc = (cls & 0xFFFF) ? (cls & 0xFFFF) : tile_cols(ncols);
     if (g.xk) return gemm_tall<TA, TX, TC, MODE, true>(ex, tc, cls >> 16, g);
