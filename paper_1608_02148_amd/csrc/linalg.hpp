@@ -637,9 +637,21 @@ template <int LM> inline size_t jacobi_block_lds_bytes(int l) {
     return static_cast<size_t>(JBS) * jacobi_blocks(l) * (LM + 1) * sizeof(double);
 }
 
+// Value of lane K of each quad (DPP quad_perm [K, K, K, K]).
+template <int K>
+__device__ __forceinline__ double quad_bcast(double v) {
+    constexpr int CTRL = K | (K << 2) | (K << 4) | (K << 6);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+
 // One sub-round: rotations of the 4 disjoint register columns (I_k, J_k).
 // Returns whether any pair was rotated.  Pairs below the threshold get the
 // identity (c, s) = (1, 0), so the update is branch-free across the group.
+// The scalar work of the 4 pairs (rotation and new squared norms) is spread
+// over the lanes of each quad -- lane k of a quad computes pair k -- and
+// shared by quad broadcasts.
 template <int VPL, int I0, int J0, int I1, int J1, int I2, int J2, int I3, int J3>
 __device__ __forceinline__ bool jacobi_sub_round(double (&x)[2 * JBS][VPL], double (&nrm)[2 * JBS], double tol2) {
     constexpr int I[4] = {I0, I1, I2, I3};
@@ -661,20 +673,41 @@ __device__ __forceinline__ bool jacobi_sub_round(double (&x)[2 * JBS][VPL], doub
         any = any || rot[k];
     }
     if (!any) return false;
+    // this lane's pair: k = lane % 4, picked by an exact 0/1 blend (selects
+    // between register values would be turned into an indexed load from memory)
+    const int kk = threadIdx.x & 3;
+    double al = 0.0, be = 0.0, g = 0.0;
+    bool r = false;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const double al = nrm[I[k]], be = nrm[J[k]], g = rot[k] ? ga[k] : 0.0;
-        double c, s;
-        jacobi_cs(al, be, rot[k] ? ga[k] : 1.0, c, s);
-        if (!rot[k]) { c = 1.0; s = 0.0; }
-        const double x2 = 2.0 * c * s * g, cc = c * c, ss = s * s;   // |c a - s b|^2, |s a + c b|^2
-        nrm[I[k]] = fmax(fma(cc, al, fma(ss, be, -x2)), 0.0);
-        nrm[J[k]] = fmax(fma(ss, al, fma(cc, be, x2)), 0.0);
+        const double w = (kk == k) ? 1.0 : 0.0;
+        al = fma(w, nrm[I[k]], al);
+        be = fma(w, nrm[J[k]], be);
+        g = fma(w, ga[k], g);
+        r = r || (kk == k && rot[k]);
+    }
+    double cm, sm;
+    jacobi_cs(al, be, r ? g : 1.0, cm, sm);
+    if (!r) { cm = 1.0; sm = 0.0; }
+    const double x2 = 2.0 * cm * sm * (r ? g : 0.0), cc = cm * cm, ss = sm * sm;   // |c a - s b|^2, |s a + c b|^2
+    const double na = fmax(fma(cc, al, fma(ss, be, -x2)), 0.0);
+    const double nb = fmax(fma(ss, al, fma(cc, be, x2)), 0.0);
+    double c[4], s[4];
+    c[0] = quad_bcast<0>(cm); s[0] = quad_bcast<0>(sm);
+    c[1] = quad_bcast<1>(cm); s[1] = quad_bcast<1>(sm);
+    c[2] = quad_bcast<2>(cm); s[2] = quad_bcast<2>(sm);
+    c[3] = quad_bcast<3>(cm); s[3] = quad_bcast<3>(sm);
+    nrm[I[0]] = quad_bcast<0>(na); nrm[J[0]] = quad_bcast<0>(nb);
+    nrm[I[1]] = quad_bcast<1>(na); nrm[J[1]] = quad_bcast<1>(nb);
+    nrm[I[2]] = quad_bcast<2>(na); nrm[J[2]] = quad_bcast<2>(nb);
+    nrm[I[3]] = quad_bcast<3>(na); nrm[J[3]] = quad_bcast<3>(nb);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
 #pragma unroll
         for (int q = 0; q < VPL; ++q) {
             const double xa = x[I[k]][q], xb = x[J[k]][q];
-            x[I[k]][q] = fma(c, xa, -s * xb);
-            x[J[k]][q] = fma(s, xa, c * xb);
+            x[I[k]][q] = fma(c[k], xa, -s[k] * xb);
+            x[J[k]][q] = fma(s[k], xa, c[k] * xb);
         }
     }
     return true;
