@@ -411,7 +411,9 @@ def main():
         if bound == "mfma":
             var = api_variants[6 * mode + 5]
             shape = {0: "4, 4, 2, 2", 1: "4, 2, 2, 4", 2: "2, 2, 4, 4"}[var]
-            kern = f"single_kernel<GemmBody<float, float, float, {mode}, {shape}>>"
+            # single solves read X from its packed copy (the instance with XKP = true);
+            # the event-timed launch covers the pack kernel and the product
+            kern = f"single_kernel<GemmBody<float, float, float, {mode}, {shape}, true>>"
         else:
             kern = f"single_kernel<Bf16Body<float, {mode}, false, 4, 4, 2, 2>>"
         kern += " (A^T Q)" if dom_name == "AT_Q" else " (A X)"
