@@ -204,7 +204,9 @@ hipError_t gemm_bf16_cls(Ex& ex, int tc, const GemmArgs<TA, float, float>& g) {
     if (tc == 64) return ex.template run<Bf16Body<TA, MODE, SPLIT, 4, 2, 2, 2>>(g);
     if (tc == 80) return ex.template run<Bf16Body<TA, MODE, SPLIT, 2, 5, 4, 1>>(g);
     if (tc == 96) return ex.template run<Bf16Body<TA, MODE, SPLIT, 4, 3, 2, 2>>(g);
-    if (tc == 256) return ex.template run<Bf16Body<TA, MODE, SPLIT, 4, 4, 2, 4>>(g);
+    // 256 columns (sketches wider than 128): 16 waves of 32 x 64 (the 8-wave
+    // 64 x 64 tiling was 5-7 % slower for A X at 200000 x 20000, l = 220)
+    if (tc == 256) return ex.template run<Bf16Body<TA, MODE, SPLIT, 2, 4, 4, 4>>(g);
     return ex.template run<Bf16Body<TA, MODE, SPLIT, 4, 4, 2, 2>>(g);
 }
 

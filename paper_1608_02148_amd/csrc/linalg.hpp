@@ -544,11 +544,10 @@ struct JacobiArgs {
 
 constexpr int JAC_GROUP = 16;      // lanes per column pair (one DPP row)
 
-// Column stride of W in LDS: l rounded up to a multiple of 16 doubles plus
-// one 64-bit bank pair, so that the columns read by the groups of a wave
-// start on different banks.
+// Column stride of W for l > 128 (global memory, block sweeps): l rounded up
+// to a multiple of 16 doubles plus one, so that the columns read by the
+// groups of a wave start on different banks when staged in LDS.
 __host__ __device__ inline int jacobi_ldw(int l) { return ((l + 15) / 16) * 16 + 1; }
-inline size_t jacobi_lds_bytes(int l) { return static_cast<size_t>(jacobi_ldw(l)) * l * sizeof(double); }
 
 // Rotation threshold: a rotated pair keeps |w_a . w_b| of order u sqrt(l)
 // |w_a| |w_b| after rounding, so asking for less than l u would never settle.
@@ -569,18 +568,6 @@ __device__ __forceinline__ double group_sum(double v) {
     v += dpp_f64<0x141>(v);   // row_half_mirror
     v += dpp_f64<0x140>(v);   // row_mirror
     return v;
-}
-// The same over the 8 lanes of a half row (quad exchanges, half-row mirror).
-__device__ __forceinline__ double half_group_sum(double v) {
-    v += dpp_f64<0xB1>(v);
-    v += dpp_f64<0x4E>(v);
-    v += dpp_f64<0x141>(v);
-    return v;
-}
-template <int G>
-__device__ __forceinline__ double lane_group_sum(double v) {
-    static_assert(G == 8 || G == 16, "8- or 16-lane groups");
-    return G == 8 ? half_group_sum(v) : group_sum(v);
 }
 
 // 1/sqrt(x) for x in [1/4, 8]: the hardware estimate, then two Newton steps
@@ -842,7 +829,7 @@ __device__ __forceinline__ void jacobi_body(const JacobiArgs& a) {
         double* wc = W + c * ldw;
         double ss = 0.0;
         for (int r = gl; r < l; r += JG) ss += wc[r] * wc[r];
-        ss = lane_group_sum<JG>(ss);
+        ss = group_sum(ss);
         const double sg = sqrt(ss);
         const double inv = (sg > 0.0) ? 1.0 / sg : 0.0;
         for (int r = gl; r < l; r += JG) wc[r] *= inv;

@@ -198,3 +198,23 @@ def test_split_bf16_is_f32_accurate(gpu_lib, dt):
     refz = A.T @ _np(Qg).astype(np.float64)
     sz = np.abs(A).max() * np.sqrt(m) * 4
     assert np.abs(_np(api.gemm_tn(Ag, Qg, "split")) - refz).max() / sz < 1e-6
+
+
+@pytest.mark.parametrize("c", [30, 100])
+@pytest.mark.parametrize("shift", [-600, 600])
+def test_small_svd_is_exactly_scale_invariant(gpu_lib, c, shift):
+    """The Jacobi works on 2^-e R with 2^(e-1) <= max |R_ij| < 2^e, an exact
+    scaling, so R 2^shift gives the singular values of R times 2^shift bit for
+    bit and the same W -- also where the squared column norms of R 2^shift
+    would overflow (shift = 600) or underflow (shift = -600) in f64."""
+    from paper_1608_02148_amd import api
+    rng = np.random.default_rng(c + 7)
+    R = np.triu(rng.standard_normal((c, c)))
+    R[np.diag_indices(c)] = np.abs(R[np.diag_indices(c)]) + 0.5
+    s0, W0, _, f0 = api.small_svd(torch.tensor(R, device=DEV))
+    s1, W1, _, f1 = api.small_svd(torch.tensor(np.ldexp(R, shift), device=DEV))
+    assert torch.equal(s1, torch.ldexp(s0, torch.tensor(shift, device=DEV)))
+    assert torch.equal(W1, W0)
+    assert int(_np(f1)[0]) & 8 == 0
+    se = np.linalg.svd(R, compute_uv=False)     # (ill-conditioned R: absolute floor as above)
+    np.testing.assert_allclose(np.ldexp(_np(s1), -shift), se, rtol=1e-12, atol=1e-14 * se[0])
