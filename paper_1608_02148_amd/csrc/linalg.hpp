@@ -91,8 +91,19 @@ struct ReduceBody {
         const int64_t r = idx / a.ncols;
         const int c = static_cast<int>(idx - r * a.ncols);
         if (r >= a.rows) return;
-        T s = a.part[r * a.ldp + c];
-        for (int k = 1; k < a.S; ++k) s += a.part[k * a.part_stride + r * a.ldp + c];
+        // loads four splits ahead, sums in split order
+        const T* src = a.part + r * a.ldp + c;
+        T s = src[0];
+        int k = 1;
+        for (; k + 4 <= a.S; k += 4) {
+            const T v0 = src[k * a.part_stride], v1 = src[(k + 1) * a.part_stride];
+            const T v2 = src[(k + 2) * a.part_stride], v3 = src[(k + 3) * a.part_stride];
+            s += v0;
+            s += v1;
+            s += v2;
+            s += v3;
+        }
+        for (; k < a.S; ++k) s += src[k * a.part_stride];
         a.out[r * a.ldo + c] = s;
     }
 };
