@@ -60,8 +60,8 @@ def tune(reps=3, log=print):
     from synth import matrices as syn
     dev = torch.device("cuda", torch.cuda.current_device())
     best = get_variants(dev)
-    c = syn.CONFIGS["c4"]
-    data = syn.c4_torch(device=dev, batch=c["batch"], seed=c["gen_seed"])
+    c = syn.CONFIGS["ragged_4096"]
+    data = syn.ragged_torch(device=dev, batch=c["batch"], seed=c["gen_seed"])
     ks = [int(x) for x in data["k"]]
 
     def batch_time():

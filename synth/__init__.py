@@ -6,6 +6,6 @@ oracle and the HIP path can both consume its output without sharing any part
 of the method.
 """
 from .matrices import (  # noqa: F401
-    haar, planted, planted_torch, spectrum, CONFIGS, c1_matrix, c2_matrix,
-    c2_offsets, c3_shape_torch, c4_batch, paper_lowrank_product,
+    haar, planted, planted_torch, spectrum, CONFIGS, harmonic_2000x1000, tall_exp_matrix,
+    tall_exp_offsets, poly_bf16_torch, ragged_batch, paper_lowrank_product,
 )

@@ -6,15 +6,18 @@ matrices from the classical compact groups", 2007).
 
 Workload recipes (sizes, spectra and seeds):
 
-* C1  2000 x 1000 float64, sigma_i = 1/i (all 1000 values); k=20, p=10, q=2.
-* C2  100000 x 5000 float32, sigma_i = exp(-i/50) for i <= 1000 plus a
-      Gaussian noise floor of 1e-6 sigma_1 (entries N(0,1) * 1e-6 sigma_1 /
-      sqrt(m)); k=100, p=20, q=2.  For PCA a column offset mu_j ~ N(0,1) *
-      sigma_1 / sqrt(m) is added.
-* C3  200000 x 20000 bfloat16, sigma_i = i^-1.5 for i <= 4096, computed in
-      float64 and rounded to bfloat16 (the rounded matrix is the instance).
-* C4  4096 ragged float32 matrices: m ~ U{256..4096}, n ~ U{64..1024},
-      k ~ U{8..min(64, min(m,n)-10)}, sigma_i = i^-alpha, alpha ~ U[0.5, 3].
+* harmonic_2000x1000: 2000 x 1000 float64, sigma_i = 1/i (all 1000 values);
+      k=20, p=10, q=2.
+* tall_exp_100000x5000: 100000 x 5000 float32, sigma_i = exp(-i/50) for
+      i <= 1000 plus a Gaussian noise floor of 1e-6 sigma_1 (entries N(0,1) *
+      1e-6 sigma_1 / sqrt(m)); k=100, p=20, q=2.  For PCA a column offset
+      mu_j ~ N(0,1) * sigma_1 / sqrt(m) is added.
+* poly_bf16_200000x20000: 200000 x 20000 bfloat16, sigma_i = i^-1.5 for
+      i <= 4096, computed in float64 and rounded to bfloat16 (the rounded
+      matrix is the instance).
+* ragged_4096: 4096 ragged float32 matrices: m ~ U{256..4096},
+      n ~ U{64..1024}, k ~ U{8..min(64, min(m,n)-10)}, sigma_i = i^-alpha,
+      alpha ~ U[0.5, 3].
 * paper-shaped: the rank-200 product of two Gaussian matrices used for the
   paper's timing study (Sec. 3.8).
 """
@@ -23,10 +26,10 @@ import math
 import numpy as np
 
 CONFIGS = {
-    "c1": dict(m=2000, n=1000, k=20, p=10, q=2, dtype="f64", gen_seed=1608, omega_seed=2148),
-    "c2": dict(m=100000, n=5000, k=100, p=20, q=2, dtype="f32", gen_seed=5000, omega_seed=2148),
-    "c3": dict(m=200000, n=20000, k=200, p=20, q=2, dtype="bf16", gen_seed=20000, omega_seed=2148),
-    "c4": dict(batch=4096, p=10, q=2, dtype="f32", gen_seed=4096, omega_seed=2148),
+    "harmonic_2000x1000": dict(m=2000, n=1000, k=20, p=10, q=2, dtype="f64", gen_seed=1608, omega_seed=2148),
+    "tall_exp_100000x5000": dict(m=100000, n=5000, k=100, p=20, q=2, dtype="f32", gen_seed=5000, omega_seed=2148),
+    "poly_bf16_200000x20000": dict(m=200000, n=20000, k=200, p=20, q=2, dtype="bf16", gen_seed=20000, omega_seed=2148),
+    "ragged_4096": dict(batch=4096, p=10, q=2, dtype="f32", gen_seed=4096, omega_seed=2148),
 }
 
 
@@ -100,38 +103,39 @@ def planted_torch(m, n, sigma, seed, noise=0.0, device="cuda", out_dtype=None,
     return A
 
 
-def c1_matrix():
-    """C1 instance: 2000 x 1000 float64 with sigma_i = 1/i."""
-    c = CONFIGS["c1"]
+def harmonic_2000x1000():
+    """The 2000 x 1000 float64 instance with sigma_i = 1/i."""
+    c = CONFIGS["harmonic_2000x1000"]
     sig = spectrum("inverse", min(c["m"], c["n"]))
     return planted(c["m"], c["n"], sig, c["gen_seed"])
 
 
-def c2_sigma():
+def tall_exp_sigma():
     return spectrum("exp", 1000, tau=50.0)
 
 
-def c2_matrix(device="cuda", m=None, n=None):
-    """C2 instance (float32 torch tensor on ``device``), optionally resized."""
+def tall_exp_matrix(device="cuda", m=None, n=None):
+    """The 100000 x 5000 exponential-spectrum instance (float32 torch tensor on
+    ``device``), optionally resized."""
     import torch
-    c = CONFIGS["c2"]
+    c = CONFIGS["tall_exp_100000x5000"]
     m = m or c["m"]
     n = n or c["n"]
-    sig = c2_sigma()[: min(m, n, 1000)]
+    sig = tall_exp_sigma()[: min(m, n, 1000)]
     noise = 1e-6 * sig[0] / math.sqrt(m)
     return planted_torch(m, n, sig, c["gen_seed"], noise=noise, device=device,
                          out_dtype=torch.float32)
 
 
-def c2_offsets(n, m, seed=5001):
+def tall_exp_offsets(n, m, seed=5001):
     """Column offsets mu_j ~ N(0,1) * sigma_1 / sqrt(m) for the PCA variant."""
     rng = np.random.default_rng(seed)
-    return rng.standard_normal(n) * (c2_sigma()[0] / math.sqrt(m))
+    return rng.standard_normal(n) * (tall_exp_sigma()[0] / math.sqrt(m))
 
 
-def c3_shape_torch(device="cuda", m=200000, n=20000, rank=4096, seed=20000, chunk_rows=8192,
+def poly_bf16_torch(device="cuda", m=200000, n=20000, rank=4096, seed=20000, chunk_rows=8192,
                    dtype=None):
-    """A matrix of C3's shape and spectrum (sigma_i = i^-1.5, i <= rank),
+    """A matrix of the 200000 x 20000 bf16 workload's shape and spectrum (sigma_i = i^-1.5, i <= rank),
     rounded once to ``dtype`` (default bfloat16).  The orthonormal factors
     are polar factors of Gaussian blocks, computed with matrix products only
     (Newton-Schulz iteration X <- X (3 I - X^T X) / 2 from the block scaled
@@ -162,9 +166,9 @@ def c3_shape_torch(device="cuda", m=200000, n=20000, rank=4096, seed=20000, chun
     return A
 
 
-def c4_shapes(batch=4096, seed=4096, m_range=(256, 4096), n_range=(64, 1024),
+def ragged_shapes(batch=4096, seed=4096, m_range=(256, 4096), n_range=(64, 1024),
               k_max=64):
-    """Ragged shapes and decay exponents of the C4 batch (numpy arrays)."""
+    """Ragged shapes and decay exponents of the 4096-matrix batch (numpy arrays)."""
     rng = np.random.default_rng(seed)
     m = rng.integers(m_range[0], m_range[1] + 1, size=batch)
     n = rng.integers(n_range[0], n_range[1] + 1, size=batch)
@@ -174,9 +178,9 @@ def c4_shapes(batch=4096, seed=4096, m_range=(256, 4096), n_range=(64, 1024),
     return m, n, k, alpha
 
 
-def c4_batch(batch=4096, seed=4096, **shape_kw):
+def ragged_batch(batch=4096, seed=4096, **shape_kw):
     """Ragged batch: list of (A float64 numpy, k, alpha).  CPU; small batches."""
-    m, n, k, alpha = c4_shapes(batch, seed, **shape_kw)
+    m, n, k, alpha = ragged_shapes(batch, seed, **shape_kw)
     out = []
     for b in range(batch):
         r = int(min(m[b], n[b]))
@@ -207,8 +211,8 @@ def _haar_torch(rows, r, g, device):
     return Q
 
 
-def c4_torch(device="cuda", batch=4096, seed=4096, out_dtype=None, **shape_kw):
-    """C4 batch on a torch device: A_b = U_b diag(i^-alpha_b) V_b^T with Haar
+def ragged_torch(device="cuda", batch=4096, seed=4096, out_dtype=None, **shape_kw):
+    """The 4096-matrix ragged batch on a torch device: A_b = U_b diag(i^-alpha_b) V_b^T with Haar
     U_b, V_b over all min(m_b, n_b) values, rounded once to ``out_dtype``
     (default float32) into one ragged buffer.
 
@@ -216,7 +220,7 @@ def c4_torch(device="cuda", batch=4096, seed=4096, out_dtype=None, **shape_kw):
     """
     import torch
     out_dtype = out_dtype or torch.float32
-    m, n, k, alpha = c4_shapes(batch, seed, **shape_kw)
+    m, n, k, alpha = ragged_shapes(batch, seed, **shape_kw)
     sizes = (m.astype(np.int64) * n.astype(np.int64))
     offs = np.concatenate([[0], np.cumsum(sizes)])
     buf = torch.empty(int(offs[-1]), dtype=out_dtype, device=device)

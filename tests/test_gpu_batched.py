@@ -169,12 +169,12 @@ def test_batch_invalid_arguments():
 
 
 def test_c4_full_batch_sampled_against_oracle():
-    """The full 4096-matrix C4 batch in the benchmark's launch configuration
+    """The full 4096-matrix ragged batch in the benchmark's launch configuration
     (f32, p=10, q=2, one captured graph); a sample of solves is checked against
     the oracle on the stored instances."""
     from paper_1608_02148_amd import api
-    c = syn.CONFIGS["c4"]
-    data = syn.c4_torch(device=DEV, batch=c["batch"], seed=c["gen_seed"])
+    c = syn.CONFIGS["ragged_4096"]
+    data = syn.ragged_torch(device=DEV, batch=c["batch"], seed=c["gen_seed"])
     ks = [int(x) for x in data["k"]]
     bt = api.Batch(data["A"], ks, p=c["p"], q=c["q"], seed=c["omega_seed"], graph=True)
     bt.run()

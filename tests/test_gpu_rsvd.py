@@ -64,9 +64,9 @@ def run_both(A_np, k, p, q, seed, dtype, sdist="normal", stream_id=0):
 
 
 def test_c1_fp64_parity():
-    """C1: 2000 x 1000 f64, sigma_i = 1/i, k=20, p=10, q=2, Omega seed 2148."""
-    c = syn.CONFIGS["c1"]
-    A = syn.c1_matrix()
+    """2000 x 1000 f64, sigma_i = 1/i, k=20, p=10, q=2, Omega seed 2148."""
+    c = syn.CONFIGS["harmonic_2000x1000"]
+    A = syn.harmonic_2000x1000()
     A_inst, (U, s, V), (Uo, so, Vo) = run_both(A, c["k"], c["p"], c["q"], c["omega_seed"], torch.float64)
     _check_sigma(s, so, torch.float64)
     np.testing.assert_allclose(U, Uo, atol=1e-9)

@@ -9,7 +9,7 @@ with the oracle's where the gap to the neighbours exceeds 1e-3 sigma_1.
 Orthonormality of the f64 factors: U's columns come from J_i = R_b^T w_i /
 sigma_i, accurate to about l u sigma_1 / sigma_i, so U^T U = I is checked to
 4 l u sigma_1 / sigma_k (1e-11 at sigma_1 / sigma_k = 236, l = 256; the narrow
-path's C1 test, l = 30 and sigma_1 / sigma_k = 20, is the same bound).
+path's 2000 x 1000 f64 test, l = 30 and sigma_1 / sigma_k = 20, is the same bound).
 """
 import numpy as np
 import pytest
@@ -71,7 +71,7 @@ def test_wide_sketch_f32_arithmetic(dtype):
 
 
 def test_wide_sketch_bf16_mixed():
-    """C3's shape of problem at small size: bf16 storage, k = 200, p = 20."""
+    """The 200000 x 20000 bf16 workload's shape of problem at small size: bf16 storage, k = 200, p = 20."""
     from paper_1608_02148_amd import api
     m, n, k, p, q = 6000, 1000, 200, 20, 2
     A = syn.planted(m, n, syn.spectrum("poly", min(m, n), alpha=1.5), 5)

@@ -164,7 +164,7 @@ def test_power_iterations_reduce_the_error():
 
 
 def test_c1_planted_reference_values():
-    A = syn.c1_matrix()
+    A = syn.harmonic_2000x1000()
     sig = 1.0 / np.arange(1, 1001)
     s_full = np.linalg.svd(A, compute_uv=False)
     np.testing.assert_allclose(s_full, sig, rtol=1e-11)
