@@ -358,7 +358,7 @@ int rsvd_profile_collect(rsvd_handle_t handle, rsvd_kernel_stat* out);
 int rsvd_philox_words(rsvd_handle_t handle, int64_t n, int32_t groups,
                       uint64_t seed, uint32_t stream_id, uint32_t* out);
 
-/* The random test matrix Omega (n x l, row-major, ld = ldo) of Alg. rqb step 2
+/* The random test matrix Omega (n x l, row-major, ld = ldo) of Alg. rqb
  * in f64 (dtype RSVD_F64) or f32 (otherwise), entries per rsvd_sdist. */
 int rsvd_test_matrix(rsvd_handle_t handle, int32_t dtype, int64_t n, int32_t l,
                      uint64_t seed, uint32_t stream_id, int32_t sdist,
@@ -373,7 +373,7 @@ int rsvd_test_matrix(rsvd_handle_t handle, int32_t dtype, int64_t n, int32_t l,
 #define RSVD_ARITH_BF16    1
 #define RSVD_ARITH_SPLIT   2
 
-/* Y = A X (Alg. rqb step 3, Alg. subspace_iter step 4): A m x K (dtype,
+/* Y = A X (Alg. rqb, Alg. subspace_iter): A m x K (dtype,
  * lda), X K x c (f64 for RSVD_F64 else f32, ldx), Y m x c (same type as X,
  * ldy).  c <= RSVD_MAX_L_SINGLE.  work: ignored (may be NULL) for
  * RSVD_ARITH_STORAGE; the bf16 arithmetics pack X into bf16 there and need
@@ -383,7 +383,7 @@ int rsvd_gemm_nn(rsvd_handle_t handle, int32_t dtype, int32_t arith, int64_t m, 
                  const void* A, int64_t lda, const void* X, int64_t ldx,
                  void* Y, int64_t ldy, void* work, size_t work_bytes);
 
-/* Z = A^T Q (Alg. subspace_iter step 3; Alg. rqb step 10 gives B^T): A m x n
+/* Z = A^T Q (Alg. subspace_iter; Alg. rqb gives B^T): A m x n
  * (dtype, lda), Q m x c (f64/f32, ldq), Z n x c (ldz).  c <= RSVD_MAX_L_SINGLE. */
 int rsvd_gemm_tn(rsvd_handle_t handle, int32_t dtype, int32_t arith, int64_t m, int64_t n, int32_t c,
                  const void* A, int64_t lda, const void* Q, int64_t ldq,

@@ -6,7 +6,7 @@ The paper leaves q and p to the user: p = 10 and q = 2 are its defaults
 picks the cheapest pair that reaches the accuracy target:
 
 * Sketch: l0 = max(2k, k + 20), clamped to min(m, n) and to 128;
-  Y0 = A Omega[:, :l0] with the solve's own test matrix (Alg. rqb steps 1-3,
+  Y0 = A Omega[:, :l0] with the solve's own test matrix (Alg. rqb,
   same seed and stream, so Omega[:, :l] of the later solve is a prefix).
 * Features (131): the singular values of Y0 divided by the largest, in
   descending order, zero-padded to 128; then log2(m)/12, log2(n)/12,
@@ -54,7 +54,7 @@ def sketch_width0(m, n, k):
 
 
 def sketch(A, k, seed=0, stream_id=0, sdist="normal"):
-    """Y0 = A Omega[:, :l0] (Alg. rqb step 3 at q = 0)."""
+    """Y0 = A Omega[:, :l0] (Alg. rqb at q = 0)."""
     m, n = A.shape
     l0 = sketch_width0(m, n, k)
     Om = philox.test_matrix(n, l0, seed, stream_id, sdist)

@@ -1,7 +1,7 @@
 """Counter-based random test matrices for the oracle (TEST INFRASTRUCTURE ONLY).
 
 The paper's default test matrix has i.i.d. standard normal entries (Sec. 2.3,
-"Random test matrices"; Alg. rqb step 2 draws it with ``rnorm(n, l)``); uniform
+"Random test matrices"; Alg. rqb draws it with ``rnorm(n, l)``); uniform
 U(-1,1) and Rademacher entries are the two alternatives of the same section.
 R's own random stream cannot be reproduced, so the entries here come from a
 counter-based generator that any implementation can evaluate independently:
@@ -108,7 +108,7 @@ def box_muller(u0, u1):
 
 
 def test_matrix(n, l, seed, stream_id=0, sdist="normal"):
-    """The n x l random test matrix Omega of Alg. rqb step 2 (float64)."""
+    """The n x l random test matrix Omega of Alg. rqb (float64)."""
     w = raw_words(n, l, seed, stream_id)
     if sdist == "normal":
         u = uniforms(w)

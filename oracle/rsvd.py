@@ -16,7 +16,7 @@ Readings where the paper is silent (each listed in the design notes):
 * QR: thin Householder QR (LAPACK via numpy) with the signs fixed so that
   R has a non-negative diagonal.
 * k + p larger than min(m, n): l is clamped to min(m, n).
-* Omega is always n x l, whatever the aspect ratio (Alg. rqb step 2).
+* Omega is always n x l, whatever the aspect ratio (Alg. rqb).
 * Sign of singular vector pairs: (u_i, v_i) is flipped together so that the
   entry of v_i with the largest magnitude is positive (lowest index on ties).
 * rPCA divides by m - 1 whether or not the data were centred; x = U S.
@@ -39,7 +39,7 @@ def check_args(m, n, k, p, q):
 
 
 def sketch_width(m, n, k, p):
-    """l = k + p (Alg. rqb step 1), clamped to min(m, n)."""
+    """l = k + p (Alg. rqb), clamped to min(m, n)."""
     return min(k + p, min(m, n))
 
 

@@ -1,9 +1,9 @@
 // Tall-skinny products with the input matrix A on the matrix cores.
 //
-//   NN:  Y = A X    (A m x K row-major, X K x c)   Alg. rqb step 3 and
-//                                                  Alg. subspace_iter step 4
-//   TN:  Z = A^T Q  (A K x n row-major, Q K x c)   Alg. subspace_iter step 3
-//                                                  and Alg. rqb step 10 (B^T)
+//   NN:  Y = A X    (A m x K row-major, X K x c)   Alg. rqb and
+//                                                  Alg. subspace_iter
+//   TN:  Z = A^T Q  (A K x n row-major, Q K x c)   Alg. subspace_iter
+//                                                  and Alg. rqb (B^T)
 //
 // Both share one tile engine.  A workgroup owns a BM x NC block of the output
 // and walks the reduction dimension k in steps of BK.  Lane (i, g) of a

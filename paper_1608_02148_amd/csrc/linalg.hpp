@@ -1,13 +1,13 @@
 // Small dense kernels around the products with A:
 //   - deterministic split-K reduction of partial blocks,
 //   - column means of A (implicit centring for PCA, Sec. 4.2),
-//   - the test matrix Omega (Alg. rqb step 2),
+//   - the test matrix Omega (Alg. rqb),
 //   - Cholesky of a Gram matrix and the inverse of its factor (the economic
-//     QR of Alg. rqb step 9 and Alg. subspace_iter steps 2-3, done as
+//     QR of Alg. rqb and Alg. subspace_iter, done as
 //     CholeskyQR2, with a shifted first pass when the Gram matrix is too
 //     ill-conditioned, Fukaya et al., SIAM J. Sci. Comput. 42, 2020),
 //   - one-sided (Hestenes) Jacobi SVD of the small triangular factor of B^T
-//     (the deterministic svd(B) of Alg. RSVDalgorithm step 2),
+//     (the deterministic svd(B) of Alg. RSVDalgorithm),
 //   - the sign convention and the lift matrices for U = Q U~ (Eq. UQU),
 //   - the final copies (singular values, PCA eigenvalues, info record).
 #pragma once

@@ -1,4 +1,4 @@
-// Counter-based test-matrix entries for Alg. rqb step 2 (Sec. 2.3).
+// Counter-based test-matrix entries for Alg. rqb (Sec. 2.3).
 //
 // Philox-4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11): per round the counter
 // words 0 and 2 are multiplied by two fixed odd constants, and the high / low

@@ -160,7 +160,7 @@ hipError_t solve_steps(Ex& ex, rsvd_handle_t prof, const Plan& P, const TA* A, i
         RSVD_TRY(ex.template run<ColmeanBody>(ColmeanBody::Args{mp, S, m, n, mu}));
     }
 
-    // Alg. rqb steps 2-3: Omega and the sketch Y = A Omega (unless a wider
+    // Alg. rqb: Omega and the sketch Y = A Omega (unless a wider
     // sketch under the same seed and stream already holds it in its leading
     // l columns: Omega's entries do not depend on l).
     if (!o.y0)
@@ -240,7 +240,7 @@ hipError_t solve_steps(Ex& ex, rsvd_handle_t prof, const Plan& P, const TA* A, i
                                     true, act, cholx, qtmp));
         RSVD_TRY(ax_step(Z, it == P.q - 1, run_bit, last_bit));
     }
-    // Alg. rqb steps 9-10: Q = qr(Y); B^T = A^T Q.
+    // Alg. rqb: Q = qr(Y); B^T = A^T Q.
     RSVD_TRY(orthonormalize<TC>(ex, tile, Y, Lp, m, l, Lp, P.sp.gram_m, partd, gram, rinv, nullptr, status, false,
                                 Gate{}, cholx, qtmp));
     RSVD_TRY(aty(Z, late, Gate{}));
