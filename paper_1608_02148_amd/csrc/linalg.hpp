@@ -277,10 +277,16 @@ __device__ __forceinline__ void chol_body(const CholArgs& a) {
     auto from_lane = [&](double v, int src) { return __shfl(v, src, CT_TX); };
 
     load(0.0);
-    if (tid == 0) {
-        double tr = 0.0;
-        for (int j = 0; j < l; ++j) tr += diag0[j];
-        s_trace = tr;
+    {   // trace of G: the first wave (or the whole workgroup when smaller)
+        // sums strided entries, then a butterfly over its lanes
+        constexpr int W = NT < 64 ? NT : 64;
+        if (tid < W) {
+            double tr = 0.0;
+            for (int j = tid; j < l; j += W) tr += diag0[j];
+#pragma unroll
+            for (int off = W / 2; off > 0; off >>= 1) tr += __shfl_xor(tr, off, W);
+            if (tid == 0) s_trace = tr;
+        }
     }
     __syncthreads();
     const double trace = s_trace;
