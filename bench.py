@@ -9,9 +9,17 @@ Metric: rSVD TFLOP/s = (2q+2) * 2 m n l / time per solve.
 Also reported:
   roofline      -- the dominant product kernel, timed with HIP events on the
                    library's stream inside the timed region;
-  excess_err    -- ||A - U S V^T||_2 / sigma_{k+1} - 1 of the last solve;
+  whole_solve   -- the solve time against max(flops / MFMA peak, bytes / HBM
+                   peak) of its (2q+2) passes;
+  excess_err    -- ||A - U S V^T||_2 / sigma_{k+1}(A) - 1 of the timed solve
+                   (spectral; also the Frobenius analogue), with sigma_{k+1}
+                   and the residual norm from float64 block Krylov iterations
+                   on the stored instance;
   cpu_baseline  -- the FP64 oracle on the host cores (same matrix, repeated
-                   for about 10 s);
+                   for about 10 s), and the GPU's singular values and vectors
+                   against the oracle's (sigma_err_vs_oracle);
+  rpca          -- randomized PCA of the same matrix plus column offsets
+                   (implicit centring), against the oracle's explicit centring;
   bf16_mixed    -- the same workload in the bf16 mixed-precision mode;
   batched       -- 4096 ragged f32 matrices (m in [256, 4096], n in
                    [64, 1024], k in [8, 64], p=10, q=2, sigma_i = i^-alpha)
@@ -67,48 +75,177 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def excess_error(A, U, S, V, sigma_next, iters=40, seed=0):
-    """Spectral norm of A - U diag(S) V^T by power iteration, relative to sigma_{k+1}."""
+def _orth_cpu(W):
+    """Orthonormal basis of the columns of W (host Householder QR, float64)."""
+    import numpy as np
     import torch
-    g = torch.Generator(device=A.device)
+    q, _ = np.linalg.qr(W.cpu().numpy())
+    return torch.from_numpy(q).to(W.device)
+
+
+def block_krylov_svals(op, opT, n, device, block, iters, seed=0):
+    """Ritz values of a linear operator from a block Krylov space.
+
+    Starting block X (n x block, Gaussian), basis K = orth[X, (op^T op) X, ...,
+    (op^T op)^iters X] with every new block re-orthogonalised twice against
+    the previous ones; returns the singular values of op K (descending, from
+    the eigenvalues of its Gram matrix in float64).  They are lower bounds of
+    the operator's leading singular values and converge far faster than a
+    single-vector power iteration when the leading values are clustered."""
+    import numpy as np
+    import torch
+    g = torch.Generator(device=device)
     g.manual_seed(seed)
-    Af = A.float()
-    s = S.float()
-    x = torch.randn(A.shape[1], 1, device=A.device, generator=g)
-    x /= x.norm()
-    est = 0.0
+    Q = _orth_cpu(torch.randn(n, block, generator=g, device=device, dtype=torch.float64))
+    basis = [Q]
     for _ in range(iters):
-        y = Af @ x - U @ (s[:, None] * (V.t() @ x))
-        z = Af.t() @ y - V @ (s[:, None] * (U.t() @ y))
-        est = math.sqrt(float(z.norm()))
-        x = z / z.norm()
-    return est / sigma_next - 1.0
+        W = opT(op(Q))
+        for _ in range(2):
+            for B in basis:
+                W -= B @ (B.t() @ W)
+        Q = _orth_cpu(W)
+        basis.append(Q)
+    K = _orth_cpu(torch.cat(basis, 1))
+    Y = op(K)
+    ev = np.linalg.eigvalsh((Y.t() @ Y).cpu().numpy())
+    return np.sqrt(np.maximum(ev[::-1], 0.0))
+
+
+def residual_norms(A64, U, S, V):
+    """Spectral norm (block Krylov) and Frobenius norm of A - U diag(S) V^T in float64."""
+    import torch
+    U64, V64, S64 = U.double(), V.double(), S.double()
+
+    def op(x):
+        return A64 @ x - U64 @ (S64[:, None] * (V64.t() @ x))
+
+    def opT(y):
+        return A64.t() @ y - V64 @ (S64[:, None] * (U64.t() @ y))
+
+    spec = float(block_krylov_svals(op, opT, A64.shape[1], A64.device, 32, 12)[0])
+    fro2 = 0.0
+    for r0 in range(0, A64.shape[0], 16384):
+        blk = A64[r0:r0 + 16384] - (U64[r0:r0 + 16384] * S64[None, :]) @ V64.t()
+        fro2 += float((blk * blk).sum())
+    del U64, V64
+    torch.cuda.empty_cache()
+    return spec, fro2 ** 0.5
+
+
+def optimum(A64, k, block=160, iters=4):
+    """Eckart-Young optimum of the stored instance: sigma_{k+1}(A) from block
+    Krylov Ritz values (float64), and the Frobenius optimum
+    sqrt(||A||_F^2 - sum_{i<=k} sigma_i^2)."""
+    s = block_krylov_svals(lambda x: A64 @ x, lambda y: A64.t() @ y, A64.shape[1], A64.device, block, iters)
+    fro2 = float((A64 * A64).sum())
+    return float(s[k]), max(fro2 - float((s[:k] ** 2).sum()), 0.0) ** 0.5, s
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(A, k, p, q, seed, rows):
-    """Time the FP64 oracle on the first ``rows`` rows of A (host cores)."""
+    """Time the FP64 oracle on the first ``rows`` rows of A (host cores).
+
+    Returns the baseline record and the oracle's factors of the last solve."""
     import numpy as np
     from threadpoolctl import threadpool_info
 
     from oracle import rsvd as orc
     sample = A[:rows].double().cpu().numpy()
     n = sample.shape[1]
-    reps = 0
+    times = []
     t0 = time.perf_counter()
     while True:            # repeat the solve until about 10 s of host work
-        orc.rsvd(sample, k, p=p, q=q, seed=seed)
-        reps += 1
-        if time.perf_counter() - t0 >= 10.0 or reps >= 20:
+        t = time.perf_counter()
+        res = orc.rsvd(sample, k, p=p, q=q, seed=seed)
+        times.append(time.perf_counter() - t)
+        if time.perf_counter() - t0 >= 10.0 or len(times) >= 20:
             break
-    dt = (time.perf_counter() - t0) / reps
+    med, mean = float(np.median(times)), float(np.mean(times))
     l = min(k + p, rows, n)
     flops = (2 * q + 2) * 2.0 * rows * n * l
     threads = max([t.get("num_threads", 1) for t in threadpool_info() if t.get("user_api") == "blas"] or [1])
-    del np
-    return dict(value=flops / dt / 1e12, unit="TFLOP/s", cores=int(threads), kind="oracle",
-                seconds=dt * reps,
-                sample=f"first {rows} of {A.shape[0]} rows, n={n}, k={k}, p={p}, q={q}, float64 numpy oracle, "
-                       f"mean of {reps} solves")
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        nproc = os.cpu_count()
+    rec = dict(value=flops / med / 1e12, unit="TFLOP/s", cores=int(threads), kind="oracle",
+               seconds=float(np.sum(times)), median_s=med, mean_s=mean, nproc=nproc, cpu_model=cpu_model(),
+               sample=f"first {rows} of {A.shape[0]} rows, n={n}, k={k}, p={p}, q={q}, float64 numpy oracle, "
+                      f"median of {len(times)} solves (BLAS threads = cores)")
+    del sample
+    return rec, res
+
+
+def compare_with_oracle(U, S, V, ora):
+    """Singular values and vectors of the GPU solve against the oracle's
+    (same matrix, same seed): normwise max |ds_i| / s_1, elementwise max
+    |ds_i| / s_i where s_i >= 1e-3 s_1, and the smallest |<u_i, u_i^ora>|,
+    |<v_i, v_i^ora>| over the values separated from their neighbours by more
+    than 1e-3 s_1."""
+    import numpy as np
+    Uo, so, Vo = ora
+    s = S.double().cpu().numpy()
+    d = np.abs(s - so)
+    big = so >= 1e-3 * so[0]
+    Un, Vn = U.double().cpu().numpy(), V.double().cpu().numpy()
+    cos = []
+    for i in range(len(so)):
+        lo = abs(so[i] - so[i + 1]) if i + 1 < len(so) else so[i]
+        hi = abs(so[i - 1] - so[i]) if i > 0 else so[i]
+        if min(lo, hi) > 1e-3 * so[0]:
+            cos.append(min(abs(float(Un[:, i] @ Uo[:, i])), abs(float(Vn[:, i] @ Vo[:, i]))))
+    return {"sigma_normwise": float(d.max() / so[0]), "sigma_rel_max": float((d[big] / so[big]).max()),
+            "vec_min_abs_cos": float(min(cos)) if cos else None, "vec_compared": len(cos)}
+
+
+def pca_arm(A, k, p, q, seed, steps, warmup, with_oracle=True):
+    """Randomized PCA of X = A + 1 mu^T (column offsets mu_j ~ N(0,1) sigma_1 /
+    sqrt(m)) with implicit centring, f32: time per solve and, against the FP64
+    oracle's explicitly centred PCA of the same X, the normwise and leading
+    relative error of sdev = sqrt(eigvals)."""
+    import numpy as np
+    import torch
+
+    from paper_1608_02148_amd import api
+    from synth import matrices as syn
+    m, n = A.shape
+    mu = torch.as_tensor(syn.tall_exp_offsets(n, m), dtype=torch.float32, device=A.device)
+    X = A + mu[None, :]
+    prm = api.make_params(p, q, seed)
+    work = api.workspace(api.workspace_size(X, k, prm), X.device)
+    for _ in range(warmup):
+        res = api.rpca(X, k, p=p, q=q, seed=seed, work=work)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res = api.rpca(X, k, p=p, q=q, seed=seed, work=work)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    l = min(k + p, m, n)
+    out = {"workload": f"rpca {m}x{n} f32 k={k} p={p} q={q}, the rsvd matrix plus column offsets "
+                       f"mu_j ~ N(0,1) sigma_1/sqrt(m), implicit centring",
+           "ms_per_step": round(ms, 4), "tflops": round((2 * q + 2) * 2.0 * m * n * l / (ms / 1e3) / 1e12, 3)}
+    if with_oracle:
+        from oracle import rsvd as orc
+        log("[rpca] oracle on the same matrix")
+        ora = orc.rpca(X.double().cpu().numpy(), k, p=p, q=q, seed=seed)
+        sd, sdo = np.sqrt(res["eigvals"].cpu().numpy()), ora["sdev"]
+        out["sdev_err_vs_oracle"] = {"normwise": float(np.max(np.abs(sd - sdo)) / sdo[0]),
+                                     "rel_leading_half": float(np.max(np.abs(sd - sdo)[: k // 2] / sdo[: k // 2]))}
+        out["center_err_vs_oracle"] = float(np.max(np.abs(res["center"].double().cpu().numpy() - ora["center"])))
+    log(f"[rpca] {out}")
+    del X, work, res
+    torch.cuda.empty_cache()
+    return out
 
 
 def batched_arm(steps, warmup, precision="plain"):
@@ -306,6 +443,7 @@ def main():
     ap.add_argument("--batched-only", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-bf16-arm", action="store_true")
+    ap.add_argument("--no-pca", action="store_true")
     ap.add_argument("--no-bf16-storage", action="store_true")
     ap.add_argument("--bf16-storage-only", action="store_true")
     ap.add_argument("--gaussian-fill", action="store_true",
@@ -390,11 +528,10 @@ def main():
         info = api.new_info(dev)
         api.rsvd(A, k, p=p, q=q, seed=args.seed, precision=precision, work=work, out=out, info=info)
         st, hinfo = api.sync_info(info)
-        U, S, V = out
-        err = excess_error(A, U, S, V, sigma_next)
         log(f"[{precision}] {ms:.3f} ms/solve; status {st} flags 0x{hinfo.flags & 0xFFFF:x} "
-            f"jacobi sweeps {hinfo.flags >> 24}; excess spectral error {err:.3e}; kernels {prof}")
-        return ms, prof, err, hinfo
+            f"jacobi sweeps {hinfo.flags >> 24}; kernels {prof}")
+        del work
+        return ms, prof, hinfo, out
 
     flops = (2 * q + 2) * 2.0 * m * n * l
 
@@ -431,21 +568,56 @@ def main():
                 "other_kernel_avg_ms": {kname: round(v["total_ms"] / max(v["count"], 1), 4)
                                         for kname, v in prof.items() if kname != dom_name}}
 
-    ms, prof, err, _ = run_arm("plain")
+    ms, prof, _, out_pl = run_arm("plain")
     tflops = flops / (ms / 1000.0) / 1e12
     roofline = roofline_of(prof, "mfma")
-    bf16_arm = None
+    # whole solve against its own roofline: (2q+2) passes of 2 m n l flops and
+    # one read of A plus the skinny operands each
+    pass_bytes = m * n * 4.0 + (m + n) * l * 4.0
+    ideal_hbm = (2 * q + 2) * pass_bytes / (PEAKS["hbm_gbs"] * 1e9)
+    ideal_f32 = max(flops / (PEAKS["f32_mfma_tflops"] * 1e12), ideal_hbm)
+    whole = {"ideal_ms": round(ideal_f32 * 1e3, 4), "bound": "mfma", "frac": round(ideal_f32 * 1e3 / ms, 4)}
+    bf16_arm, out_bf = None, None
     if not args.no_bf16_arm:
-        ms_bf, prof_bf, err_bf, _ = run_arm("bf16_mixed")
+        ms_bf, prof_bf, _, out_bf = run_arm("bf16_mixed")
         bf16_arm = {"ms_per_step": round(ms_bf, 4), "value": round(flops / (ms_bf / 1000.0) / 1e12, 3),
-                    "unit": "TFLOP/s (same algorithmic flops)", "excess_err_spectral": round(err_bf, 6),
-                    "speedup_vs_f32_plain": round(ms / ms_bf, 3), "roofline": roofline_of(prof_bf, "hbm")}
+                    "unit": "TFLOP/s (same algorithmic flops)",
+                    "speedup_vs_f32_plain": round(ms / ms_bf, 3), "roofline": roofline_of(prof_bf, "hbm"),
+                    "whole_solve": {"ideal_ms": round(ideal_hbm * 1e3, 4), "bound": "hbm",
+                                    "frac": round(ideal_hbm * 1e3 / ms_bf, 4)}}
 
-    cpu = None
+    # accuracy of the timed solves on the stored instance, in float64: the
+    # optimum sigma_{k+1}(A) and the residual norms by block Krylov
+    log("accuracy: float64 block Krylov on the stored instance")
+    A64 = A.double()
+    sig_next, fro_opt, _ = optimum(A64, k)
+    acc = {"sigma_next": sig_next, "sigma_next_planted": sigma_next, "fro_optimum": fro_opt}
+    errs = {}
+    for name, o in (("plain", out_pl), ("bf16_mixed", out_bf)):
+        if o is None:
+            continue
+        spec, fro = residual_norms(A64, *o)
+        errs[name] = {"excess_err_spectral": spec / sig_next - 1.0, "excess_err_fro": fro / fro_opt - 1.0}
+        log(f"[{name}] excess error spectral {errs[name]['excess_err_spectral']:.3e} "
+            f"frobenius {errs[name]['excess_err_fro']:.3e}")
+    del A64
+    torch.cuda.empty_cache()
+    if bf16_arm is not None:
+        bf16_arm.update({kk: round(v, 7) for kk, v in errs["bf16_mixed"].items()})
+
+    cpu, sigma_vs_oracle = None, None
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle on {args.cpu_rows} rows")
-        cpu = cpu_baseline(A, k, p, q, args.seed, min(args.cpu_rows, m))
-        log(f"cpu baseline {cpu['value']:.4f} TFLOP/s in {cpu['seconds']:.1f} s on {cpu['cores']} threads")
+        cpu, ora = cpu_baseline(A, k, p, q, args.seed, min(args.cpu_rows, m))
+        log(f"cpu baseline {cpu['value']:.4f} TFLOP/s, median {cpu['median_s']:.2f} s on {cpu['cores']} threads")
+        if min(args.cpu_rows, m) == m:
+            sigma_vs_oracle = {"plain": compare_with_oracle(*out_pl, ora)}
+            if out_bf is not None:
+                sigma_vs_oracle["bf16_mixed"] = compare_with_oracle(*out_bf, ora)
+            log(f"against the oracle: {sigma_vs_oracle}")
+    del out_pl, out_bf
+    pca = None if args.no_pca else pca_arm(A, k, p, q, args.seed, args.steps, args.warmup,
+                                           with_oracle=not args.no_cpu_baseline)
     del A
     torch.cuda.empty_cache()
     bf16_storage = None if args.no_bf16_storage else bf16_storage_arm(min(args.steps, 5), 1)
@@ -461,9 +633,14 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"rsvd {m}x{n} f32 k={k} p={p} q={q}, sigma_i=exp(-i/50) + 1e-6 noise floor",
                    "m": m, "n": n, "k": k, "p": p, "q": q, "l": l},
-        "excess_err_spectral": round(err, 6),
+        "excess_err_spectral": round(errs["plain"]["excess_err_spectral"], 7),
+        "excess_err_fro": round(errs["plain"]["excess_err_fro"], 7),
+        "accuracy_reference": acc,
+        "sigma_err_vs_oracle": sigma_vs_oracle,
         "roofline": roofline,
+        "whole_solve": whole,
         "cpu_baseline": cpu,
+        "rpca": pca,
         "bf16_mixed": bf16_arm,
         "bf16_storage": bf16_storage,
         "batched": batched,

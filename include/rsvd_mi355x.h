@@ -5,7 +5,7 @@
  * Using R" (arXiv:1608.02148).
  *   - rsvd_run  : Alg. RSVDalgorithm (Sec. 3.3) on top of Alg. rqb (Sec. 3.3)
  *                 with Alg. subspace_iter (Sec. 2.2) as the power scheme.
- *   - rpca_run  : Alg. RPCAalgorithm (Sec. 4.2), interface of Sec. 4.4, with
+ *   - rpca_run  : Alg. RPCAalgorithm (Sec. 4.2), interface of Sec. 4.3, with
  *                 the column centring applied implicitly (A is never modified).
  *
  * Conventions shared by every entry point
@@ -47,6 +47,17 @@ typedef enum { RSVD_F64 = 0, RSVD_F32 = 1, RSVD_BF16 = 2 } rsvd_dtype;
 /* Distribution of the random test matrix Omega (Sec. 2.3). */
 typedef enum { RSVD_NORMAL = 0, RSVD_UNIF = 1, RSVD_RADEMACHER = 2 } rsvd_sdist;
 
+/* Normalisation of the power iterations (Sec. 2.2).
+ * RSVD_SCHEME_QR: Alg. subspace_iter, each half-step re-orthonormalised by
+ *   QR (CholeskyQR here).
+ * RSVD_SCHEME_LU: Alg. normalized_iter, each half-step replaced by the L
+ *   factor of a pivoted LU (tournament pivoting on the device; the span, and
+ *   so the result in exact arithmetic, is the same).  Sketch widths
+ *   l <= RSVD_MAX_L; single solves only (batches return
+ *   RSVD_ERR_UNSUPPORTED).  The final basis Q = qr(Y) is orthonormal in
+ *   either scheme. */
+typedef enum { RSVD_SCHEME_QR = 0, RSVD_SCHEME_LU = 1 } rsvd_power_scheme;
+
 /* Arithmetic of the passes over A.
  * RSVD_PREC_PLAIN: products in the storage precision of A (f64 MFMA for f64,
  *   f32 MFMA for f32 and bf16).
@@ -67,7 +78,8 @@ typedef struct {
     int32_t  precision;  /* rsvd_precision                                       */
     int32_t  probes;     /* r > 0: a-posteriori error bound from r Gaussian probes
                             (rsvd_info.est_err; 0..16, default 0 = off)           */
-    int32_t  reserved[2];
+    int32_t  scheme;     /* rsvd_power_scheme (default RSVD_SCHEME_QR)           */
+    int32_t  reserved;
 } rsvd_params;
 
 /* Device-side outcome record (optional; written by the last kernel). */
@@ -89,6 +101,8 @@ typedef struct {
 #define RSVD_FLAG_DEGENERATE   2u  /* a column was numerically zero after shifting */
 #define RSVD_FLAG_NONFINITE    4u  /* NaN or Inf reached a Gram matrix             */
 #define RSVD_FLAG_JACOBI_SLOW  8u  /* small SVD stopped at its sweep limit         */
+#define RSVD_FLAG_ZERO_SCALE  16u  /* scaled PCA: a column had zero spread (its
+                                      scale was set to 1; see rpca_run_ex)       */
 /* Bits 24..31 of rsvd_info.flags hold the number of Jacobi sweeps the small SVD
  * of B took (diagnostic). */
 #define RSVD_FLAG_SWEEPS_SHIFT 24
@@ -149,7 +163,7 @@ int rsvd_run(rsvd_handle_t handle, int32_t dtype, int64_t m, int64_t n,
              void* U, int64_t ldu, double* S, void* V, int64_t ldv,
              void* work, size_t work_bytes, rsvd_info* info);
 
-/* Randomized PCA, Alg. RPCAalgorithm (Sec. 4.2) with the outputs of Sec. 4.4.
+/* Randomized PCA, Alg. RPCAalgorithm (Sec. 4.2) with the outputs of Sec. 4.3.
  * center != 0: the column means mu are removed implicitly (the products use
  *   A - 1 mu^T without forming it).  center == 0: A is used as is.
  * rotation : n x k principal directions W = V (ldr >= k), required.
@@ -162,6 +176,67 @@ int rpca_run(rsvd_handle_t handle, int32_t dtype, int64_t m, int64_t n,
              const rsvd_params* params, void* rotation, int64_t ldr,
              double* eigvals, double* sdev, void* x, int64_t ldx, void* center_out,
              void* work, size_t work_bytes, rsvd_info* info);
+
+/* Randomized PCA with the options and outputs of Sec. 4.3 and the extras of
+ * Sec. 4.1 (Alg. RPCAalgorithm on the centred and optionally scaled data).
+ * opt->center != 0: the column means mu are removed implicitly.
+ * opt->scale != 0: each (centred) column is also divided by its root mean
+ *   square about the centre with the m - 1 divisor (its standard deviation
+ *   when centring), so the analysis is that of the correlation matrix; the
+ *   division is applied to the skinny operands of the products (A is read as
+ *   is).  A column with zero spread keeps scale 1 (it contributes nothing)
+ *   and sets RSVD_FLAG_ZERO_SCALE in info->flags.
+ * Outputs (device pointers, element type as for rpca_run; NULL = not wanted
+ * unless marked required):
+ *   rotation  n x k principal directions W (ldr >= k), required;
+ *   eigvals   k values s^2 / (m - 1) (f64), required;
+ *   sdev      k values sqrt(eigvals) (f64);
+ *   x         m x k principal components U S (ldx >= k);
+ *   x_white   m x k whitened components x_i / sdev_i, each of unit variance
+ *             (Sec. 4.1; zero columns where sdev_i = 0) (ldxw >= k);
+ *   loadings  n x k loadings W diag(sdev) (Sec. 4.1) (ldl >= k);
+ *   center    n centre values (zeros without centring);
+ *   scale     n scale values (ones without scaling);
+ *   total_var one f64: the sum of the column variances of the analysed
+ *             (centred, scaled) data, so eigvals / total_var are the
+ *             explained proportions of Sec. 4.1.
+ * Workspace: rsvd_workspace_size with the same arguments.  Errors as
+ * rsvd_run. */
+typedef struct {
+    int32_t center;
+    int32_t scale;
+    int32_t reserved[2];
+} rpca_options;
+
+typedef struct {
+    void* rotation; int64_t ldr;
+    double* eigvals;
+    double* sdev;
+    void* x; int64_t ldx;
+    void* x_white; int64_t ldxw;
+    void* loadings; int64_t ldl;
+    void* center;
+    void* scale;
+    double* total_var;
+} rpca_outputs;
+
+int rpca_run_ex(rsvd_handle_t handle, int32_t dtype, int64_t m, int64_t n,
+                const void* A, int64_t lda, int32_t k, const rpca_options* opt,
+                const rsvd_params* params, const rpca_outputs* out,
+                void* work, size_t work_bytes, rsvd_info* info);
+
+/* Principal components of new observations (the predict step of Sec. 4.4):
+ * x = ((A - 1 center^T) diag(scale)^-1) rotation for A m x n (dtype, lda >=
+ * n), with rotation n x k (ldr >= k), center and scale n-vectors as returned
+ * by rpca_run_ex (element type of the outputs; NULL = no centring / no
+ * scaling), x m x k (ldx >= k).  k <= RSVD_MAX_L_SINGLE.  Storage-precision
+ * arithmetic (f64 matrix cores for f64, f32 otherwise); the centre is
+ * subtracted while A is read.  work: rpca_predict_workspace_size bytes. */
+int rpca_predict_workspace_size(rsvd_handle_t handle, int32_t dtype, int64_t m, int64_t n,
+                                int32_t k, size_t* bytes);
+int rpca_predict(rsvd_handle_t handle, int32_t dtype, int64_t m, int64_t n, const void* A,
+                 int64_t lda, int32_t k, const void* rotation, int64_t ldr, const void* center,
+                 const void* scale, void* x, int64_t ldx, void* work, size_t work_bytes);
 
 /* Synchronise the handle's stream, copy the device record `dinfo` to the host
  * record `hinfo`, and map its flags to a status: RSVD_ERR_NONFINITE when
@@ -263,8 +338,10 @@ int rsvd_select(rsvd_handle_t handle, int32_t dtype, int32_t count, const rsvd_b
  * takes three phases: (1) for every matrix the q = 0 sketch Y0 = A Omega[:, :l0]
  * (l0 as for the selector features below) and its 131 features; (2) the
  * network on all features and, per matrix, q_b = the fewest power iterations
- * whose classes (q' <= q_b, any p') hold at least tau of the network's
- * probability mass (tau <= 0: the q of the most probable class); theta = NULL
+ * whose classes (q' <= q_b, p' <= params->p: the pairs a solve with q_b
+ * iterations and oversampling params->p covers) hold at least tau of the
+ * network's probability mass, RSVD_LEARNED_QMAX when no q_b does (tau <= 0:
+ * the q of the most probable class); theta = NULL
  * skips the network and takes q_b = RSVD_LEARNED_FALLBACK_Q for every matrix;
  * (3) every solve with its own q_b (<= RSVD_LEARNED_QMAX; the extra
  * iterations of its group are switched off on the device) and p = params->p
@@ -328,6 +405,31 @@ int rsvd_mlp_train_step(rsvd_handle_t handle, float* theta, float* adam_m, float
                         const int32_t* labels, float* grad, float* loss,
                         void* work, size_t work_bytes);
 
+/* Selector checkpoint file (what the training driver writes): a 64-byte
+ * little-endian header -- magic "RSVDMLP1", u32 format version (1), u32
+ * parameter count (RSVD_MLP_PARAMS), u32 Adam step, u64 seed, u64 size of the
+ * training set, 8 bytes of a digest of the training data, zero padding --
+ * then theta, adam_m and adam_v as RSVD_MLP_PARAMS float32 each. */
+typedef struct {
+    uint32_t version, params, step, reserved;
+    uint64_t seed, n_train;
+    uint8_t  digest[8];
+} rsvd_mlp_header;
+
+/* Read a selector checkpoint from the host file `path` into the device
+ * vectors theta and, when not NULL, adam_m and adam_v (RSVD_MLP_PARAMS floats
+ * each, caller-owned); header (host, may be NULL) receives the header fields.
+ * The file is checked in full before anything is written to the device:
+ * RSVD_ERR_INVALID when an argument is NULL, the file cannot be opened, its
+ * size is not 64 + 3 * 4 * RSVD_MLP_PARAMS bytes, or any stored value is not
+ * finite; RSVD_ERR_UNSUPPORTED for a wrong magic, format version or
+ * parameter count.  theta = NULL (then adam_m and adam_v NULL too) only
+ * checks the file and fills header, with no device access.  Otherwise
+ * synchronises the handle's stream (the copies are done when the call
+ * returns). */
+int rsvd_mlp_load(rsvd_handle_t handle, const char* path, float* theta, float* adam_m,
+                  float* adam_v, rsvd_mlp_header* header);
+
 /* ---- Optional per-kernel timing ------------------------------------------
  * When enabled, every product with A (the passes of Alg. rqb and
  * Alg. subspace_iter) is bracketed by HIP events on the handle's stream, so a
@@ -375,13 +477,18 @@ int rsvd_test_matrix(rsvd_handle_t handle, int32_t dtype, int64_t n, int32_t l,
 
 /* Y = A X (Alg. rqb, Alg. subspace_iter): A m x K (dtype,
  * lda), X K x c (f64 for RSVD_F64 else f32, ldx), Y m x c (same type as X,
- * ldy).  c <= RSVD_MAX_L_SINGLE.  work: ignored (may be NULL) for
- * RSVD_ARITH_STORAGE; the bf16 arithmetics pack X into bf16 there and need
- * rsvd_block_workspace_size(dtype, m, K, c) bytes (RSVD_ERR_INVALID
- * otherwise). */
+ * ldy).  c <= RSVD_MAX_L_SINGLE.
+ * splits: 0 = the split of the K-reduction that rsvd_run uses for this shape;
+ * 1..4 = that many chunks of K, each product writing a partial block to the
+ * workspace, summed in chunk order (deterministic).  Other values:
+ * RSVD_ERR_INVALID.
+ * work: ignored (may be NULL) for RSVD_ARITH_STORAGE without a split; the
+ * bf16 arithmetics pack X into bf16 there and split products keep their
+ * partial blocks there, which needs rsvd_block_workspace_size(dtype, m, K, c)
+ * bytes (RSVD_ERR_INVALID otherwise). */
 int rsvd_gemm_nn(rsvd_handle_t handle, int32_t dtype, int32_t arith, int64_t m, int64_t K, int32_t c,
                  const void* A, int64_t lda, const void* X, int64_t ldx,
-                 void* Y, int64_t ldy, void* work, size_t work_bytes);
+                 void* Y, int64_t ldy, int32_t splits, void* work, size_t work_bytes);
 
 /* Z = A^T Q (Alg. subspace_iter; Alg. rqb gives B^T): A m x n
  * (dtype, lda), Q m x c (f64/f32, ldq), Z n x c (ldz).  c <= RSVD_MAX_L_SINGLE. */
@@ -401,6 +508,20 @@ int rsvd_orthonormalize(rsvd_handle_t handle, int32_t dtype, int64_t m, int32_t 
  * RSVD_MAX_L_SINGLE for the products, RSVD_MAX_L for the other two). */
 int rsvd_block_workspace_size(rsvd_handle_t handle, int32_t dtype, int64_t m,
                               int64_t n, int32_t c, size_t* bytes);
+
+/* Pivoted LU normalisation of Y (m x c, f64 or f32 per dtype, ldy) in place,
+ * the step of Alg. normalized_iter: Y = L U with L row-permuted unit lower
+ * trapezoidal (Y <- L) and U upper triangular (c x c, f64, row-major, ld c,
+ * or NULL).  piv (device int32, c entries, or NULL): the row of Y that
+ * pivots at step i, so L[piv[i]][0..i) holds the multipliers, L[piv[i]][i] = 1
+ * and L[piv[i]][i+1..c) = 0 up to rounding.  Pivot rows are chosen by
+ * tournament pivoting over blocks of 256 rows; for m <= 256 they are those of
+ * partial pivoting.  c <= RSVD_MAX_L, c <= m.  flags as for
+ * rsvd_orthonormalize (RSVD_FLAG_DEGENERATE on a zero pivot).  work:
+ * rsvd_block_workspace_size(dtype, m, m, c) bytes. */
+int rsvd_lu_normalize(rsvd_handle_t handle, int32_t dtype, int64_t m, int32_t c, void* Y,
+                      int64_t ldy, int32_t* piv, double* U, uint32_t* flags, void* work,
+                      size_t work_bytes);
 
 /* SVD of a small square upper-triangular R (c x c, f64, row-major, ld c):
  * R = W diag(s) J^T with s descending.  W and J are c x c (f64, row-major,

@@ -6,6 +6,8 @@ Follows Erichson et al., arXiv:1608.02148, step by step:
   Y = sub_iterations(A, Y, q); Q = qr(Y); B = Q^T A.
 * Alg. subspace_iter (Sec. 2.2, "Power iteration scheme"): q times
   Q = qr(Y); Q = qr(A^T Q); Y = A Q.
+* Alg. normalized_iter (Sec. 2.2): the same with the pivoted LU factor L in
+  place of Q (L = lu(Y); L = lu(A^T L); Y = A L).
 * Alg. RSVDalgorithm (Sec. 3.3): [U~, S, V] = svd(B); U = Q U~; keep the
   first k columns / values.
 * Alg. RPCAalgorithm (Sec. 4.2): run the randomized SVD on the column-centred
@@ -15,6 +17,8 @@ Readings where the paper is silent (each listed in the design notes):
 
 * QR: thin Householder QR (LAPACK via numpy) with the signs fixed so that
   R has a non-negative diagonal.
+* Pivoted LU: partial row pivoting (LAPACK via scipy); L is the row-permuted
+  unit lower trapezoidal factor, Y = L U (the two-output form of lu).
 * k + p larger than min(m, n): l is clamped to min(m, n).
 * Omega is always n x l, whatever the aspect ratio (Alg. rqb).
 * Sign of singular vector pairs: (u_i, v_i) is flipped together so that the
@@ -60,6 +64,29 @@ def sub_iterations(A, Y, q):
     return Y
 
 
+def lu_factor(Y):
+    """Pivoted LU of the paper's normalized power iterations: partial (row)
+    pivoting, Y = L U with L the row-permuted unit lower trapezoidal factor
+    (m x l) and U upper triangular (l x l).  Returns (L, U, piv), piv[i] the
+    row of Y chosen at step i (so L[piv] is unit lower triangular)."""
+    import scipy.linalg
+    P, Lt, U = scipy.linalg.lu(Y)              # Y = P Lt U
+    piv = np.argmax(P[:, :Y.shape[1]], axis=0)  # step i takes row piv[i] of Y
+    return P @ Lt, U, piv
+
+
+def norm_iterations(A, Y, q):
+    """Alg. normalized_iter: q power iterations normalised by pivoted LU
+    (Rokhlin, Szlam & Tygert 2009): L = lu(Y); L = lu(A^T L); Y = A L.
+    L spans the same space as the matrix it factors, so the result matches
+    Alg. subspace_iter in exact arithmetic."""
+    for _ in range(q):
+        L, _, _ = lu_factor(Y)
+        L, _, _ = lu_factor(A.T @ L)
+        Y = A @ L
+    return Y
+
+
 def power_iterations(A, Y, q):
     """Alg. poweriter_direct: the direct power scheme, no re-orthonormalisation.
 
@@ -72,15 +99,17 @@ def power_iterations(A, Y, q):
     return Y
 
 
-def rqb(A, k, p=10, q=2, seed=0, stream_id=0, sdist="normal"):
-    """Alg. rqb: randomized QB decomposition.  Returns (Q, B, Omega)."""
+def rqb(A, k, p=10, q=2, seed=0, stream_id=0, sdist="normal", scheme="qr"):
+    """Alg. rqb: randomized QB decomposition.  Returns (Q, B, Omega).
+
+    scheme: "qr" (Alg. subspace_iter) or "lu" (Alg. normalized_iter)."""
     A = np.asarray(A, dtype=np.float64)
     m, n = A.shape
     check_args(m, n, k, p, q)
     l = sketch_width(m, n, k, p)
     omega = philox.test_matrix(n, l, seed, stream_id, sdist)
     Y = A @ omega
-    Y = sub_iterations(A, Y, q)
+    Y = norm_iterations(A, Y, q) if scheme == "lu" else sub_iterations(A, Y, q)
     Q, _ = hqr(Y)
     B = Q.T @ A
     return Q, B, omega
@@ -94,13 +123,14 @@ def sign_rule(U, V):
     return U * s[None, :], V * s[None, :]
 
 
-def rsvd(A, k, p=10, q=2, seed=0, stream_id=0, sdist="normal", full=False):
+def rsvd(A, k, p=10, q=2, seed=0, stream_id=0, sdist="normal", full=False, scheme="qr"):
     """Alg. RSVDalgorithm.  Returns (U m x k, s k, V n x k), V not transposed.
 
     With ``full=True`` also returns a dict holding Q, B, Omega and the
-    untruncated factors for diagnostics.
+    untruncated factors for diagnostics.  scheme: normalisation of the power
+    iterations ("qr" subspace iterations, "lu" normalized iterations).
     """
-    Q, B, omega = rqb(A, k, p, q, seed, stream_id, sdist)
+    Q, B, omega = rqb(A, k, p, q, seed, stream_id, sdist, scheme)
     Ut, s, Vt = np.linalg.svd(B, full_matrices=False)
     U = Q @ Ut
     V = Vt.T
@@ -111,19 +141,58 @@ def rsvd(A, k, p=10, q=2, seed=0, stream_id=0, sdist="normal", full=False):
     return Uk, sk, Vk
 
 
-def rpca(A, k, p=10, q=2, center=True, seed=0, stream_id=0, sdist="normal"):
-    """Alg. RPCAalgorithm with explicit centring (Sec. 4.2 and 4.4).
+def column_scales(A, c):
+    """Column scalings of Sec. 4.3's scale option: the root mean square of
+    each column about c (the column means when centring, else zero) with the
+    m - 1 divisor, i.e. the column standard deviation when centring.  A zero
+    scale (a constant column) is replaced by 1: the column then stays zero
+    after centring instead of dividing by zero."""
+    A = np.asarray(A, dtype=np.float64)
+    d = A - c[None, :]
+    s = np.sqrt(np.sum(d * d, axis=0) / (A.shape[0] - 1))
+    zero = s == 0
+    s[zero] = 1.0
+    return s, zero
 
-    Returns a dict with rotation (n x k), eigvals, sdev, x (m x k), center.
+
+def rpca(A, k, p=10, q=2, center=True, seed=0, stream_id=0, sdist="normal", scale=False):
+    """Alg. RPCAalgorithm with explicit centring and scaling (Sec. 4.2 and 4.3).
+
+    The data are X = (A - 1 mu^T) D^-1 with mu the column means (center) and
+    D the column scalings (scale, see column_scales; identity otherwise),
+    formed explicitly.  Returns a dict with rotation (n x k), eigvals = s^2 /
+    (m - 1), sdev, x = U S (m x k), center, scale (ones when not scaling),
+    loadings = rotation diag(sdev) and x_white = x diag(1 / sdev) (the
+    whitened components, Sec. 4.1; zero where sdev = 0), and total_var, the
+    sum of the column variances of X (the trace of its covariance, so that
+    eigvals / total_var are the explained proportions of Sec. 4.1).
     """
     A = np.asarray(A, dtype=np.float64)
     m, n = A.shape
     mu = A.mean(axis=0) if center else np.zeros(n)
-    X = A - mu[None, :]
+    if scale:
+        sc, zero = column_scales(A, mu)
+    else:
+        sc, zero = np.ones(n), np.zeros(n, dtype=bool)
+    X = (A - mu[None, :]) / sc[None, :]
     U, s, V = rsvd(X, k, p, q, seed, stream_id, sdist)
     eigvals = s ** 2 / (m - 1)
-    return dict(rotation=V, eigvals=eigvals, sdev=np.sqrt(eigvals),
-                x=U * s[None, :], center=mu, s=s, U=U)
+    sdev = np.sqrt(eigvals)
+    x = U * s[None, :]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        x_white = np.where(sdev[None, :] > 0, x / sdev[None, :], 0.0)
+    return dict(rotation=V, eigvals=eigvals, sdev=sdev, x=x, center=mu, s=s, U=U, scale=sc,
+                zero_scale=zero, loadings=V * sdev[None, :], x_white=x_white,
+                total_var=float(np.sum(X * X)) / (m - 1))
+
+
+def rpca_predict(model, A_new):
+    """Principal components of new rows (the predict step of Sec. 4.4): the rows are
+    centred and scaled with the model's centre and scalings, then rotated:
+    ((A_new - 1 center^T) D^-1) rotation."""
+    A_new = np.asarray(A_new, dtype=np.float64)
+    X = (A_new - model["center"][None, :]) / model["scale"][None, :]
+    return X @ model["rotation"]
 
 
 # --------------------------------------------------------------- diagnostics

@@ -51,13 +51,14 @@ def _apply_tuned_variants(lib, h, idx):
         pass
 
 
-def make_params(p=10, q=2, seed=0, stream_id=0, sdist="normal", precision="plain", probes=0):
+def make_params(p=10, q=2, seed=0, stream_id=0, sdist="normal", precision="plain", probes=0, scheme="qr"):
     prm = L.Params()
     L.load().rsvd_default_params(ctypes.byref(prm))
     prm.p, prm.q, prm.seed, prm.stream_id = int(p), int(q), int(seed), int(stream_id)
     prm.probes = int(probes)
     prm.sdist = L.SDIST[sdist]
     prm.precision = L.PRECISION[precision]
+    prm.scheme = L.SCHEME[scheme]
     return prm
 
 
@@ -93,17 +94,18 @@ def workspace(nbytes, device):
 
 
 def rsvd(A, k, p=10, q=2, seed=0, stream_id=0, sdist="normal", precision="plain",
-         compute_u=True, compute_v=True, work=None, out=None, info=None, probes=0):
+         compute_u=True, compute_v=True, work=None, out=None, info=None, probes=0, scheme="qr"):
     """Randomized SVD (Alg. RSVDalgorithm).  Returns (U m x k, S k, V n x k).
 
     U / V are None when not requested.  ``work`` (uint8 tensor) and ``out``
     (tuple U, S, V) may be passed to reuse buffers; ``info`` may be a 24-byte
     uint8 device tensor receiving the device-side record; with ``probes`` > 0
     its est_err holds the a-posteriori bound on ||A - U S V^T||_2.
+    ``scheme``: "qr" (subspace iterations) or "lu" (normalized iterations).
     """
     dt = _check_matrix(A)
     m, n = A.shape
-    prm = make_params(p, q, seed, stream_id, sdist, precision, probes)
+    prm = make_params(p, q, seed, stream_id, sdist, precision, probes, scheme)
     h = handle(A.device)
     nbytes = workspace_size(A, k, prm)
     if work is None or work.numel() < nbytes:
@@ -124,10 +126,13 @@ def rsvd(A, k, p=10, q=2, seed=0, stream_id=0, sdist="normal", precision="plain"
 
 
 def rpca(A, k, center=True, retx=True, p=10, q=2, seed=0, stream_id=0, sdist="normal",
-         precision="plain", work=None, info=None, probes=0):
-    """Randomized PCA (Alg. RPCAalgorithm) with implicit centring.
+         precision="plain", work=None, info=None, probes=0, scale=False, whiten=False, loadings=False):
+    """Randomized PCA (Alg. RPCAalgorithm) with implicit centring and, with
+    ``scale=True``, implicit scaling to unit variance (rpca_run_ex).
 
-    Returns a dict: rotation (n x k), eigvals, sdev, x (m x k or None), center.
+    Returns a dict: rotation (n x k), eigvals, sdev, x (m x k or None),
+    center, scale, total_var (0-d f64 tensor), and with ``whiten`` /
+    ``loadings`` the whitened components x_white (m x k) / loadings (n x k).
     """
     dt = _check_matrix(A)
     m, n = A.shape
@@ -137,17 +142,57 @@ def rpca(A, k, center=True, retx=True, p=10, q=2, seed=0, stream_id=0, sdist="no
     if work is None or work.numel() < nbytes:
         work = workspace(nbytes, A.device)
     od = out_dtype(A)
-    rot = torch.empty(n, k, dtype=od, device=A.device)
-    ev = torch.empty(k, dtype=torch.float64, device=A.device)
-    sd = torch.empty(k, dtype=torch.float64, device=A.device)
-    x = torch.empty(m, k, dtype=od, device=A.device) if retx else None
-    ctr = torch.empty(n, dtype=od, device=A.device)
-    st = L.load().rpca_run(h, dt, m, n, _ptr(A), A.stride(0), int(k), int(bool(center)),
-                           ctypes.byref(prm), _ptr(rot), rot.stride(0), _ptr(ev), _ptr(sd),
-                           _ptr(x), x.stride(0) if x is not None else 0, _ptr(ctr),
-                           _ptr(work), work.numel(), _ptr(info))
-    L.check(st, "rpca_run")
-    return dict(rotation=rot, eigvals=ev, sdev=sd, x=x, center=ctr)
+    dev = A.device
+    rot = torch.empty(n, k, dtype=od, device=dev)
+    ev = torch.empty(k, dtype=torch.float64, device=dev)
+    sd = torch.empty(k, dtype=torch.float64, device=dev)
+    x = torch.empty(m, k, dtype=od, device=dev) if retx else None
+    xw = torch.empty(m, k, dtype=od, device=dev) if whiten else None
+    ld = torch.empty(n, k, dtype=od, device=dev) if loadings else None
+    ctr = torch.empty(n, dtype=od, device=dev)
+    scl = torch.empty(n, dtype=od, device=dev)
+    tv = torch.empty((), dtype=torch.float64, device=dev)
+    opt = L.RpcaOptions(int(bool(center)), int(bool(scale)))
+    out = L.RpcaOutputs(_ptr(rot), rot.stride(0), _ptr(ev), _ptr(sd), _ptr(x), x.stride(0) if retx else 0,
+                        _ptr(xw), xw.stride(0) if whiten else 0, _ptr(ld), ld.stride(0) if loadings else 0,
+                        _ptr(ctr), _ptr(scl), _ptr(tv))
+    st = L.load().rpca_run_ex(h, dt, m, n, _ptr(A), A.stride(0), int(k), ctypes.byref(opt), ctypes.byref(prm),
+                              ctypes.byref(out), _ptr(work), work.numel(), _ptr(info))
+    L.check(st, "rpca_run_ex")
+    res = dict(rotation=rot, eigvals=ev, sdev=sd, x=x, center=ctr, scale=scl, total_var=tv)
+    if whiten:
+        res["x_white"] = xw
+    if loadings:
+        res["loadings"] = ld
+    return res
+
+
+def rpca_predict(A_new, res, center=True, scale=True):
+    """Principal components of new rows with a fitted rpca result ``res``
+    (rpca_predict): ((A_new - 1 center^T) / scale) rotation."""
+    dt = _check_matrix(A_new)
+    m, n = A_new.shape
+    rot = res["rotation"]
+    k = rot.shape[1]
+    nbytes = ctypes.c_size_t()
+    h = handle(A_new.device)
+    L.check(L.load().rpca_predict_workspace_size(h, dt, m, n, k, ctypes.byref(nbytes)),
+            "rpca_predict_workspace_size")
+    work = workspace(nbytes.value, A_new.device)
+    x = torch.empty(m, k, dtype=out_dtype(A_new), device=A_new.device)
+    L.check(L.load().rpca_predict(h, dt, m, n, _ptr(A_new), A_new.stride(0), k, _ptr(rot), rot.stride(0),
+                                  _ptr(res["center"]) if center else None, _ptr(res["scale"]) if scale else None,
+                                  _ptr(x), x.stride(0), _ptr(work), work.numel()), "rpca_predict")
+    return x
+
+
+def rpca_summary(res):
+    """Sec. 4.3's summary of a fitted rpca result (host arithmetic on the k
+    returned values): standard deviations, proportion of variance
+    eigvals / total_var, and its cumulative sum."""
+    ev = res["eigvals"].double().cpu()
+    prop = ev / float(res["total_var"])
+    return dict(sdev=res["sdev"].double().cpu(), proportion=prop, cumulative=torch.cumsum(prop, 0))
 
 
 _DESC_DTYPE = None
@@ -386,16 +431,19 @@ def _block_ws(dt, m, n, c, device):
     return workspace(nbytes.value, device)
 
 
-def gemm_nn(A, X, arith="storage"):
-    """Y = A X with the library's product kernel (arith: storage, bf16, split)."""
+def gemm_nn(A, X, arith="storage", splits=1):
+    """Y = A X with the library's product kernel (arith: storage, bf16, split).
+
+    splits: chunks of the K-reduction (1..4), or 0 for the split rsvd_run
+    takes at this shape."""
     dt = _check_matrix(A)
     m, K = A.shape
     c = X.shape[1]
     Y = torch.empty(m, c, dtype=out_dtype(A), device=A.device)
-    work = _block_ws(dt, m, K, c, A.device) if arith != "storage" else None
+    work = _block_ws(dt, m, K, c, A.device) if (arith != "storage" or splits != 1) else None
     L.check(L.load().rsvd_gemm_nn(handle(A.device), dt, L.ARITH[arith], m, K, c, _ptr(A), A.stride(0), _ptr(X),
-                                  X.stride(0), _ptr(Y), Y.stride(0), _ptr(work), work.numel() if work is not None
-                                  else 0), "rsvd_gemm_nn")
+                                  X.stride(0), _ptr(Y), Y.stride(0), int(splits), _ptr(work),
+                                  work.numel() if work is not None else 0), "rsvd_gemm_nn")
     return Y
 
 
@@ -422,6 +470,20 @@ def orthonormalize(Y):
     L.check(L.load().rsvd_orthonormalize(handle(Y.device), dt, m, c, _ptr(Y), Y.stride(0), _ptr(R),
                                          _ptr(flags), _ptr(work), work.numel()), "rsvd_orthonormalize")
     return Y, R, flags
+
+
+def lu_normalize(Y):
+    """In-place pivoted LU normalisation of Y (m x c): Y <- L; returns (Y, U,
+    piv, flags tensor)."""
+    dt = _check_matrix(Y)
+    m, c = Y.shape
+    U = torch.empty(c, c, dtype=torch.float64, device=Y.device)
+    piv = torch.empty(c, dtype=torch.int32, device=Y.device)
+    flags = torch.zeros(1, dtype=torch.int32, device=Y.device)
+    work = _block_ws(dt, m, m, c, Y.device)
+    L.check(L.load().rsvd_lu_normalize(handle(Y.device), dt, m, c, _ptr(Y), Y.stride(0), _ptr(piv), _ptr(U),
+                                       _ptr(flags), _ptr(work), work.numel()), "rsvd_lu_normalize")
+    return Y, U, piv, flags
 
 
 def small_svd(R):

@@ -155,6 +155,52 @@ int rpca_run(rsvd_handle_t handle, int32_t dtype, int64_t m, int64_t n, const vo
     return dispatch(handle, dtype, P, A, lda, params, o, work);
 }
 
+int rpca_run_ex(rsvd_handle_t handle, int32_t dtype, int64_t m, int64_t n, const void* A, int64_t lda,
+                int32_t k, const rpca_options* opt, const rsvd_params* params, const rpca_outputs* out,
+                void* work, size_t work_bytes, rsvd_info* info) {
+    if (!opt || !out) return RSVD_ERR_INVALID;
+    Plan P;
+    const int c = check_common(handle, dtype, m, n, A, lda, k, params, work, work_bytes, &P);
+    if (c != RSVD_OK) return c;
+    if (!out->rotation || out->ldr < k || !out->eigvals || (out->x && out->ldx < k) ||
+        (out->x_white && out->ldxw < k) || (out->loadings && out->ldl < k))
+        return RSVD_ERR_INVALID;
+    SolveOut o{};
+    o.U = out->x; o.ldu = out->ldx; o.V = out->rotation; o.ldv = out->ldr; o.S = nullptr;
+    o.eigvals = out->eigvals; o.sdev = out->sdev; o.center_out = out->center;
+    o.scale_u = 1; o.center = opt->center ? 1 : 0; o.info = info;
+    o.scale = opt->scale ? 1 : 0; o.scale_out = out->scale; o.total_var = out->total_var;
+    o.loadings = out->loadings; o.ldl = out->ldl; o.xwhite = out->x_white; o.ldxw = out->ldxw;
+    return dispatch(handle, dtype, P, A, lda, params, o, work);
+}
+
+int rpca_predict_workspace_size(rsvd_handle_t handle, int32_t dtype, int64_t m, int64_t n, int32_t k,
+                                size_t* bytes) {
+    if (!handle || !bytes || m < 1 || n < 1 || k < 1 || k > RSVD_MAX_L_SINGLE) return RSVD_ERR_INVALID;
+    if (dtype != RSVD_F64 && dtype != RSVD_F32 && dtype != RSVD_BF16) return RSVD_ERR_UNSUPPORTED;
+    *bytes = predict_plan(dtype, m, n, k, handle->dev.num_cu).bytes;
+    return RSVD_OK;
+}
+
+int rpca_predict(rsvd_handle_t handle, int32_t dtype, int64_t m, int64_t n, const void* A, int64_t lda,
+                 int32_t k, const void* rotation, int64_t ldr, const void* center, const void* scale, void* x,
+                 int64_t ldx, void* work, size_t work_bytes) {
+    if (!handle || m < 1 || n < 1 || k < 1 || k > RSVD_MAX_L_SINGLE) return RSVD_ERR_INVALID;
+    if (dtype != RSVD_F64 && dtype != RSVD_F32 && dtype != RSVD_BF16) return RSVD_ERR_UNSUPPORTED;
+    if (!A || lda < n || !rotation || ldr < k || !x || ldx < k || !work) return RSVD_ERR_INVALID;
+    if (reinterpret_cast<uintptr_t>(work) % kAlign != 0) return RSVD_ERR_INVALID;
+    const PredictPlan P = predict_plan(dtype, m, n, k, handle->dev.num_cu);
+    if (work_bytes < P.bytes) return RSVD_ERR_INVALID;
+    hipError_t e = hipErrorInvalidValue;
+    switch (dtype) {
+        case RSVD_F64: e = predict_f64(handle, P, A, lda, rotation, ldr, center, scale, x, ldx, work); break;
+        case RSVD_F32: e = predict_f32(handle, P, A, lda, rotation, ldr, center, scale, x, ldx, work); break;
+        case RSVD_BF16: e = predict_bf16(handle, P, A, lda, rotation, ldr, center, scale, x, ldx, work); break;
+        default: return RSVD_ERR_UNSUPPORTED;
+    }
+    return hip_status(handle, e);
+}
+
 int rsvd_sync_info(rsvd_handle_t handle, const rsvd_info* dinfo, rsvd_info* hinfo) {
     if (!handle || !dinfo || !hinfo) return RSVD_ERR_INVALID;
     hipError_t e = hipMemcpyAsync(hinfo, dinfo, sizeof(rsvd_info), hipMemcpyDeviceToHost, handle->stream);
@@ -327,7 +373,7 @@ inline hipError_t launch_all(const rsvd_batch_s* B, hipStream_t st) {
         unsigned char* base = static_cast<unsigned char*>(B->work);
         RSVD_TRY(launch_groups(B, B->groups0, st));
         RSVD_TRY(learned_choose_q(st, B->theta, static_cast<int>(B->desc.size()), at<float>(base, B->feat_off),
-                                  at<float>(base, B->prob_off), B->tau, kLearnedFallbackQ,
+                                  at<float>(base, B->prob_off), B->tau, B->prm.p, kLearnedFallbackQ,
                                   at<int32_t>(base, B->q_off)));
     }
     return launch_groups(B, B->groups, st);
@@ -399,6 +445,7 @@ int rsvd_batch_create(rsvd_handle_t handle, int32_t dtype, int32_t count, const 
     if (!handle || count < 1 || !descs || !params || !batch || !work_bytes) return RSVD_ERR_INVALID;
     if (flags & ~(RSVD_BATCH_GRAPH | RSVD_BATCH_STAMPS | RSVD_BATCH_FEATURES | RSVD_BATCH_OWN_QP))
         return RSVD_ERR_INVALID;
+    if (params->scheme != RSVD_SCHEME_QR) return RSVD_ERR_UNSUPPORTED;   // LU: single solves only
     const bool feat = (flags & RSVD_BATCH_FEATURES) != 0;
     const bool with_u = !feat && descs[0].U != nullptr;
     std::vector<rsvd_params> prm(count, *params);
@@ -449,6 +496,7 @@ int rsvd_batch_create_learned(rsvd_handle_t handle, int32_t dtype, int32_t count
     if (!handle || count < 1 || !descs || !params || !batch || !work_bytes) return RSVD_ERR_INVALID;
     if (flags & ~(RSVD_BATCH_GRAPH | RSVD_BATCH_STAMPS)) return RSVD_ERR_INVALID;
     if (params->p < 0 || params->p > RSVD_LEARNED_PMAX || !(tau <= 1.0f)) return RSVD_ERR_INVALID;
+    if (params->scheme != RSVD_SCHEME_QR) return RSVD_ERR_UNSUPPORTED;
     const bool with_u = descs[0].U != nullptr;
     std::vector<rsvd_params> prm0(count, *params), prm1(count, *params);
     for (int32_t i = 0; i < count; ++i) {

@@ -63,29 +63,42 @@ inline XPack xpack_of(const Plan& P, void* work) {
 }
 
 template <typename TA, typename TC>
-static hipError_t gemm_nn_typed(hipStream_t st, int arith, int64_t m, int64_t K, int c, const void* A, int64_t lda,
-                                const void* X, int64_t ldx, void* Y, int64_t ldy, XPack xp) {
+static hipError_t gemm_nn_typed(hipStream_t st, int arith, const Plan& P, int S, int64_t m, int64_t K, int c,
+                                const void* A, int64_t lda, const void* X, int64_t ldx, void* Y, int64_t ldy,
+                                void* work) {
     SingleExec ex{st};
-    return gemm_step<TA, TC, MODE_NN>(ex, arith, 0, static_cast<const TA*>(A), lda, m, K, static_cast<const TC*>(X),
-                                      ldx, c, static_cast<TC*>(Y), ldy, 1, 0, nullptr, nullptr, 0, Gate{}, xp);
+    const XPack xp = xpack_of(P, arith != 0 ? work : nullptr);
+    if (S == 1)
+        return gemm_step<TA, TC, MODE_NN>(ex, arith, 0, static_cast<const TA*>(A), lda, m, K,
+                                          static_cast<const TC*>(X), ldx, c, static_cast<TC*>(Y), ldy, 1, 0,
+                                          nullptr, nullptr, 0, Gate{}, xp);
+    // split n-reduction: S partial blocks (m x Lp each) summed in split order
+    TC* part = at<TC>(work, P.part);
+    const int64_t stride = m * P.Lp;
+    RSVD_TRY((gemm_step<TA, TC, MODE_NN>(ex, arith, 0, static_cast<const TA*>(A), lda, m, K,
+                                        static_cast<const TC*>(X), ldx, c, part, P.Lp, S, stride, nullptr, nullptr,
+                                        0, Gate{}, xp)));
+    return reduce_step<TC>(ex, part, S, stride, P.Lp, m, c, static_cast<TC*>(Y), ldy);
 }
 
 extern "C" {
 
 int rsvd_gemm_nn(rsvd_handle_t handle, int32_t dtype, int32_t arith, int64_t m, int64_t K, int32_t c,
-                 const void* A, int64_t lda, const void* X, int64_t ldx, void* Y, int64_t ldy, void* work,
-                 size_t work_bytes) {
+                 const void* A, int64_t lda, const void* X, int64_t ldx, void* Y, int64_t ldy, int32_t splits,
+                 void* work, size_t work_bytes) {
     if (!handle || m < 1 || K < 1 || c < 1 || c > RSVD_MAX_L_SINGLE || !A || !X || !Y) return RSVD_ERR_INVALID;
     if (lda < K || ldx < c || ldy < c || arith < 0 || arith > 2) return RSVD_ERR_INVALID;
+    if (splits < 0 || splits > kMaxNNSplit) return RSVD_ERR_INVALID;
     if (arith != 0 && dtype == RSVD_F64) return RSVD_ERR_UNSUPPORTED;
     const Plan P = block_plan(dtype, m, K, c, handle->dev.num_cu);
-    if (arith != 0 && (!work || work_bytes < P.bytes)) return RSVD_ERR_INVALID;   // packed-X scratch
-    const XPack xp = xpack_of(P, arith != 0 ? work : nullptr);
+    const int S = splits == 0 ? P.sp.nn : splits;
+    // packed-X scratch (bf16 arithmetics) and split partial blocks live in work
+    if ((arith != 0 || S > 1) && (!work || work_bytes < P.bytes)) return RSVD_ERR_INVALID;
     hipError_t e;
     switch (dtype) {
-        case RSVD_F64: e = gemm_nn_typed<double, double>(handle->stream, arith, m, K, c, A, lda, X, ldx, Y, ldy, xp); break;
-        case RSVD_F32: e = gemm_nn_typed<float, float>(handle->stream, arith, m, K, c, A, lda, X, ldx, Y, ldy, xp); break;
-        case RSVD_BF16: e = gemm_nn_typed<bf16_t, float>(handle->stream, arith, m, K, c, A, lda, X, ldx, Y, ldy, xp); break;
+        case RSVD_F64: e = gemm_nn_typed<double, double>(handle->stream, arith, P, S, m, K, c, A, lda, X, ldx, Y, ldy, work); break;
+        case RSVD_F32: e = gemm_nn_typed<float, float>(handle->stream, arith, P, S, m, K, c, A, lda, X, ldx, Y, ldy, work); break;
+        case RSVD_BF16: e = gemm_nn_typed<bf16_t, float>(handle->stream, arith, P, S, m, K, c, A, lda, X, ldx, Y, ldy, work); break;
         default: return RSVD_ERR_UNSUPPORTED;
     }
     return hip_status(handle, e);
@@ -156,6 +169,30 @@ int rsvd_orthonormalize(rsvd_handle_t handle, int32_t dtype, int64_t m, int32_t 
         e = hipMemcpyAsync(R, at<double>(work, P.racc) + 3 * static_cast<size_t>(c) * c,
                            static_cast<size_t>(c) * c * sizeof(double), hipMemcpyDeviceToDevice, st);
     if (e == hipSuccess && flags) e = hipMemcpyAsync(flags, status, sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
+    return hip_status(handle, e);
+}
+
+int rsvd_lu_normalize(rsvd_handle_t handle, int32_t dtype, int64_t m, int32_t c, void* Y, int64_t ldy,
+                      int32_t* piv, double* U, uint32_t* flags, void* work, size_t work_bytes) {
+    if (!handle || m < 1 || c < 1 || c > RSVD_MAX_L || c > m || !Y || ldy < c || !work) return RSVD_ERR_INVALID;
+    if (dtype != RSVD_F64 && dtype != RSVD_F32) return RSVD_ERR_UNSUPPORTED;
+    const Plan P = block_plan(dtype, m, m, c, handle->dev.num_cu);
+    if (work_bytes < P.bytes) return RSVD_ERR_INVALID;
+    SingleExec ex{handle->stream};
+    uint32_t* status = at<uint32_t>(work, P.status);
+    hipError_t e = ex.run<ClearBody>(ClearBody::Args{status, 1});
+    int32_t* cand = at<int32_t>(work, P.lucand);
+    int32_t* cnt = at<int32_t>(work, P.lucnt);
+    if (e == hipSuccess) {
+        if (dtype == RSVD_F64)
+            e = lu_normalize<double>(ex, 0, static_cast<double*>(Y), ldy, m, c, P.Lp, cand, cnt,
+                                     at<double>(work, P.rinv), status, U, piv);
+        else
+            e = lu_normalize<float>(ex, 0, static_cast<float*>(Y), ldy, m, c, P.Lp, cand, cnt,
+                                    at<float>(work, P.rinv), status, U, piv);
+    }
+    if (e == hipSuccess && flags) e = hipMemcpyAsync(flags, status, sizeof(uint32_t), hipMemcpyDeviceToDevice,
+                                                     handle->stream);
     return hip_status(handle, e);
 }
 

@@ -92,10 +92,10 @@ struct DeviceInfo {
 
 // Learned q per matrix, on stream st (defined with the selector network):
 // network forward on feat (count x 131) into prob (count x 15), then q[b] =
-// the fewest iterations whose (q', p') pairs hold mass >= tau.  theta null:
-// q[b] = fallback_q and neither feat nor prob is read.
+// the fewest iterations whose pairs (q' <= q, p' <= p_solve) hold mass >= tau.
+// theta null: q[b] = fallback_q and neither feat nor prob is read.
 hipError_t learned_choose_q(hipStream_t st, const float* theta, int count, const float* feat, float* prob,
-                            float tau, int fallback_q, int32_t* q);
+                            float tau, int p_solve, int fallback_q, int32_t* q);
 
 }  // namespace rsvd
 

@@ -74,14 +74,19 @@ struct XPackBody {
     }
 };
 
-template <typename TA, int MODE, bool SPLIT, int WR, int WC, int WGM, int WGN, int BK>
+// CENT (bf16-stored A with the column means subtracted, split arithmetic
+// only): A - mu is not exact in bf16, so it is formed in f32 and staged as
+// hi + lo planes like f32-stored A, instead of moving raw bf16 words.
+template <typename TA, int MODE, bool SPLIT, int WR, int WC, int WGM, int WGN, int BK, bool CENT = false>
 struct Bf16Tile {
     static constexpr int BM = 16 * WR * WGM;
     static constexpr int NC = 16 * WC * WGN;
     static constexpr int NT = 64 * WGM * WGN;
     static constexpr int SK = BK + 8;                // LDS row stride (bf16 elements)
     static constexpr int OCT = BK / 8;               // k-octets per row and tile
-    static constexpr bool A_LO = SPLIT && (sizeof(TA) > 2);   // bf16-stored A is exact
+    static constexpr bool A_LO = SPLIT && (sizeof(TA) > 2 || CENT);   // bf16-stored A is exact
+    static constexpr bool RAW = sizeof(TA) == 2 && !CENT;    // A staged as raw bf16 words
+    static_assert(!CENT || (SPLIT && sizeof(TA) == 2), "CENT: split products of bf16-stored A");
     // NN A items: (row, octet).  TN A / X items: (k-quad, 8-column block).
     static constexpr int A_ITEMS = (MODE == MODE_NN) ? BM * OCT : (BK / 4) * (BM / 8);
     static constexpr int X_ITEMS = NC * OCT;          // (column, k-octet) of the packed X
@@ -121,9 +126,9 @@ __device__ __forceinline__ void load8(const TA* p, bool vec, int valid, float (&
     }
 }
 
-template <typename TA, int MODE, bool SPLIT, int WR, int WC, int WGM, int WGN, int BK>
+template <typename TA, int MODE, bool SPLIT, int WR, int WC, int WGM, int WGN, int BK, bool CENT = false>
 __device__ __forceinline__ void gemm_bf16_body(const GemmArgs<TA, float, float>& g, int bx, int by, int bz) {
-    typedef Bf16Tile<TA, MODE, SPLIT, WR, WC, WGM, WGN, BK> T;
+    typedef Bf16Tile<TA, MODE, SPLIT, WR, WC, WGM, WGN, BK, CENT> T;
     constexpr int SK = T::SK, OCT = T::OCT;
     if (g.skip_flag && ((*g.skip_flag & g.skip_mask) == 0u)) return;
     if (g.gate && ((*g.gate & g.gate_mask) == 0u)) return;
@@ -144,9 +149,10 @@ __device__ __forceinline__ void gemm_bf16_body(const GemmArgs<TA, float, float>&
     const int64_t kend = min(g.K, kbeg + g.kchunk);
 
     // bf16-stored A moves as raw 16-bit words from global memory to LDS (no
-    // widening and re-rounding), except where the column means are
-    // subtracted (rounded once, as in the f32 path).
-    constexpr bool RAW = sizeof(TA) == 2;
+    // widening and re-rounding); in the plain bf16 arithmetic the column
+    // means are subtracted from those words and the difference rounded once
+    // to bf16, in the split arithmetic (CENT) A - mu goes through f32.
+    constexpr bool RAW = T::RAW;
     float ra[RAW ? 1 : T::A_PASSES][RAW ? 1 : T::A_VALS];
     uint32_t rb[RAW ? T::A_PASSES : 1][RAW ? T::A_VALS / 2 : 1];
     uint32_t rx[T::X_PASSES][SPLIT ? 8 : 4];
@@ -379,12 +385,6 @@ __device__ __forceinline__ void gemm_bf16_body(const GemmArgs<TA, float, float>&
             }
         }
     }
-}
-
-template <typename TA, int MODE, bool SPLIT, int WR, int WC, int WGM, int WGN, int BK>
-__global__ __launch_bounds__(64 * WGM * WGN)
-void gemm_bf16_kernel(GemmArgs<TA, float, float> g) {
-    gemm_bf16_body<TA, MODE, SPLIT, WR, WC, WGM, WGN, BK>(g, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 }  // namespace rsvd

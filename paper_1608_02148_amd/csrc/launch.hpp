@@ -38,11 +38,12 @@ struct GemmBody {
     }
 };
 
-// bf16 matrix-core product (f32 in / out), plain or split.
-template <typename TA, int MODE, bool SPLIT, int WR, int WC, int WGM, int WGN>
+// bf16 matrix-core product (f32 in / out), plain or split; CENT: split
+// product of bf16-stored A with the column means subtracted.
+template <typename TA, int MODE, bool SPLIT, int WR, int WC, int WGM, int WGN, bool CENT = false>
 struct Bf16Body {
     static constexpr int BK = SPLIT ? 32 : 64;
-    typedef Bf16Tile<TA, MODE, SPLIT, WR, WC, WGM, WGN, BK> T;
+    typedef Bf16Tile<TA, MODE, SPLIT, WR, WC, WGM, WGN, BK, CENT> T;
     typedef GemmArgs<TA, float, float> Args;
     static constexpr int THREADS = T::NT;
     static int blocks(const Args& g) {
@@ -53,7 +54,7 @@ struct Bf16Body {
         const int gx = static_cast<int>(cdiv(g.rows, T::BM));
         const int nct = static_cast<int>(cdiv(g.ncols, T::NC));
         const int rest = b / nct;
-        gemm_bf16_body<TA, MODE, SPLIT, WR, WC, WGM, WGN, BK>(g, rest % gx, rest / gx, b % nct);
+        gemm_bf16_body<TA, MODE, SPLIT, WR, WC, WGM, WGN, BK, CENT>(g, rest % gx, rest / gx, b % nct);
     }
 };
 
@@ -197,17 +198,17 @@ hipError_t gemm_plain(Ex& ex, int cls, bool square, const TA* A, int64_t lda, in
     return gemm_tall<TA, TX, TC, MODE, false>(ex, tc, cls >> 16, g);
 }
 
-template <typename TA, int MODE, bool SPLIT, class Ex>
+template <typename TA, int MODE, bool SPLIT, bool CENT, class Ex>
 hipError_t gemm_bf16_cls(Ex& ex, int tc, const GemmArgs<TA, float, float>& g) {
-    if (tc == 32) return ex.template run<Bf16Body<TA, MODE, SPLIT, 2, 2, 4, 1>>(g);
-    if (tc == 48) return ex.template run<Bf16Body<TA, MODE, SPLIT, 2, 3, 4, 1>>(g);
-    if (tc == 64) return ex.template run<Bf16Body<TA, MODE, SPLIT, 4, 2, 2, 2>>(g);
-    if (tc == 80) return ex.template run<Bf16Body<TA, MODE, SPLIT, 2, 5, 4, 1>>(g);
-    if (tc == 96) return ex.template run<Bf16Body<TA, MODE, SPLIT, 4, 3, 2, 2>>(g);
+    if (tc == 32) return ex.template run<Bf16Body<TA, MODE, SPLIT, 2, 2, 4, 1, CENT>>(g);
+    if (tc == 48) return ex.template run<Bf16Body<TA, MODE, SPLIT, 2, 3, 4, 1, CENT>>(g);
+    if (tc == 64) return ex.template run<Bf16Body<TA, MODE, SPLIT, 4, 2, 2, 2, CENT>>(g);
+    if (tc == 80) return ex.template run<Bf16Body<TA, MODE, SPLIT, 2, 5, 4, 1, CENT>>(g);
+    if (tc == 96) return ex.template run<Bf16Body<TA, MODE, SPLIT, 4, 3, 2, 2, CENT>>(g);
     // 256 columns (sketches wider than 128): 16 waves of 32 x 64 (the 8-wave
     // 64 x 64 tiling was 5-7 % slower for A X at 200000 x 20000, l = 220)
-    if (tc == 256) return ex.template run<Bf16Body<TA, MODE, SPLIT, 2, 4, 4, 4>>(g);
-    return ex.template run<Bf16Body<TA, MODE, SPLIT, 4, 4, 2, 2>>(g);
+    if (tc == 256) return ex.template run<Bf16Body<TA, MODE, SPLIT, 2, 4, 4, 4, CENT>>(g);
+    return ex.template run<Bf16Body<TA, MODE, SPLIT, 4, 4, 2, 2, CENT>>(g);
 }
 
 // The bf16 products read X packed once per product into bf16 planes (hi, and
@@ -229,8 +230,14 @@ hipError_t gemm_bf16(Ex& ex, bool split, int cls, const TA* A, int64_t lda, int6
                                                               split ? 1 : 0, skip_flag, skip_mask, gate});
     if (e != hipSuccess) return e;
     g.xb = xp.p; g.ldxb = xp.ld; g.xb_plane = xp.plane;
-    if (split) return gemm_bf16_cls<TA, MODE, true>(ex, tc, g);
-    return gemm_bf16_cls<TA, MODE, false>(ex, tc, g);
+    if (split) {
+        // bf16-stored A minus its column means is not exact in bf16: the
+        // split product then stages it as hi + lo terms (f32-accurate)
+        if constexpr (sizeof(TA) == 2)
+            if (mu) return gemm_bf16_cls<TA, MODE, true, true>(ex, tc, g);
+        return gemm_bf16_cls<TA, MODE, true, false>(ex, tc, g);
+    }
+    return gemm_bf16_cls<TA, MODE, false, false>(ex, tc, g);
 }
 
 // One product with A in the requested arithmetic: 0 = storage precision

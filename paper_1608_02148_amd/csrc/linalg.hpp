@@ -108,9 +108,14 @@ struct ReduceBody {
     }
 };
 
-// ------------------------------------------------------------- column means
-// Partial column sums over S chunks of rows: part[s][j] = sum_{i in chunk s} A[i][j],
-// then mu[j] = sum_s part[s][j] / m in split order.
+// ------------------------------------------------------- column statistics
+// Column means and root mean squares (PCA centring and scaling, Sec. 4.2 and
+// 4.3) in one pass over A.  Sums are shifted by the column's first entry
+// a0_j (sums of d = a - a0_j), which keeps the sum of squares well
+// conditioned when the offset of a column dwarfs its spread:
+//   part[s][j] = sum_{i in chunk s} d_ij,  part[S + s][j] = sum d_ij^2,
+//   part[2S][j] = a0_j.
+// One thread per column, rows of a chunk in order (coalesced row reads).
 template <typename TA>
 struct ColsumBody {
     struct Args { const TA* A; int64_t lda; int64_t m; int64_t n; int64_t rows_per_split; int S; double* part; };
@@ -122,24 +127,159 @@ struct ColsumBody {
         const int64_t j = static_cast<int64_t>(b % cb) * THREADS + threadIdx.x;
         const int s = b / cb;
         if (j >= a.n) return;
+        const double a0 = Conv<double>::to(a.A[j]);
         const int64_t i0 = s * a.rows_per_split, i1 = min(a.m, i0 + a.rows_per_split);
-        double acc = 0.0;
-        for (int64_t i = i0; i < i1; ++i) acc += Conv<double>::to(a.A[i * a.lda + j]);
+        double acc = 0.0, acc2 = 0.0;
+        for (int64_t i = i0; i < i1; ++i) {
+            const double d = Conv<double>::to(a.A[i * a.lda + j]) - a0;
+            acc += d;
+            acc2 += d * d;
+        }
         a.part[s * a.n + j] = acc;
+        a.part[(a.S + s) * a.n + j] = acc2;
+        if (s == 0) a.part[2 * a.S * a.n + j] = a0;
     }
 };
 
+// From the partial sums (split order): the centre c_j = a0_j + sum d / m when
+// centring (mu, else 0); the mean square about it v_j = sum (a - c_j)^2 /
+// (m - 1); with scaling the divisor s_j = sqrt(v_j) (1 for a constant
+// column, flagged RSVD_FLAG_ZERO_SCALE in status) and inv[j] = 1 / s_j.
+// var[j] = the variance of the column as the solve sees it (v_j / s_j^2).
+// mu, inv, var may each be null.
 struct ColmeanBody {
-    struct Args { const double* part; int S; int64_t m; int64_t n; double* mu; };
+    struct Args {
+        const double* part; int S; int64_t m; int64_t n; int center; double* mu; double* inv; double* var;
+        double* sc; uint32_t* status;
+    };
     static constexpr int THREADS = 256;
     static int blocks(const Args& a) { return static_cast<int>(cdiv(a.n, THREADS)); }
     static size_t lds(const Args&) { return 0; }
     static __device__ void run(const Args& a, int b) {
         const int64_t j = static_cast<int64_t>(b) * THREADS + threadIdx.x;
         if (j >= a.n) return;
-        double acc = 0.0;
-        for (int s = 0; s < a.S; ++s) acc += a.part[s * a.n + j];
-        a.mu[j] = acc / static_cast<double>(a.m);
+        double s1 = 0.0, s2 = 0.0;
+        for (int s = 0; s < a.S; ++s) s1 += a.part[s * a.n + j];
+        for (int s = 0; s < a.S; ++s) s2 += a.part[(a.S + s) * a.n + j];
+        const double a0 = a.part[2 * a.S * a.n + j];
+        const double md = s1 / static_cast<double>(a.m);            // mean of d
+        // sum (a - c)^2 with c = a0 + md (centring) or c = 0: sum (d - e)^2 for
+        // e = md or e = -a0, = s2 - 2 e s1 + m e^2
+        const double e = a.center ? md : -a0;
+        const double ss = fmax(0.0, s2 - 2.0 * e * s1 + static_cast<double>(a.m) * e * e);
+        const double v = ss / static_cast<double>(a.m - 1);
+        if (a.mu) a.mu[j] = a.center ? a0 + md : 0.0;
+        double sc = 1.0;
+        if (a.inv) {
+            if (v > 0.0) {
+                sc = sqrt(v);
+            } else if (a.status) {
+                atomicOr(a.status, RSVD_FLAG_ZERO_SCALE);
+            }
+            a.inv[j] = 1.0 / sc;
+            if (a.sc) a.sc[j] = sc;
+        }
+        if (a.var) a.var[j] = v / (sc * sc);
+    }
+};
+
+// Sum of var[0..n) in a fixed order (strided partial sums, then a tree) into
+// *total: the total variance of the data the PCA sees.  One workgroup.
+struct TotalVarBody {
+    struct Args { const double* var; int64_t n; double* total; };
+    static constexpr int THREADS = 256;
+    static int blocks(const Args&) { return 1; }
+    static size_t lds(const Args&) { return 0; }
+    static __device__ void run(const Args& a, int) {
+        __shared__ double sh[THREADS];
+        double s = 0.0;
+        for (int64_t j = threadIdx.x; j < a.n; j += THREADS) s += a.var[j];
+        sh[threadIdx.x] = s;
+        __syncthreads();
+        for (int off = THREADS / 2; off > 0; off >>= 1) {
+            if (static_cast<int>(threadIdx.x) < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) *a.total = sh[0];
+    }
+};
+
+// M[j][c] *= inv[j] for j < rows, c < cols (the diagonal scaling D^-1 of
+// scaled PCA applied to the skinny side of a product).
+template <typename TC>
+struct ScaleRowsVecBody {
+    struct Args { TC* M; int64_t ld; int64_t rows; int cols; const double* inv; };
+    static constexpr int THREADS = 256;
+    static int blocks(const Args& a) { return static_cast<int>(cdiv(a.rows * a.cols, THREADS)); }
+    static size_t lds(const Args&) { return 0; }
+    static __device__ void run(const Args& a, int b) {
+        const int64_t idx = static_cast<int64_t>(b) * THREADS + threadIdx.x;
+        if (idx >= a.rows * a.cols) return;
+        const int64_t j = idx / a.cols;
+        const int c = static_cast<int>(idx - j * a.cols);
+        TC* p = a.M + j * a.ld + c;
+        *p = static_cast<TC>(static_cast<double>(*p) * a.inv[j]);
+    }
+};
+
+// PCA outputs from the singular values (sdev_i = sigma_i / sqrt(m - 1)):
+// loadings L[j][i] = V[j][i] sdev_i (n x k) and whitened components
+// W[r][i] = X[r][i] / sdev_i (m x k; 0 where sdev_i = 0).  X and W may be
+// the same matrix.  Either output may be null.
+template <typename TC>
+struct PcaOutBody {
+    struct Args {
+        const TC* V; int64_t ldv; TC* L; int64_t ldl; int64_t n;
+        const TC* X; int64_t ldx; TC* W; int64_t ldw; int64_t m; int k; const double* sigma; double denom;
+    };
+    static constexpr int THREADS = 256;
+    static int blocks(const Args& a) {
+        return static_cast<int>(cdiv(((a.L ? a.n : 0) + (a.W ? a.m : 0)) * a.k, THREADS));
+    }
+    static size_t lds(const Args&) { return 0; }
+    static __device__ void run(const Args& a, int b) {
+        int64_t idx = static_cast<int64_t>(b) * THREADS + threadIdx.x;
+        const int64_t nl = a.L ? a.n * a.k : 0;
+        if (idx < nl) {
+            const int64_t j = idx / a.k;
+            const int i = static_cast<int>(idx - j * a.k);
+            const double sd = a.sigma[i] / sqrt(a.denom);
+            a.L[j * a.ldl + i] = static_cast<TC>(static_cast<double>(a.V[j * a.ldv + i]) * sd);
+            return;
+        }
+        idx -= nl;
+        if (!a.W || idx >= a.m * a.k) return;
+        const int64_t r = idx / a.k;
+        const int i = static_cast<int>(idx - r * a.k);
+        const double sd = a.sigma[i] / sqrt(a.denom);
+        a.W[r * a.ldw + i] = static_cast<TC>(sd > 0.0 ? static_cast<double>(a.X[r * a.ldx + i]) / sd : 0.0);
+    }
+};
+
+// rpca_predict's operands: mu[j] = center[j] (widened to f64) and
+// W'[j][c] = rotation[j][c] / scale[j] for c < k, 0 for k <= c < kp.
+// center / scale null: no centring / no scaling.
+template <typename TC>
+struct PredictPrepBody {
+    struct Args {
+        const TC* rot; int64_t ldr; const TC* center; const TC* scale; int64_t n; int k; int kp;
+        double* mu; TC* W;
+    };
+    static constexpr int THREADS = 256;
+    static int blocks(const Args& a) { return static_cast<int>(cdiv(a.n * a.kp, THREADS)); }
+    static size_t lds(const Args&) { return 0; }
+    static __device__ void run(const Args& a, int b) {
+        const int64_t idx = static_cast<int64_t>(b) * THREADS + threadIdx.x;
+        if (idx >= a.n * a.kp) return;
+        const int64_t j = idx / a.kp;
+        const int c = static_cast<int>(idx - j * a.kp);
+        if (c == 0 && a.center) a.mu[j] = static_cast<double>(a.center[j]);
+        double w = 0.0;
+        if (c < a.k) {
+            w = static_cast<double>(a.rot[j * a.ldr + c]);
+            if (a.scale) w /= static_cast<double>(a.scale[j]);
+        }
+        a.W[j * a.kp + c] = static_cast<TC>(w);
     }
 };
 
@@ -1160,10 +1300,14 @@ struct FinalizeBody {
         int l; int q; int p;
         const double* est;        // a-posteriori bound or null
         const int32_t* qsrc;      // q chosen on the device, or null (q above)
+        const double* scl;        // PCA column scales (null: not scaled)
+        TC* scale_out;            // n scales (ones when not scaled) or null
+        const double* tvar;       // total variance computed on the device, or null
+        double* total_var;        // its output or null
     };
     static constexpr int THREADS = 256;
     static int blocks(const Args& a) {
-        return static_cast<int>(cdiv(std::max<int64_t>(a.k, a.center_out ? a.n : 0), THREADS));
+        return static_cast<int>(cdiv(std::max<int64_t>(a.k, (a.center_out || a.scale_out) ? a.n : 0), THREADS));
     }
     static size_t lds(const Args&) { return 0; }
     static __device__ void run(const Args& a, int b) {
@@ -1175,6 +1319,8 @@ struct FinalizeBody {
             if (a.sdev) a.sdev[tid] = sqrt(s * s / a.denom);
         }
         if (a.center_out && tid < a.n) a.center_out[tid] = static_cast<TC>(a.mu ? a.mu[tid] : 0.0);
+        if (a.scale_out && tid < a.n) a.scale_out[tid] = static_cast<TC>(a.scl ? a.scl[tid] : 1.0);
+        if (a.total_var && tid == 0) *a.total_var = a.tvar ? *a.tvar : 0.0;
         if (a.info && tid == 0) {
             a.info->l = a.l; a.info->q = a.qsrc ? *a.qsrc : a.q; a.info->p = a.p;
             a.info->flags = *a.status & 0xFF00FFFFu;   // RSVD_FLAG_* and the sweep count

@@ -16,6 +16,9 @@
 // The products are tiny (13583 parameters, a few MFLOP per batch), so plain
 // FMA code is used; there is nothing here for the matrix cores to amortise.
 #include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
 
 #include "common.hpp"
 #include "philox.hpp"
@@ -127,16 +130,19 @@ __global__ __launch_bounds__(NH) void mlp_fwd_bwd_kernel(const float* __restrict
     w.d1[static_cast<size_t>(b) * NH + j] = (h1 > 0.0f) ? d1 : 0.0f;
 }
 
-// q per matrix from the network's distribution when every solve runs with the
-// largest oversampling: pair (q', p') is covered by (q, p_max) when q' <= q, so
-// q_b is the fewest iterations whose pairs hold probability mass >= tau (tau
-// <= 0: the q of the most probable pair).  No network: fallback_q for all.
+// q per matrix from the network's distribution, for solves that all run with
+// oversampling p_solve: pair (q', p') is covered by (q, p_solve) when q' <= q
+// and p' <= p_solve, so q_b is the fewest iterations whose covered pairs hold
+// probability mass >= tau; when no q reaches tau (possible for p_solve below
+// the largest class value), the most iterations, q = 4.  tau <= 0: the q of
+// the most probable pair.  No network: fallback_q for all.
 __global__ __launch_bounds__(256) void mlp_choose_q_kernel(const float* __restrict__ prob, int B, float tau,
-                                                           int fallback_q, int32_t* q) {
+                                                           int p_solve, int fallback_q, int32_t* q) {
     const int b = blockIdx.x * 256 + threadIdx.x;
     if (b >= B) return;
     if (!prob) { q[b] = fallback_q; return; }
     const float* pb = prob + static_cast<size_t>(b) * NO;
+    constexpr int kP[3] = {5, 10, 20};
     int pick = NO / 3 - 1;
     if (tau <= 0.0f) {
         int best = 0;
@@ -145,7 +151,8 @@ __global__ __launch_bounds__(256) void mlp_choose_q_kernel(const float* __restri
     } else {
         double cum = 0.0;
         for (int qq = 0; qq < NO / 3; ++qq) {
-            for (int c = 3 * qq; c < 3 * qq + 3; ++c) cum += pb[c];
+            for (int j = 0; j < 3; ++j)
+                if (kP[j] <= p_solve) cum += pb[3 * qq + j];
             if (cum >= tau) { pick = qq; break; }
         }
     }
@@ -214,7 +221,7 @@ int status_of(rsvd_handle_t h, hipError_t e) {
 namespace rsvd {
 
 hipError_t learned_choose_q(hipStream_t st, const float* theta, int count, const float* feat, float* prob,
-                            float tau, int fallback_q, int32_t* q) {
+                            float tau, int p_solve, int fallback_q, int32_t* q) {
     if (theta) {
         MlpWork w{};
         hipLaunchKernelGGL(mlp_fwd_bwd_kernel, dim3(count), dim3(NH), 0, st, theta, count, feat, nullptr, w, prob,
@@ -223,7 +230,7 @@ hipError_t learned_choose_q(hipStream_t st, const float* theta, int count, const
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(mlp_choose_q_kernel, dim3((count + 255) / 256), dim3(256), 0, st, theta ? prob : nullptr,
-                       count, tau, fallback_q, q);
+                       count, tau, p_solve, fallback_q, q);
     return hipGetLastError();
 }
 
@@ -272,6 +279,49 @@ int rsvd_mlp_train_step(rsvd_handle_t handle, float* theta, float* adam_m, float
                            lr, static_cast<float>(c1), static_cast<float>(c2));
     }
     return status_of(handle, hipGetLastError());
+}
+
+// Checkpoint file: 64-byte header (magic, u32 version, u32 parameter count,
+// u32 Adam step, u64 seed, u64 training-set size, 8-byte digest, zero
+// padding), then theta, adam_m, adam_v as little-endian f32.
+int rsvd_mlp_load(rsvd_handle_t handle, const char* path, float* theta, float* adam_m, float* adam_v,
+                  rsvd_mlp_header* header) {
+    if (!handle || !path || (!theta && (adam_m || adam_v))) return RSVD_ERR_INVALID;
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return RSVD_ERR_INVALID;
+    const size_t want = 64 + 3 * sizeof(float) * static_cast<size_t>(NP);
+    std::vector<unsigned char> raw(want + 1);
+    const size_t got = std::fread(raw.data(), 1, raw.size(), f);
+    std::fclose(f);
+    static const char kMagic[8] = {'R', 'S', 'V', 'D', 'M', 'L', 'P', '1'};
+    if (got < 36) return RSVD_ERR_INVALID;
+    if (std::memcmp(raw.data(), kMagic, 8) != 0) return RSVD_ERR_UNSUPPORTED;
+    uint32_t version, nparams, step;
+    uint64_t seed, ntrain;
+    std::memcpy(&version, raw.data() + 8, 4);
+    std::memcpy(&nparams, raw.data() + 12, 4);
+    std::memcpy(&step, raw.data() + 16, 4);
+    std::memcpy(&seed, raw.data() + 20, 8);
+    std::memcpy(&ntrain, raw.data() + 28, 8);
+    if (version != 1 || nparams != static_cast<uint32_t>(NP)) return RSVD_ERR_UNSUPPORTED;
+    if (got != want) return RSVD_ERR_INVALID;             // truncated or trailing bytes
+    const float* vals = reinterpret_cast<const float*>(raw.data() + 64);
+    for (size_t i = 0; i < 3 * static_cast<size_t>(NP); ++i)
+        if (!std::isfinite(vals[i])) return RSVD_ERR_INVALID;
+    if (header) {
+        header->version = version; header->params = nparams; header->step = step; header->reserved = 0;
+        header->seed = seed; header->n_train = ntrain;
+        std::memcpy(header->digest, raw.data() + 36, 8);
+    }
+    if (!theta) return RSVD_OK;                           // checked only
+    float* dst[3] = {theta, adam_m, adam_v};
+    for (int t = 0; t < 3; ++t) {
+        if (!dst[t]) continue;
+        const hipError_t e = hipMemcpyAsync(dst[t], vals + static_cast<size_t>(t) * NP, sizeof(float) * NP,
+                                            hipMemcpyHostToDevice, handle->stream);
+        if (e != hipSuccess) return status_of(handle, e);
+    }
+    return status_of(handle, hipStreamSynchronize(handle->stream));
 }
 
 }  // extern "C"

@@ -48,6 +48,9 @@ inline int gram_split(int64_t rows, int num_cu) {
     return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(cdiv(rows, 64), num_cu)));
 }
 
+// Largest split of the n-reduction of A X (partial blocks of m x Lp each).
+constexpr int kMaxNNSplit = 4;
+
 // A^T Q: as many splits as fit the 2 resident workgroups per CU in one round
 // (a partly filled second round would idle most CUs), at least 256 rows each.
 // A X: split the n-reduction when the row tiles (128 rows each) leave the last
@@ -62,7 +65,7 @@ inline int nn_split(int64_t m, int64_t n, int num_cu) {
     };
     int best = 1;
     double be = filled(1);
-    for (int S = 2; S <= 4 && n / S >= 1024; ++S)
+    for (int S = 2; S <= kMaxNNSplit && n / S >= 1024; ++S)
         if (filled(S) > be + 0.1) { best = S; be = filled(S); }
     return best;
 }
@@ -90,6 +93,12 @@ struct Plan {
     Splits sp{};
     size_t Y = 0, Z = 0, Om = 0, part = 0, gram = 0, rinv = 0, racc = 0, sigma = 0,
            xv = 0, xu = 0, jk = 0, wks = 0, vtmp = 0, mu = 0, mupart = 0, status = 0, bytes = 0;
+    // PCA column statistics: inverse scales, scales and variances (n f64 each) and the
+    // total variance (one f64)
+    size_t cinv = 0, cscl = 0, cvar = 0, tvar = 0;
+    // LU normalisation (tournament pivoting): two candidate lists of
+    // cdiv(max(m, n), 256) x l row indices and two count arrays
+    size_t lucand = 0, lucnt = 0;
     // a-posteriori estimate (probes > 0): probes n x 32, A probes and U (S V^T
     // probes) m x 32, V^T probes k x 32, U scratch m x k, column partial sums
     int probes = 0, est_split = 1;
@@ -116,9 +125,11 @@ inline int validate(int32_t dtype, int64_t m, int64_t n, int32_t k, const rsvd_p
     if (prm->precision != RSVD_PREC_PLAIN && prm->precision != RSVD_PREC_BF16_MIXED) return RSVD_ERR_UNSUPPORTED;
     if (prm->precision == RSVD_PREC_BF16_MIXED && dtype == RSVD_F64) return RSVD_ERR_UNSUPPORTED;
     if (prm->probes < 0 || prm->probes > 16) return RSVD_ERR_INVALID;
+    if (prm->scheme != RSVD_SCHEME_QR && prm->scheme != RSVD_SCHEME_LU) return RSVD_ERR_INVALID;
     if (m > (int64_t(1) << 32) || n > (int64_t(1) << 32)) return RSVD_ERR_UNSUPPORTED;
     const int64_t l = std::min<int64_t>(static_cast<int64_t>(k) + prm->p, std::min(m, n));
     if (l > max_l) return RSVD_ERR_UNSUPPORTED;
+    if (prm->scheme == RSVD_SCHEME_LU && l > RSVD_MAX_L) return RSVD_ERR_UNSUPPORTED;
     return RSVD_OK;
 }
 
@@ -169,7 +180,11 @@ inline Plan make_plan(int dtype, int64_t m, int64_t n, int k, const rsvd_params*
     P.wks = L.take(static_cast<size_t>(P.Lp) * P.kp * 8);
     P.vtmp = L.take(static_cast<size_t>(n) * P.kp * cs);
     P.mu = L.take(static_cast<size_t>(n) * 8);
-    P.mupart = L.take(static_cast<size_t>(P.sp.colsum) * n * 8);
+    P.mupart = L.take((2 * static_cast<size_t>(P.sp.colsum) + 1) * n * 8);
+    P.cinv = L.take(static_cast<size_t>(n) * 8);
+    P.cscl = L.take(static_cast<size_t>(n) * 8);
+    P.cvar = L.take(static_cast<size_t>(n) * 8);
+    P.tvar = L.take(8);
     if (P.l > 128) {
         P.cholx = L.take(7 * 128 * 128 * sizeof(double));
         P.wglob = L.take(static_cast<size_t>(P.l) * (rup(P.l, 16) + 1) * sizeof(double));
@@ -183,6 +198,11 @@ inline Plan make_plan(int dtype, int64_t m, int64_t n, int k, const rsvd_params*
     } else if (!batch) {
         P.ldxk = rup(std::max(m, n), 8);
         P.xk = L.take(static_cast<size_t>(P.Lp) * P.ldxk * cs);
+    }
+    if (prm->scheme == RSVD_SCHEME_LU) {
+        const size_t leaves = static_cast<size_t>(cdiv(std::max(m, n), 256));
+        P.lucand = L.take(2 * leaves * P.l * sizeof(int32_t));
+        P.lucnt = L.take(2 * leaves * sizeof(int32_t));
     }
     P.probes = prm->probes;
     if (P.probes > 0) {
@@ -209,13 +229,6 @@ template <typename T> inline T* at(void* work, size_t off) {
         if (_e != hipSuccess) return _e;                 \
     } while (0)
 
-// In-place orthonormalisation of M (rows x l, ld ldm, precision TC):
-// CholeskyQR2, with a shifted first pass and a third pass when needed.
-// adaptive = true (bases inside the power scheme, whose span is all that the
-// next product uses) runs the second pass only when the first pass shows an
-// ill-conditioned Gram matrix.
-// rfac (optional, f64, 4 consecutive l x l blocks) receives R1, R2, R3 (R3 = I
-
 struct SolveOut {
     void* U; int64_t ldu;      // m x k or null
     void* V; int64_t ldv;      // n x k or null (then workspace)
@@ -224,6 +237,11 @@ struct SolveOut {
     void* center_out;
     int scale_u;               // 1: U columns scaled by sigma (PCA x = U S)
     int center;
+    int scale;                 // PCA: divide the centred columns by their root mean square
+    void* scale_out;           // PCA: n column scales or null
+    double* total_var;         // PCA: total variance of the analysed data or null
+    void* loadings; int64_t ldl;     // PCA: n x k loadings or null
+    void* xwhite; int64_t ldxw;      // PCA: m x k whitened components or null
     rsvd_info* info;
     uint64_t* stamps;          // optional [first step, last step] device clock
     float* features;           // non-null: stop after the sketch and write the 131 selector inputs
@@ -248,8 +266,9 @@ inline Plan block_plan(int32_t dtype, int64_t m, int64_t n, int32_t c, int num_c
     const size_t cs = comp_size(dtype);
     Layout L;
     P.status = L.take(kAlign);
-    P.part = L.take(std::max(static_cast<size_t>(P.sp.tn) * n * P.Lp * cs,
-                             static_cast<size_t>(std::max(P.sp.gram_m, P.sp.gram_n)) * P.Lp * P.Lp * 8));
+    P.part = L.take(std::max({static_cast<size_t>(P.sp.tn) * n * P.Lp * cs,
+                              static_cast<size_t>(kMaxNNSplit) * m * P.Lp * cs,
+                              static_cast<size_t>(std::max(P.sp.gram_m, P.sp.gram_n)) * P.Lp * P.Lp * 8}));
     P.gram = L.take(static_cast<size_t>(P.Lp) * P.Lp * 8);
     P.rinv = L.take(static_cast<size_t>(P.Lp) * P.Lp * cs);
     P.racc = L.take(4 * static_cast<size_t>(P.Lp) * P.Lp * 8);
@@ -257,6 +276,34 @@ inline Plan block_plan(int32_t dtype, int64_t m, int64_t n, int32_t c, int num_c
     P.ldxp = rup(std::max(m, n), 8);
     P.xplane = static_cast<int64_t>(P.Lp) * P.ldxp;
     P.xpack = L.take(2 * static_cast<size_t>(P.xplane) * sizeof(uint16_t));
+    if (c <= RSVD_MAX_L) {
+        const size_t leaves = static_cast<size_t>(cdiv(std::max(m, n), 256));
+        P.lucand = L.take(2 * leaves * c * sizeof(int32_t));
+        P.lucnt = L.take(2 * leaves * sizeof(int32_t));
+    }
+    P.bytes = L.off;
+    return P;
+}
+
+// Workspace of rpca_predict: the centre widened to f64 (n), the rotation
+// with its rows divided by the scales, D^-1 W (n x kp in the compute type,
+// zero-padded columns), and the partial blocks of a split n-reduction.
+struct PredictPlan {
+    int dtype = 0;
+    int64_t m = 0, n = 0;
+    int k = 0, kp = 0, S = 1;
+    size_t mu = 0, w = 0, part = 0, bytes = 0;
+};
+
+inline PredictPlan predict_plan(int32_t dtype, int64_t m, int64_t n, int32_t k, int num_cu) {
+    PredictPlan P;
+    P.dtype = dtype; P.m = m; P.n = n; P.k = k; P.kp = tile_cols(k);
+    P.S = nn_split(m, n, num_cu);
+    const size_t cs = comp_size(dtype);
+    Layout L;
+    P.mu = L.take(static_cast<size_t>(n) * 8);
+    P.w = L.take(static_cast<size_t>(n) * P.kp * cs);
+    P.part = L.take(P.S > 1 ? static_cast<size_t>(P.S) * m * P.kp * cs : 0);
     P.bytes = L.off;
     return P;
 }
@@ -274,5 +321,15 @@ RSVD_DECLARE_SOLVE(f64)
 RSVD_DECLARE_SOLVE(f32)
 RSVD_DECLARE_SOLVE(bf16)
 #undef RSVD_DECLARE_SOLVE
+
+// Principal components of new rows per storage type (rpca_predict).
+#define RSVD_DECLARE_PREDICT(NAME)                                                                     \
+    hipError_t predict_##NAME(rsvd_handle_t h, const PredictPlan& P, const void* A, int64_t lda,       \
+                              const void* rot, int64_t ldr, const void* center, const void* scale,      \
+                              void* x, int64_t ldx, void* work);
+RSVD_DECLARE_PREDICT(f64)
+RSVD_DECLARE_PREDICT(f32)
+RSVD_DECLARE_PREDICT(bf16)
+#undef RSVD_DECLARE_PREDICT
 
 }  // namespace rsvd

@@ -3,6 +3,7 @@
 #pragma once
 
 #include "launch.hpp"
+#include "lu.hpp"
 #include "plan.hpp"
 
 namespace rsvd {
@@ -39,6 +40,17 @@ hipError_t chol_blocked(Ex& ex, const CholArgs& ca, double* x) {
         R11, I11, R12, T, R22, I22, l, static_cast<TC*>(ca.rinv), ca.ldr, ca.rout, skip, need, ca.gate});
 }
 
+// In-place orthonormalisation of M (rows x l, ld ldm, precision TC):
+// CholeskyQR2, with a shifted first pass and a third pass when needed.
+// adaptive = true (bases inside the power scheme, whose span is all that the
+// next product uses) runs the second pass only when the first pass shows an
+// ill-conditioned Gram matrix.
+// rfac (optional, f64, 4 consecutive l x l blocks, ld l) receives the factors
+// R1, R2, R3 of the three passes in its first three blocks and their product
+// R = R3 R2 R1 (M_in = M_out R) in the fourth.  A pass that is skipped on
+// the device (the second of an adaptive call, or the third) writes the
+// identity as its factor (CholBody, CholAssembleBody), so the product holds
+// whichever passes ran.
 template <typename TC, class Ex>
 hipError_t orthonormalize(Ex& ex, int tile, TC* M, int64_t ldm, int64_t rows, int l, int Lp, int S,
                           double* part, double* gram, TC* rinv, double* rfac, uint32_t* status,
@@ -91,6 +103,32 @@ hipError_t orthonormalize(Ex& ex, int tile, TC* M, int64_t ldm, int64_t rows, in
     return hipSuccess;
 }
 
+// Pivoted LU normalisation of M (rows x l <= LU_MAX_L) in place, M <- L with
+// M = L U (Alg. normalized_iter; tournament pivoting, see lu.hpp).  cand:
+// 2 cdiv(rows, LU_ROWS) l ints, cnt: 2 cdiv(rows, LU_ROWS) ints; uinv: U^-1
+// (ld Lp, compute type); uout / piv: optional U (f64, ld l) and pivot rows.
+template <typename TC, class Ex>
+hipError_t lu_normalize(Ex& ex, int tile, TC* M, int64_t ldm, int64_t rows, int l, int Lp, int32_t* cand,
+                        int32_t* cnt, TC* uinv, uint32_t* status, double* uout = nullptr, int32_t* piv = nullptr) {
+    if (l > LU_MAX_L || l > rows) return hipErrorInvalidValue;
+    const int64_t leaves = cdiv(rows, LU_ROWS);
+    int32_t *cin = cand, *nin = cnt, *cout = cand + leaves * l, *nout = cnt + leaves;
+    typedef typename LuSelectBody<TC>::Args SelArgs;
+    RSVD_TRY(ex.template run<LuSelectBody<TC>>(SelArgs{M, ldm, rows, l, nullptr, nullptr, 0, 0, cin, nin}));
+    const int G = LU_ROWS / l;                       // >= 2 lists per merge
+    for (int64_t count = leaves; count > 1; count = cdiv(count, G)) {
+        RSVD_TRY(ex.template run<LuSelectBody<TC>>(SelArgs{M, ldm, rows, l, cin, nin, static_cast<int>(count), G,
+                                                           cout, nout}));
+        std::swap(cin, cout);
+        std::swap(nin, nout);
+    }
+    RSVD_TRY(ex.template run<LuFinalBody<TC>>(typename LuFinalBody<TC>::Args{M, ldm, l, cin, uout, uinv, Lp, piv,
+                                                                             status}));
+    // L = M U^-1 in place (one column tile holds all l <= 128 columns)
+    return gemm_plain<TC, TC, TC, MODE_NN>(ex, tile, false, M, ldm, rows, l, uinv, Lp, l, M, ldm, 1, 0, nullptr,
+                                           nullptr, 0);
+}
+
 // Optional event bracketing of the products with A (rsvd_profile_enable).
 inline hipEvent_t pool_event(rsvd_handle_t h) {
     if (h->pool_used == h->event_pool.size()) {
@@ -140,6 +178,8 @@ hipError_t solve_steps(Ex& ex, rsvd_handle_t prof, const Plan& P, const TA* A, i
     TC* xu = at<TC>(work, P.xu);
     double* jk = at<double>(work, P.jk);
     double* mu = o.center ? at<double>(work, P.mu) : nullptr;
+    double* dinv = o.scale ? at<double>(work, P.cinv) : nullptr;      // scaled PCA: D^-1
+    if (dinv && P.gated) return hipErrorInvalidValue;   // (a gated step may issue a product twice)
     double* cholx = P.cholx ? at<double>(work, P.cholx) : nullptr;     // l > 128
     TC* qtmp = P.qtmp ? at<TC>(work, P.qtmp) : nullptr;                   // l > 128
 
@@ -153,12 +193,24 @@ hipError_t solve_steps(Ex& ex, rsvd_handle_t prof, const Plan& P, const TA* A, i
     RSVD_TRY(ex.template run<ClearBody>(ClearBody::Args{status, gated ? 2 : 1, iteration_word(P.q, qmax), o.qsrc,
                                                         qmax}));
 
-    if (mu) {   // column means (implicit centring, Sec. 4.2)
+    if (mu || dinv || o.total_var) {
+        // column means (implicit centring, Sec. 4.2), root mean squares
+        // (scaling, Sec. 4.3) and variances, in one pass over A
         const int S = P.sp.colsum;
         double* mp = at<double>(work, P.mupart);
+        double* var = o.total_var ? at<double>(work, P.cvar) : nullptr;
         RSVD_TRY(ex.template run<ColsumBody<TA>>(typename ColsumBody<TA>::Args{A, lda, m, n, cdiv(m, S), S, mp}));
-        RSVD_TRY(ex.template run<ColmeanBody>(ColmeanBody::Args{mp, S, m, n, mu}));
+        RSVD_TRY(ex.template run<ColmeanBody>(ColmeanBody::Args{mp, S, m, n, o.center, mu, dinv, var,
+                                                                dinv ? at<double>(work, P.cscl) : nullptr,
+                                                                status}));
+        if (var) RSVD_TRY(ex.template run<TotalVarBody>(TotalVarBody::Args{var, n, at<double>(work, P.tvar)}));
     }
+    // Scaled PCA works on (A - 1 mu^T) D^-1 without forming it: the skinny
+    // operand of A X is scaled first (D^-1 X), the result of A^T Y after.
+    auto scale_rows = [&](TC* M, int cols, int64_t ldm) -> hipError_t {
+        if (!dinv) return hipSuccess;
+        return ex.template run<ScaleRowsVecBody<TC>>(typename ScaleRowsVecBody<TC>::Args{M, ldm, n, cols, dinv});
+    };
 
     // Alg. rqb: Omega and the sketch Y = A Omega (unless a wider
     // sketch under the same seed and stream already holds it in its leading
@@ -179,6 +231,7 @@ hipError_t solve_steps(Ex& ex, rsvd_handle_t prof, const Plan& P, const TA* A, i
     TC* xk = P.ldxk ? at<TC>(work, P.xk) : nullptr;                                     // storage-precision products
     auto ax = [&](const TC* X, int arith, Gate gt) -> hipError_t {     // Y (m x Lp) = A X
         const int S = P.sp.nn;
+        RSVD_TRY(scale_rows(const_cast<TC*>(X), l, Lp));
         if (S == 1)
             return timed(prof, 0, pass_flops, nn_bytes, [&] {
                 return gemm_step<TA, TC, MODE_NN>(ex, arith, tile, A, lda, m, n, X, Lp, l, Y, Lp, 1, 0, mu,
@@ -217,27 +270,41 @@ hipError_t solve_steps(Ex& ex, rsvd_handle_t prof, const Plan& P, const TA* A, i
 
     auto aty = [&](TC* dst, int arith, Gate gt) -> hipError_t {     // dst (n x Lp) = A^T Y
         const int S = P.sp.tn;
-        if (S == 1)
-            return timed(prof, 1, pass_flops, tn_bytes, [&] {
+        if (S == 1) {
+            RSVD_TRY(timed(prof, 1, pass_flops, tn_bytes, [&] {
                 return gemm_step<TA, TC, MODE_TN>(ex, arith, tile_tn, A, lda, n, m, Y, Lp, l, dst, Lp, 1, 0, mu,
                                                   nullptr, 0, gt, xp, xk, P.ldxk);
-            });
+            }));
+            return scale_rows(dst, l, Lp);
+        }
         RSVD_TRY(timed(prof, 1, pass_flops, tn_bytes, [&] {
             return gemm_step<TA, TC, MODE_TN>(ex, arith, tile_tn, A, lda, n, m, Y, Lp, l, partc, Lp, S,
                                               static_cast<int64_t>(n) * Lp, mu, nullptr, 0, gt, xp, xk, P.ldxk);
         }));
-        return reduce_step<TC>(ex, partc, S, static_cast<int64_t>(n) * Lp, Lp, n, l, dst, Lp, nullptr, 0, gt);
+        RSVD_TRY(reduce_step<TC>(ex, partc, S, static_cast<int64_t>(n) * Lp, Lp, n, l, dst, Lp, nullptr, 0, gt));
+        return scale_rows(dst, l, Lp);
     };
 
-    // Alg. subspace_iter: q rounds of orth(Y); Z = orth(A^T Y); Y = A Z.
+    // Alg. subspace_iter: q rounds of orth(Y); Z = orth(A^T Y); Y = A Z
+    // (Alg. normalized_iter: the pivoted LU factor L in place of orth).
+    const bool lu = prm->scheme == RSVD_SCHEME_LU;
+    if (lu && (gated || l > LU_MAX_L)) return hipErrorInvalidValue;
+    int32_t* lucand = lu ? at<int32_t>(work, P.lucand) : nullptr;
+    int32_t* lucnt = lu ? at<int32_t>(work, P.lucnt) : nullptr;
     for (int it = 0; it < qmax; ++it) {
         const uint32_t run_bit = 1u << it, last_bit = 1u << (IT_LAST_SHIFT + it);
         const Gate act = gated ? Gate{itw, run_bit | last_bit} : Gate{};
-        RSVD_TRY(orthonormalize<TC>(ex, tile, Y, Lp, m, l, Lp, P.sp.gram_m, partd, gram, rinv, nullptr, status,
-                                    true, act, cholx, qtmp));
+        if (lu)
+            RSVD_TRY(lu_normalize<TC>(ex, tile, Y, Lp, m, l, Lp, lucand, lucnt, rinv, status));
+        else
+            RSVD_TRY(orthonormalize<TC>(ex, tile, Y, Lp, m, l, Lp, P.sp.gram_m, partd, gram, rinv, nullptr, status,
+                                        true, act, cholx, qtmp));
         RSVD_TRY(aty(Z, early, act));
-        RSVD_TRY(orthonormalize<TC>(ex, tile, Z, Lp, n, l, Lp, P.sp.gram_n, partd, gram, rinv, nullptr, status,
-                                    true, act, cholx, qtmp));
+        if (lu)
+            RSVD_TRY(lu_normalize<TC>(ex, tile, Z, Lp, n, l, Lp, lucand, lucnt, rinv, status));
+        else
+            RSVD_TRY(orthonormalize<TC>(ex, tile, Z, Lp, n, l, Lp, P.sp.gram_n, partd, gram, rinv, nullptr, status,
+                                        true, act, cholx, qtmp));
         RSVD_TRY(ax_step(Z, it == P.q - 1, run_bit, last_bit));
     }
     // Alg. rqb: Q = qr(Y); B^T = A^T Q.
@@ -285,9 +352,13 @@ hipError_t solve_steps(Ex& ex, rsvd_handle_t prof, const Plan& P, const TA* A, i
                                               0)));
     RSVD_TRY(ex.template run<SignLiftBody<TC>>(typename SignLiftBody<TC>::Args{
         V, ldv, n, l, k, jk, sigma, o.scale_u, xu, Lp, P.kp}));
-    if (o.U)
-        RSVD_TRY((gemm_plain<TC, TC, TC, MODE_NN>(ex, tile, false, Y, Lp, m, l, xu, P.kp, k, static_cast<TC*>(o.U), o.ldu,
-                                                  1, 0, nullptr, nullptr, 0)));
+    // PCA: x = U S lands in the whitened output when only that is wanted
+    // (scaled in place below)
+    TC* xout = static_cast<TC*>(o.U ? o.U : o.xwhite);
+    const int64_t ldxo = o.U ? o.ldu : o.ldxw;
+    if (xout)
+        RSVD_TRY((gemm_plain<TC, TC, TC, MODE_NN>(ex, tile, false, Y, Lp, m, l, xu, P.kp, k, xout, ldxo, 1, 0,
+                                                  nullptr, nullptr, 0)));
     // A-posteriori bound from r Gaussian probes w (Halko, Martinsson & Tropp
     // 2011, Sec. 4.3): one more pass over A for A w, then U (S (V^T w)).
     double* est = nullptr;
@@ -309,6 +380,7 @@ hipError_t solve_steps(Ex& ex, rsvd_handle_t prof, const Plan& P, const TA* A, i
         }
         RSVD_TRY(ex.template run<OmegaBody<TC>>(typename OmegaBody<TC>::Args{
             n, r, 32, prm->seed, stream_id ^ 0x80000000u, RSVD_NORMAL, eOm, 32}));
+        RSVD_TRY(scale_rows(eOm, r, 32));        // (A - 1 mu^T) D^-1 w
         RSVD_TRY((gemm_step<TA, TC, MODE_NN>(ex, late, 32, A, lda, m, n, eOm, 32, r, eY, 32, 1, 0, mu, nullptr, 0,
                                              Gate{}, xp)));
         const int S = P.sp.gram_n;
@@ -329,11 +401,38 @@ hipError_t solve_steps(Ex& ex, rsvd_handle_t prof, const Plan& P, const TA* A, i
                                                                                   epart}));
         RSVD_TRY(ex.template run<EstBody>(EstBody::Args{epart, P.est_split, r, est}));
     }
+    if (o.loadings || o.xwhite)
+        RSVD_TRY(ex.template run<PcaOutBody<TC>>(typename PcaOutBody<TC>::Args{
+            V, ldv, static_cast<TC*>(o.loadings), o.ldl, n, xout, ldxo, static_cast<TC*>(o.xwhite), o.ldxw, m, k,
+            sigma, static_cast<double>(m - 1)}));
     RSVD_TRY(ex.template run<FinalizeBody<TC>>(typename FinalizeBody<TC>::Args{
         sigma, k, o.S, o.eigvals, o.sdev, static_cast<double>(m - 1), mu, n, static_cast<TC*>(o.center_out),
-        status, o.info, l, P.q, P.p, est, o.qsrc}));
+        status, o.info, l, P.q, P.p, est, o.qsrc, dinv ? at<double>(work, P.cscl) : nullptr,
+        static_cast<TC*>(o.scale_out), o.total_var ? at<double>(work, P.tvar) : nullptr, o.total_var}));
     if (o.stamps && (stamp_sel & 2)) RSVD_TRY(ex.template run<StampBody>(StampBody::Args{o.stamps + 1}));
     return hipSuccess;
+}
+
+// x = ((A - 1 c^T) D^-1) W for new rows A (the predict step of Sec. 4.4):
+// the rows of W are divided by the scales once, the centre is subtracted
+// while A's tiles are staged (as in the solve), and the n-reduction is split
+// like the solve's A X when the row tiles alone would leave the device idle.
+template <typename TA, typename TC>
+hipError_t predict_steps(rsvd_handle_t h, const PredictPlan& P, const TA* A, int64_t lda, const TC* rot,
+                         int64_t ldr, const TC* center, const TC* scale, TC* x, int64_t ldx, void* work) {
+    SingleExec ex{h->stream};
+    double* mu = center ? at<double>(work, P.mu) : nullptr;
+    TC* W = at<TC>(work, P.w);
+    RSVD_TRY(ex.template run<PredictPrepBody<TC>>(typename PredictPrepBody<TC>::Args{
+        rot, ldr, center, scale, P.n, P.k, P.kp, mu, W}));
+    const int tc = tile_class(P.k, sizeof(TC) == 4);
+    if (P.S == 1)
+        return gemm_step<TA, TC, MODE_NN>(ex, 0, tc, A, lda, P.m, P.n, W, P.kp, P.k, x, ldx, 1, 0, mu, nullptr, 0);
+    TC* part = at<TC>(work, P.part);
+    const int64_t stride = P.m * P.kp;
+    RSVD_TRY((gemm_step<TA, TC, MODE_NN>(ex, 0, tc, A, lda, P.m, P.n, W, P.kp, P.k, part, P.kp, P.S, stride, mu,
+                                        nullptr, 0)));
+    return reduce_step<TC>(ex, part, P.S, stride, P.kp, P.m, P.k, x, ldx);
 }
 
 #define RSVD_DEFINE_SOLVE(NAME, TA, TC)                                                                 \
@@ -348,6 +447,13 @@ hipError_t solve_steps(Ex& ex, rsvd_handle_t prof, const Plan& P, const TA* A, i
                                    void* work) {                                                       \
         return solve_steps<TA, TC>(rec, nullptr, P, static_cast<const TA*>(A), lda, prm, stream_id, o, \
                                    work);                                                              \
+    }                                                                                                  \
+    hipError_t predict_##NAME(rsvd_handle_t h, const PredictPlan& P, const void* A, int64_t lda,       \
+                              const void* rot, int64_t ldr, const void* center, const void* scale,      \
+                              void* x, int64_t ldx, void* work) {                                       \
+        return predict_steps<TA, TC>(h, P, static_cast<const TA*>(A), lda, static_cast<const TC*>(rot), ldr, \
+                                     static_cast<const TC*>(center), static_cast<const TC*>(scale),     \
+                                     static_cast<TC*>(x), ldx, work);                                   \
     }
 
 }  // namespace rsvd

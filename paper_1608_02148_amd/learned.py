@@ -27,6 +27,7 @@ count, Adam step, seed, training-set size, 8-byte hash of the training
 features and labels), then theta, adam_m, adam_v as little-endian float32.
 """
 import argparse
+import ctypes
 import hashlib
 import json
 import math
@@ -212,19 +213,29 @@ def save_checkpoint(path, tr, seed, n_train, digest):
             f.write(t.detach().cpu().numpy().astype("<f4").tobytes())
 
 
-def load_checkpoint(path=DEFAULT_CHECKPOINT, device="cuda"):
-    """(theta tensor on device, header dict).  Raises on a malformed file."""
-    raw = open(path, "rb").read()
-    if len(raw) != 64 + 3 * 4 * L.MLP_PARAMS or raw[:8] != MAGIC:
-        raise ValueError(f"{path}: not a selector checkpoint")
-    ver, npar, step, seed, ntrain = struct.unpack("<IIIQQ", raw[8:36])
-    if ver != 1 or npar != L.MLP_PARAMS:
-        raise ValueError(f"{path}: unsupported checkpoint version or size")
-    vals = np.frombuffer(raw, dtype="<f4", offset=64)
-    theta = torch.tensor(vals[:npar].copy(), device=device)
-    if not torch.all(torch.isfinite(theta)):
-        raise ValueError(f"{path}: non-finite weights")
-    return theta, dict(step=step, seed=seed, n_train=ntrain, digest=raw[36:44].hex())
+def load_checkpoint(path=DEFAULT_CHECKPOINT, device="cuda", adam=False):
+    """(theta tensor on device, header dict), read and checked by the
+    library's rsvd_mlp_load; with adam=True also the Adam moments (theta,
+    adam_m, adam_v).  Raises ValueError on a malformed file."""
+    lib = L.load()
+    hdr = L.MlpHeader()
+    # check the file first (no device access), then copy it to the device
+    h = ctypes.c_void_p()
+    L.check(lib.rsvd_create(ctypes.byref(h), None), "rsvd_create")
+    try:
+        st = lib.rsvd_mlp_load(h, os.fsencode(path), None, None, None, ctypes.byref(hdr))
+    finally:
+        lib.rsvd_destroy(h)
+    if st != 0:
+        raise ValueError(f"{path}: not a usable selector checkpoint ({L.STATUS.get(st, st)})")
+    theta = torch.empty(L.MLP_PARAMS, dtype=torch.float32, device=device)
+    m = torch.empty_like(theta) if adam else None
+    v = torch.empty_like(theta) if adam else None
+    L.check(lib.rsvd_mlp_load(api.handle(theta.device), os.fsencode(path), theta.data_ptr(),
+                              m.data_ptr() if adam else None, v.data_ptr() if adam else None,
+                              ctypes.byref(hdr)), "rsvd_mlp_load")
+    info = dict(step=hdr.step, seed=hdr.seed, n_train=hdr.n_train, digest=bytes(hdr.digest).hex())
+    return ((theta, m, v) if adam else theta), info
 
 
 # ------------------------------------------------------------------ learned solve

@@ -14,6 +14,7 @@ c_void_p, c_size_t, c_double = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_double
 RSVD_F64, RSVD_F32, RSVD_BF16 = 0, 1, 2
 SDIST = {"normal": 0, "unif": 1, "rademacher": 2}
 PRECISION = {"plain": 0, "bf16_mixed": 1}
+SCHEME = {"qr": 0, "lu": 1}
 ARITH = {"storage": 0, "bf16": 1, "split": 2}
 
 STATUS = {
@@ -21,14 +22,15 @@ STATUS = {
     -3: "HIP runtime error", -4: "non-finite values reached a Gram matrix",
     -5: "numerical breakdown after the shifted Cholesky",
 }
-FLAG_CHOL_SHIFT, FLAG_DEGENERATE, FLAG_NONFINITE, FLAG_JACOBI_SLOW = 1, 2, 4, 8
+FLAG_CHOL_SHIFT, FLAG_DEGENERATE, FLAG_NONFINITE, FLAG_JACOBI_SLOW, FLAG_ZERO_SCALE = 1, 2, 4, 8, 16
 MAX_L = 128              # batches and kernel-level entry points
 MAX_L_SINGLE = 256       # rsvd_run / rpca_run
 
 
 class Params(ctypes.Structure):
     _fields_ = [("p", c_int32), ("q", c_int32), ("seed", c_uint64), ("stream_id", c_uint32),
-                ("sdist", c_int32), ("precision", c_int32), ("probes", c_int32), ("reserved", c_int32 * 2)]
+                ("sdist", c_int32), ("precision", c_int32), ("probes", c_int32), ("scheme", c_int32),
+                ("reserved", c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -39,6 +41,22 @@ class Info(ctypes.Structure):
 class KernelStat(ctypes.Structure):
     _fields_ = [("count", c_int32), ("reserved", c_int32), ("total_ms", c_double),
                 ("flops", c_double), ("bytes", c_double)]
+
+
+class RpcaOptions(ctypes.Structure):
+    _fields_ = [("center", c_int32), ("scale", c_int32), ("reserved", c_int32 * 2)]
+
+
+class RpcaOutputs(ctypes.Structure):
+    _fields_ = [("rotation", c_void_p), ("ldr", c_int64), ("eigvals", c_void_p), ("sdev", c_void_p),
+                ("x", c_void_p), ("ldx", c_int64), ("x_white", c_void_p), ("ldxw", c_int64),
+                ("loadings", c_void_p), ("ldl", c_int64), ("center", c_void_p), ("scale", c_void_p),
+                ("total_var", c_void_p)]
+
+
+class MlpHeader(ctypes.Structure):
+    _fields_ = [("version", c_uint32), ("params", c_uint32), ("step", c_uint32), ("reserved", c_uint32),
+                ("seed", c_uint64), ("n_train", c_uint64), ("digest", ctypes.c_uint8 * 8)]
 
 
 class BatchDesc(ctypes.Structure):
@@ -77,6 +95,11 @@ _PROTOS = {
     "rpca_run": (c_int32, [c_void_p, c_int32, c_int64, c_int64, c_void_p, c_int64, c_int32, c_int32,
                            c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_int64, c_void_p,
                            c_void_p, c_size_t, c_void_p]),
+    "rpca_run_ex": (c_int32, [c_void_p, c_int32, c_int64, c_int64, c_void_p, c_int64, c_int32, c_void_p,
+                              c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "rpca_predict_workspace_size": (c_int32, [c_void_p, c_int32, c_int64, c_int64, c_int32, c_void_p]),
+    "rpca_predict": (c_int32, [c_void_p, c_int32, c_int64, c_int64, c_void_p, c_int64, c_int32, c_void_p,
+                               c_int64, c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_size_t]),
     "rsvd_sync_info": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "rsvd_batch_create": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_int32, c_void_p,
                                     c_void_p]),
@@ -95,18 +118,21 @@ _PROTOS = {
     "rsvd_mlp_forward": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
     "rsvd_mlp_train_step": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, ctypes.c_float, c_int32,
                                       c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t]),
+    "rsvd_mlp_load": (c_int32, [c_void_p, ctypes.c_char_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "rsvd_profile_enable": (c_int32, [c_void_p, c_int32]),
     "rsvd_profile_collect": (c_int32, [c_void_p, c_void_p]),
     "rsvd_philox_words": (c_int32, [c_void_p, c_int64, c_int32, c_uint64, c_uint32, c_void_p]),
     "rsvd_test_matrix": (c_int32, [c_void_p, c_int32, c_int64, c_int32, c_uint64, c_uint32, c_int32,
                                    c_void_p, c_int64]),
     "rsvd_gemm_nn": (c_int32, [c_void_p, c_int32, c_int32, c_int64, c_int64, c_int32, c_void_p, c_int64,
-                               c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_size_t]),
+                               c_void_p, c_int64, c_void_p, c_int64, c_int32, c_void_p, c_size_t]),
     "rsvd_gemm_tn": (c_int32, [c_void_p, c_int32, c_int32, c_int64, c_int64, c_int32, c_void_p, c_int64,
                                c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_size_t]),
     "rsvd_orthonormalize": (c_int32, [c_void_p, c_int32, c_int64, c_int32, c_void_p, c_int64, c_void_p,
                                       c_void_p, c_void_p, c_size_t]),
     "rsvd_block_workspace_size": (c_int32, [c_void_p, c_int32, c_int64, c_int64, c_int32, c_void_p]),
+    "rsvd_lu_normalize": (c_int32, [c_void_p, c_int32, c_int64, c_int32, c_void_p, c_int64, c_void_p, c_void_p,
+                                    c_void_p, c_void_p, c_size_t]),
     "rsvd_small_svd": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                  c_void_p, c_size_t]),
 }

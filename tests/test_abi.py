@@ -303,3 +303,77 @@ def test_single_solve_width_limit(lib, handle):
     assert _ws(lib, handle, L.RSVD_F32, 3000, 1000, 236, p=20)[0] == 0      # l = 256
     assert _ws(lib, handle, L.RSVD_F32, 3000, 1000, 237, p=20)[0] == -2     # l = 257
     assert _create(lib, handle, [(3000, 1000, 200)])[0] == -2          # batches: l <= 128
+
+
+def _checkpoint_bytes(version=1, nparams=13583, values=None, magic=b"RSVDMLP1"):
+    import struct
+    import numpy as np
+    hdr = magic + struct.pack("<IIIQQ", version, nparams, 77, 5, 8192) + bytes(range(8))
+    hdr += b"\0" * (64 - len(hdr))
+    vals = np.zeros(3 * 13583, dtype="<f4") if values is None else values
+    return hdr + vals.astype("<f4").tobytes()
+
+
+def test_mlp_load_checks_the_file_without_a_device(lib, handle, tmp_path):
+    """rsvd_mlp_load reads and checks the whole checkpoint before any device
+    access: theta = NULL checks only; a bad file fails with theta set too."""
+    import numpy as np
+    good = tmp_path / "good.bin"
+    good.write_bytes(_checkpoint_bytes(values=np.linspace(-1, 1, 3 * 13583)))
+    hdr = L.MlpHeader()
+    assert lib.rsvd_mlp_load(handle, str(good).encode(), None, None, None, ctypes.byref(hdr)) == 0
+    assert (hdr.version, hdr.params, hdr.step, hdr.seed, hdr.n_train) == (1, 13583, 77, 5, 8192)
+    assert bytes(hdr.digest) == bytes(range(8))
+    fake = ctypes.c_void_p(16)          # never dereferenced: every case below fails first
+    cases = {
+        "absent.bin": None,
+        "magic.bin": _checkpoint_bytes(magic=b"NOTMLP01"),
+        "version.bin": _checkpoint_bytes(version=2),
+        "count.bin": _checkpoint_bytes(nparams=100),
+        "short.bin": _checkpoint_bytes()[:-4],
+        "long.bin": _checkpoint_bytes() + b"\0",
+        "header.bin": b"RSVDMLP1\x01",
+    }
+    want = {"absent.bin": -1, "magic.bin": -2, "version.bin": -2, "count.bin": -2, "short.bin": -1,
+            "long.bin": -1, "header.bin": -1}
+    for name, raw in cases.items():
+        p = tmp_path / name
+        if raw is not None:
+            p.write_bytes(raw)
+        assert lib.rsvd_mlp_load(handle, str(p).encode(), fake, None, None, None) == want[name], name
+    for bad in (np.nan, np.inf):
+        vals = np.zeros(3 * 13583)
+        vals[2 * 13583 + 5] = bad                 # in adam_v
+        p = tmp_path / "nonfinite.bin"
+        p.write_bytes(_checkpoint_bytes(values=vals))
+        assert lib.rsvd_mlp_load(handle, str(p).encode(), fake, fake, fake, None) == -1
+    assert lib.rsvd_mlp_load(handle, None, fake, None, None, None) == -1
+    assert lib.rsvd_mlp_load(None, str(good).encode(), None, None, None, None) == -1
+    assert lib.rsvd_mlp_load(handle, str(good).encode(), None, fake, None, None) == -1
+
+
+def test_committed_checkpoint_passes_the_library_check(lib, handle):
+    from paper_1608_02148_amd import learned
+    hdr = L.MlpHeader()
+    assert lib.rsvd_mlp_load(handle, learned.DEFAULT_CHECKPOINT.encode(), None, None, None,
+                             ctypes.byref(hdr)) == 0
+    assert hdr.params == 13583 and hdr.step > 0 and hdr.n_train > 0
+
+
+def test_power_scheme_rules(lib, handle):
+    """LU normalisation: l <= 128 and single solves only; unknown schemes are
+    invalid (all checked before any launch)."""
+    st, with_lu = _ws(lib, handle, L.RSVD_F32, 5000, 1000, 100, 20, 2, scheme=1)
+    assert st == 0 and with_lu > _ws(lib, handle, L.RSVD_F32, 5000, 1000, 100, 20, 2)[1]   # pivot lists
+    assert _ws(lib, handle, L.RSVD_F32, 5000, 1000, 120, 20, 2, scheme=1)[0] == -2
+    assert _ws(lib, handle, L.RSVD_F32, 5000, 1000, 10, 10, 2, scheme=2)[0] == -1
+    prm = L.Params()
+    lib.rsvd_default_params(ctypes.byref(prm))
+    prm.scheme = 1
+    d = (L.BatchDesc * 1)()
+    d[0].A, d[0].lda, d[0].m, d[0].n, d[0].k = 256, 100, 300, 100, 10
+    d[0].S = 512
+    b = ctypes.c_void_p()
+    nbytes = ctypes.c_size_t()
+    assert lib.rsvd_batch_create(handle, L.RSVD_F32, 1, d, ctypes.byref(prm), 0, ctypes.byref(b),
+                                 ctypes.byref(nbytes)) == -2

@@ -218,3 +218,39 @@ def test_small_svd_is_exactly_scale_invariant(gpu_lib, c, shift):
     assert int(_np(f1)[0]) & 8 == 0
     se = np.linalg.svd(R, compute_uv=False)     # (ill-conditioned R: absolute floor as above)
     np.testing.assert_allclose(np.ldexp(_np(s1), -shift), se, rtol=1e-12, atol=1e-14 * se[0])
+
+
+@pytest.mark.parametrize("dt,arith", [("f64", "storage"), ("f32", "storage"), ("bf16", "storage"),
+                                      ("f32", "bf16"), ("f32", "split"), ("bf16", "split")])
+@pytest.mark.parametrize("m,K,c,splits", [(2000, 4100, 100, 3), (777, 3001, 220, 4), (129, 2048, 30, 2),
+                                          (300, 257, 64, 4)])
+def test_gemm_nn_split_k_exact_integers(gpu_lib, dt, arith, m, K, c, splits):
+    """A X with its K-reduction split into partial blocks (the form rsvd_run
+    takes when the row tiles alone leave most of the device idle), summed in
+    chunk order: on small integers every partial sum is exact, so the result
+    equals A X bit for bit whatever the split; at (300, 257) the chunks are
+    rounded up to the tile's K-step, so the last ones reach past K (partly
+    or wholly) and must contribute zeros."""
+    from paper_1608_02148_amd import api
+    rng = np.random.default_rng(m + K + c + splits)
+    A = _int_matrix(rng, (m, K), -4, 4)
+    X = _int_matrix(rng, (K, c), -4, 4)
+    xdt = torch.float64 if dt == "f64" else torch.float32
+    Ag = torch.tensor(A, dtype=DT[dt], device=DEV)
+    Xg = torch.tensor(X, dtype=xdt, device=DEV)
+    Y = _np(api.gemm_nn(Ag, Xg, arith, splits=splits))
+    assert np.array_equal(Y, A @ X)
+
+
+@pytest.mark.parametrize("splits", [0, 2, 3, 4])
+def test_gemm_nn_split_k_random_f64(gpu_lib, splits):
+    """Random f64 operands: each split (and the split rsvd_run picks, 0) agrees
+    with the exact product to the rounding of a K-term dot product."""
+    from paper_1608_02148_amd import api
+    rng = np.random.default_rng(11 + splits)
+    m, K, c = 20000, 4096, 120
+    A = rng.standard_normal((m, K))
+    X = rng.standard_normal((K, c))
+    Y = _np(api.gemm_nn(torch.tensor(A, device=DEV), torch.tensor(X, device=DEV), splits=splits))
+    ref = A @ X
+    np.testing.assert_allclose(Y, ref, rtol=0, atol=K * 2.0 ** -52 * np.sqrt(K) * 4)

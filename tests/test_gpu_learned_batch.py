@@ -39,8 +39,9 @@ def _mats(dtype, seed0):
     return out
 
 
-def q_rule(prob, tau):
-    """Host statement of the device rule (float64 sums in class order)."""
+def q_rule(prob, tau, p_solve=20):
+    """Host statement of the device rule (float64 sums in class order): the
+    fewest q whose pairs (q' <= q, p' <= p_solve) hold mass >= tau, else 4."""
     out = []
     for pb in prob:
         if tau <= 0:
@@ -48,8 +49,9 @@ def q_rule(prob, tau):
             continue
         cum, pick = 0.0, 4
         for q in range(5):
-            for c in range(3 * q, 3 * q + 3):
-                cum += float(pb[c])
+            for j, pp in enumerate((5, 10, 20)):
+                if pp <= p_solve:
+                    cum += float(pb[3 * q + j])
             if cum >= tau:
                 pick = q
                 break
@@ -83,25 +85,28 @@ def test_fallback_q3_matches_oracle_f64():
     bt.close()
 
 
-@pytest.mark.parametrize("tau", [0.0, 0.5, 0.8, 0.95])
-def test_network_choice_and_solves_f32(tau):
+@pytest.mark.parametrize("tau,p", [(0.0, 20), (0.5, 20), (0.8, 20), (0.95, 20), (0.8, 10), (0.5, 5)])
+def test_network_choice_and_solves_f32(tau, p):
+    """The device's choice of q equals the host rule for the solves'
+    oversampling p (pairs needing more oversampling than p do not count as
+    covered), and each solve equals the oracle's with that (q, p)."""
     from paper_1608_02148_amd import api
     from paper_1608_02148_amd import learned as L
     theta, _ = L.load_checkpoint(device=DEV)
     As = _mats(torch.float32, 300)
     ks = [k for *_, k in SHAPES]
-    bt = api.Batch(As, ks, p=20, seed=5, learned=True, theta=theta, tau=tau, infos=True)
+    bt = api.Batch(As, ks, p=p, seed=5, learned=True, theta=theta, tau=tau, infos=True)
     bt.run()
     q = bt.choices()
     # the same features as an RSVD_BATCH_FEATURES batch under the same seed
     fb = api.Batch(As, ks, seed=5, features=True)
     fb.run()
     prob, _ = api.mlp_forward(theta, fb.features)
-    np.testing.assert_array_equal(q, q_rule(prob.cpu().numpy(), tau))
+    np.testing.assert_array_equal(q, q_rule(prob.cpu().numpy(), tau, p))
     infos = bt.infos()
     for b, (A, k) in enumerate(zip(As, ks)):
         assert infos[b].q == q[b]
-        _, so, _ = orc.rsvd(_np(A), k, p=20, q=int(q[b]), seed=5, stream_id=b)
+        _, so, _ = orc.rsvd(_np(A), k, p=p, q=int(q[b]), seed=5, stream_id=b)
         _check_f32(_np(bt.S[b]), so)
     bt.close()
     fb.close()

@@ -110,3 +110,21 @@ def test_training_learns_a_separable_rule():
     _, cls = api.mlp_forward(tr.theta, Xg)
     acc = float(np.mean(_np(cls).astype(int) == y))
     assert last < 0.3 * first and acc > 0.9, (first, last, acc)
+
+
+def test_mlp_load_round_trip(gpu_lib, tmp_path):
+    """A checkpoint written from device vectors reads back bit for bit through
+    rsvd_mlp_load (theta and both Adam moments)."""
+    import struct
+    from paper_1608_02148_amd import learned as L
+    g = torch.Generator(device="cuda")
+    g.manual_seed(3)
+    vecs = [torch.randn(13583, generator=g, device="cuda") for _ in range(3)]
+    path = tmp_path / "ck.bin"
+    hdr = b"RSVDMLP1" + struct.pack("<IIIQQ", 1, 13583, 9, 4, 123) + b"\x01" * 8
+    path.write_bytes(hdr + b"\0" * (64 - len(hdr)) + b"".join(v.cpu().numpy().astype("<f4").tobytes()
+                                                              for v in vecs))
+    (theta, m, v), info = L.load_checkpoint(str(path), device="cuda", adam=True)
+    torch.cuda.synchronize()
+    assert torch.equal(theta, vecs[0]) and torch.equal(m, vecs[1]) and torch.equal(v, vecs[2])
+    assert info["step"] == 9 and info["n_train"] == 123 and info["seed"] == 4

@@ -201,3 +201,25 @@ def test_rpca_full_width_equals_covariance_eigendecomposition():
     np.testing.assert_allclose(res["eigvals"], w[:10], rtol=1e-11)
     np.testing.assert_allclose(np.abs(np.sum(res["rotation"] * W[:, :10], axis=0)), 1.0, atol=1e-9)
     np.testing.assert_allclose(res["x"], X @ res["rotation"], atol=1e-10)
+
+
+@pytest.mark.parametrize("m,n,k,p,q,want", [
+    (2000, 1000, 20, 10, 2, 2.18),        # 2000 x 1000, k = 20, p = 10, q = 2
+    (100000, 5000, 100, 20, 2, 2.55),     # 100000 x 5000, k = 100, p = 20, q = 2
+    (200000, 20000, 200, 20, 1, 6.60),    # 200000 x 20000, k = 200, p = 20, q = 1..3
+    (200000, 20000, 200, 20, 2, 3.10),
+    (200000, 20000, 200, 20, 3, 2.25),
+])
+def test_expected_error_factor_values(m, n, k, p, q, want):
+    """Eq. rsvd_expected_error evaluated independently (by hand, to two
+    decimals) at the benchmark workloads' sizes."""
+    assert orc.expected_error_factor(m, n, k, p, q) == pytest.approx(want, abs=0.005)
+
+
+def test_expected_error_factor_closed_form():
+    """k = 1, p = 2, min(m, n) = 10, q = 0: the bracket is
+    1 + sqrt(1/1) + e sqrt(3) / 2 * sqrt(9) = 2 + 1.5 e sqrt(3) = 9.06230...;
+    with q the bracket's (2q+1)-th root: q = 1 gives 2.08487...."""
+    assert orc.expected_error_factor(10, 12, 1, 2, 0) == pytest.approx(9.06230, abs=1e-5)
+    assert orc.expected_error_factor(12, 10, 1, 2, 1) == pytest.approx(9.06230 ** (1 / 3), abs=1e-5)
+    assert orc.expected_error_factor(12, 10, 1, 2, 1) == pytest.approx(2.08487, abs=1e-5)
