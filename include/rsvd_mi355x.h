@@ -238,6 +238,22 @@ int rpca_predict(rsvd_handle_t handle, int32_t dtype, int64_t m, int64_t n, cons
                  int64_t lda, int32_t k, const void* rotation, int64_t ldr, const void* center,
                  const void* scale, void* x, int64_t ldx, void* work, size_t work_bytes);
 
+/* rsvd_run for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops, harnesses that forbid allocation): same
+ * arguments, results and rules as rsvd_run, without `work` / `work_bytes`.
+ * The workspace is a fixed device array of RSVD_NOALLOC_SCRATCH_BYTES that
+ * the library holds on each device it runs on, from the first call there
+ * until the process ends; the call itself allocates nothing.  Problems whose
+ * rsvd_workspace_size exceeds it return RSVD_ERR_UNSUPPORTED before any
+ * launch.  Every call on one device shares the array: calls that overlap on
+ * a device (different streams or threads) race and must be serialised by the
+ * caller.  Event timing (rsvd_profile_enable) is not recorded for these
+ * calls. */
+#define RSVD_NOALLOC_SCRATCH_BYTES (256ull << 20)
+int rsvd_run_noalloc(rsvd_handle_t handle, int32_t dtype, int64_t m, int64_t n,
+                     const void* A, int64_t lda, int32_t k, const rsvd_params* params,
+                     void* U, int64_t ldu, double* S, void* V, int64_t ldv, rsvd_info* info);
+
 /* Synchronise the handle's stream, copy the device record `dinfo` to the host
  * record `hinfo`, and map its flags to a status: RSVD_ERR_NONFINITE when
  * non-finite data reached a Gram matrix, RSVD_ERR_BREAKDOWN when a column

@@ -101,6 +101,8 @@ _PROTOS = {
     "rpca_predict": (c_int32, [c_void_p, c_int32, c_int64, c_int64, c_void_p, c_int64, c_int32, c_void_p,
                                c_int64, c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_size_t]),
     "rsvd_sync_info": (c_int32, [c_void_p, c_void_p, c_void_p]),
+    "rsvd_run_noalloc": (c_int32, [c_void_p, c_int32, c_int64, c_int64, c_void_p, c_int64, c_int32, c_void_p,
+                                   c_void_p, c_int64, c_void_p, c_void_p, c_int64, c_void_p]),
     "rsvd_batch_create": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_int32, c_void_p,
                                     c_void_p]),
     "rsvd_batch_bind": (c_int32, [c_void_p, c_void_p, c_size_t]),
