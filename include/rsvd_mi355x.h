@@ -238,6 +238,79 @@ int rpca_predict(rsvd_handle_t handle, int32_t dtype, int64_t m, int64_t n, cons
                  int64_t lda, int32_t k, const void* rotation, int64_t ldr, const void* center,
                  const void* scale, void* x, int64_t ldx, void* work, size_t work_bytes);
 
+/* ---- Robust PCA (Alg. rpca, Sec. 5.2) -------------------------------------
+ * A = L + S with L low rank and S sparse, by the inexact augmented Lagrange
+ * multiplier method (Eq. IALM) with the randomized SVD of rsvd_run (params:
+ * p, q, seed, stream_id, sdist; plain precision) at a target rank that the
+ * method predicts each iteration.  Where the paper defers to Lin, Chen & Ma
+ * (2010, arXiv:1009.5055) this follows their inexact ALM: mu starts at
+ * mu0_scale / ||A||_2 (the listing's 1.25 ||A||_2 read as 1.25 / ||A||_2) and
+ * grows by rho per iteration up to 1e7 times its start; the multiplier starts
+ * at A / max(||A||_2, ||A||_max / lambda); the target rank starts at 2 and is
+ * l + 1 when fewer than k singular values exceed 1/mu (l of them), else
+ * l + round(0.05 min(m, n)), clamped to [1, k_max]; the iteration stops when
+ * ||A - L - S||_F / ||A||_F < tol or after maxiter iterations.  ||A||_2 is the
+ * randomized SVD's rank-1 estimate.  The randomized SVD is used at every
+ * rank (the paper switches to a deterministic SVD above min(m, n) / 4; here
+ * the rank is capped at k_max instead).
+ * A, L, S: m x n row-major (f64 or f32, lda / ldl / lds >= n); L and S are
+ * written.  The host reads two scalars per iteration (the singular values
+ * and the residual), so the call synchronises the handle's stream and
+ * returns when done; result (host, may be NULL) receives the iteration
+ * count, the final rank l and target rank k, the relative residual and the
+ * lambda used.  work: rrpca_workspace_size bytes (two m x n matrices plus
+ * the randomized SVD's workspace at rank k_max). */
+typedef struct {
+    double  lambda;     /* weight of ||S||_1; <= 0: max(m, n)^-1/2 (Sec. 5.4)     */
+    double  tol;        /* relative residual to stop at (default 1e-5)            */
+    double  rho;        /* growth of mu per iteration (default 1.6)               */
+    double  mu0_scale;  /* mu starts at mu0_scale / ||A||_2 (default 1.25)       */
+    int32_t maxiter;    /* default 50                                            */
+    int32_t k_max;      /* largest target rank; <= 0: min(m, n) - 1, at most
+                           RSVD_MAX_L_SINGLE - p                                  */
+} rrpca_options;
+
+typedef struct {
+    int32_t iterations, rank, k, reserved;
+    double  residual;   /* ||A - L - S||_F / ||A||_F after the last iteration      */
+    double  lambda;
+} rrpca_result;
+
+void rrpca_default_options(rrpca_options* opt);
+int rrpca_workspace_size(rsvd_handle_t handle, int32_t dtype, int64_t m, int64_t n,
+                         const rrpca_options* opt, const rsvd_params* params, size_t* bytes);
+int rrpca_run(rsvd_handle_t handle, int32_t dtype, int64_t m, int64_t n, const void* A,
+              int64_t lda, const rrpca_options* opt, const rsvd_params* params, void* L,
+              int64_t ldl, void* S, int64_t lds, void* work, size_t work_bytes,
+              rrpca_result* result);
+
+/* ---- Interpolative and CUR decompositions (Sec. 6) -----------------------
+ * rid_run, Alg. rid: [Q, B] = rqb(A, k, p, q) (the passes of rsvd_run up to
+ * B = Q^T A, params as there, plain precision), then the column ID of B
+ * (Alg. id): k steps of column-pivoted QR (at each step the column with the
+ * largest remaining norm; lowest index on ties), T = S11^-1 S12 (S = the
+ * triangular factor; a zero diagonal entry of S11 gives a zero row of T),
+ * Z[:, P] = [I_k, T], J = P[:k], and C = A[:, J].  A ~ C Z.
+ * rcur_run, Alg. rcur: C, Z, J as rid_run, then k steps of column-pivoted QR
+ * of C^T choose the rows I, R = A[I, :], U = Z pinv(R) (R of full row rank:
+ * pinv(R) = Q_r T_r^-T from the QR R^T = Q_r T_r).  A ~ C U R.  k <= RSVD_MAX_L.
+ * A: m x n (dtype, lda >= n); C m x k (ldc >= k), Z k x n (ldz >= n), U k x k
+ * (ldu >= k), R k x n (ldr >= n), element type as rsvd_run's U (C and R hold
+ * A's entries exactly); J, I: device int32 arrays of k column / row indices
+ * in pivot order.  rid_run: C and Z may be NULL (indices only).  The row ID
+ * is the column ID of A^T (pass the transpose).  work: rid_workspace_size
+ * bytes with cur = 0 for rid_run, 1 for rcur_run.  Asynchronous on the
+ * handle's stream; errors as rsvd_run. */
+int rid_workspace_size(rsvd_handle_t handle, int32_t dtype, int64_t m, int64_t n, int32_t k,
+                       const rsvd_params* params, int32_t cur, size_t* bytes);
+int rid_run(rsvd_handle_t handle, int32_t dtype, int64_t m, int64_t n, const void* A,
+            int64_t lda, int32_t k, const rsvd_params* params, int32_t* J, void* C,
+            int64_t ldc, void* Z, int64_t ldz, void* work, size_t work_bytes);
+int rcur_run(rsvd_handle_t handle, int32_t dtype, int64_t m, int64_t n, const void* A,
+             int64_t lda, int32_t k, const rsvd_params* params, int32_t* J, int32_t* I,
+             void* C, int64_t ldc, void* U, int64_t ldu, void* R, int64_t ldr, void* work,
+             size_t work_bytes);
+
 /* rsvd_run for callers that cannot allocate device memory (code under HIP
  * graph capture, serving loops, harnesses that forbid allocation): same
  * arguments, results and rules as rsvd_run, without `work` / `work_bytes`.

@@ -195,6 +195,76 @@ def rpca_summary(res):
     return dict(sdev=res["sdev"].double().cpu(), proportion=prop, cumulative=torch.cumsum(prop, 0))
 
 
+def rrpca(A, lam=None, maxiter=50, tol=1e-5, p=10, q=2, seed=0, rho=1.6, k_max=0, work=None):
+    """Robust PCA (Alg. rpca, rrpca_run): A = L + S.  Synchronises the stream
+    (the method reads two scalars per iteration).  Returns dict(L, S,
+    iterations, rank, k, residual, lam)."""
+    dt = _check_matrix(A)
+    m, n = A.shape
+    prm = make_params(p, q, seed)
+    opt = L.RrpcaOptions()
+    L.load().rrpca_default_options(ctypes.byref(opt))
+    opt.lam = 0.0 if lam is None else float(lam)
+    opt.maxiter, opt.tol, opt.rho, opt.k_max = int(maxiter), float(tol), float(rho), int(k_max)
+    h = handle(A.device)
+    nbytes = ctypes.c_size_t()
+    L.check(L.load().rrpca_workspace_size(h, dt, m, n, ctypes.byref(opt), ctypes.byref(prm), ctypes.byref(nbytes)),
+            "rrpca_workspace_size")
+    if work is None or work.numel() < nbytes.value:
+        work = workspace(nbytes.value, A.device)
+    Lo = torch.empty(m, n, dtype=out_dtype(A), device=A.device)
+    So = torch.empty(m, n, dtype=out_dtype(A), device=A.device)
+    res = L.RrpcaResult()
+    L.check(L.load().rrpca_run(h, dt, m, n, _ptr(A), A.stride(0), ctypes.byref(opt), ctypes.byref(prm), _ptr(Lo),
+                               Lo.stride(0), _ptr(So), So.stride(0), _ptr(work), work.numel(), ctypes.byref(res)),
+            "rrpca_run")
+    return dict(L=Lo, S=So, iterations=res.iterations, rank=res.rank, k=res.k, residual=res.residual,
+                lam=res.lam)
+
+
+def _id_work(dt, A, k, prm, cur):
+    nbytes = ctypes.c_size_t()
+    L.check(L.load().rid_workspace_size(handle(A.device), dt, A.shape[0], A.shape[1], int(k), ctypes.byref(prm),
+                                        int(cur), ctypes.byref(nbytes)), "rid_workspace_size")
+    return workspace(nbytes.value, A.device)
+
+
+def rid(A, k, p=10, q=0, seed=0, stream_id=0, sdist="normal", idx_only=False):
+    """Randomized column interpolative decomposition (Alg. rid, rid_run):
+    returns dict(J (k column indices), C (m x k) and Z (k x n), None with
+    idx_only) with A ~ C Z."""
+    dt = _check_matrix(A)
+    m, n = A.shape
+    prm = make_params(p, q, seed, stream_id, sdist)
+    work = _id_work(dt, A, k, prm, 0)
+    od = out_dtype(A)
+    J = torch.empty(k, dtype=torch.int32, device=A.device)
+    C = None if idx_only else torch.empty(m, k, dtype=od, device=A.device)
+    Z = None if idx_only else torch.empty(k, n, dtype=od, device=A.device)
+    L.check(L.load().rid_run(handle(A.device), dt, m, n, _ptr(A), A.stride(0), int(k), ctypes.byref(prm), _ptr(J),
+                             _ptr(C), k, _ptr(Z), n, _ptr(work), work.numel()), "rid_run")
+    return dict(J=J, C=C, Z=Z)
+
+
+def rcur(A, k, p=10, q=0, seed=0, stream_id=0, sdist="normal"):
+    """Randomized CUR decomposition (Alg. rcur, rcur_run): dict(C m x k,
+    U k x k, R k x n, J column indices, I row indices) with A ~ C U R."""
+    dt = _check_matrix(A)
+    m, n = A.shape
+    prm = make_params(p, q, seed, stream_id, sdist)
+    work = _id_work(dt, A, k, prm, 1)
+    od = out_dtype(A)
+    dev = A.device
+    J = torch.empty(k, dtype=torch.int32, device=dev)
+    I = torch.empty(k, dtype=torch.int32, device=dev)
+    C = torch.empty(m, k, dtype=od, device=dev)
+    U = torch.empty(k, k, dtype=od, device=dev)
+    R = torch.empty(k, n, dtype=od, device=dev)
+    L.check(L.load().rcur_run(handle(dev), dt, m, n, _ptr(A), A.stride(0), int(k), ctypes.byref(prm), _ptr(J),
+                              _ptr(I), _ptr(C), k, _ptr(U), k, _ptr(R), n, _ptr(work), work.numel()), "rcur_run")
+    return dict(C=C, U=U, R=R, J=J, I=I)
+
+
 _DESC_DTYPE = None
 
 

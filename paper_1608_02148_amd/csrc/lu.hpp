@@ -17,10 +17,11 @@
 //      Y R^-1), in place.
 // When Y has at most LU_ROWS rows the leaf is the whole matrix and the
 // pivots are those of partial pivoting on Y.  The selection phases run in
-// f32 (they only decide which rows pivot); step 3 and the product run in the
-// basis precision.  A zero pivot (rank-deficient Y) gives a zero column of
-// U^-1 and of L and sets RSVD_FLAG_DEGENERATE; a NaN pivot sets
-// RSVD_FLAG_NONFINITE.
+// f32 (they only decide which rows pivot); step 3 runs in f64 and the product
+// in the basis precision.  A pivot at or below l eps max |Y| (eps of the
+// basis precision: Y's columns dependent to working accuracy) is set to zero,
+// gives a zero column of U^-1 and of L and sets RSVD_FLAG_DEGENERATE; a NaN
+// pivot sets RSVD_FLAG_NONFINITE.
 #pragma once
 
 #include "common.hpp"
@@ -158,11 +159,21 @@ struct LuFinalBody {
         if (tid == 0) flags = 0;
         for (int r = tid; r < l; r += THREADS) { gid[r] = a.cand[r]; order[r] = r; }
         __syncthreads();
+        float amax = 0.0f;
         for (int idx = tid; idx < l * l; idx += THREADS) {
             const int r = idx / l, c = idx - r * l;
-            T[r * LS + c] = static_cast<double>(a.Y[static_cast<int64_t>(gid[r]) * a.ldy + c]);
+            const double y = static_cast<double>(a.Y[static_cast<int64_t>(gid[r]) * a.ldy + c]);
+            T[r * LS + c] = y;
+            amax = fmaxf(amax, static_cast<float>(fabs(y)));
         }
+        // pivots below l eps |Y|_max (eps of the basis precision) count as
+        // zero: the rows are linearly dependent to working accuracy
+        const int who = lu_block_argmax(amax, tid, redv, redk);
+        __shared__ float s_amax;
+        if (tid == who) s_amax = amax;
         __syncthreads();
+        const double tiny = static_cast<double>(s_amax) * l *
+                            (sizeof(TC) == 8 ? 2.220446049250313e-16 : 1.1920928955078125e-07);
         for (int j = 0; j < l; ++j) {
             float v = -1.0f;
             int key = j;
@@ -182,7 +193,10 @@ struct LuFinalBody {
                 const int pr = order[p];
                 order[p] = order[j]; order[j] = pr;
                 const double pv = T[pr * LS + j];
-                if (pv == 0.0) flags |= RSVD_FLAG_DEGENERATE;
+                if (fabs(pv) <= tiny) {
+                    flags |= RSVD_FLAG_DEGENERATE;
+                    T[pr * LS + j] = 0.0;
+                }
                 if (!(pv == pv)) flags |= RSVD_FLAG_NONFINITE;
             }
             __syncthreads();

@@ -242,6 +242,7 @@ struct SolveOut {
     double* total_var;         // PCA: total variance of the analysed data or null
     void* loadings; int64_t ldl;     // PCA: n x k loadings or null
     void* xwhite; int64_t ldxw;      // PCA: m x k whitened components or null
+    void* bt; int64_t ldbt;          // non-null: stop after B^T = A^T Q (n x l) and copy it here
     rsvd_info* info;
     uint64_t* stamps;          // optional [first step, last step] device clock
     float* features;           // non-null: stop after the sketch and write the 131 selector inputs
@@ -321,6 +322,11 @@ RSVD_DECLARE_SOLVE(f64)
 RSVD_DECLARE_SOLVE(f32)
 RSVD_DECLARE_SOLVE(bf16)
 #undef RSVD_DECLARE_SOLVE
+
+// One single solve on the handle's stream, by storage type (defined with the
+// C entry points); returns an RSVD_* status.
+int dispatch(rsvd_handle_t h, int32_t dtype, const Plan& P, const void* A, int64_t lda,
+             const rsvd_params* prm, const SolveOut& o, void* work);
 
 // Principal components of new rows per storage type (rpca_predict).
 #define RSVD_DECLARE_PREDICT(NAME)                                                                     \

@@ -311,6 +311,12 @@ hipError_t solve_steps(Ex& ex, rsvd_handle_t prof, const Plan& P, const TA* A, i
     RSVD_TRY(orthonormalize<TC>(ex, tile, Y, Lp, m, l, Lp, P.sp.gram_m, partd, gram, rinv, nullptr, status, false,
                                 Gate{}, cholx, qtmp));
     RSVD_TRY(aty(Z, late, Gate{}));
+    if (o.bt) {   // the QB decomposition's B is the product (ID / CUR work on it)
+        RSVD_TRY(ex.template run<CopyColsBody<TC>>(typename CopyColsBody<TC>::Args{
+            Z, Lp, static_cast<TC*>(o.bt), o.ldbt, n, l, nullptr, 0, Gate{}}));
+        if (o.stamps && (stamp_sel & 2)) RSVD_TRY(ex.template run<StampBody>(StampBody::Args{o.stamps + 1}));
+        return hipSuccess;
+    }
     // svd(B): B^T = Q_b R_b (Q_b overwrites Z), R_b = W S J^T by Jacobi.
     RSVD_TRY(orthonormalize<TC>(ex, tile, Z, Lp, n, l, Lp, P.sp.gram_n, partd, gram, rinv, racc, status, false,
                                 Gate{}, cholx, qtmp));

@@ -54,6 +54,16 @@ class RpcaOutputs(ctypes.Structure):
                 ("total_var", c_void_p)]
 
 
+class RrpcaOptions(ctypes.Structure):
+    _fields_ = [("lam", c_double), ("tol", c_double), ("rho", c_double), ("mu0_scale", c_double),
+                ("maxiter", c_int32), ("k_max", c_int32)]
+
+
+class RrpcaResult(ctypes.Structure):
+    _fields_ = [("iterations", c_int32), ("rank", c_int32), ("k", c_int32), ("reserved", c_int32),
+                ("residual", c_double), ("lam", c_double)]
+
+
 class MlpHeader(ctypes.Structure):
     _fields_ = [("version", c_uint32), ("params", c_uint32), ("step", c_uint32), ("reserved", c_uint32),
                 ("seed", c_uint64), ("n_train", c_uint64), ("digest", ctypes.c_uint8 * 8)]
@@ -100,6 +110,15 @@ _PROTOS = {
     "rpca_predict_workspace_size": (c_int32, [c_void_p, c_int32, c_int64, c_int64, c_int32, c_void_p]),
     "rpca_predict": (c_int32, [c_void_p, c_int32, c_int64, c_int64, c_void_p, c_int64, c_int32, c_void_p,
                                c_int64, c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_size_t]),
+    "rrpca_default_options": (None, [c_void_p]),
+    "rrpca_workspace_size": (c_int32, [c_void_p, c_int32, c_int64, c_int64, c_void_p, c_void_p, c_void_p]),
+    "rrpca_run": (c_int32, [c_void_p, c_int32, c_int64, c_int64, c_void_p, c_int64, c_void_p, c_void_p,
+                            c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_size_t, c_void_p]),
+    "rid_workspace_size": (c_int32, [c_void_p, c_int32, c_int64, c_int64, c_int32, c_void_p, c_int32, c_void_p]),
+    "rid_run": (c_int32, [c_void_p, c_int32, c_int64, c_int64, c_void_p, c_int64, c_int32, c_void_p, c_void_p,
+                          c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_size_t]),
+    "rcur_run": (c_int32, [c_void_p, c_int32, c_int64, c_int64, c_void_p, c_int64, c_int32, c_void_p, c_void_p,
+                           c_void_p, c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_size_t]),
     "rsvd_sync_info": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "rsvd_run_noalloc": (c_int32, [c_void_p, c_int32, c_int64, c_int64, c_void_p, c_int64, c_int32, c_void_p,
                                    c_void_p, c_int64, c_void_p, c_void_p, c_int64, c_void_p]),

@@ -190,25 +190,31 @@ def ragged_batch(batch=4096, seed=4096, **shape_kw):
     return out
 
 
-def _haar_torch(rows, r, g, device):
-    """rows x r Haar-distributed orthonormal columns on a torch device.
-
-    Q = X R^-1 from the Cholesky factor R of X^T X (twice), X Gaussian: with
-    R's positive diagonal this is the Q of the QR of X, hence Haar.  Falls back
-    to Householder QR (sign-fixed) when X is too ill-conditioned for it.
-    """
+def _haar_torch(rows, r, g, device, max_iter=80):
+    """rows x r Haar-distributed orthonormal columns on a torch device: the
+    polar factor of a Gaussian block (orthogonally invariant, hence Haar),
+    by the Newton-Schulz iteration X <- X (3 I - X^T X) / 2 from the block
+    scaled below its largest singular value (matrix products only).  Near-
+    square blocks converge slowly (their smallest singular value is small),
+    so the iteration runs until X^T X = I to 1e-13 or max_iter steps, then
+    falls back to Householder QR (sign-fixed) for the rare block that has not
+    converged."""
     import torch
     X = torch.randn(rows, r, generator=g, device=device, dtype=torch.float64)
-    Q = X
-    for _ in range(2):
-        R, info = torch.linalg.cholesky_ex(Q.t() @ Q, upper=True)
-        if int(info) != 0:
-            q, rr = torch.linalg.qr(X, mode="reduced")
-            sgn = torch.sign(torch.diagonal(rr))
-            sgn[sgn == 0] = 1.0
-            return q * sgn[None, :]
-        Q = torch.linalg.solve_triangular(R, Q, upper=True, left=False)
-    return Q
+    G0 = X
+    X = X / (math.sqrt(rows) + math.sqrt(r) + 10.0)
+    eye = torch.eye(r, dtype=torch.float64, device=device)
+    for it in range(max_iter):
+        XtX = X.t() @ X
+        if it % 8 == 7 and float((XtX - eye).abs().max()) < 1e-13:
+            return X
+        X = X @ (1.5 * eye - 0.5 * XtX)
+    if float((X.t() @ X - eye).abs().max()) < 1e-13:
+        return X
+    q, rr = torch.linalg.qr(G0, mode="reduced")
+    sgn = torch.sign(torch.diagonal(rr))
+    sgn[sgn == 0] = 1.0
+    return q * sgn[None, :]
 
 
 def ragged_torch(device="cuda", batch=4096, seed=4096, out_dtype=None, **shape_kw):

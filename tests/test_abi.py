@@ -15,7 +15,7 @@ HEADER = os.path.join(ROOT, "include", "rsvd_mi355x.h")
 def header_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(rsvd_\w+|rpca_\w+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(rsvd_\w+|rpca_\w+|rrpca_\w+|rid_\w+|rcur_\w+)\s*\(", text)))
 
 
 @pytest.fixture(scope="module")
