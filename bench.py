@@ -20,6 +20,8 @@ Also reported:
                    against the oracle's (sigma_err_vs_oracle);
   rpca          -- randomized PCA of the same matrix plus column offsets
                    (implicit centring), against the oracle's explicit centring;
+  next_rows     -- LU-normalised power iterations, randomized ID / CUR on the
+                   same matrix, robust PCA of a 2000 x 2000 corrupted product;
   bf16_mixed    -- the same workload in the bf16 mixed-precision mode;
   batched       -- 4096 ragged f32 matrices (m in [256, 4096], n in
                    [64, 1024], k in [8, 64], p=10, q=2, sigma_i = i^-alpha)
@@ -109,6 +111,44 @@ def block_krylov_svals(op, opT, n, device, block, iters, seed=0):
     Y = op(K)
     ev = np.linalg.eigvalsh((Y.t() @ Y).cpu().numpy())
     return np.sqrt(np.maximum(ev[::-1], 0.0))
+
+
+def block_krylov_ritz(op, opT, n, device, block, iters, k, seed=0):
+    """Leading Ritz triplets of a linear operator from a block Krylov space
+    (basis as in block_krylov_svals): sigma (descending), U (m x k) and V
+    (n x k) from the eigen-decomposition of (op K)^T (op K), all float64."""
+    import numpy as np
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    Q = _orth_cpu(torch.randn(n, block, generator=g, device=device, dtype=torch.float64))
+    basis = [Q]
+    for _ in range(iters):
+        W = opT(op(Q))
+        for _ in range(2):
+            for B in basis:
+                W -= B @ (B.t() @ W)
+        Q = _orth_cpu(W)
+        basis.append(Q)
+    K = _orth_cpu(torch.cat(basis, 1))
+    del basis
+    Y = op(K)
+    ev, W = np.linalg.eigh((Y.t() @ Y).cpu().numpy())
+    order = np.argsort(ev)[::-1][:k]
+    s = np.sqrt(np.maximum(ev[order], 0.0))
+    Wk = torch.from_numpy(np.ascontiguousarray(W[:, order])).to(device)
+    V = K @ Wk
+    U = (Y @ Wk) / torch.from_numpy(s).to(device)[None, :]
+    return s, U, V
+
+
+def max_angle_sin(Q1, Q2):
+    """sin of the largest principal angle between span(Q1) and span(Q2)
+    (both with orthonormal columns, float64 tensors)."""
+    import torch
+    s = torch.linalg.svdvals(Q1.t() @ Q2)
+    c = float(s.min())
+    return max(0.0, 1.0 - c * c) ** 0.5
 
 
 def residual_norms(A64, U, S, V):
@@ -248,12 +288,65 @@ def pca_arm(A, k, p, q, seed, steps, warmup, with_oracle=True):
     return out
 
 
+def next_rows_arm(A, k, p, q, seed, steps):
+    """The NEXT-row entry points on the same 100000 x 5000 f32 matrix: the
+    rSVD with LU-normalised power iterations (against subspace iterations),
+    the randomized column ID and CUR decompositions at rank k, and robust PCA
+    of the paper's synthetic study shape scaled up (2000 x 2000, a rank-20
+    Gaussian product plus 20 % sparse corruption in [-500, 500])."""
+    import numpy as np
+    import torch
+
+    from paper_1608_02148_amd import api
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / reps
+
+    out = {}
+    m, n = A.shape
+    l = min(k + p, m, n)
+    flops = (2 * q + 2) * 2.0 * m * n * l
+    ms_lu = timed(lambda: api.rsvd(A, k, p=p, q=q, seed=seed, scheme="lu"), steps)
+    out["rsvd_lu_iterations"] = {"ms_per_step": round(ms_lu, 3), "tflops": round(flops / ms_lu / 1e9, 3)}
+    ms_id = timed(lambda: api.rid(A, k, p=p, q=q, seed=seed), max(steps // 2, 1))
+    ms_cur = timed(lambda: api.rcur(A, k, p=p, q=q, seed=seed), max(steps // 2, 1))
+    out["rid"] = {"workload": f"{m}x{n} f32 k={k} p={p} q={q}", "ms": round(ms_id, 3)}
+    out["rcur"] = {"workload": f"{m}x{n} f32 k={k} p={p} q={q}", "ms": round(ms_cur, 3)}
+    g = torch.Generator(device=A.device)
+    g.manual_seed(2101)
+    mm = nn = 2000
+    L0 = torch.randn(mm, 20, generator=g, device=A.device) @ torch.randn(20, nn, generator=g, device=A.device)
+    mask = (torch.rand(mm, nn, generator=g, device=A.device) < 0.2).float()
+    S0 = (torch.rand(mm, nn, generator=g, device=A.device) * 1000.0 - 500.0) * mask
+    M = (L0 + S0).contiguous()
+    t0 = time.perf_counter()
+    res = api.rrpca(M, seed=seed)
+    torch.cuda.synchronize()
+    ms_rr = (time.perf_counter() - t0) * 1e3
+    err = float(torch.linalg.norm(res["L"] - L0) / torch.linalg.norm(L0))
+    out["rrpca"] = {"workload": "2000x2000 f32, rank-20 Gaussian product + 20% sparse uniform[-500,500]",
+                    "ms": round(ms_rr, 2), "iterations": res["iterations"], "rank": res["rank"],
+                    "rel_err_lowrank": err}
+    del M, L0, S0, mask, res
+    del np
+    log(f"[next] {out}")
+    return out
+
+
 def batched_arm(steps, warmup, precision="plain"):
-    """4096 ragged f32 matrices, p=10, q=2, one captured graph per run.
+    """4096 ragged f32 matrices, p=10, q=2, one captured graph per run, as
+    grouped launches over each size class (the default) and with the classes
+    split into chunks run one after another (RSVD_BATCH_CHUNKED).
 
     Returns solves/s over `steps` graph replays, algorithmic TFLOP/s and GB/s
     of the batch, and p50 / p99 of the per-solve latency (device clock from a
-    solve's first step to its last) in the last replay.
+    solve's first step to its last) in the last replay, per mode.
     """
     import numpy as np
     import torch
@@ -263,41 +356,48 @@ def batched_arm(steps, warmup, precision="plain"):
 
     c = syn.CONFIGS["ragged_4096"]
     log(f"[c4] generating {c['batch']} ragged matrices")
+    t0 = time.perf_counter()
     data = syn.ragged_torch(device="cuda", batch=c["batch"], seed=c["gen_seed"])
     torch.cuda.synchronize()
+    log(f"[c4] generated in {time.perf_counter() - t0:.1f} s")
     ks = [int(x) for x in data["k"]]
     m, n = data["m"].astype(np.float64), data["n"].astype(np.float64)
     l = np.minimum(np.array(ks) + c["p"], np.minimum(m, n))
     flops = float(np.sum((2 * c["q"] + 2) * 2.0 * m * n * l))
     a_bytes = float(np.sum(m * n * 4.0)) * (2 * c["q"] + 2)
     log(f"[c4] planning; {flops / 1e12:.3f} TFLOP and {a_bytes / 1e9:.1f} GB of A reads per batch")
-    bt = api.Batch(data["A"], ks, p=c["p"], q=c["q"], seed=c["omega_seed"], precision=precision,
-                   graph=True, stamps=True)
-    for _ in range(warmup):
-        bt.run()
-    torch.cuda.synchronize()
-    log(f"[c4] timing {steps} graph replays")
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        bt.run()
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / steps
-    st, hz = bt.stamps()
-    lat_ms = (st[:, 1] - st[:, 0]) / hz * 1e3
-    out = {
-        "workload": f"{c['batch']} ragged f32 matrices, m~U[256,4096], n~U[64,1024], k~U[8,64], p={c['p']}, "
-                    f"q={c['q']}, sigma_i=i^-alpha, alpha~U[0.5,3]",
-        "precision": precision,
-        "solves_per_s": round(c["batch"] / dt, 1), "ms_per_batch": round(dt * 1e3, 3),
-        "tflops": round(flops / dt / 1e12, 3), "a_read_gbs": round(a_bytes / dt / 1e9, 1),
-        "mfma_frac": round(flops / dt / 1e12 / PEAKS["f32_mfma_tflops"], 4),
-        "hbm_frac": round(a_bytes / dt / 1e9 / PEAKS["hbm_gbs"], 4),
-        "latency_ms_p50": round(float(np.percentile(lat_ms, 50)), 3),
-        "latency_ms_p99": round(float(np.percentile(lat_ms, 99)), 3),
-        "work_bytes": bt.work_bytes,
-    }
-    log(f"[c4] {out}")
-    bt.close()
+    out = None
+    for chunked in (False, True):
+        bt = api.Batch(data["A"], ks, p=c["p"], q=c["q"], seed=c["omega_seed"], precision=precision,
+                       graph=True, stamps=True, chunked=chunked)
+        for _ in range(warmup):
+            bt.run()
+        torch.cuda.synchronize()
+        log(f"[c4] timing {steps} graph replays (chunked={chunked})")
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            bt.run()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        st, hz = bt.stamps()
+        lat_ms = (st[:, 1] - st[:, 0]) / hz * 1e3
+        rec = {
+            "solves_per_s": round(c["batch"] / dt, 1), "ms_per_batch": round(dt * 1e3, 3),
+            "tflops": round(flops / dt / 1e12, 3), "a_read_gbs": round(a_bytes / dt / 1e9, 1),
+            "mfma_frac": round(flops / dt / 1e12 / PEAKS["f32_mfma_tflops"], 4),
+            "hbm_frac": round(a_bytes / dt / 1e9 / PEAKS["hbm_gbs"], 4),
+            "latency_ms_p50": round(float(np.percentile(lat_ms, 50)), 3),
+            "latency_ms_p99": round(float(np.percentile(lat_ms, 99)), 3),
+            "work_bytes": bt.work_bytes,
+        }
+        log(f"[c4] chunked={chunked}: {rec}")
+        bt.close()
+        if out is None:
+            out = {"workload": f"{c['batch']} ragged f32 matrices, m~U[256,4096], n~U[64,1024], k~U[8,64], "
+                               f"p={c['p']}, q={c['q']}, sigma_i=i^-alpha, alpha~U[0.5,3]",
+                   "precision": precision, **rec}
+        else:
+            out["chunked"] = rec
     del data
     torch.cuda.empty_cache()
     return out
@@ -317,6 +417,7 @@ def bf16_storage_arm(steps, warmup, m=200000, n=20000, k=200, p=20, q=2, seed=21
     from synth import matrices as syn
 
     dev = torch.device("cuda", 0)
+    dev_t = dev
     log(f"[bf16_storage] generating A {m}x{n} bfloat16")
     A = syn.poly_bf16_torch(device=dev, m=m, n=n)
     torch.cuda.synchronize()
@@ -325,7 +426,7 @@ def bf16_storage_arm(steps, warmup, m=200000, n=20000, k=200, p=20, q=2, seed=21
     planted = syn.spectrum("poly", 4096, alpha=1.5)[:k]
     out = {"workload": f"rsvd {m}x{n} bf16 k={k} p={p} q={q}, sigma_i=i^-1.5 (i <= 4096), rounded to bf16",
            "a_bytes": m * n * 2}
-    svals = {}
+    svals, factors = {}, {}
     for precision in ("plain", "bf16_mixed"):
         prm = api.make_params(p, q, seed, precision=precision)
         work = api.workspace(api.workspace_size(A, k, prm), dev)
@@ -360,10 +461,11 @@ def bf16_storage_arm(steps, warmup, m=200000, n=20000, k=200, p=20, q=2, seed=21
                     "frac": round(ach / PEAKS["hbm_gbs"], 4)}
         roof.update({"kernel": dom, "avg_launch_ms": round(avg, 4), "launches": d["count"]})
         svals[precision] = res[1].cpu().numpy()
+        factors[precision] = (res[0], res[2])
         out[precision] = {"ms_per_step": round(ms, 3), "tflops": round(flops / (ms / 1e3) / 1e12, 3),
                           "a_read_gbs": round((2 * q + 2) * m * n * 2 / (ms / 1e3) / 1e9, 1), "roofline": roof}
         log(f"[bf16_storage] {precision}: {ms:.3f} ms/solve, kernels {prof}")
-        del work, res
+        del work
         torch.cuda.empty_cache()
     # the mixed mode at the other power-iteration counts of the configuration
     out["bf16_mixed_by_q"] = {}
@@ -388,40 +490,95 @@ def bf16_storage_arm(steps, warmup, m=200000, n=20000, k=200, p=20, q=2, seed=21
     out["max_sigma_diff_mixed_vs_plain_rel_sigma1"] = float(np.max(np.abs(s_pl - s_bf)) / s_pl[0])
     dev = np.abs(s_pl - planted) / planted
     out["max_rel_dev_from_planted_sigma"] = {"top50": float(np.max(dev[:50])), f"all_{k}": float(np.max(dev))}
+    # float64 reference of the stored instance (block Krylov over row chunks
+    # of A widened to f64): per-sigma error and the largest principal angle
+    # of U_k and V_k of each arm against it
+    log("[bf16_storage] float64 block Krylov reference")
+    chunk = 16384
+
+    def op(X):
+        return torch.cat([A[r:r + chunk].double() @ X for r in range(0, m, chunk)], 0)
+
+    def opT(Y):
+        acc = None
+        for r in range(0, m, chunk):
+            t = A[r:r + chunk].double().t() @ Y[r:r + chunk]
+            acc = t if acc is None else acc + t
+        return acc
+
+    s_ref, U_ref, V_ref = block_krylov_ritz(op, opT, n, dev_t, 2 * k, 4, k)
+    ref = {}
+    for precision in ("plain", "bf16_mixed"):
+        Ug, Vg = factors[precision]
+        sv = svals[precision]
+        ref[precision] = {
+            "sigma_rel_err_max": float(np.max(np.abs(sv - s_ref) / s_ref)),
+            "sigma_rel_err_top50": float(np.max(np.abs(sv[:50] - s_ref[:50]) / s_ref[:50])),
+            "sin_max_angle_U": max_angle_sin(U_ref, Ug.double()),
+            "sin_max_angle_V": max_angle_sin(V_ref, Vg.double()),
+            "sin_max_angle_U_top50": max_angle_sin(U_ref[:, :50], Ug[:, :50].double()),
+            "sin_max_angle_V_top50": max_angle_sin(V_ref[:, :50], Vg[:, :50].double()),
+        }
+    out["vs_f64_reference"] = ref
+    out["reference"] = "float64 block Krylov, block 2k = 400, 4 iterations (Krylov dimension 2000), on the stored bf16 instance"
+    log(f"[bf16_storage] against the f64 reference: {ref}")
+    del U_ref, V_ref, factors
+    torch.cuda.empty_cache()
     del A
     torch.cuda.empty_cache()
     return out
 
 
 def learned_arm(count, reps=3):
-    """Held-out generated matrices (selector workload): FP32 plain at q=2,
-    p=10 and at q=4, p=20 against bf16 mixed precision with the learned
-    (q, p), timed end to end; exact fraction within 1 % excess error."""
+    """Learned (q, p) against fixed pairs on two held-out sets of `count`
+    matrices with dense Haar factors: the selector's test distribution
+    (poly/exp spectra with a spectral floor, seed 5103) and `count` matrices
+    drawn by the batch workload's recipe (sigma_i = i^-alpha, seed 4096).  Arms:
+    FP32 plain at q = 2, p = 10 and at q = 4, p = 20, and learned q with
+    p = 20 in f32 and bf16-mixed arithmetic, as one device graph and through
+    the host; exact fraction within 1 % excess error (residual norms from the
+    stored matrices, sigma_{k+1} from the planted spectra)."""
     import numpy as np
     import torch
 
     from paper_1608_02148_amd import learned as L
     from synth import learned_data as ld
+    from synth import matrices as syn
 
     theta, hdr = L.load_checkpoint(device="cuda")
-    log(f"[learned] generating {count} held-out matrices")
-    data = ld.build(count, "test")
+    tau_graph = hdr["tau"] if hdr.get("tau") else L.DEFAULT_TAU
+    sets = {}
+    log(f"[learned] generating {count} held-out selector-workload matrices (Haar factors)")
+    sets["selector_test_haar"] = ld.build(count, "test", factors="haar")
+    log(f"[learned] generating {count} matrices by the batch workload's recipe")
+    rb = syn.ragged_torch(device="cuda", batch=count, seed=syn.CONFIGS["ragged_4096"]["gen_seed"])
+    r = np.minimum(rb["m"], rb["n"])
+    sets["batch_workload_recipe"] = dict(
+        A=rb["A"], buffer=rb["buffer"], hh=None,
+        spec=dict(m=rb["m"], n=rb["n"], k=rb["k"]),
+        sigma=[np.arange(1, int(rr) + 1, dtype=np.float64) ** (-float(a)) for rr, a in zip(r, rb["alpha"])])
     torch.cuda.synchronize()
-    res = L.evaluate_arms(data, theta, reps=reps)
-    ok = {k: np.asarray(v["errors"]) <= L.TOL for k, v in res.items()}
-    feasible = ok["fp32_fixed_q4_p20"] | ok["fp32_default_q2_p10"]
-    out = {"workload": f"{count} generated f32 matrices (batch-workload shapes; poly/exp spectra with a "
-                       f"spectral floor), seed 5103", "checkpoint_step": hdr["step"],
-           "n_train": hdr["n_train"], "precision_infeasible": int(np.sum(~feasible))}
-    for k, v in res.items():
-        out[k] = {"solves_per_s": round(v["solves_per_s"], 1), "ms": round(v["ms"], 3),
-                  "frac_within_1pct": round(float(ok[k].mean()), 4),
-                  "frac_within_1pct_feasible": round(float(ok[k][feasible].mean()), 4)}
-        for extra in ("select_ms", "plan_ms", "solve_ms", "q_hist", "p_hist"):
-            if extra in v:
-                out[k][extra] = v[extra] if not isinstance(v[extra], float) else round(v[extra], 3)
-    log(f"[learned] {out}")
-    del data
+    out = {"checkpoint_step": hdr["step"], "n_train": hdr["n_train"], "tau_graph": tau_graph}
+    for name, data in sets.items():
+        res = L.evaluate_arms(data, theta, reps=reps, tau_graph=tau_graph)
+        ok = {k: np.asarray(v["errors"]) <= L.TOL for k, v in res.items()}
+        feasible = ok["fp32_fixed_q4_p20"] | ok["fp32_default_q2_p10"]
+        rec = {"matrices": count, "precision_infeasible": int(np.sum(~feasible))}
+        for k, v in res.items():
+            rec[k] = {"solves_per_s": round(v["solves_per_s"], 1), "ms": round(v["ms"], 3),
+                      "frac_within_1pct": round(float(ok[k].mean()), 4),
+                      "frac_within_1pct_feasible": round(float(ok[k][feasible].mean()), 4)}
+            for extra in ("select_ms", "plan_ms", "solve_ms", "q_hist", "p_hist"):
+                if extra in v:
+                    rec[k][extra] = v[extra] if not isinstance(v[extra], float) else round(v[extra], 3)
+        fixed = rec["fp32_fixed_q4_p20"]
+        best = rec["bf16_learned_graph"]
+        rec["bf16_learned_vs_fixed_q4_p20"] = {
+            "success_at_least_fixed": best["frac_within_1pct"] >= fixed["frac_within_1pct"],
+            "speedup": round(best["solves_per_s"] / fixed["solves_per_s"], 3)}
+        out[name] = rec
+        log(f"[learned] {name}: {rec}")
+    del sets, rb
     torch.cuda.empty_cache()
     return out
 
@@ -444,6 +601,7 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-bf16-arm", action="store_true")
     ap.add_argument("--no-pca", action="store_true")
+    ap.add_argument("--no-next", action="store_true")
     ap.add_argument("--no-bf16-storage", action="store_true")
     ap.add_argument("--bf16-storage-only", action="store_true")
     ap.add_argument("--gaussian-fill", action="store_true",
@@ -618,6 +776,7 @@ def main():
     del out_pl, out_bf
     pca = None if args.no_pca else pca_arm(A, k, p, q, args.seed, args.steps, args.warmup,
                                            with_oracle=not args.no_cpu_baseline)
+    nxt = None if args.no_next else next_rows_arm(A, k, p, q, args.seed, args.steps)
     del A
     torch.cuda.empty_cache()
     bf16_storage = None if args.no_bf16_storage else bf16_storage_arm(min(args.steps, 5), 1)
@@ -641,6 +800,7 @@ def main():
         "whole_solve": whole,
         "cpu_baseline": cpu,
         "rpca": pca,
+        "next_rows": nxt,
         "bf16_mixed": bf16_arm,
         "bf16_storage": bf16_storage,
         "batched": batched,

@@ -382,6 +382,11 @@ typedef struct rsvd_batch_s* rsvd_batch_t;
                                   write its selector inputs (desc.features,
                                   see the selector network below); S, U, V
                                   are not written                               */
+#define RSVD_BATCH_CHUNKED 16  /* split each size class into 4 chunks of about
+                                  equal work that run one after another on
+                                  the class's stream: a matrix's solve spans
+                                  its chunk's launches (about a quarter of the
+                                  batch time) instead of all of them        */
 #define RSVD_BATCH_OWN_QP   8  /* take q and p from each desc instead of
                                   params (a group runs its largest q; each
                                   member's extra iterations are switched off
@@ -497,12 +502,15 @@ int rsvd_mlp_train_step(rsvd_handle_t handle, float* theta, float* adam_m, float
 /* Selector checkpoint file (what the training driver writes): a 64-byte
  * little-endian header -- magic "RSVDMLP1", u32 format version (1), u32
  * parameter count (RSVD_MLP_PARAMS), u32 Adam step, u64 seed, u64 size of the
- * training set, 8 bytes of a digest of the training data, zero padding --
+ * training set, 8 bytes of a digest of the training data, f32 decision
+ * threshold tau tuned on the validation split (0 = not set), zero padding --
  * then theta, adam_m and adam_v as RSVD_MLP_PARAMS float32 each. */
 typedef struct {
     uint32_t version, params, step, reserved;
     uint64_t seed, n_train;
     uint8_t  digest[8];
+    float    tau;
+    uint32_t reserved2;
 } rsvd_mlp_header;
 
 /* Read a selector checkpoint from the host file `path` into the device

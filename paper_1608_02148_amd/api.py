@@ -329,12 +329,14 @@ class Batch:
     MLP_PARAMS values, or None for q = LEARNED_FALLBACK_Q everywhere) with
     threshold ``tau``, every solve with oversampling ``p`` (<= LEARNED_PMAX)
     and starting from its q = 0 sketch; ``q``, ``qs``, ``ps`` are not used and
-    ``choices()`` returns the q of the last run.
+    ``choices()`` returns the q of the last run.  ``chunked=True``
+    (RSVD_BATCH_CHUNKED): each size class runs as 4 chunks of about equal
+    work one after another, so a solve spans about a quarter of the batch.
     """
 
     def __init__(self, As, ks, p=10, q=2, seed=0, stream_ids=None, sdist="normal", precision="plain",
                  compute_u=True, compute_v=True, graph=True, stamps=False, infos=False, qs=None, ps=None,
-                 features=False, work=None, probes=0, learned=False, theta=None, tau=0.8):
+                 features=False, work=None, probes=0, learned=False, theta=None, tau=0.8, chunked=False):
         global _DESC_DTYPE
         if _DESC_DTYPE is None:
             _DESC_DTYPE = _desc_dtype()
@@ -393,6 +395,7 @@ class Batch:
         prm = make_params(p, q, seed, 0, sdist, precision, 0 if features else probes)
         flags = (L.BATCH_GRAPH if graph else 0) | (L.BATCH_STAMPS if stamps else 0)
         flags |= (L.BATCH_FEATURES if features else 0) | (L.BATCH_OWN_QP if (qs is not None or ps is not None) else 0)
+        flags |= L.BATCH_CHUNKED if chunked else 0
         self._lib = L.load()
         self._h = handle(dev)
         self._b = ctypes.c_void_p()

@@ -252,6 +252,7 @@ namespace rsvd {
 
 struct BatchGroup {
     int tile = 0;
+    int lane = 0;       // stream lane: one per size class; a lane runs its groups in order
     int q = 0;          // largest q of the members (iterations issued)
     std::vector<int> members;
     BatchRecorder rec;
@@ -338,24 +339,32 @@ inline hipError_t record_all(rsvd_batch_s* B, void* base, unsigned char* host) {
 }
 
 constexpr int kLearnedFallbackQ = RSVD_LEARNED_FALLBACK_Q;
+constexpr int kBatchChunks = 4;     // RSVD_BATCH_CHUNKED: chunks per size class
 
 // Group g runs on lane g % lanes: lane 0 is the caller's stream, the others
 // are side streams forked from it and joined back with events.
 constexpr size_t kMaxLanes = 6;
 
-inline size_t lanes_of(const rsvd_batch_s* B) {
-    return std::min(std::max(B->groups.size(), B->groups0.size()), kMaxLanes);
+inline size_t lanes_in(const std::vector<BatchGroup>& groups) {
+    size_t n = 0;
+    for (const BatchGroup& g : groups) n = std::max(n, static_cast<size_t>(g.lane) + 1);
+    return std::min(n, kMaxLanes);
 }
 
-// One phase: fork the lanes from st, groups round-robin over them, join back.
+inline size_t lanes_of(const rsvd_batch_s* B) {
+    return std::max(lanes_in(B->groups), lanes_in(B->groups0));
+}
+
+// One phase: fork the lanes from st, each group on its lane in order, join back.
 inline hipError_t launch_groups(const rsvd_batch_s* B, const std::vector<BatchGroup>& groups, hipStream_t st) {
     const unsigned char* base = static_cast<const unsigned char*>(B->work);
-    const size_t lanes = std::min(groups.size(), kMaxLanes);
+    const size_t lanes = lanes_in(groups);
     rsvd_handle_t h = B->h;
     if (lanes > 1) RSVD_TRY(hipEventRecord(h->fork, st));
     for (size_t s = 1; s < lanes; ++s) RSVD_TRY(hipStreamWaitEvent(h->side[s - 1], h->fork, 0));
     for (size_t g = 0; g < groups.size(); ++g) {
-        hipStream_t ls = (g % lanes == 0) ? st : h->side[g % lanes - 1];
+        const size_t ln = static_cast<size_t>(groups[g].lane) % lanes;
+        hipStream_t ls = (ln == 0) ? st : h->side[ln - 1];
         RSVD_TRY(groups[g].rec.launch(base + groups[g].table_off, ls));
     }
     for (size_t s = 1; s < lanes; ++s) {
@@ -394,26 +403,48 @@ inline hipError_t make_side_streams(rsvd_batch_s* B) {
     return hipSuccess;
 }
 
-// Groups of one phase by tile class; each group issues its largest q.
-inline void build_groups(std::vector<Plan>& plans, std::vector<BatchGroup>& out) {
+// Groups of one phase by tile class, each class on its own stream lane and,
+// with chunks > 1, split into up to `chunks` groups of about equal work that
+// its lane runs one after another (a member's solve then spans its chunk's
+// launches only, not the whole batch's).  Members are ordered by descending
+// work (passes over A times the sketch width), so the largest tiles start
+// first; each group issues its largest q.
+inline void build_groups(std::vector<Plan>& plans, std::vector<BatchGroup>& out, int chunks = 1) {
     const int count = static_cast<int>(plans.size());
+    auto work = [&](int i) {
+        const Plan& p = plans[i];
+        return static_cast<double>(p.m) * p.n * p.l * (p.q + 1);
+    };
+    int lane = 0;
     for (int tile : {128, 96, 80, 64, 48, 32}) {
+        std::vector<int> members;
+        for (int32_t i = 0; i < count; ++i)
+            if (plans[i].tile == tile) members.push_back(i);
+        if (members.empty()) continue;
+        std::stable_sort(members.begin(), members.end(), [&](int a, int b) { return work(a) > work(b); });
+        double total = 0.0;
+        for (int i : members) total += work(i);
+        double acc = 0.0;
+        int c = 0;
         BatchGroup g;
         g.tile = tile;
-        for (int32_t i = 0; i < count; ++i)
-            if (plans[i].tile == tile) {
-                g.members.push_back(i);
-                g.q = std::max(g.q, plans[i].q);
+        g.lane = lane;
+        for (size_t mi = 0; mi < members.size(); ++mi) {
+            const int i = members[mi];
+            g.members.push_back(i);
+            g.q = std::max(g.q, plans[i].q);
+            acc += work(i);
+            const bool cut = (c + 1 < chunks) && acc >= total * (c + 1) / chunks && mi + 1 < members.size();
+            if (cut || mi + 1 == members.size()) {
+                for (int j : g.members) plans[j].qmax = g.q;
+                out.push_back(std::move(g));
+                g = BatchGroup();
+                g.tile = tile;
+                g.lane = lane;
+                ++c;
             }
-        if (g.members.empty()) continue;
-        for (int i : g.members) plans[i].qmax = g.q;
-        // most work first: passes over A times the sketch width
-        std::stable_sort(g.members.begin(), g.members.end(), [&](int a, int b) {
-            const Plan &pa = plans[a], &pb = plans[b];
-            return static_cast<double>(pa.m) * pa.n * pa.l * (pa.q + 1) >
-                   static_cast<double>(pb.m) * pb.n * pb.l * (pb.q + 1);
-        });
-        out.push_back(std::move(g));
+        }
+        ++lane;
     }
 }
 
@@ -443,7 +474,8 @@ extern "C" {
 int rsvd_batch_create(rsvd_handle_t handle, int32_t dtype, int32_t count, const rsvd_batch_desc* descs,
                       const rsvd_params* params, int32_t flags, rsvd_batch_t* batch, size_t* work_bytes) {
     if (!handle || count < 1 || !descs || !params || !batch || !work_bytes) return RSVD_ERR_INVALID;
-    if (flags & ~(RSVD_BATCH_GRAPH | RSVD_BATCH_STAMPS | RSVD_BATCH_FEATURES | RSVD_BATCH_OWN_QP))
+    if (flags & ~(RSVD_BATCH_GRAPH | RSVD_BATCH_STAMPS | RSVD_BATCH_FEATURES | RSVD_BATCH_OWN_QP |
+                  RSVD_BATCH_CHUNKED))
         return RSVD_ERR_INVALID;
     if (params->scheme != RSVD_SCHEME_QR) return RSVD_ERR_UNSUPPORTED;   // LU: single solves only
     const bool feat = (flags & RSVD_BATCH_FEATURES) != 0;
@@ -477,7 +509,7 @@ int rsvd_batch_create(rsvd_handle_t handle, int32_t dtype, int32_t count, const 
     for (int32_t i = 0; i < count; ++i)
         B->plans[i] = make_plan(dtype, descs[i].m, descs[i].n, descs[i].k, &prm[i], handle->dev.num_cu, true,
                                 handle->variants);
-    build_groups(B->plans, B->groups);
+    build_groups(B->plans, B->groups, (flags & RSVD_BATCH_CHUNKED) ? kBatchChunks : 1);
     B->offs.assign(count, 0);
     Layout L;
     if (!size_tables(B, B->groups, 1, L)) { delete B; return RSVD_ERR_UNSUPPORTED; }

@@ -206,7 +206,10 @@ hipError_t gemm_bf16_cls(Ex& ex, int tc, const GemmArgs<TA, float, float>& g) {
     if (tc == 80) return ex.template run<Bf16Body<TA, MODE, SPLIT, 2, 5, 4, 1, CENT>>(g);
     if (tc == 96) return ex.template run<Bf16Body<TA, MODE, SPLIT, 4, 3, 2, 2, CENT>>(g);
     // 256 columns (sketches wider than 128): 16 waves of 32 x 64 (the 8-wave
-    // 64 x 64 tiling was 5-7 % slower for A X at 200000 x 20000, l = 220)
+    // 64 x 64 tiling was 5-7 % slower for A X at 200000 x 20000, l = 220, and
+    // 16 waves of 64 x 64 over 256 rows, which halve the re-reads of the
+    // packed X, took 1.3x (A X) and 1.8x (A^T Q) as long: one workgroup per
+    // CU with its double-buffered 144-160 KB of LDS)
     if (tc == 256) return ex.template run<Bf16Body<TA, MODE, SPLIT, 2, 4, 4, 4, CENT>>(g);
     return ex.template run<Bf16Body<TA, MODE, SPLIT, 4, 4, 2, 2, CENT>>(g);
 }

@@ -282,8 +282,8 @@ int rsvd_mlp_train_step(rsvd_handle_t handle, float* theta, float* adam_m, float
 }
 
 // Checkpoint file: 64-byte header (magic, u32 version, u32 parameter count,
-// u32 Adam step, u64 seed, u64 training-set size, 8-byte digest, zero
-// padding), then theta, adam_m, adam_v as little-endian f32.
+// u32 Adam step, u64 seed, u64 training-set size, 8-byte digest, f32 tau,
+// zero padding), then theta, adam_m, adam_v as little-endian f32.
 int rsvd_mlp_load(rsvd_handle_t handle, const char* path, float* theta, float* adam_m, float* adam_v,
                   rsvd_mlp_header* header) {
     if (!handle || !path || (!theta && (adam_m || adam_v))) return RSVD_ERR_INVALID;
@@ -312,6 +312,8 @@ int rsvd_mlp_load(rsvd_handle_t handle, const char* path, float* theta, float* a
         header->version = version; header->params = nparams; header->step = step; header->reserved = 0;
         header->seed = seed; header->n_train = ntrain;
         std::memcpy(header->digest, raw.data() + 36, 8);
+        std::memcpy(&header->tau, raw.data() + 44, 4);
+        header->reserved2 = 0;
     }
     if (!theta) return RSVD_OK;                           // checked only
     float* dst[3] = {theta, adam_m, adam_v};

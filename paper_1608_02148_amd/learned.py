@@ -9,14 +9,24 @@ reads the spectrum of a q = 0 sketch (rsvd_select) and picks the cheapest pair
 
 Labels (training data).  For each matrix and each of the 15 pairs, one
 batched solve (FP32 plain, the matrix's own Omega stream) gives U; the excess
-error is ||(I - U U^T) A||_2 / sigma_{k+1} - 1 against the planted matrix
-(whose spectrum and left factor are known exactly, synth.learned_data).  For
-the rSVD's outputs U^T A = S V^T holds up to rounding, so this is the error
-of A - U S V^T.  The spectral norm is the largest eigenvalue of
-Sigma (I - W W^T) Sigma with W = U_true^T U (an r x k matrix), found by a
-Krylov (Lanczos-type) iteration with full re-orthogonalisation and a
-Rayleigh-Ritz step.  The label is the cheapest pair with excess error <= 1 %
-(class 14 and "unreachable" when none is).
+error is ||(I - U U^T) A||_2 / sigma_{k+1} - 1 with sigma_{k+1} from the
+planted spectrum (synth.learned_data).  For the rSVD's outputs U^T A = S V^T
+holds up to rounding, so this is the error of A - U S V^T.  The spectral norm
+comes from a Krylov (Lanczos-type) iteration with full re-orthogonalisation
+and a Rayleigh-Ritz step: on Sigma (I - W W^T) Sigma with W = U_true^T U when
+the planted factors are Householder reflections (residual_norms), or on
+E^T E with E = (I - U U^T) A from the stored matrices when they are dense
+Haar factors (residual_norms_dense).  The label is the cheapest pair with
+excess error <= 1 % (class 14 and "unreachable" when none is).
+
+Pipeline (python -m paper_1608_02148_amd.learned ...):
+  label --split train --count 40000 --lo L --hi H --dir D   shards of 4096
+        matrices (dense Haar factors by default), each labelled and stored
+        as D/<split>_<count>_<lo>_<hi>.npz (features, labels, error table);
+  train --dir D --out selector.bin --report r.json           Adam on the
+        train split, the device rule's threshold tau tuned on the validation
+        split (the cheapest tau whose success reaches the fixed pair (4, 20)),
+        test-split report, checkpoint.
 
 Training: Adam on mean cross-entropy through rsvd_mlp_train_step (the
 library's own forward / backward / update kernels); torch only holds the
@@ -24,7 +34,8 @@ tensors and shuffles the sample order.
 
 Checkpoint file: 64-byte header (magic b"RSVDMLP1", format version, parameter
 count, Adam step, seed, training-set size, 8-byte hash of the training
-features and labels), then theta, adam_m, adam_v as little-endian float32.
+features and labels, f32 tau), then theta, adam_m, adam_v as little-endian
+float32.
 """
 import argparse
 import ctypes
@@ -70,6 +81,8 @@ def _buckets(order, size):
 
 def residual_norms(data, Us, idx, krylov=40, bucket=256):
     """||(I - U U^T) A_b||_2 for the planted matrices b in idx (float64 numpy)."""
+    if data.get("hh") is None:
+        return residual_norms_dense(data, Us, idx, krylov)
     dev = data["A"][0].device
     spec = data["spec"]
     out = np.zeros(len(idx))
@@ -122,6 +135,74 @@ def residual_norms(data, Us, idx, krylov=40, bucket=256):
         lam = torch.linalg.eigvalsh(H)[:, -1].clamp_min(0.0)
         for i, b in enumerate(grp):
             out[pos[b]] = math.sqrt(float(lam[i]))
+    return out
+
+
+def residual_norms_dense(data, Us, idx, krylov=40, max_bytes=4 << 30):
+    """||(I - U U^T) A_b||_2 from the stored matrices themselves (float64
+    numpy), for inputs without known factors: E = P A with P = I - U U^T,
+    the largest eigenvalue of E^T E by a Krylov iteration with full
+    re-orthogonalisation (Lanczos-type, as residual_norms), matrices grouped
+    by size into padded batches of at most max_bytes of float64 A."""
+    A_list = data["A"]
+    dev = A_list[0].device
+    out = np.zeros(len(idx))
+    pos = {b: i for i, b in enumerate(idx)}
+    order = sorted(idx, key=lambda b: (A_list[b].shape[1], A_list[b].shape[0]))
+    g = torch.Generator(device=dev)
+    g.manual_seed(54321)
+    i0 = 0
+    while i0 < len(order):
+        grp = [order[i0]]
+        mx, nx = A_list[order[i0]].shape
+        while i0 + len(grp) < len(order):
+            b = order[i0 + len(grp)]
+            m2, n2 = max(mx, A_list[b].shape[0]), max(nx, A_list[b].shape[1])
+            if (len(grp) + 1) * m2 * n2 * 8 > max_bytes:
+                break
+            grp.append(b)
+            mx, nx = m2, n2
+        i0 += len(grp)
+        B = len(grp)
+        kx = int(max(Us[b].shape[1] for b in grp))
+        A = torch.zeros(B, mx, nx, dtype=torch.float64, device=dev)
+        U = torch.zeros(B, mx, kx, dtype=torch.float64, device=dev)
+        mask = torch.zeros(B, nx, dtype=torch.float64, device=dev)
+        for i, b in enumerate(grp):
+            m, n = A_list[b].shape
+            A[i, :m, :n] = A_list[b].to(torch.float64)
+            U[i, :m, :Us[b].shape[1]] = Us[b].to(torch.float64)
+            mask[i, :n] = 1.0
+        At = A.transpose(1, 2).contiguous()
+        Ut = U.transpose(1, 2).contiguous()
+
+        def proj(w):                       # (I - U U^T) w
+            return w - torch.bmm(U, torch.bmm(Ut, w[:, :, None]))[:, :, 0]
+
+        def apply(v):                      # E^T E v, E = (I - U U^T) A
+            w = proj(torch.bmm(A, v[:, :, None])[:, :, 0])
+            return torch.bmm(At, proj(w)[:, :, None])[:, :, 0]
+
+        s = min(krylov, nx)
+        Q = torch.zeros(B, nx, s, dtype=torch.float64, device=dev)
+        MQ = torch.zeros_like(Q)
+        v = torch.randn(B, nx, generator=g, device=dev, dtype=torch.float64) * mask
+        v = v / v.norm(dim=1, keepdim=True).clamp_min(1e-300)
+        scale = torch.linalg.matrix_norm(A, ord="fro")[:, None] ** 2
+        for j in range(s):
+            Q[:, :, j] = v
+            w = apply(v)
+            MQ[:, :, j] = w
+            for _ in range(2):
+                w = w - torch.bmm(Q[:, :, :j + 1], torch.bmm(Q[:, :, :j + 1].transpose(1, 2), w[:, :, None]))[:, :, 0]
+            nrm = w.norm(dim=1, keepdim=True)
+            v = torch.where(nrm > 1e-14 * scale, w / nrm.clamp_min(1e-300), torch.zeros_like(w))
+        H = torch.bmm(Q.transpose(1, 2), MQ)
+        H = 0.5 * (H + H.transpose(1, 2))
+        lam = torch.linalg.eigvalsh(H)[:, -1].clamp_min(0.0)
+        for i, b in enumerate(grp):
+            out[pos[b]] = math.sqrt(float(lam[i]))
+        del A, At, U, Ut, Q, MQ
     return out
 
 
@@ -204,8 +285,9 @@ def data_hash(F, y):
     return h.digest()[:8]
 
 
-def save_checkpoint(path, tr, seed, n_train, digest):
+def save_checkpoint(path, tr, seed, n_train, digest, tau=0.0):
     hdr = MAGIC + struct.pack("<IIIQQ", 1, L.MLP_PARAMS, tr.step_no, seed, n_train) + digest
+    hdr += struct.pack("<f", float(tau))
     hdr += b"\0" * (64 - len(hdr))
     with open(path, "wb") as f:
         f.write(hdr)
@@ -234,7 +316,8 @@ def load_checkpoint(path=DEFAULT_CHECKPOINT, device="cuda", adam=False):
     L.check(lib.rsvd_mlp_load(api.handle(theta.device), os.fsencode(path), theta.data_ptr(),
                               m.data_ptr() if adam else None, v.data_ptr() if adam else None,
                               ctypes.byref(hdr)), "rsvd_mlp_load")
-    info = dict(step=hdr.step, seed=hdr.seed, n_train=hdr.n_train, digest=bytes(hdr.digest).hex())
+    info = dict(step=hdr.step, seed=hdr.seed, n_train=hdr.n_train, digest=bytes(hdr.digest).hex(),
+                tau=float(hdr.tau) if hdr.tau > 0 else None)
     return ((theta, m, v) if adam else theta), info
 
 
@@ -297,12 +380,14 @@ def _timed_batch(data, ks, reps, **kw):
     return bt, (time.perf_counter() - t0) * 1e3 / reps
 
 
-def evaluate_arms(data, theta, seed=2148, reps=3, tau=DEFAULT_TAU, fixed=(4, 20)):
+def evaluate_arms(data, theta, seed=2148, reps=3, tau=DEFAULT_TAU, fixed=(4, 20), tau_graph=None):
     """Three arms on one generated split (solves/s, fraction within 1 %):
     (i) FP32 plain at the paper's defaults q = 2, p = 10; (ii) FP32 plain at a
     fixed stronger pair; (iii) bf16 mixed precision with the learned (q, p),
     timed end to end (sketch features, network, planning, solve).  Excess
-    errors are exact (residual_norms against the planted matrices)."""
+    errors are exact (residual_norms against the planted matrices).  tau:
+    threshold of the host route (decide); tau_graph: of the device rule
+    (default tau)."""
     n_mat = len(data["A"])
     ks = [int(x) for x in data["spec"]["k"]]
     sk1 = np.array([data["sigma"][b][ks[b]] for b in range(n_mat)])
@@ -326,7 +411,7 @@ def evaluate_arms(data, theta, seed=2148, reps=3, tau=DEFAULT_TAU, fixed=(4, 20)
     # matrix, which covers every class of the label set at the chosen q)
     for name, prec in (("fp32_learned_graph", "plain"), ("bf16_learned_graph", "bf16_mixed")):
         bt, ms = _timed_batch(data, ks, reps, p=P_CHOICES[-1], seed=seed, precision=prec, learned=True,
-                              theta=theta, tau=tau)
+                              theta=theta, tau=tau if tau_graph is None else tau_graph)
         q = bt.choices()
         err = success(bt)
         out[name] = dict(ms=ms, solves_per_s=n_mat / ms * 1e3, errors=err,
@@ -363,67 +448,135 @@ def evaluate_arms(data, theta, seed=2148, reps=3, tau=DEFAULT_TAU, fixed=(4, 20)
     return out
 
 
-def main(argv=None):
-    ap = argparse.ArgumentParser(description="train the (q, p) selector on generated matrices")
-    ap.add_argument("--n-train", type=int, default=4096)
-    ap.add_argument("--n-val", type=int, default=1024)
-    ap.add_argument("--epochs", type=int, default=300)
-    ap.add_argument("--lr", type=float, default=2e-3)
-    ap.add_argument("--seed", type=int, default=7)
-    ap.add_argument("--out", default=DEFAULT_CHECKPOINT)
-    ap.add_argument("--report", default=None)
-    ap.add_argument("--dump", default=None, help="also save features, labels and error tables (.npz)")
-    args = ap.parse_args(argv)
+def device_q_rule(prob, tau):
+    """The choice of q that rsvd_batch_create_learned makes on the device for
+    solves at p = 20 (every class covered by its q): the fewest q whose
+    classes hold mass >= tau, else 4 (tau <= 0: the most probable class)."""
+    prob = np.asarray(prob, dtype=np.float64)
+    if tau <= 0:
+        return np.argmax(prob, axis=1) // len(P_CHOICES)
+    cum = np.cumsum(prob.reshape(len(prob), -1, len(P_CHOICES)).sum(axis=2), axis=1)
+    hit = cum >= tau
+    return np.where(hit.any(axis=1), np.argmax(hit, axis=1), 4)
+
+
+def label_shard(count, split, lo, hi, factors):
+    """Features (float32 numpy, (hi - lo) x 131), labels, error table,
+    reachability and target ranks of matrices lo..hi-1 of a split of `count`
+    generated matrices."""
     from synth import learned_data as ld
+    data = ld.build_range(count, split, lo, hi, factors=factors)
+    tab = excess_table(data)
+    ks = np.array([int(x) for x in data["spec"]["k"]])
+    lab, ok = labels_from_table(tab, ks)
+    F = features(data).cpu().numpy()
+    del data
+    torch.cuda.empty_cache()
+    return dict(F=F, y=lab, tab=tab, ok=ok, k=ks)
 
-    def log(msg):
-        print(f"[selector] {msg}", file=sys.stderr, flush=True)
 
-    out = {}
-    sets = {}
-    for split, count in (("train", args.n_train), ("val", args.n_val)):
+def _log(msg):
+    print(f"[selector] {msg}", file=sys.stderr, flush=True)
+
+
+def cmd_label(args):
+    """Label shards of a split and store them as .npz files (one per shard)."""
+    os.makedirs(args.dir, exist_ok=True)
+    hi_all = args.count if args.hi is None else min(args.hi, args.count)
+    for lo in range(args.lo, hi_all, args.shard):
+        hi = min(hi_all, lo + args.shard)
         t0 = time.perf_counter()
-        data = ld.build(count, split)
-        torch.cuda.synchronize()
-        log(f"{split}: {count} matrices generated in {time.perf_counter() - t0:.1f} s")
-        t0 = time.perf_counter()
-        tab = excess_table(data, log=log)
-        ks = [int(x) for x in data["spec"]["k"]]
-        lab, ok = labels_from_table(tab, ks)
-        F = features(data)
-        log(f"{split}: labels in {time.perf_counter() - t0:.1f} s; reachable {ok.mean():.4f}; "
-            f"class histogram {np.bincount(lab, minlength=N_CLASSES).tolist()}")
-        sets[split] = (F, torch.tensor(lab, device=F.device), tab, ok, ks)
-        out[f"{split}_reachable"] = float(ok.mean())
-        out[f"{split}_hist"] = np.bincount(lab, minlength=N_CLASSES).tolist()
-        del data
-        torch.cuda.empty_cache()
-    F, y = sets["train"][0], sets["train"][1]
-    Fv, yv = sets["val"][0], sets["val"][1]
-    tr, hist = train(F, y, epochs=args.epochs, lr=args.lr, seed=args.seed, Fv=Fv, yv=yv, log=log)
+        d = label_shard(args.count, args.split, lo, hi, args.factors)
+        np.savez(os.path.join(args.dir, f"{args.split}_{args.count}_{lo:06d}_{hi:06d}.npz"), **d)
+        _log(f"{args.split} [{lo}, {hi}) of {args.count}: {time.perf_counter() - t0:.1f} s, reachable "
+             f"{d['ok'].mean():.4f}")
+
+
+def _load_split(dirname, split):
+    parts = sorted(f for f in os.listdir(dirname) if f.startswith(split + "_") and f.endswith(".npz"))
+    if not parts:
+        return None
+    ds = [np.load(os.path.join(dirname, f)) for f in parts]
+    return {key: np.concatenate([d[key] for d in ds]) for key in ("F", "y", "tab", "ok", "k")}
+
+
+def cmd_train(args):
+    """Train on labelled shards, tune the device rule's threshold on the
+    validation split, evaluate on the test split, write the checkpoint."""
+    sets = {sp: _load_split(args.dir, sp) for sp in ("train", "val", "test")}
+    out = {f"n_{sp}": (0 if d is None else int(len(d["y"]))) for sp, d in sets.items()}
+    for sp, d in sets.items():
+        if d is not None:
+            out[f"{sp}_reachable"] = float(d["ok"].mean())
+            out[f"{sp}_hist"] = np.bincount(d["y"], minlength=N_CLASSES).tolist()
+    dev = torch.device("cuda")
+    F = torch.tensor(sets["train"]["F"], device=dev)
+    y = torch.tensor(sets["train"]["y"], device=dev)
+    Fv = torch.tensor(sets["val"]["F"], device=dev)
+    yv = torch.tensor(sets["val"]["y"], device=dev)
+    tr, hist = train(F, y, epochs=args.epochs, lr=args.lr, seed=args.seed, Fv=Fv, yv=yv, log=_log)
     out["history"] = hist
-    # validation: success rate and cost of the decision rule for several tau
-    tabv, okv, ksv = sets["val"][2], sets["val"][3], sets["val"][4]
-    prob, _ = api.mlp_forward(tr.theta, Fv)
-    prob = prob.cpu().numpy()
-    base = np.array([pair_cost(k, 7) for k in ksv]).sum()          # q = 2, p = 10
-    for tau in (0.5, 0.7, DEFAULT_TAU, 0.9):
-        pick = decide(prob, ksv, tau)
-        err = tabv[np.arange(len(pick)), pick]
-        cost = np.array([pair_cost(k, c) for k, c in zip(ksv, pick)]).sum()
-        out[f"val_tau_{tau}"] = dict(success=float(np.mean(err <= TOL)),
-                                     success_reachable=float(np.mean(err[okv] <= TOL)),
-                                     cost_vs_default=float(cost / base))
-        log(f"val tau={tau}: {out[f'val_tau_{tau}']}")
-    if args.dump:
-        np.savez(args.dump, **{f"{sp}_{name}": val for sp, (Fs, ys, tab, ok, ks) in sets.items()
-                               for name, val in (("F", Fs.cpu().numpy()), ("y", ys.cpu().numpy()), ("tab", tab),
-                                                 ("ok", ok), ("k", np.array(ks)))})
-    save_checkpoint(args.out, tr, args.seed, args.n_train, data_hash(F, y))
-    log(f"checkpoint written to {args.out}")
+
+    def rule_stats(sp, tau):
+        d = sets[sp]
+        prob = api.mlp_forward(tr.theta, torch.tensor(d["F"], device=dev))[0].cpu().numpy()
+        q = device_q_rule(prob, tau)
+        err = d["tab"][np.arange(len(q)), 3 * q + 2]               # solves at p = 20
+        cost = np.array([pair_cost(int(k), 3 * int(qq) + 2) for k, qq in zip(d["k"], q)]).sum()
+        fixed = np.array([pair_cost(int(k), N_CLASSES - 1) for k in d["k"]]).sum()
+        return dict(success=float(np.mean(err <= TOL)), success_reachable=float(np.mean(err[d["ok"]] <= TOL)),
+                    cost_vs_fixed_q4_p20=float(cost / fixed), q_hist=np.bincount(q, minlength=5).tolist())
+
+    # threshold of the device rule: the cheapest tau whose validation success
+    # reaches that of the fixed pair (q, p) = (4, 20)
+    target = float(np.mean(sets["val"]["tab"][:, N_CLASSES - 1] <= TOL))
+    out["val_fixed_q4_p20_success"] = target
+    best = None
+    for tau in np.round(np.arange(0.50, 1.0, 0.01), 2):
+        st = rule_stats("val", float(tau))
+        out[f"val_tau_{tau:.2f}"] = st
+        if st["success"] >= target and (best is None or st["cost_vs_fixed_q4_p20"] < best[1]["cost_vs_fixed_q4_p20"]):
+            best = (float(tau), st)
+    tau = best[0] if best else 0.99
+    out["tau"] = tau
+    _log(f"tau {tau}: validation {best[1] if best else None} (fixed (4, 20): {target:.4f})")
+    if sets["test"] is not None:
+        tab = sets["test"]["tab"]
+        out["test_fixed_q4_p20_success"] = float(np.mean(tab[:, N_CLASSES - 1] <= TOL))
+        out["test_fixed_q2_p10_success"] = float(np.mean(tab[:, 7] <= TOL))
+        out["test_learned"] = rule_stats("test", tau)
+        _log(f"test: learned {out['test_learned']}, fixed (4, 20) {out['test_fixed_q4_p20_success']:.4f}, "
+             f"(2, 10) {out['test_fixed_q2_p10_success']:.4f}")
+    save_checkpoint(args.out, tr, args.seed, len(sets["train"]["y"]), data_hash(F, y), tau)
+    _log(f"checkpoint written to {args.out}")
     if args.report:
         with open(args.report, "w") as f:
             json.dump(out, f, indent=1)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description="label generated matrices and train the (q, p) selector")
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    lb = sub.add_parser("label", help="label shards of a split into .npz files")
+    lb.add_argument("--split", required=True, choices=("train", "val", "test"))
+    lb.add_argument("--count", type=int, required=True, help="size of the whole split")
+    lb.add_argument("--lo", type=int, default=0)
+    lb.add_argument("--hi", type=int, default=None)
+    lb.add_argument("--shard", type=int, default=4096)
+    lb.add_argument("--factors", default="haar", choices=("haar", "householder"))
+    lb.add_argument("--dir", required=True)
+    tn = sub.add_parser("train", help="train on labelled shards and write the checkpoint")
+    tn.add_argument("--dir", required=True)
+    tn.add_argument("--epochs", type=int, default=200)
+    tn.add_argument("--lr", type=float, default=2e-3)
+    tn.add_argument("--seed", type=int, default=7)
+    tn.add_argument("--out", default=DEFAULT_CHECKPOINT)
+    tn.add_argument("--report", default=None)
+    args = ap.parse_args(argv)
+    if args.cmd == "label":
+        cmd_label(args)
+    else:
+        cmd_train(args)
 
 
 if __name__ == "__main__":

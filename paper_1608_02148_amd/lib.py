@@ -66,7 +66,8 @@ class RrpcaResult(ctypes.Structure):
 
 class MlpHeader(ctypes.Structure):
     _fields_ = [("version", c_uint32), ("params", c_uint32), ("step", c_uint32), ("reserved", c_uint32),
-                ("seed", c_uint64), ("n_train", c_uint64), ("digest", ctypes.c_uint8 * 8)]
+                ("seed", c_uint64), ("n_train", c_uint64), ("digest", ctypes.c_uint8 * 8),
+                ("tau", ctypes.c_float), ("reserved2", c_uint32)]
 
 
 class BatchDesc(ctypes.Structure):
@@ -76,7 +77,7 @@ class BatchDesc(ctypes.Structure):
                 ("q", c_int32), ("p", c_int32)]
 
 
-BATCH_GRAPH, BATCH_STAMPS, BATCH_FEATURES, BATCH_OWN_QP = 1, 2, 4, 8
+BATCH_GRAPH, BATCH_STAMPS, BATCH_FEATURES, BATCH_OWN_QP, BATCH_CHUNKED = 1, 2, 4, 8, 16
 MLP_INPUTS, MLP_HIDDEN, MLP_CLASSES, MLP_PARAMS = 131, 64, 15, 13583
 LEARNED_QMAX, LEARNED_PMAX, LEARNED_FALLBACK_Q = 4, 20, 3
 

@@ -9,14 +9,19 @@ Recipe (the shape distribution of the 4096-matrix batch workload):
   f(i) = exp(-(i - 1) / tau), tau ~ logU[2, 200]; f(1) = 1.  Then a spectral
   floor: sigma_i = f(i) + nu with nu ~ logU[1e-8, 1e-2], so every singular
   value of the planted matrix is known exactly.
-* Singular vectors: U = H(a1) H(a2) and V = H(b1) H(b2) with Householder
+* Singular vectors (factors="householder", the default): U = H(a1) H(a2)
+  and V = H(b1) H(b2) with Householder
   reflections H(x) = I - 2 x x^T about Gaussian unit vectors, so A =
   U[:, :r] diag(sigma) V[:, :r]^T is dense and has exactly the planted
   singular values.  A Gaussian test matrix only sees the spectrum (V^T Omega
   has the same distribution as Omega), so the randomized SVD's error
   statistics are those of Haar-distributed factors, at a fraction of the
   generation cost.  The reflection vectors are kept so that an evaluation can
-  apply U^T exactly.
+  apply U^T exactly.  These factors are close to the identity (a rank-two
+  change each), so A is nearly diagonal and its f32 rounding is relative to
+  each singular value; factors="haar" draws dense Haar factors instead
+  (polar factors of Gaussian blocks), whose rounding error spreads over all
+  entries as in the 4096-matrix batch workload.
 * A is formed in float64 and rounded once to the storage type.
 
 Splits use separate seeds: train 5101, validation 5102, test 5103.
@@ -50,16 +55,36 @@ def spectrum_of(spec, b):
     return f + spec["nu"][b]
 
 
-def build(count, split="train", device="cuda", out_dtype=None, **shape_kw):
+def build_range(count, split, lo, hi, device="cuda", out_dtype=None, factors="householder", **shape_kw):
+    """Matrices lo..hi-1 of a split of `count` matrices (the shapes and
+    spectra of shapes(count, seed)), generated with their own torch generator
+    seeded from (split seed, lo): a large split is built shard by shard with
+    a fixed shard layout.  Returns the same dict as build() for that range."""
+    seed = SPLIT_SEEDS[split] if isinstance(split, str) else int(split)
+    full = shapes(count, seed, **shape_kw)
+    spec = {key: val[lo:hi] for key, val in full.items()}
+    return _form(spec, seed * 1000003 + lo, device, out_dtype, factors)
+
+
+def build(count, split="train", device="cuda", out_dtype=None, factors="householder", **shape_kw):
     """The split's matrices in one ragged buffer on ``device``.
 
     Returns dict(buffer, A (list of row-major views), spec (shapes()), sigma
     (list of float64 numpy spectra), hh (list of (a1, a2) float64 tensors)).
     """
+    seed = SPLIT_SEEDS[split] if isinstance(split, str) else int(split)
+    return _form(shapes(count, seed, **shape_kw), seed, device, out_dtype, factors)
+
+
+def _form(spec, seed, device, out_dtype, factors="householder"):
+    """Planted matrices for the shapes and spectra in spec (see build()).
+
+    factors = "householder": U = H(a1) H(a2), V = H(b1) H(b2) (hh holds the
+    reflection vectors); "haar": dense Haar factors (polar factors of
+    Gaussian blocks, synth.matrices._haar_torch), hh = None."""
     import torch
     out_dtype = out_dtype or torch.float32
-    seed = SPLIT_SEEDS[split] if isinstance(split, str) else int(split)
-    spec = shapes(count, seed, **shape_kw)
+    count = len(spec["m"])
     m, n = spec["m"].astype(np.int64), spec["n"].astype(np.int64)
     offs = np.concatenate([[0], np.cumsum(m * n)])
     buf = torch.empty(int(offs[-1]), dtype=out_dtype, device=device)
@@ -76,6 +101,15 @@ def build(count, split="train", device="cuda", out_dtype=None, **shape_kw):
         mb, nb = int(m[b]), int(n[b])
         sig = spectrum_of(spec, b)
         r = len(sig)
+        if factors == "haar":
+            from . import matrices as mat
+            U = mat._haar_torch(mb, r, g, device)
+            V = mat._haar_torch(nb, r, g, device)
+            view = buf[int(offs[b]):int(offs[b + 1])].view(mb, nb)
+            view.copy_((U * torch.as_tensor(sig, device=device)[None, :]) @ V.t())
+            views.append(view)
+            sigmas.append(sig)
+            continue
         a1, a2, b1, b2 = unit(mb), unit(mb), unit(nb), unit(nb)
         A = torch.zeros(mb, nb, dtype=f64, device=device)
         A[torch.arange(r, device=device), torch.arange(r, device=device)] = torch.as_tensor(sig, device=device)
@@ -88,4 +122,4 @@ def build(count, split="train", device="cuda", out_dtype=None, **shape_kw):
         views.append(view)
         sigmas.append(sig)
         hh.append((a1, a2))
-    return dict(buffer=buf, A=views, spec=spec, sigma=sigmas, hh=hh)
+    return dict(buffer=buf, A=views, spec=spec, sigma=sigmas, hh=hh if factors != "haar" else None)

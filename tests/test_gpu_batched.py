@@ -191,3 +191,26 @@ def test_c4_full_batch_sampled_against_oracle():
         big = so >= 1e-3 * so[0]
         np.testing.assert_allclose(s[big], so[big], rtol=1e-4, err_msg=f"matrix {b}")
     assert torch.all(torch.isfinite(bt.s_flat))
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_chunked_batch_equals_unchunked(dtype):
+    """RSVD_BATCH_CHUNKED only changes which launches a solve shares (each
+    size class split into chunks run one after another): every member's steps
+    and kernels are the same, so the outputs are bit for bit those of the
+    unchunked batch, and each member's device-clock span is recorded."""
+    from paper_1608_02148_amd import api
+    shapes = SHAPES * 6                        # several members per size class
+    As = _mats(dtype, shapes, 700)
+    ks = [k for _, _, k in shapes]
+    ref = api.Batch(As, ks, p=10, q=2, seed=3)
+    ref.run()
+    ch = api.Batch(As, ks, p=10, q=2, seed=3, chunked=True, stamps=True)
+    ch.run()
+    torch.cuda.synchronize()
+    assert torch.equal(ref.s_flat, ch.s_flat) and torch.equal(ref.u_flat, ch.u_flat)
+    assert torch.equal(ref.v_flat, ch.v_flat)
+    st, hz = ch.stamps()
+    assert np.all(st[:, 1] > st[:, 0])
+    ref.close()
+    ch.close()

@@ -94,3 +94,32 @@ def test_decision_rule():
     # cheaper class dominates both
     assert pick[1] == lrn.pair_class(2, 20)
     assert L.decide(prob, [20, 20], tau=0.4)[1] == lrn.pair_class(0, 5)
+
+
+def test_dense_haar_data_and_their_residual_norms():
+    """factors="haar": the planted spectrum is exact (numpy SVD of the stored
+    f64 instance) and the residual norm computed from the stored matrices
+    equals numpy's 2-norm."""
+    data = ld.build(6, 79, device="cpu", out_dtype=torch.float64, m_range=(60, 200), n_range=(40, 120), k_max=20,
+                    factors="haar")
+    assert data["hh"] is None
+    Us, want = [], []
+    for b, A in enumerate(data["A"]):
+        s = np.linalg.svd(A.numpy(), compute_uv=False)
+        np.testing.assert_allclose(s, data["sigma"][b], rtol=1e-10, atol=1e-14 * s[0])
+        k = int(data["spec"]["k"][b])
+        U, _, _ = orc.rsvd(A.numpy(), k, p=5, q=b % 3, seed=2, stream_id=b)
+        Us.append(torch.tensor(U))
+        want.append(np.linalg.norm(A.numpy() - U @ (U.T @ A.numpy()), 2))
+    np.testing.assert_allclose(L.residual_norms(data, Us, list(range(6))), want, rtol=1e-9)
+
+
+def test_sharded_build_is_deterministic_and_matches_the_recipe():
+    a = ld.build_range(40, "val", 8, 16, device="cpu", out_dtype=torch.float64, m_range=(60, 120),
+                       n_range=(40, 80), k_max=20)
+    b = ld.build_range(40, "val", 8, 16, device="cpu", out_dtype=torch.float64, m_range=(60, 120),
+                       n_range=(40, 80), k_max=20)
+    full = ld.shapes(40, ld.SPLIT_SEEDS["val"], m_range=(60, 120), n_range=(40, 80), k_max=20)
+    assert np.array_equal(a["spec"]["m"], full["m"][8:16]) and np.array_equal(a["spec"]["k"], full["k"][8:16])
+    for x, y in zip(a["A"], b["A"]):
+        assert torch.equal(x, y)
