@@ -53,7 +53,8 @@ PEAKS = {  # MI355X published dense peaks
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_c2_f32_traffic.md")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_1608_02148_amd", "csrc", f) for f in ("gemm.hpp", "exec.hpp", "launch.hpp")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1608_02148_amd", "csrc", f)
+                  for f in ("gemm.hpp", "gemm_stream.hpp", "exec.hpp", "launch.hpp")]
 
 
 def measured_traffic():
@@ -71,6 +72,14 @@ def measured_traffic():
     if vals.get("kernel_sources_sha256") != h.hexdigest()[:16]:
         return {}
     return {"AT_Q": float(vals["AT_Q_hbm_bytes"]), "A_X": float(vals["A_X_hbm_bytes"])}
+
+
+def streamed_product(m, n, l, mode):
+    """Whether the library runs this single-solve product (mode 0: A X, 1: A^T
+    Q) on the streamed-A kernel: m n >= 2^24, 64 < l <= 224, and for A^T Q
+    n % 4 == 0 (A's rows are 16-byte aligned here)."""
+    return m >= 256 and n >= 256 and m * n >= (1 << 24) and 64 < l <= 224 and (mode == 0 or n % 4 == 0) \
+        and os.environ.get("RSVD_PRODUCTS") != "staged"
 
 
 def log(msg):
@@ -703,11 +712,16 @@ def main():
         cnt = max(d["count"], 1)
         avg_ms = d["total_ms"] / cnt
         mode = 1 if dom_name == "AT_Q" else 0
-        if bound == "mfma":
+        arith = 0 if bound == "mfma" else 1
+        if streamed_product(m, n, l, mode):
+            # the streamed-A kernel (A read straight into the matrix cores); the
+            # event-timed launch covers the packing of X and the product
+            ncb = 8 if l <= 128 else 14
+            kern = f"single_kernel<StreamBody<float, {mode}, {arith}, {ncb}, 1, false, false>>"
+        elif bound == "mfma":
             var = api_variants[6 * mode + 5]
             shape = {0: "4, 4, 2, 2", 1: "4, 2, 2, 4", 2: "2, 2, 4, 4"}[var]
-            # single solves read X from its packed copy (the instance with XKP = true);
-            # the event-timed launch covers the pack kernel and the product
+            # single solves read X from its packed copy (the instance with XKP = true)
             kern = f"single_kernel<GemmBody<float, float, float, {mode}, {shape}, true>>"
         else:
             kern = f"single_kernel<Bf16Body<float, {mode}, false, 4, 4, 2, 2>>"

@@ -579,16 +579,23 @@ int rsvd_test_matrix(rsvd_handle_t handle, int32_t dtype, int64_t n, int32_t l,
  * 1..4 = that many chunks of K, each product writing a partial block to the
  * workspace, summed in chunk order (deterministic).  Other values:
  * RSVD_ERR_INVALID.
- * work: ignored (may be NULL) for RSVD_ARITH_STORAGE without a split; the
+ * work: optional (may be NULL) for RSVD_ARITH_STORAGE without a split; the
  * bf16 arithmetics pack X into bf16 there and split products keep their
  * partial blocks there, which needs rsvd_block_workspace_size(dtype, m, K, c)
- * bytes (RSVD_ERR_INVALID otherwise). */
+ * bytes (RSVD_ERR_INVALID otherwise).  Given at that size for the storage
+ * arithmetic, it lets large products take the streamed kernel (X copied
+ * k-contiguous there); smaller or NULL work keeps the LDS-staged tiles.
+ * Kernel choice: products with m K >= 2^24, 64 < c <= 224 and 16-byte
+ * aligned rows of A stream A straight into the matrix cores; others stage
+ * tiles of A in LDS.  Results agree to rounding (the order of the sum over K
+ * differs); RSVD_PRODUCTS=staged in the environment keeps the staged tiles. */
 int rsvd_gemm_nn(rsvd_handle_t handle, int32_t dtype, int32_t arith, int64_t m, int64_t K, int32_t c,
                  const void* A, int64_t lda, const void* X, int64_t ldx,
                  void* Y, int64_t ldy, int32_t splits, void* work, size_t work_bytes);
 
 /* Z = A^T Q (Alg. subspace_iter; Alg. rqb gives B^T): A m x n
- * (dtype, lda), Q m x c (f64/f32, ldq), Z n x c (ldz).  c <= RSVD_MAX_L_SINGLE. */
+ * (dtype, lda), Q m x c (f64/f32, ldq), Z n x c (ldz).  c <= RSVD_MAX_L_SINGLE.
+ * Kernel choice as for rsvd_gemm_nn (the streamed kernel also needs n % 4 == 0). */
 int rsvd_gemm_tn(rsvd_handle_t handle, int32_t dtype, int32_t arith, int64_t m, int64_t n, int32_t c,
                  const void* A, int64_t lda, const void* Q, int64_t ldq,
                  void* Z, int64_t ldz, void* work, size_t work_bytes);

@@ -513,7 +513,7 @@ def gemm_nn(A, X, arith="storage", splits=1):
     m, K = A.shape
     c = X.shape[1]
     Y = torch.empty(m, c, dtype=out_dtype(A), device=A.device)
-    work = _block_ws(dt, m, K, c, A.device) if (arith != "storage" or splits != 1) else None
+    work = _block_ws(dt, m, K, c, A.device)
     L.check(L.load().rsvd_gemm_nn(handle(A.device), dt, L.ARITH[arith], m, K, c, _ptr(A), A.stride(0), _ptr(X),
                                   X.stride(0), _ptr(Y), Y.stride(0), int(splits), _ptr(work),
                                   work.numel() if work is not None else 0), "rsvd_gemm_nn")

@@ -68,16 +68,18 @@ static hipError_t gemm_nn_typed(hipStream_t st, int arith, const Plan& P, int S,
                                 void* work) {
     SingleExec ex{st};
     const XPack xp = xpack_of(P, arith != 0 ? work : nullptr);
+    // k-contiguous copy of X for the storage-precision streamed products
+    TC* xk = work ? at<TC>(work, P.xk) : nullptr;
     if (S == 1)
         return gemm_step<TA, TC, MODE_NN>(ex, arith, 0, static_cast<const TA*>(A), lda, m, K,
                                           static_cast<const TC*>(X), ldx, c, static_cast<TC*>(Y), ldy, 1, 0,
-                                          nullptr, nullptr, 0, Gate{}, xp);
+                                          nullptr, nullptr, 0, Gate{}, xp, xk, P.ldxk);
     // split n-reduction: S partial blocks (m x Lp each) summed in split order
     TC* part = at<TC>(work, P.part);
     const int64_t stride = m * P.Lp;
     RSVD_TRY((gemm_step<TA, TC, MODE_NN>(ex, arith, 0, static_cast<const TA*>(A), lda, m, K,
                                         static_cast<const TC*>(X), ldx, c, part, P.Lp, S, stride, nullptr, nullptr,
-                                        0, Gate{}, xp)));
+                                        0, Gate{}, xp, xk, P.ldxk)));
     return reduce_step<TC>(ex, part, S, stride, P.Lp, m, c, static_cast<TC*>(Y), ldy);
 }
 
@@ -94,6 +96,7 @@ int rsvd_gemm_nn(rsvd_handle_t handle, int32_t dtype, int32_t arith, int64_t m, 
     const int S = splits == 0 ? P.sp.nn : splits;
     // packed-X scratch (bf16 arithmetics) and split partial blocks live in work
     if ((arith != 0 || S > 1) && (!work || work_bytes < P.bytes)) return RSVD_ERR_INVALID;
+    if (work_bytes < P.bytes) work = nullptr;     // optional: the streamed products' copy of X lives there
     hipError_t e;
     switch (dtype) {
         case RSVD_F64: e = gemm_nn_typed<double, double>(handle->stream, arith, P, S, m, K, c, A, lda, X, ldx, Y, ldy, work); break;
@@ -113,13 +116,15 @@ static hipError_t gemm_tn_typed(rsvd_handle_t h, int arith, const Plan& P, int64
     const int S = P.sp.tn;
     TC* part = at<TC>(work, P.part);
     const XPack xp = xpack_of(P, work);
+    TC* xk = at<TC>(work, P.xk);
     if (S == 1)
         return gemm_step<TA, TC, MODE_TN>(ex, arith, 0, static_cast<const TA*>(A), lda, n, m,
                                           static_cast<const TC*>(Q), ldq, c, static_cast<TC*>(Z), ldz, 1, 0, nullptr,
-                                          nullptr, 0, Gate{}, xp);
+                                          nullptr, 0, Gate{}, xp, xk, P.ldxk);
     RSVD_TRY((gemm_step<TA, TC, MODE_TN>(ex, arith, 0, static_cast<const TA*>(A), lda, n, m,
                                         static_cast<const TC*>(Q), ldq, c, part, P.Lp, S,
-                                        static_cast<int64_t>(n) * P.Lp, nullptr, nullptr, 0, Gate{}, xp)));
+                                        static_cast<int64_t>(n) * P.Lp, nullptr, nullptr, 0, Gate{}, xp, xk,
+                                        P.ldxk)));
     return reduce_step<TC>(ex, part, S, static_cast<int64_t>(n) * P.Lp, P.Lp, n, c, static_cast<TC*>(Z), ldz);
 }
 

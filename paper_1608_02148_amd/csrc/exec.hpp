@@ -58,6 +58,7 @@ inline hipError_t raise_lds_limit(K kernel, size_t bytes) {
 
 // Launches each step immediately for one problem.
 struct SingleExec {
+    static constexpr bool kSingle = true;
     hipStream_t stream;
     template <class Body>
     hipError_t run(const typename Body::Args& a) {
@@ -81,6 +82,7 @@ struct SingleExec {
 // prefix sums into device memory; launch() then issues one grouped launch per
 // step with no host synchronisation.
 struct BatchRecorder {
+    static constexpr bool kSingle = false;
     typedef hipError_t (*LaunchFn)(hipStream_t, const void* args, const int* prefix, int nprob, int total,
                                    size_t lds);
     typedef hipError_t (*PrepFn)(size_t lds);

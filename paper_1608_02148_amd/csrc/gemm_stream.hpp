@@ -1,0 +1,449 @@
+// Streamed-A tall-skinny products: Y = A X (NN) and Z = A^T Q (TN) for large A.
+//
+// The large operand A is read from global memory straight into matrix-core
+// operand registers, once, and never staged through LDS; only the skinny
+// operand (X, or Q, packed k-contiguous per column) is staged in LDS, where
+// the four waves of a workgroup (one per SIMD) share it.  Each wave owns 64
+// output rows and every output column of the product (NC = 16 NCB <= 224), so
+// one A fragment feeds NCB column blocks of matrix-core work and one X
+// fragment feeds four row blocks: per 16-byte LDS read a wave issues four
+// MFMAs.  The accumulators (up to 224 registers) live in the AGPR file; the
+// next chunk of A is loaded into registers while the current one is
+// multiplied (one chunk ahead), and X's next chunk is staged through
+// registers into the other of two LDS buffers.  (CS > 1 splits the columns
+// over CS groups of four waves; not launched, see stream_fits.)
+//
+// Lane (r, g) (r = lane & 15, g = lane >> 4) owns the k-run [k0 + LK g,
+// k0 + LK (g + 1)) of each chunk of KC = 4 LK reduction elements; substep s of
+// the chunk uses elements V s .. V s + V - 1 of every lane's run (V = 1 for the
+// f32 16x16x4 MFMA, 8 for the bf16 16x16x32 MFMA), so lane group g always
+// supplies the k-values the MFMA expects from it and A and X agree on the
+// order.  (The order in which a product sums its reduction does not change
+// what it computes.)
+//
+//   NN: lane (r, g) loads LK consecutive elements of row r0 + 16 i + r for each
+//       of the wave's four row blocks i (32 or 64 contiguous bytes: whole cache
+//       lines per row and chunk).
+//   TN: the output rows are columns of A.  Lane (i, g) loads four consecutive
+//       columns c0 + 4 i .. c0 + 4 i + 3 of each of its LK rows of A (16 lanes
+//       read 64 or 128 contiguous bytes of a row); MFMA row block e then takes
+//       column c0 + 4 i + e as its row i, so the wave's 64 output rows are the
+//       columns c0 + 16 g + 4 v + e of accumulator element v of block e.  For
+//       bf16 the lane transposes its LK x 4 block in registers into k-octets.
+//
+// Arithmetic (as in the LDS-staged tiles): 0 = f32 MFMA (bf16-stored A widened
+// exactly), 1 = bf16 MFMA on A and X rounded to bf16, 2 = split bf16: X = X_hi
+// + X_lo and, for f32-stored A or centred bf16 A (CENT), A = A_hi + A_lo, with
+// A_hi X_hi + A_hi X_lo + A_lo X_hi accumulated in f32.
+//
+// Split reduction: workgroup (tile t, split s) sums k in [s kchunk, min(K,
+// (s + 1) kchunk)) and writes partial block s (S > 1) or the result.
+#pragma once
+
+#include "common.hpp"
+#include "gemm.hpp"
+
+namespace rsvd {
+
+typedef __bf16 s8bf __attribute__((ext_vector_type(8)));
+
+template <typename TA, int MODE, int ARITH, int NCB, int CS = 1, bool CENT = false, bool MU = false>
+struct StreamTile {
+    static constexpr bool BF = ARITH != 0;
+    static constexpr bool SPLIT = ARITH == 2;
+    static constexpr bool A_LO = SPLIT && (sizeof(TA) == 4 || CENT);
+    static constexpr int V = BF ? 8 : 1;            // values per lane per MFMA
+    // k-run per lane per chunk: 16 (f32 with up to 128 columns: 64-element
+    // chunks halve the per-chunk barrier and waits), else 16 for bf16 and 8
+    // for f32 (the registers of two chunks of A beside 224 columns of
+    // accumulators)
+    static constexpr int LK = (BF || NCB <= 8) ? 16 : 8;
+    static constexpr int KC = 4 * LK;               // chunk extent
+    static constexpr int SUB = LK / V;              // MFMA substeps per chunk
+    static constexpr int RB = 4;                    // MFMA row blocks per wave
+    static constexpr int WAVES = 4 * CS;            // four row strips x CS column groups
+    static constexpr int NT = 64 * WAVES;
+    static constexpr int TROWS = 4 * 16 * RB;       // output rows per tile
+    static constexpr int NC = 16 * NCB * CS;        // output columns per tile
+    static constexpr int ESZ = BF ? 2 : 4;          // staged X element bytes
+    static constexpr int SX = KC + 16 / ESZ;        // LDS column stride: 16 bytes past a multiple of 128
+    static constexpr int XPL = SPLIT ? 2 : 1;
+    static constexpr int VPC = KC * ESZ / 16;       // 16-byte vectors per column and chunk (8)
+    static constexpr int X_PASSES = (NC * VPC + NT - 1) / NT;
+    static constexpr size_t PLANE = static_cast<size_t>(NC) * SX;
+    static constexpr size_t STAGE = XPL * PLANE;    // elements
+    static constexpr size_t LDS_BYTES = 2 * STAGE * ESZ;
+    // raw A words per lane and chunk (32-bit registers)
+    static constexpr int A_WORDS = (MODE == MODE_NN) ? RB * LK * static_cast<int>(sizeof(TA)) / 4
+                                                     : LK * 4 * static_cast<int>(sizeof(TA)) / 4;
+    static_assert((SX * ESZ) % 128 == 16, "LDS column stride");
+    static_assert(!CENT || (SPLIT && sizeof(TA) == 2 && MU), "CENT: split products of centred bf16-stored A");
+};
+
+template <typename TA>
+__device__ __forceinline__ float word_elem(const uint32_t* w, int e) {
+    if constexpr (sizeof(TA) == 4) return __uint_as_float(w[e]);
+    else return __uint_as_float(((w[e >> 1] >> (16 * (e & 1))) & 0xFFFFu) << 16);
+}
+
+__device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
+    return static_cast<uint32_t>(__builtin_bit_cast(uint16_t, static_cast<__bf16>(a))) |
+           (static_cast<uint32_t>(__builtin_bit_cast(uint16_t, static_cast<__bf16>(b))) << 16);
+}
+
+__device__ __forceinline__ float bf16_round(float x) {
+    return static_cast<float>(static_cast<__bf16>(x));
+}
+
+// One (tile, reduction range) of the product: output rows tile * TROWS ..
+// of the tile, summed over k in [kbeg, kend), written to out (row r at
+// out + (r - row0) ldo).
+template <typename TA, int MODE, int ARITH, int NCB, int CS, bool CENT, bool MU>
+__device__ __forceinline__ void gemm_stream_body(const GemmArgs<TA, float, float>& g, int tile, int64_t kbeg,
+                                                 int64_t kend, float* out, int64_t row0) {
+    typedef StreamTile<TA, MODE, ARITH, NCB, CS, CENT, MU> T;
+    constexpr int LK = T::LK, KC = T::KC, SUB = T::SUB, RB = T::RB, SX = T::SX;
+    constexpr int AW = T::A_WORDS;
+    if (g.skip_flag && ((*g.skip_flag & g.skip_mask) == 0u)) return;
+    if (g.gate && ((*g.gate & g.gate_mask) == 0u)) return;
+
+    // An (empty) use of an accumulation register: without one the compiler
+    // gives the MFMAs their all-VGPR form, which caps the wave at 256 registers
+    // and spills; with it the accumulators live in the AGPR file and the
+    // operands, staging and addresses in the VGPR file (512 in all at one wave
+    // per SIMD).
+    asm volatile("" ::: "a0");
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lg = lane >> 4;
+    const int strip = wave & 3, cb0 = (wave >> 2) * NCB;     // row strip, first column block
+    const int64_t w0 = static_cast<int64_t>(tile) * T::TROWS + static_cast<int64_t>(strip) * 16 * RB;
+
+    // ---- A: raw words of one chunk
+    auto load_a = [&](int64_t k0, uint32_t (&w)[AW], bool full) {
+        if constexpr (MODE == MODE_NN) {
+            constexpr int WPR = LK * sizeof(TA) / 4;          // words per row block
+#pragma unroll
+            for (int i = 0; i < RB; ++i) {
+                const int64_t r = min(w0 + 16 * i + lr, g.rows - 1);     // rows past the end: never stored
+                const int64_t k = k0 + LK * lg;
+                const TA* p = g.A + r * g.lda + k;
+                if (full) {
+#pragma unroll
+                    for (int v = 0; v < WPR / 4; ++v) {
+                        const u32x4 x = *reinterpret_cast<const u32x4*>(p + v * (16 / sizeof(TA)));
+#pragma unroll
+                        for (int d = 0; d < 4; ++d) w[i * WPR + 4 * v + d] = x[d];
+                    }
+                } else {
+#pragma unroll
+                    for (int d = 0; d < WPR; ++d) w[i * WPR + d] = 0u;
+                    if constexpr (sizeof(TA) == 4) {
+#pragma unroll
+                        for (int e = 0; e < LK; ++e)
+                            if (k + e < kend) w[i * WPR + e] = reinterpret_cast<const uint32_t*>(p)[e];
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < LK; ++e)
+                            if (k + e < kend)
+                                w[i * WPR + (e >> 1)] |= static_cast<uint32_t>(reinterpret_cast<const uint16_t*>(p)[e])
+                                                         << (16 * (e & 1));
+                    }
+                }
+            }
+        } else {
+            constexpr int WPR = sizeof(TA);                   // words per row of 4 columns (16 or 8 bytes)
+            // columns past the end (whole groups of 4: rows % 4 == 0) read
+            // column 0 instead and are never stored
+            const int64_t c = (w0 + 4 * lr < g.rows) ? w0 + 4 * lr : 0;
+#pragma unroll
+            for (int t = 0; t < LK; ++t) {
+                const int64_t k = k0 + LK * lg + t;
+                const TA* p = g.A + k * g.lda + c;
+                if (full || k < kend) {
+                    if constexpr (sizeof(TA) == 4) {
+                        const u32x4 x = *reinterpret_cast<const u32x4*>(p);
+#pragma unroll
+                        for (int d = 0; d < 4; ++d) w[t * WPR + d] = x[d];
+                    } else {
+                        const u32x2 x = *reinterpret_cast<const u32x2*>(p);
+                        w[t * WPR] = x[0];
+                        w[t * WPR + 1] = x[1];
+                    }
+                } else {
+#pragma unroll
+                    for (int d = 0; d < WPR; ++d) w[t * WPR + d] = 0u;
+                }
+            }
+        }
+    };
+
+    // TN with column means: this lane's four columns are fixed
+    double mu_c[4] = {0.0, 0.0, 0.0, 0.0};
+    if constexpr (MODE == MODE_TN && MU) {
+        {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t c = w0 + 4 * lr + e;
+                mu_c[e] = c < g.rows ? g.mu[c] : 0.0;
+            }
+        }
+    }
+
+    // ---- X: one chunk of the packed columns, staged through registers
+    typedef typename std::conditional<T::BF, uint16_t, float>::type XE;
+    XE* xs = reinterpret_cast<XE*>(smem_raw);
+    uint32_t rx[T::X_PASSES][T::XPL][4];
+    auto load_x = [&](int64_t k0) {
+#pragma unroll
+        for (int p = 0; p < T::X_PASSES; ++p) {
+            const int it = p * T::NT + tid;
+            const int col = it / T::VPC, v = it % T::VPC;
+            const int64_t k = k0 + v * (16 / T::ESZ);
+#pragma unroll
+            for (int pl = 0; pl < T::XPL; ++pl) {
+                u32x4 x = u32x4{0u, 0u, 0u, 0u};
+                if (col < T::NC && k < kend) {
+                    if constexpr (T::BF) {
+                        x = *reinterpret_cast<const u32x4*>(g.xb + pl * g.xb_plane + static_cast<int64_t>(col) * g.ldxb + k);
+                    } else {
+                        if (col < g.ncols) x = *reinterpret_cast<const u32x4*>(g.xk + static_cast<int64_t>(col) * g.ldxk + k);
+                    }
+                }
+#pragma unroll
+                for (int d = 0; d < 4; ++d) rx[p][pl][d] = x[d];
+            }
+        }
+    };
+    auto store_x = [&](int buf) {
+#pragma unroll
+        for (int p = 0; p < T::X_PASSES; ++p) {
+            const int it = p * T::NT + tid;
+            const int col = it / T::VPC, v = it % T::VPC;
+            if (col >= T::NC) continue;
+#pragma unroll
+            for (int pl = 0; pl < T::XPL; ++pl) {
+                XE* dst = xs + buf * T::STAGE + pl * T::PLANE + col * SX + v * (16 / T::ESZ);
+                *reinterpret_cast<u32x4*>(dst) = u32x4{rx[p][pl][0], rx[p][pl][1], rx[p][pl][2], rx[p][pl][3]};
+            }
+        }
+    };
+
+    v4f acc[RB][NCB];
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+#pragma unroll
+        for (int j = 0; j < NCB; ++j) acc[i][j] = v4f{0, 0, 0, 0};
+
+    // ---- one chunk of matrix-core work from raw A words w and X stage buf.
+    // The column blocks are software-pipelined by hand (the X fragment of
+    // block j + 1 is read while block j's MFMAs issue) and fenced with
+    // scheduling barriers, so that the scheduler does not hoist every LDS read
+    // of the chunk and run out of registers.
+    // (past the end of the reduction A reads as zero and stays zero)
+    auto mu_nn = [&](int64_t k0, int kk, float v, bool full) -> float {     // NN: A(r, k) - mu(k) in f64
+        const int64_t k = k0 + LK * lg + kk;
+        return (full || k < kend) ? static_cast<float>(static_cast<double>(v) - g.mu[k]) : v;
+    };
+    auto mu_tn = [&](int64_t k0, int kk, int e, float v, bool full) -> float {   // TN: A(k, c) - mu(c)
+        return (full || k0 + LK * lg + kk < kend) ? static_cast<float>(static_cast<double>(v) - mu_c[e]) : v;
+    };
+    auto compute = [&](const uint32_t (&w)[AW], int64_t k0, int buf, bool full) {
+        const XE* xb = xs + buf * T::STAGE;
+        if constexpr (!T::BF) {
+            // f32: operand of row block i, substep t
+            float a[RB][SUB];
+#pragma unroll
+            for (int i = 0; i < RB; ++i)
+#pragma unroll
+                for (int t = 0; t < SUB; ++t) {
+                    if constexpr (MODE == MODE_NN) {
+                        const float x = word_elem<TA>(w + i * (LK * sizeof(TA) / 4), t);
+                        a[i][t] = MU ? mu_nn(k0, t, x, full) : x;
+                    } else {
+                        const float x = word_elem<TA>(w + t * sizeof(TA), i);
+                        a[i][t] = MU ? mu_tn(k0, t, i, x, full) : x;
+                    }
+                }
+            constexpr int BV = LK / 4;
+            auto read_b = [&](int j, v4f (&b)[BV]) {
+                const float* src = xb + (16 * (cb0 + j) + lr) * SX + LK * lg;
+#pragma unroll
+                for (int v = 0; v < BV; ++v) b[v] = *reinterpret_cast<const v4f*>(src + 4 * v);
+            };
+            v4f bc[BV], bn[BV];
+            read_b(0, bn);
+#pragma unroll
+            for (int j = 0; j < NCB; ++j) {
+#pragma unroll
+                for (int v = 0; v < BV; ++v) bc[v] = bn[v];
+                if (j + 1 < NCB) read_b(j + 1, bn);
+#pragma unroll
+                for (int t = 0; t < SUB; ++t)
+#pragma unroll
+                    for (int i = 0; i < RB; ++i)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][t], bc[t >> 2][t & 3], acc[i][j], 0, 0, 0);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        } else {
+            // bf16: k-octet operands (hi, and lo for A_LO) of row block i, substep s
+            s8bf ah[RB][SUB], al[T::A_LO ? RB : 1][T::A_LO ? SUB : 1];
+            constexpr bool RAWNN = (MODE == MODE_NN) && sizeof(TA) == 2 && !CENT;
+            constexpr bool RAWTN = (MODE == MODE_TN) && sizeof(TA) == 2 && !MU;
+            if constexpr (RAWNN) {
+                // bf16-stored A: the words are the operands (minus the means, if any,
+                // rounded once to bf16)
+#pragma unroll
+                for (int i = 0; i < RB; ++i)
+#pragma unroll
+                    for (int s = 0; s < SUB; ++s) {
+                        u32x4 q;
+#pragma unroll
+                        for (int d = 0; d < 4; ++d) {
+                            q[d] = w[i * (LK / 2) + 4 * s + d];
+                            if constexpr (MU)
+                                q[d] = pack_bf16(mu_nn(k0, 8 * s + 2 * d, __uint_as_float(q[d] << 16), full),
+                                                 mu_nn(k0, 8 * s + 2 * d + 1, __uint_as_float(q[d] & 0xFFFF0000u), full));
+                        }
+                        ah[i][s] = __builtin_bit_cast(s8bf, q);
+                    }
+            } else if constexpr (RAWTN) {
+                // bf16-stored A, TN: transpose the lane's 16 x 4 block of 16-bit
+                // words into k-octets (row pairs of one column per word)
+#pragma unroll
+                for (int i = 0; i < RB; ++i)
+#pragma unroll
+                    for (int s = 0; s < SUB; ++s) {
+                        u32x4 q;
+#pragma unroll
+                        for (int d = 0; d < 4; ++d) {
+                            const uint32_t lo = w[(8 * s + 2 * d) * 2 + (i >> 1)];
+                            const uint32_t hi = w[(8 * s + 2 * d + 1) * 2 + (i >> 1)];
+                            q[d] = (i & 1) ? ((lo >> 16) | (hi & 0xFFFF0000u)) : ((lo & 0xFFFFu) | (hi << 16));
+                        }
+                        ah[i][s] = __builtin_bit_cast(s8bf, q);
+                    }
+            } else {
+                // values x(i, s, u) (row block i, substep s, element u of the octet)
+                // in f32, then rounded to bf16 hi (+ lo)
+#pragma unroll
+                for (int i = 0; i < RB; ++i)
+#pragma unroll
+                    for (int s = 0; s < SUB; ++s) {
+                        u32x4 qh, ql;
+#pragma unroll
+                        for (int d = 0; d < 4; ++d) {
+                            float x[2];
+#pragma unroll
+                            for (int h = 0; h < 2; ++h) {
+                                const int kk = 8 * s + 2 * d + h;      // position in the lane's run
+                                if constexpr (MODE == MODE_NN) {
+                                    const float v = word_elem<TA>(w + i * (LK * sizeof(TA) / 4), kk);
+                                    x[h] = MU ? mu_nn(k0, kk, v, full) : v;
+                                } else {
+                                    const float v = word_elem<TA>(w + kk * sizeof(TA), i);
+                                    x[h] = MU ? mu_tn(k0, kk, i, v, full) : v;
+                                }
+                            }
+                            qh[d] = pack_bf16(x[0], x[1]);
+                            if constexpr (T::A_LO)
+                                ql[d] = pack_bf16(x[0] - bf16_round(x[0]), x[1] - bf16_round(x[1]));
+                        }
+                        ah[i][s] = __builtin_bit_cast(s8bf, qh);
+                        if constexpr (T::A_LO) al[i][s] = __builtin_bit_cast(s8bf, ql);
+                    }
+            }
+            auto read_b = [&](int j, s8bf (&bh)[SUB], s8bf (&bl)[SUB]) {
+                const uint16_t* src = xb + (16 * (cb0 + j) + lr) * SX + LK * lg;
+#pragma unroll
+                for (int s = 0; s < SUB; ++s) {
+                    bh[s] = *reinterpret_cast<const s8bf*>(src + 8 * s);
+                    if constexpr (T::SPLIT) bl[s] = *reinterpret_cast<const s8bf*>(src + T::PLANE + 8 * s);
+                }
+            };
+            s8bf bhc[SUB], blc[SUB], bhn[SUB], bln[SUB];
+            read_b(0, bhn, bln);
+#pragma unroll
+            for (int j = 0; j < NCB; ++j) {
+#pragma unroll
+                for (int s = 0; s < SUB; ++s) { bhc[s] = bhn[s]; if constexpr (T::SPLIT) blc[s] = bln[s]; }
+                if (j + 1 < NCB) read_b(j + 1, bhn, bln);
+#pragma unroll
+                for (int s = 0; s < SUB; ++s)
+#pragma unroll
+                    for (int i = 0; i < RB; ++i) {
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i][s], bhc[s], acc[i][j], 0, 0, 0);
+                        if constexpr (T::SPLIT)
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i][s], blc[s], acc[i][j], 0, 0, 0);
+                        if constexpr (T::A_LO)
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i][s], bhc[s], acc[i][j], 0, 0, 0);
+                    }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    };
+
+    if (kbeg < kend) {
+        // full chunks in the loop; a ragged last chunk is loaded with masks
+        const int64_t nfull = (kend - kbeg) / KC;
+        const bool tail = (kend - kbeg) % KC != 0;
+        uint32_t wa[AW], wb[AW];
+        load_a(kbeg, wa, nfull > 0);
+        load_x(kbeg);
+        store_x(0);
+        __syncthreads();
+        int buf = 0;
+        for (int64_t c = 0; c < nfull; ++c) {
+            const int64_t k0 = kbeg + c * KC;
+            const bool more = c + 1 < nfull || tail;
+            if (more) { load_a(k0 + KC, wb, c + 1 < nfull); load_x(k0 + KC); }
+            compute(wa, k0, buf, true);
+            if (more) store_x(buf ^ 1);
+            __syncthreads();
+#pragma unroll
+            for (int d = 0; d < AW; ++d) wa[d] = wb[d];
+            buf ^= 1;
+        }
+        if (tail) compute(wa, kbeg + nfull * KC, buf, false);
+    }
+
+    // ---- epilogue
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+#pragma unroll
+        for (int j = 0; j < NCB; ++j) {
+            const int c = 16 * (cb0 + j) + lr;
+            if (c >= g.ncols) continue;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t r = (MODE == MODE_NN) ? w0 + 16 * i + 4 * lg + v : w0 + 16 * lg + 4 * v + i;
+                if (r < g.rows) out[(r - row0) * g.ldo + c] = acc[i][j][v];
+            }
+        }
+}
+
+// Launch body: workgroup b -> (tile b % T, split b / T), split-major, so
+// that the consecutive workgroups an XCD receives (one contiguous range each)
+// work on the same chunks of X in step and share them in its L2.  (Dealing
+// equal shares of the (tile, chunk) units to one workgroup per CU instead
+// fills the last round but scatters the workgroups of an XCD over X: measured
+// 10-45 % slower at C2's and C3's shapes.)
+template <typename TA, int MODE, int ARITH, int NCB, int CS = 1, bool CENT = false, bool MU = false>
+struct StreamBody {
+    typedef StreamTile<TA, MODE, ARITH, NCB, CS, CENT, MU> T;
+    typedef GemmArgs<TA, float, float> Args;
+    static constexpr int THREADS = T::NT;
+    __host__ __device__ static int tiles(const Args& g) { return static_cast<int>(cdiv(g.rows, T::TROWS)); }
+    static int blocks(const Args& g) { return tiles(g) * g.splits; }
+    static size_t lds(const Args&) { return T::LDS_BYTES; }
+    static __device__ __forceinline__ void run(const Args& g, int b) {
+        const int nt = tiles(g);
+        const int tile = b % nt, split = b / nt;
+        const int64_t kbeg = static_cast<int64_t>(split) * g.kchunk;
+        gemm_stream_body<TA, MODE, ARITH, NCB, CS, CENT, MU>(g, tile, kbeg, min(g.K, kbeg + g.kchunk),
+                                                             g.out + static_cast<int64_t>(split) * g.part_stride, 0);
+    }
+};
+
+}  // namespace rsvd

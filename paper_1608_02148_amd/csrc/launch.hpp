@@ -2,12 +2,15 @@
 // the solve, issued through an executor (SingleExec or BatchRecorder).
 #pragma once
 
+#include <cstdlib>
+#include <cstring>
 #include <type_traits>
 
 #include "common.hpp"
 #include "exec.hpp"
 #include "gemm.hpp"
 #include "gemm_bf16.hpp"
+#include "gemm_stream.hpp"
 #include "linalg.hpp"
 #include "plan.hpp"
 
@@ -243,6 +246,113 @@ hipError_t gemm_bf16(Ex& ex, bool split, int cls, const TA* A, int64_t lda, int6
     return gemm_bf16_cls<TA, MODE, false, false>(ex, tc, g);
 }
 
+// Streamed-A products (gemm_stream.hpp) for the large products of a single
+// solve.  RSVD_PRODUCTS=staged in the environment keeps every product on the
+// LDS-staged tiles (for comparisons).
+inline bool streamed_products_enabled() {
+    static const bool on = [] {
+        const char* s = std::getenv("RSVD_PRODUCTS");
+        return !(s && std::strcmp(s, "staged") == 0);
+    }();
+    return on;
+}
+
+// Column classes of the streamed-A kernel: 128 (65..128 columns) and 224
+// (129..224).  Narrower products stay on the LDS-staged tiles (too little
+// matrix-core work per loaded byte of A to hide the memory latency at one
+// wave per SIMD), and so do the variants whose registers do not fit one wave
+// (accumulators, two chunks of A and the staged X over 512 registers: they
+// would spill).
+inline int stream_cols(int ncols) { return ncols <= 128 ? 128 : 224; }
+
+// Variants that fit one wave per SIMD without spilling (a compile-time
+// record of the register counts; the 2-group variants, CS = 2 with two waves
+// per SIMD at half the columns each, measured no faster at C2's shapes and
+// spill at 224 columns, so they are not launched).
+template <typename TA, int MODE, int ARITH, int NCB, int CS, bool CENT, bool MU>
+constexpr bool stream_fits() {
+    if (CS != 1) return false;
+    if (NCB == 8) return !(MODE == MODE_TN && ARITH == 2 && sizeof(TA) == 4 && MU);
+    return !MU && !CENT && (ARITH == 0 || sizeof(TA) == 2);
+}
+
+template <typename TA, int MODE, int ARITH, bool CENT, bool MU, class Ex>
+hipError_t stream_ncb(Ex& ex, const GemmArgs<TA, float, float>& g) {
+    if (g.ncols <= 128) {
+        if constexpr (stream_fits<TA, MODE, ARITH, 8, 1, CENT, MU>())
+            return ex.template run<StreamBody<TA, MODE, ARITH, 8, 1, CENT, MU>>(g);
+    } else {
+        if constexpr (stream_fits<TA, MODE, ARITH, 14, 1, CENT, MU>())
+            return ex.template run<StreamBody<TA, MODE, ARITH, 14, 1, CENT, MU>>(g);
+    }
+    return hipErrorNotSupported;
+}
+
+// Whether stream_ncb would launch (checked before X is packed).
+template <typename TA, int MODE>
+bool stream_variant(int arith, int ncols, bool mu) {
+    const bool wide = ncols > 128;
+    auto fits = [&](bool ncb8, bool ncb14) { return wide ? ncb14 : ncb8; };
+    if (arith == 0)
+        return mu ? fits(stream_fits<TA, MODE, 0, 8, 1, false, true>(), stream_fits<TA, MODE, 0, 14, 1, false, true>())
+                  : fits(stream_fits<TA, MODE, 0, 8, 1, false, false>(), stream_fits<TA, MODE, 0, 14, 1, false, false>());
+    if (arith == 1)
+        return mu ? fits(stream_fits<TA, MODE, 1, 8, 1, false, true>(), stream_fits<TA, MODE, 1, 14, 1, false, true>())
+                  : fits(stream_fits<TA, MODE, 1, 8, 1, false, false>(), stream_fits<TA, MODE, 1, 14, 1, false, false>());
+    constexpr bool cent = sizeof(TA) == 2;
+    return mu ? fits(stream_fits<TA, MODE, 2, 8, 1, cent, true>(), stream_fits<TA, MODE, 2, 14, 1, cent, true>())
+              : fits(stream_fits<TA, MODE, 2, 8, 1, false, false>(), stream_fits<TA, MODE, 2, 14, 1, false, false>());
+}
+
+// Returns hipErrorNotSupported (nothing launched) when the product does not
+// qualify: a batch, a small or misaligned A, or no packing scratch for X.
+template <typename TA, int MODE, class Ex>
+hipError_t gemm_streamed(Ex& ex, int arith, const TA* A, int64_t lda, int64_t rows, int64_t K, const float* X,
+                         int64_t ldx, int ncols, float* out, int64_t ldo, int S, int64_t part_stride,
+                         const double* mu, const uint32_t* skip_flag, uint32_t skip_mask, Gate gate, XPack xp,
+                         float* xk, int64_t ldxk) {
+    if constexpr (!Ex::kSingle) {
+        return hipErrorNotSupported;       // batches: many small products
+    } else {
+        if (!streamed_products_enabled() || !streamed_size(rows, K) || ncols <= 64 || ncols > 224)
+            return hipErrorNotSupported;
+        if (!stream_variant<TA, MODE>(arith, ncols, mu != nullptr)) return hipErrorNotSupported;
+        // 16-byte aligned rows of A; TN reads A in groups of 4 columns (rows % 4 == 0)
+        if (reinterpret_cast<uintptr_t>(A) % 16 != 0 || (lda * static_cast<int64_t>(sizeof(TA))) % 16 != 0)
+            return hipErrorNotSupported;
+        if (MODE == MODE_TN && rows % 4 != 0) return hipErrorNotSupported;
+        const int nc = stream_cols(ncols);
+        if (arith == 0) {
+            if (!xk || ldxk < rup(K, 4) || ldxk % 4 != 0 || reinterpret_cast<uintptr_t>(xk) % 16 != 0)
+                return hipErrorNotSupported;
+        } else if (!xp.p || xp.ld < rup(K, 8) || xp.ld % 8 != 0 || xp.plane < static_cast<int64_t>(nc) * xp.ld) {
+            return hipErrorNotSupported;
+        }
+        auto g = gemm_args<TA, float, float>(A, lda, rows, K, X, ldx, ncols, out, ldo, S, part_stride, mu, skip_flag,
+                                             skip_mask, 64, 16, gate);
+        hipError_t e;
+        if (arith == 0) {
+            e = ex.template run<XKPackBody<float>>(typename XKPackBody<float>::Args{
+                X, ldx, K, ncols, xk, ldxk, skip_flag, skip_mask, gate});
+            g.xk = xk;
+            g.ldxk = ldxk;
+        } else {
+            e = ex.template run<XPackBody>(XPackArgs{X, ldx, K, ncols, nc, xp.p, xp.ld, xp.plane, arith == 2 ? 1 : 0,
+                                                     skip_flag, skip_mask, gate});
+            g.xb = xp.p; g.ldxb = xp.ld; g.xb_plane = xp.plane;
+        }
+        if (e != hipSuccess) return e;
+        if (mu) {
+            if (arith == 0) return stream_ncb<TA, MODE, 0, false, true>(ex, g);
+            if (arith == 1) return stream_ncb<TA, MODE, 1, false, true>(ex, g);
+            return stream_ncb<TA, MODE, 2, sizeof(TA) == 2, true>(ex, g);
+        }
+        if (arith == 0) return stream_ncb<TA, MODE, 0, false, false>(ex, g);
+        if (arith == 1) return stream_ncb<TA, MODE, 1, false, false>(ex, g);
+        return stream_ncb<TA, MODE, 2, false, false>(ex, g);
+    }
+}
+
 // One product with A in the requested arithmetic: 0 = storage precision
 // (f32 / f64 matrix cores), 1 = bf16, 2 = split bf16 (near-f32-accurate).
 // xk / ldxk (optional): scratch for the k-contiguous copy of X that the
@@ -253,6 +363,9 @@ hipError_t gemm_step(Ex& ex, int arith, int cls, const TA* A, int64_t lda, int64
                      const double* mu, const uint32_t* skip_flag, uint32_t skip_mask, Gate gate = {},
                      XPack xp = {}, TC* xk = nullptr, int64_t ldxk = 0) {
     if constexpr (std::is_same<TC, float>::value) {
+        const hipError_t e = gemm_streamed<TA, MODE>(ex, arith, A, lda, rows, K, X, ldx, ncols, out, ldo, S,
+                                                     part_stride, mu, skip_flag, skip_mask, gate, xp, xk, ldxk);
+        if (e != hipErrorNotSupported) return e;
         if (arith != 0)
             return gemm_bf16<TA, MODE>(ex, arith == 2, cls, A, lda, rows, K, X, ldx, ncols, out, ldo, S,
                                        part_stride, mu, skip_flag, skip_mask, gate, xp);

@@ -70,11 +70,49 @@ inline int nn_split(int64_t m, int64_t n, int num_cu) {
     return best;
 }
 
-inline Splits make_splits(int64_t m, int64_t n, int num_cu) {
+// Products large enough for the streamed-A kernel (rows x K elements of A).
+inline bool streamed_size(int64_t rows, int64_t K) {
+    return rows >= 256 && K >= 256 && rows * K >= (int64_t(1) << 24);
+}
+
+// Split of the reduction for the streamed-A products (256 output rows per
+// workgroup, one workgroup per CU): the count that minimises the estimated
+// time, rounds of workgroups (a partly filled last round costs a whole one)
+// plus one more write and read of each partial block (S x rows x Lp f32),
+// relative to one read of A (rows x K f32); at most `max_s` splits of at least
+// 1024 reduction elements, and at most 8 rounds.
+inline int stream_split(int64_t rows, int64_t K, int Lp, int num_cu, int max_s) {
+    const int64_t tiles = cdiv(rows, 256);
+    int best = 1;
+    double best_t = 1e300;
+    for (int S = 1; S <= max_s && (S == 1 || K / S >= 1024); ++S) {
+        const int64_t wg = tiles * S, rounds = cdiv(wg, num_cu);
+        if (S > 1 && rounds > 8) break;
+        const double fill = static_cast<double>(wg) / static_cast<double>(rounds * num_cu);
+        const double t = 1.0 / fill + (S > 1 ? 2.0 * S * Lp / static_cast<double>(K) : 0.0);
+        if (t < best_t - 1e-9) { best_t = t; best = S; }
+    }
+    return best;
+}
+
+// Whether a single solve's products of sketch width l run the streamed-A
+// kernel (A X always; A^T Q also needs n % 4 == 0; A's rows must also be
+// 16-byte aligned, which only the run checks).
+inline bool stream_product(int dtype, int64_t m, int64_t n, int l, bool tn) {
+    return dtype != RSVD_F64 && streamed_size(m, n) && l > 64 && l <= 224 && (!tn || n % 4 == 0);
+}
+
+// streamed: f32 / bf16 storage, where the large products of sketch width l
+// take the streamed-A kernel (Lp: the padded width).
+inline Splits make_splits(int64_t m, int64_t n, int num_cu, bool streamed = false, int l = 0, int Lp = 128) {
     Splits s;
     s.nn = nn_split(m, n, num_cu);
     const int64_t tn_tiles = cdiv(n, 128);
     s.tn = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>((2 * num_cu) / tn_tiles, cdiv(m, 256))));
+    if (streamed) {
+        if (stream_product(RSVD_F32, m, n, l, false)) s.nn = stream_split(m, n, Lp, num_cu, kMaxNNSplit);
+        if (stream_product(RSVD_F32, m, n, l, true)) s.tn = stream_split(n, m, Lp, num_cu, 64);
+    }
     s.gram_m = gram_split(m, num_cu);
     s.gram_n = gram_split(n, num_cu);
     const int64_t cs_cols = cdiv(n, 256);
@@ -159,7 +197,7 @@ inline Plan make_plan(int dtype, int64_t m, int64_t n, int k, const rsvd_params*
     }
     P.qmax = P.q;
     P.gated = batch;
-    P.sp = batch ? Splits{1, 1, 1, 1, 1} : make_splits(m, n, num_cu);
+    P.sp = batch ? Splits{1, 1, 1, 1, 1} : make_splits(m, n, num_cu, dtype != RSVD_F64, P.l, P.Lp);
     const size_t cs = comp_size(dtype);
     Layout L;
     P.status = L.take(kAlign);
@@ -263,7 +301,7 @@ inline int hip_status(rsvd_handle_t h, hipError_t e) {
 inline Plan block_plan(int32_t dtype, int64_t m, int64_t n, int32_t c, int num_cu) {
     Plan P;
     P.dtype = dtype; P.m = m; P.n = n; P.l = c; P.Lp = tile_cols(c);
-    P.sp = make_splits(m, n, num_cu);
+    P.sp = make_splits(m, n, num_cu, dtype != RSVD_F64, c, P.Lp);
     const size_t cs = comp_size(dtype);
     Layout L;
     P.status = L.take(kAlign);
@@ -277,6 +315,8 @@ inline Plan block_plan(int32_t dtype, int64_t m, int64_t n, int32_t c, int num_c
     P.ldxp = rup(std::max(m, n), 8);
     P.xplane = static_cast<int64_t>(P.Lp) * P.ldxp;
     P.xpack = L.take(2 * static_cast<size_t>(P.xplane) * sizeof(uint16_t));
+    P.ldxk = rup(std::max(m, n), 8);
+    P.xk = L.take(static_cast<size_t>(P.Lp) * P.ldxk * cs);
     if (c <= RSVD_MAX_L) {
         const size_t leaves = static_cast<size_t>(cdiv(std::max(m, n), 256));
         P.lucand = L.take(2 * leaves * c * sizeof(int32_t));
