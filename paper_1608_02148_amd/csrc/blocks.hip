@@ -70,16 +70,18 @@ static hipError_t gemm_nn_typed(hipStream_t st, int arith, const Plan& P, int S,
     const XPack xp = xpack_of(P, arith != 0 ? work : nullptr);
     // k-contiguous copy of X for the storage-precision streamed products
     TC* xk = work ? at<TC>(work, P.xk) : nullptr;
+    const StreamTail tail = (work && P.tailslot) ? StreamTail{at<float>(work, P.tailslot),
+                                                              tail_slot_bytes(P.ncu, P.Lp), P.ncu} : StreamTail{};
     if (S == 1)
         return gemm_step<TA, TC, MODE_NN>(ex, arith, 0, static_cast<const TA*>(A), lda, m, K,
                                           static_cast<const TC*>(X), ldx, c, static_cast<TC*>(Y), ldy, 1, 0,
-                                          nullptr, nullptr, 0, Gate{}, xp, xk, P.ldxk);
+                                          nullptr, nullptr, 0, Gate{}, xp, xk, P.ldxk, tail);
     // split n-reduction: S partial blocks (m x Lp each) summed in split order
     TC* part = at<TC>(work, P.part);
     const int64_t stride = m * P.Lp;
     RSVD_TRY((gemm_step<TA, TC, MODE_NN>(ex, arith, 0, static_cast<const TA*>(A), lda, m, K,
                                         static_cast<const TC*>(X), ldx, c, part, P.Lp, S, stride, nullptr, nullptr,
-                                        0, Gate{}, xp, xk, P.ldxk)));
+                                        0, Gate{}, xp, xk, P.ldxk, tail)));
     return reduce_step<TC>(ex, part, S, stride, P.Lp, m, c, static_cast<TC*>(Y), ldy);
 }
 
@@ -117,14 +119,16 @@ static hipError_t gemm_tn_typed(rsvd_handle_t h, int arith, const Plan& P, int64
     TC* part = at<TC>(work, P.part);
     const XPack xp = xpack_of(P, work);
     TC* xk = at<TC>(work, P.xk);
+    const StreamTail tail = P.tailslot ? StreamTail{at<float>(work, P.tailslot), tail_slot_bytes(P.ncu, P.Lp), P.ncu}
+                                       : StreamTail{};
     if (S == 1)
         return gemm_step<TA, TC, MODE_TN>(ex, arith, 0, static_cast<const TA*>(A), lda, n, m,
                                           static_cast<const TC*>(Q), ldq, c, static_cast<TC*>(Z), ldz, 1, 0, nullptr,
-                                          nullptr, 0, Gate{}, xp, xk, P.ldxk);
+                                          nullptr, 0, Gate{}, xp, xk, P.ldxk, tail);
     RSVD_TRY((gemm_step<TA, TC, MODE_TN>(ex, arith, 0, static_cast<const TA*>(A), lda, n, m,
                                         static_cast<const TC*>(Q), ldq, c, part, P.Lp, S,
                                         static_cast<int64_t>(n) * P.Lp, nullptr, nullptr, 0, Gate{}, xp, xk,
-                                        P.ldxk)));
+                                        P.ldxk, tail)));
     return reduce_step<TC>(ex, part, S, static_cast<int64_t>(n) * P.Lp, P.Lp, n, c, static_cast<TC*>(Z), ldz);
 }
 

@@ -46,6 +46,12 @@ struct GemmArgs {
     int64_t K;           // reduction length (NN: n, TN: m)
     int64_t kchunk;      // reduction elements per split (multiple of BK)
     int32_t splits;      // number of splits S (grid extent along the reduction)
+    // streamed products: the (tile, split) pairs past the last whole round of
+    // tail_groups workgroups are dealt to tail_groups more workgroups in equal
+    // shares of chunks, which write slots of TROWS x ld_slot (see StreamBody)
+    int32_t tail_groups;
+    float* tail_slots;
+    int64_t ld_slot;
     const TX* X;         // K x (col tiles * NC) operand
     int64_t ldx;
     int32_t ncols;       // valid output columns (all column tiles together)

@@ -41,6 +41,7 @@
 #pragma once
 
 #include "common.hpp"
+#include "exec.hpp"
 #include "gemm.hpp"
 
 namespace rsvd {
@@ -100,7 +101,7 @@ __device__ __forceinline__ float bf16_round(float x) {
 // out + (r - row0) ldo).
 template <typename TA, int MODE, int ARITH, int NCB, int CS, bool CENT, bool MU>
 __device__ __forceinline__ void gemm_stream_body(const GemmArgs<TA, float, float>& g, int tile, int64_t kbeg,
-                                                 int64_t kend, float* out, int64_t row0) {
+                                                 int64_t kend, float* out, int64_t row0, int64_t ldo) {
     typedef StreamTile<TA, MODE, ARITH, NCB, CS, CENT, MU> T;
     constexpr int LK = T::LK, KC = T::KC, SUB = T::SUB, RB = T::RB, SX = T::SX;
     constexpr int AW = T::A_WORDS;
@@ -418,31 +419,124 @@ __device__ __forceinline__ void gemm_stream_body(const GemmArgs<TA, float, float
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int64_t r = (MODE == MODE_NN) ? w0 + 16 * i + 4 * lg + v : w0 + 16 * lg + 4 * v + i;
-                if (r < g.rows) out[(r - row0) * g.ldo + c] = acc[i][j][v];
+                if (r < g.rows) out[(r - row0) * ldo + c] = acc[i][j][v];
             }
         }
 }
 
-// Launch body: workgroup b -> (tile b % T, split b / T), split-major, so
-// that the consecutive workgroups an XCD receives (one contiguous range each)
-// work on the same chunks of X in step and share them in its L2.  (Dealing
-// equal shares of the (tile, chunk) units to one workgroup per CU instead
-// fills the last round but scatters the workgroups of an XCD over X: measured
-// 10-45 % slower at C2's and C3's shapes.)
+// Launch body.  Workgroup b < F -> (tile b % T, split b / T), split-major,
+// so that the consecutive workgroups an XCD receives (one contiguous range
+// each) work on the same chunks of X in step and share them in its L2.  F is
+// all T S pairs, or with tail dealing (g.tail_groups = G > 0) the pairs of
+// whole rounds of G workgroups; the L = T S - F pairs left over (a partly
+// filled last round) are cut into pieces, pair p into f_p = floor(G / L) or
+// one more (the first G mod L pairs) pieces of about equal chunk counts, and
+// the G pieces go to G more workgroups, so that the last round ends on every
+// CU at about the same time.  Tail workgroup w writes its piece to slot w
+// (TROWS rows of ld_slot) and TailFixBody sums the f_p slots of each pair in
+// order into the pair's output block (deterministic).  (Dealing all of the
+// work in equal shares instead scatters an XCD's workgroups over X, whose
+// chunks then miss in L2: 10-45 % slower at C2's and C3's shapes.)
+__host__ __device__ inline void tail_piece(int64_t w, int64_t leftover, int groups, int64_t& pair, int64_t& piece,
+                                           int64_t& pieces) {
+    const int64_t q = groups / leftover, r = groups % leftover;
+    if (w < r * (q + 1)) { pair = w / (q + 1); piece = w % (q + 1); pieces = q + 1; }
+    else { pair = r + (w - r * (q + 1)) / q; piece = (w - r * (q + 1)) % q; pieces = q; }
+}
+__host__ __device__ inline int64_t tail_first(int64_t pair, int64_t leftover, int groups) {
+    const int64_t q = groups / leftover, r = groups % leftover;
+    return pair < r ? pair * (q + 1) : r * (q + 1) + (pair - r) * q;
+}
+
 template <typename TA, int MODE, int ARITH, int NCB, int CS = 1, bool CENT = false, bool MU = false>
 struct StreamBody {
     typedef StreamTile<TA, MODE, ARITH, NCB, CS, CENT, MU> T;
     typedef GemmArgs<TA, float, float> Args;
     static constexpr int THREADS = T::NT;
+    static constexpr int TROWS = T::TROWS, KC = T::KC;
     __host__ __device__ static int tiles(const Args& g) { return static_cast<int>(cdiv(g.rows, T::TROWS)); }
-    static int blocks(const Args& g) { return tiles(g) * g.splits; }
+    __host__ __device__ static int64_t pairs(const Args& g) { return static_cast<int64_t>(tiles(g)) * g.splits; }
+    __host__ __device__ static int64_t whole(const Args& g) {
+        return g.tail_groups > 0 ? (pairs(g) / g.tail_groups) * g.tail_groups : pairs(g);
+    }
+    static int blocks(const Args& g) {
+        return static_cast<int>(whole(g) + (pairs(g) > whole(g) ? g.tail_groups : 0));
+    }
     static size_t lds(const Args&) { return T::LDS_BYTES; }
     static __device__ __forceinline__ void run(const Args& g, int b) {
         const int nt = tiles(g);
-        const int tile = b % nt, split = b / nt;
-        const int64_t kbeg = static_cast<int64_t>(split) * g.kchunk;
-        gemm_stream_body<TA, MODE, ARITH, NCB, CS, CENT, MU>(g, tile, kbeg, min(g.K, kbeg + g.kchunk),
-                                                             g.out + static_cast<int64_t>(split) * g.part_stride, 0);
+        const int64_t F = whole(g);
+        if (g.tail_groups > 0) {
+            // the launch order decides the rounds: hardware block h < F runs
+            // in the whole rounds (h % 8 is its XCD, which keeps one contiguous
+            // range of pairs), h >= F in the last one (the logical order of
+            // xcd_block would give some XCDs only whole pairs and the others
+            // only tail pieces)
+            const int64_t h = blockIdx.x;
+            b = static_cast<int>((h < F && F % kXcds == 0) ? (h % kXcds) * (F / kXcds) + h / kXcds : h);
+        }
+        int64_t pair = b, kbeg, kend, row0 = 0, ldo = g.ldo;
+        float* out;
+        if (b < F) {
+            kbeg = (pair / nt) * g.kchunk;
+            kend = min(g.K, kbeg + g.kchunk);
+            out = g.out + (pair / nt) * g.part_stride;
+        } else {
+            int64_t pl, piece, pieces;
+            tail_piece(b - F, pairs(g) - F, g.tail_groups, pl, piece, pieces);
+            pair = F + pl;
+            const int64_t nch = cdiv(g.kchunk, T::KC);
+            const int64_t ks = (pair / nt) * g.kchunk, ke = min(g.K, ks + g.kchunk);
+            kbeg = min(ke, ks + (piece * nch / pieces) * T::KC);
+            kend = min(ke, ks + ((piece + 1) * nch / pieces) * T::KC);
+            out = g.tail_slots + (b - F) * T::TROWS * g.ld_slot;
+            row0 = (pair % nt) * T::TROWS;
+            ldo = g.ld_slot;
+        }
+        gemm_stream_body<TA, MODE, ARITH, NCB, CS, CENT, MU>(g, static_cast<int>(pair % nt), kbeg, kend, out, row0,
+                                                             ldo);
+    }
+};
+
+// Sum of the tail slots: for each leftover pair p (tile t, split s) and each
+// of its rows and columns, the slots of its pieces in order, into the pair's
+// output block (out + s part_stride).
+struct TailFixArgs {
+    const float* slots; int64_t ld_slot; int64_t rows; int ncols; int tiles; int trows; int64_t first_pair;
+    int64_t leftover; int groups; float* out; int64_t ldo; int64_t part_stride;
+    const uint32_t* skip_flag; uint32_t skip_mask; Gate gate;
+};
+struct TailFixBody {
+    typedef TailFixArgs Args;
+    static constexpr int THREADS = 256;
+    static int blocks(const Args& a) {
+        return static_cast<int>(cdiv(a.leftover * a.trows * cdiv(a.ncols, 4), THREADS));
+    }
+    static size_t lds(const Args&) { return 0; }
+    static __device__ void run(const Args& a, int b) {
+        if (a.skip_flag && ((*a.skip_flag & a.skip_mask) == 0u)) return;
+        if (a.gate.w && ((*a.gate.w & a.gate.mask) == 0u)) return;
+        const int cg = static_cast<int>(cdiv(a.ncols, 4));
+        const int64_t idx = static_cast<int64_t>(b) * THREADS + threadIdx.x;
+        if (idx >= a.leftover * a.trows * cg) return;
+        const int64_t pl = idx / (static_cast<int64_t>(a.trows) * cg);
+        const int rr = static_cast<int>((idx / cg) % a.trows);
+        const int c = 4 * static_cast<int>(idx % cg);
+        const int64_t pair = a.first_pair + pl, t = pair % a.tiles, s = pair / a.tiles;
+        const int64_t r = t * a.trows + rr;
+        if (r >= a.rows) return;
+        const int64_t w0 = tail_first(pl, a.leftover, a.groups), w1 = tail_first(pl + 1, a.leftover, a.groups);
+        float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        for (int64_t w = w0; w < w1; ++w) {
+            const float* p = a.slots + (w * a.trows + rr) * a.ld_slot + c;
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (c + e < a.ncols) acc[e] += p[e];
+        }
+        float* o = a.out + s * a.part_stride + r * a.ldo + c;
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if (c + e < a.ncols) o[e] = acc[e];
     }
 };
 

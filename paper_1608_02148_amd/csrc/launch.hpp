@@ -73,6 +73,7 @@ GemmArgs<TA, TX, TC> gemm_args(const TA* A, int64_t lda, int64_t rows, int64_t K
     S = S < 1 ? 1 : S;
     g.kchunk = rup(cdiv(K, S), kchunk_multiple);   // splits past the end of K write zero partials
     g.splits = S;
+    g.tail_groups = 0; g.tail_slots = nullptr; g.ld_slot = 0;
     g.X = X; g.ldx = ldx; g.ncols = ncols; g.out = out; g.ldo = ldo;
     g.part_stride = part_stride; g.mu = mu; g.skip_flag = skip_flag; g.skip_mask = skip_mask;
     g.gate = gate.w; g.gate_mask = gate.mask;
@@ -276,6 +277,11 @@ constexpr bool stream_fits() {
     return !MU && !CENT && (ARITH == 0 || sizeof(TA) == 2);
 }
 
+// Chunk of the reduction of the streamed kernel that stream_ncb launches.
+inline int stream_kc(int arith, int ncols) { return (arith != 0 || ncols <= 128) ? 64 : 32; }
+static_assert(StreamTile<float, MODE_NN, 0, 8>::KC == 64 && StreamTile<float, MODE_NN, 0, 14>::KC == 32 &&
+              StreamTile<float, MODE_NN, 1, 14>::KC == 64, "stream_kc");
+
 template <typename TA, int MODE, int ARITH, bool CENT, bool MU, class Ex>
 hipError_t stream_ncb(Ex& ex, const GemmArgs<TA, float, float>& g) {
     if (g.ncols <= 128) {
@@ -304,13 +310,21 @@ bool stream_variant(int arith, int ncols, bool mu) {
               : fits(stream_fits<TA, MODE, 2, 8, 1, false, false>(), stream_fits<TA, MODE, 2, 14, 1, false, false>());
 }
 
+// Scratch for the tail dealing of the streamed products (see StreamBody):
+// slots for groups x 256 rows x ncols f32, and the workgroups of a round (one
+// per CU).
+struct StreamTail { float* p = nullptr; size_t bytes = 0; int groups = 0; };
+
 // Returns hipErrorNotSupported (nothing launched) when the product does not
 // qualify: a batch, a small or misaligned A, or no packing scratch for X.
+// With tail scratch, the (tile, split) pairs of a last round that would fill
+// at most half of the CUs are cut into pieces for a whole round of workgroups
+// and summed into their output blocks by TailFixBody.
 template <typename TA, int MODE, class Ex>
 hipError_t gemm_streamed(Ex& ex, int arith, const TA* A, int64_t lda, int64_t rows, int64_t K, const float* X,
                          int64_t ldx, int ncols, float* out, int64_t ldo, int S, int64_t part_stride,
                          const double* mu, const uint32_t* skip_flag, uint32_t skip_mask, Gate gate, XPack xp,
-                         float* xk, int64_t ldxk) {
+                         float* xk, int64_t ldxk, StreamTail tail = {}) {
     if constexpr (!Ex::kSingle) {
         return hipErrorNotSupported;       // batches: many small products
     } else {
@@ -342,14 +356,31 @@ hipError_t gemm_streamed(Ex& ex, int arith, const TA* A, int64_t lda, int64_t ro
             g.xb = xp.p; g.ldxb = xp.ld; g.xb_plane = xp.plane;
         }
         if (e != hipSuccess) return e;
-        if (mu) {
-            if (arith == 0) return stream_ncb<TA, MODE, 0, false, true>(ex, g);
-            if (arith == 1) return stream_ncb<TA, MODE, 1, false, true>(ex, g);
-            return stream_ncb<TA, MODE, 2, sizeof(TA) == 2, true>(ex, g);
+        // tail dealing: when the pairs left over by whole rounds fill at most
+        // half of a round (each then splits into two or more pieces)
+        const int64_t tiles = cdiv(rows, 256), pairs = tiles * g.splits;
+        const int64_t ld_slot = rup(ncols, 4), leftover = tail.groups > 0 ? pairs % tail.groups : 0;
+        bool dealt = false;
+        if (tail.p && leftover > 0 && 2 * leftover <= tail.groups &&
+            tail.bytes >= static_cast<size_t>(tail.groups) * 256 * ld_slot * sizeof(float)) {
+            g.tail_groups = tail.groups;
+            g.tail_slots = tail.p;
+            g.ld_slot = ld_slot;
+            dealt = true;
         }
-        if (arith == 0) return stream_ncb<TA, MODE, 0, false, false>(ex, g);
-        if (arith == 1) return stream_ncb<TA, MODE, 1, false, false>(ex, g);
-        return stream_ncb<TA, MODE, 2, false, false>(ex, g);
+        if (mu) {
+            if (arith == 0) e = stream_ncb<TA, MODE, 0, false, true>(ex, g);
+            else if (arith == 1) e = stream_ncb<TA, MODE, 1, false, true>(ex, g);
+            else e = stream_ncb<TA, MODE, 2, sizeof(TA) == 2, true>(ex, g);
+        } else {
+            if (arith == 0) e = stream_ncb<TA, MODE, 0, false, false>(ex, g);
+            else if (arith == 1) e = stream_ncb<TA, MODE, 1, false, false>(ex, g);
+            else e = stream_ncb<TA, MODE, 2, false, false>(ex, g);
+        }
+        if (e != hipSuccess || !dealt) return e;
+        return ex.template run<TailFixBody>(TailFixArgs{tail.p, ld_slot, rows, ncols, static_cast<int>(tiles), 256,
+                                                        pairs - leftover, leftover, tail.groups, out, ldo, part_stride,
+                                                        skip_flag, skip_mask, gate});
     }
 }
 
@@ -361,10 +392,10 @@ template <typename TA, typename TC, int MODE, class Ex>
 hipError_t gemm_step(Ex& ex, int arith, int cls, const TA* A, int64_t lda, int64_t rows, int64_t K,
                      const TC* X, int64_t ldx, int ncols, TC* out, int64_t ldo, int S, int64_t part_stride,
                      const double* mu, const uint32_t* skip_flag, uint32_t skip_mask, Gate gate = {},
-                     XPack xp = {}, TC* xk = nullptr, int64_t ldxk = 0) {
+                     XPack xp = {}, TC* xk = nullptr, int64_t ldxk = 0, StreamTail tail = {}) {
     if constexpr (std::is_same<TC, float>::value) {
         const hipError_t e = gemm_streamed<TA, MODE>(ex, arith, A, lda, rows, K, X, ldx, ncols, out, ldo, S,
-                                                     part_stride, mu, skip_flag, skip_mask, gate, xp, xk, ldxk);
+                                                     part_stride, mu, skip_flag, skip_mask, gate, xp, xk, ldxk, tail);
         if (e != hipErrorNotSupported) return e;
         if (arith != 0)
             return gemm_bf16<TA, MODE>(ex, arith == 2, cls, A, lda, rows, K, X, ldx, ncols, out, ldo, S,

@@ -77,23 +77,30 @@ inline bool streamed_size(int64_t rows, int64_t K) {
 
 // Split of the reduction for the streamed-A products (256 output rows per
 // workgroup, one workgroup per CU): the count that minimises the estimated
-// time, rounds of workgroups (a partly filled last round costs a whole one)
-// plus one more write and read of each partial block (S x rows x Lp f32),
-// relative to one read of A (rows x K f32); at most `max_s` splits of at least
-// 1024 reduction elements, and at most 8 rounds.
+// time, whole rounds of workgroups plus the last one, whose L < num_cu pairs
+// are dealt in floor(num_cu / L) pieces each when L <= num_cu / 2 (a whole
+// round otherwise), plus one more write and read of each partial block
+// (S x rows x Lp f32) relative to one read of A (rows x K f32); at most
+// `max_s` splits of at least 1024 reduction elements, at most 8 rounds.
 inline int stream_split(int64_t rows, int64_t K, int Lp, int num_cu, int max_s) {
     const int64_t tiles = cdiv(rows, 256);
     int best = 1;
     double best_t = 1e300;
     for (int S = 1; S <= max_s && (S == 1 || K / S >= 1024); ++S) {
-        const int64_t wg = tiles * S, rounds = cdiv(wg, num_cu);
-        if (S > 1 && rounds > 8) break;
-        const double fill = static_cast<double>(wg) / static_cast<double>(rounds * num_cu);
-        const double t = 1.0 / fill + (S > 1 ? 2.0 * S * Lp / static_cast<double>(K) : 0.0);
+        const int64_t wg = tiles * S, whole = wg / num_cu, left = wg % num_cu;
+        if (S > 1 && whole > 8) break;
+        double rounds = static_cast<double>(whole);
+        if (left > 0) rounds += (2 * left <= num_cu) ? 1.0 / static_cast<double>(num_cu / left) : 1.0;
+        const double t = rounds / S / (static_cast<double>(tiles) / num_cu) +
+                         (S > 1 ? 2.0 * S * Lp / static_cast<double>(K) : 0.0);
         if (t < best_t - 1e-9) { best_t = t; best = S; }
     }
     return best;
 }
+
+// Slots of the tail dealing of the streamed products: one round's worth of
+// 256-row tiles of Lp f32 columns.
+inline size_t tail_slot_bytes(int num_cu, int Lp) { return static_cast<size_t>(num_cu) * 256 * Lp * sizeof(float); }
 
 // Whether a single solve's products of sketch width l run the streamed-A
 // kernel (A X always; A^T Q also needs n % 4 == 0; A's rows must also be
@@ -124,6 +131,7 @@ struct Plan {
     int dtype = 0;
     int64_t m = 0, n = 0;
     int k = 0, p = 0, q = 0, l = 0, Lp = 0, kp = 0;
+    int ncu = 0;        // compute units (the workgroups of one round of the streamed products)
     int tile = 0;       // column class of the tall product tiles (tile_class of l)
     int var_nn = 0, var_tn = 0;   // tile variants of the NN / TN products (tile_variant_index)
     int qmax = 0;       // gated: power iterations issued for the whole batch group
@@ -148,6 +156,9 @@ struct Plan {
     // Lp columns x ldxp (max(m, n) rounded up to 8) each
     size_t xpack = 0;
     int64_t ldxp = 0, xplane = 0;
+    // streamed products of a single solve: slots of their tail dealing
+    // (ncu x 256 x Lp f32)
+    size_t tailslot = 0;
     // storage-precision products of a single solve: X copied k-contiguous,
     // Lp columns x ldxk (max(m, n) rounded up to 8) in the compute type
     size_t xk = 0;
@@ -198,6 +209,7 @@ inline Plan make_plan(int dtype, int64_t m, int64_t n, int k, const rsvd_params*
     P.qmax = P.q;
     P.gated = batch;
     P.sp = batch ? Splits{1, 1, 1, 1, 1} : make_splits(m, n, num_cu, dtype != RSVD_F64, P.l, P.Lp);
+    P.ncu = num_cu;
     const size_t cs = comp_size(dtype);
     Layout L;
     P.status = L.take(kAlign);
@@ -229,6 +241,8 @@ inline Plan make_plan(int dtype, int64_t m, int64_t n, int k, const rsvd_params*
         P.jrot = L.take(64 * sizeof(uint32_t));
         P.qtmp = L.take(static_cast<size_t>(std::max(m, n)) * P.Lp * cs);
     }
+    if (!batch && (stream_product(dtype, m, n, P.l, false) || stream_product(dtype, m, n, P.l, true)))
+        P.tailslot = L.take(tail_slot_bytes(num_cu, P.Lp));
     if (prm->precision == RSVD_PREC_BF16_MIXED) {
         P.ldxp = rup(std::max(m, n), 8);
         P.xplane = static_cast<int64_t>(P.Lp) * P.ldxp;
@@ -302,6 +316,7 @@ inline Plan block_plan(int32_t dtype, int64_t m, int64_t n, int32_t c, int num_c
     Plan P;
     P.dtype = dtype; P.m = m; P.n = n; P.l = c; P.Lp = tile_cols(c);
     P.sp = make_splits(m, n, num_cu, dtype != RSVD_F64, c, P.Lp);
+    P.ncu = num_cu;
     const size_t cs = comp_size(dtype);
     Layout L;
     P.status = L.take(kAlign);
@@ -317,6 +332,8 @@ inline Plan block_plan(int32_t dtype, int64_t m, int64_t n, int32_t c, int num_c
     P.xpack = L.take(2 * static_cast<size_t>(P.xplane) * sizeof(uint16_t));
     P.ldxk = rup(std::max(m, n), 8);
     P.xk = L.take(static_cast<size_t>(P.Lp) * P.ldxk * cs);
+    if (stream_product(dtype, m, n, c, false) || stream_product(dtype, m, n, c, true))
+        P.tailslot = L.take(tail_slot_bytes(num_cu, P.Lp));
     if (c <= RSVD_MAX_L) {
         const size_t leaves = static_cast<size_t>(cdiv(std::max(m, n), 256));
         P.lucand = L.take(2 * leaves * c * sizeof(int32_t));

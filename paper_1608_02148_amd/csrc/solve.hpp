@@ -229,17 +229,19 @@ hipError_t solve_steps(Ex& ex, rsvd_handle_t prof, const Plan& P, const TA* A, i
     const int early = mixed ? 1 : 0, late = mixed ? 2 : 0;
     const XPack xp{P.ldxp ? at<uint16_t>(work, P.xpack) : nullptr, P.ldxp, P.xplane};   // bf16 products
     TC* xk = P.ldxk ? at<TC>(work, P.xk) : nullptr;                                     // storage-precision products
+    const StreamTail tail = (P.tailslot && !gated)                                      // streamed products
+        ? StreamTail{at<float>(work, P.tailslot), tail_slot_bytes(P.ncu, Lp), P.ncu} : StreamTail{};
     auto ax = [&](const TC* X, int arith, Gate gt) -> hipError_t {     // Y (m x Lp) = A X
         const int S = P.sp.nn;
         RSVD_TRY(scale_rows(const_cast<TC*>(X), l, Lp));
         if (S == 1)
             return timed(prof, 0, pass_flops, nn_bytes, [&] {
                 return gemm_step<TA, TC, MODE_NN>(ex, arith, tile, A, lda, m, n, X, Lp, l, Y, Lp, 1, 0, mu,
-                                                  nullptr, 0, gt, xp, xk, P.ldxk);
+                                                  nullptr, 0, gt, xp, xk, P.ldxk, tail);
             });
         RSVD_TRY(timed(prof, 0, pass_flops, nn_bytes, [&] {
             return gemm_step<TA, TC, MODE_NN>(ex, arith, tile, A, lda, m, n, X, Lp, l, partc, Lp, S,
-                                              static_cast<int64_t>(m) * Lp, mu, nullptr, 0, gt, xp, xk, P.ldxk);
+                                              static_cast<int64_t>(m) * Lp, mu, nullptr, 0, gt, xp, xk, P.ldxk, tail);
         }));
         return reduce_step<TC>(ex, partc, S, static_cast<int64_t>(m) * Lp, Lp, m, l, Y, Lp, nullptr, 0, gt);
     };
@@ -273,13 +275,13 @@ hipError_t solve_steps(Ex& ex, rsvd_handle_t prof, const Plan& P, const TA* A, i
         if (S == 1) {
             RSVD_TRY(timed(prof, 1, pass_flops, tn_bytes, [&] {
                 return gemm_step<TA, TC, MODE_TN>(ex, arith, tile_tn, A, lda, n, m, Y, Lp, l, dst, Lp, 1, 0, mu,
-                                                  nullptr, 0, gt, xp, xk, P.ldxk);
+                                                  nullptr, 0, gt, xp, xk, P.ldxk, tail);
             }));
             return scale_rows(dst, l, Lp);
         }
         RSVD_TRY(timed(prof, 1, pass_flops, tn_bytes, [&] {
             return gemm_step<TA, TC, MODE_TN>(ex, arith, tile_tn, A, lda, n, m, Y, Lp, l, partc, Lp, S,
-                                              static_cast<int64_t>(n) * Lp, mu, nullptr, 0, gt, xp, xk, P.ldxk);
+                                              static_cast<int64_t>(n) * Lp, mu, nullptr, 0, gt, xp, xk, P.ldxk, tail);
         }));
         RSVD_TRY(reduce_step<TC>(ex, partc, S, static_cast<int64_t>(n) * Lp, Lp, n, l, dst, Lp, nullptr, 0, gt));
         return scale_rows(dst, l, Lp);

@@ -4,7 +4,7 @@
 runs Y = A X (nn) or Z = A^T Q (tn) through rsvd_gemm_nn / rsvd_gemm_tn on
 seeded Gaussian data at the benchmark shapes and prints the mean time per
 product (HIP events).  Shapes: c2 = 100000 x 5000 f32 with 120 columns, c3 =
-200000 x 20000 bf16 with 220 columns.
+200000 x 20000 bf16 with 220 columns (--m, --n, --c override them).
 """
 import argparse
 import json
@@ -16,8 +16,9 @@ from . import api
 SHAPES = {"c2": (100000, 5000, 120, torch.float32), "c3": (200000, 20000, 220, torch.bfloat16)}
 
 
-def run(shape, arith, mode, reps, warmup=1, splits=0):
-    m, n, c, dt = SHAPES[shape]
+def run(shape, arith, mode, reps, warmup=1, splits=0, m=None, n=None, c=None):
+    m0, n0, c0, dt = SHAPES[shape]
+    m, n, c = m or m0, n or n0, c or c0
     dev = torch.device("cuda", 0)
     g = torch.Generator(device=dev)
     g.manual_seed(2148)
@@ -49,8 +50,13 @@ def main():
     ap.add_argument("--arith", choices=["storage", "bf16", "split"], default="bf16")
     ap.add_argument("--mode", choices=["nn", "tn"], default="nn")
     ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--m", type=int, default=None, help="rows of A (default: the shape's)")
+    ap.add_argument("--n", type=int, default=None, help="columns of A")
+    ap.add_argument("--c", type=int, default=None, help="columns of X")
+    ap.add_argument("--splits", type=int, default=0, help="A X: chunks of the reduction (0: the library's choice)")
     args = ap.parse_args()
-    print(json.dumps(run(args.shape, args.arith, args.mode, args.reps)), flush=True)
+    print(json.dumps(run(args.shape, args.arith, args.mode, args.reps, splits=args.splits, m=args.m, n=args.n,
+                         c=args.c)), flush=True)
 
 
 if __name__ == "__main__":
