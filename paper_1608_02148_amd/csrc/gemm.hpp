@@ -49,6 +49,7 @@ struct GemmArgs {
     // streamed products: the (tile, split) pairs past the last whole round of
     // tail_groups workgroups are dealt to tail_groups more workgroups in equal
     // shares of chunks, which write slots of TROWS x ld_slot (see StreamBody)
+    int32_t upper_only;  // square tiles of a symmetric product: skip the tiles below the diagonal
     int32_t tail_groups;
     float* tail_slots;
     int64_t ld_slot;

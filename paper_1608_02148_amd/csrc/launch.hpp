@@ -37,6 +37,7 @@ struct GemmBody {
         const int gx = static_cast<int>(cdiv(g.rows, T::BM));
         const int nct = static_cast<int>(cdiv(g.ncols, T::NC));
         const int rest = b / nct;
+        if (g.upper_only && rest % gx > b % nct) return;     // a tile below the diagonal of a symmetric product
         gemm_tile_body<TA, TX, TC, MODE, WR, WC, WGM, WGN, BK, XKP>(g, rest % gx, rest / gx, b % nct);
     }
 };
@@ -73,6 +74,7 @@ GemmArgs<TA, TX, TC> gemm_args(const TA* A, int64_t lda, int64_t rows, int64_t K
     S = S < 1 ? 1 : S;
     g.kchunk = rup(cdiv(K, S), kchunk_multiple);   // splits past the end of K write zero partials
     g.splits = S;
+    g.upper_only = 0;
     g.tail_groups = 0; g.tail_slots = nullptr; g.ld_slot = 0;
     g.X = X; g.ldx = ldx; g.ncols = ncols; g.out = out; g.ldo = ldo;
     g.part_stride = part_stride; g.mu = mu; g.skip_flag = skip_flag; g.skip_mask = skip_mask;
@@ -165,10 +167,11 @@ template <typename TA, typename TX, typename TC, int MODE, class Ex>
 hipError_t gemm_plain(Ex& ex, int cls, bool square, const TA* A, int64_t lda, int64_t rows, int64_t K,
                       const TX* X, int64_t ldx, int ncols, TC* out, int64_t ldo, int S, int64_t part_stride,
                       const double* mu, const uint32_t* skip_flag, uint32_t skip_mask, Gate gate = {},
-                      TC* xk = nullptr, int64_t ldxk = 0) {
+                      TC* xk = nullptr, int64_t ldxk = 0, bool upper_only = false) {
     const size_t vb = (16 / sizeof(TC)) * sizeof(TA);    // 16 / sizeof(TC) consecutive elements of A
     auto g = gemm_args<TA, TX, TC>(A, lda, rows, K, X, ldx, ncols, out, ldo, S, part_stride, mu, skip_flag,
                                    skip_mask, gemm_bk<TC>(), vb, gate);
+    g.upper_only = (square && upper_only) ? 1 : 0;
     if constexpr (std::is_same<TX, TC>::value) {
         // optional k-contiguous copy of X (scratch xk, ld ldxk >= K, a multiple
         // of 16 / sizeof(TC)): one vector load per k-vector in the tiles

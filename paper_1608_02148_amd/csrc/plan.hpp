@@ -72,7 +72,7 @@ inline int nn_split(int64_t m, int64_t n, int num_cu) {
 
 // Products large enough for the streamed-A kernel (rows x K elements of A).
 inline bool streamed_size(int64_t rows, int64_t K) {
-    return rows >= 256 && K >= 256 && rows * K >= (int64_t(1) << 24);
+    return rows >= 256 && K >= 64 && rows * K >= (int64_t(1) << 24);
 }
 
 // Split of the reduction for the streamed-A products (256 output rows per
@@ -103,10 +103,10 @@ inline int stream_split(int64_t rows, int64_t K, int Lp, int num_cu, int max_s) 
 inline size_t tail_slot_bytes(int num_cu, int Lp) { return static_cast<size_t>(num_cu) * 256 * Lp * sizeof(float); }
 
 // Whether a single solve's products of sketch width l run the streamed-A
-// kernel (A X always; A^T Q also needs n % 4 == 0; A's rows must also be
-// 16-byte aligned, which only the run checks).
+// kernel (A X: m rows, reduction n; A^T Q: n rows, n % 4 == 0, reduction m;
+// A's rows must also be 16-byte aligned, which only the run checks).
 inline bool stream_product(int dtype, int64_t m, int64_t n, int l, bool tn) {
-    return dtype != RSVD_F64 && streamed_size(m, n) && l > 64 && l <= 224 && (!tn || n % 4 == 0);
+    return dtype != RSVD_F64 && (tn ? streamed_size(n, m) && n % 4 == 0 : streamed_size(m, n)) && l > 64 && l <= 224;
 }
 
 // streamed: f32 / bf16 storage, where the large products of sketch width l

@@ -59,8 +59,11 @@ hipError_t orthonormalize(Ex& ex, int tile, TC* M, int64_t ldm, int64_t rows, in
         const bool conditional = (pass == 3) || (pass == 2 && adaptive);
         const uint32_t* skip = conditional ? status : nullptr;
         const uint32_t need = (pass == 2) ? ST_NEED_P2 : ST_NEED_P3;
+        // (l > 128: the blocked Cholesky reads only the blocks on and above the
+        // diagonal, so the tile below it is not formed)
         RSVD_TRY((gemm_plain<TC, TC, double, MODE_TN>(ex, 0, true, M, ldm, l, rows, M, ldm, l, part, Lp, S,
-                                                      static_cast<int64_t>(Lp) * Lp, nullptr, skip, need, gate)));
+                                                      static_cast<int64_t>(Lp) * Lp, nullptr, skip, need, gate,
+                                                      nullptr, 0, l > CHOL_MAX_L)));
         if (S > 1) RSVD_TRY(reduce_step<double>(ex, part, S, static_cast<int64_t>(Lp) * Lp, Lp, l, l, gram, Lp,
                                                 skip, need, gate));
         CholArgs ca;
@@ -76,7 +79,18 @@ hipError_t orthonormalize(Ex& ex, int tile, TC* M, int64_t ldm, int64_t rows, in
         } else {
             RSVD_TRY(run_chol<TC>(ex, ca));
         }
-        // Q = M R^{-1} in place is safe while one column tile holds all l
+        // Q = M R^{-1} in place: the streamed kernel takes it when the product
+        // is large (one workgroup owns whole rows and writes them after its
+        // last read of them; R^{-1} is packed k-contiguous into the Gram
+        // scratch, free once the factor is formed).
+        if constexpr (std::is_same<TC, float>::value) {
+            const hipError_t e = gemm_streamed<TC, MODE_NN>(ex, 0, M, ldm, rows, l, rinv, Lp, l, M, ldm, 1, 0, nullptr,
+                                                            skip, need, gate, XPack{},
+                                                            reinterpret_cast<float*>(gram), Lp);
+            if (e == hipSuccess) continue;
+            if (e != hipErrorNotSupported) return e;
+        }
+        // Otherwise in place is safe while one column tile holds all l
         // columns (each workgroup reads its rows before writing them); with
         // two tiles (l > 128) one tile's writes would race the other's reads,
         // so the product goes through qtmp (rows x Lp) and is copied back.

@@ -6,8 +6,9 @@ X staged in LDS) at the sizes where the library takes them: m K >= 2^24,
   whatever the summation order, so those comparisons are bitwise: they cover
   ragged row tiles (m not a multiple of 256), a ragged last chunk of the
   reduction (K not a multiple of the 32 / 64-element chunk), split reductions
-  with their partial blocks, both column classes (c <= 128 and c <= 224) and
-  TN strips whose last columns fall past n.
+  with their partial blocks, both column classes (c <= 128 and c <= 224), TN
+  strips whose last columns fall past n, and the last-round pieces (tail
+  dealing) after whole rounds and on their own.
 * Random operands bound the rounding: f32 arithmetic and split bf16 within a
   few f32 roundings of a K-term dot product, bf16 within bf16 rounding.
 * Full solves at streamed sizes (f32 and bf16 storage, plain and mixed, with
@@ -48,6 +49,37 @@ def test_streamed_nn_exact_integers(gpu_lib, dt, arith, m, K, c, splits):
     Xg = torch.tensor(X, dtype=torch.float32, device=DEV)
     Y = _np(api.gemm_nn(Ag, Xg, arith, splits=splits))
     assert np.array_equal(Y, A @ X)
+
+
+@pytest.mark.parametrize("dt,arith", [("f32", "storage"), ("f32", "bf16")])
+@pytest.mark.parametrize("m,K,c", [(76837, 1100, 100), (76837, 1100, 220)])
+def test_streamed_nn_whole_rounds_and_tail(gpu_lib, dt, arith, m, K, c):
+    """301 row tiles: one whole round of 256 workgroups (placed by hardware
+    block index) and 45 tiles dealt in pieces to a second round, whose slots
+    TailFixBody sums; bitwise on small integers."""
+    from paper_1608_02148_amd import api
+    print(f"streamed NN tail {dt} {arith} m={m} K={K} c={c}", flush=True)
+    rng = np.random.default_rng(m + c)
+    A = _ints(rng, (m, K), -8, 8)
+    X = _ints(rng, (K, c), -4, 4)
+    Y = _np(api.gemm_nn(torch.tensor(A, dtype=DT[dt], device=DEV), torch.tensor(X, dtype=torch.float32, device=DEV),
+                        arith, splits=1))
+    assert np.array_equal(Y, A @ X)
+
+
+@pytest.mark.parametrize("dt,arith", [("f32", "storage"), ("bf16", "bf16"), ("bf16", "split")])
+def test_streamed_tn_split_rounds_and_tail(gpu_lib, dt, arith):
+    """A^T Q at 50000 x 5120: 20 column tiles x 13 splits = 260 pairs, one
+    whole round and 4 pairs dealt in 64 pieces each; bitwise on integers."""
+    from paper_1608_02148_amd import api
+    m, n, c = 50000, 5120, 120
+    print(f"streamed TN tail {dt} {arith} m={m} n={n} c={c}", flush=True)
+    rng = np.random.default_rng(5120)
+    A = _ints(rng, (m, n), -4, 4)
+    Q = _ints(rng, (m, c), -3, 3)
+    Z = _np(api.gemm_tn(torch.tensor(A, dtype=DT[dt], device=DEV),
+                        torch.tensor(Q, dtype=torch.float32, device=DEV), arith))
+    assert np.array_equal(Z, A.T @ Q)
 
 
 @pytest.mark.parametrize("dt,arith", [("f32", "storage"), ("bf16", "storage"), ("f32", "bf16"),
