@@ -389,7 +389,7 @@ __device__ __forceinline__ void chol_body(const CholArgs& a) {
     __shared__ uint32_t s_flags;
     __shared__ double s_trace;
     __shared__ int s_fail, s_dead;
-    __shared__ double s_min_ratio;
+    __shared__ int s_ratio;           // bit 0: some d_j < 1e-6 G_jj; bit 1: some d_j < G_jj / 2
     double g[CT_R][CT_C];
     const int npanel = (l + CT_R - 1) / CT_R;
 
@@ -441,127 +441,144 @@ __device__ __forceinline__ void chol_body(const CholArgs& a) {
                 load(11.0 * (static_cast<double>(a.mrows) * l + static_cast<double>(l) * (l + 1)) * u * trace);
                 shifted = true;
             }
-            if (tid == 0) { s_fail = 0; s_dead = 0; s_min_ratio = 1.0; }
+            if (tid == 0) { s_fail = 0; s_dead = 0; s_ratio = 0; }
             __syncthreads();
-            for (int P = 0; P < npanel; ++P) {
-                const int j0 = CT_R * P, buf = P & 1;
-                if (ty == P) {
-                    // The panel's 4 x 4 diagonal block lies in one lane (columns
-                    // j0..j0+3: lane j0 / 8, offset j0 % 8).  Its upper half is
-                    // broadcast to the group; every lane factors it (R_PP, pivot
-                    // rules above), inverts it (X_PP = R_PP^{-1}, zero row and
-                    // column for a dead pivot) and forms its own columns of the
-                    // panel rows as R_P = X_PP^T G_P: no step-by-step chain.
-                    const int dl = j0 / CT_C;
-                    const bool hi = (j0 % CT_C) != 0;
-                    double Gd[CT_R][CT_R], Rd[CT_R][CT_R], Xd[CT_R][CT_R], dv[CT_R] = {};
-                    // (two static copies: a select between g[t][v] and
-                    // g[t][4 + v] would become an indexed load from memory)
-                    if (hi) {
-#pragma unroll
-                        for (int t = 0; t < CT_R; ++t)
-#pragma unroll
-                            for (int v = 0; v < CT_R; ++v) Gd[t][v] = (v >= t) ? from_lane(g[t][CT_R + v], dl) : 0.0;
-                    } else {
-#pragma unroll
-                        for (int t = 0; t < CT_R; ++t)
-#pragma unroll
-                            for (int v = 0; v < CT_R; ++v) Gd[t][v] = (v >= t) ? from_lane(g[t][v], dl) : 0.0;
-                    }
+            // the owner group of panel P turns its rows into rows of R and
+            // publishes them in panel[buf]
+            auto factor_panel = [&](const int P, const int buf) {
+                const int j0 = CT_R * P;
+                // The panel's 4 x 4 diagonal block lies in one lane (columns
+                // j0..j0+3: lane j0 / 8, offset j0 % 8).  Its upper half is
+                // broadcast to the group; every lane factors it (R_PP, pivot
+                // rules above), inverts it (X_PP = R_PP^{-1}, zero row and
+                // column for a dead pivot) and forms its own columns of the
+                // panel rows as R_P = X_PP^T G_P: no step-by-step chain.
+                const int dl = j0 / CT_C;
+                const bool hi = (j0 % CT_C) != 0;
+                double Gd[CT_R][CT_R], Rd[CT_R][CT_R], Xd[CT_R][CT_R], dv[CT_R] = {};
+                // (two static copies: a select between g[t][v] and
+                // g[t][4 + v] would become an indexed load from memory)
+                if (hi) {
 #pragma unroll
                     for (int t = 0; t < CT_R; ++t)
 #pragma unroll
-                        for (int v = 0; v < CT_R; ++v) {
-                            Rd[t][v] = 0.0;
-                            Xd[t][v] = 0.0;
-                        }
-                    bool fail = false, dead_any = false;
-                    double min_ratio = 1.0;
+                        for (int v = 0; v < CT_R; ++v) Gd[t][v] = (v >= t) ? from_lane(g[t][CT_R + v], dl) : 0.0;
+                } else {
+#pragma unroll
+                    for (int t = 0; t < CT_R; ++t)
+#pragma unroll
+                        for (int v = 0; v < CT_R; ++v) Gd[t][v] = (v >= t) ? from_lane(g[t][v], dl) : 0.0;
+                }
+#pragma unroll
+                for (int t = 0; t < CT_R; ++t)
+#pragma unroll
+                    for (int v = 0; v < CT_R; ++v) {
+                        Rd[t][v] = 0.0;
+                        Xd[t][v] = 0.0;
+                    }
+                // Branch-free pivots: the diagonal of G is read ahead of the
+                // chain, the square root and its reciprocal come from one
+                // reciprocal square root (sqrt(d) = d / sqrt(d)), and the pivot
+                // ratios d_j / G_jj are only compared with the two thresholds
+                // above (1e-6 and 1/2), by multiplication.
+                double d0v[CT_R];
+#pragma unroll
+                for (int t = 0; t < CT_R; ++t) d0v[t] = (j0 + t < l) ? diag0[j0 + t] : 1.0;
+                const bool first_try = (a.pass == 1) && (attempt == 0);
+                bool fail = false, dead_any = false, low = false, half = false;
+#pragma unroll
+                for (int t = 0; t < CT_R; ++t) {
+                    // rows past l stay zero; after a failed pivot the
+                    // attempt is restarted, so the rest is not needed
+                    const int j = j0 + t;
+                    const bool live = (j < l) & !fail;
+                    double d = Gd[t][t];
+#pragma unroll
+                    for (int i = 0; i < t; ++i) d -= Rd[i][t] * Rd[i][t];
+                    const double d0 = d0v[t];
+                    const bool finite = isfinite(d);
+                    const bool bad = live & first_try & (!(d > 100.0 * u * d0) | !finite);
+                    fail = fail | bad;
+                    const bool dead = !(d > 1e-30 * d0) | !finite | (d0 == 0.0);
+                    const bool use = live & !bad & !dead;
+                    const double inv_sq = use ? rsqrt(use ? d : 1.0) : 0.0;
+                    const double sq = use ? d * inv_sq : 0.0;
+                    dead_any = dead_any | (live & !bad & dead);
+                    low = low | (use & (d < 1e-6 * d0));
+                    half = half | (use & (d < 0.5 * d0));
+                    Rd[t][t] = sq;
+                    dv[t] = inv_sq;
+#pragma unroll
+                    for (int v = t + 1; v < CT_R; ++v) {
+                        double w = Gd[t][v];
+#pragma unroll
+                        for (int i = 0; i < t; ++i) w -= Rd[i][t] * Rd[i][v];
+                        Rd[t][v] = w * inv_sq;
+                    }
+                }
+#pragma unroll
+                for (int v = 0; v < CT_R; ++v) {          // R_PP X = I, column by column
+                    Xd[v][v] = dv[v];
+#pragma unroll
+                    for (int t = v - 1; t >= 0; --t) {
+                        double w = 0.0;
+#pragma unroll
+                        for (int i = t + 1; i <= v; ++i) w += Rd[t][i] * Xd[i][v];
+                        Xd[t][v] = -dv[t] * w;
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < CT_C; ++q) {          // rows j0..j0+3 of R
+                    const int c = b0 + q;
+                    double gc[CT_R];
+#pragma unroll
+                    for (int i = 0; i < CT_R; ++i) gc[i] = g[i][q];
 #pragma unroll
                     for (int t = 0; t < CT_R; ++t) {
-                        // rows past l stay zero; after a failed pivot the
-                        // attempt is restarted, so the rest is not needed
-                        const int j = j0 + t;
-                        const bool live = (j < l) && !fail;
-                        double d = Gd[t][t];
+                        double v = 0.0;
 #pragma unroll
-                        for (int i = 0; i < t; ++i) d -= Rd[i][t] * Rd[i][t];
-                        const double d0 = live ? diag0[j] : 1.0;
-                        const bool bad = live && a.pass == 1 && attempt == 0 && (!(d > 100.0 * u * d0) || !isfinite(d));
-                        fail = fail || bad;
-                        const bool dead = !(d > 1e-30 * d0) || !isfinite(d) || d0 == 0.0;
-                        const bool use = live && !bad && !dead;
-                        const double sq = use ? sqrt(d) : 0.0;
-                        const double inv_sq = use ? 1.0 / sq : 0.0;
-                        if (live && !bad) {
-                            if (dead) dead_any = true;
-                            else min_ratio = fmin(min_ratio, d / d0);
-                        }
-                        Rd[t][t] = sq;
-                        dv[t] = inv_sq;
-#pragma unroll
-                        for (int v = t + 1; v < CT_R; ++v) {
-                            double w = Gd[t][v];
-#pragma unroll
-                            for (int i = 0; i < t; ++i) w -= Rd[i][t] * Rd[i][v];
-                            Rd[t][v] = w * inv_sq;
-                        }
+                        for (int i = 0; i <= t; ++i) v += Xd[i][t] * gc[i];
+                        g[t][q] = (c < j0 + t) ? 0.0 : v;
                     }
-#pragma unroll
-                    for (int v = 0; v < CT_R; ++v) {          // R_PP X = I, column by column
-                        Xd[v][v] = dv[v];
-#pragma unroll
-                        for (int t = v - 1; t >= 0; --t) {
-                            double w = 0.0;
-#pragma unroll
-                            for (int i = t + 1; i <= v; ++i) w += Rd[t][i] * Xd[i][v];
-                            Xd[t][v] = -dv[t] * w;
-                        }
-                    }
-#pragma unroll
-                    for (int q = 0; q < CT_C; ++q) {          // rows j0..j0+3 of R
-                        const int c = b0 + q;
-                        double gc[CT_R];
-#pragma unroll
-                        for (int i = 0; i < CT_R; ++i) gc[i] = g[i][q];
-#pragma unroll
-                        for (int t = 0; t < CT_R; ++t) {
-                            double v = 0.0;
-#pragma unroll
-                            for (int i = 0; i <= t; ++i) v += Xd[i][t] * gc[i];
-                            g[t][q] = (c < j0 + t) ? 0.0 : v;
-                        }
-                    }
-                    if (tx == 0) {
-                        if (fail) s_fail = 1;
-                        if (dead_any) s_dead = 1;
-                        s_min_ratio = fmin(s_min_ratio, min_ratio);
-#pragma unroll
-                        for (int t = 0; t < CT_R; ++t)
-#pragma unroll
-                            for (int v = 0; v < CT_R; ++v) xdiag[P][t][v] = Xd[t][v];
-                    }
+                }
+                if (tx == 0) {
+                    if (fail) s_fail = 1;
+                    if (dead_any) s_dead = 1;
+                    s_ratio |= (low ? 1 : 0) | (half ? 2 : 0);
 #pragma unroll
                     for (int t = 0; t < CT_R; ++t)
 #pragma unroll
-                        for (int q = 0; q < CT_C; ++q) panel[buf][t][b0 + q] = g[t][q];
+                        for (int v = 0; v < CT_R; ++v) xdiag[P][t][v] = Xd[t][v];
                 }
-                __syncthreads();
+#pragma unroll
+                for (int t = 0; t < CT_R; ++t)
+#pragma unroll
+                    for (int q = 0; q < CT_C; ++q) panel[buf][t][b0 + q] = g[t][q];
+            };
+            // rows below panel P: G -= R_P^T R_P from panel[buf]
+            auto update_from = [&](const int buf) {
+#pragma unroll
+                for (int t = 0; t < CT_R; ++t) {
+                    double pc[CT_C];
+#pragma unroll
+                    for (int q = 0; q < CT_C; ++q) pc[q] = panel[buf][t][b0 + q];
+#pragma unroll
+                    for (int i = 0; i < CT_R; ++i) {
+                        const double pr = panel[buf][t][a0 + i];
+#pragma unroll
+                        for (int q = 0; q < CT_C; ++q) g[i][q] -= pr * pc[q];
+                    }
+                }
+            };
+            // Look-ahead: while the rows below panel P apply its update, the
+            // owner of panel P + 1 applies it to its own rows first and factors
+            // and publishes panel P + 1 in the same phase, so a panel's serial
+            // factorisation overlaps the previous panel's update.
+            for (int P = -1; P < npanel; ++P) {
                 if (s_fail) break;                          // uniform after the barrier
-                if (ty > P) {                               // trailing rows: G -= R_p^T R_p
-#pragma unroll
-                    for (int t = 0; t < CT_R; ++t) {
-                        double pc[CT_C];
-#pragma unroll
-                        for (int q = 0; q < CT_C; ++q) pc[q] = panel[buf][t][b0 + q];
-#pragma unroll
-                        for (int i = 0; i < CT_R; ++i) {
-                            const double pr = panel[buf][t][a0 + i];
-#pragma unroll
-                            for (int q = 0; q < CT_C; ++q) g[i][q] -= pr * pc[q];
-                        }
-                    }
-                }
+                if (P >= 0 && ty > P) update_from(P & 1);
+                if (ty == P + 1 && P + 1 < npanel) factor_panel(P + 1, (P + 1) & 1);
+                __syncthreads();
             }
             const bool failed = s_fail != 0;
             __syncthreads();
@@ -576,7 +593,7 @@ __device__ __forceinline__ void chol_body(const CholArgs& a) {
     }
     if (tid == 0) {
         const bool dead_any = !nonfinite && !zero && s_dead;
-        const double min_ratio = (!nonfinite && !zero) ? s_min_ratio : 1.0;
+        const int ratio = (!nonfinite && !zero) ? s_ratio : 0;
         uint32_t f = s_flags;
         if (nonfinite) f |= RSVD_FLAG_NONFINITE;
         if (zero || dead_any) f |= RSVD_FLAG_DEGENERATE;
@@ -584,9 +601,9 @@ __device__ __forceinline__ void chol_body(const CholArgs& a) {
         // so the Gram, Cholesky and apply kernels of a pass all see them.
         if (a.pass == 1) {
             if (shifted) f |= RSVD_FLAG_CHOL_SHIFT | ST_SHIFTED | ST_NEED_P2;
-            else if (a.adaptive && min_ratio < 1e-6) f |= ST_NEED_P2;
+            else if (a.adaptive && (ratio & 1)) f |= ST_NEED_P2;
         } else if (a.pass == 2) {
-            if ((f & ST_SHIFTED) || min_ratio < 0.5) f |= ST_NEED_P3;
+            if ((f & ST_SHIFTED) || (ratio & 2)) f |= ST_NEED_P3;
         }
         s_flags = f;
     }
@@ -608,42 +625,49 @@ __device__ __forceinline__ void chol_body(const CholArgs& a) {
     for (int i = 0; i < CT_R; ++i)
 #pragma unroll
         for (int q = 0; q < CT_C; ++q) x[i][q] = (a0 + i == b0 + q && a0 + i < l) ? 1.0 : 0.0;
-    for (int P = npanel - 1; P >= 0; --P) {
-        const int j0 = CT_R * P, buf = P & 1;
-        if (ty == P) {                  // X_P = X_PP B_P (B_P: rows j0..j0+3 so far)
+    // the owner group of panel P forms its rows X_P = X_PP B_P (B_P: rows
+    // j0..j0+3 so far) and publishes them in panel[buf]
+    auto form_rows = [&](const int P, const int buf) {
 #pragma unroll
-            for (int q = 0; q < CT_C; ++q) {
-                double bq[CT_R];
+        for (int q = 0; q < CT_C; ++q) {
+            double bq[CT_R];
 #pragma unroll
-                for (int i = 0; i < CT_R; ++i) bq[i] = x[i][q];
-#pragma unroll
-                for (int t = 0; t < CT_R; ++t) {
-                    double v = 0.0;
-#pragma unroll
-                    for (int i = t; i < CT_R; ++i) v += xdiag[P][t][i] * bq[i];
-                    x[t][q] = v;
-                }
-            }
-#pragma unroll
-            for (int t = 0; t < CT_R; ++t)
-#pragma unroll
-                for (int q = 0; q < CT_C; ++q) panel[buf][t][b0 + q] = x[t][q];
-        }
-        __syncthreads();
-        if (ty < P) {
+            for (int i = 0; i < CT_R; ++i) bq[i] = x[i][q];
 #pragma unroll
             for (int t = 0; t < CT_R; ++t) {
-                double xr[CT_C];
+                double v = 0.0;
 #pragma unroll
-                for (int q = 0; q < CT_C; ++q) xr[q] = panel[buf][t][b0 + q];
-#pragma unroll
-                for (int i = 0; i < CT_R; ++i) {
-                    const double rij = Rs[(a0 + i) * LDR + j0 + t];
-#pragma unroll
-                    for (int q = 0; q < CT_C; ++q) x[i][q] -= rij * xr[q];
-                }
+                for (int i = t; i < CT_R; ++i) v += xdiag[P][t][i] * bq[i];
+                x[t][q] = v;
             }
         }
+#pragma unroll
+        for (int t = 0; t < CT_R; ++t)
+#pragma unroll
+            for (int q = 0; q < CT_C; ++q) panel[buf][t][b0 + q] = x[t][q];
+    };
+    // rows above panel P: x -= R[., 4P..4P+3] X_P from panel[buf]
+    auto apply_from = [&](const int P, const int buf) {
+        const int j0 = CT_R * P;
+#pragma unroll
+        for (int t = 0; t < CT_R; ++t) {
+            double xr[CT_C];
+#pragma unroll
+            for (int q = 0; q < CT_C; ++q) xr[q] = panel[buf][t][b0 + q];
+#pragma unroll
+            for (int i = 0; i < CT_R; ++i) {
+                const double rij = Rs[(a0 + i) * LDR + j0 + t];
+#pragma unroll
+                for (int q = 0; q < CT_C; ++q) x[i][q] -= rij * xr[q];
+            }
+        }
+    };
+    // look-ahead as in the factorisation: the owner of panel P - 1 applies
+    // panel P to its rows and forms its own in the same phase
+    for (int P = npanel; P >= 1; --P) {
+        if (P < npanel && ty < P) apply_from(P, P & 1);
+        if (ty == P - 1) form_rows(P - 1, (P - 1) & 1);
+        __syncthreads();
     }
     TC* rinv = static_cast<TC*>(a.rinv);
 #pragma unroll
