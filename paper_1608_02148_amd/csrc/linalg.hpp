@@ -354,16 +354,26 @@ struct CholArgs {
 };
 
 constexpr int CHOL_MAX_L = RSVD_MAX_L;
-constexpr int CT_R = 4, CT_C = 8;                 // register tile per thread
-// The kernel instance for l <= LM: (LM / 4) x (LM / 8) threads cover LM x LM,
-// so small problems take small workgroups and more of them fit on a CU.
-template <int LM> constexpr int chol_threads() { return (LM / CT_R) * (LM / CT_C); }
+constexpr int CT_R = 4;                           // rows of the register tile per thread
+// Columns of the register tile: 12 in the l <= 96 instance, else 8; either
+// way a power of two of thread columns, and a 4-column panel in one lane.
+template <int LM> constexpr int chol_cols() { return LM == 96 ? 12 : 8; }
+// The kernel instance for l <= LM: (LM / 4) x (LM / cols) threads cover
+// LM x LM, so small problems take small workgroups and more of them fit on a
+// CU (the l <= 96 instance: 192 threads instead of the 512 of l <= 128).
+template <int LM> constexpr int chol_threads() { return (LM / CT_R) * (LM / chol_cols<LM>()); }
 static_assert(chol_threads<CHOL_MAX_L>() == 512, "tiles must cover the matrix");
+static_assert(chol_threads<96>() == 192, "tiles must cover the matrix");
 
-inline size_t chol_lds_bytes(int) { return 0; }
+// Dynamic LDS of R: l rounded up to whole 4-row panels, one padding column.
+inline size_t chol_r_lds(int l) {
+    const size_t lp = static_cast<size_t>(CT_R) * ((l + CT_R - 1) / CT_R);
+    return lp * (lp + 1) * sizeof(double);
+}
 
 template <typename TC, int LM>
 __device__ __forceinline__ void chol_body(const CholArgs& a) {
+    constexpr int CT_C = chol_cols<LM>();
     constexpr int CT_TX = LM / CT_C;              // thread columns (a power of two)
     constexpr int NT = chol_threads<LM>();
     const int l = a.l, tid = threadIdx.x;
@@ -454,21 +464,18 @@ __device__ __forceinline__ void chol_body(const CholArgs& a) {
                 // column for a dead pivot) and forms its own columns of the
                 // panel rows as R_P = X_PP^T G_P: no step-by-step chain.
                 const int dl = j0 / CT_C;
-                const bool hi = (j0 % CT_C) != 0;
-                double Gd[CT_R][CT_R], Rd[CT_R][CT_R], Xd[CT_R][CT_R], dv[CT_R] = {};
-                // (two static copies: a select between g[t][v] and
-                // g[t][4 + v] would become an indexed load from memory)
-                if (hi) {
+                const int off = j0 % CT_C;
+                double Gd[CT_R][CT_R] = {}, Rd[CT_R][CT_R], Xd[CT_R][CT_R], dv[CT_R] = {};
+                // (a static copy per offset: a select between g[t][o + v]
+                // would become an indexed load from memory)
 #pragma unroll
-                    for (int t = 0; t < CT_R; ++t)
+                for (int o = 0; o < CT_C; o += CT_R)
+                    if (off == o) {
 #pragma unroll
-                        for (int v = 0; v < CT_R; ++v) Gd[t][v] = (v >= t) ? from_lane(g[t][CT_R + v], dl) : 0.0;
-                } else {
+                        for (int t = 0; t < CT_R; ++t)
 #pragma unroll
-                    for (int t = 0; t < CT_R; ++t)
-#pragma unroll
-                        for (int v = 0; v < CT_R; ++v) Gd[t][v] = (v >= t) ? from_lane(g[t][v], dl) : 0.0;
-                }
+                            for (int v = 0; v < CT_R; ++v) Gd[t][v] = (v >= t) ? from_lane(g[t][o + v], dl) : 0.0;
+                    }
 #pragma unroll
                 for (int t = 0; t < CT_R; ++t)
 #pragma unroll
@@ -607,15 +614,17 @@ __device__ __forceinline__ void chol_body(const CholArgs& a) {
         }
         s_flags = f;
     }
-    // R goes to LDS (dynamic, LM x (LM + 1)): the inverse and the output read
-    // it there, so the factor's registers are free for the inverse's.
+    // R goes to LDS (dynamic, LP x (LP + 1) for l rounded up to LP = 4 npanel):
+    // the inverse and the output read it there, so the factor's registers are
+    // free for the inverse's.
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double* Rs = reinterpret_cast<double*>(smem_raw);
-    constexpr int LDR = LM + 1;
+    const int LP = CT_R * npanel, LDR = LP + 1;
 #pragma unroll
     for (int i = 0; i < CT_R; ++i)
 #pragma unroll
-        for (int q = 0; q < CT_C; ++q) Rs[(a0 + i) * LDR + b0 + q] = (b0 + q >= a0 + i) ? g[i][q] : 0.0;
+        for (int q = 0; q < CT_C; ++q)
+            if (a0 + i < LP && b0 + q < LP) Rs[(a0 + i) * LDR + b0 + q] = (b0 + q >= a0 + i) ? g[i][q] : 0.0;
     __syncthreads();
     // Inverse X = R^{-1} by panels from the bottom: the panel's group forms its
     // 4 rows as X_PP B_P (X_PP kept from the factorisation), publishes them, and
@@ -689,7 +698,7 @@ struct CholBody {
     typedef CholArgs Args;
     static constexpr int THREADS = chol_threads<LM>();
     static int blocks(const Args&) { return 1; }
-    static size_t lds(const Args&) { return static_cast<size_t>(LM) * (LM + 1) * sizeof(double); }
+    static size_t lds(const Args& a) { return chol_r_lds(a.l); }
     static __device__ void run(const Args& a, int) { chol_body<TC, LM>(a); }
 };
 
@@ -1058,6 +1067,9 @@ struct JacobiBody {
 
 template <typename TC, class Ex>
 hipError_t run_chol(Ex& ex, const CholArgs& a) {
+    // f32 results, 64 < l <= 96: the 192-thread instance (batch groups of
+    // f32 and bf16 problems never mix l <= 96 with l > 96)
+    if (sizeof(TC) == 4 && a.l > 64 && a.l <= 96) return ex.template run<CholBody<TC, 96>>(a);
     switch (small_lm(a.l)) {
         case 32: return ex.template run<CholBody<TC, 32>>(a);
         case 64: return ex.template run<CholBody<TC, 64>>(a);

@@ -42,6 +42,10 @@ struct Splits {
     int colsum;  // row split of the column-mean pass
 };
 
+// Gram matrices of a batch member: one split per 512 rows, at most 8 (the
+// Cholesky sums them).
+inline int batch_gram_split(int64_t rows) { return static_cast<int>(std::min<int64_t>(8, std::max<int64_t>(1, cdiv(rows, 512)))); }
+
 // Gram matrices: one split per CU at most, at least 64 rows per split (a
 // short n x l Gram then still spreads over most CUs).
 inline int gram_split(int64_t rows, int num_cu) {
@@ -132,6 +136,10 @@ struct Plan {
     int64_t m = 0, n = 0;
     int k = 0, p = 0, q = 0, l = 0, Lp = 0, kp = 0;
     int ncu = 0;        // compute units (the workgroups of one round of the streamed products)
+    // batch members: row splits of the m x l and n x l Gram matrices, whose
+    // partial sums the Cholesky adds itself (no extra step, so members with
+    // different splits still issue the same steps)
+    int fold_m = 1, fold_n = 1;
     int tile = 0;       // column class of the tall product tiles (tile_class of l)
     int var_nn = 0, var_tn = 0;   // tile variants of the NN / TN products (tile_variant_index)
     int qmax = 0;       // gated: power iterations issued for the whole batch group
@@ -209,6 +217,10 @@ inline Plan make_plan(int dtype, int64_t m, int64_t n, int k, const rsvd_params*
     P.qmax = P.q;
     P.gated = batch;
     P.sp = batch ? Splits{1, 1, 1, 1, 1} : make_splits(m, n, num_cu, dtype != RSVD_F64, P.l, P.Lp);
+    if (batch && P.Lp <= RSVD_MAX_L) {
+        P.fold_m = batch_gram_split(m);
+        P.fold_n = batch_gram_split(n);
+    }
     P.ncu = num_cu;
     const size_t cs = comp_size(dtype);
     Layout L;
@@ -218,7 +230,8 @@ inline Plan make_plan(int dtype, int64_t m, int64_t n, int k, const rsvd_params*
     P.Om = L.take(static_cast<size_t>(n) * P.Lp * cs);
     const size_t part_tn = std::max(P.sp.tn > 1 ? static_cast<size_t>(P.sp.tn) * n * P.Lp * cs : 0,
                                     P.sp.nn > 1 ? static_cast<size_t>(P.sp.nn) * m * P.Lp * cs : 0);
-    const size_t part_g = static_cast<size_t>(std::max(P.sp.gram_m, P.sp.gram_n)) * P.Lp * P.Lp * 8;
+    const size_t part_g = static_cast<size_t>(std::max({P.sp.gram_m, P.sp.gram_n, P.fold_m, P.fold_n})) * P.Lp *
+                          P.Lp * 8;
     P.part = L.take(std::max(part_tn, part_g));
     P.gram = L.take(static_cast<size_t>(P.Lp) * P.Lp * 8);
     P.rinv = L.take(static_cast<size_t>(P.Lp) * P.Lp * cs);

@@ -64,10 +64,13 @@ hipError_t orthonormalize(Ex& ex, int tile, TC* M, int64_t ldm, int64_t rows, in
         RSVD_TRY((gemm_plain<TC, TC, double, MODE_TN>(ex, 0, true, M, ldm, l, rows, M, ldm, l, part, Lp, S,
                                                       static_cast<int64_t>(Lp) * Lp, nullptr, skip, need, gate,
                                                       nullptr, 0, l > CHOL_MAX_L)));
-        if (S > 1) RSVD_TRY(reduce_step<double>(ex, part, S, static_cast<int64_t>(Lp) * Lp, Lp, l, l, gram, Lp,
-                                                skip, need, gate));
+        // (batch members: the Cholesky adds the S partial Gram matrices itself)
+        const bool reduce = S > 1 && Ex::kSingle;
+        if (reduce) RSVD_TRY(reduce_step<double>(ex, part, S, static_cast<int64_t>(Lp) * Lp, Lp, l, l, gram, Lp,
+                                                 skip, need, gate));
         CholArgs ca;
-        ca.part = (S > 1) ? gram : part; ca.S = 1; ca.part_stride = 0; ca.ldp = Lp;
+        ca.part = reduce ? gram : part; ca.S = reduce ? 1 : S;
+        ca.part_stride = static_cast<int64_t>(Lp) * Lp; ca.ldp = Lp;
         ca.l = l; ca.mrows = rows; ca.rinv = rinv; ca.ldr = Lp;
         ca.rout = rfac ? rfac + static_cast<size_t>(pass - 1) * l * l : nullptr;
         ca.status = status; ca.pass = pass; ca.skip_unless_pending = conditional; ca.adaptive = adaptive;
@@ -185,6 +188,7 @@ hipError_t solve_steps(Ex& ex, rsvd_handle_t prof, const Plan& P, const TA* A, i
     TC* partc = at<TC>(work, P.part);
     double* partd = at<double>(work, P.part);
     double* gram = at<double>(work, P.gram);
+    const int gsm = Ex::kSingle ? P.sp.gram_m : P.fold_m, gsn = Ex::kSingle ? P.sp.gram_n : P.fold_n;
     TC* rinv = at<TC>(work, P.rinv);
     double* racc = at<double>(work, P.racc);
     double* sigma = at<double>(work, P.sigma);
@@ -313,18 +317,18 @@ hipError_t solve_steps(Ex& ex, rsvd_handle_t prof, const Plan& P, const TA* A, i
         if (lu)
             RSVD_TRY(lu_normalize<TC>(ex, tile, Y, Lp, m, l, Lp, lucand, lucnt, rinv, status));
         else
-            RSVD_TRY(orthonormalize<TC>(ex, tile, Y, Lp, m, l, Lp, P.sp.gram_m, partd, gram, rinv, nullptr, status,
+            RSVD_TRY(orthonormalize<TC>(ex, tile, Y, Lp, m, l, Lp, gsm, partd, gram, rinv, nullptr, status,
                                         true, act, cholx, qtmp));
         RSVD_TRY(aty(Z, early, act));
         if (lu)
             RSVD_TRY(lu_normalize<TC>(ex, tile, Z, Lp, n, l, Lp, lucand, lucnt, rinv, status));
         else
-            RSVD_TRY(orthonormalize<TC>(ex, tile, Z, Lp, n, l, Lp, P.sp.gram_n, partd, gram, rinv, nullptr, status,
+            RSVD_TRY(orthonormalize<TC>(ex, tile, Z, Lp, n, l, Lp, gsn, partd, gram, rinv, nullptr, status,
                                         true, act, cholx, qtmp));
         RSVD_TRY(ax_step(Z, it == P.q - 1, run_bit, last_bit));
     }
     // Alg. rqb: Q = qr(Y); B^T = A^T Q.
-    RSVD_TRY(orthonormalize<TC>(ex, tile, Y, Lp, m, l, Lp, P.sp.gram_m, partd, gram, rinv, nullptr, status, false,
+    RSVD_TRY(orthonormalize<TC>(ex, tile, Y, Lp, m, l, Lp, gsm, partd, gram, rinv, nullptr, status, false,
                                 Gate{}, cholx, qtmp));
     RSVD_TRY(aty(Z, late, Gate{}));
     if (o.bt) {   // the QB decomposition's B is the product (ID / CUR work on it)
@@ -334,7 +338,7 @@ hipError_t solve_steps(Ex& ex, rsvd_handle_t prof, const Plan& P, const TA* A, i
         return hipSuccess;
     }
     // svd(B): B^T = Q_b R_b (Q_b overwrites Z), R_b = W S J^T by Jacobi.
-    RSVD_TRY(orthonormalize<TC>(ex, tile, Z, Lp, n, l, Lp, P.sp.gram_n, partd, gram, rinv, racc, status, false,
+    RSVD_TRY(orthonormalize<TC>(ex, tile, Z, Lp, n, l, Lp, gsn, partd, gram, rinv, racc, status, false,
                                 Gate{}, cholx, qtmp));
     racc += 3 * static_cast<size_t>(l) * l;       // R_b = R3 R2 R1
     {

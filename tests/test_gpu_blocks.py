@@ -94,7 +94,8 @@ def test_gemm_random_f64_accuracy_and_strided_input(gpu_lib):
 
 
 @pytest.mark.parametrize("dt,tol", [("f64", 1e-13), ("f32", 2e-6)])
-@pytest.mark.parametrize("m,c", [(5000, 30), (1000, 128), (33, 17), (20000, 100)])
+@pytest.mark.parametrize("m,c", [(5000, 30), (1000, 128), (33, 17), (20000, 100), (3000, 73), (4000, 96), (777, 65),
+                                 (2000, 81)])
 def test_orthonormalize_matches_householder(gpu_lib, dt, tol, m, c):
     from paper_1608_02148_amd import api
     rng = np.random.default_rng(m + c)
