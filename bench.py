@@ -717,7 +717,8 @@ def main():
             # the streamed-A kernel (A read straight into the matrix cores); the
             # event-timed launch covers the packing of X and the product
             ncb = 8 if l <= 128 else 14
-            kern = f"single_kernel<StreamBody<float, {mode}, {arith}, {ncb}, 1, false, false>>"
+            wps = 2 if mode == 0 and os.environ.get("RSVD_STREAM_WPS") != "1" else 1
+            kern = f"single_kernel<StreamBody<float, {mode}, {arith}, {ncb}, {wps}, false, false>>"
         elif bound == "mfma":
             var = api_variants[6 * mode + 5]
             shape = {0: "4, 4, 2, 2", 1: "4, 2, 2, 4", 2: "2, 2, 4, 4"}[var]

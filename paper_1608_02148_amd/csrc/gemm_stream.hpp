@@ -10,8 +10,12 @@
 // MFMAs.  The accumulators (up to 224 registers) live in the AGPR file; the
 // next chunk of A is loaded into registers while the current one is
 // multiplied (one chunk ahead), and X's next chunk is staged through
-// registers into the other of two LDS buffers.  (CS > 1 splits the columns
-// over CS groups of four waves; not launched, see stream_fits.)
+// registers into the other of two LDS buffers.  WPS = 2 (A X only; in A^T Q
+// a lane's four-column loads fix four row blocks per wave) runs two waves per
+// SIMD instead: eight waves of 32 rows, two row blocks each, half the
+// registers per wave, so that while one wave waits for a load, a barrier or
+// an LDS read the other's MFMAs keep the matrix core busy; each X fragment
+// then feeds two MFMAs.
 //
 // Lane (r, g) (r = lane & 15, g = lane >> 4) owns the k-run [k0 + LK g,
 // k0 + LK (g + 1)) of each chunk of KC = 4 LK reduction elements; substep s of
@@ -48,7 +52,7 @@ namespace rsvd {
 
 typedef __bf16 s8bf __attribute__((ext_vector_type(8)));
 
-template <typename TA, int MODE, int ARITH, int NCB, int CS = 1, bool CENT = false, bool MU = false>
+template <typename TA, int MODE, int ARITH, int NCB, int WPS = 1, bool CENT = false, bool MU = false>
 struct StreamTile {
     static constexpr bool BF = ARITH != 0;
     static constexpr bool SPLIT = ARITH == 2;
@@ -61,11 +65,11 @@ struct StreamTile {
     static constexpr int LK = (BF || NCB <= 8) ? 16 : 8;
     static constexpr int KC = 4 * LK;               // chunk extent
     static constexpr int SUB = LK / V;              // MFMA substeps per chunk
-    static constexpr int RB = 4;                    // MFMA row blocks per wave
-    static constexpr int WAVES = 4 * CS;            // four row strips x CS column groups
+    static constexpr int RB = 4 / WPS;              // MFMA row blocks per wave
+    static constexpr int WAVES = 4 * WPS;           // row strips, WPS per SIMD
     static constexpr int NT = 64 * WAVES;
-    static constexpr int TROWS = 4 * 16 * RB;       // output rows per tile
-    static constexpr int NC = 16 * NCB * CS;        // output columns per tile
+    static constexpr int TROWS = WAVES * 16 * RB;   // output rows per tile (256)
+    static constexpr int NC = 16 * NCB;             // output columns per tile
     static constexpr int ESZ = BF ? 2 : 4;          // staged X element bytes
     static constexpr int SX = KC + 16 / ESZ;        // LDS column stride: 16 bytes past a multiple of 128
     static constexpr int XPL = SPLIT ? 2 : 1;
@@ -79,6 +83,8 @@ struct StreamTile {
                                                      : LK * 4 * static_cast<int>(sizeof(TA)) / 4;
     static_assert((SX * ESZ) % 128 == 16, "LDS column stride");
     static_assert(!CENT || (SPLIT && sizeof(TA) == 2 && MU), "CENT: split products of centred bf16-stored A");
+    static_assert((WPS == 1 || WPS == 2) && TROWS == 256, "two row-strip layouts, 256 rows per tile");
+    static_assert(WPS == 1 || MODE == MODE_NN, "two waves per SIMD: A X only");
 };
 
 template <typename TA>
@@ -99,10 +105,10 @@ __device__ __forceinline__ float bf16_round(float x) {
 // One (tile, reduction range) of the product: output rows tile * TROWS ..
 // of the tile, summed over k in [kbeg, kend), written to out (row r at
 // out + (r - row0) ldo).
-template <typename TA, int MODE, int ARITH, int NCB, int CS, bool CENT, bool MU>
+template <typename TA, int MODE, int ARITH, int NCB, int WPS, bool CENT, bool MU>
 __device__ __forceinline__ void gemm_stream_body(const GemmArgs<TA, float, float>& g, int tile, int64_t kbeg,
                                                  int64_t kend, float* out, int64_t row0, int64_t ldo) {
-    typedef StreamTile<TA, MODE, ARITH, NCB, CS, CENT, MU> T;
+    typedef StreamTile<TA, MODE, ARITH, NCB, WPS, CENT, MU> T;
     constexpr int LK = T::LK, KC = T::KC, SUB = T::SUB, RB = T::RB, SX = T::SX;
     constexpr int AW = T::A_WORDS;
     if (g.skip_flag && ((*g.skip_flag & g.skip_mask) == 0u)) return;
@@ -112,13 +118,13 @@ __device__ __forceinline__ void gemm_stream_body(const GemmArgs<TA, float, float
     // gives the MFMAs their all-VGPR form, which caps the wave at 256 registers
     // and spills; with it the accumulators live in the AGPR file and the
     // operands, staging and addresses in the VGPR file (512 in all at one wave
-    // per SIMD).
+    // per SIMD, 256 at two).
     asm volatile("" ::: "a0");
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int lr = lane & 15, lg = lane >> 4;
-    const int strip = wave & 3, cb0 = (wave >> 2) * NCB;     // row strip, first column block
+    const int strip = wave, cb0 = 0;                      // row strip, first column block
     const int64_t w0 = static_cast<int64_t>(tile) * T::TROWS + static_cast<int64_t>(strip) * 16 * RB;
 
     // ---- A: raw words of one chunk
@@ -448,9 +454,9 @@ __host__ __device__ inline int64_t tail_first(int64_t pair, int64_t leftover, in
     return pair < r ? pair * (q + 1) : r * (q + 1) + (pair - r) * q;
 }
 
-template <typename TA, int MODE, int ARITH, int NCB, int CS = 1, bool CENT = false, bool MU = false>
+template <typename TA, int MODE, int ARITH, int NCB, int WPS = 1, bool CENT = false, bool MU = false>
 struct StreamBody {
-    typedef StreamTile<TA, MODE, ARITH, NCB, CS, CENT, MU> T;
+    typedef StreamTile<TA, MODE, ARITH, NCB, WPS, CENT, MU> T;
     typedef GemmArgs<TA, float, float> Args;
     static constexpr int THREADS = T::NT;
     static constexpr int TROWS = T::TROWS, KC = T::KC;
@@ -493,7 +499,7 @@ struct StreamBody {
             row0 = (pair % nt) * T::TROWS;
             ldo = g.ld_slot;
         }
-        gemm_stream_body<TA, MODE, ARITH, NCB, CS, CENT, MU>(g, static_cast<int>(pair % nt), kbeg, kend, out, row0,
+        gemm_stream_body<TA, MODE, ARITH, NCB, WPS, CENT, MU>(g, static_cast<int>(pair % nt), kbeg, kend, out, row0,
                                                              ldo);
     }
 };

@@ -269,15 +269,25 @@ inline bool streamed_products_enabled() {
 // would spill).
 inline int stream_cols(int ncols) { return ncols <= 128 ? 128 : 224; }
 
-// Variants that fit one wave per SIMD without spilling (a compile-time
-// record of the register counts; the 2-group variants, CS = 2 with two waves
-// per SIMD at half the columns each, measured no faster at C2's shapes and
-// spill at 224 columns, so they are not launched).
-template <typename TA, int MODE, int ARITH, int NCB, int CS, bool CENT, bool MU>
+// Variants that fit their registers without spilling (a compile-time record
+// of the register counts): one wave per SIMD (WPS = 1, 512 registers a wave)
+// for every product, two per SIMD (WPS = 2, 256 registers a wave) for A X
+// without column means.
+template <typename TA, int MODE, int ARITH, int NCB, int WPS, bool CENT, bool MU>
 constexpr bool stream_fits() {
-    if (CS != 1) return false;
+    if (WPS == 2) return MODE == MODE_NN && !MU && !CENT;
     if (NCB == 8) return !(MODE == MODE_TN && ARITH == 2 && sizeof(TA) == 4 && MU);
     return !MU && !CENT && (ARITH == 0 || sizeof(TA) == 2);
+}
+
+// Waves per SIMD of the A X kernels: 2 (RSVD_STREAM_WPS=1 forces the
+// one-wave layout; C2 A X 1.43 -> 1.35 ms, C3 bf16 2.82 -> 2.65 ms with two).
+inline int stream_wps() {
+    static const int w = [] {
+        const char* v = std::getenv("RSVD_STREAM_WPS");
+        return (v && std::strcmp(v, "1") == 0) ? 1 : 2;
+    }();
+    return w;
 }
 
 // Chunk of the reduction of the streamed kernel that stream_ncb launches.
@@ -287,6 +297,12 @@ static_assert(StreamTile<float, MODE_NN, 0, 8>::KC == 64 && StreamTile<float, MO
 
 template <typename TA, int MODE, int ARITH, bool CENT, bool MU, class Ex>
 hipError_t stream_ncb(Ex& ex, const GemmArgs<TA, float, float>& g) {
+    if constexpr (MODE == MODE_NN && !CENT && !MU) {
+        if (stream_wps() == 2) {
+            if (g.ncols <= 128) return ex.template run<StreamBody<TA, MODE, ARITH, 8, 2, CENT, MU>>(g);
+            return ex.template run<StreamBody<TA, MODE, ARITH, 14, 2, CENT, MU>>(g);
+        }
+    }
     if (g.ncols <= 128) {
         if constexpr (stream_fits<TA, MODE, ARITH, 8, 1, CENT, MU>())
             return ex.template run<StreamBody<TA, MODE, ARITH, 8, 1, CENT, MU>>(g);
