@@ -10,12 +10,11 @@
 // MFMAs.  The accumulators (up to 224 registers) live in the AGPR file; the
 // next chunk of A is loaded into registers while the current one is
 // multiplied (one chunk ahead), and X's next chunk is staged through
-// registers into the other of two LDS buffers.  WPS = 2 (A X only; in A^T Q
-// a lane's four-column loads fix four row blocks per wave) runs two waves per
+// registers into the other of two LDS buffers.  WPS = 2 runs two waves per
 // SIMD instead: eight waves of 32 rows, two row blocks each, half the
 // registers per wave, so that while one wave waits for a load, a barrier or
 // an LDS read the other's MFMAs keep the matrix core busy; each X fragment
-// then feeds two MFMAs.
+// then feeds two MFMAs (A^T Q: a lane then loads two columns per row of A).
 //
 // Lane (r, g) (r = lane & 15, g = lane >> 4) owns the k-run [k0 + LK g,
 // k0 + LK (g + 1)) of each chunk of KC = 4 LK reduction elements; substep s of
@@ -28,12 +27,13 @@
 //   NN: lane (r, g) loads LK consecutive elements of row r0 + 16 i + r for each
 //       of the wave's four row blocks i (32 or 64 contiguous bytes: whole cache
 //       lines per row and chunk).
-//   TN: the output rows are columns of A.  Lane (i, g) loads four consecutive
-//       columns c0 + 4 i .. c0 + 4 i + 3 of each of its LK rows of A (16 lanes
-//       read 64 or 128 contiguous bytes of a row); MFMA row block e then takes
-//       column c0 + 4 i + e as its row i, so the wave's 64 output rows are the
-//       columns c0 + 16 g + 4 v + e of accumulator element v of block e.  For
-//       bf16 the lane transposes its LK x 4 block in registers into k-octets.
+//   TN: the output rows are columns of A.  Lane (i, g) loads RB consecutive
+//       columns c0 + RB i .. c0 + RB i + RB - 1 of each of its LK rows of A (16
+//       lanes read 32 to 128 contiguous bytes of a row); MFMA row block e then
+//       takes column c0 + RB i + e as its row i, so the wave's 16 RB output rows
+//       are the columns c0 + RB (4 g + v) + e of accumulator element v of block
+//       e.  For bf16 the lane transposes its LK x RB block in registers into
+//       k-octets.
 //
 // Arithmetic (as in the LDS-staged tiles): 0 = f32 MFMA (bf16-stored A widened
 // exactly), 1 = bf16 MFMA on A and X rounded to bf16, 2 = split bf16: X = X_hi
@@ -79,12 +79,12 @@ struct StreamTile {
     static constexpr size_t STAGE = XPL * PLANE;    // elements
     static constexpr size_t LDS_BYTES = 2 * STAGE * ESZ;
     // raw A words per lane and chunk (32-bit registers)
-    static constexpr int A_WORDS = (MODE == MODE_NN) ? RB * LK * static_cast<int>(sizeof(TA)) / 4
-                                                     : LK * 4 * static_cast<int>(sizeof(TA)) / 4;
+    static constexpr int A_WORDS = RB * LK * static_cast<int>(sizeof(TA)) / 4;
+    // TN: words per row of A of a lane's RB consecutive columns
+    static constexpr int TW = RB * static_cast<int>(sizeof(TA)) / 4;
     static_assert((SX * ESZ) % 128 == 16, "LDS column stride");
     static_assert(!CENT || (SPLIT && sizeof(TA) == 2 && MU), "CENT: split products of centred bf16-stored A");
     static_assert((WPS == 1 || WPS == 2) && TROWS == 256, "two row-strip layouts, 256 rows per tile");
-    static_assert(WPS == 1 || MODE == MODE_NN, "two waves per SIMD: A X only");
 };
 
 template <typename TA>
@@ -160,23 +160,25 @@ __device__ __forceinline__ void gemm_stream_body(const GemmArgs<TA, float, float
                 }
             }
         } else {
-            constexpr int WPR = sizeof(TA);                   // words per row of 4 columns (16 or 8 bytes)
-            // columns past the end (whole groups of 4: rows % 4 == 0) read
+            constexpr int WPR = T::TW;                      // words per row of RB columns (4 to 16 bytes)
+            // columns past the end (whole groups of RB: rows % 4 == 0) read
             // column 0 instead and are never stored
-            const int64_t c = (w0 + 4 * lr < g.rows) ? w0 + 4 * lr : 0;
+            const int64_t c = (w0 + RB * lr < g.rows) ? w0 + RB * lr : 0;
 #pragma unroll
             for (int t = 0; t < LK; ++t) {
                 const int64_t k = k0 + LK * lg + t;
                 const TA* p = g.A + k * g.lda + c;
                 if (full || k < kend) {
-                    if constexpr (sizeof(TA) == 4) {
+                    if constexpr (WPR == 4) {
                         const u32x4 x = *reinterpret_cast<const u32x4*>(p);
 #pragma unroll
                         for (int d = 0; d < 4; ++d) w[t * WPR + d] = x[d];
-                    } else {
+                    } else if constexpr (WPR == 2) {
                         const u32x2 x = *reinterpret_cast<const u32x2*>(p);
                         w[t * WPR] = x[0];
                         w[t * WPR + 1] = x[1];
+                    } else {
+                        w[t] = *reinterpret_cast<const uint32_t*>(p);
                     }
                 } else {
 #pragma unroll
@@ -269,7 +271,7 @@ __device__ __forceinline__ void gemm_stream_body(const GemmArgs<TA, float, float
                         const float x = word_elem<TA>(w + i * (LK * sizeof(TA) / 4), t);
                         a[i][t] = MU ? mu_nn(k0, t, x, full) : x;
                     } else {
-                        const float x = word_elem<TA>(w + t * sizeof(TA), i);
+                        const float x = word_elem<TA>(w + t * T::TW, i);
                         a[i][t] = MU ? mu_tn(k0, t, i, x, full) : x;
                     }
                 }
@@ -316,7 +318,7 @@ __device__ __forceinline__ void gemm_stream_body(const GemmArgs<TA, float, float
                         ah[i][s] = __builtin_bit_cast(s8bf, q);
                     }
             } else if constexpr (RAWTN) {
-                // bf16-stored A, TN: transpose the lane's 16 x 4 block of 16-bit
+                // bf16-stored A, TN: transpose the lane's 16 x RB block of 16-bit
                 // words into k-octets (row pairs of one column per word)
 #pragma unroll
                 for (int i = 0; i < RB; ++i)
@@ -325,8 +327,8 @@ __device__ __forceinline__ void gemm_stream_body(const GemmArgs<TA, float, float
                         u32x4 q;
 #pragma unroll
                         for (int d = 0; d < 4; ++d) {
-                            const uint32_t lo = w[(8 * s + 2 * d) * 2 + (i >> 1)];
-                            const uint32_t hi = w[(8 * s + 2 * d + 1) * 2 + (i >> 1)];
+                            const uint32_t lo = w[(8 * s + 2 * d) * T::TW + (i >> 1)];
+                            const uint32_t hi = w[(8 * s + 2 * d + 1) * T::TW + (i >> 1)];
                             q[d] = (i & 1) ? ((lo >> 16) | (hi & 0xFFFF0000u)) : ((lo & 0xFFFFu) | (hi << 16));
                         }
                         ah[i][s] = __builtin_bit_cast(s8bf, q);
@@ -349,7 +351,7 @@ __device__ __forceinline__ void gemm_stream_body(const GemmArgs<TA, float, float
                                     const float v = word_elem<TA>(w + i * (LK * sizeof(TA) / 4), kk);
                                     x[h] = MU ? mu_nn(k0, kk, v, full) : v;
                                 } else {
-                                    const float v = word_elem<TA>(w + kk * sizeof(TA), i);
+                                    const float v = word_elem<TA>(w + kk * T::TW, i);
                                     x[h] = MU ? mu_tn(k0, kk, i, v, full) : v;
                                 }
                             }
@@ -424,7 +426,7 @@ __device__ __forceinline__ void gemm_stream_body(const GemmArgs<TA, float, float
             if (c >= g.ncols) continue;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int64_t r = (MODE == MODE_NN) ? w0 + 16 * i + 4 * lg + v : w0 + 16 * lg + 4 * v + i;
+                const int64_t r = (MODE == MODE_NN) ? w0 + 16 * i + 4 * lg + v : w0 + RB * (4 * lg + v) + i;
                 if (r < g.rows) out[(r - row0) * ldo + c] = acc[i][j][v];
             }
         }

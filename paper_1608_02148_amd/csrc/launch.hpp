@@ -271,17 +271,26 @@ inline int stream_cols(int ncols) { return ncols <= 128 ? 128 : 224; }
 
 // Variants that fit their registers without spilling (a compile-time record
 // of the register counts): one wave per SIMD (WPS = 1, 512 registers a wave)
-// for every product, two per SIMD (WPS = 2, 256 registers a wave) for A X
-// without column means.
+// for every product, two per SIMD (WPS = 2, 256 registers a wave) for the
+// products without column means.
 template <typename TA, int MODE, int ARITH, int NCB, int WPS, bool CENT, bool MU>
 constexpr bool stream_fits() {
-    if (WPS == 2) return MODE == MODE_NN && !MU && !CENT;
+    if (WPS == 2) {
+        if (MU || CENT) return false;
+        if (MODE == MODE_NN) return true;
+        // A^T Q (a lane loads half as many columns per row of A): faster at
+        // two waves only with f32 arithmetic on bf16-stored A (C3 13.9 -> 13.5
+        // ms; f32 A at C2 1.36 -> 1.39 ms, bf16 arithmetic unchanged, the split
+        // one spills at 224 columns)
+        return sizeof(TA) == 2 && ARITH == 0;
+    }
     if (NCB == 8) return !(MODE == MODE_TN && ARITH == 2 && sizeof(TA) == 4 && MU);
     return !MU && !CENT && (ARITH == 0 || sizeof(TA) == 2);
 }
 
-// Waves per SIMD of the A X kernels: 2 (RSVD_STREAM_WPS=1 forces the
-// one-wave layout; C2 A X 1.43 -> 1.35 ms, C3 bf16 2.82 -> 2.65 ms with two).
+// Waves per SIMD of the streamed kernels without column means: 2
+// (RSVD_STREAM_WPS=1 forces the one-wave layout; A X at C2 1.43 -> 1.35 ms,
+// C3 bf16 2.82 -> 2.65 ms with two).
 inline int stream_wps() {
     static const int w = [] {
         const char* v = std::getenv("RSVD_STREAM_WPS");
@@ -297,16 +306,15 @@ static_assert(StreamTile<float, MODE_NN, 0, 8>::KC == 64 && StreamTile<float, MO
 
 template <typename TA, int MODE, int ARITH, bool CENT, bool MU, class Ex>
 hipError_t stream_ncb(Ex& ex, const GemmArgs<TA, float, float>& g) {
-    if constexpr (MODE == MODE_NN && !CENT && !MU) {
-        if (stream_wps() == 2) {
-            if (g.ncols <= 128) return ex.template run<StreamBody<TA, MODE, ARITH, 8, 2, CENT, MU>>(g);
-            return ex.template run<StreamBody<TA, MODE, ARITH, 14, 2, CENT, MU>>(g);
-        }
-    }
+    const bool two = stream_wps() == 2;
     if (g.ncols <= 128) {
+        if constexpr (stream_fits<TA, MODE, ARITH, 8, 2, CENT, MU>())
+            if (two) return ex.template run<StreamBody<TA, MODE, ARITH, 8, 2, CENT, MU>>(g);
         if constexpr (stream_fits<TA, MODE, ARITH, 8, 1, CENT, MU>())
             return ex.template run<StreamBody<TA, MODE, ARITH, 8, 1, CENT, MU>>(g);
     } else {
+        if constexpr (stream_fits<TA, MODE, ARITH, 14, 2, CENT, MU>())
+            if (two) return ex.template run<StreamBody<TA, MODE, ARITH, 14, 2, CENT, MU>>(g);
         if constexpr (stream_fits<TA, MODE, ARITH, 14, 1, CENT, MU>())
             return ex.template run<StreamBody<TA, MODE, ARITH, 14, 1, CENT, MU>>(g);
     }
