@@ -12,6 +12,7 @@
 #pragma once
 
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "common.hpp"
@@ -34,6 +35,19 @@ __device__ __forceinline__ int xcd_block(int b, int total) {
 
 template <class Body>
 __global__ __launch_bounds__(Body::THREADS) void single_kernel(typename Body::Args a) {
+    Body::run(a, xcd_block(blockIdx.x, gridDim.x));
+}
+
+// Bodies that run two workgroups per CU at two waves per SIMD declare
+// WAVES_PER_SIMD = 2; their kernel is compiled for that register budget.
+template <class Body, class = void> struct waves_per_simd { static constexpr int value = 1; };
+template <class Body>
+struct waves_per_simd<Body, std::void_t<decltype(Body::WAVES_PER_SIMD)>> {
+    static constexpr int value = Body::WAVES_PER_SIMD;
+};
+
+template <class Body>
+__global__ __launch_bounds__(Body::THREADS, 2) void single_kernel_w2(typename Body::Args a) {
     Body::run(a, xcd_block(blockIdx.x, gridDim.x));
 }
 
@@ -66,12 +80,21 @@ struct SingleExec {
         if (nb <= 0) return hipSuccess;
         const size_t lds = Body::lds(a);
         static size_t raised = 0;
-        if (lds > raised) {
-            hipError_t e = raise_lds_limit(single_kernel<Body>, lds);
-            if (e != hipSuccess) return e;
-            raised = lds;
+        if constexpr (waves_per_simd<Body>::value == 2) {
+            if (lds > raised) {
+                hipError_t e = raise_lds_limit(single_kernel_w2<Body>, lds);
+                if (e != hipSuccess) return e;
+                raised = lds;
+            }
+            hipLaunchKernelGGL(single_kernel_w2<Body>, dim3(nb), dim3(Body::THREADS), lds, stream, a);
+        } else {
+            if (lds > raised) {
+                hipError_t e = raise_lds_limit(single_kernel<Body>, lds);
+                if (e != hipSuccess) return e;
+                raised = lds;
+            }
+            hipLaunchKernelGGL(single_kernel<Body>, dim3(nb), dim3(Body::THREADS), lds, stream, a);
         }
-        hipLaunchKernelGGL(single_kernel<Body>, dim3(nb), dim3(Body::THREADS), lds, stream, a);
         return hipGetLastError();
     }
 };

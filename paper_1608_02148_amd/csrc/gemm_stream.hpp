@@ -15,6 +15,8 @@
 // registers per wave, so that while one wave waits for a load, a barrier or
 // an LDS read the other's MFMAs keep the matrix core busy; each X fragment
 // then feeds two MFMAs (A^T Q: a lane then loads two columns per row of A).
+// WPS = 3 splits those eight waves into two workgroups of four (128-row
+// tiles, two per CU), whose barriers and X stages are independent.
 //
 // Lane (r, g) (r = lane & 15, g = lane >> 4) owns the k-run [k0 + LK g,
 // k0 + LK (g + 1)) of each chunk of KC = 4 LK reduction elements; substep s of
@@ -65,10 +67,13 @@ struct StreamTile {
     static constexpr int LK = (BF || NCB <= 8) ? 16 : 8;
     static constexpr int KC = 4 * LK;               // chunk extent
     static constexpr int SUB = LK / V;              // MFMA substeps per chunk
-    static constexpr int RB = 4 / WPS;              // MFMA row blocks per wave
-    static constexpr int WAVES = 4 * WPS;           // row strips, WPS per SIMD
+    // layouts: WPS = 1: four waves of four row blocks (one per SIMD); 2: eight
+    // waves of two (two per SIMD); 3: four waves of two in 128-row tiles, two
+    // workgroups per CU
+    static constexpr int RB = WPS == 1 ? 4 : 2;     // MFMA row blocks per wave
+    static constexpr int WAVES = WPS == 2 ? 8 : 4;  // row strips
     static constexpr int NT = 64 * WAVES;
-    static constexpr int TROWS = WAVES * 16 * RB;   // output rows per tile (256)
+    static constexpr int TROWS = WAVES * 16 * RB;   // output rows per tile
     static constexpr int NC = 16 * NCB;             // output columns per tile
     static constexpr int ESZ = BF ? 2 : 4;          // staged X element bytes
     static constexpr int SX = KC + 16 / ESZ;        // LDS column stride: 16 bytes past a multiple of 128
@@ -84,7 +89,7 @@ struct StreamTile {
     static constexpr int TW = RB * static_cast<int>(sizeof(TA)) / 4;
     static_assert((SX * ESZ) % 128 == 16, "LDS column stride");
     static_assert(!CENT || (SPLIT && sizeof(TA) == 2 && MU), "CENT: split products of centred bf16-stored A");
-    static_assert((WPS == 1 || WPS == 2) && TROWS == 256, "two row-strip layouts, 256 rows per tile");
+    static_assert(WPS >= 1 && WPS <= 3 && TROWS == (WPS == 3 ? 128 : 256), "row-strip layouts");
 };
 
 template <typename TA>
@@ -461,6 +466,7 @@ struct StreamBody {
     typedef StreamTile<TA, MODE, ARITH, NCB, WPS, CENT, MU> T;
     typedef GemmArgs<TA, float, float> Args;
     static constexpr int THREADS = T::NT;
+    static constexpr int WAVES_PER_SIMD = WPS == 3 ? 2 : 1;   // register budget of the launch
     static constexpr int TROWS = T::TROWS, KC = T::KC;
     __host__ __device__ static int tiles(const Args& g) { return static_cast<int>(cdiv(g.rows, T::TROWS)); }
     __host__ __device__ static int64_t pairs(const Args& g) { return static_cast<int64_t>(tiles(g)) * g.splits; }

@@ -275,6 +275,11 @@ inline int stream_cols(int ncols) { return ncols <= 128 ? 128 : 224; }
 // products without column means.
 template <typename TA, int MODE, int ARITH, int NCB, int WPS, bool CENT, bool MU>
 constexpr bool stream_fits() {
+    // two workgroups of 128 rows per CU: measured faster only for A X of
+    // bf16-stored A at 224 columns (C3 bf16 2.69 -> 2.57 ms, f32 arithmetic
+    // 13.66 -> 13.50 ms; C2 f32 A X 1.34 -> 1.39 ms, A^T Q slower as well, the
+    // split arithmetic spills)
+    if (WPS == 3) return !MU && !CENT && MODE == MODE_NN && NCB == 14 && sizeof(TA) == 2 && ARITH != 2;
     if (WPS == 2) {
         if (MU || CENT) return false;
         if (MODE == MODE_NN) return true;
@@ -288,15 +293,30 @@ constexpr bool stream_fits() {
     return !MU && !CENT && (ARITH == 0 || sizeof(TA) == 2);
 }
 
-// Waves per SIMD of the streamed kernels without column means: 2
-// (RSVD_STREAM_WPS=1 forces the one-wave layout; A X at C2 1.43 -> 1.35 ms,
-// C3 bf16 2.82 -> 2.65 ms with two).
+// Layout limit of the streamed kernels: RSVD_STREAM_WPS=1 keeps one wave per
+// SIMD, =2 allows the eight-wave layout but not the 128-row one, otherwise
+// every layout that fits (A X at C2 1.43 -> 1.35 ms, C3 bf16 2.82 -> 2.57 ms
+// against one wave per SIMD).
 inline int stream_wps() {
     static const int w = [] {
         const char* v = std::getenv("RSVD_STREAM_WPS");
-        return (v && std::strcmp(v, "1") == 0) ? 1 : 2;
+        if (v && std::strcmp(v, "1") == 0) return 1;
+        if (v && std::strcmp(v, "2") == 0) return 2;
+        return 3;
     }();
     return w;
+}
+
+// The layout stream_ncb launches for these arguments.
+template <typename TA, int MODE, int ARITH, bool CENT, bool MU>
+int stream_lay(int ncols) {
+    const int w = stream_wps();
+    const bool wide = ncols > 128;
+    if (w >= 3 && (wide ? stream_fits<TA, MODE, ARITH, 14, 3, CENT, MU>() : stream_fits<TA, MODE, ARITH, 8, 3, CENT, MU>()))
+        return 3;
+    if (w >= 2 && (wide ? stream_fits<TA, MODE, ARITH, 14, 2, CENT, MU>() : stream_fits<TA, MODE, ARITH, 8, 2, CENT, MU>()))
+        return 2;
+    return 1;
 }
 
 // Chunk of the reduction of the streamed kernel that stream_ncb launches.
@@ -306,19 +326,35 @@ static_assert(StreamTile<float, MODE_NN, 0, 8>::KC == 64 && StreamTile<float, MO
 
 template <typename TA, int MODE, int ARITH, bool CENT, bool MU, class Ex>
 hipError_t stream_ncb(Ex& ex, const GemmArgs<TA, float, float>& g) {
-    const bool two = stream_wps() == 2;
+    const int lay = stream_lay<TA, MODE, ARITH, CENT, MU>(g.ncols);
     if (g.ncols <= 128) {
+        if constexpr (stream_fits<TA, MODE, ARITH, 8, 3, CENT, MU>())
+            if (lay == 3) return ex.template run<StreamBody<TA, MODE, ARITH, 8, 3, CENT, MU>>(g);
         if constexpr (stream_fits<TA, MODE, ARITH, 8, 2, CENT, MU>())
-            if (two) return ex.template run<StreamBody<TA, MODE, ARITH, 8, 2, CENT, MU>>(g);
+            if (lay == 2) return ex.template run<StreamBody<TA, MODE, ARITH, 8, 2, CENT, MU>>(g);
         if constexpr (stream_fits<TA, MODE, ARITH, 8, 1, CENT, MU>())
             return ex.template run<StreamBody<TA, MODE, ARITH, 8, 1, CENT, MU>>(g);
     } else {
+        if constexpr (stream_fits<TA, MODE, ARITH, 14, 3, CENT, MU>())
+            if (lay == 3) return ex.template run<StreamBody<TA, MODE, ARITH, 14, 3, CENT, MU>>(g);
         if constexpr (stream_fits<TA, MODE, ARITH, 14, 2, CENT, MU>())
-            if (two) return ex.template run<StreamBody<TA, MODE, ARITH, 14, 2, CENT, MU>>(g);
+            if (lay == 2) return ex.template run<StreamBody<TA, MODE, ARITH, 14, 2, CENT, MU>>(g);
         if constexpr (stream_fits<TA, MODE, ARITH, 14, 1, CENT, MU>())
             return ex.template run<StreamBody<TA, MODE, ARITH, 14, 1, CENT, MU>>(g);
     }
     return hipErrorNotSupported;
+}
+
+// Rows per tile of the kernel stream_ncb launches (the 128-row layout runs two
+// workgroups per CU, so a round holds twice as many).
+template <typename TA, int MODE>
+int stream_trows(int arith, int ncols, bool mu) {
+    constexpr bool cent = sizeof(TA) == 2;
+    int lay = 1;
+    if (arith == 0) lay = mu ? stream_lay<TA, MODE, 0, false, true>(ncols) : stream_lay<TA, MODE, 0, false, false>(ncols);
+    else if (arith == 1) lay = mu ? stream_lay<TA, MODE, 1, false, true>(ncols) : stream_lay<TA, MODE, 1, false, false>(ncols);
+    else lay = mu ? stream_lay<TA, MODE, 2, cent, true>(ncols) : stream_lay<TA, MODE, 2, false, false>(ncols);
+    return lay == 3 ? 128 : 256;
 }
 
 // Whether stream_ncb would launch (checked before X is packed).
@@ -385,12 +421,14 @@ hipError_t gemm_streamed(Ex& ex, int arith, const TA* A, int64_t lda, int64_t ro
         if (e != hipSuccess) return e;
         // tail dealing: when the pairs left over by whole rounds fill at most
         // half of a round (each then splits into two or more pieces)
-        const int64_t tiles = cdiv(rows, 256), pairs = tiles * g.splits;
-        const int64_t ld_slot = rup(ncols, 4), leftover = tail.groups > 0 ? pairs % tail.groups : 0;
+        const int trows = stream_trows<TA, MODE>(arith, ncols, mu != nullptr);
+        const int groups = tail.groups * (256 / trows);       // workgroups of one round
+        const int64_t tiles = cdiv(rows, trows), pairs = tiles * g.splits;
+        const int64_t ld_slot = rup(ncols, 4), leftover = groups > 0 ? pairs % groups : 0;
         bool dealt = false;
-        if (tail.p && leftover > 0 && 2 * leftover <= tail.groups &&
-            tail.bytes >= static_cast<size_t>(tail.groups) * 256 * ld_slot * sizeof(float)) {
-            g.tail_groups = tail.groups;
+        if (tail.p && leftover > 0 && 2 * leftover <= groups &&
+            tail.bytes >= static_cast<size_t>(groups) * trows * ld_slot * sizeof(float)) {
+            g.tail_groups = groups;
             g.tail_slots = tail.p;
             g.ld_slot = ld_slot;
             dealt = true;
@@ -405,8 +443,8 @@ hipError_t gemm_streamed(Ex& ex, int arith, const TA* A, int64_t lda, int64_t ro
             else e = stream_ncb<TA, MODE, 2, false, false>(ex, g);
         }
         if (e != hipSuccess || !dealt) return e;
-        return ex.template run<TailFixBody>(TailFixArgs{tail.p, ld_slot, rows, ncols, static_cast<int>(tiles), 256,
-                                                        pairs - leftover, leftover, tail.groups, out, ldo, part_stride,
+        return ex.template run<TailFixBody>(TailFixArgs{tail.p, ld_slot, rows, ncols, static_cast<int>(tiles), trows,
+                                                        pairs - leftover, leftover, groups, out, ldo, part_stride,
                                                         skip_flag, skip_mask, gate});
     }
 }
