@@ -51,12 +51,14 @@ def test_streamed_nn_exact_integers(gpu_lib, dt, arith, m, K, c, splits):
     assert np.array_equal(Y, A @ X)
 
 
-@pytest.mark.parametrize("dt,arith", [("f32", "storage"), ("f32", "bf16")])
+@pytest.mark.parametrize("dt,arith", [("f32", "storage"), ("f32", "bf16"), ("bf16", "storage"), ("bf16", "bf16")])
 @pytest.mark.parametrize("m,K,c", [(76837, 1100, 100), (76837, 1100, 220)])
 def test_streamed_nn_whole_rounds_and_tail(gpu_lib, dt, arith, m, K, c):
-    """301 row tiles: one whole round of 256 workgroups (placed by hardware
-    block index) and 45 tiles dealt in pieces to a second round, whose slots
-    TailFixBody sums; bitwise on small integers."""
+    """f32 A (and bf16 A at 100 columns): 301 tiles of 256 rows, one whole
+    round of 256 workgroups (placed by hardware block index) and 45 tiles
+    dealt in pieces to a second round, whose slots TailFixBody sums.  bf16 A
+    at 220 columns runs 128-row tiles, two workgroups per CU: 601 tiles, one
+    round of 512 and 89 dealt.  Bitwise on small integers."""
     from paper_1608_02148_amd import api
     print(f"streamed NN tail {dt} {arith} m={m} K={K} c={c}", flush=True)
     rng = np.random.default_rng(m + c)
