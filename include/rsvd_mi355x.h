@@ -588,7 +588,9 @@ int rsvd_test_matrix(rsvd_handle_t handle, int32_t dtype, int64_t n, int32_t l,
  * Kernel choice: products with m K >= 2^24, 64 < c <= 224 and 16-byte
  * aligned rows of A stream A straight into the matrix cores; others stage
  * tiles of A in LDS.  Results agree to rounding (the order of the sum over K
- * differs); RSVD_PRODUCTS=staged in the environment keeps the staged tiles. */
+ * differs); RSVD_PRODUCTS=staged in the environment keeps the staged tiles,
+ * and RSVD_STREAM_WPS=1 (=2) keeps the streamed kernels at one wave per SIMD
+ * (at most eight-wave workgroups). */
 int rsvd_gemm_nn(rsvd_handle_t handle, int32_t dtype, int32_t arith, int64_t m, int64_t K, int32_t c,
                  const void* A, int64_t lda, const void* X, int64_t ldx,
                  void* Y, int64_t ldy, int32_t splits, void* work, size_t work_bytes);
