@@ -540,17 +540,29 @@ struct TailFixBody {
         const int64_t r = t * a.trows + rr;
         if (r >= a.rows) return;
         const int64_t w0 = tail_first(pl, a.leftover, a.groups), w1 = tail_first(pl + 1, a.leftover, a.groups);
-        float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-        for (int64_t w = w0; w < w1; ++w) {
-            const float* p = a.slots + (w * a.trows + rr) * a.ld_slot + c;
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-                if (c + e < a.ncols) acc[e] += p[e];
+        // one 16-byte load per slot (ld_slot is a multiple of 4 and the slots
+        // start 256-byte aligned), four slots in flight, summed in slot order
+        const int64_t step = static_cast<int64_t>(a.trows) * a.ld_slot;
+        const float4* p = reinterpret_cast<const float4*>(a.slots + (w0 * a.trows + rr) * a.ld_slot + c);
+        const int64_t st = step / 4;
+        float4 acc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        int64_t w = w0;
+        for (; w + 4 <= w1; w += 4, p += 4 * st) {
+            const float4 v0 = p[0], v1 = p[st], v2 = p[2 * st], v3 = p[3 * st];
+            acc.x += v0.x; acc.y += v0.y; acc.z += v0.z; acc.w += v0.w;
+            acc.x += v1.x; acc.y += v1.y; acc.z += v1.z; acc.w += v1.w;
+            acc.x += v2.x; acc.y += v2.y; acc.z += v2.z; acc.w += v2.w;
+            acc.x += v3.x; acc.y += v3.y; acc.z += v3.z; acc.w += v3.w;
         }
+        for (; w < w1; ++w, p += st) {
+            const float4 v = p[0];
+            acc.x += v.x; acc.y += v.y; acc.z += v.z; acc.w += v.w;
+        }
+        const float av[4] = {acc.x, acc.y, acc.z, acc.w};
         float* o = a.out + s * a.part_stride + r * a.ldo + c;
 #pragma unroll
         for (int e = 0; e < 4; ++e)
-            if (c + e < a.ncols) o[e] = acc[e];
+            if (c + e < a.ncols) o[e] = av[e];
     }
 };
 

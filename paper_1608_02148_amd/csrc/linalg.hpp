@@ -61,9 +61,17 @@ struct ReduceBody {
     };
     static constexpr int THREADS = 256;
     static constexpr int SLICES = 4, PER_BLOCK = THREADS / SLICES;
+    static constexpr int V = 16 / sizeof(T);                 // elements of one 16-byte access
     static bool sliced(const Args& a) { return a.S >= 8 && a.rows * a.ncols <= 65536; }
+    // otherwise, with 16-byte aligned rows and blocks, a thread sums V
+    // adjacent outputs with one 16-byte load per split
+    __host__ __device__ static bool vec(const Args& a) {
+        return a.ncols % V == 0 && a.ldp % V == 0 && a.ldo % V == 0 && a.part_stride % V == 0 &&
+               reinterpret_cast<uintptr_t>(a.part) % 16 == 0 && reinterpret_cast<uintptr_t>(a.out) % 16 == 0;
+    }
     static int blocks(const Args& a) {
-        return static_cast<int>(cdiv(a.rows * a.ncols, sliced(a) ? PER_BLOCK : THREADS));
+        if (sliced(a)) return static_cast<int>(cdiv(a.rows * a.ncols, PER_BLOCK));
+        return static_cast<int>(cdiv(a.rows * (vec(a) ? a.ncols / V : a.ncols), THREADS));
     }
     static size_t lds(const Args&) { return 0; }
     static __device__ void run(const Args& a, int b) {
@@ -88,6 +96,27 @@ struct ReduceBody {
             return;
         }
         const int64_t idx = static_cast<int64_t>(b) * THREADS + threadIdx.x;
+        if (vec(a)) {
+            typedef __attribute__((ext_vector_type(V))) T vec_t;
+            const int cv = a.ncols / V;
+            const int64_t r = idx / cv;
+            const int c = V * static_cast<int>(idx - r * cv);
+            if (r >= a.rows) return;
+            const vec_t* src = reinterpret_cast<const vec_t*>(a.part + r * a.ldp + c);
+            const int64_t st = a.part_stride / V;
+            vec_t s = src[0];
+            int k = 1;
+            for (; k + 4 <= a.S; k += 4) {
+                const vec_t v0 = src[k * st], v1 = src[(k + 1) * st], v2 = src[(k + 2) * st], v3 = src[(k + 3) * st];
+                s += v0;
+                s += v1;
+                s += v2;
+                s += v3;
+            }
+            for (; k < a.S; ++k) s += src[k * st];
+            *reinterpret_cast<vec_t*>(a.out + r * a.ldo + c) = s;
+            return;
+        }
         const int64_t r = idx / a.ncols;
         const int c = static_cast<int>(idx - r * a.ncols);
         if (r >= a.rows) return;
