@@ -748,6 +748,13 @@ inline int small_lm(int l) { return l <= 32 ? 32 : (l <= 64 ? 64 : (l <= CHOL_MA
 //   sigma[0..l), xv (ldx x xcols, TC): xv[t][i] = W[t][perm[i]] for i < k,
 //   wks (f64, l x k, ld k): wks[t][i] = W[t][perm[i]] / sigma_i, from which
 //   J_k = R^T wks is formed by a product kernel.
+// Outer sweeps of the block Jacobi for 128 < l <= 256 (JacobiBlockBody) and
+// the layout of its word array rot (sweep flags, barrier counters, failure).
+constexpr int kJacobiOuter = 30;       // outer sweeps issued (converged ones exit at once)
+constexpr int kJacobiCtr = 32;         // rot[32 + s]: barrier arrivals of sweep s
+constexpr int kJacobiFail = 63;        // rot[63]: a barrier wait gave up
+constexpr int kJacobiRotWords = 64;
+static_assert(kJacobiCtr >= kJacobiOuter && kJacobiCtr + kJacobiOuter <= kJacobiFail, "rot layout");
 struct JacobiArgs {
     const double* R; int ldr; int l; int k;
     double* sigma;       // l
@@ -1038,6 +1045,7 @@ __device__ __forceinline__ void jacobi_body(const JacobiArgs& a) {
             sweep = 0;
             while (sweep < a.outer && a.rot[sweep]) ++sweep;
             limit = a.outer;
+            if (a.rot[kJacobiFail]) sweep = limit;     // a block round was not synchronised
         }
         const uint32_t sw = static_cast<uint32_t>(min(sweep + 1, 255)) << 24;
         atomicOr(a.status, sw | (sweep >= limit ? RSVD_FLAG_JACOBI_SLOW : 0u));
@@ -1182,15 +1190,41 @@ struct CholAssembleBody {
 
 // ---------------------------------------------- block Jacobi for 128 < l <= 256
 // W (l x l, column c at W + c ldw, global memory) is split into JB = 8 column
-// blocks of bs = ceil(l / 8) <= 32.  One outer sweep takes JB - 1 rounds; in
-// round r the JB / 2 block pairs of the round-robin schedule go to JB / 2
-// workgroups, each of which loads its two blocks (<= 64 columns) into LDS,
-// rotates every pair of those columns once (one-sided Jacobi, same rotation
-// test as above), and writes them back.  rot[s] = 1 when outer sweep s rotated
-// any pair; a launch of sweep s > 0 exits at once when rot[s - 1] = 0.
+// blocks of bs = ceil(l / 8) <= 32.  One outer sweep takes JB - 1 rounds, all
+// in one launch of JB / 2 workgroups: in round r the JB / 2 block pairs of the
+// round-robin schedule go to the workgroups, each of which loads its two
+// blocks (<= 64 columns) into LDS, rotates every pair of those columns once
+// (one-sided Jacobi, same rotation test as above), and writes them back; a
+// grid-wide barrier separates the rounds.  rot[s] = 1 when outer sweep s
+// rotated any pair; a launch of sweep s > 0 exits at once when rot[s - 1] = 0.
+// The barrier of sweep s counts arrivals in rot[kJacobiCtr + s]; its wait is
+// bounded, and a wait that gives up sets rot[kJacobiFail] (the finishing pass
+// then reports the small SVD as not converged).  The JB / 2 workgroups need
+// JB / 2 CUs at once, which any launch on an otherwise idle stream gets.
 constexpr int JB = 8;
-constexpr int kJacobiOuter = 30;       // outer sweeps issued (converged ones exit at once)
-struct JacobiBlockArgs { double* W; int ldw; int l; int bs; int sweep; int round; uint32_t* rot; double tol; };
+struct JacobiBlockArgs { double* W; int ldw; int l; int bs; int sweep; uint32_t* rot; double tol; };
+
+// Barrier of the JacobiBlockBody workgroups: every thread's stores of W are
+// released at agent scope, one thread per workgroup arrives and waits for
+// `target` arrivals (at most 2^20 polls, none once a wait has given up), and
+// every thread then acquires, so that its loads see the other workgroups'
+// stores (W crosses XCDs and their separate L2 caches).
+__device__ __forceinline__ void jacobi_grid_sync(uint32_t* ctr, uint32_t target, uint32_t* fail) {
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        for (int spins = 0; __hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target; ++spins) {
+            if (spins == (1 << 20) || __hip_atomic_load(fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+                __hip_atomic_store(fail, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+    }
+    __syncthreads();
+    __threadfence();
+}
 struct JacobiPrepArgs { const double* R; int ldr; int l; double* W; int ldw; uint32_t* rot; int nrot; };
 
 // W[c][r] = R[r][c]; rot[0..nrot) = 0.
@@ -1217,80 +1251,86 @@ struct JacobiBlockBody {
     static size_t lds(const Args& a) { return static_cast<size_t>(NLOC) * a.ldw * sizeof(double); }
     static __device__ void run(const Args& a, int p) {
         if (a.sweep > 0 && a.rot[a.sweep - 1] == 0u) return;        // converged
+        if (a.rot[kJacobiFail] != 0u) return;                        // a barrier gave up
         extern __shared__ __align__(16) unsigned char smem_raw[];
         double* Ws = reinterpret_cast<double*>(smem_raw);
         __shared__ int s_gcol[NLOC];
         __shared__ double s_norm[NLOC];
         __shared__ int s_rotated;
         const int tid = threadIdx.x, l = a.l, ldw = a.ldw;
-        int ba, bb;
-        if (p == 0) { ba = a.round; bb = JB - 1; }
-        else { ba = (a.round + p) % (JB - 1); bb = (a.round - p + JB - 1) % (JB - 1); }
-        const int a0 = ba * a.bs, a1 = min(l, a0 + a.bs), b0 = bb * a.bs, b1 = min(l, b0 + a.bs);
-        const int na = max(0, a1 - a0), nloc = na + max(0, b1 - b0);
-        if (tid < NLOC) s_gcol[tid] = (tid < na) ? a0 + tid : (tid < nloc ? b0 + tid - na : -1);
         if (tid == 0) s_rotated = 0;
-        __syncthreads();
-        for (int idx = tid; idx < nloc * l; idx += THREADS) {
-            const int i = idx / l, r = idx - i * l;
-            Ws[i * ldw + r] = a.W[s_gcol[i] * ldw + r];
-        }
-        __syncthreads();
-        const int group = tid / JAC_GROUP, gl = tid % JAC_GROUP;
-        constexpr int NG = THREADS / JAC_GROUP;
-        for (int c = group; c < nloc; c += NG) {
-            double ss = 0.0;
-            for (int r = gl; r < l; r += JAC_GROUP) ss += Ws[c * ldw + r] * Ws[c * ldw + r];
-            ss = group_sum(ss);
-            if (gl == 0) s_norm[c] = ss;
-        }
-        __syncthreads();
-        const int lp = nloc + (nloc & 1), npairs = lp / 2;
-        for (int round = 0; round < lp - 1; ++round) {
-            for (int q = group; q < npairs; q += NG) {
-                int ca, cb;
-                if (q == 0) { ca = round; cb = lp - 1; }
-                else { ca = (round + q) % (lp - 1); cb = (round - q + lp - 1) % (lp - 1); }
-                if (ca >= nloc || cb >= nloc) continue;
-                double* wa = Ws + ca * ldw;
-                double* wb = Ws + cb * ldw;
-                double xa[PER_LANE], xb[PER_LANE];
-#pragma unroll
-                for (int t = 0; t < PER_LANE; ++t) {
-                    const int r = gl + JAC_GROUP * t;
-                    xa[t] = (r < l) ? wa[r] : 0.0;
-                    xb[t] = (r < l) ? wb[r] : 0.0;
-                }
-                const double al = s_norm[ca], be = s_norm[cb];
-                double ga = 0.0;
-#pragma unroll
-                for (int t = 0; t < PER_LANE; ++t) ga += xa[t] * xb[t];
-                ga = group_sum(ga);
-                if (ga != 0.0 && fabs(ga) > a.tol * sqrt(al * be)) {
-                    const double zeta = (be - al) / (2.0 * ga);
-                    const double tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                    const double c = 1.0 / sqrt(1.0 + tt * tt), sn = c * tt;
-                    if (gl == 0) {
-                        s_norm[ca] = fmax(al - tt * ga, 0.0);
-                        s_norm[cb] = be + tt * ga;
-                        s_rotated = 1;
-                    }
-#pragma unroll
+        for (int bround = 0; bround < JB - 1; ++bround) {
+            // the other workgroups' writes of the previous round must land first
+            if (bround > 0) jacobi_grid_sync(a.rot + kJacobiCtr + a.sweep, bround * (JB / 2), a.rot + kJacobiFail);
+            int ba, bb;
+            if (p == 0) { ba = bround; bb = JB - 1; }
+            else { ba = (bround + p) % (JB - 1); bb = (bround - p + JB - 1) % (JB - 1); }
+            const int a0 = ba * a.bs, a1 = min(l, a0 + a.bs), b0 = bb * a.bs, b1 = min(l, b0 + a.bs);
+            const int na = max(0, a1 - a0), nloc = na + max(0, b1 - b0);
+            if (tid < NLOC) s_gcol[tid] = (tid < na) ? a0 + tid : (tid < nloc ? b0 + tid - na : -1);
+            __syncthreads();
+            for (int idx = tid; idx < nloc * l; idx += THREADS) {
+                const int i = idx / l, r = idx - i * l;
+                Ws[i * ldw + r] = a.W[s_gcol[i] * ldw + r];
+            }
+            __syncthreads();
+            const int group = tid / JAC_GROUP, gl = tid % JAC_GROUP;
+            constexpr int NG = THREADS / JAC_GROUP;
+            for (int c = group; c < nloc; c += NG) {
+                double ss = 0.0;
+                for (int r = gl; r < l; r += JAC_GROUP) ss += Ws[c * ldw + r] * Ws[c * ldw + r];
+                ss = group_sum(ss);
+                if (gl == 0) s_norm[c] = ss;
+            }
+            __syncthreads();
+            const int lp = nloc + (nloc & 1), npairs = lp / 2;
+            for (int round = 0; round < lp - 1; ++round) {
+                for (int q = group; q < npairs; q += NG) {
+                    int ca, cb;
+                    if (q == 0) { ca = round; cb = lp - 1; }
+                    else { ca = (round + q) % (lp - 1); cb = (round - q + lp - 1) % (lp - 1); }
+                    if (ca >= nloc || cb >= nloc) continue;
+                    double* wa = Ws + ca * ldw;
+                    double* wb = Ws + cb * ldw;
+                    double xa[PER_LANE], xb[PER_LANE];
+    #pragma unroll
                     for (int t = 0; t < PER_LANE; ++t) {
                         const int r = gl + JAC_GROUP * t;
-                        if (r < l) {
-                            wa[r] = c * xa[t] - sn * xb[t];
-                            wb[r] = sn * xa[t] + c * xb[t];
+                        xa[t] = (r < l) ? wa[r] : 0.0;
+                        xb[t] = (r < l) ? wb[r] : 0.0;
+                    }
+                    const double al = s_norm[ca], be = s_norm[cb];
+                    double ga = 0.0;
+    #pragma unroll
+                    for (int t = 0; t < PER_LANE; ++t) ga += xa[t] * xb[t];
+                    ga = group_sum(ga);
+                    if (ga != 0.0 && fabs(ga) > a.tol * sqrt(al * be)) {
+                        const double zeta = (be - al) / (2.0 * ga);
+                        const double tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                        const double c = 1.0 / sqrt(1.0 + tt * tt), sn = c * tt;
+                        if (gl == 0) {
+                            s_norm[ca] = fmax(al - tt * ga, 0.0);
+                            s_norm[cb] = be + tt * ga;
+                            s_rotated = 1;
+                        }
+    #pragma unroll
+                        for (int t = 0; t < PER_LANE; ++t) {
+                            const int r = gl + JAC_GROUP * t;
+                            if (r < l) {
+                                wa[r] = c * xa[t] - sn * xb[t];
+                                wb[r] = sn * xa[t] + c * xb[t];
+                            }
                         }
                     }
                 }
+                __syncthreads();
             }
-            __syncthreads();
+            for (int idx = tid; idx < nloc * l; idx += THREADS) {
+                const int i = idx / l, r = idx - i * l;
+                a.W[s_gcol[i] * ldw + r] = Ws[i * ldw + r];
+            }
         }
-        for (int idx = tid; idx < nloc * l; idx += THREADS) {
-            const int i = idx / l, r = idx - i * l;
-            a.W[s_gcol[i] * ldw + r] = Ws[i * ldw + r];
-        }
+        __syncthreads();
         if (tid == 0 && s_rotated) a.rot[a.sweep] = 1u;
     }
 };
