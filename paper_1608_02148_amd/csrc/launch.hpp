@@ -190,7 +190,12 @@ hipError_t gemm_plain(Ex& ex, int cls, bool square, const TA* A, int64_t lda, in
         // 128 for the Gram of an f32 basis, 32 / 64 / 128 otherwise (the same
         // coarser classes the f64 solves and their batch groups use)
         const int extent = static_cast<int>(std::max<int64_t>(rows, ncols));
-        const int sc = tile_class(extent, sizeof(TA) == 4);
+        int sc = tile_class(extent, sizeof(TA) == 4);
+        // a single solve's small f64 products (R factors, Schur blocks, J_k:
+        // reduction <= 256) spread over 32 x 32 tiles, one workgroup each,
+        // instead of leaving one CU to do all of a 128 x 128 tile
+        if constexpr (Ex::kSingle)
+            if (sizeof(TA) == 8 && K <= 256) sc = 32;
         if (sc == 32) return ex.template run<GemmBody<TA, TX, TC, MODE, 1, 1, 2, 2>>(g);
         if (sc == 48) return ex.template run<GemmBody<TA, TX, TC, MODE, 1, 3, 3, 1>>(g);
         if (sc == 64) return ex.template run<GemmBody<TA, TX, TC, MODE, 2, 2, 2, 2>>(g);
