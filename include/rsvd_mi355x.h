@@ -100,7 +100,11 @@ typedef struct {
 #define RSVD_FLAG_CHOL_SHIFT   1u  /* a Gram matrix needed the shifted Cholesky    */
 #define RSVD_FLAG_DEGENERATE   2u  /* a column was numerically zero after shifting */
 #define RSVD_FLAG_NONFINITE    4u  /* NaN or Inf reached a Gram matrix             */
-#define RSVD_FLAG_JACOBI_SLOW  8u  /* small SVD stopped at its sweep limit         */
+#define RSVD_FLAG_JACOBI_SLOW  8u  /* small SVD stopped at its sweep limit (for
+                                      l > 128 also: a round of its block sweeps
+                                      timed out waiting for the other
+                                      workgroups; the results are then not
+                                      reliable)                                  */
 #define RSVD_FLAG_ZERO_SCALE  16u  /* scaled PCA: a column had zero spread (its
                                       scale was set to 1; see rpca_run_ex)       */
 /* Bits 24..31 of rsvd_info.flags hold the number of Jacobi sweeps the small SVD
