@@ -750,11 +750,11 @@ inline int small_lm(int l) { return l <= 32 ? 32 : (l <= 64 ? 64 : (l <= CHOL_MA
 //   J_k = R^T wks is formed by a product kernel.
 // Outer sweeps of the block Jacobi for 128 < l <= 256 (JacobiBlockBody) and
 // the layout of its word array rot (sweep flags, barrier counters, failure).
-constexpr int kJacobiOuter = 30;       // outer sweeps issued (converged ones exit at once)
-constexpr int kJacobiCtr = 32;         // rot[32 + s]: barrier arrivals of sweep s
+constexpr int kJacobiOuter = 30;       // most outer sweeps
+constexpr int kJacobiCtr = 32;         // rot[32]: barrier arrivals
 constexpr int kJacobiFail = 63;        // rot[63]: a barrier wait gave up
 constexpr int kJacobiRotWords = 64;
-static_assert(kJacobiCtr >= kJacobiOuter && kJacobiCtr + kJacobiOuter <= kJacobiFail, "rot layout");
+static_assert(kJacobiCtr >= kJacobiOuter && kJacobiCtr < kJacobiFail, "rot layout");
 struct JacobiArgs {
     const double* R; int ldr; int l; int k;
     double* sigma;       // l
@@ -1190,19 +1190,22 @@ struct CholAssembleBody {
 
 // ---------------------------------------------- block Jacobi for 128 < l <= 256
 // W (l x l, column c at W + c ldw, global memory) is split into JB = 8 column
-// blocks of bs = ceil(l / 8) <= 32.  One outer sweep takes JB - 1 rounds, all
-// in one launch of JB / 2 workgroups: in round r the JB / 2 block pairs of the
-// round-robin schedule go to the workgroups, each of which loads its two
-// blocks (<= 64 columns) into LDS, rotates every pair of those columns once
-// (one-sided Jacobi, same rotation test as above), and writes them back; a
-// grid-wide barrier separates the rounds.  rot[s] = 1 when outer sweep s
-// rotated any pair; a launch of sweep s > 0 exits at once when rot[s - 1] = 0.
-// The barrier of sweep s counts arrivals in rot[kJacobiCtr + s]; its wait is
-// bounded, and a wait that gives up sets rot[kJacobiFail] (the finishing pass
-// then reports the small SVD as not converged).  The JB / 2 workgroups need
-// JB / 2 CUs at once, which any launch on an otherwise idle stream gets.
+// blocks of bs = ceil(l / 8) <= 32.  All sweeps run in one launch of JB / 2
+// workgroups.  An outer sweep takes JB - 1 rounds: in round r the JB / 2
+// block pairs of the round-robin schedule go to the workgroups, each of which
+// loads its two blocks (<= 64 columns) into LDS, rotates every pair of those
+// columns once (one-sided Jacobi, same rotation test as above), and writes
+// them back.  A grid-wide barrier separates consecutive rounds and sweeps.
+// rot[s] = 1 when outer sweep s rotated any pair; after the barrier that ends
+// sweep s every workgroup reads rot[s] and stops when it is 0 (all read the
+// same word, so all stop together), at the latest after kJacobiOuter sweeps.
+// The barriers count arrivals in rot[kJacobiCtr] (the b-th barrier waits for
+// b JB / 2); a wait is bounded, and one that gives up sets rot[kJacobiFail],
+// which stops the sweeps (the finishing pass then reports the small SVD as
+// not converged).  The JB / 2 workgroups need JB / 2 CUs at once, which any
+// launch on an otherwise idle stream gets.
 constexpr int JB = 8;
-struct JacobiBlockArgs { double* W; int ldw; int l; int bs; int sweep; uint32_t* rot; double tol; };
+struct JacobiBlockArgs { double* W; int ldw; int l; int bs; uint32_t* rot; double tol; };
 
 // Barrier of the JacobiBlockBody workgroups: every thread's stores of W are
 // released at agent scope, one thread per workgroup arrives and waits for
@@ -1250,88 +1253,99 @@ struct JacobiBlockBody {
     static int blocks(const Args&) { return JB / 2; }
     static size_t lds(const Args& a) { return static_cast<size_t>(NLOC) * a.ldw * sizeof(double); }
     static __device__ void run(const Args& a, int p) {
-        if (a.sweep > 0 && a.rot[a.sweep - 1] == 0u) return;        // converged
-        if (a.rot[kJacobiFail] != 0u) return;                        // a barrier gave up
         extern __shared__ __align__(16) unsigned char smem_raw[];
         double* Ws = reinterpret_cast<double*>(smem_raw);
         __shared__ int s_gcol[NLOC];
         __shared__ double s_norm[NLOC];
-        __shared__ int s_rotated;
+        __shared__ int s_rotated, s_stop;
         const int tid = threadIdx.x, l = a.l, ldw = a.ldw;
-        if (tid == 0) s_rotated = 0;
-        for (int bround = 0; bround < JB - 1; ++bround) {
-            // the other workgroups' writes of the previous round must land first
-            if (bround > 0) jacobi_grid_sync(a.rot + kJacobiCtr + a.sweep, bround * (JB / 2), a.rot + kJacobiFail);
-            int ba, bb;
-            if (p == 0) { ba = bround; bb = JB - 1; }
-            else { ba = (bround + p) % (JB - 1); bb = (bround - p + JB - 1) % (JB - 1); }
-            const int a0 = ba * a.bs, a1 = min(l, a0 + a.bs), b0 = bb * a.bs, b1 = min(l, b0 + a.bs);
-            const int na = max(0, a1 - a0), nloc = na + max(0, b1 - b0);
-            if (tid < NLOC) s_gcol[tid] = (tid < na) ? a0 + tid : (tid < nloc ? b0 + tid - na : -1);
-            __syncthreads();
-            for (int idx = tid; idx < nloc * l; idx += THREADS) {
-                const int i = idx / l, r = idx - i * l;
-                Ws[i * ldw + r] = a.W[s_gcol[i] * ldw + r];
+        uint32_t* const ctr = a.rot + kJacobiCtr;
+        uint32_t* const fail = a.rot + kJacobiFail;
+        uint32_t nbar = 0;
+        for (int sweep = 0; sweep < kJacobiOuter; ++sweep) {
+            if (sweep > 0) {
+                // every workgroup's flag for the previous sweep is out: stop when
+                // it rotated nothing (or a barrier gave up)
+                jacobi_grid_sync(ctr, ++nbar * (JB / 2), fail);
+                if (tid == 0) s_stop = (a.rot[sweep - 1] == 0u || *fail != 0u) ? 1 : 0;
+                __syncthreads();
+                if (s_stop) break;
             }
-            __syncthreads();
-            const int group = tid / JAC_GROUP, gl = tid % JAC_GROUP;
-            constexpr int NG = THREADS / JAC_GROUP;
-            for (int c = group; c < nloc; c += NG) {
-                double ss = 0.0;
-                for (int r = gl; r < l; r += JAC_GROUP) ss += Ws[c * ldw + r] * Ws[c * ldw + r];
-                ss = group_sum(ss);
-                if (gl == 0) s_norm[c] = ss;
-            }
-            __syncthreads();
-            const int lp = nloc + (nloc & 1), npairs = lp / 2;
-            for (int round = 0; round < lp - 1; ++round) {
-                for (int q = group; q < npairs; q += NG) {
-                    int ca, cb;
-                    if (q == 0) { ca = round; cb = lp - 1; }
-                    else { ca = (round + q) % (lp - 1); cb = (round - q + lp - 1) % (lp - 1); }
-                    if (ca >= nloc || cb >= nloc) continue;
-                    double* wa = Ws + ca * ldw;
-                    double* wb = Ws + cb * ldw;
-                    double xa[PER_LANE], xb[PER_LANE];
-    #pragma unroll
-                    for (int t = 0; t < PER_LANE; ++t) {
-                        const int r = gl + JAC_GROUP * t;
-                        xa[t] = (r < l) ? wa[r] : 0.0;
-                        xb[t] = (r < l) ? wb[r] : 0.0;
-                    }
-                    const double al = s_norm[ca], be = s_norm[cb];
-                    double ga = 0.0;
-    #pragma unroll
-                    for (int t = 0; t < PER_LANE; ++t) ga += xa[t] * xb[t];
-                    ga = group_sum(ga);
-                    if (ga != 0.0 && fabs(ga) > a.tol * sqrt(al * be)) {
-                        const double zeta = (be - al) / (2.0 * ga);
-                        const double tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                        const double c = 1.0 / sqrt(1.0 + tt * tt), sn = c * tt;
-                        if (gl == 0) {
-                            s_norm[ca] = fmax(al - tt * ga, 0.0);
-                            s_norm[cb] = be + tt * ga;
-                            s_rotated = 1;
-                        }
-    #pragma unroll
+            if (tid == 0) s_rotated = 0;
+            for (int bround = 0; bround < JB - 1; ++bround) {
+                // the other workgroups' writes of the previous round must land first
+                if (bround > 0) jacobi_grid_sync(ctr, ++nbar * (JB / 2), fail);
+                int ba, bb;
+                if (p == 0) { ba = bround; bb = JB - 1; }
+                else { ba = (bround + p) % (JB - 1); bb = (bround - p + JB - 1) % (JB - 1); }
+                const int a0 = ba * a.bs, a1 = min(l, a0 + a.bs), b0 = bb * a.bs, b1 = min(l, b0 + a.bs);
+                const int na = max(0, a1 - a0), nloc = na + max(0, b1 - b0);
+                if (tid < NLOC) s_gcol[tid] = (tid < na) ? a0 + tid : (tid < nloc ? b0 + tid - na : -1);
+                __syncthreads();
+                for (int idx = tid; idx < nloc * l; idx += THREADS) {
+                    const int i = idx / l, r = idx - i * l;
+                    Ws[i * ldw + r] = a.W[s_gcol[i] * ldw + r];
+                }
+                __syncthreads();
+                const int group = tid / JAC_GROUP, gl = tid % JAC_GROUP;
+                constexpr int NG = THREADS / JAC_GROUP;
+                for (int c = group; c < nloc; c += NG) {
+                    double ss = 0.0;
+                    for (int r = gl; r < l; r += JAC_GROUP) ss += Ws[c * ldw + r] * Ws[c * ldw + r];
+                    ss = group_sum(ss);
+                    if (gl == 0) s_norm[c] = ss;
+                }
+                __syncthreads();
+                const int lp = nloc + (nloc & 1), npairs = lp / 2;
+                for (int round = 0; round < lp - 1; ++round) {
+                    for (int q = group; q < npairs; q += NG) {
+                        int ca, cb;
+                        if (q == 0) { ca = round; cb = lp - 1; }
+                        else { ca = (round + q) % (lp - 1); cb = (round - q + lp - 1) % (lp - 1); }
+                        if (ca >= nloc || cb >= nloc) continue;
+                        double* wa = Ws + ca * ldw;
+                        double* wb = Ws + cb * ldw;
+                        double xa[PER_LANE], xb[PER_LANE];
+        #pragma unroll
                         for (int t = 0; t < PER_LANE; ++t) {
                             const int r = gl + JAC_GROUP * t;
-                            if (r < l) {
-                                wa[r] = c * xa[t] - sn * xb[t];
-                                wb[r] = sn * xa[t] + c * xb[t];
+                            xa[t] = (r < l) ? wa[r] : 0.0;
+                            xb[t] = (r < l) ? wb[r] : 0.0;
+                        }
+                        const double al = s_norm[ca], be = s_norm[cb];
+                        double ga = 0.0;
+        #pragma unroll
+                        for (int t = 0; t < PER_LANE; ++t) ga += xa[t] * xb[t];
+                        ga = group_sum(ga);
+                        if (ga != 0.0 && fabs(ga) > a.tol * sqrt(al * be)) {
+                            const double zeta = (be - al) / (2.0 * ga);
+                            const double tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                            const double c = 1.0 / sqrt(1.0 + tt * tt), sn = c * tt;
+                            if (gl == 0) {
+                                s_norm[ca] = fmax(al - tt * ga, 0.0);
+                                s_norm[cb] = be + tt * ga;
+                                s_rotated = 1;
+                            }
+        #pragma unroll
+                            for (int t = 0; t < PER_LANE; ++t) {
+                                const int r = gl + JAC_GROUP * t;
+                                if (r < l) {
+                                    wa[r] = c * xa[t] - sn * xb[t];
+                                    wb[r] = sn * xa[t] + c * xb[t];
+                                }
                             }
                         }
                     }
+                    __syncthreads();
                 }
-                __syncthreads();
+                for (int idx = tid; idx < nloc * l; idx += THREADS) {
+                    const int i = idx / l, r = idx - i * l;
+                    a.W[s_gcol[i] * ldw + r] = Ws[i * ldw + r];
+                }
             }
-            for (int idx = tid; idx < nloc * l; idx += THREADS) {
-                const int i = idx / l, r = idx - i * l;
-                a.W[s_gcol[i] * ldw + r] = Ws[i * ldw + r];
-            }
+            __syncthreads();
+            if (tid == 0 && s_rotated) a.rot[sweep] = 1u;
         }
-        __syncthreads();
-        if (tid == 0 && s_rotated) a.rot[a.sweep] = 1u;
     }
 };
 

@@ -360,8 +360,7 @@ hipError_t solve_steps(Ex& ex, rsvd_handle_t prof, const Plan& P, const TA* A, i
             uint32_t* rot = at<uint32_t>(work, P.jrot);
             const int ldw = jacobi_ldw(l), bs = static_cast<int>(cdiv(l, JB));
             RSVD_TRY(ex.template run<JacobiPrepBody>(JacobiPrepArgs{racc, l, l, ja.wglob, ldw, rot, kJacobiRotWords}));
-            for (int s = 0; s < kJacobiOuter; ++s)
-                RSVD_TRY(ex.template run<JacobiBlockBody>(JacobiBlockArgs{ja.wglob, ldw, l, bs, s, rot, ja.tol}));
+            RSVD_TRY(ex.template run<JacobiBlockBody>(JacobiBlockArgs{ja.wglob, ldw, l, bs, rot, ja.tol}));
             ja.rot = rot; ja.outer = kJacobiOuter;
         }
         RSVD_TRY(run_jacobi<TC>(ex, ja));
