@@ -1207,13 +1207,14 @@ struct CholAssembleBody {
 constexpr int JB = 8;
 struct JacobiBlockArgs { double* W; int ldw; int l; int bs; uint32_t* rot; double tol; };
 
-// Barrier of the JacobiBlockBody workgroups: every thread's stores of W are
-// released at agent scope, one thread per workgroup arrives and waits for
-// `target` arrivals (at most 2^20 polls, none once a wait has given up), and
-// every thread then acquires, so that its loads see the other workgroups'
-// stores (W crosses XCDs and their separate L2 caches).
+// Barrier of the JacobiBlockBody workgroups: after a workgroup barrier, one
+// thread per workgroup arrives with an agent-scope release (which carries the
+// workgroup's stores of W, ordered before it by the barrier) and waits with
+// agent-scope acquires for `target` arrivals (at most 2^20 polls, none once a
+// wait has given up); a second workgroup barrier then orders the other
+// threads' loads after that acquire, so they see the other workgroups' stores
+// (W crosses XCDs and their separate L2 caches).
 __device__ __forceinline__ void jacobi_grid_sync(uint32_t* ctr, uint32_t target, uint32_t* fail) {
-    __threadfence();
     __syncthreads();
     if (threadIdx.x == 0) {
         __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
@@ -1226,7 +1227,6 @@ __device__ __forceinline__ void jacobi_grid_sync(uint32_t* ctr, uint32_t target,
         }
     }
     __syncthreads();
-    __threadfence();
 }
 struct JacobiPrepArgs { const double* R; int ldr; int l; double* W; int ldw; uint32_t* rot; int nrot; };
 
