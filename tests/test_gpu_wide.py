@@ -42,6 +42,9 @@ def test_wide_sketch_f64_matches_oracle(m, n, k, p, q):
     U, S, V = api.rsvd(Ag, k, p=p, q=q, seed=11, info=info)
     st, rec = api.sync_info(info)
     assert st == 0 and rec.l == min(k + p, m, n)
+    # the block sweeps (one launch, grid barriers between rounds) converged:
+    # no sweep-limit / barrier time-out flag, and bits 24..31 count the sweeps
+    assert not (rec.flags & 8) and 2 <= (rec.flags >> 24) <= 30, hex(rec.flags)
     Uo, so, Vo = orc.rsvd(A, k, p=p, q=q, seed=11)
     U, s, V = _np(U), _np(S), _np(V)
     np.testing.assert_allclose(s, so, rtol=1e-10)
